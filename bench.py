@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the gamma-index search on one MI355X.
+
+One step = one full gamma map of a synthetic IMRT-like dose pair (dose maximum, mask,
+gamma0, compaction, cell table, DD sort, search, pass counts), inputs resident in HBM.
+Prints one JSON line: reference voxels per second, the search kernel's roofline, and the
+FP64 CPU oracle timed on this host as a baseline.
+
+  python bench.py [--steps K] [--warmup W] [--workload c1|c2] [--dd 0.03 --dta 3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ref voxels/sec, 3D 3%/3mm: plain vs learned-radius at |Δγ|≤1e-5; %FP32 peak"
+
+# FP32 operations per evaluated cell of the closed-form face projections (3D: 8 corner
+# differences, 19 chain steps, 1 vertex, 7 edges, 12 triangles, 6 tetrahedra; FMA = 2,
+# add/mul/rcp = 1, compares and min = 0).  2D: 4 corners, 5 steps, 1 vertex, 3 edges,
+# 2 triangles.
+FLOP_PER_CELL = {3: 392, 2: 82}
+PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (packed)
+
+WORKLOADS = {
+    "c1": ("c1", 100, "3D 128x128x96 at 2.5 mm, 7-beam synthetic IMRT-like pair (seed 100)"),
+    "c2": ("c2", 200, "3D 256x256x192 at 1.25 mm, 7-beam synthetic IMRT-like pair (seed 200)"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def work_counts(cfg, seed, dd, dta):
+    path = os.path.join(ROOT, "tests", "golden", "work_counts.json")
+    try:
+        with open(path) as f:
+            table = json.load(f)
+    except OSError:
+        return None
+    return table.get(f"{cfg}/seed{seed}/{dd * 100:g}%/{dta:g}mm/global/thr0.1")
+
+
+def cpu_baseline(pair, dd, dta, reps):
+    """The FP64 oracle as it stands, on every host core, over the whole workload."""
+    import oracle
+    oracle.build()
+    best = None
+    for _ in range(max(1, reps)):
+        t = time.perf_counter()
+        o = oracle.gamma(pair.ref, pair.eval, pair.spacing, dd, dta, 0.1)
+        dt = time.perf_counter() - t
+        best = dt if best is None else min(best, dt)
+    return {
+        "value": o.n_evaluated / best,
+        "unit": "ref voxels/s",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": f"whole workload ({o.n_evaluated} masked nodes, {o.cells_visited} cells), "
+                  f"best of {max(1, reps)}, {best:.2f} s",
+    }, o
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c1")
+    ap.add_argument("--dd", type=float, default=0.03)
+    ap.add_argument("--dta", type=float, default=3.0)
+    ap.add_argument("--sort", choices=["dd", "none"], default="dd")
+    ap.add_argument("--precision", choices=["fp32", "guarded", "fp64"], default="guarded")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-reps", type=int, default=2)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the gamma search of one dose pair is measured on a "
+              "single MI355X (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1012_1900_amd as gx
+    from dosegen import make_config_pair
+
+    cfg, seed, desc = WORKLOADS[args.workload]
+    log(f"generating {desc}")
+    pair = make_config_pair(cfg, seed)
+    nd = pair.ref.ndim
+    dev = torch.device("cuda", 0)
+    ref = torch.from_numpy(pair.ref).to(dev)
+    ev = torch.from_numpy(pair.eval).to(dev)
+    out = torch.empty_like(ref)
+    torch.cuda.synchronize()
+
+    kw = dict(sort=args.sort, precision=args.precision, out=out)
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, **kw)
+    torch.cuda.synchronize()
+
+    log(f"timing {args.steps} steps")
+    phases = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, r = gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, timing=True, **kw)
+        phases.append(r)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    M = phases[-1].n_evaluated
+    value = M / (wall / args.steps)
+    mean = lambda f: float(np.mean([getattr(p, f) for p in phases]))  # noqa: E731
+    ms_search = mean("ms_search")
+    log(f"{M} nodes, {ms_per_step:.3f} ms/step, search {ms_search:.4f} ms")
+
+    wc = work_counts(cfg, seed, args.dd, args.dta)
+    cells = wc["cells_visited"] if wc else None
+    roofline = None
+    if cells:
+        flops = cells * FLOP_PER_CELL[nd]
+        achieved = flops / (ms_search * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                    "traffic": None, "kernel": "k_search (main pass)",
+                    "algorithmic_flop_per_launch": flops, "avg_launch_ms": round(ms_search, 5)}
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (FP64 oracle)")
+        cpu, o = cpu_baseline(pair, args.dd, args.dta, args.cpu_reps)
+        if cells is None:
+            cells = o.cells_visited
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "ref voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision != "fp64" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{desc}, {args.dd * 100:g}%/{args.dta:g}mm global, 10% cutoff, plain search",
+            "shape": list(pair.ref.shape),
+            "spacing_mm": list(pair.spacing),
+            "n_evaluated": int(M),
+            "sort": args.sort,
+            "precision": args.precision,
+            "cells_visited_oracle": cells,
+            "phases_ms": {k: round(mean(k), 4) for k in ("ms_prep", "ms_table", "ms_sort", "ms_search",
+                                                         "ms_guard")},
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

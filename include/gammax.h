@@ -1,0 +1,183 @@
+/*
+ * gammax — gamma-index dose comparison on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library libgammax.so.  Plain pointers and sizes only; no C++ exception
+ * crosses it; every call returns a gammax_status_t and never aborts the process.
+ *
+ * Method: Gu, Jia & Jiang, "GPU-based fast gamma index calculation" (arXiv:1012.1900).
+ *   gamma(r) = min over the evaluation surface of |r~ - x~|              (Sec. 2.1, Eq. (1))
+ *   with r~ = (r / DTA, D_r(r) / dD); the evaluation surface is the piecewise-linear
+ *   interpolant of D_e over the Kuhn triangulation of the grid (the geometric method the
+ *   paper adopts), searched over a radially sorted cell table with an early break
+ *   (Algorithm A1) by one lane per reference node over dose-difference-sorted nodes
+ *   (Sec. 2.2, Algorithm A2).
+ *
+ * Grids.  Reference and evaluation doses share one regular grid.  Arrays are C-ordered
+ * float32 with the fastest axis last: 3D shape = (nz, ny, nx), 2D shape = (ny, nx).
+ * Node i of an axis sits at i * spacing.  Every axis needs at least 2 nodes.
+ *
+ * Memory.  Dose and gamma buffers are device memory owned by the caller.  The context
+ * owns every scratch buffer it needs; it grows them on demand and frees them on destroy.
+ * A context serves one caller at a time (not thread-safe); use one per host thread.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Calls that return
+ * results on the host synchronise that stream before they return.
+ *
+ * Errors.  Argument errors are detected on the host before any launch.  Conditions that
+ * only the device can see (non-finite doses, no positive reference dose) are reported
+ * after the device pass that finds them; the gamma buffer is then unspecified.
+ */
+#ifndef GAMMAX_H
+#define GAMMAX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GAMMAX_OK = 0,
+    GAMMAX_E_NULL = -1,       /* a required pointer is NULL */
+    GAMMAX_E_SHAPE = -2,      /* ndim not 2 or 3, an axis with < 2 nodes, or > 2^31 nodes */
+    GAMMAX_E_PARAM = -3,      /* spacing, DD or DTA <= 0 (or not finite), threshold outside [0,1), bad option */
+    GAMMAX_E_NONFINITE = -4,  /* a dose value is NaN or infinite */
+    GAMMAX_E_NOMEM = -5,      /* device or pinned host allocation failed */
+    GAMMAX_E_DEVICE = -6,     /* a HIP runtime call failed; see gammax_last_error() */
+    GAMMAX_E_RADIUS = -7,     /* the cell table for this search radius exceeds the table cap */
+    GAMMAX_E_DOSE = -8        /* global normalisation with no positive reference dose */
+} gammax_status_t;
+
+typedef enum { GAMMAX_GLOBAL = 0, GAMMAX_LOCAL = 1 } gammax_norm_t;
+
+/* Work order of reference nodes handed to the search (Sec. 2.2; results do not depend on it). */
+typedef enum {
+    GAMMAX_SORT_NONE = 0,     /* grid order of the masked nodes */
+    GAMMAX_SORT_DD = 1        /* ascending |DD| / dD ("DD sorting" of Algorithm A2 step 3), default */
+} gammax_sort_t;
+
+/* Arithmetic of the per-simplex projections. */
+typedef enum {
+    GAMMAX_PREC_FP32 = 0,        /* FP32 everywhere */
+    GAMMAX_PREC_GUARDED = 1,     /* FP32; a tetrahedron whose Gram matrix condition number may
+                                    exceed cond_threshold is re-projected in FP64 (default) */
+    GAMMAX_PREC_FP64 = 2         /* FP64 for every face */
+} gammax_precision_t;
+
+/* The problem: the paper's statement gamma_map(ref, eval, spacing, DD, DTA, threshold, norm). */
+typedef struct {
+    int32_t ndim;             /* 2 or 3 */
+    int32_t norm;             /* gammax_norm_t: dD = DD * max(D_r) (global) or DD * D_r(r) (local) */
+    int64_t shape[3];         /* slowest axis first; 2D uses shape[0..1] = (ny, nx) */
+    double spacing_mm[3];     /* same axis order as shape; > 0 */
+    double dd;                /* dose criterion as a fraction, e.g. 0.03 */
+    double dta_mm;            /* distance-to-agreement criterion in mm, e.g. 3.0 */
+    double dose_threshold;    /* low-dose cutoff as a fraction of max(D_r), in [0, 1), e.g. 0.10.
+                                 Reference nodes with D_r < fl32(threshold * max D_r) are not
+                                 evaluated (local normalisation also skips D_r <= 0). */
+} gammax_problem_t;
+
+typedef struct {
+    int32_t sort_mode;        /* gammax_sort_t */
+    int32_t precision;        /* gammax_precision_t */
+    double cond_threshold;    /* condition-number bound of the FP64 guard, default 1e6 */
+    int32_t timing;           /* 1: time the phases with HIP events (fills ms_* in the result) */
+    int32_t reserved[7];      /* must be 0 */
+} gammax_options_t;
+
+typedef struct {
+    uint64_t n_evaluated;     /* M: masked reference nodes */
+    uint64_t n_pass;          /* nodes with gamma <= 1 */
+    uint64_t n_borderline;    /* nodes with |gamma - 1| <= 1e-5 (their pass decision is precision-bound) */
+    uint64_t n_fp64_tets;     /* tetrahedron projections redone in FP64 by the guard */
+    uint64_t n_cells;         /* cells evaluated by the search, summed over nodes */
+    double pass_rate;         /* n_pass / n_evaluated (NaN when n_evaluated == 0) */
+    float max_gamma;          /* largest gamma found */
+    float dose_max;           /* max(D_r) */
+    float search_radius;      /* R = max gamma0 = max |DD| / dD over masked nodes (Algorithm A1 step 1) */
+    int32_t table_len;        /* cells in the sorted table used by the search */
+    float ms_prep;            /* timing = 1 only: dose max, mask, gamma0, compaction */
+    float ms_table;           /*   cell table build (0 when the cached table was reused) */
+    float ms_sort;            /*   DD sort of the reference nodes */
+    float ms_search;          /*   the search kernel (Algorithm A2 step 6), main pass */
+    float ms_guard;           /*   the FP64-guarded pass over nodes that met an ill-conditioned
+                                   tetrahedron (guarded precision, 3D) */
+} gammax_result_t;
+
+typedef struct gammax_ctx gammax_ctx_t;
+
+/* Fill `opt` with the defaults: DD sort, guarded FP32, cond_threshold 1e6, no timing. */
+void gammax_options_default(gammax_options_t *opt);
+
+/* Create a context bound to HIP device `device`.  *ctx receives the handle. */
+gammax_status_t gammax_ctx_create(int device, gammax_ctx_t **ctx);
+
+/* Release the context and everything it allocated.  NULL is accepted. */
+gammax_status_t gammax_ctx_destroy(gammax_ctx_t *ctx);
+
+/*
+ * Gamma map of one dose pair (Algorithm A2 steps 2-7 on device memory).
+ *   ref_dev, eval_dev : N = prod(shape) floats each (device).
+ *   gamma_dev         : N floats (device, caller-owned) receive gamma; -1 marks nodes that
+ *                       are not evaluated.  May not alias the inputs.
+ *   opt               : NULL for the defaults.
+ *   result            : host struct, required; filled on GAMMAX_OK.
+ * Synchronises `stream` (the search radius and the counts come back to the host).
+ */
+gammax_status_t gammax_map(gammax_ctx_t *ctx, const gammax_problem_t *problem,
+                           const gammax_options_t *opt, const float *ref_dev,
+                           const float *eval_dev, float *gamma_dev, gammax_result_t *result,
+                           void *stream);
+
+/*
+ * The problem statement as a flat call (Sec. 2.1): gamma and pass rate of one dose pair
+ * with the default options on a library-owned context for the current device.
+ * shape/spacing_mm hold ndim entries each (slowest axis first); norm is gammax_norm_t.
+ * pass_rate may be NULL.  Not thread-safe.
+ */
+gammax_status_t gamma_map(const float *ref_dose, const float *eval_dose, int32_t ndim,
+                          const int64_t *shape, const double *spacing_mm, double dd,
+                          double dta_mm, double dose_threshold, int32_t norm, float *gamma,
+                          double *pass_rate, void *stream);
+
+/*
+ * Stable ascending sort of n (key, value) pairs of uint32 in place on the device: the
+ * LDS radix sort used for the DD sort (Algorithm A2 step 3) and for the cell table
+ * (step 5).  Equal keys keep their input order.
+ */
+gammax_status_t gammax_sort_pairs(gammax_ctx_t *ctx, uint32_t *keys_dev, uint32_t *vals_dev,
+                                  int64_t n, void *stream);
+
+/*
+ * The radially sorted cell table (Algorithm A1 steps 2-3, Algorithm A2 steps 4-5).
+ * Lists every cell offset a (lower corner relative to the reference node, slowest axis
+ * first) that can hold a grid cell of `shape` and whose key
+ *     key(a)^2 = sum_i (s_i * max(0, a_i, -a_i - 1))^2,  s_i = spacing_i / DTA,
+ * is < radius^2, in ascending key order (ties: slowest axis, then the others, ascending).
+ * key2_dev receives key(a)^2 rounded toward -inf to float; offs_dev receives 3 int32 per
+ * entry (2D: a_y, a_x, 0).  cap is the capacity of both buffers in entries; *len receives
+ * the entry count, or GAMMAX_E_RADIUS is returned when it would exceed cap.
+ * Synchronises `stream`.
+ */
+gammax_status_t gammax_build_table(gammax_ctx_t *ctx, int32_t ndim, const int64_t *shape,
+                                   const double *spacing_over_dta, double radius,
+                                   float *key2_dev, int32_t *offs_dev, int64_t cap,
+                                   int64_t *len, void *stream);
+
+/*
+ * Pass-rate counts of a gamma map (n floats, device): counts[0] = nodes with gamma >= 0
+ * (evaluated), counts[1] = gamma <= 1, counts[2] = |gamma - 1| <= 1e-5.  Synchronises.
+ */
+gammax_status_t gammax_pass_count(gammax_ctx_t *ctx, const float *gamma_dev, int64_t n,
+                                  uint64_t *counts, void *stream);
+
+/* Static description of a status code. */
+const char *gammax_status_string(gammax_status_t status);
+
+/* Detail of the last failure on this context (HIP error text etc.); never NULL. */
+const char *gammax_last_error(const gammax_ctx_t *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GAMMAX_H */

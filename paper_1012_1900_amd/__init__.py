@@ -1,0 +1,19 @@
+"""gammax: gamma-index dose comparison on AMD Instinct MI355X (gfx950).
+
+The method of Gu, Jia & Jiang, "GPU-based fast gamma index calculation" (Sec. 2,
+Algorithms A1/A2), computed by the hand-written HIP kernels of ``libgammax.so``.
+This package is the thin Python binding of its C ABI (``include/gammax.h``).
+"""
+from ._abi import (  # noqa: F401
+    Context,
+    GammaResult,
+    GammaxError,
+    build_table,
+    context,
+    gamma_map,
+    gammax_map,
+    pass_count,
+    sort_pairs,
+    status_string,
+    LIB_PATH,
+)

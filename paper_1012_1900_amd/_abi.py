@@ -1,0 +1,347 @@
+"""ctypes binding of libgammax (declared in include/gammax.h).
+
+Argument marshalling only: every step of the gamma computation runs in the library's
+HIP kernels.  PyTorch supplies device memory (tensors' data pointers) and the current
+HIP stream.  Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import threading
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libgammax.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libgammax.so is not built ({LIB_PATH}); run `python -m paper_1012_1900_amd._build` "
+        "or __graft_entry__.build() first")
+
+_lib = C.CDLL(LIB_PATH)
+
+# ---- status codes (gammax_status_t) ------------------------------------------------------
+OK = 0
+E_NULL = -1
+E_SHAPE = -2
+E_PARAM = -3
+E_NONFINITE = -4
+E_NOMEM = -5
+E_DEVICE = -6
+E_RADIUS = -7
+E_DOSE = -8
+
+GLOBAL, LOCAL = 0, 1
+SORT_NONE, SORT_DD = 0, 1
+PREC_FP32, PREC_GUARDED, PREC_FP64 = 0, 1, 2
+
+_SORT = {"none": SORT_NONE, "dd": SORT_DD}
+_PREC = {"fp32": PREC_FP32, "guarded": PREC_GUARDED, "fp64": PREC_FP64}
+
+
+class GammaxError(RuntimeError):
+    def __init__(self, status: int, detail: str = ""):
+        self.status = status
+        msg = _lib.gammax_status_string(status).decode()
+        super().__init__(f"gammax status {status}: {msg}" + (f" ({detail})" if detail else ""))
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int32),
+        ("norm", C.c_int32),
+        ("shape", C.c_int64 * 3),
+        ("spacing_mm", C.c_double * 3),
+        ("dd", C.c_double),
+        ("dta_mm", C.c_double),
+        ("dose_threshold", C.c_double),
+    ]
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("sort_mode", C.c_int32),
+        ("precision", C.c_int32),
+        ("cond_threshold", C.c_double),
+        ("timing", C.c_int32),
+        ("reserved", C.c_int32 * 7),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("n_evaluated", C.c_uint64),
+        ("n_pass", C.c_uint64),
+        ("n_borderline", C.c_uint64),
+        ("n_fp64_tets", C.c_uint64),
+        ("n_cells", C.c_uint64),
+        ("pass_rate", C.c_double),
+        ("max_gamma", C.c_float),
+        ("dose_max", C.c_float),
+        ("search_radius", C.c_float),
+        ("table_len", C.c_int32),
+        ("ms_prep", C.c_float),
+        ("ms_table", C.c_float),
+        ("ms_sort", C.c_float),
+        ("ms_search", C.c_float),
+        ("ms_guard", C.c_float),
+    ]
+
+
+_vp = C.c_void_p
+_lib.gammax_options_default.restype = None
+_lib.gammax_options_default.argtypes = [C.POINTER(Options)]
+_lib.gammax_ctx_create.restype = C.c_int
+_lib.gammax_ctx_create.argtypes = [C.c_int, C.POINTER(_vp)]
+_lib.gammax_ctx_destroy.restype = C.c_int
+_lib.gammax_ctx_destroy.argtypes = [_vp]
+_lib.gammax_map.restype = C.c_int
+_lib.gammax_map.argtypes = [_vp, C.POINTER(Problem), C.POINTER(Options), _vp, _vp, _vp,
+                            C.POINTER(Result), _vp]
+_lib.gamma_map.restype = C.c_int
+_lib.gamma_map.argtypes = [_vp, _vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                           C.c_double, C.c_double, C.c_double, C.c_int32, _vp,
+                           C.POINTER(C.c_double), _vp]
+_lib.gammax_sort_pairs.restype = C.c_int
+_lib.gammax_sort_pairs.argtypes = [_vp, _vp, _vp, C.c_int64, _vp]
+_lib.gammax_build_table.restype = C.c_int
+_lib.gammax_build_table.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                    C.c_double, _vp, _vp, C.c_int64, C.POINTER(C.c_int64), _vp]
+_lib.gammax_pass_count.restype = C.c_int
+_lib.gammax_pass_count.argtypes = [_vp, _vp, C.c_int64, C.POINTER(C.c_uint64), _vp]
+_lib.gammax_status_string.restype = C.c_char_p
+_lib.gammax_status_string.argtypes = [C.c_int]
+_lib.gammax_last_error.restype = C.c_char_p
+_lib.gammax_last_error.argtypes = [_vp]
+
+
+def status_string(status: int) -> str:
+    return _lib.gammax_status_string(status).decode()
+
+
+def default_options() -> Options:
+    o = Options()
+    _lib.gammax_options_default(C.byref(o))
+    return o
+
+
+class Context:
+    """A library context on one HIP device (owns scratch memory and the table cache)."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        st = _lib.gammax_ctx_create(int(device), C.byref(h))
+        if st != OK:
+            raise GammaxError(st, f"device {device}")
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if self.handle:
+            _lib.gammax_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st: int):
+        if st != OK:
+            raise GammaxError(st, _lib.gammax_last_error(self.handle).decode())
+
+
+_ctx_lock = threading.Lock()
+_contexts = {}
+
+
+def context(device: int) -> Context:
+    with _ctx_lock:
+        c = _contexts.get(device)
+        if c is None:
+            c = _contexts[device] = Context(device)
+        return c
+
+
+@dataclass
+class GammaResult:
+    n_evaluated: int
+    n_pass: int
+    n_borderline: int
+    n_fp64_tets: int
+    n_cells: int
+    pass_rate: float
+    max_gamma: float
+    dose_max: float
+    search_radius: float
+    table_len: int
+    ms_prep: float
+    ms_table: float
+    ms_sort: float
+    ms_search: float
+    ms_guard: float
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_tensor(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device (cuda/hip) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def make_problem(shape: Sequence[int], spacing: Sequence[float], dd: float, dta: float,
+                 dose_threshold: float, local: bool) -> Problem:
+    p = Problem()
+    nd = len(shape)
+    p.ndim = nd
+    p.norm = LOCAL if local else GLOBAL
+    for i in range(3):
+        p.shape[i] = int(shape[i]) if i < nd else 0
+        p.spacing_mm[i] = float(spacing[i]) if i < nd else 0.0
+    p.dd, p.dta_mm, p.dose_threshold = float(dd), float(dta), float(dose_threshold)
+    return p
+
+
+def make_options(sort: str = "dd", precision: str = "guarded", cond_threshold: float = 1e6,
+                 timing: bool = False) -> Options:
+    o = default_options()
+    o.sort_mode = _SORT[sort]
+    o.precision = _PREC[precision]
+    o.cond_threshold = float(cond_threshold)
+    o.timing = 1 if timing else 0
+    return o
+
+
+def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
+               dose_threshold: float = 0.1, local: bool = False, *, sort: str = "dd",
+               precision: str = "guarded", cond_threshold: float = 1e6, timing: bool = False,
+               out=None, ctx: Optional[Context] = None, stream=None):
+    """Gamma map of a dose pair on the GPU.  Returns (gamma tensor, GammaResult).
+
+    ``ref``/``ev``: float32 device tensors of shape (ny, nx) or (nz, ny, nx); ``spacing``
+    in mm in the same axis order.  gamma is -1 where a node is not evaluated.
+    """
+    torch = _torch()
+    _dev_tensor(ref, "ref")
+    _dev_tensor(ev, "ev")
+    if ref.shape != ev.shape or ref.device != ev.device:
+        raise ValueError("ref and ev must share shape and device")
+    if len(spacing) != ref.dim():
+        raise ValueError("spacing needs one entry per axis")
+    if out is None:
+        out = torch.empty_like(ref)
+    else:
+        _dev_tensor(out, "out")
+        if out.shape != ref.shape or out.device != ref.device:
+            raise ValueError("out must match ref")
+    dev = ref.device.index if ref.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or context(dev)
+    p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
+    o = make_options(sort, precision, cond_threshold, timing)
+    r = Result()
+    s = stream if stream is not None else torch.cuda.current_stream(ref.device)
+    with torch.cuda.device(ref.device):
+        st = _lib.gammax_map(ctx.handle, C.byref(p), C.byref(o), ref.data_ptr(), ev.data_ptr(),
+                             out.data_ptr(), C.byref(r), _vp(s.cuda_stream))
+    ctx.check(st)
+    res = GammaResult(**{f[0]: getattr(r, f[0]) for f in Result._fields_})
+    return out, res
+
+
+def gamma_map(ref_dose, eval_dose, spacing: Sequence[float], dd: float, dta: float,
+              dose_threshold: float = 0.1, local: bool = False) -> Tuple[object, float]:
+    """The paper's problem statement: (gamma tensor, pass rate) with default options,
+    through the flat C entry point ``gamma_map``."""
+    torch = _torch()
+    _dev_tensor(ref_dose, "ref_dose")
+    _dev_tensor(eval_dose, "eval_dose")
+    if ref_dose.shape != eval_dose.shape:
+        raise ValueError("ref_dose and eval_dose must share a shape")
+    nd = ref_dose.dim()
+    shape = (C.c_int64 * 3)(*(list(ref_dose.shape) + [0] * (3 - nd)))
+    sp = (C.c_double * 3)(*(list(map(float, spacing)) + [0.0] * (3 - nd)))
+    out = torch.empty_like(ref_dose)
+    pr = C.c_double(float("nan"))
+    s = torch.cuda.current_stream(ref_dose.device)
+    with torch.cuda.device(ref_dose.device):
+        st = _lib.gamma_map(ref_dose.data_ptr(), eval_dose.data_ptr(), nd, shape, sp, float(dd),
+                            float(dta), float(dose_threshold), LOCAL if local else GLOBAL,
+                            out.data_ptr(), C.byref(pr), _vp(s.cuda_stream))
+    if st != OK:
+        raise GammaxError(st)
+    return out, pr.value
+
+
+def sort_pairs(keys, vals, ctx: Optional[Context] = None):
+    """Stable ascending sort of uint32 (key, value) pairs in place (int32 tensors holding
+    the uint32 bit patterns)."""
+    torch = _torch()
+    for t, nm in ((keys, "keys"), (vals, "vals")):
+        if t.device.type != "cuda" or t.dtype != torch.int32 or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous int32 device tensor")
+    if keys.numel() != vals.numel():
+        raise ValueError("keys and vals differ in length")
+    ctx = ctx or context(keys.device.index or 0)
+    s = torch.cuda.current_stream(keys.device)
+    with torch.cuda.device(keys.device):
+        st = _lib.gammax_sort_pairs(ctx.handle, keys.data_ptr(), vals.data_ptr(), keys.numel(),
+                                    _vp(s.cuda_stream))
+    ctx.check(st)
+    return keys, vals
+
+
+def build_table(shape: Sequence[int], spacing_over_dta: Sequence[float], radius: float,
+                cap: Optional[int] = None, device: int = 0, ctx: Optional[Context] = None):
+    """Sorted cell table: (key2 float32 tensor [T], offsets int32 tensor [T, 3])."""
+    torch = _torch()
+    nd = len(shape)
+    if cap is None:
+        cap = 1
+        for i in range(nd):
+            r = int(math.ceil(radius / spacing_over_dta[i])) + 1
+            cap *= min(2 * r + 2, 2 * int(shape[i]) - 1)
+    dev = torch.device("cuda", device)
+    key2 = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    offs = torch.empty((max(cap, 1), 3), dtype=torch.int32, device=dev)
+    n = C.c_int64(0)
+    shp = (C.c_int64 * 3)(*(list(shape) + [0] * (3 - nd)))
+    sp = (C.c_double * 3)(*(list(map(float, spacing_over_dta)) + [0.0] * (3 - nd)))
+    ctx = ctx or context(device)
+    s = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        st = _lib.gammax_build_table(ctx.handle, nd, shp, sp, float(radius), key2.data_ptr(),
+                                     offs.data_ptr(), int(cap), C.byref(n), _vp(s.cuda_stream))
+    ctx.check(st)
+    return key2[: n.value], offs[: n.value]
+
+
+def pass_count(gamma, ctx: Optional[Context] = None) -> Tuple[int, int, int]:
+    """(evaluated, pass, borderline) counts of a gamma map on the device."""
+    torch = _torch()
+    _dev_tensor(gamma, "gamma")
+    ctx = ctx or context(gamma.device.index or 0)
+    counts = (C.c_uint64 * 3)()
+    s = torch.cuda.current_stream(gamma.device)
+    with torch.cuda.device(gamma.device):
+        st = _lib.gammax_pass_count(ctx.handle, gamma.data_ptr(), gamma.numel(), counts,
+                                    _vp(s.cuda_stream))
+    ctx.check(st)
+    return int(counts[0]), int(counts[1]), int(counts[2])
+
+
+def raw_library() -> C.CDLL:
+    """The loaded shared library (for symbol checks)."""
+    return _lib

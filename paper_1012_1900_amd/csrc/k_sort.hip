@@ -1,0 +1,161 @@
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 4 passes of 8 bits.
+//
+// Used for the DD sort of the reference nodes (Algorithm A2 step 3) and for the cell
+// table (step 5).  Per pass: a per-tile digit histogram (LDS atomics), a per-digit scan
+// over tiles, and a stable scatter in which each wave ranks its 64 elements by digit
+// with eight ballots (lanes sharing a digit form a peer mask) and the LDS holds the
+// running per-digit offsets of the tile.
+#include "internal.hpp"
+
+namespace gammax {
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_CHUNKS = 16;
+constexpr int SORT_TILE = SORT_THREADS * SORT_CHUNKS;
+constexpr int RADIX = 256;
+constexpr int NWAVES = SORT_THREADS / WAVE;
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                             int64_t n, int shift,
+                                                             uint32_t* __restrict__ hist,
+                                                             int64_t nb) {
+    __shared__ uint32_t h[RADIX];
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+#pragma unroll 4
+    for (int k = 0; k < SORT_CHUNKS; ++k) {
+        int64_t i = base + (int64_t)k * SORT_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Block-wide exclusive scan of one value per thread; returns the exclusive prefix and
+// writes the block total to *total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave,
+                                                         uint32_t* total) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    uint32_t x = v;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        uint32_t y = (uint32_t)__shfl_up((int)x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == WAVE - 1) s_wave[w] = x;
+    __syncthreads();
+    uint32_t off = 0u, tot = 0u;
+    for (int j = 0; j < NWAVES; ++j) {
+        uint32_t c = s_wave[j];
+        if (j < w) off += c;
+        tot += c;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+// One workgroup per digit: exclusive scan of that digit's counts over the tiles.
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scan(uint32_t* __restrict__ hist, int64_t nb,
+                                                             uint32_t* __restrict__ totals) {
+    __shared__ uint32_t s_wave[NWAVES];
+    uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+    uint32_t carry = 0u;
+    for (int64_t b0 = 0; b0 < nb; b0 += SORT_THREADS) {
+        int64_t i = b0 + threadIdx.x;
+        uint32_t v = i < nb ? row[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan(v, s_wave, &tot);
+        if (i < nb) row[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, int64_t n, int shift, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ totals, int64_t nb) {
+    __shared__ uint32_t s_base[RADIX];
+    __shared__ uint32_t s_wcnt[NWAVES][RADIX];
+    __shared__ uint32_t s_wave[NWAVES];
+    const int t = threadIdx.x;
+    {
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan(totals[t], s_wave, &tot);
+        s_base[t] = ex + hist[(int64_t)t * nb + blockIdx.x];
+        for (int w = 0; w < NWAVES; ++w) s_wcnt[w][t] = 0u;
+    }
+    __syncthreads();
+    const int lane = t & (WAVE - 1), w = t / WAVE;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    for (int k = 0; k < SORT_CHUNKS; ++k) {
+        const int64_t i = base + (int64_t)k * SORT_THREADS + t;
+        const bool valid = i < n;
+        uint32_t key = 0u, val = 0u;
+        if (valid) {
+            key = kin[i];
+            val = vin[i];
+        }
+        const uint32_t dig = (key >> shift) & (RADIX - 1);
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const unsigned long long m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0u) s_wcnt[w][dig] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = s_base[dig] + rank;
+            for (int j = 0; j < w; ++j) pos += s_wcnt[j][dig];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0u;
+        for (int j = 0; j < NWAVES; ++j) {
+            add += s_wcnt[j][t];
+            s_wcnt[j][t] = 0u;
+        }
+        s_base[t] += add;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int64_t sort_hist_words(int64_t n) {
+    const int64_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+    return (int64_t)RADIX * (nb > 0 ? nb : 1) + RADIX;
+}
+
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
+                            int64_t n, uint32_t* hist, hipStream_t s) {
+    if (n <= 1) return hipSuccess;
+    const int64_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+    uint32_t* totals = hist + (int64_t)RADIX * nb;
+    uint32_t *ki = keys, *vi = vals, *ko = tmp_keys, *vo = tmp_vals;
+    for (int shift = 0; shift < 32; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(SORT_THREADS), 0, s, ki, n, shift,
+                           hist, nb);
+        hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nb, totals);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo,
+                           n, shift, hist, totals, nb);
+        uint32_t* tk = ki;
+        ki = ko;
+        ko = tk;
+        uint32_t* tv = vi;
+        vi = vo;
+        vo = tv;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gammax

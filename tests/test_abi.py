@@ -1,0 +1,97 @@
+"""The C ABI library: it loads, exports every function include/gammax.h declares, and
+rejects bad arguments on the host before touching a device (no GPU needed)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gammax.h")
+
+
+@pytest.fixture(scope="module")
+def abi():
+    lib_path = os.path.join(ROOT, "paper_1012_1900_amd", "lib", "libgammax.so")
+    if not os.path.exists(lib_path):
+        from paper_1012_1900_amd import _build
+        _build.build()
+    from paper_1012_1900_amd import _abi
+    return _abi
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+char\s*\*|gammax_status_t|void)\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["gamma_map", "gammax_map", "gammax_ctx_create", "gammax_ctx_destroy",
+                 "gammax_sort_pairs", "gammax_build_table", "gammax_pass_count",
+                 "gammax_status_string", "gammax_last_error", "gammax_options_default"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(abi):
+    lib = abi.raw_library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_options_defaults(abi):
+    o = abi.default_options()
+    assert o.sort_mode == abi.SORT_DD
+    assert o.precision == abi.PREC_GUARDED
+    assert o.cond_threshold == 1e6
+    assert o.timing == 0 and list(o.reserved) == [0] * 7
+
+
+def test_status_strings(abi):
+    for st in range(0, -9, -1):
+        s = abi.status_string(st)
+        assert s and s != "unknown status"
+    assert abi.status_string(-99) == "unknown status"
+
+
+def _flat(abi, ndim=2, shape=(16, 16), spacing=(1.0, 1.0), dd=0.03, dta=3.0, thr=0.1, norm=0,
+          ptr=1):
+    lib = abi.raw_library()
+    sh = (C.c_int64 * 3)(*(list(shape) + [0] * (3 - len(shape))))
+    sp = (C.c_double * 3)(*(list(spacing) + [0.0] * (3 - len(spacing))))
+    p = C.c_void_p(ptr) if ptr else None
+    return lib.gamma_map(p, p, ndim, sh, sp, dd, dta, thr, norm, p, None, None)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(ptr=0), -1),
+    (dict(ndim=4), -2),
+    (dict(ndim=1), -2),
+    (dict(shape=(1, 16)), -2),
+    (dict(ndim=3, shape=(2, 2, 1)), -2),
+    (dict(ndim=3, shape=(2048, 2048, 2048), spacing=(1, 1, 1)), -2),
+    (dict(spacing=(0.0, 1.0)), -3),
+    (dict(spacing=(1.0, -2.0)), -3),
+    (dict(spacing=(1.0, math.inf)), -3),
+    (dict(dd=0.0), -3),
+    (dict(dd=math.nan), -3),
+    (dict(dta=-1.0), -3),
+    (dict(thr=1.0), -3),
+    (dict(thr=-0.01), -3),
+    (dict(norm=2), -3),
+])
+def test_host_argument_checks(abi, kw, expect):
+    assert _flat(abi, **kw) == expect
+
+
+def test_null_context(abi):
+    lib = abi.raw_library()
+    r = abi.Result()
+    p = abi.make_problem((8, 8), (1.0, 1.0), 0.03, 3.0, 0.1, False)
+    assert lib.gammax_map(None, C.byref(p), None, None, None, None, C.byref(r), None) == abi.E_NULL
+    assert lib.gammax_sort_pairs(None, None, None, 0, None) == abi.E_NULL
+    assert lib.gammax_pass_count(None, None, 0, None, None) == abi.E_NULL
+    assert lib.gammax_ctx_destroy(None) == abi.OK
