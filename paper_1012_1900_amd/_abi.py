@@ -21,6 +21,11 @@ if not os.path.exists(LIB_PATH):
         f"libgammax.so is not built ({LIB_PATH}); run `python -m paper_1012_1900_amd._build` "
         "or __graft_entry__.build() first")
 
+# PyTorch ships its own HIP runtime.  Loading torch first makes the library bind to that
+# same runtime, so device pointers and streams from torch are valid in our calls (two
+# runtimes in one process would not share streams or contexts).
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 # ---- status codes (gammax_status_t) ------------------------------------------------------

@@ -17,8 +17,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions stay disabled (-packed-fp32-ops): the compiler emits only
 # scalar FP32 VALU code.  No fast-math: the search relies on IEEE comparisons and min.
+# Code object v5: loadable by the HIP runtime that PyTorch bundles as well as /opt/rocm's.
 FLAGS = [
     "--offload-arch=gfx950",
+    "-mcode-object-version=5",
     "-O3",
     "-std=c++17",
     "-fPIC",
