@@ -90,7 +90,7 @@ typedef struct {
     uint64_t n_pass;          /* nodes with gamma <= 1 */
     uint64_t n_borderline;    /* nodes with |gamma - 1| <= 1e-5 (their pass decision is precision-bound) */
     uint64_t n_fp64_tets;     /* tetrahedron projections redone in FP64 by the guard */
-    uint64_t n_cells;         /* cells evaluated by the search, summed over nodes */
+    uint64_t n_cells;         /* full grid cells evaluated by the search, summed over nodes */
     double pass_rate;         /* n_pass / n_evaluated (NaN when n_evaluated == 0) */
     float max_gamma;          /* largest gamma found */
     float dose_max;           /* max(D_r) */

@@ -385,7 +385,7 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a, const T
             const bool edge = !(okx && oky && okz);
             const bool wave_masked = __ballot(work && edge) != 0ull;
             if (!work) continue;
-            ++lane_cells;
+            lane_cells += edge ? 0u : 1u;   // full grid cells, the unit of the work count
             const int base = (DIM == 3 ? qz * sxy : 0) + qy * nx + qx;
             const int ox = okx ? 1 : 0, oy = oky ? nx : 0, oz = (DIM == 3 && okz) ? sxy : 0;
             Geo<T> G;
