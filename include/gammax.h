@@ -50,10 +50,15 @@ typedef enum {
 
 typedef enum { GAMMAX_GLOBAL = 0, GAMMAX_LOCAL = 1 } gammax_norm_t;
 
-/* Work order of reference nodes handed to the search (Sec. 2.2; results do not depend on it). */
+/*
+ * Work order of the search (Sec. 2.2; results never depend on it).  Every masked node
+ * first evaluates the 2^d cells with key 0 around it, in grid order; nodes whose bound
+ * then still exceeds the next key continue the walk, in this order:
+ */
 typedef enum {
-    GAMMAX_SORT_NONE = 0,     /* grid order of the masked nodes */
-    GAMMAX_SORT_DD = 1        /* ascending |DD| / dD ("DD sorting" of Algorithm A2 step 3), default */
+    GAMMAX_SORT_NONE = 0,     /* as they were queued (default) */
+    GAMMAX_SORT_DD = 1,       /* ascending |DD| / dD ("DD sorting", Algorithm A2 step 3) */
+    GAMMAX_SORT_BOUND = 2     /* ascending gamma bound after the key-0 cells */
 } gammax_sort_t;
 
 /* Arithmetic of the per-simplex projections. */
@@ -82,7 +87,10 @@ typedef struct {
     int32_t precision;        /* gammax_precision_t */
     double cond_threshold;    /* condition-number bound of the FP64 guard, default 1e6 */
     int32_t timing;           /* 1: time the phases with HIP events (fills ms_* in the result) */
-    int32_t reserved[7];      /* must be 0 */
+    int32_t tail_lanes;       /* lanes that share one node in the walk past the key-0 cells:
+                                 0 = automatic, 1 = one lane per node (the paper's layout),
+                                 8, 16, 32 or 64 = that many table rows of a node at once */
+    int32_t reserved[6];      /* must be 0 */
 } gammax_options_t;
 
 typedef struct {
@@ -91,6 +99,8 @@ typedef struct {
     uint64_t n_borderline;    /* nodes with |gamma - 1| <= 1e-5 (their pass decision is precision-bound) */
     uint64_t n_fp64_tets;     /* tetrahedron projections redone in FP64 by the guard */
     uint64_t n_cells;         /* full grid cells evaluated by the search, summed over nodes */
+    uint64_t n_tail;          /* nodes that walked past the key-0 cells */
+    uint64_t n_guarded;       /* nodes redone because they met an ill-conditioned tetrahedron */
     double pass_rate;         /* n_pass / n_evaluated (NaN when n_evaluated == 0) */
     float max_gamma;          /* largest gamma found */
     float dose_max;           /* max(D_r) */
@@ -98,15 +108,17 @@ typedef struct {
     int32_t table_len;        /* cells in the sorted table used by the search */
     float ms_prep;            /* timing = 1 only: dose max, mask, gamma0, compaction */
     float ms_table;           /*   cell table build (0 when the cached table was reused) */
-    float ms_sort;            /*   DD sort of the reference nodes */
-    float ms_search;          /*   the search kernel (Algorithm A2 step 6), main pass */
-    float ms_guard;           /*   the FP64-guarded pass over nodes that met an ill-conditioned
-                                   tetrahedron (guarded precision, 3D) */
+    float ms_search;          /*   search over the key-0 cells of every node (Algorithm A2 step 6) */
+    float ms_sort;            /*   sort of the nodes that walk further (step 3) */
+    float ms_tail;            /*   their table walk (step 6) */
+    float ms_guard;           /*   FP64-guarded redo of nodes that met an ill-conditioned
+                                   tetrahedron (guarded precision, 3D), and the count reduction */
 } gammax_result_t;
 
 typedef struct gammax_ctx gammax_ctx_t;
 
-/* Fill `opt` with the defaults: DD sort, guarded FP32, cond_threshold 1e6, no timing. */
+/* Fill `opt` with the defaults: no sort, guarded FP32, cond_threshold 1e6, no timing,
+ * automatic tail lanes. */
 void gammax_options_default(gammax_options_t *opt);
 
 /* Create a context bound to HIP device `device`.  *ctx receives the handle. */

@@ -37,6 +37,7 @@ class _Stats(C.Structure):
         ("n_pass", C.c_int64),
         ("n_borderline", C.c_int64),
         ("cells_visited", C.c_int64),
+        ("cells_key0", C.c_int64),
         ("table_len", C.c_int64),
         ("n_masked", C.c_int64),
         ("dose_max", C.c_double),
@@ -78,6 +79,7 @@ class OracleResult:
     n_pass: int
     n_borderline: int
     cells_visited: int
+    cells_key0: int
     table_len: int
     n_masked: int
     dose_max: float
@@ -130,7 +132,7 @@ def gamma(ref: np.ndarray, ev: np.ndarray, spacing: Sequence[float], dd: float, 
         out = out.reshape(ref64.shape)
         cells = cells.reshape(ref64.shape)
     return OracleResult(out, cells, st.n_evaluated, st.n_pass, st.n_borderline, st.cells_visited,
-                        st.table_len, st.n_masked, st.dose_max, st.threshold, st.radius)
+                        st.cells_key0, st.table_len, st.n_masked, st.dose_max, st.threshold, st.radius)
 
 
 def simplex_dist(verts: np.ndarray) -> float:

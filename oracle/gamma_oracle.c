@@ -73,6 +73,7 @@ typedef struct {
     int64_t n_pass;        /* gamma <= 1 */
     int64_t n_borderline;  /* |gamma - 1| <= 1e-5 */
     int64_t cells_visited; /* cells whose simplices were evaluated, summed */
+    int64_t cells_key0;    /* of those, cells with key 0 (the 2^d cells around the node) */
     int64_t table_len;
     int64_t n_masked;      /* masked nodes in the whole grid */
     double dose_max;
@@ -258,7 +259,7 @@ static const int PERM2[2][2] = {{0, 1}, {1, 0}};
 
 static double search_node(const oracle_problem_t *pb, const double *ref, const double *ev,
                           int64_t r, double dD, double gamma0, const cell_entry_t *tab,
-                          int64_t tlen, int32_t *cells, int64_t *n_proj)
+                          int64_t tlen, int32_t *cells, int32_t *cells0, int64_t *n_proj)
 {
     const int nd = pb->ndim;
     const int64_t *n = pb->shape;
@@ -267,7 +268,7 @@ static double search_node(const oracle_problem_t *pb, const double *ref, const d
     for (int i = nd - 1; i >= 0; --i) { rc[i] = rem % n[i]; rem /= n[i]; }
     const double Dr = ref[r];
     double g = gamma0;
-    int32_t visited = 0;
+    int32_t visited = 0, visited0 = 0;
     for (int64_t e = 0; e < tlen; ++e) {
         if (tab[e].key >= g) break;
         int64_t q[3];
@@ -278,6 +279,7 @@ static double search_node(const oracle_problem_t *pb, const double *ref, const d
         }
         if (!inside) continue;
         ++visited;
+        if (tab[e].key == 0.0) ++visited0;
         /* lifted corner coordinates, relative to the reference point */
         double corner[8][AMB];
         for (int b = 0; b < (1 << nd); ++b) {
@@ -317,6 +319,7 @@ static double search_node(const oracle_problem_t *pb, const double *ref, const d
         }
     }
     if (cells) *cells = visited;
+    if (cells0) *cells0 = visited0;
     return g;
 }
 
@@ -370,23 +373,24 @@ int oracle_gamma(const oracle_problem_t *pb, const double *ref, const double *ev
     if (!tab) return ORACLE_E_NOMEM;
 
     const int64_t count = subset ? n_subset : N;
-    int64_t n_eval = 0, n_pass = 0, n_border = 0, cells_total = 0, n_proj = 0;
+    int64_t n_eval = 0, n_pass = 0, n_border = 0, cells_total = 0, cells0_total = 0, n_proj = 0;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
-#pragma omp parallel for schedule(dynamic, 256) reduction(+ : n_eval, n_pass, n_border, cells_total, n_proj)
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : n_eval, n_pass, n_border, cells_total, cells0_total, n_proj)
     for (int64_t k = 0; k < count; ++k) {
         const int64_t r = subset ? subset[k] : k;
         double gout = -1.0;
-        int32_t cells = 0;
+        int32_t cells = 0, cells0 = 0;
         if (r >= 0 && r < N && ref[r] >= t && !(pb->local && !(ref[r] > 0.0))) {
             double dD = pb->local ? pb->dd * ref[r] : dD_global;
             double g0 = fabs(ev[r] - ref[r]) / dD;                 /* step 4a */
-            gout = search_node(pb, ref, ev, r, dD, g0, tab, tlen, &cells, &n_proj);
+            gout = search_node(pb, ref, ev, r, dD, g0, tab, tlen, &cells, &cells0, &n_proj);
             ++n_eval;
             if (gout <= 1.0) ++n_pass;
             if (fabs(gout - 1.0) <= 1e-5) ++n_border;
             cells_total += cells;
+            cells0_total += cells0;
         }
         gamma_out[k] = gout;
         if (cells_out) cells_out[k] = cells;
@@ -397,6 +401,7 @@ int oracle_gamma(const oracle_problem_t *pb, const double *ref, const double *ev
         st->n_pass = n_pass;
         st->n_borderline = n_border;
         st->cells_visited = cells_total;
+        st->cells_key0 = cells0_total;
         st->table_len = tlen;
         st->n_masked = n_masked;
         st->dose_max = dmax;

@@ -40,10 +40,10 @@ E_RADIUS = -7
 E_DOSE = -8
 
 GLOBAL, LOCAL = 0, 1
-SORT_NONE, SORT_DD = 0, 1
+SORT_NONE, SORT_DD, SORT_BOUND = 0, 1, 2
 PREC_FP32, PREC_GUARDED, PREC_FP64 = 0, 1, 2
 
-_SORT = {"none": SORT_NONE, "dd": SORT_DD}
+_SORT = {"none": SORT_NONE, "dd": SORT_DD, "bound": SORT_BOUND}
 _PREC = {"fp32": PREC_FP32, "guarded": PREC_GUARDED, "fp64": PREC_FP64}
 
 
@@ -72,7 +72,8 @@ class Options(C.Structure):
         ("precision", C.c_int32),
         ("cond_threshold", C.c_double),
         ("timing", C.c_int32),
-        ("reserved", C.c_int32 * 7),
+        ("tail_lanes", C.c_int32),
+        ("reserved", C.c_int32 * 6),
     ]
 
 
@@ -83,6 +84,8 @@ class Result(C.Structure):
         ("n_borderline", C.c_uint64),
         ("n_fp64_tets", C.c_uint64),
         ("n_cells", C.c_uint64),
+        ("n_tail", C.c_uint64),
+        ("n_guarded", C.c_uint64),
         ("pass_rate", C.c_double),
         ("max_gamma", C.c_float),
         ("dose_max", C.c_float),
@@ -90,8 +93,9 @@ class Result(C.Structure):
         ("table_len", C.c_int32),
         ("ms_prep", C.c_float),
         ("ms_table", C.c_float),
-        ("ms_sort", C.c_float),
         ("ms_search", C.c_float),
+        ("ms_sort", C.c_float),
+        ("ms_tail", C.c_float),
         ("ms_guard", C.c_float),
     ]
 
@@ -179,6 +183,8 @@ class GammaResult:
     n_borderline: int
     n_fp64_tets: int
     n_cells: int
+    n_tail: int
+    n_guarded: int
     pass_rate: float
     max_gamma: float
     dose_max: float
@@ -186,8 +192,9 @@ class GammaResult:
     table_len: int
     ms_prep: float
     ms_table: float
-    ms_sort: float
     ms_search: float
+    ms_sort: float
+    ms_tail: float
     ms_guard: float
 
 
@@ -220,20 +227,21 @@ def make_problem(shape: Sequence[int], spacing: Sequence[float], dd: float, dta:
     return p
 
 
-def make_options(sort: str = "dd", precision: str = "guarded", cond_threshold: float = 1e6,
-                 timing: bool = False) -> Options:
+def make_options(sort: str = "none", precision: str = "guarded", cond_threshold: float = 1e6,
+                 timing: bool = False, tail_lanes: int = 0) -> Options:
     o = default_options()
     o.sort_mode = _SORT[sort]
     o.precision = _PREC[precision]
     o.cond_threshold = float(cond_threshold)
     o.timing = 1 if timing else 0
+    o.tail_lanes = int(tail_lanes)
     return o
 
 
 def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
-               dose_threshold: float = 0.1, local: bool = False, *, sort: str = "dd",
+               dose_threshold: float = 0.1, local: bool = False, *, sort: str = "none",
                precision: str = "guarded", cond_threshold: float = 1e6, timing: bool = False,
-               out=None, ctx: Optional[Context] = None, stream=None):
+               tail_lanes: int = 0, out=None, ctx: Optional[Context] = None, stream=None):
     """Gamma map of a dose pair on the GPU.  Returns (gamma tensor, GammaResult).
 
     ``ref``/``ev``: float32 device tensors of shape (ny, nx) or (nz, ny, nx); ``spacing``
@@ -255,7 +263,7 @@ def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
     dev = ref.device.index if ref.device.index is not None else torch.cuda.current_device()
     ctx = ctx or context(dev)
     p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
-    o = make_options(sort, precision, cond_threshold, timing)
+    o = make_options(sort, precision, cond_threshold, timing, tail_lanes)
     r = Result()
     s = stream if stream is not None else torch.cuda.current_stream(ref.device)
     with torch.cuda.device(ref.device):

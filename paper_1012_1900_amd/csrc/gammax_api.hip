@@ -1,5 +1,14 @@
 // C ABI of libgammax: argument checks, the per-context workspace and cell-table cache,
 // and the device pipeline of one gamma map (Algorithm A2 steps 2-7).
+//
+// Two ways through a call:
+//  * steady state (the cached cell table fits this grid and spacing): every kernel is
+//    queued without a host round trip (the masked count M and the radius stay on the
+//    device; the grids are sized for all N nodes) and, without timing, replayed from a
+//    captured HIP graph.  One synchronisation at the end returns the counts.  If the
+//    radius turned out larger than the cached table covers, the call is redone below.
+//  * table build: the compaction runs first, the host reads M and R, builds the sorted
+//    cell table for R (cached with headroom), then queues the search.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -11,34 +20,62 @@
 
 using namespace gammax;
 
+namespace {
+
+// Everything a captured graph depends on; a new capture is made when any of it changes.
+struct GraphKey {
+    const void* ref;
+    const void* ev;
+    const void* gamma;
+    int32_t ndim, norm;
+    int64_t shape[3];
+    double spacing[3], dd, dta, thr;
+    int32_t sort_mode, precision, tail_lanes, timing;
+    double cond_threshold;
+    uint64_t generation;   // bumped on every (re)allocation and table build
+};
+
+}  // namespace
+
 struct gammax_ctx {
     int device = 0;
     std::string err;
+    uint64_t generation = 1;
     // per-call scalars
     Scalars* d_sc = nullptr;
     Scalars* h_sc = nullptr;  // pinned
     unsigned long long* d_cnt = nullptr;
     unsigned long long* h_cnt = nullptr;  // pinned
     uint32_t* d_count = nullptr;
-    uint32_t* h_count = nullptr;  // pinned
-    // node work list and sort scratch
-    uint32_t *keys = nullptr, *vals = nullptr, *tkeys = nullptr, *tvals = nullptr;
-    int64_t item_cap = 0;
-    uint32_t* blockcnt = nullptr;
+    uint32_t* h_count = nullptr;  // pinned (also receives the table's first non-zero key^2)
+    // node work lists: 8 arrays of work_cap uint32 in one allocation
+    uint32_t* work = nullptr;
+    int64_t work_cap = 0;
+    uint32_t* blockcnt = nullptr;   // prep tiles: counts, then maxima
     int64_t blk_cap = 0;
+    uint32_t* part = nullptr;       // dose-max partials
+    int64_t part_cap = 0;
     uint32_t* hist = nullptr;
     int64_t hist_cap = 0;
+    BlockSums* sums = nullptr;
+    int64_t sums_cap = 0;
     // cell table cache
     TabEntry* tab = nullptr;
     int64_t tab_cap = 0;
     int64_t tab_len = 0;
+    float tab_k1 = INFINITY;        // key^2 of the first row after the zero-key cells
     bool tab_valid = false;
     TableGeom tab_geom{};
-    uint32_t *tb_keys = nullptr, *tb_vals = nullptr, *tb_tk = nullptr, *tb_tv = nullptr;
+    uint32_t* tb = nullptr;         // table build scratch: 4 arrays of tb_cap
     int64_t tb_cap = 0;
     uint32_t* tb_hist = nullptr;
     int64_t tb_hist_cap = 0;
-    hipEvent_t ev[8] = {};
+    // graph of the steady-state pipeline
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    GraphKey graph_key{};
+    bool graph_broken = false;      // capture failed once: launch directly from then on
+    hipEvent_t ev[10] = {};
     bool events = false;
 };
 
@@ -72,16 +109,18 @@ gammax_status_t fail(gammax_ctx* c, gammax_status_t st, const std::string& why) 
                         std::string(#call) + ": " + hipGetErrorString(e_));                 \
     } while (0)
 
+// Grow a device buffer to `need` elements (contents are not kept).
 template <typename P>
 gammax_status_t grow(gammax_ctx* c, P** p, int64_t* cap, int64_t need) {
     if (need <= *cap && *p) return GAMMAX_OK;
+    ++c->generation;
     if (*p) {
         hipError_t e = hipFree(*p);
         *p = nullptr;
         *cap = 0;
         if (e != hipSuccess) return fail(c, GAMMAX_E_DEVICE, std::string("hipFree: ") + hipGetErrorString(e));
     }
-    int64_t n = need > 0 ? need : 1;
+    const int64_t n = need > 0 ? need : 1;
     hipError_t e = hipMalloc((void**)p, (size_t)n * sizeof(P));
     if (e != hipSuccess) {
         *p = nullptr;
@@ -91,27 +130,16 @@ gammax_status_t grow(gammax_ctx* c, P** p, int64_t* cap, int64_t need) {
     return GAMMAX_OK;
 }
 
-// Four uint32 buffers of one capacity (keys, values and their sort ping-pong copies).
-gammax_status_t grow4(gammax_ctx* c, uint32_t** a, uint32_t** b, uint32_t** d, uint32_t** e, int64_t* cap,
-                      int64_t need) {
-    if (need <= *cap && *a) return GAMMAX_OK;
-    uint32_t** bufs[4] = {a, b, d, e};
-    for (uint32_t** p : bufs) {
-        if (*p) (void)hipFree(*p);
-        *p = nullptr;
-    }
-    *cap = 0;
-    const int64_t n = need > 0 ? need : 1;
-    for (uint32_t** p : bufs) {
-        hipError_t err = hipMalloc((void**)p, (size_t)n * sizeof(uint32_t));
-        if (err != hipSuccess) {
-            *p = nullptr;
-            return fail(c, GAMMAX_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(err));
-        }
-    }
-    *cap = n;
-    return GAMMAX_OK;
+// The 8 node work arrays share one allocation of 8 * cap words.
+gammax_status_t grow_work(gammax_ctx* c, int64_t n) {
+    if (n <= c->work_cap && c->work) return GAMMAX_OK;
+    int64_t words = c->work ? 8 * c->work_cap : 0;
+    gammax_status_t st = grow(c, &c->work, &words, 8 * (n > 0 ? n : 1));
+    c->work_cap = st == GAMMAX_OK ? words / 8 : 0;
+    return st;
 }
+uint32_t* work_array(gammax_ctx* c, int k) { return c->work + (int64_t)k * c->work_cap; }
+enum { W_NODES, W_TAIL_NODE, W_TAIL_F, W_TAIL_KEY, W_TAIL_POS, W_TMP_K, W_TMP_V, W_GUARD };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -136,13 +164,16 @@ gammax_status_t check_problem(gammax_ctx* c, const gammax_problem_t* p, int64_t*
 }
 
 gammax_status_t check_options(gammax_ctx* c, const gammax_options_t* o) {
-    if (o->sort_mode != GAMMAX_SORT_NONE && o->sort_mode != GAMMAX_SORT_DD)
+    if (o->sort_mode < GAMMAX_SORT_NONE || o->sort_mode > GAMMAX_SORT_BOUND)
         return fail(c, GAMMAX_E_PARAM, "unknown sort_mode");
     if (o->precision < GAMMAX_PREC_FP32 || o->precision > GAMMAX_PREC_FP64)
         return fail(c, GAMMAX_E_PARAM, "unknown precision");
     if (!(o->cond_threshold >= 1.0)) return fail(c, GAMMAX_E_PARAM, "cond_threshold must be >= 1");
     if (o->timing != 0 && o->timing != 1) return fail(c, GAMMAX_E_PARAM, "timing must be 0 or 1");
-    for (int i = 0; i < 7; ++i)
+    const int tl = o->tail_lanes;
+    if (!(tl == 0 || tl == 1 || tl == 8 || tl == 16 || tl == 32 || tl == 64))
+        return fail(c, GAMMAX_E_PARAM, "tail_lanes must be 0, 1, 8, 16, 32 or 64");
+    for (int i = 0; i < 6; ++i)
         if (o->reserved[i] != 0) return fail(c, GAMMAX_E_PARAM, "reserved option fields must be 0");
     return GAMMAX_OK;
 }
@@ -158,23 +189,46 @@ bool same_geom(const TableGeom& a, const TableGeom& b) {
     return true;
 }
 
+float round_down_float(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+
 // Build the sorted cell table for `g` into the context cache (synchronises `s`).
 gammax_status_t build_table(gammax_ctx* c, TableGeom g, hipStream_t s) {
     table_box(g);
     if (g.box > kMaxTableBox)
         return fail(c, GAMMAX_E_RADIUS, "cell table candidate box of " + std::to_string(g.box) + " entries");
     c->tab_valid = false;
+    ++c->generation;
     gammax_status_t st;
-    if ((st = grow4(c, &c->tb_keys, &c->tb_vals, &c->tb_tk, &c->tb_tv, &c->tb_cap, g.box)) != GAMMAX_OK) return st;
+    if (g.box > c->tb_cap || !c->tb) {
+        int64_t words = c->tb ? 4 * c->tb_cap : 0;
+        c->tb_cap = 0;
+        if ((st = grow(c, &c->tb, &words, 4 * g.box)) != GAMMAX_OK) return st;
+        c->tb_cap = words / 4;
+    }
     if ((st = grow(c, &c->tb_hist, &c->tb_hist_cap, sort_hist_words(g.box))) != GAMMAX_OK) return st;
+    uint32_t* keys = c->tb;
+    uint32_t* vals = c->tb + c->tb_cap;
+    uint32_t* tk = c->tb + 2 * c->tb_cap;
+    uint32_t* tv = c->tb + 3 * c->tb_cap;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c->d_count);
-    HIPCHK(c, launch_table_gen(g, c->tb_keys, c->tb_vals, c->d_count, s));
-    HIPCHK(c, radix_sort_pairs(c->tb_keys, c->tb_vals, c->tb_tk, c->tb_tv, g.box, c->tb_hist, s));
+    HIPCHK(c, launch_table_gen(g, keys, vals, c->d_count, s));
+    HIPCHK(c, radix_sort_pairs(keys, vals, tk, tv, g.box, nullptr, c->tb_hist, s));
     HIPCHK(c, hipMemcpyAsync(c->h_count, c->d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     const int64_t T = *c->h_count;
     if ((st = grow(c, &c->tab, &c->tab_cap, T)) != GAMMAX_OK) return st;
-    HIPCHK(c, launch_table_rows(g, c->tb_vals, T, c->tab, s));
+    HIPCHK(c, launch_table_rows(g, vals, T, c->tab, s));
+    const int zero_rows = g.ndim == 3 ? 8 : 4;
+    c->tab_k1 = INFINITY;
+    if (T > zero_rows) {
+        HIPCHK(c, hipMemcpyAsync(c->h_count, &c->tab[zero_rows].key2, sizeof(float), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        std::memcpy(&c->tab_k1, c->h_count, sizeof(float));
+    }
     c->tab_len = T;
     c->tab_geom = g;
     c->tab_valid = true;
@@ -200,8 +254,213 @@ gammax_status_t ensure_events(gammax_ctx* c) {
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();   // do not leave an ignored error for the caller's next check
+        return 0.0f;
+    }
     return ms;
+}
+
+struct CallSetup {
+    const gammax_problem_t* p;
+    const gammax_options_t* opt;
+    const float* ref;
+    const float* ev;
+    float* gamma;
+    int64_t n;
+};
+
+// Queue the compaction (Kernel 1).  ev0/ev1 (optional) bracket it.
+gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const int64_t ntiles = (cs.n + PREP_TILE - 1) / PREP_TILE;
+    if (ev0) HIPCHK(c, hipEventRecord(ev0, s));
+    PrepArgs pa{};
+    pa.ref = cs.ref;
+    pa.ev = cs.ev;
+    pa.gamma = cs.gamma;
+    pa.n = cs.n;
+    pa.thr = (float)cs.p->dose_threshold;
+    pa.dd = (float)cs.p->dd;
+    pa.local = cs.p->norm == GAMMAX_LOCAL ? 1 : 0;
+    pa.sc = c->d_sc;
+    pa.part = c->part;
+    pa.blockcnt = c->blockcnt;
+    pa.blockmax = c->blockcnt + ntiles;
+    pa.nodes = work_array(c, W_NODES);
+    pa.sums = c->sums;
+    HIPCHK(c, launch_prep(pa, s));
+    if (ev1) HIPCHK(c, hipEventRecord(ev1, s));
+    return GAMMAX_OK;
+}
+
+// Queue the search (steps 3, 6, 7) over at most m_bound nodes with the cached table.
+gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bound, float r2_cap,
+                               hipStream_t s, bool timing) {
+    const gammax_problem_t* p = cs.p;
+    const gammax_options_t& opt = *cs.opt;
+    SearchArgs sa{};
+    sa.ref = cs.ref;
+    sa.ev = cs.ev;
+    sa.gamma = cs.gamma;
+    sa.sc = c->d_sc;
+    sa.tab = c->tab;
+    sa.tab_len = c->tab_valid ? (int)c->tab_len : 0;
+    if (p->ndim == 3) {
+        sa.nz = (int)p->shape[0];
+        sa.ny = (int)p->shape[1];
+        sa.nx = (int)p->shape[2];
+    } else {
+        sa.nz = 1;
+        sa.ny = (int)p->shape[0];
+        sa.nx = (int)p->shape[1];
+    }
+    sa.dd = (float)p->dd;
+    sa.dd64 = p->dd;
+    sa.local = p->norm == GAMMAX_LOCAL ? 1 : 0;
+    const int nd = p->ndim;
+    const double sx = p->spacing_mm[nd - 1] / p->dta_mm, sy = p->spacing_mm[nd - 2] / p->dta_mm;
+    const double sz = nd == 3 ? p->spacing_mm[0] / p->dta_mm : 0.0;
+    sa.sx = sx;
+    sa.sy = sy;
+    sa.sz = sz;
+    sa.s2x = (float)(sx * sx);
+    sa.s2y = (float)(sy * sy);
+    sa.s2z = (float)(sz * sz);
+    double smin = std::fmin(sx, sy), smax = std::fmax(sx, sy);
+    if (nd == 3) {
+        smin = std::fmin(smin, sz);
+        smax = std::fmax(smax, sz);
+    }
+    // kappa(Gram) <= (s_max^2 / s_min^2) * Den for the chain basis of a tetrahedron
+    double guard = opt.cond_threshold * (smin * smin) / (smax * smax);
+    if (opt.precision != GAMMAX_PREC_GUARDED) guard = INFINITY;
+    sa.den_guard = (float)guard;
+    sa.k1 = c->tab_valid ? c->tab_k1 : INFINITY;
+    sa.r2_cap = r2_cap;
+    sa.tail_key = opt.sort_mode == GAMMAX_SORT_BOUND ? 1 : 0;
+    sa.nodes = work_array(c, W_NODES);
+    sa.tail_node = work_array(c, W_TAIL_NODE);
+    sa.tail_f = work_array(c, W_TAIL_F);
+    sa.tail_key_arr = work_array(c, W_TAIL_KEY);
+    sa.tail_pos = work_array(c, W_TAIL_POS);
+    sa.guard_list = work_array(c, W_GUARD);
+    sa.sums = c->sums;
+
+    SearchPlan plan{};
+    plan.ndim = nd;
+    plan.precision = opt.precision;
+    plan.tail_lanes = opt.tail_lanes;
+    plan.M = m_bound;
+    const double s3[3] = {p->spacing_mm[0] / p->dta_mm, p->spacing_mm[1] / p->dta_mm,
+                          nd == 3 ? p->spacing_mm[2] / p->dta_mm : 1.0};
+    for (int k = 0; k < (nd == 3 ? 8 : 4); ++k) {
+        // zero-key cells in table order: offsets in {-1,0}^d, slowest axis first
+        if (nd == 3) table_row_host(3, s3, (k >> 2) - 1, ((k >> 1) & 1) - 1, (k & 1) - 1, &plan.zero.row[k]);
+        else table_row_host(2, s3, 0, (k >> 1) - 1, (k & 1) - 1, &plan.zero.row[k]);
+    }
+    plan.tmp_keys = work_array(c, W_TMP_K);
+    plan.tmp_vals = work_array(c, W_TMP_V);
+    plan.hist = opt.sort_mode == GAMMAX_SORT_NONE ? nullptr : c->hist;
+    if (timing) {
+        HIPCHK(c, hipEventRecord(c->ev[4], s));
+        plan.ev_shell_end = c->ev[5];
+        plan.ev_sort_end = c->ev[6];
+        plan.ev_tail_end = c->ev[7];
+    }
+    HIPCHK(c, launch_search(sa, plan, s));
+    if (timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
+    return GAMMAX_OK;
+}
+
+GraphKey key_of(gammax_ctx* c, const CallSetup& cs) {
+    GraphKey k;
+    std::memset(&k, 0, sizeof(k));
+    k.ref = cs.ref;
+    k.ev = cs.ev;
+    k.gamma = cs.gamma;
+    k.ndim = cs.p->ndim;
+    k.norm = cs.p->norm;
+    for (int i = 0; i < 3; ++i) {
+        k.shape[i] = i < cs.p->ndim ? cs.p->shape[i] : 0;
+        k.spacing[i] = i < cs.p->ndim ? cs.p->spacing_mm[i] : 0.0;
+    }
+    k.dd = cs.p->dd;
+    k.dta = cs.p->dta_mm;
+    k.thr = cs.p->dose_threshold;
+    k.sort_mode = cs.opt->sort_mode;
+    k.precision = cs.opt->precision;
+    k.tail_lanes = cs.opt->tail_lanes;
+    k.timing = cs.opt->timing;
+    k.cond_threshold = cs.opt->cond_threshold;
+    k.generation = c->generation;
+    return k;
+}
+
+void drop_graph(gammax_ctx* c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+}
+
+// Steady state without timing: replay (or capture, then replay) the whole queue.
+gammax_status_t launch_graph(gammax_ctx* c, const CallSetup& cs, uint32_t m_bound, float r2_cap, hipStream_t s) {
+    const GraphKey k = key_of(c, cs);
+    const bool timing = false;
+    if (!c->graph || std::memcmp(&k, &c->graph_key, sizeof(k)) != 0) {
+        drop_graph(c);
+        if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        gammax_status_t st = enqueue_prep(c, cs, c->cap_stream, timing ? c->ev[0] : nullptr,
+                                          timing ? c->ev[1] : nullptr);
+        if (st == GAMMAX_OK) st = enqueue_search(c, cs, m_bound, r2_cap, c->cap_stream, timing);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (st != GAMMAX_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess || !g) return fail(c, GAMMAX_E_DEVICE, "graph capture failed");
+        e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->graph = nullptr;
+            return fail(c, GAMMAX_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        c->graph_key = k;
+    }
+    HIPCHK(c, hipGraphLaunch(c->graph, s));
+    return GAMMAX_OK;
+}
+
+void fill_result(gammax_ctx* c, gammax_result_t* res, bool timing, float ms_table) {
+    const Scalars& h = *c->h_sc;
+    const float r2 = u2f(h.r2_bits);
+    res->n_evaluated = h.n_masked;
+    res->n_pass = h.n_pass;
+    res->n_borderline = h.n_border;
+    res->n_fp64_tets = h.n_fp64;
+    res->n_cells = h.n_cells;
+    res->n_tail = h.n_tail;
+    res->n_guarded = h.n_guard;
+    res->pass_rate = h.n_masked ? (double)h.n_pass / (double)h.n_masked : NAN;
+    res->max_gamma = std::sqrt(u2f(h.maxg2_bits));
+    res->dose_max = ord_to_float(h.dmax_ord);
+    res->search_radius = std::sqrt(r2);
+    res->table_len = (h.n_masked > 0 && r2 > 0.0f) ? (int32_t)c->tab_len : 0;
+    if (timing) {
+        res->ms_prep = elapsed(c->ev[0], c->ev[1]);
+        res->ms_table = ms_table;
+        res->ms_search = elapsed(c->ev[4], c->ev[5]);
+        res->ms_sort = elapsed(c->ev[5], c->ev[6]);
+        res->ms_tail = elapsed(c->ev[6], c->ev[7]);
+        res->ms_guard = elapsed(c->ev[7], c->ev[8]);
+    }
+}
+
+gammax_status_t device_errors(gammax_ctx* c, bool local) {
+    if (c->h_sc->flags & FLAG_NONFINITE) return fail(c, GAMMAX_E_NONFINITE, "a dose value is NaN or infinite");
+    if (!local && !(ord_to_float(c->h_sc->dmax_ord) > 0.0f))
+        return fail(c, GAMMAX_E_DOSE, "max reference dose is not positive");
+    return GAMMAX_OK;
 }
 
 }  // namespace
@@ -211,14 +470,15 @@ extern "C" {
 void gammax_options_default(gammax_options_t* opt) {
     if (!opt) return;
     std::memset(opt, 0, sizeof(*opt));
-    opt->sort_mode = GAMMAX_SORT_DD;
+    opt->sort_mode = GAMMAX_SORT_NONE;
     opt->precision = GAMMAX_PREC_GUARDED;
     opt->cond_threshold = 1e6;
     opt->timing = 0;
+    opt->tail_lanes = 0;
 }
 
 const char* gammax_status_string(gammax_status_t st) {
-    int k = -(int)st;
+    const int k = -(int)st;
     if (k < 0 || k >= (int)(sizeof(kStatusText) / sizeof(kStatusText[0]))) return "unknown status";
     return kStatusText[k];
 }
@@ -251,8 +511,10 @@ gammax_status_t gammax_ctx_destroy(gammax_ctx_t* c) {
     if (!c) return GAMMAX_OK;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    void* dev[] = {c->d_sc, c->d_cnt, c->d_count, c->keys, c->vals, c->tkeys, c->tvals, c->blockcnt,
-                   c->hist, c->tab, c->tb_keys, c->tb_vals, c->tb_tk, c->tb_tv, c->tb_hist};
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    void* dev[] = {c->d_sc, c->d_cnt, c->d_count, c->work, c->blockcnt, c->part, c->hist,
+                   c->sums, c->tab, c->tb, c->tb_hist};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* host[] = {c->h_sc, c->h_cnt, c->h_count};
@@ -281,131 +543,86 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, hipSetDevice(c->device));
     std::memset(res, 0, sizeof(*res));
-
-    // workspace
-    if ((st = grow4(c, &c->keys, &c->vals, &c->tkeys, &c->tvals, &c->item_cap, n)) != GAMMAX_OK) return st;
-    if ((st = grow(c, &c->blockcnt, &c->blk_cap, (n + PREP_TILE - 1) / PREP_TILE)) != GAMMAX_OK) return st;
-    if ((st = grow(c, &c->hist, &c->hist_cap, sort_hist_words(n))) != GAMMAX_OK) return st;
-    if (opt.timing && (st = ensure_events(c)) != GAMMAX_OK) return st;
-
+    const bool timing = opt.timing != 0;
     const bool local = p->norm == GAMMAX_LOCAL;
-    // step 2 (Kernel 1): dose maximum, mask, gamma0, ordered compaction
-    if (opt.timing) HIPCHK(c, hipEventRecord(c->ev[0], s));
-    HIPCHK(c, launch_init_scalars(c->d_sc, s));
-    HIPCHK(c, launch_dose_max(ref, ev, n, c->d_sc, s));
-    PrepArgs pa{};
-    pa.ref = ref;
-    pa.ev = ev;
-    pa.gamma = gamma;
-    pa.n = n;
-    pa.thr = (float)p->dose_threshold;
-    pa.dd = (float)p->dd;
-    pa.local = local ? 1 : 0;
-    pa.sc = c->d_sc;
-    pa.blockcnt = c->blockcnt;
-    pa.keys = c->keys;
-    pa.vals = c->vals;
-    HIPCHK(c, launch_prep(pa, s));
-    if (opt.timing) HIPCHK(c, hipEventRecord(c->ev[1], s));
+
+    // workspace, sized for all n nodes so that the steady path needs no count from the host
+    const int64_t ntiles = (n + PREP_TILE - 1) / PREP_TILE;
+    if ((st = grow_work(c, n)) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->blockcnt, &c->blk_cap, 2 * ntiles)) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->part, &c->part_cap, 2 * MAX_BLOCKS)) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->hist, &c->hist_cap, sort_hist_words(n))) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->sums, &c->sums_cap, search_sums_needed((uint32_t)n))) != GAMMAX_OK) return st;
+    if (timing && (st = ensure_events(c)) != GAMMAX_OK) return st;
+
+    CallSetup cs{p, &opt, ref, ev, gamma, n};
+    const TableGeom g = geom_of(p);
+
+    // steady state: the cached table serves this geometry; no host round trip before the end
+    if (c->tab_valid && same_geom(c->tab_geom, g)) {
+        const float r2_cap = round_down_float(c->tab_geom.r2_cap);
+        // timed calls launch directly: event timestamps are not read back from graph nodes
+        if (timing || c->graph_broken) {
+            if ((st = enqueue_prep(c, cs, s, timing ? c->ev[0] : nullptr, timing ? c->ev[1] : nullptr)) != GAMMAX_OK)
+                return st;
+            if ((st = enqueue_search(c, cs, (uint32_t)n, r2_cap, s, timing)) != GAMMAX_OK) return st;
+        } else {
+            st = launch_graph(c, cs, (uint32_t)n, r2_cap, s);
+            if (st != GAMMAX_OK) {
+                // graph unavailable (remembered unless only the timed capture failed): queue
+                // the kernels directly
+                if (!timing) c->graph_broken = true;
+                drop_graph(c);
+                (void)hipGetLastError();
+                if ((st = enqueue_prep(c, cs, s, timing ? c->ev[0] : nullptr, timing ? c->ev[1] : nullptr)) !=
+                    GAMMAX_OK)
+                    return st;
+                if ((st = enqueue_search(c, cs, (uint32_t)n, r2_cap, s, timing)) != GAMMAX_OK) return st;
+            }
+        }
+        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if ((st = device_errors(c, local)) != GAMMAX_OK) return st;
+        if (!(c->h_sc->flags & FLAG_TABLE_SHORT)) {
+            fill_result(c, res, timing, 0.0f);
+            return GAMMAX_OK;
+        }
+        // the radius outgrew the cached table: build a larger one below and run again
+    }
+
+    // table build: compaction first, then the table for the radius found, then the search
+    if ((st = enqueue_prep(c, cs, s, timing ? c->ev[0] : nullptr, timing ? c->ev[1] : nullptr)) != GAMMAX_OK)
+        return st;
     HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    if (c->h_sc->flags & FLAG_NONFINITE) return fail(c, GAMMAX_E_NONFINITE, "a dose value is NaN or infinite");
-    const float dmax = ord_to_float(c->h_sc->dmax_ord);
-    if (!local && !(dmax > 0.0f)) return fail(c, GAMMAX_E_DOSE, "max reference dose is not positive");
+    if ((st = device_errors(c, local)) != GAMMAX_OK) return st;
     const uint32_t M = c->h_sc->n_masked;
     const float r2 = u2f(c->h_sc->r2_bits);
-
-    // steps 4-5 (Kernel 2 + sort): the cell table, cached while it still covers the radius
     float ms_table = 0.0f;
-    TableGeom g = geom_of(p);
-    const bool need_walk = M > 0 && r2 > 0.0f;
-    if (need_walk && !(c->tab_valid && same_geom(c->tab_geom, g) && c->tab_geom.r2_cap >= (double)r2)) {
-        g.r2_cap = (double)r2 * 1.5;   // headroom so that nearby radii reuse the table
-        if (opt.timing) HIPCHK(c, hipEventRecord(c->ev[2], s));
-        if ((st = build_table(c, g, s)) != GAMMAX_OK) return st;
-        if (opt.timing) {
+    if (M > 0 && r2 > 0.0f) {
+        TableGeom gb = g;
+        gb.r2_cap = (double)r2 * 1.5;   // headroom so that nearby radii reuse the table
+        if (timing) HIPCHK(c, hipEventRecord(c->ev[2], s));
+        if ((st = build_table(c, gb, s)) != GAMMAX_OK) return st;
+        if (timing) {
             HIPCHK(c, hipEventRecord(c->ev[3], s));
             HIPCHK(c, hipEventSynchronize(c->ev[3]));
             ms_table = elapsed(c->ev[2], c->ev[3]);
         }
     }
-
-    // step 3: DD sort of the reference nodes (stable; ties keep grid order)
-    if (opt.timing) HIPCHK(c, hipEventRecord(c->ev[4], s));
-    if (opt.sort_mode == GAMMAX_SORT_DD && M > 1)
-        HIPCHK(c, radix_sort_pairs(c->keys, c->vals, c->tkeys, c->tvals, M, c->hist, s));
-    if (opt.timing) HIPCHK(c, hipEventRecord(c->ev[5], s));
-
-    // step 6 (Kernel 3) with step 7 fused: each lane writes gamma at its node index
     if (M > 0) {
-        SearchArgs sa{};
-        sa.ref = ref;
-        sa.ev = ev;
-        sa.gamma = gamma;
-        sa.order = c->vals;
-        sa.guard_list = c->tkeys;   // free after the sort
-        sa.sc_in = c->d_sc;
-        sa.sc = c->d_sc;
-        sa.tab = c->tab;
-        sa.tab_len = need_walk ? (int)c->tab_len : 0;
-        if (p->ndim == 3) {
-            sa.nz = (int)p->shape[0];
-            sa.ny = (int)p->shape[1];
-            sa.nx = (int)p->shape[2];
-        } else {
-            sa.nz = 1;
-            sa.ny = (int)p->shape[0];
-            sa.nx = (int)p->shape[1];
-        }
-        sa.dd = (float)p->dd;
-        sa.dd64 = p->dd;
-        sa.local = local ? 1 : 0;
-        const int nd = p->ndim;
-        const double sx = p->spacing_mm[nd - 1] / p->dta_mm, sy = p->spacing_mm[nd - 2] / p->dta_mm;
-        const double sz = nd == 3 ? p->spacing_mm[0] / p->dta_mm : 0.0;
-        sa.sx = sx;
-        sa.sy = sy;
-        sa.sz = sz;
-        sa.s2x = (float)(sx * sx);
-        sa.s2y = (float)(sy * sy);
-        sa.s2z = (float)(sz * sz);
-        double smin = std::fmin(sx, sy), smax = std::fmax(sx, sy);
-        if (nd == 3) {
-            smin = std::fmin(smin, sz);
-            smax = std::fmax(smax, sz);
-        }
-        // kappa(Gram) <= (s_max^2 / s_min^2) * Den for the chain basis of a tetrahedron
-        double guard = opt.cond_threshold * (smin * smin) / (smax * smax);
-        if (opt.precision != GAMMAX_PREC_GUARDED) guard = INFINITY;
-        sa.den_guard = (float)guard;
-        HIPCHK(c, launch_search(sa, p->ndim, opt.precision, M, s));
-        if (opt.timing) HIPCHK(c, hipEventRecord(c->ev[6], s));
-        HIPCHK(c, launch_search_guard(sa, p->ndim, opt.precision, s));
-    } else if (opt.timing) {
-        HIPCHK(c, hipEventRecord(c->ev[6], s));
+        const bool walk = r2 > 0.0f && c->tab_valid;
+        const bool keep = c->tab_valid;
+        if (!walk) c->tab_valid = false;   // no table needed (every gamma0 is 0)
+        st = enqueue_search(c, cs, M, INFINITY, s, timing);
+        c->tab_valid = keep;
+        if (st != GAMMAX_OK) return st;
+    } else if (timing) {
+        for (int k = 4; k <= 8; ++k) HIPCHK(c, hipEventRecord(c->ev[k], s));
     }
-    if (opt.timing) HIPCHK(c, hipEventRecord(c->ev[7], s));
     HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-
-    const Scalars& h = *c->h_sc;
-    res->n_evaluated = h.n_masked;
-    res->n_pass = h.n_pass;
-    res->n_borderline = h.n_border;
-    res->n_fp64_tets = h.n_fp64;
-    res->n_cells = h.n_cells;
-    res->pass_rate = h.n_masked ? (double)h.n_pass / (double)h.n_masked : NAN;
-    res->max_gamma = std::sqrt(u2f(h.maxg2_bits));
-    res->dose_max = dmax;
-    res->search_radius = std::sqrt(r2);
-    res->table_len = need_walk ? (int32_t)c->tab_len : 0;
-    if (opt.timing) {
-        res->ms_prep = elapsed(c->ev[0], c->ev[1]);
-        res->ms_table = ms_table;
-        res->ms_sort = elapsed(c->ev[4], c->ev[5]);
-        res->ms_search = elapsed(c->ev[5], c->ev[6]);
-        res->ms_guard = elapsed(c->ev[6], c->ev[7]);
-    }
+    fill_result(c, res, timing, ms_table);
     return GAMMAX_OK;
 }
 
@@ -449,9 +666,10 @@ gammax_status_t gammax_sort_pairs(gammax_ctx_t* c, uint32_t* keys, uint32_t* val
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, hipSetDevice(c->device));
     gammax_status_t st;
-    if ((st = grow4(c, &c->keys, &c->vals, &c->tkeys, &c->tvals, &c->item_cap, n)) != GAMMAX_OK) return st;
+    if ((st = grow_work(c, n)) != GAMMAX_OK) return st;
     if ((st = grow(c, &c->hist, &c->hist_cap, sort_hist_words(n))) != GAMMAX_OK) return st;
-    HIPCHK(c, radix_sort_pairs(keys, vals, c->tkeys, c->tvals, n, c->hist, s));
+    HIPCHK(c, radix_sort_pairs(keys, vals, work_array(c, W_TMP_K), work_array(c, W_TMP_V), n, nullptr,
+                               c->hist, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return GAMMAX_OK;
 }

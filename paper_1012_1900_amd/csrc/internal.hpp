@@ -6,24 +6,34 @@
 
 namespace gammax {
 
-// Device-resident scalars of one gamma_map call.  One copy lives in device memory; the
-// host reads it back once the search has finished.
+// Device-resident scalars of one gamma map.  The host reads them back after the
+// compaction (M, R) and after the search (counts).
 struct Scalars {
     uint32_t dmax_ord;      // max D_r as an order-preserving uint32 (see float_to_ord)
     uint32_t r2_bits;       // max gamma0^2 over masked nodes (non-negative float bits)
     uint32_t n_masked;      // M
     uint32_t flags;         // FLAG_*
-    uint32_t maxg2_bits;    // max gamma^2 found (non-negative float bits)
     float thr_val;          // fl32(fl32(threshold) * max D_r): mask is D_r >= thr_val
     float inv_dd;           // 1 / fl32(DD * max D_r) (global normalisation)
+    uint32_t n_tail;        // nodes whose walk continues past the zero-key cells
     uint32_t n_guard;       // nodes queued for the FP64-guarded pass
+    uint32_t maxg2_bits;    // max gamma^2 found (non-negative float bits)
+    uint32_t pad[3];
     unsigned long long n_pass;
     unsigned long long n_border;
     unsigned long long n_fp64;
     unsigned long long n_cells;
 };
 
-enum : uint32_t { FLAG_NONFINITE = 1u };
+enum : uint32_t { FLAG_NONFINITE = 1u, FLAG_TABLE_SHORT = 2u };
+
+// Per-block partial counts of a search launch; reduced by one finishing block (no
+// contended atomics on a single address).
+struct BlockSums {
+    unsigned long long pass, border, fp64, cells;
+    uint32_t maxg2, pad;
+};
+constexpr int SUM_BINS = 256;   // partial-count slots of one gamma map (zeroed by the prep)
 
 // One row of the sorted cell table.  Everything that depends only on the cell offset
 // and the normalised spacing is precomputed here, so a wave reads it with one scalar
@@ -47,7 +57,7 @@ static_assert(sizeof(TabEntry) == 64, "table entry is one 64-byte row");
 __host__ __device__ inline uint32_t f2u(float f) { return __builtin_bit_cast(uint32_t, f); }
 __host__ __device__ inline float u2f(uint32_t u) { return __builtin_bit_cast(float, u); }
 
-// Order-preserving map of floats onto uint32 (for atomicMax over signed values).
+// Order-preserving map of floats onto uint32 (max over signed values).
 __host__ __device__ inline uint32_t float_to_ord(float f) {
     uint32_t u = f2u(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
@@ -58,8 +68,7 @@ __host__ __device__ inline float ord_to_float(uint32_t o) {
 }
 
 // gamma0^2 of a node, the upper bound every search starts from (Algorithm A1 step 4a).
-// The same expression is used by the compaction and by the search so that both see the
-// same bits.
+// Compaction and search use this one expression, so both see the same bits.
 __device__ __forceinline__ float node_inv_dd(float dr, float inv_dd_global, float dd, int local) {
     return local ? 1.0f / (dd * dr) : inv_dd_global;
 }
@@ -68,7 +77,12 @@ __device__ __forceinline__ float gamma0_sq(float de, float dr, float inv_dd) {
     return g * g;
 }
 
-// ---- launchers (each defined next to its kernels) -------------------------------------
+// ---- prep: dose max, mask, gamma0, ordered compaction ---------------------------------
+
+constexpr int PREP_THREADS = 256;
+constexpr int PREP_ITEMS = 16;
+constexpr int PREP_TILE = PREP_THREADS * PREP_ITEMS;
+constexpr int MAX_BLOCKS = 1024;   // blocks of the grid-stride dose-max reduction
 
 struct PrepArgs {
     const float* ref;
@@ -79,25 +93,26 @@ struct PrepArgs {
     float dd;           // fl32(DD)
     int local;
     Scalars* sc;
-    uint32_t* blockcnt; // one per prep tile
-    uint32_t* keys;     // M entries: gamma0^2 bits
-    uint32_t* vals;     // M entries: node index
+    uint32_t* part;     // 2 * MAX_BLOCKS words: dose-max partials and non-finite flags
+    uint32_t* blockcnt; // one per prep tile: masked count (then its exclusive scan)
+    uint32_t* blockmax; // one per prep tile: max gamma0^2 bits
+    uint32_t* nodes;    // M entries: masked node indices in grid order
+    BlockSums* sums;    // SUM_BINS partial-count slots of the search, zeroed here
 };
 
-constexpr int PREP_THREADS = 256;
-constexpr int PREP_ITEMS = 16;
-constexpr int PREP_TILE = PREP_THREADS * PREP_ITEMS;
-
-hipError_t launch_init_scalars(Scalars* sc, hipStream_t s);
-hipError_t launch_dose_max(const float* ref, const float* ev, int64_t n, Scalars* sc, hipStream_t s);
-hipError_t launch_prep(const PrepArgs& a, hipStream_t s);  // count, scan, emit
+hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_pass_count(const float* gamma, int64_t n, unsigned long long* counts3, hipStream_t s);
 
-// LDS radix sort of (key, value) uint32 pairs.  tmp_* hold n entries each; hist needs
-// sort_hist_words(n) words.  The sorted result ends in keys/vals.
-int64_t sort_hist_words(int64_t n);
+// ---- sort --------------------------------------------------------------------------------
+
+// LDS radix sort of (key, value) uint32 pairs.  n_dev (optional) holds the element count
+// on the device, at most n_max; without it n_max is the count.  tmp_* hold n_max entries;
+// hist needs sort_hist_words(n_max) words.  The result ends in keys/vals.
+int64_t sort_hist_words(int64_t n_max);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
-                            int64_t n, uint32_t* hist, hipStream_t s);
+                            int64_t n_max, const uint32_t* n_dev, uint32_t* hist, hipStream_t s);
+
+// ---- cell table --------------------------------------------------------------------------
 
 struct TableGeom {
     int ndim;
@@ -108,24 +123,23 @@ struct TableGeom {
     int64_t box;        // prod(ext)
 };
 void table_box(TableGeom& g);
-// Fill keys (rounded-down key^2 bits, or 0xFFFFFFFF when key^2 >= r2_cap) and values
-// (box index) for every candidate, counting the kept ones into *count.
 hipError_t launch_table_gen(const TableGeom& g, uint32_t* keys, uint32_t* vals, uint32_t* count,
                             hipStream_t s);
-// Rows of the first n sorted candidates.
 hipError_t launch_table_rows(const TableGeom& g, const uint32_t* vals, int64_t n, TabEntry* rows,
                              hipStream_t s);
 hipError_t launch_table_export(const TabEntry* rows, int64_t n, int ndim, float* key2, int32_t* offs,
                                hipStream_t s);
+// The same row on the host (double, rounded to float like the device rows); used for the
+// zero-key cells, whose constants the first search pass takes as kernel arguments.
+void table_row_host(int ndim, const double s[3], int az, int ay, int ax, TabEntry* out);
+
+// ---- search ------------------------------------------------------------------------------
 
 struct SearchArgs {
     const float* ref;
     const float* ev;
     float* gamma;
-    const uint32_t* order;   // node indices in work order
-    uint32_t* guard_list;    // nodes that met an ill-conditioned tetrahedron (capacity M)
-    const Scalars* sc_in;    // n_masked
-    Scalars* sc;             // counters
+    Scalars* sc;             // inputs n_masked, inv_dd, dmax; counters n_tail, n_guard
     const TabEntry* tab;
     int tab_len;
     int nx, ny, nz;          // nz = 1 in 2D
@@ -133,14 +147,41 @@ struct SearchArgs {
     double dd64;             // DD in double for the FP64 paths
     int local;
     float s2x, s2y, s2z;     // s_i^2, s_i = spacing_i / DTA
-    float den_guard;         // FP64 re-projection when the tetrahedron's Den exceeds this
+    float den_guard;         // FP64 re-projection when a tetrahedron's Den exceeds this
     double sx, sy, sz;       // s_i in double for the FP64 paths
+    float k1;                // key^2 of the first table row after the zero-key cells (+inf: none)
+    float r2_cap;            // the table holds every cell with key^2 < r2_cap
+    int tail_key;            // key of the tail sort: 0 = gamma0^2 (DD sort), 1 = bound after shell 0
+    // work lists
+    const uint32_t* nodes;   // masked nodes in grid order (M)
+    uint32_t* tail_node;     // tail: node index
+    uint32_t* tail_f;        // tail: gamma^2 bound after the zero-key cells (float bits)
+    uint32_t* tail_key_arr;  // tail: sort key
+    uint32_t* tail_pos;      // tail: position (sort payload)
+    uint32_t* guard_list;    // nodes that met an ill-conditioned tetrahedron
+    BlockSums* sums;         // per-block partial counts
 };
-// Main search pass over the M nodes in work order.
-hipError_t launch_search(const SearchArgs& a, int ndim, int precision, uint32_t max_items,
-                         hipStream_t s);
-// Guarded precision only: nodes that met an ill-conditioned tetrahedron, again with FP64
-// re-projection (grid-stride over the device-side list; returns at once when it is empty).
-hipError_t launch_search_guard(const SearchArgs& a, int ndim, int precision, hipStream_t s);
+
+struct ZeroGeo {
+    TabEntry row[8];         // the 2^d zero-key cells in table order
+};
+
+// The whole search on `s`: zero-key pass over all M nodes (grid order), sort of the tail,
+// tail walk from the first non-zero key, FP64-guarded pass (precision 1), count reduction.
+// precision: 0 FP32, 1 guarded FP32, 2 FP64 (one walk over all nodes).
+struct SearchPlan {
+    int ndim, precision;
+    int tail_lanes;          // lanes per node in the tail walk: 1 (one lane per node) or 8..64
+    uint32_t M;
+    ZeroGeo zero;
+    uint32_t* tmp_keys;      // sort scratch, M entries each
+    uint32_t* tmp_vals;
+    uint32_t* hist;          // sort_hist_words(M)
+    hipEvent_t ev_shell_end; // optional: recorded after the zero-key pass
+    hipEvent_t ev_sort_end;  // optional: recorded after the tail sort
+    hipEvent_t ev_tail_end;  // optional: recorded after the tail walk
+};
+int64_t search_sums_needed(uint32_t M);
+hipError_t launch_search(const SearchArgs& a, const SearchPlan& plan, hipStream_t s);
 
 }  // namespace gammax

@@ -326,21 +326,262 @@ __device__ __forceinline__ T cell2(const T* g, const Geo<T>& G, const InvS2<T>& 
     return best;
 }
 
-// MODE 0: FP32.  MODE 1: FP32; a node that meets an ill-conditioned tetrahedron is not
-// written but appended to the guard list.  MODE 2: FP32 with FP64 re-projection of the
-// ill-conditioned tetrahedra (run over the guard list).  MODE 3: FP64 throughout.
-template <int DIM, int MODE>
-__global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a, const TabEntry* __restrict__ tab,
-                                                           const uint32_t* __restrict__ order,
-                                                           const uint32_t* __restrict__ count) {
+// ---------------------------------------------------------------------------------------
+// Work passes.
+//
+// Pass A (zero-key cells, all M nodes in grid order): the 2^d cells with key 0 surround
+// every node, so every lane runs the same work and neighbouring lanes read neighbouring
+// doses.  The 3^d dose neighbourhood is loaded once (all loads issued before the first
+// use) and shared by the 2^d cells.  A node whose bound after these cells is <= the next
+// key^2 is finished (the walk would break there); the others are queued for pass B.
+//
+// Pass B (tail): the queued nodes, sorted by the chosen key (the paper's DD sort:
+// gamma0; or the bound after pass A), walk the table from the first non-zero key in
+// wave lockstep.
+//
+// Guard pass (guarded precision): nodes that met an ill-conditioned tetrahedron in A or
+// B are redone from the start with those tetrahedra projected in FP64.
+// ---------------------------------------------------------------------------------------
+
+// Per-block reduction of the counts, added into one of SUM_BINS partial slots (blocks
+// spread over the slots, so no address sees more than a few hundred atomics).
+__device__ __forceinline__ void block_sums(BlockSums* bins, uint32_t npass, uint32_t nborder,
+                                           uint32_t nfp64, uint32_t ncells, uint32_t gm) {
+    __shared__ uint32_t s[5][SEARCH_THREADS / WAVE];
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        npass += (uint32_t)__shfl_xor((int)npass, o);
+        nborder += (uint32_t)__shfl_xor((int)nborder, o);
+        nfp64 += (uint32_t)__shfl_xor((int)nfp64, o);
+        ncells += (uint32_t)__shfl_xor((int)ncells, o);
+        gm = max(gm, (uint32_t)__shfl_xor((int)gm, o));
+    }
+    const int w = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        s[0][w] = npass;
+        s[1][w] = nborder;
+        s[2][w] = nfp64;
+        s[3][w] = ncells;
+        s[4][w] = gm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long p = 0, b = 0, f = 0, c = 0;
+        uint32_t m = 0;
+        for (int j = 0; j < SEARCH_THREADS / WAVE; ++j) {
+            p += s[0][j];
+            b += s[1][j];
+            f += s[2][j];
+            c += s[3][j];
+            m = max(m, s[4][j]);
+        }
+        BlockSums* out = &bins[blockIdx.x & (SUM_BINS - 1)];
+        if (p) atomicAdd(&out->pass, p);
+        if (b) atomicAdd(&out->border, b);
+        if (f) atomicAdd(&out->fp64, f);
+        if (c) atomicAdd(&out->cells, c);
+        if (m) atomicMax(&out->maxg2, m);
+    }
+}
+
+// Block-aggregated append to a device list: one atomic per block.  Returns the slot of
+// this lane (valid where `want`).  All threads of the block must call it.
+__device__ __forceinline__ uint32_t block_append(bool want, uint32_t* counter) {
+    __shared__ uint32_t s_cnt[SEARCH_THREADS / WAVE];
+    __shared__ uint32_t s_base;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const unsigned long long bal = __ballot(want);
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    if (lane == 0) s_cnt[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0u;
+        for (int j = 0; j < SEARCH_THREADS / WAVE; ++j) tot += s_cnt[j];
+        s_base = tot ? atomicAdd(counter, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t off = s_base;
+    for (int j = 0; j < w; ++j) off += s_cnt[j];
+    __syncthreads();   // s_cnt/s_base may be reused by the next call
+    return off + (uint32_t)__popcll(bal & lt);
+}
+
+// Finished node: write gamma, update the per-lane counts.
+__device__ __forceinline__ void finish_node(const SearchArgs& a, int node, float F, uint32_t& npass,
+                                            uint32_t& nborder, uint32_t& gm) {
+    const float gam = sqrtf(F);
+    a.gamma[node] = gam;
+    npass += gam <= 1.0f;
+    nborder += fabsf(gam - 1.0f) <= 1e-5f;
+    gm = max(gm, f2u(gam * gam));
+}
+
+// Pass A in 3D.  MODE 0: FP32; MODE 1: FP32 and flag ill-conditioned tetrahedra.
+template <int MODE>
+__global__ __launch_bounds__(SEARCH_THREADS) void k_zero3(SearchArgs a, ZeroGeo zg, BlockSums* sums) {
+    constexpr int GMODE = MODE == 1 ? 1 : 0;
+    const uint32_t M = a.sc->n_masked;
+    if (blockIdx.x * SEARCH_THREADS >= M) {   // grid sized for every grid node; M is on the device
+        return;
+    }
+    const uint32_t i = blockIdx.x * SEARCH_THREADS + threadIdx.x;
+    const bool live = i < M;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, sxy = nx * ny;
+    const int node = live ? (int)a.nodes[i] : 0;
+    const int x = node % nx, y = (node / nx) % ny, z = node / sxy;
+    const float dr = a.ref[node];
+    const float inv_dd = node_inv_dd(dr, a.sc->inv_dd, a.dd, a.local);
+    const float F0 = live ? gamma0_sq(a.ev[node], dr, inv_dd) : 0.0f;
+    // neighbourhood offsets, clamped at the grid faces (clamped values feed only cells
+    // that do not exist or faces that are masked out)
+    const int oxm = x > 0 ? -1 : 0, oxp = x + 1 < nx ? 1 : 0;
+    const int oym = y > 0 ? -nx : 0, oyp = y + 1 < ny ? nx : 0;
+    const int ozm = z > 0 ? -sxy : 0, ozp = z + 1 < nz ? sxy : 0;
+    const int ox[3] = {oxm, 0, oxp}, oy[3] = {oym, 0, oyp}, oz[3] = {ozm, 0, ozp};
+    float g27[27];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) g27[k] = a.ev[node + oz[k / 9] + oy[(k / 3) % 3] + ox[k % 3]];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) g27[k] = (g27[k] - dr) * inv_dd;
+
+    const InvS2<float> is = inv_s2<float>(a.s2x, a.s2y, a.s2z);
+    const bool bnd = x == 0 || x + 1 == nx || y == 0 || y + 1 == ny || z == 0 || z + 1 == nz;
+    const bool wave_masked = __ballot(live && bnd) != 0ull;
+    float F = F0;
+    uint32_t cells = 0, n_fp64 = 0;
+    bool ill = false;
+    GuardCtx gc{};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        // table order of the zero-key cells: (az, ay, ax) in {-1,0}^3, lexicographic
+        const int az = (c >> 2) - 1, ay = ((c >> 1) & 1) - 1, ax = (c & 1) - 1;
+        float g[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            g[b] = g27[(az + 1 + ((b >> 2) & 1)) * 9 + (ay + 1 + ((b >> 1) & 1)) * 3 + (ax + 1 + (b & 1))];
+        const Geo<float> G = geo_from_row(zg.row[c]);
+        float v;
+        if (wave_masked) {
+            const bool exists = (ax == 0 || x > 0) && (ay == 0 || y > 0) && (az == 0 || z > 0);
+            const bool okx = ax < 0 || x + 1 < nx, oky = ay < 0 || y + 1 < ny, okz = az < 0 || z + 1 < nz;
+            v = cell3<float, true, GMODE>(g, G, is, okx, oky, okz, a.den_guard, gc, n_fp64, ill);
+            v = exists ? v : Num<float>::inf();
+            cells += (F > 0.0f && exists && okx && oky && okz) ? 1u : 0u;
+        } else {
+            v = cell3<float, false, GMODE>(g, G, is, true, true, true, a.den_guard, gc, n_fp64, ill);
+            cells += F > 0.0f ? 1u : 0u;
+        }
+        F = F0 > 0.0f ? vmin<float>(F, v) : F;
+    }
+    ill = ill && live && F0 > 0.0f;
+    const bool to_guard = MODE == 1 && ill;
+    const bool to_tail = live && !to_guard && F > a.k1;
+    uint32_t npass = 0, nborder = 0, gm = 0, ncells = 0;
+    if (live && !to_guard && !to_tail) {
+        finish_node(a, node, F, npass, nborder, gm);
+        ncells = cells;
+    }
+    // queue the tail (one atomic per block), then the guard list
+    const uint32_t pos = block_append(to_tail, &a.sc->n_tail);
+    if (to_tail) {
+        a.tail_node[pos] = (uint32_t)node;
+        a.tail_f[pos] = f2u(F);
+        a.tail_key_arr[pos] = a.tail_key ? f2u(F) : f2u(F0);
+        a.tail_pos[pos] = pos;
+    }
+    if (MODE == 1) {
+        const uint32_t gpos = block_append(to_guard, &a.sc->n_guard);
+        if (to_guard) a.guard_list[gpos] = (uint32_t)node;
+    }
+    block_sums(sums, npass, nborder, 0u, ncells, gm);
+}
+
+// Pass A in 2D (4 zero-key cells, 3x3 neighbourhood).
+template <int MODE>
+__global__ __launch_bounds__(SEARCH_THREADS) void k_zero2(SearchArgs a, ZeroGeo zg, BlockSums* sums) {
+    const uint32_t M = a.sc->n_masked;
+    if (blockIdx.x * SEARCH_THREADS >= M) {
+        return;
+    }
+    const uint32_t i = blockIdx.x * SEARCH_THREADS + threadIdx.x;
+    const bool live = i < M;
+    const int nx = a.nx, ny = a.ny;
+    const int node = live ? (int)a.nodes[i] : 0;
+    const int x = node % nx, y = node / nx;
+    const float dr = a.ref[node];
+    const float inv_dd = node_inv_dd(dr, a.sc->inv_dd, a.dd, a.local);
+    const float F0 = live ? gamma0_sq(a.ev[node], dr, inv_dd) : 0.0f;
+    const int ox[3] = {x > 0 ? -1 : 0, 0, x + 1 < nx ? 1 : 0};
+    const int oy[3] = {y > 0 ? -nx : 0, 0, y + 1 < ny ? nx : 0};
+    float g9[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g9[k] = a.ev[node + oy[k / 3] + ox[k % 3]];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g9[k] = (g9[k] - dr) * inv_dd;
+    const InvS2<float> is = inv_s2<float>(a.s2x, a.s2y, 0.0f);
+    const bool bnd = x == 0 || x + 1 == nx || y == 0 || y + 1 == ny;
+    const bool wave_masked = __ballot(live && bnd) != 0ull;
+    float F = F0;
+    uint32_t cells = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int ay = (c >> 1) - 1, ax = (c & 1) - 1;
+        float g[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) g[b] = g9[(ay + 1 + ((b >> 1) & 1)) * 3 + (ax + 1 + (b & 1))];
+        const Geo<float> G = geo_from_row(zg.row[c]);
+        float v;
+        if (wave_masked) {
+            const bool exists = (ax == 0 || x > 0) && (ay == 0 || y > 0);
+            const bool okx = ax < 0 || x + 1 < nx, oky = ay < 0 || y + 1 < ny;
+            v = cell2<float, true>(g, G, is, okx, oky);
+            v = exists ? v : Num<float>::inf();
+            cells += (F > 0.0f && exists && okx && oky) ? 1u : 0u;
+        } else {
+            v = cell2<float, false>(g, G, is, true, true);
+            cells += F > 0.0f ? 1u : 0u;
+        }
+        F = F0 > 0.0f ? vmin<float>(F, v) : F;
+    }
+    const bool to_tail = live && F > a.k1;
+    uint32_t npass = 0, nborder = 0, gm = 0, ncells = 0;
+    if (live && !to_tail) {
+        finish_node(a, node, F, npass, nborder, gm);
+        ncells = cells;
+    }
+    const uint32_t pos = block_append(to_tail, &a.sc->n_tail);
+    if (to_tail) {
+        a.tail_node[pos] = (uint32_t)node;
+        a.tail_f[pos] = f2u(F);
+        a.tail_key_arr[pos] = a.tail_key ? f2u(F) : f2u(F0);
+        a.tail_pos[pos] = pos;
+    }
+    block_sums(sums, npass, nborder, 0u, ncells, gm);
+    (void)MODE;
+}
+
+// Full cells among the zero-key cells of a node (every one is evaluated for a tail node).
+__device__ __forceinline__ uint32_t zero_cells(int DIM, int x, int y, int z, int nx, int ny, int nz) {
+    const uint32_t cx = (x > 0) + (x + 1 < nx), cy = (y > 0) + (y + 1 < ny);
+    const uint32_t cz = DIM == 3 ? (uint32_t)((z > 0) + (z + 1 < nz)) : 1u;
+    return cx * cy * cz;
+}
+
+// The walk.  TAIL: items are tail positions, the walk starts at row `first` with the bound
+// left by pass A; otherwise items are node indices and the walk starts at row 0 with
+// gamma0.  MODE 0: FP32; 1: FP32 + flag; 2: FP32 with FP64 re-projection; 3: FP64.
+template <int DIM, int MODE, bool TAIL>
+__global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const TabEntry* __restrict__ tab,
+                                                         const uint32_t* __restrict__ order,
+                                                         const uint32_t* __restrict__ count, int first,
+                                                         BlockSums* sums) {
     using T = typename std::conditional<MODE == 3, double, float>::type;
     constexpr int GMODE = DIM == 3 ? (MODE == 1 ? 1 : (MODE == 2 ? 2 : 0)) : 0;
     const uint32_t M = *count;
     const int lane = threadIdx.x & (WAVE - 1);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int sxy = nx * ny;
-    const float inv_dd_g = a.sc_in->inv_dd;
-    const double dmax = (double)ord_to_float(a.sc_in->dmax_ord);
+    const float inv_dd_g = a.sc->inv_dd;
+    const double dmax = (double)ord_to_float(a.sc->dmax_ord);
     const InvS2<T> is = inv_s2<T>(MODE == 3 ? (T)(a.sx * a.sx) : (T)a.s2x,
                                   MODE == 3 ? (T)(a.sy * a.sy) : (T)a.s2y,
                                   DIM == 3 ? (MODE == 3 ? (T)(a.sz * a.sz) : (T)a.s2z) : T(0));
@@ -348,32 +589,44 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a, const T
     const uint32_t stride = gridDim.x * SEARCH_THREADS;
     uint32_t cells = 0, n_fp64 = 0, gm = 0, npass = 0, nborder = 0;
 
-    for (uint32_t wbase = blockIdx.x * SEARCH_THREADS + (threadIdx.x & ~(WAVE - 1)); wbase < M;
-         wbase += stride) {
-        const uint32_t i = wbase + lane;
+    // the loop bound is uniform per wave, so every lane reaches the block-wide calls below
+    const uint32_t wave0 = blockIdx.x * SEARCH_THREADS + (threadIdx.x & ~(WAVE - 1));
+    const uint32_t iters = wave0 < M ? (M - wave0 + stride - 1) / stride : 0u;
+    uint32_t it_max = iters;
+    // block-uniform trip count (all waves of a block take part in block_append)
+    {
+        __shared__ uint32_t s_it[SEARCH_THREADS / WAVE];
+        if (lane == 0) s_it[threadIdx.x / WAVE] = iters;
+        __syncthreads();
+        it_max = 0u;
+        for (int j = 0; j < SEARCH_THREADS / WAVE; ++j) it_max = max(it_max, s_it[j]);
+        __syncthreads();
+    }
+    for (uint32_t it = 0; it < it_max; ++it) {
+        const uint32_t i = wave0 + it * stride + lane;
         const bool live = i < M;
-        const int node = live ? (int)order[i] : 0;
+        const uint32_t item = live ? order[i] : 0u;
+        const int node = TAIL ? (live ? (int)a.tail_node[item] : 0) : (int)item;
         const int x = node % nx;
         const int y = (node / nx) % ny;
         const int z = DIM == 3 ? node / sxy : 0;
         const float dr = a.ref[node];
-        const float de0 = a.ev[node];
         const float inv_dd = node_inv_dd(dr, inv_dd_g, a.dd, a.local);
         const double inv_dd64 = a.local ? 1.0 / (a.dd64 * (double)dr) : 1.0 / (a.dd64 * dmax);
         T F;
         if constexpr (MODE == 3) {
-            const double g0 = ((double)de0 - (double)dr) * inv_dd64;
+            const double g0 = ((double)a.ev[node] - (double)dr) * inv_dd64;
             F = g0 * g0;
         } else {
-            F = gamma0_sq(de0, dr, inv_dd);
+            F = TAIL ? u2f(live ? a.tail_f[item] : 0u) : gamma0_sq(a.ev[node], dr, inv_dd);
         }
         if (!live) F = T(0);
         const T invdd = MODE == 3 ? (T)inv_dd64 : (T)inv_dd;
         const T drT = (T)dr;
-        uint32_t lane_cells = 0, lane_fp64 = 0;
+        uint32_t lane_cells = TAIL ? zero_cells(DIM, x, y, z, nx, ny, nz) : 0u, lane_fp64 = 0;
         bool ill = false;
 
-        for (int n = 0; n < a.tab_len; ++n) {
+        for (int n = first; n < a.tab_len; ++n) {
             const TabEntry e = tab[n];
             const bool act = live && ((T)e.key2 < F);
             if (__ballot(act) == 0ull) break;
@@ -435,66 +688,282 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a, const T
             }
         }
 
-        if (MODE == 1 && live && ill) {
-            // redone by the guarded pass; nothing of this node is written or counted here
-            const uint32_t pos = atomicAdd(&a.sc->n_guard, 1u);
-            a.guard_list[pos] = (uint32_t)node;
-        } else if (live) {
-            const float gam = (float)sqrt(F);
-            a.gamma[node] = gam;
-            npass += gam <= 1.0f;
-            nborder += fabsf(gam - 1.0f) <= 1e-5f;
-            gm = max(gm, __float_as_uint(gam * gam));
+        const bool to_guard = MODE == 1 && live && ill;
+        if (live && !to_guard) {
+            finish_node(a, node, (float)F, npass, nborder, gm);
             cells += lane_cells;
             n_fp64 += lane_fp64;
         }
+        if (MODE == 1) {
+            const uint32_t gpos = block_append(to_guard, &a.sc->n_guard);
+            if (to_guard) a.guard_list[gpos] = (uint32_t)node;
+        }
     }
+    block_sums(sums, npass, nborder, n_fp64, cells, gm);
+}
 
-    // counters: one atomic per wave
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
-        cells += (uint32_t)__shfl_xor((int)cells, o);
-        n_fp64 += (uint32_t)__shfl_xor((int)n_fp64, o);
-        npass += (uint32_t)__shfl_xor((int)npass, o);
-        nborder += (uint32_t)__shfl_xor((int)nborder, o);
-        gm = max(gm, (uint32_t)__shfl_xor((int)gm, o));
+// Pass B with G lanes per node: the G lanes of a group take G consecutive table rows of
+// one node at once (independent loads, so the gathers of G cells overlap instead of
+// forming one dependent chain), then take the minimum over the group and move to the next
+// G rows while the first of them still has key^2 < gamma^2.  Every row the sequential walk
+// would evaluate is evaluated; up to G-1 rows past its break may be too.
+// MODE 0: FP32; 1: FP32 + flag ill-conditioned tetrahedra (3D).
+// g_req: lanes per node (8..64), or 0 to pick it from the tail length on the device: about
+// 2^19 lanes in flight fill the GPU, so a short tail gets wide groups (latency) and a long
+// one narrow groups (fewer rows past the break).
+template <int DIM, int MODE>
+__global__ __launch_bounds__(SEARCH_THREADS) void k_tail_group(SearchArgs a, const TabEntry* __restrict__ tab,
+                                                               const uint32_t* __restrict__ order,
+                                                               const uint32_t* __restrict__ count, int first,
+                                                               int g_req, BlockSums* sums) {
+    constexpr int GMODE = (DIM == 3 && MODE == 1) ? 1 : 0;
+    const uint32_t M = *count;
+    int G = g_req;
+    if (G == 0) {
+        G = 64;
+        while (G > 8 && (uint64_t)M * (uint64_t)G > (1ull << 19)) G >>= 1;
     }
-    if (lane == 0) {
-        if (npass) atomicAdd(&a.sc->n_pass, (unsigned long long)npass);
-        if (nborder) atomicAdd(&a.sc->n_border, (unsigned long long)nborder);
-        if (cells) atomicAdd(&a.sc->n_cells, (unsigned long long)cells);
-        if (n_fp64) atomicAdd(&a.sc->n_fp64, (unsigned long long)n_fp64);
-        if (gm) atomicMax(&a.sc->maxg2_bits, gm);
+    const int GROUPS = SEARCH_THREADS / G;
+    const int gl = threadIdx.x % G;               // lane within the group
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int sxy = nx * ny;
+    const float inv_dd_g = a.sc->inv_dd;
+    const InvS2<float> is = inv_s2<float>(a.s2x, a.s2y, DIM == 3 ? a.s2z : 0.0f);
+    uint32_t cells = 0, gm = 0, npass = 0, nborder = 0;
+    GuardCtx gc{};
+    uint32_t dummy_fp64 = 0;
+
+    // block-uniform trip count
+    for (uint32_t base = blockIdx.x * GROUPS; base < M; base += gridDim.x * GROUPS) {
+        const uint32_t i = base + threadIdx.x / G;
+        const bool live = i < M;
+        const uint32_t item = live ? order[i] : 0u;
+        const int node = live ? (int)a.tail_node[item] : 0;
+        const int x = node % nx;
+        const int y = (node / nx) % ny;
+        const int z = DIM == 3 ? node / sxy : 0;
+        const float dr = a.ref[node];
+        const float inv_dd = node_inv_dd(dr, inv_dd_g, a.dd, a.local);
+        float F = live ? u2f(a.tail_f[item]) : 0.0f;
+        uint32_t lane_cells = 0;
+        bool ill = false;
+
+        for (int n0 = first; n0 < a.tab_len; n0 += G) {
+            const float k_first = tab[n0].key2;       // wave-uniform row: scalar load
+            const bool grp_act = live && k_first < F;
+            if (__ballot(grp_act) == 0ull) break;
+            const int n = n0 + gl;
+            TabEntry e;
+            bool act = false;
+            if (grp_act && n < a.tab_len) {
+                e = tab[n];
+                act = e.key2 < F;
+            }
+            int qx = 0, qy = 0, qz = 0;
+            if (act) {
+                qx = x + e.ax;
+                qy = y + e.ay;
+                qz = z + e.az;
+            }
+            const bool cin = (unsigned)qx < (unsigned)nx && (unsigned)qy < (unsigned)ny &&
+                             (DIM == 2 || (unsigned)qz < (unsigned)nz);
+            const bool okx = qx + 1 < nx, oky = qy + 1 < ny, okz = DIM == 2 || qz + 1 < nz;
+            const bool work = act && cin;
+            const bool edge = !(okx && oky && okz);
+            const bool wave_masked = __ballot(work && edge) != 0ull;
+            float c = Num<float>::inf();
+            if (work) {
+                lane_cells += edge ? 0u : 1u;
+                const int base_i = (DIM == 3 ? qz * sxy : 0) + qy * nx + qx;
+                const int ox = okx ? 1 : 0, oy = oky ? nx : 0, oz = (DIM == 3 && okz) ? sxy : 0;
+                const Geo<float> Gm = geo_from_row(e);
+                if constexpr (DIM == 3) {
+                    float g[8];
+                    g[0] = a.ev[base_i];
+                    g[1] = a.ev[base_i + ox];
+                    g[2] = a.ev[base_i + oy];
+                    g[3] = a.ev[base_i + oy + ox];
+                    g[4] = a.ev[base_i + oz];
+                    g[5] = a.ev[base_i + oz + ox];
+                    g[6] = a.ev[base_i + oz + oy];
+                    g[7] = a.ev[base_i + oz + oy + ox];
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) g[b] = (g[b] - dr) * inv_dd;
+                    if (wave_masked)
+                        c = cell3<float, true, GMODE>(g, Gm, is, okx, oky, okz, a.den_guard, gc, dummy_fp64, ill);
+                    else
+                        c = cell3<float, false, GMODE>(g, Gm, is, true, true, true, a.den_guard, gc, dummy_fp64,
+                                                       ill);
+                } else {
+                    float g[4];
+                    g[0] = a.ev[base_i];
+                    g[1] = a.ev[base_i + ox];
+                    g[2] = a.ev[base_i + oy];
+                    g[3] = a.ev[base_i + oy + ox];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) g[b] = (g[b] - dr) * inv_dd;
+                    if (wave_masked)
+                        c = cell2<float, true>(g, Gm, is, okx, oky);
+                    else
+                        c = cell2<float, false>(g, Gm, is, true, true);
+                }
+            }
+            // group minimum (the group is G consecutive lanes of the wave)
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) c = vmin<float>(c, __shfl_xor(c, o));
+            F = vmin<float>(F, c);
+        }
+        // reduce the group's flags and cell counts onto its first lane
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) {
+            lane_cells += (uint32_t)__shfl_xor((int)lane_cells, o);
+            ill = (__shfl_xor((int)ill, o) != 0) || ill;
+        }
+        const bool leader = live && gl == 0;
+        const bool to_guard = MODE == 1 && leader && ill;
+        if (leader && !to_guard) {
+            finish_node(a, node, F, npass, nborder, gm);
+            cells += lane_cells + zero_cells(DIM, x, y, z, nx, ny, nz);
+        }
+        if (MODE == 1) {
+            const uint32_t gpos = block_append(to_guard, &a.sc->n_guard);
+            if (to_guard) a.guard_list[gpos] = (uint32_t)node;
+        }
     }
+    block_sums(sums, npass, nborder, 0u, cells, gm);
+}
+
+// One block: sum the per-block partial counts into the scalars, and flag a cell table
+// that does not reach the search radius (the host then rebuilds it and runs again).
+__global__ __launch_bounds__(SEARCH_THREADS) void k_finalize(const BlockSums* __restrict__ sums, int n,
+                                                             Scalars* sc, float r2_cap) {
+    if (threadIdx.x == 0 && u2f(sc->r2_bits) > r2_cap && sc->n_masked > 0) sc->flags |= FLAG_TABLE_SHORT;
+    unsigned long long p = 0, b = 0, f = 0, c = 0;
+    uint32_t m = 0;
+    for (int j = threadIdx.x; j < n; j += SEARCH_THREADS) {
+        p += sums[j].pass;
+        b += sums[j].border;
+        f += sums[j].fp64;
+        c += sums[j].cells;
+        m = max(m, sums[j].maxg2);
+    }
+    __shared__ unsigned long long s[4][SEARCH_THREADS];
+    __shared__ uint32_t sm[SEARCH_THREADS];
+    s[0][threadIdx.x] = p;
+    s[1][threadIdx.x] = b;
+    s[2][threadIdx.x] = f;
+    s[3][threadIdx.x] = c;
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = SEARCH_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            for (int k = 0; k < 4; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + h];
+            sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sc->n_pass = s[0][0];
+        sc->n_border = s[1][0];
+        sc->n_fp64 = s[2][0];
+        sc->n_cells = s[3][0];
+        sc->maxg2_bits = sm[0];
+    }
+}
+
+constexpr unsigned kTailBlocks = 1024;   // grid-stride blocks of the tail walk
+constexpr unsigned kGuardBlocks = 64;    // grid-stride blocks of the guard pass
+
+unsigned blocks_for(uint32_t m) { return (m + SEARCH_THREADS - 1) / SEARCH_THREADS; }
+
+template <int DIM, int MODE, bool TAIL>
+void walk(const SearchArgs& a, const uint32_t* order, const uint32_t* count, int first, unsigned blocks,
+          BlockSums* sums, hipStream_t s) {
+    hipLaunchKernelGGL((k_walk<DIM, MODE, TAIL>), dim3(blocks), dim3(SEARCH_THREADS), 0, s, a, a.tab, order,
+                       count, first, sums);
 }
 
 template <int DIM, int MODE>
-hipError_t launch_one(const SearchArgs& a, const uint32_t* order, const uint32_t* count, unsigned blocks,
-                      hipStream_t s) {
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_search<DIM, MODE>), dim3(blocks), dim3(SEARCH_THREADS), 0, s, a, a.tab, order, count);
-    return hipGetLastError();
+void tail_group_g(const SearchArgs& a, int G, int first, unsigned blocks, BlockSums* sums, hipStream_t s) {
+    hipLaunchKernelGGL((k_tail_group<DIM, MODE>), dim3(blocks), dim3(SEARCH_THREADS), 0, s, a, a.tab, a.tail_pos,
+                       &a.sc->n_tail, first, G, sums);
 }
 
-// Blocks of the pass over the guard list (grid-stride; the list is almost always empty).
-constexpr unsigned kGuardBlocks = 64;
+void tail_group(const SearchArgs& a, int ndim, int mode, int G, int first, unsigned blocks, BlockSums* sums,
+                hipStream_t s) {
+    if (ndim == 3) {
+        if (mode == 1) tail_group_g<3, 1>(a, G, first, blocks, sums, s);
+        else tail_group_g<3, 0>(a, G, first, blocks, sums, s);
+    } else {
+        tail_group_g<2, 0>(a, G, first, blocks, sums, s);
+    }
+}
 
 }  // namespace
 
-hipError_t launch_search(const SearchArgs& a, int ndim, int precision, uint32_t max_items, hipStream_t s) {
-    const unsigned blocks = (max_items + SEARCH_THREADS - 1) / SEARCH_THREADS;
-    const uint32_t* cnt = &a.sc_in->n_masked;
-    if (ndim == 3) {
-        if (precision == 0) return launch_one<3, 0>(a, a.order, cnt, blocks, s);
-        if (precision == 2) return launch_one<3, 3>(a, a.order, cnt, blocks, s);
-        return launch_one<3, 1>(a, a.order, cnt, blocks, s);
-    }
-    if (precision == 2) return launch_one<2, 3>(a, a.order, cnt, blocks, s);
-    return launch_one<2, 0>(a, a.order, cnt, blocks, s);
-}
+int64_t search_sums_needed(uint32_t) { return SUM_BINS; }
 
-hipError_t launch_search_guard(const SearchArgs& a, int ndim, int precision, hipStream_t s) {
-    if (ndim != 3 || precision != 1) return hipSuccess;
-    return launch_one<3, 2>(a, a.guard_list, &a.sc_in->n_guard, kGuardBlocks, s);
+hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s) {
+    const unsigned nb = blocks_for(p.M);
+    if (nb == 0) return hipSuccess;
+    const unsigned tb = nb < kTailBlocks ? nb : kTailBlocks;
+    BlockSums* sums = a.sums;
+    int used = 0;
+    if (p.precision == 2) {
+        // FP64 throughout: one walk over all nodes from the first row
+        if (p.ndim == 3) walk<3, 3, false>(a, a.nodes, &a.sc->n_masked, 0, nb, sums, s);
+        else walk<2, 3, false>(a, a.nodes, &a.sc->n_masked, 0, nb, sums, s);
+        used = (int)nb;
+        if (p.ev_shell_end) (void)hipEventRecord(p.ev_shell_end, s);
+        if (p.ev_sort_end) (void)hipEventRecord(p.ev_sort_end, s);
+        if (p.ev_tail_end) (void)hipEventRecord(p.ev_tail_end, s);
+    } else {
+        const bool guarded = p.precision == 1 && p.ndim == 3;
+        const int first = p.ndim == 3 ? 8 : 4;
+        // pass A
+        if (p.ndim == 3) {
+            if (guarded) hipLaunchKernelGGL(k_zero3<1>, dim3(nb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
+            else hipLaunchKernelGGL(k_zero3<0>, dim3(nb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
+        } else {
+            hipLaunchKernelGGL(k_zero2<0>, dim3(nb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
+        }
+        used += (int)nb;
+        if (p.ev_shell_end) (void)hipEventRecord(p.ev_shell_end, s);
+        // tail sort (count read on the device)
+        if (p.hist) {
+            hipError_t e = radix_sort_pairs(a.tail_key_arr, a.tail_pos, p.tmp_keys, p.tmp_vals, p.M,
+                                            &a.sc->n_tail, p.hist, s);
+            if (e != hipSuccess) return e;
+        }
+        if (p.ev_sort_end) (void)hipEventRecord(p.ev_sort_end, s);
+        // pass B
+        if (a.tab_len > first) {
+            const int G = p.tail_lanes;   // 0: chosen on the device from the tail length
+            if (G == 1) {
+                if (p.ndim == 3) {
+                    if (guarded) walk<3, 1, true>(a, a.tail_pos, &a.sc->n_tail, first, tb, sums, s);
+                    else walk<3, 0, true>(a, a.tail_pos, &a.sc->n_tail, first, tb, sums, s);
+                } else {
+                    walk<2, 0, true>(a, a.tail_pos, &a.sc->n_tail, first, tb, sums, s);
+                }
+                used += (int)tb;
+            } else {
+                const unsigned groups = SEARCH_THREADS / (unsigned)(G ? G : 8);
+                unsigned gb = (p.M + groups - 1) / groups;
+                if (gb > kTailBlocks) gb = kTailBlocks;
+                tail_group(a, p.ndim, guarded ? 1 : 0, G, first, gb, sums, s);
+                used += (int)gb;
+            }
+        }
+        if (p.ev_tail_end) (void)hipEventRecord(p.ev_tail_end, s);
+        // guard pass
+        if (guarded) {
+            walk<3, 2, false>(a, a.guard_list, &a.sc->n_guard, 0, kGuardBlocks, sums, s);
+            used += (int)kGuardBlocks;
+        }
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(SEARCH_THREADS), 0, s, sums, SUM_BINS, a.sc, a.r2_cap);
+    return hipGetLastError();
 }
 
 }  // namespace gammax

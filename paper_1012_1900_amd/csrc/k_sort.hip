@@ -18,10 +18,15 @@ constexpr int SORT_TILE = SORT_THREADS * SORT_CHUNKS;
 constexpr int RADIX = 256;
 constexpr int NWAVES = SORT_THREADS / WAVE;
 
+__device__ __forceinline__ int64_t count_of(int64_t n_max, const uint32_t* n_dev) {
+    return n_dev ? (int64_t)*n_dev : n_max;
+}
+
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
-                                                             int64_t n, int shift,
-                                                             uint32_t* __restrict__ hist,
+                                                             int64_t n_max, const uint32_t* n_dev,
+                                                             int shift, uint32_t* __restrict__ hist,
                                                              int64_t nb) {
+    const int64_t n = count_of(n_max, n_dev);
     __shared__ uint32_t h[RADIX];
     h[threadIdx.x] = 0u;
     __syncthreads();
@@ -77,8 +82,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scan(uint32_t* __restric
 
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, int64_t n, int shift, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ totals, int64_t nb) {
+    uint32_t* __restrict__ vout, int64_t n_max, const uint32_t* n_dev, int shift,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int64_t nb) {
+    const int64_t n = count_of(n_max, n_dev);
+    if ((int64_t)blockIdx.x * SORT_TILE >= n) return;   // uniform: nothing of this tile exists
     __shared__ uint32_t s_base[RADIX];
     __shared__ uint32_t s_wcnt[NWAVES][RADIX];
     __shared__ uint32_t s_wave[NWAVES];
@@ -131,23 +138,23 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 
 }  // namespace
 
-int64_t sort_hist_words(int64_t n) {
-    const int64_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+int64_t sort_hist_words(int64_t n_max) {
+    const int64_t nb = (n_max + SORT_TILE - 1) / SORT_TILE;
     return (int64_t)RADIX * (nb > 0 ? nb : 1) + RADIX;
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
-                            int64_t n, uint32_t* hist, hipStream_t s) {
-    if (n <= 1) return hipSuccess;
-    const int64_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+                            int64_t n_max, const uint32_t* n_dev, uint32_t* hist, hipStream_t s) {
+    if (n_max <= 1) return hipSuccess;
+    const int64_t nb = (n_max + SORT_TILE - 1) / SORT_TILE;
     uint32_t* totals = hist + (int64_t)RADIX * nb;
     uint32_t *ki = keys, *vi = vals, *ko = tmp_keys, *vo = tmp_vals;
     for (int shift = 0; shift < 32; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(SORT_THREADS), 0, s, ki, n, shift,
-                           hist, nb);
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(SORT_THREADS), 0, s, ki, n_max, n_dev,
+                           shift, hist, nb);
         hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nb, totals);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo,
-                           n, shift, hist, totals, nb);
+                           n_max, n_dev, shift, hist, totals, nb);
         uint32_t* tk = ki;
         ki = ko;
         ko = tk;

@@ -49,23 +49,18 @@ __global__ __launch_bounds__(256) void k_table_gen(TableGeom g, uint32_t* __rest
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (uint32_t)__popcll(b));
 }
 
-__global__ __launch_bounds__(256) void k_table_rows(TableGeom g, const uint32_t* __restrict__ vals,
-                                                    int64_t n, TabEntry* __restrict__ rows) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int64_t a[3] = {0, 0, 0};
-    decode_box(g, vals[i], a);
+// Spatial constants of the row for offset a (slowest axis first), in double, rounded to
+// float; key2 is filled by the caller.
+__host__ __device__ inline void fill_row(int ndim, const double* s, const int64_t* a, TabEntry& e) {
     // axis letters: x = fastest, y, z = slowest
     double ax, ay, az, sx2, sy2, sz2;
-    if (g.ndim == 3) {
+    if (ndim == 3) {
         az = (double)a[0]; ay = (double)a[1]; ax = (double)a[2];
-        sz2 = g.s[0] * g.s[0]; sy2 = g.s[1] * g.s[1]; sx2 = g.s[2] * g.s[2];
+        sz2 = s[0] * s[0]; sy2 = s[1] * s[1]; sx2 = s[2] * s[2];
     } else {
         az = 0.0; ay = (double)a[0]; ax = (double)a[1];
-        sz2 = 0.0; sy2 = g.s[0] * g.s[0]; sx2 = g.s[1] * g.s[1];
+        sz2 = 0.0; sy2 = s[0] * s[0]; sx2 = s[1] * s[1];
     }
-    TabEntry e;
-    e.key2 = __double2float_rd(key2_of(g, a));
     e.ax = (int32_t)ax;
     e.ay = (int32_t)ay;
     e.az = (int32_t)az;
@@ -75,7 +70,7 @@ __global__ __launch_bounds__(256) void k_table_rows(TableGeom g, const uint32_t*
     const double dxy = ax - ay, dxz = ax - az, dyz = ay - az;
     e.vxy = (float)(sx2 * sy2 * dxy * dxy / (sx2 + sy2));
     e.mxy = (float)((sx2 * ax + sy2 * ay) / (sx2 + sy2));
-    if (g.ndim == 3) {
+    if (ndim == 3) {
         const double sxyz = sx2 + sy2 + sz2;
         e.vxz = (float)(sx2 * sz2 * dxz * dxz / (sx2 + sz2));
         e.vyz = (float)(sy2 * sz2 * dyz * dyz / (sy2 + sz2));
@@ -88,6 +83,17 @@ __global__ __launch_bounds__(256) void k_table_rows(TableGeom g, const uint32_t*
         e.mxz = e.myz = e.mxyz = 0.0f;
     }
     e.pad = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_table_rows(TableGeom g, const uint32_t* __restrict__ vals,
+                                                    int64_t n, TabEntry* __restrict__ rows) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t a[3] = {0, 0, 0};
+    decode_box(g, vals[i], a);
+    TabEntry e;
+    fill_row(g.ndim, g.s, a, e);
+    e.key2 = __double2float_rd(key2_of(g, a));
     rows[i] = e;
 }
 
@@ -112,6 +118,25 @@ __global__ __launch_bounds__(256) void k_table_export(const TabEntry* __restrict
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
+
+void table_row_host(int ndim, const double s[3], int az, int ay, int ax, TabEntry* out) {
+    int64_t a[3];
+    if (ndim == 3) {
+        a[0] = az; a[1] = ay; a[2] = ax;
+    } else {
+        a[0] = ay; a[1] = ax; a[2] = 0;
+    }
+    fill_row(ndim, s, a, *out);
+    double k2 = 0.0;
+    for (int i = 0; i < ndim; ++i) {
+        const int64_t m = a[i] > 0 ? a[i] : (a[i] < -1 ? -a[i] - 1 : 0);
+        const double d = s[i] * (double)m;
+        k2 += d * d;
+    }
+    float f = (float)k2;                       // nearest, then step down if above
+    if ((double)f > k2) f = std::nextafter(f, -INFINITY);
+    out->key2 = f;
+}
 
 void table_box(TableGeom& g) {
     const double r = std::sqrt(g.r2_cap);

@@ -36,6 +36,7 @@ def main():
         out[key(cfg, seed, dd, dta)] = {
             "shape": list(p.ref.shape), "spacing_mm": list(p.spacing),
             "n_evaluated": int(o.n_evaluated), "cells_visited": int(o.cells_visited),
+            "cells_visited_key0": int(o.cells_key0),
             "n_pass": int(o.n_pass), "n_borderline": int(o.n_borderline),
             "radius": float(o.radius), "table_len": int(o.table_len),
         }

@@ -44,10 +44,10 @@ def test_library_exports_every_declared_symbol(abi):
 
 def test_options_defaults(abi):
     o = abi.default_options()
-    assert o.sort_mode == abi.SORT_DD
+    assert o.sort_mode == abi.SORT_NONE
     assert o.precision == abi.PREC_GUARDED
     assert o.cond_threshold == 1e6
-    assert o.timing == 0 and list(o.reserved) == [0] * 7
+    assert o.timing == 0 and o.tail_lanes == 0 and list(o.reserved) == [0] * 6
 
 
 def test_status_strings(abi):
