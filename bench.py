@@ -6,7 +6,7 @@ gamma0, compaction, cell table, DD sort, search, pass counts), inputs resident i
 Prints one JSON line: reference voxels per second, the search kernel's roofline, and the
 FP64 CPU oracle timed on this host as a baseline.
 
-  python bench.py [--steps K] [--warmup W] [--workload c1|c2] [--dd 0.03 --dta 3]
+  python bench.py [--steps K] [--warmup W] [--workload 3d_128x128x96_2.5mm] [--dd 0.03 --dta 3]
 """
 from __future__ import annotations
 
@@ -29,8 +29,8 @@ FLOP_PER_CELL = {3: 392, 2: 82}
 PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (packed)
 
 WORKLOADS = {
-    "c1": ("c1", 100, "3D 128x128x96 at 2.5 mm, 7-beam synthetic IMRT-like pair (seed 100)"),
-    "c2": ("c2", 200, "3D 256x256x192 at 1.25 mm, 7-beam synthetic IMRT-like pair (seed 200)"),
+    "3d_128x128x96_2.5mm": ("3d_128x128x96_2.5mm", 100, "3D 128x128x96 at 2.5 mm, 7-beam synthetic IMRT-like pair (seed 100)"),
+    "3d_256x256x192_1.25mm": ("3d_256x256x192_1.25mm", 200, "3D 256x256x192 at 1.25 mm, 7-beam synthetic IMRT-like pair (seed 200)"),
 }
 
 
@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c1")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="3d_128x128x96_2.5mm")
     ap.add_argument("--dd", type=float, default=0.03)
     ap.add_argument("--dta", type=float, default=3.0)
     ap.add_argument("--sort", choices=["dd", "bound", "none"], default="none")

@@ -166,9 +166,9 @@ def make_pair_3d(seed: int, shape=(96, 128, 128), spacing=(2.5, 2.5, 2.5), n_bea
 
 # Grid shapes of the workloads (slowest axis first) and spacings in mm.
 CONFIG_SHAPES = {
-    "c0": ((64, 64), (1.0, 1.0)),
-    "c1": ((96, 128, 128), (2.5, 2.5, 2.5)),
-    "c2": ((192, 256, 256), (1.25, 1.25, 1.25)),
+    "2d_64x64_1mm": ((64, 64), (1.0, 1.0)),
+    "3d_128x128x96_2.5mm": ((96, 128, 128), (2.5, 2.5, 2.5)),
+    "3d_256x256x192_1.25mm": ((192, 256, 256), (1.25, 1.25, 1.25)),
 }
 
 

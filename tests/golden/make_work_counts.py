@@ -18,8 +18,8 @@ import oracle  # noqa: E402
 from dosegen import make_config_pair  # noqa: E402
 
 WORKLOADS = [
-    ("c1", 100, 0.03, 3.0), ("c1", 100, 0.02, 2.0), ("c1", 100, 0.01, 1.0),
-    ("c2", 200, 0.03, 3.0), ("c2", 200, 0.02, 2.0),
+    ("3d_128x128x96_2.5mm", 100, 0.03, 3.0), ("3d_128x128x96_2.5mm", 100, 0.02, 2.0), ("3d_128x128x96_2.5mm", 100, 0.01, 1.0),
+    ("3d_256x256x192_1.25mm", 200, 0.03, 3.0), ("3d_256x256x192_1.25mm", 200, 0.02, 2.0),
 ]
 
 

@@ -13,7 +13,7 @@ def test_seed_determinism():
 
 
 def test_2d_ranges():
-    p = make_config_pair("c0", 0)
+    p = make_config_pair("2d_64x64_1mm", 0)
     assert p.ref.shape == (64, 64) and p.ref.dtype == np.float32
     assert p.ref.max() == np.float32(1.0)
     assert all(-1.5 <= s <= 1.5 for s in p.meta["shift_mm"])

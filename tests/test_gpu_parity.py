@@ -28,10 +28,10 @@ def small3d():
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
 def test_c0_2d(gx, seed):
-    p = make_config_pair("c0", seed)
+    p = make_config_pair("2d_64x64_1mm", seed)
     o = oracle.gamma(p.ref, p.eval, p.spacing, 0.03, 3.0, 0.1)
     g, r = gx.gammax_map(dev(p.ref), dev(p.eval), p.spacing, 0.03, 3.0, 0.1)
-    assert_parity(host(g), o.gamma, f"c0 seed {seed}")
+    assert_parity(host(g), o.gamma, f"2D 64x64 seed {seed}")
     assert r.n_evaluated == o.n_evaluated
     assert abs(int(r.n_pass) - o.n_pass) <= o.n_borderline + r.n_borderline
 
@@ -97,10 +97,10 @@ def test_sort_modes_and_determinism(gx, small3d):
 
 def test_full_c1_bench_configuration(gx):
     """The benchmark workload, every node compared (the oracle takes about a second)."""
-    p = make_config_pair("c1", 100)
+    p = make_config_pair("3d_128x128x96_2.5mm", 100)
     o = oracle.gamma(p.ref, p.eval, p.spacing, 0.03, 3.0, 0.1)
     g, r = gx.gammax_map(dev(p.ref), dev(p.eval), p.spacing, 0.03, 3.0, 0.1, timing=True)
-    assert_parity(host(g), o.gamma, "c1 3%/3mm")
+    assert_parity(host(g), o.gamma, "128x128x96 3%/3mm")
     assert r.n_evaluated == o.n_evaluated
     assert abs(int(r.n_pass) - o.n_pass) <= o.n_borderline + r.n_borderline
     # visited cells: every cell of the exact walk (up to float rounding at the break); the
@@ -115,7 +115,7 @@ def test_full_c1_bench_configuration(gx):
 
 def test_c2_sampled(gx):
     """256x256x192 at 1.25 mm: sampled nodes (random plus the largest gamma0) vs the oracle."""
-    p = make_config_pair("c2", 200)
+    p = make_config_pair("3d_256x256x192_1.25mm", 200)
     g, r = gx.gammax_map(dev(p.ref), dev(p.eval), p.spacing, 0.02, 2.0, 0.1)
     gh = host(g).ravel()
     rng = np.random.default_rng(5)
@@ -124,7 +124,7 @@ def test_c2_sampled(gx):
     heavy = masked[np.argsort(g0)[-300:]]
     idx = np.unique(np.concatenate([rng.choice(masked, 3000, replace=False), heavy]))
     o = oracle.gamma(p.ref, p.eval, p.spacing, 0.02, 2.0, 0.1, subset=idx)
-    assert_parity(gh[idx], o.gamma, "c2 sampled")
+    assert_parity(gh[idx], o.gamma, "256x256x192 sampled")
     assert r.n_evaluated == o.n_masked
 
 
@@ -193,7 +193,7 @@ def test_device_side_errors(gx):
 
 
 def test_flat_entry_point(gx):
-    p = make_config_pair("c0", 4)
+    p = make_config_pair("2d_64x64_1mm", 4)
     a, pr = gx.gamma_map(dev(p.ref), dev(p.eval), p.spacing, 0.03, 3.0, 0.1)
     b, r = gx.gammax_map(dev(p.ref), dev(p.eval), p.spacing, 0.03, 3.0, 0.1)
     assert np.array_equal(host(a), host(b))
