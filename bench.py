@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--sort", choices=["dd", "bound", "none"], default="none")
     ap.add_argument("--precision", choices=["fp32", "guarded", "fp64"], default="guarded")
     ap.add_argument("--tail-lanes", type=int, default=0, choices=[0, 1, 8, 16, 32, 64])
+    ap.add_argument("--cell-lanes", type=int, default=0, choices=[0, 1, 4, 8])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -116,7 +117,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    kw = dict(sort=args.sort, precision=args.precision, tail_lanes=args.tail_lanes, out=out)
+    kw = dict(sort=args.sort, precision=args.precision, tail_lanes=args.tail_lanes,
+              cell_lanes=args.cell_lanes, out=out)
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
         gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, **kw)
@@ -153,7 +155,7 @@ def main():
         # dominant kernel: the pass over the key-0 cells of every node
         flops = wc["cells_visited_key0"] * FLOP_PER_CELL[nd]
         achieved = flops / (ms_search * 1e-3) / 1e12
-        kern = "k_zero3" if nd == 3 else "k_zero2"
+        kern = "k_zero_group" if args.cell_lanes in (4, 8) else ("k_zero3" if nd == 3 else "k_zero2")
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                     "traffic": None, "kernel": f"{kern} (key-0 cells of every node)",

@@ -90,7 +90,10 @@ typedef struct {
     int32_t tail_lanes;       /* lanes that share one node in the walk past the key-0 cells:
                                  0 = automatic, 1 = one lane per node (the paper's layout),
                                  8, 16, 32 or 64 = that many table rows of a node at once */
-    int32_t reserved[6];      /* must be 0 */
+    int32_t cell_lanes;       /* layout of the pass over the key-0 cells: 0 = automatic
+                                 (one lane per node), 1 = one lane per node, 4 (2D) or
+                                 8 (3D) = one lane per cell */
+    int32_t reserved[5];      /* must be 0 */
 } gammax_options_t;
 
 typedef struct {

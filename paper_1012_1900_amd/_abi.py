@@ -73,7 +73,8 @@ class Options(C.Structure):
         ("cond_threshold", C.c_double),
         ("timing", C.c_int32),
         ("tail_lanes", C.c_int32),
-        ("reserved", C.c_int32 * 6),
+        ("cell_lanes", C.c_int32),
+        ("reserved", C.c_int32 * 5),
     ]
 
 
@@ -228,20 +229,22 @@ def make_problem(shape: Sequence[int], spacing: Sequence[float], dd: float, dta:
 
 
 def make_options(sort: str = "none", precision: str = "guarded", cond_threshold: float = 1e6,
-                 timing: bool = False, tail_lanes: int = 0) -> Options:
+                 timing: bool = False, tail_lanes: int = 0, cell_lanes: int = 0) -> Options:
     o = default_options()
     o.sort_mode = _SORT[sort]
     o.precision = _PREC[precision]
     o.cond_threshold = float(cond_threshold)
     o.timing = 1 if timing else 0
     o.tail_lanes = int(tail_lanes)
+    o.cell_lanes = int(cell_lanes)
     return o
 
 
 def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
                dose_threshold: float = 0.1, local: bool = False, *, sort: str = "none",
                precision: str = "guarded", cond_threshold: float = 1e6, timing: bool = False,
-               tail_lanes: int = 0, out=None, ctx: Optional[Context] = None, stream=None):
+               tail_lanes: int = 0, cell_lanes: int = 0, out=None, ctx: Optional[Context] = None,
+               stream=None):
     """Gamma map of a dose pair on the GPU.  Returns (gamma tensor, GammaResult).
 
     ``ref``/``ev``: float32 device tensors of shape (ny, nx) or (nz, ny, nx); ``spacing``
@@ -263,7 +266,7 @@ def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
     dev = ref.device.index if ref.device.index is not None else torch.cuda.current_device()
     ctx = ctx or context(dev)
     p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
-    o = make_options(sort, precision, cond_threshold, timing, tail_lanes)
+    o = make_options(sort, precision, cond_threshold, timing, tail_lanes, cell_lanes)
     r = Result()
     s = stream if stream is not None else torch.cuda.current_stream(ref.device)
     with torch.cuda.device(ref.device):

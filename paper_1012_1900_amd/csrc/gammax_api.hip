@@ -173,7 +173,9 @@ gammax_status_t check_options(gammax_ctx* c, const gammax_options_t* o) {
     const int tl = o->tail_lanes;
     if (!(tl == 0 || tl == 1 || tl == 8 || tl == 16 || tl == 32 || tl == 64))
         return fail(c, GAMMAX_E_PARAM, "tail_lanes must be 0, 1, 8, 16, 32 or 64");
-    for (int i = 0; i < 6; ++i)
+    if (!(o->cell_lanes == 0 || o->cell_lanes == 1 || o->cell_lanes == 4 || o->cell_lanes == 8))
+        return fail(c, GAMMAX_E_PARAM, "cell_lanes must be 0, 1, 4 or 8");
+    for (int i = 0; i < 5; ++i)
         if (o->reserved[i] != 0) return fail(c, GAMMAX_E_PARAM, "reserved option fields must be 0");
     return GAMMAX_OK;
 }
@@ -272,7 +274,7 @@ struct CallSetup {
 
 // Queue the compaction (Kernel 1).  ev0/ev1 (optional) bracket it.
 gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    const int64_t ntiles = (cs.n + PREP_TILE - 1) / PREP_TILE;
+    const int64_t ntiles = prep_tiles(cs.n);
     if (ev0) HIPCHK(c, hipEventRecord(ev0, s));
     PrepArgs pa{};
     pa.ref = cs.ref;
@@ -350,6 +352,8 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
     plan.ndim = nd;
     plan.precision = opt.precision;
     plan.tail_lanes = opt.tail_lanes;
+    // one lane per node (shared neighbourhood loads) unless one lane per cell is asked for
+    plan.zero_lanes = (opt.cell_lanes == 4 || opt.cell_lanes == 8) ? 1 : 0;
     plan.M = m_bound;
     const double s3[3] = {p->spacing_mm[0] / p->dta_mm, p->spacing_mm[1] / p->dta_mm,
                           nd == 3 ? p->spacing_mm[2] / p->dta_mm : 1.0};
@@ -547,7 +551,7 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
     const bool local = p->norm == GAMMAX_LOCAL;
 
     // workspace, sized for all n nodes so that the steady path needs no count from the host
-    const int64_t ntiles = (n + PREP_TILE - 1) / PREP_TILE;
+    const int64_t ntiles = prep_tiles(n);
     if ((st = grow_work(c, n)) != GAMMAX_OK) return st;
     if ((st = grow(c, &c->blockcnt, &c->blk_cap, 2 * ntiles)) != GAMMAX_OK) return st;
     if ((st = grow(c, &c->part, &c->part_cap, 2 * MAX_BLOCKS)) != GAMMAX_OK) return st;

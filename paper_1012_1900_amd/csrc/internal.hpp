@@ -80,7 +80,7 @@ __device__ __forceinline__ float gamma0_sq(float de, float dr, float inv_dd) {
 // ---- prep: dose max, mask, gamma0, ordered compaction ---------------------------------
 
 constexpr int PREP_THREADS = 256;
-constexpr int PREP_ITEMS = 16;
+constexpr int PREP_ITEMS = 4;
 constexpr int PREP_TILE = PREP_THREADS * PREP_ITEMS;
 constexpr int MAX_BLOCKS = 1024;   // blocks of the grid-stride dose-max reduction
 
@@ -100,6 +100,7 @@ struct PrepArgs {
     BlockSums* sums;    // SUM_BINS partial-count slots of the search, zeroed here
 };
 
+int64_t prep_tiles(int64_t n);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_pass_count(const float* gamma, int64_t n, unsigned long long* counts3, hipStream_t s);
 
@@ -172,6 +173,7 @@ struct ZeroGeo {
 struct SearchPlan {
     int ndim, precision;
     int tail_lanes;          // lanes per node in the tail walk: 1 (one lane per node) or 8..64
+    int zero_lanes;          // pass A: 1 = one lane per cell, 0 = one lane per node
     uint32_t M;
     ZeroGeo zero;
     uint32_t* tmp_keys;      // sort scratch, M entries each

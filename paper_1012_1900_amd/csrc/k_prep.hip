@@ -1,7 +1,15 @@
 // Normalisation, mask, gamma0 and ordered compaction (Algorithm A2 step 2, "Kernel 1"),
-// plus the stand-alone pass-rate reduction.  Every pass streams the dose arrays with
-// coalesced loads; reductions go through per-block partials and one finishing block, so
-// no address is hit by thousands of atomics.
+// plus the stand-alone pass-rate reduction.
+//
+// Four launches, each a coalesced stream over the dose arrays or a short single-block
+// step; results cross blocks only at kernel boundaries (a cross-block hand-over inside
+// a kernel would need device-scope release fences, which write back the XCD's L2):
+//   1. dose maximum and finiteness check: one partial per block;
+//   2. every block reduces those partials itself (a few KB from L2), derives the
+//      threshold and the global 1/dD, then counts the masked nodes of its tile and their
+//      max gamma0^2; block 0 also stores the scalars and clears the search counters;
+//   3. one block: exclusive scan of the tile counts, M and R^2;
+//   4. ordered emit of the masked node indices.
 #include "internal.hpp"
 
 namespace gammax {
@@ -19,7 +27,7 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
-// Block-wide max and or over 256 threads (result valid in thread 0).
+// Block-wide max and or over PREP_THREADS threads (result valid in every thread).
 __device__ __forceinline__ void block_max_or(uint32_t& m, uint32_t& f) {
     __shared__ uint32_t s_m[PREP_THREADS / WAVE], s_f[PREP_THREADS / WAVE];
     m = wave_max_u32(m);
@@ -30,59 +38,29 @@ __device__ __forceinline__ void block_max_or(uint32_t& m, uint32_t& f) {
         s_f[w] = f;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int j = 1; j < PREP_THREADS / WAVE; ++j) {
-            m = max(m, s_m[j]);
-            f |= s_f[j];
-        }
+    m = s_m[0];
+    f = s_f[0];
+    for (int j = 1; j < PREP_THREADS / WAVE; ++j) {
+        m = max(m, s_m[j]);
+        f |= s_f[j];
     }
+    __syncthreads();
 }
 
-// max D_r and a finiteness check of both doses: grid-stride, one partial per block.
-__global__ __launch_bounds__(PREP_THREADS) void k_dose_max(const float* __restrict__ ref,
-                                                           const float* __restrict__ ev, int64_t n,
-                                                           uint32_t* __restrict__ part) {
+// 1. dose maximum and finiteness of both doses, one partial per block.
+__global__ __launch_bounds__(PREP_THREADS) void k_dose_max(PrepArgs a) {
     uint32_t best = 0u, bad = 0u;
     const int64_t stride = (int64_t)gridDim.x * PREP_THREADS;
-    for (int64_t i = (int64_t)blockIdx.x * PREP_THREADS + threadIdx.x; i < n; i += stride) {
-        const float r = ref[i];
-        const float e = ev[i];
+    for (int64_t i = (int64_t)blockIdx.x * PREP_THREADS + threadIdx.x; i < a.n; i += stride) {
+        const float r = a.ref[i];
+        const float e = a.ev[i];
         bad |= (!isfinite(r) || !isfinite(e)) ? 1u : 0u;
         best = max(best, float_to_ord(r));
     }
     block_max_or(best, bad);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = best;
-        part[MAX_BLOCKS + blockIdx.x] = bad;
-    }
-}
-
-// One block: reduce the partials, set the threshold and global 1/dD, clear the counters.
-__global__ __launch_bounds__(PREP_THREADS) void k_finish_max(const uint32_t* __restrict__ part, int nb,
-                                                             Scalars* sc, float thr, float dd,
-                                                             BlockSums* sums) {
-    for (int j = threadIdx.x; j < SUM_BINS; j += PREP_THREADS) sums[j] = BlockSums{};
-    uint32_t m = 0u, f = 0u;
-    for (int j = threadIdx.x; j < nb; j += PREP_THREADS) {
-        m = max(m, part[j]);
-        f |= part[MAX_BLOCKS + j];
-    }
-    block_max_or(m, f);
-    if (threadIdx.x == 0) {
-        const float dmax = ord_to_float(m);
-        sc->dmax_ord = m;
-        sc->flags = f ? FLAG_NONFINITE : 0u;
-        sc->thr_val = thr * dmax;
-        sc->inv_dd = 1.0f / (dd * dmax);
-        sc->r2_bits = 0u;
-        sc->n_masked = 0u;
-        sc->n_tail = 0u;
-        sc->n_guard = 0u;
-        sc->maxg2_bits = 0u;
-        sc->n_pass = 0ull;
-        sc->n_border = 0ull;
-        sc->n_fp64 = 0ull;
-        sc->n_cells = 0ull;
+        a.part[blockIdx.x] = best;
+        a.part[MAX_BLOCKS + blockIdx.x] = bad;
     }
 }
 
@@ -90,13 +68,40 @@ __device__ __forceinline__ bool node_masked(float dr, float thr_val, int local) 
     return dr >= thr_val && (!local || dr > 0.0f);
 }
 
-// Pass 1: per tile, count masked nodes, take max gamma0^2, write -1 for unmasked nodes.
-__global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a) {
-    const float thr_val = a.sc->thr_val;
-    const float inv_dd_g = a.sc->inv_dd;
+// 2. every block: the dose maximum from the partials, then per tile the masked count, max
+// gamma0^2 and -1 for unmasked nodes.  Block 0 stores the scalars of this map.
+__global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a, int nb_red) {
+    uint32_t dm = 0u, bad = 0u;
+    for (int j = threadIdx.x; j < nb_red; j += PREP_THREADS) {
+        dm = max(dm, a.part[j]);
+        bad |= a.part[MAX_BLOCKS + j];
+    }
+    block_max_or(dm, bad);
+    const float dmax = ord_to_float(dm);
+    const float thr_val = a.thr * dmax;
+    const float inv_dd_g = 1.0f / (a.dd * dmax);
+    if (blockIdx.x == 0) {
+        for (int j = threadIdx.x; j < SUM_BINS; j += PREP_THREADS) a.sums[j] = BlockSums{};
+        if (threadIdx.x == 0) {
+            Scalars* sc = a.sc;
+            sc->dmax_ord = dm;
+            sc->flags = bad ? FLAG_NONFINITE : 0u;
+            sc->thr_val = thr_val;
+            sc->inv_dd = inv_dd_g;
+            sc->r2_bits = 0u;
+            sc->n_masked = 0u;
+            sc->n_tail = 0u;
+            sc->n_guard = 0u;
+            sc->maxg2_bits = 0u;
+            sc->n_pass = 0ull;
+            sc->n_border = 0ull;
+            sc->n_fp64 = 0ull;
+            sc->n_cells = 0ull;
+        }
+    }
     const int64_t base = (int64_t)blockIdx.x * PREP_TILE;
     uint32_t cnt = 0u, best = 0u;
-#pragma unroll 4
+#pragma unroll
     for (int k = 0; k < PREP_ITEMS; ++k) {
         const int64_t i = base + (int64_t)k * PREP_THREADS + threadIdx.x;
         if (i < a.n) {
@@ -111,40 +116,31 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a) {
             }
         }
     }
-    __shared__ uint32_t s_cnt[PREP_THREADS / WAVE], s_max[PREP_THREADS / WAVE];
+    __shared__ uint32_t s_cnt[PREP_THREADS / WAVE];
     cnt = wave_sum_u32(cnt);
-    best = wave_max_u32(best);
-    const int w = threadIdx.x / WAVE;
-    if ((threadIdx.x & (WAVE - 1)) == 0) {
-        s_cnt[w] = cnt;
-        s_max[w] = best;
-    }
-    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) s_cnt[threadIdx.x / WAVE] = cnt;
+    uint32_t unused = 0u;
+    block_max_or(best, unused);   // also orders s_cnt
     if (threadIdx.x == 0) {
-        uint32_t c = 0u, m = 0u;
-        for (int j = 0; j < PREP_THREADS / WAVE; ++j) {
-            c += s_cnt[j];
-            m = max(m, s_max[j]);
-        }
+        uint32_t c = 0u;
+        for (int j = 0; j < PREP_THREADS / WAVE; ++j) c += s_cnt[j];
         a.blockcnt[blockIdx.x] = c;
-        a.blockmax[blockIdx.x] = m;
+        a.blockmax[blockIdx.x] = best;
     }
 }
 
-// Pass 2 (one workgroup): exclusive scan of the tile counts, M and R^2 into the scalars.
-__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* cnt, const uint32_t* bmax, int64_t nb,
-                                                      Scalars* sc) {
-    __shared__ uint32_t s_wave[1024 / WAVE];
-    __shared__ uint32_t s_wmax[1024 / WAVE];
+// 3. one block: exclusive scan of the tile counts in place, M and R^2.
+__global__ __launch_bounds__(PREP_THREADS) void k_prep_scan(PrepArgs a, int nb) {
+    __shared__ uint32_t s_wave[PREP_THREADS / WAVE];
     __shared__ uint32_t s_carry;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     if (threadIdx.x == 0) s_carry = 0u;
     __syncthreads();
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     uint32_t mx = 0u;
-    for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
-        const int64_t i = b0 + threadIdx.x;
-        const uint32_t v = i < nb ? cnt[i] : 0u;
-        if (i < nb) mx = max(mx, bmax[i]);
+    for (int b0 = 0; b0 < nb; b0 += PREP_THREADS) {
+        const int i = b0 + threadIdx.x;
+        const uint32_t v = i < nb ? a.blockcnt[i] : 0u;
+        if (i < nb) mx = max(mx, a.blockmax[i]);
         uint32_t x = v;
         for (int o = 1; o < WAVE; o <<= 1) {
             const uint32_t y = (uint32_t)__shfl_up((int)x, o);
@@ -152,53 +148,52 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* cnt, const uint3
         }
         if (lane == WAVE - 1) s_wave[w] = x;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t run = s_carry;
-            for (int j = 0; j < 1024 / WAVE; ++j) {
-                const uint32_t t = s_wave[j];
-                s_wave[j] = run;
-                run += t;
-            }
-            s_carry = run;
+        uint32_t off = s_carry, tot = 0u;
+        for (int j = 0; j < PREP_THREADS / WAVE; ++j) {
+            if (j < w) off += s_wave[j];
+            tot += s_wave[j];
         }
+        if (i < nb) a.blockcnt[i] = off + x - v;
         __syncthreads();
-        if (i < nb) cnt[i] = s_wave[w] + x - v;
+        if (threadIdx.x == 0) s_carry += tot;
         __syncthreads();
     }
-    mx = wave_max_u32(mx);
-    if (lane == 0) s_wmax[w] = mx;
-    __syncthreads();
+    uint32_t none = 0u;
+    block_max_or(mx, none);
     if (threadIdx.x == 0) {
-        uint32_t m = 0u;
-        for (int j = 0; j < 1024 / WAVE; ++j) m = max(m, s_wmax[j]);
-        sc->n_masked = s_carry;
-        sc->r2_bits = m;
+        a.sc->n_masked = s_carry;
+        a.sc->r2_bits = mx;
     }
 }
 
-// Pass 3: the masked nodes in grid order.
+// 3. the masked nodes in grid order.
 __global__ __launch_bounds__(PREP_THREADS) void k_prep_emit(PrepArgs a) {
     const float thr_val = a.sc->thr_val;
     const int64_t base = (int64_t)blockIdx.x * PREP_TILE;
-    __shared__ uint32_t s_wave[PREP_THREADS / WAVE];
-    uint32_t run = a.blockcnt[blockIdx.x];
+    __shared__ uint32_t s_wave[PREP_ITEMS][PREP_THREADS / WAVE];
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    bool m[PREP_ITEMS];
+    unsigned long long bal[PREP_ITEMS];
+#pragma unroll
     for (int k = 0; k < PREP_ITEMS; ++k) {
         const int64_t i = base + (int64_t)k * PREP_THREADS + threadIdx.x;
-        const bool m = i < a.n && node_masked(a.ref[i], thr_val, a.local);
-        const unsigned long long bal = __ballot(m);
-        if (lane == 0) s_wave[w] = (uint32_t)__popcll(bal);
-        __syncthreads();
+        m[k] = i < a.n && node_masked(a.ref[i], thr_val, a.local);
+        bal[k] = __ballot(m[k]);
+        if (lane == 0) s_wave[k][w] = (uint32_t)__popcll(bal[k]);
+    }
+    __syncthreads();
+    uint32_t run = a.blockcnt[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < PREP_ITEMS; ++k) {
         uint32_t off = run, tot = 0u;
         for (int j = 0; j < PREP_THREADS / WAVE; ++j) {
-            const uint32_t c = s_wave[j];
+            const uint32_t c = s_wave[k][j];
             if (j < w) off += c;
             tot += c;
         }
-        if (m) a.nodes[off + (uint32_t)__popcll(bal & lt)] = (uint32_t)i;
+        if (m[k]) a.nodes[off + (uint32_t)__popcll(bal[k] & lt)] = (uint32_t)(base + (int64_t)k * PREP_THREADS + threadIdx.x);
         run += tot;
-        __syncthreads();
     }
 }
 
@@ -234,13 +229,14 @@ int reduce_blocks(int64_t n) {
 
 }  // namespace
 
+int64_t prep_tiles(int64_t n) { return (n + PREP_TILE - 1) / PREP_TILE; }
+
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
     const int nbr = reduce_blocks(a.n);
-    const int64_t nb = (a.n + PREP_TILE - 1) / PREP_TILE;
-    hipLaunchKernelGGL(k_dose_max, dim3(nbr), dim3(PREP_THREADS), 0, s, a.ref, a.ev, a.n, a.part);
-    hipLaunchKernelGGL(k_finish_max, dim3(1), dim3(PREP_THREADS), 0, s, a.part, nbr, a.sc, a.thr, a.dd, a.sums);
-    hipLaunchKernelGGL(k_prep_count, dim3((unsigned)nb), dim3(PREP_THREADS), 0, s, a);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, a.blockcnt, a.blockmax, nb, a.sc);
+    const int64_t nb = prep_tiles(a.n);
+    hipLaunchKernelGGL(k_dose_max, dim3(nbr), dim3(PREP_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_prep_count, dim3((unsigned)nb), dim3(PREP_THREADS), 0, s, a, nbr);
+    hipLaunchKernelGGL(k_prep_scan, dim3(1), dim3(PREP_THREADS), 0, s, a, (int)nb);
     hipLaunchKernelGGL(k_prep_emit, dim3((unsigned)nb), dim3(PREP_THREADS), 0, s, a);
     return hipGetLastError();
 }

@@ -566,6 +566,105 @@ __device__ __forceinline__ uint32_t zero_cells(int DIM, int x, int y, int z, int
     return cx * cy * cz;
 }
 
+// Pass A with one lane per cell: the 2^d lanes of a group share one node (grid order) and
+// each takes one of its zero-key cells (table rows 0 .. 2^d-1), then the group takes the
+// minimum with shuffles.  Lighter waves than one lane per node (more of them resident, no
+// wave-quantisation tail).  Grid-stride over the nodes; MODE 0: FP32, 1: FP32 + flag.
+template <int DIM, int MODE>
+__global__ __launch_bounds__(SEARCH_THREADS) void k_zero_group(SearchArgs a, ZeroGeo zg, BlockSums* sums) {
+    constexpr int G = 1 << DIM;
+    constexpr int GROUPS = SEARCH_THREADS / G;
+    constexpr int GMODE = (DIM == 3 && MODE == 1) ? 1 : 0;
+    const uint32_t M = a.sc->n_masked;
+    const int gl = threadIdx.x % G;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, sxy = nx * ny;
+    const float inv_dd_g = a.sc->inv_dd;
+    const InvS2<float> is = inv_s2<float>(a.s2x, a.s2y, DIM == 3 ? a.s2z : 0.0f);
+    const TabEntry row = zg.row[gl];            // this lane's zero-key cell
+    const Geo<float> Gm = geo_from_row(row);
+    GuardCtx gc{};
+    uint32_t dummy_fp64 = 0, cells = 0, gm = 0, npass = 0, nborder = 0;
+
+    for (uint32_t base = blockIdx.x * GROUPS; base < M; base += gridDim.x * GROUPS) {
+        const uint32_t i = base + threadIdx.x / G;
+        const bool live = i < M;
+        const int node = live ? (int)a.nodes[i] : 0;
+        const int x = node % nx, y = (node / nx) % ny, z = DIM == 3 ? node / sxy : 0;
+        const float dr = a.ref[node];
+        const float inv_dd = node_inv_dd(dr, inv_dd_g, a.dd, a.local);
+        const float F0 = live ? gamma0_sq(a.ev[node], dr, inv_dd) : 0.0f;
+        const int qx = x + row.ax, qy = y + row.ay, qz = z + row.az;
+        const bool cin = (unsigned)qx < (unsigned)nx && (unsigned)qy < (unsigned)ny &&
+                         (DIM == 2 || (unsigned)qz < (unsigned)nz);
+        const bool okx = qx + 1 < nx, oky = qy + 1 < ny, okz = DIM == 2 || qz + 1 < nz;
+        const bool work = F0 > 0.0f && cin;
+        const bool edge = !(okx && oky && okz);
+        const bool wave_masked = __ballot(work && edge) != 0ull;
+        float c = Num<float>::inf();
+        bool ill = false;
+        if (work) {
+            const int b0 = (DIM == 3 ? qz * sxy : 0) + qy * nx + qx;
+            const int ox = okx ? 1 : 0, oy = oky ? nx : 0, oz = (DIM == 3 && okz) ? sxy : 0;
+            if constexpr (DIM == 3) {
+                float g[8];
+                g[0] = a.ev[b0];
+                g[1] = a.ev[b0 + ox];
+                g[2] = a.ev[b0 + oy];
+                g[3] = a.ev[b0 + oy + ox];
+                g[4] = a.ev[b0 + oz];
+                g[5] = a.ev[b0 + oz + ox];
+                g[6] = a.ev[b0 + oz + oy];
+                g[7] = a.ev[b0 + oz + oy + ox];
+#pragma unroll
+                for (int b = 0; b < 8; ++b) g[b] = (g[b] - dr) * inv_dd;
+                if (wave_masked)
+                    c = cell3<float, true, GMODE>(g, Gm, is, okx, oky, okz, a.den_guard, gc, dummy_fp64, ill);
+                else
+                    c = cell3<float, false, GMODE>(g, Gm, is, true, true, true, a.den_guard, gc, dummy_fp64, ill);
+            } else {
+                float g[4];
+                g[0] = a.ev[b0];
+                g[1] = a.ev[b0 + ox];
+                g[2] = a.ev[b0 + oy];
+                g[3] = a.ev[b0 + oy + ox];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) g[b] = (g[b] - dr) * inv_dd;
+                if (wave_masked)
+                    c = cell2<float, true>(g, Gm, is, okx, oky);
+                else
+                    c = cell2<float, false>(g, Gm, is, true, true);
+            }
+        }
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) {
+            c = vmin<float>(c, __shfl_xor(c, o));
+            ill = (__shfl_xor((int)ill, o) != 0) || ill;
+        }
+        // every lane of the group now holds the same F0, minimum and flag
+        const float F = vmin<float>(F0, c);
+        const bool node_guard = MODE == 1 && live && ill;
+        const bool node_tail = live && !node_guard && F > a.k1;
+        // cells are counted by the pass that finishes the node
+        if (live && !node_guard && !node_tail && work && !edge) ++cells;
+        const bool leader = gl == 0;
+        const bool to_guard = leader && node_guard;
+        const bool to_tail = leader && node_tail;
+        if (leader && live && !node_guard && !node_tail) finish_node(a, node, F, npass, nborder, gm);
+        const uint32_t pos = block_append(to_tail, &a.sc->n_tail);
+        if (to_tail) {
+            a.tail_node[pos] = (uint32_t)node;
+            a.tail_f[pos] = f2u(F);
+            a.tail_key_arr[pos] = a.tail_key ? f2u(F) : f2u(F0);
+            a.tail_pos[pos] = pos;
+        }
+        if (MODE == 1) {
+            const uint32_t gpos = block_append(to_guard, &a.sc->n_guard);
+            if (to_guard) a.guard_list[gpos] = (uint32_t)node;
+        }
+    }
+    block_sums(sums, npass, nborder, 0u, cells, gm);
+}
+
 // The walk.  TAIL: items are tail positions, the walk starts at row `first` with the bound
 // left by pass A; otherwise items are node indices and the walk starts at row 0 with
 // gamma0.  MODE 0: FP32; 1: FP32 + flag; 2: FP32 with FP64 re-projection; 3: FP64.
@@ -873,6 +972,7 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_finalize(const BlockSums* __
 
 constexpr unsigned kTailBlocks = 1024;   // grid-stride blocks of the tail walk
 constexpr unsigned kGuardBlocks = 64;    // grid-stride blocks of the guard pass
+constexpr unsigned kZeroGroupBlocks = 8192;   // grid-stride blocks of pass A, one lane per cell
 
 unsigned blocks_for(uint32_t m) { return (m + SEARCH_THREADS - 1) / SEARCH_THREADS; }
 
@@ -921,7 +1021,18 @@ hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s
         const bool guarded = p.precision == 1 && p.ndim == 3;
         const int first = p.ndim == 3 ? 8 : 4;
         // pass A
-        if (p.ndim == 3) {
+        if (p.zero_lanes) {
+            // one lane per zero-key cell, grid-stride over the nodes
+            const unsigned lanes = p.ndim == 3 ? 8u : 4u;
+            uint64_t want = ((uint64_t)p.M * lanes + SEARCH_THREADS - 1) / SEARCH_THREADS;
+            const unsigned zb = (unsigned)(want < kZeroGroupBlocks ? want : kZeroGroupBlocks);
+            if (p.ndim == 3) {
+                if (guarded) hipLaunchKernelGGL((k_zero_group<3, 1>), dim3(zb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
+                else hipLaunchKernelGGL((k_zero_group<3, 0>), dim3(zb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
+            } else {
+                hipLaunchKernelGGL((k_zero_group<2, 0>), dim3(zb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
+            }
+        } else if (p.ndim == 3) {
             if (guarded) hipLaunchKernelGGL(k_zero3<1>, dim3(nb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
             else hipLaunchKernelGGL(k_zero3<0>, dim3(nb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
         } else {

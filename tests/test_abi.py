@@ -47,7 +47,7 @@ def test_options_defaults(abi):
     assert o.sort_mode == abi.SORT_NONE
     assert o.precision == abi.PREC_GUARDED
     assert o.cond_threshold == 1e6
-    assert o.timing == 0 and o.tail_lanes == 0 and list(o.reserved) == [0] * 6
+    assert o.timing == 0 and o.tail_lanes == 0 and o.cell_lanes == 0 and list(o.reserved) == [0] * 5
 
 
 def test_status_strings(abi):
