@@ -28,6 +28,19 @@ METRIC = "ref voxels/sec, 3D 3%/3mm: plain vs learned-radius at |Δγ|≤1e-5; %
 FLOP_PER_CELL = {3: 392, 2: 82}
 PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (packed)
 
+# HBM bytes per launch of the dominant kernel, from the FETCH_SIZE and WRITE_SIZE counter
+# runs summarised in the named profile (each counter scaled by what it reads for a plain
+# 256 MiB device copy).  They hold only for the kernel source they were taken on: when its
+# hash differs the traffic is reported as null.
+TRAFFIC = {
+    "3d_128x128x96_2.5mm": {
+        "bytes": (15.62 + 2.25) * 1e6,
+        "source": "paper_1012_1900_amd/csrc/k_search.hip",
+        "sha256": "740b2005b4861fd6fa1ae5638b1f6a2639b9a43ba51ae3483dcfabdb5ac33b29",
+        "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
+    },
+}
+
 WORKLOADS = {
     "3d_128x128x96_2.5mm": ("3d_128x128x96_2.5mm", 100, "3D 128x128x96 at 2.5 mm, 7-beam synthetic IMRT-like pair (seed 100)"),
     "3d_256x256x192_1.25mm": ("3d_256x256x192_1.25mm", 200, "3D 256x256x192 at 1.25 mm, 7-beam synthetic IMRT-like pair (seed 200)"),
@@ -46,6 +59,20 @@ def work_counts(cfg, seed, dd, dta):
     except OSError:
         return None
     return table.get(f"{cfg}/seed{seed}/{dd * 100:g}%/{dta:g}mm/global/thr0.1")
+
+
+def traffic_bytes(workload, kernel_default):
+    t = TRAFFIC.get(workload)
+    if t is None or not kernel_default:
+        return None
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, t["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+                return None
+    except OSError:
+        return None
+    return t["bytes"]
 
 
 def cpu_baseline(pair, dd, dta, reps):
@@ -158,7 +185,9 @@ def main():
         kern = "k_zero_group" if args.cell_lanes in (4, 8) else ("k_zero3" if nd == 3 else "k_zero2")
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                    "traffic": None, "kernel": f"{kern} (key-0 cells of every node)",
+                    "traffic": traffic_bytes(args.workload, kern == "k_zero3" and args.dd == 0.03
+                                             and args.dta == 3.0 and args.precision == "guarded"),
+                    "kernel": f"{kern} (key-0 cells of every node)",
                     "algorithmic_flop_per_launch": flops, "avg_launch_ms": round(ms_search, 5)}
 
     cpu = None

@@ -186,6 +186,78 @@ gammax_status_t gammax_build_table(gammax_ctx_t *ctx, int32_t ndim, const int64_
 gammax_status_t gammax_pass_count(gammax_ctx_t *ctx, const float *gamma_dev, int64_t n,
                                   uint64_t *counts, void *stream);
 
+/*
+ * ---- Learned search radius (an addition around the paper's method) ----------------------
+ *
+ * A small 3D CNN predicts y = log(gamma + 0.01) at every node from the 9x9x9 neighbourhood
+ * of two features, f0 = D_r / max D_r and f1 = (D_e - D_r) / (DD * max D_r) (global dD),
+ * zero outside the grid.  Four valid 3x3x3 convolutions with channels 2 -> 16 -> 16 ->
+ * 16 -> 1, ReLU after the first three, over the features padded by 4 nodes.  bf16
+ * operands on the matrix cores, FP32 accumulation and biases, bf16 hidden activations.
+ * The prediction only orders the search and bounds its first attempt; every gamma the
+ * library returns is still the exact search result.
+ *
+ * Parameters: GAMMAX_MODEL_NPARAM floats, per layer W[co][ci][dz][dy][dx] then b[co].
+ */
+#define GAMMAX_MODEL_NPARAM 15169
+
+typedef struct gammax_model gammax_model_t;
+
+typedef struct {
+    float lr;       /* Adam step size */
+    float beta1;    /* 0.9 */
+    float beta2;    /* 0.999 */
+    float eps;      /* 1e-8 */
+} gammax_adam_t;
+
+/* Create a model on HIP device `device` from GAMMAX_MODEL_NPARAM host floats (copied). */
+gammax_status_t gammax_model_create(int device, const float *params, gammax_model_t **model);
+
+/* Release the model.  NULL is accepted. */
+gammax_status_t gammax_model_destroy(gammax_model_t *model);
+
+/* Copy the FP32 parameters and/or the gradient of the last training step (each
+ * GAMMAX_MODEL_NPARAM host floats; either pointer may be NULL, not both).  Synchronises. */
+gammax_status_t gammax_model_get_params(gammax_model_t *model, float *params, float *grad);
+
+/* Detail of the last failure of a model call; never NULL. */
+const char *gammax_model_last_error(const gammax_model_t *model);
+
+/*
+ * Input features of one dose pair on the grid padded by 4 nodes: (nz+8) x (ny+8) x (nx+8)
+ * nodes of 2 bf16 each (uint16 bit patterns, channel fastest), device memory.  3D only.
+ * Uses the context's dose maximum pass.  Synchronises.
+ */
+gammax_status_t gammax_model_features(gammax_ctx_t *ctx, const gammax_problem_t *problem,
+                                      const float *ref_dev, const float *eval_dev,
+                                      uint16_t *feat_dev, void *stream);
+
+/*
+ * Prediction y = log(gamma_hat + 0.01) at every node of one dose pair (N floats, device).
+ * 3D only.  Synchronises.
+ */
+gammax_status_t gammax_model_predict(gammax_ctx_t *ctx, gammax_model_t *model,
+                                     const gammax_problem_t *problem, const float *ref_dev,
+                                     const float *eval_dev, float *y_dev, void *stream);
+
+/*
+ * Forward pass over nvol crops: feat_dev holds nvol volumes of (c0+8) x (c1+8) x (c2+8)
+ * feature nodes (2 bf16 each), y_dev receives nvol x c0 x c1 x c2 floats.  Synchronises.
+ */
+gammax_status_t gammax_model_forward(gammax_model_t *model, int32_t nvol, const int64_t *crop,
+                                     const uint16_t *feat_dev, float *y_dev, void *stream);
+
+/*
+ * One training step on nvol crops: features as in gammax_model_forward, gamma_dev holds
+ * nvol x c0 x c1 x c2 labels (gamma >= 0 marks a node that counts; others are ignored).
+ * Loss = mean over counted nodes of (y - log(gamma + 0.01))^2.  Computes the gradient
+ * (readable with gammax_model_get_params), takes one Adam step on the FP32 parameters
+ * and returns the loss before the step in *loss (may be NULL).  Synchronises.
+ */
+gammax_status_t gammax_model_train_step(gammax_model_t *model, int32_t nvol, const int64_t *crop,
+                                        const uint16_t *feat_dev, const float *gamma_dev,
+                                        const gammax_adam_t *adam, double *loss, void *stream);
+
 /* Static description of a status code. */
 const char *gammax_status_string(gammax_status_t status);
 

@@ -23,8 +23,10 @@ log(gamma + 0.01) at that node.
 * Training: loss = mean over masked nodes of (y - log(gamma + 0.01))^2; gradients by
   the chain rule written out (bwd-data = full correlation with the flipped, transposed
   kernel; bwd-weight = correlation of the layer input with the output gradient; ReLU
-  passes the gradient where its output is > 0); Adam (Kingma & Ba 2015) with bias
-  correction on the FP32 master weights.
+  passes the gradient where its stored output is > 0); Adam (Kingma & Ba 2015) with bias
+  correction on the FP32 master weights.  The output gradient of every layer is rounded
+  to bfloat16 (it is a matrix-core operand in the kernels); the weight gradients are
+  exact sums of those bf16 products here, FP32 sums in the kernels.
 
 Parameter layout (one flat float array, the order the C ABI uses): for each layer l,
 W_l[co][ci][dz][dy][dx] followed by b_l[co].
@@ -138,16 +140,18 @@ class Forward:
     y: np.ndarray                # last layer output (grid shape)
 
 
-def forward(theta: np.ndarray, feats: np.ndarray, rounding: bool = True) -> Forward:
+def forward(theta: np.ndarray, feats: np.ndarray, rounding: bool = True, padded: bool = False) -> Forward:
     """Run the network on features of shape (2, Z, Y, X); returns every activation.
 
+    padded=False pads the features with zeros by 4 nodes (output shape = input shape);
+    padded=True takes them as given (a crop with its neighbourhood: output 8 smaller).
     rounding=False drops the bf16 rounding of weights and activations and the FP32
     rounding of the biases (exact FP64 network) - used by the finite-difference checks.
     """
     rnd = bf16 if rounding else (lambda a: np.asarray(a, dtype=np.float64))
     f32 = (lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)) if rounding else rnd
     params = unflatten(theta)
-    x = pad(rnd(feats))
+    x = rnd(feats) if padded else pad(rnd(feats))
     inputs, pre = [], []
     for l, (w, b) in enumerate(params):
         inputs.append(x)
@@ -163,17 +167,21 @@ def target(gamma: np.ndarray) -> np.ndarray:
 
 
 def loss_and_grad(theta: np.ndarray, feats: np.ndarray, gamma: np.ndarray, mask: np.ndarray,
-                  rounding: bool = True):
-    """Masked mean-squared error on log(gamma + 0.01) and its gradient (flat, FP64)."""
+                  rounding: bool = True, padded: bool = False, count: int = None):
+    """Masked mean-squared error on log(gamma + 0.01) and its gradient (flat, FP64).
+
+    count: the number of nodes the mean runs over (default: the masked nodes here; a
+    batch of crops shares the count of the whole batch).
+    """
     rnd = bf16 if rounding else (lambda a: np.asarray(a, dtype=np.float64))
-    fw = forward(theta, feats, rounding)
+    fw = forward(theta, feats, rounding, padded)
     params = unflatten(theta)
     m = np.asarray(mask, dtype=bool)
-    cnt = max(int(m.sum()), 1)
+    cnt = max(int(m.sum()), 1) if count is None else count
     t = np.where(m, target(np.where(m, gamma, 1.0)), 0.0)
     r = np.where(m, fw.y - t, 0.0)
     loss = float((r * r).sum() / cnt)
-    g = (2.0 / cnt) * r[None]                       # d loss / d (last layer output)
+    g = rnd((2.0 / cnt) * r[None])                  # d loss / d (last layer output)
     grads = [None] * len(params)
     for l in range(len(params) - 1, -1, -1):
         w, _ = params[l]
@@ -182,7 +190,9 @@ def loss_and_grad(theta: np.ndarray, feats: np.ndarray, gamma: np.ndarray, mask:
         grads[l] = (gw, gb)
         if l > 0:
             gx = conv3d_bwd_data(g, rnd(w), x.shape[1:])
-            g = gx * (fw.pre[l - 1] > 0.0)           # ReLU of the previous layer
+            # ReLU of the previous layer: the gradient passes where the stored activation
+            # (this layer's input) is positive
+            g = rnd(gx * (x > 0.0))
     return loss, flatten(grads), fw
 
 

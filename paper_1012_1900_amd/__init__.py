@@ -7,6 +7,9 @@ This package is the thin Python binding of its C ABI (``include/gammax.h``).
 from ._abi import (  # noqa: F401
     Context,
     GammaResult,
+    Model,
+    MODEL_NPARAM,
+    model_features,
     GammaxError,
     build_table,
     context,

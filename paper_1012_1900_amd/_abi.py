@@ -358,6 +358,150 @@ def pass_count(gamma, ctx: Optional[Context] = None) -> Tuple[int, int, int]:
     return int(counts[0]), int(counts[1]), int(counts[2])
 
 
+# ---- learned search radius ---------------------------------------------------------------
+
+MODEL_NPARAM = 15169
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+_lib.gammax_model_create.restype = C.c_int
+_lib.gammax_model_create.argtypes = [C.c_int, C.POINTER(C.c_float), C.POINTER(_vp)]
+_lib.gammax_model_destroy.restype = C.c_int
+_lib.gammax_model_destroy.argtypes = [_vp]
+_lib.gammax_model_get_params.restype = C.c_int
+_lib.gammax_model_get_params.argtypes = [_vp, _vp, _vp]
+_lib.gammax_model_last_error.restype = C.c_char_p
+_lib.gammax_model_last_error.argtypes = [_vp]
+_lib.gammax_model_features.restype = C.c_int
+_lib.gammax_model_features.argtypes = [_vp, C.POINTER(Problem), _vp, _vp, _vp, _vp]
+_lib.gammax_model_predict.restype = C.c_int
+_lib.gammax_model_predict.argtypes = [_vp, _vp, C.POINTER(Problem), _vp, _vp, _vp, _vp]
+_lib.gammax_model_forward.restype = C.c_int
+_lib.gammax_model_forward.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64), _vp, _vp, _vp]
+_lib.gammax_model_train_step.restype = C.c_int
+_lib.gammax_model_train_step.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64), _vp, _vp,
+                                         C.POINTER(Adam), C.POINTER(C.c_double), _vp]
+
+
+class Model:
+    """The learned-radius CNN on one device (``gammax_model_*``)."""
+
+    def __init__(self, params, device: int = 0):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        if p.size != MODEL_NPARAM:
+            raise ValueError(f"expected {MODEL_NPARAM} parameters, got {p.size}")
+        h = _vp()
+        st = _lib.gammax_model_create(int(device), p.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h))
+        if st != 0:
+            raise GammaxError(st)
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gammax_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st: int):
+        if st != 0:
+            raise GammaxError(st, _lib.gammax_model_last_error(self.handle).decode(errors="replace"))
+
+    def params(self):
+        import numpy as np
+        out = np.empty(MODEL_NPARAM, dtype=np.float32)
+        self.check(_lib.gammax_model_get_params(self.handle, out.ctypes.data, None))
+        return out
+
+    def grad(self):
+        import numpy as np
+        out = np.empty(MODEL_NPARAM, dtype=np.float32)
+        self.check(_lib.gammax_model_get_params(self.handle, None, out.ctypes.data))
+        return out
+
+    def forward(self, feats):
+        """y for a batch of feature crops: int16/uint16 tensor (B, c0+8, c1+8, c2+8, 2)."""
+        torch = _torch()
+        if feats.dim() != 5 or feats.shape[-1] != 2 or feats.dtype not in (torch.int16, torch.uint16):
+            raise ValueError("features must be a (B, z, y, x, 2) 16-bit tensor")
+        if not feats.is_contiguous() or feats.device.type != "cuda":
+            raise ValueError("features must be a contiguous device tensor")
+        b = feats.shape[0]
+        crop = (C.c_int64 * 3)(*[int(n) - 8 for n in feats.shape[1:4]])
+        y = torch.empty((b, crop[0], crop[1], crop[2]), dtype=torch.float32, device=feats.device)
+        s = torch.cuda.current_stream(feats.device)
+        with torch.cuda.device(feats.device):
+            st = _lib.gammax_model_forward(self.handle, b, crop, feats.data_ptr(), y.data_ptr(), _vp(s.cuda_stream))
+        self.check(st)
+        return y
+
+    def train_step(self, feats, gamma, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                   eps: float = 1e-8) -> float:
+        """One Adam step on a batch of crops; returns the loss before the step."""
+        torch = _torch()
+        if feats.dim() != 5 or feats.shape[-1] != 2 or feats.dtype not in (torch.int16, torch.uint16):
+            raise ValueError("features must be a (B, z, y, x, 2) 16-bit tensor")
+        _dev_tensor(gamma, "gamma")
+        b = feats.shape[0]
+        crop = (C.c_int64 * 3)(*[int(n) - 8 for n in feats.shape[1:4]])
+        if tuple(gamma.shape) != (b, crop[0], crop[1], crop[2]):
+            raise ValueError("gamma must have shape (B, c0, c1, c2)")
+        hp = Adam(lr, beta1, beta2, eps)
+        loss = C.c_double()
+        s = torch.cuda.current_stream(feats.device)
+        with torch.cuda.device(feats.device):
+            st = _lib.gammax_model_train_step(self.handle, b, crop, feats.data_ptr(), gamma.data_ptr(),
+                                              C.byref(hp), C.byref(loss), _vp(s.cuda_stream))
+        self.check(st)
+        return loss.value
+
+    def predict(self, ref, ev, spacing: Sequence[float], dd: float, dta: float = 3.0,
+                ctx: Optional[Context] = None):
+        """y = log(gamma_hat + 0.01) on the grid of a 3D dose pair (float32 tensor)."""
+        torch = _torch()
+        _dev_tensor(ref, "ref")
+        _dev_tensor(ev, "ev")
+        ctx = ctx or context(ref.device.index or 0)
+        prob = make_problem(ref.shape, spacing, dd, dta, 0.1, False)
+        y = torch.empty_like(ref)
+        s = torch.cuda.current_stream(ref.device)
+        with torch.cuda.device(ref.device):
+            st = _lib.gammax_model_predict(ctx.handle, self.handle, C.byref(prob), ref.data_ptr(),
+                                           ev.data_ptr(), y.data_ptr(), _vp(s.cuda_stream))
+        ctx.check(st)
+        return y
+
+
+def model_features(ref, ev, spacing: Sequence[float], dd: float, dta: float = 3.0,
+                   ctx: Optional[Context] = None):
+    """Input features of a 3D pair on the grid padded by 4: int16 tensor (z+8, y+8, x+8, 2)
+    holding bf16 bit patterns."""
+    torch = _torch()
+    _dev_tensor(ref, "ref")
+    _dev_tensor(ev, "ev")
+    if ref.dim() != 3:
+        raise ValueError("the learned radius is 3D only")
+    ctx = ctx or context(ref.device.index or 0)
+    prob = make_problem(ref.shape, spacing, dd, dta, 0.1, False)
+    feat = torch.empty((ref.shape[0] + 8, ref.shape[1] + 8, ref.shape[2] + 8, 2), dtype=torch.int16,
+                       device=ref.device)
+    s = torch.cuda.current_stream(ref.device)
+    with torch.cuda.device(ref.device):
+        st = _lib.gammax_model_features(ctx.handle, C.byref(prob), ref.data_ptr(), ev.data_ptr(),
+                                        feat.data_ptr(), _vp(s.cuda_stream))
+    ctx.check(st)
+    return feat
+
+
 def raw_library() -> C.CDLL:
     """The loaded shared library (for symbol checks)."""
     return _lib

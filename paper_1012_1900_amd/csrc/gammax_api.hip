@@ -17,6 +17,7 @@
 
 #include "gammax.h"
 #include "internal.hpp"
+#include "model.hpp"
 
 using namespace gammax;
 
@@ -77,6 +78,9 @@ struct gammax_ctx {
     bool graph_broken = false;      // capture failed once: launch directly from then on
     hipEvent_t ev[10] = {};
     bool events = false;
+    // learned radius: features and hidden activations of one grid
+    unsigned char* cnn_ws = nullptr;
+    int64_t cnn_ws_cap = 0;
 };
 
 namespace {
@@ -467,6 +471,71 @@ gammax_status_t device_errors(gammax_ctx* c, bool local) {
     return GAMMAX_OK;
 }
 
+// Workspace of the CNN over one grid: features (o+8, 2 channels), then the three hidden
+// activations (o+6, o+4, o+2; 16 channels), each 256-byte aligned.
+struct CnnWs {
+    uint16_t *feat, *a1, *a2, *a3;
+    int64_t bytes;
+};
+CnnWs cnn_layout(unsigned char* base, const int o[3]) {
+    CnnWs w{};
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        uint16_t* p = base ? (uint16_t*)(base + off) : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    int sh[3];
+    act_shape(o, 8, sh);
+    w.feat = take(vol_of(sh) * 4);
+    act_shape(o, 6, sh);
+    w.a1 = take(vol_of(sh) * 32);
+    act_shape(o, 4, sh);
+    w.a2 = take(vol_of(sh) * 32);
+    act_shape(o, 2, sh);
+    w.a3 = take(vol_of(sh) * 32);
+    w.bytes = off;
+    return w;
+}
+
+gammax_status_t grow_cnn(gammax_ctx* c, const int o[3], CnnWs* w) {
+    const int64_t need = cnn_layout(nullptr, o).bytes;
+    if (need > c->cnn_ws_cap || !c->cnn_ws) {
+        gammax_status_t st = grow(c, &c->cnn_ws, &c->cnn_ws_cap, need);
+        if (st != GAMMAX_OK) return st;
+    }
+    *w = cnn_layout(c->cnn_ws, o);
+    return GAMMAX_OK;
+}
+
+// Dose maximum and the global 1/dD of a pair into the context's scalars.
+gammax_status_t enqueue_dose_scalars(gammax_ctx* c, const gammax_problem_t* p, const float* ref, const float* ev,
+                                     int64_t n, hipStream_t s) {
+    gammax_status_t st = grow(c, &c->part, &c->part_cap, 2 * MAX_BLOCKS);
+    if (st != GAMMAX_OK) return st;
+    PrepArgs pa{};
+    pa.ref = ref;
+    pa.ev = ev;
+    pa.n = n;
+    pa.thr = (float)p->dose_threshold;
+    pa.dd = (float)p->dd;
+    pa.local = p->norm == GAMMAX_LOCAL ? 1 : 0;
+    pa.sc = c->d_sc;
+    pa.part = c->part;
+    HIPCHK(c, launch_dose_scalars(pa, s));
+    return GAMMAX_OK;
+}
+
+gammax_status_t model_inputs(gammax_ctx* c, const gammax_problem_t* p, const float* ref, const float* ev,
+                             int o[3], int64_t* n) {
+    if (!ref || !ev) return fail(c, GAMMAX_E_NULL, "dose pointers are required");
+    gammax_status_t st = check_problem(c, p, n);
+    if (st != GAMMAX_OK) return st;
+    if (p->ndim != 3) return fail(c, GAMMAX_E_SHAPE, "the learned radius is 3D only");
+    for (int i = 0; i < 3; ++i) o[i] = (int)p->shape[i];
+    return GAMMAX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -518,7 +587,7 @@ gammax_status_t gammax_ctx_destroy(gammax_ctx_t* c) {
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void* dev[] = {c->d_sc, c->d_cnt, c->d_count, c->work, c->blockcnt, c->part, c->hist,
-                   c->sums, c->tab, c->tb, c->tb_hist};
+                   c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* host[] = {c->h_sc, c->h_cnt, c->h_count};
@@ -726,6 +795,48 @@ gammax_status_t gammax_pass_count(gammax_ctx_t* c, const float* gamma_dev, int64
     HIPCHK(c, hipStreamSynchronize(s));
     for (int i = 0; i < 3; ++i) counts[i] = c->h_cnt[i];
     return GAMMAX_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+gammax_status_t gammax_model_features(gammax_ctx_t* c, const gammax_problem_t* p, const float* ref,
+                                      const float* ev, uint16_t* feat, void* stream) {
+    if (!c) return GAMMAX_E_NULL;
+    if (!feat) return fail(c, GAMMAX_E_NULL, "feature buffer is required");
+    int o[3];
+    int64_t n = 0;
+    gammax_status_t st = model_inputs(c, p, ref, ev, o, &n);
+    if (st != GAMMAX_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((st = enqueue_dose_scalars(c, p, ref, ev, n, s)) != GAMMAX_OK) return st;
+    HIPCHK(c, launch_features(ref, ev, o, c->d_sc, feat, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return device_errors(c, false);
+}
+
+gammax_status_t gammax_model_predict(gammax_ctx_t* c, gammax_model_t* m, const gammax_problem_t* p,
+                                     const float* ref, const float* ev, float* y, void* stream) {
+    if (!c) return GAMMAX_E_NULL;
+    if (!m || !y) return fail(c, GAMMAX_E_NULL, "model and output are required");
+    if (m->device != c->device) return fail(c, GAMMAX_E_PARAM, "model and context live on different devices");
+    int o[3];
+    int64_t n = 0;
+    gammax_status_t st = model_inputs(c, p, ref, ev, o, &n);
+    if (st != GAMMAX_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    CnnWs w;
+    if ((st = grow_cnn(c, o, &w)) != GAMMAX_OK) return st;
+    if ((st = enqueue_dose_scalars(c, p, ref, ev, n, s)) != GAMMAX_OK) return st;
+    HIPCHK(c, launch_features(ref, ev, o, c->d_sc, w.feat, s));
+    HIPCHK(c, model_forward(m, w.feat, 1, o, w.a1, w.a2, w.a3, y, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return device_errors(c, false);
 }
 
 }  // extern "C"

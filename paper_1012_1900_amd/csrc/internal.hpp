@@ -102,6 +102,9 @@ struct PrepArgs {
 
 int64_t prep_tiles(int64_t n);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
+// Only the dose maximum, the finiteness flag, the threshold value and the global 1/dD
+// (uses ref, ev, n, thr, dd, sc, part).
+hipError_t launch_dose_scalars(const PrepArgs& a, hipStream_t s);
 hipError_t launch_pass_count(const float* gamma, int64_t n, unsigned long long* counts3, hipStream_t s);
 
 // ---- sort --------------------------------------------------------------------------------

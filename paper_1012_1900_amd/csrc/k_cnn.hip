@@ -1,0 +1,506 @@
+// The learned search radius: a 3D CNN that predicts log(gamma + 0.01) at every node from
+// the 9x9x9 neighbourhood of two dose features, with its training kernels.  Not part of
+// the paper's method; an addition around it (its output only orders and bounds the
+// search, never changes a gamma value).
+//
+// Network: four valid 3x3x3 convolutions, channels 2 -> 16 -> 16 -> 16 -> 1, ReLU after
+// the first three, on features zero-padded by 4 nodes, so the output covers the grid.
+// Arithmetic: bf16 operands (weights and activations, round to nearest even) on the
+// matrix cores (v_mfma_f32_16x16x32_bf16), FP32 accumulation, FP32 biases; hidden
+// activations are stored as bf16 after the ReLU, the last layer's output as FP32.
+//
+// Layouts.  Activations are channel-last: [volume][z][y][x][C] bf16 (C = 16, or 2 for the
+// features), so one node's 16 channels are one 32-byte load.  A convolution is an
+// implicit GEMM per 16-node row segment along x: D[co][node] = sum_k W[co][k] X[k][node],
+// k = (tap, ci).  The weights are the A operand, packed once per update into the lane
+// order of the instruction ("fragments", 16 bytes per lane per 32-wide k chunk) and held
+// in registers; the input tile (with its halo) is staged in LDS and read as the B operand;
+// each lane's result is 4 consecutive output channels of one node (an 8-byte store).
+//
+// Backward: bwd-data is the same kernel run on the output gradient with the flipped,
+// transposed kernel and an input offset of -2 (full correlation), times the ReLU mask of
+// the stored activation; bwd-weight contracts over nodes (D[co][ci] per tap, both
+// operands staged planar in LDS), one partial per workgroup, reduced deterministically.
+#include "internal.hpp"
+#include "cnn.hpp"
+
+namespace gammax {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct alignas(16) U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint32_t h) { return __builtin_bit_cast(float, (h & 0xFFFFu) << 16); }
+
+__device__ __forceinline__ f32x4 mfma_bf16(const U4& a, const U4& b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+constexpr int TX = CNN_TILE_X, TY = CNN_TILE_Y, TZ = CNN_TILE_Z;
+constexpr int LX = TX + 2, LY = TY + 2, LZ = TZ + 2;
+constexpr int NTHREADS = 256;
+
+__device__ __forceinline__ void tap_xyz(int t, int& dz, int& dy, int& dx) {
+    dz = t / 9;
+    dy = (t / 3) % 3;
+    dx = t % 3;
+}
+
+// ---- forward / bwd-data convolution ----------------------------------------------------
+//
+// MODE 0: out = bf16(relu(acc + bias)), 16 channels.
+// MODE 1: out = acc + bias, channel 0 only, FP32 (the last layer).
+// MODE 2: out = bf16(mask > 0 ? acc : 0), 16 channels, no bias (bwd-data with the ReLU
+//         derivative of the stored activation `mask`, which has the output's shape).
+template <int CIN, int MODE>
+__global__ __launch_bounds__(NTHREADS) void k_conv(ConvArgs a) {
+    constexpr int NCH = CIN == 16 ? 14 : 2;      // 32-wide k chunks: ceil(27 * CIN / 32)
+    __shared__ __align__(16) uint16_t tile[LZ * LY * LX * CIN];
+
+    int b = blockIdx.x;
+    const int txi = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int tyi = b % a.tiles_y;
+    b /= a.tiles_y;
+    const int tzi = b % a.tiles_z;
+    const int vol = b / a.tiles_z;
+    const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * TZ;
+    const uint16_t* in = a.in + (int64_t)vol * a.in_vstride;
+
+    // stage the input tile (halo 2 on the upper side; coordinates shifted by `off`);
+    // nodes outside the input volume read as 0
+    if (CIN == 16) {
+        for (int u = threadIdx.x; u < LZ * LY * LX * 2; u += NTHREADS) {
+            const int v = u >> 1, h = u & 1;
+            const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
+            const int gx = x0 + lx + a.off, gy = y0 + ly + a.off, gz = z0 + lz + a.off;
+            U4 q = {0u, 0u, 0u, 0u};
+            if (gx >= 0 && gx < a.ix && gy >= 0 && gy < a.iy && gz >= 0 && gz < a.iz)
+                q = *reinterpret_cast<const U4*>(in + (((int64_t)gz * a.iy + gy) * a.ix + gx) * 16 + h * 8);
+            *reinterpret_cast<U4*>(&tile[v * 16 + h * 8]) = q;
+        }
+    } else {
+        for (int v = threadIdx.x; v < LZ * LY * LX; v += NTHREADS) {
+            const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
+            const int gx = x0 + lx + a.off, gy = y0 + ly + a.off, gz = z0 + lz + a.off;
+            uint32_t q = 0u;
+            if (gx >= 0 && gx < a.ix && gy >= 0 && gy < a.iy && gz >= 0 && gz < a.iz)
+                q = *reinterpret_cast<const uint32_t*>(in + (((int64_t)gz * a.iy + gy) * a.ix + gx) * 2);
+            *reinterpret_cast<uint32_t*>(&tile[v * 2]) = q;
+        }
+    }
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    U4 wr[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) wr[c] = reinterpret_cast<const U4*>(a.wfrag)[c * 64 + lane];
+    float bias[4] = {0.f, 0.f, 0.f, 0.f};
+    if (MODE != 2) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bias[r] = (4 * g + r < a.cout) ? a.bias[4 * g + r] : 0.f;
+    }
+    // per-lane LDS offsets (in nodes) of the taps this lane reads in each chunk
+    int toff[CIN == 16 ? NCH : NCH * 4];
+    if (CIN == 16) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            int t = 2 * c + (g >> 1);
+            t = t > 26 ? 26 : t;   // zero weights there; any finite operand will do
+            int dz, dy, dx;
+            tap_xyz(t, dz, dy, dx);
+            toff[c] = (dz * LY + dy) * LX + dx;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                int t = 16 * c + 4 * g + q;
+                t = t > 26 ? 26 : t;
+                int dz, dy, dx;
+                tap_xyz(t, dz, dy, dx);
+                toff[c * 4 + q] = (dz * LY + dy) * LX + dx;
+            }
+    }
+    __syncthreads();
+
+    for (int row = wv; row < TY * TZ; row += NTHREADS / 64) {
+        const int ry = row % TY, rz = row / TY;
+        const int oy = y0 + ry, oz = z0 + rz;
+        if (oy >= a.oy || oz >= a.oz) continue;   // wave-uniform
+        const int base = (rz * LY + ry) * LX + j;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            U4 bop;
+            if (CIN == 16) {
+                bop = *reinterpret_cast<const U4*>(&tile[(base + toff[c]) * 16 + (g & 1) * 8]);
+            } else {
+                bop.x = *reinterpret_cast<const uint32_t*>(&tile[(base + toff[c * 4 + 0]) * 2]);
+                bop.y = *reinterpret_cast<const uint32_t*>(&tile[(base + toff[c * 4 + 1]) * 2]);
+                bop.z = *reinterpret_cast<const uint32_t*>(&tile[(base + toff[c * 4 + 2]) * 2]);
+                bop.w = *reinterpret_cast<const uint32_t*>(&tile[(base + toff[c * 4 + 3]) * 2]);
+            }
+            acc = mfma_bf16(wr[c], bop, acc);
+        }
+        const int ox = x0 + j;
+        if (ox >= a.ox) continue;
+        const int64_t node = ((int64_t)oz * a.oy + oy) * a.ox + ox;
+        if (MODE == 1) {
+            if (g == 0) reinterpret_cast<float*>(a.out)[(int64_t)vol * a.out_vstride + node] = acc[0] + bias[0];
+        } else {
+            uint16_t h[4];
+            if (MODE == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h[r] = f2bf(fmaxf(acc[r] + bias[r], 0.f));
+            } else {
+                const uint2 m = *reinterpret_cast<const uint2*>(a.mask + (int64_t)vol * a.out_vstride + node * 16 + 4 * g);
+                h[0] = bf2f(m.x) > 0.f ? f2bf(acc[0]) : 0;
+                h[1] = bf2f(m.x >> 16) > 0.f ? f2bf(acc[1]) : 0;
+                h[2] = bf2f(m.y) > 0.f ? f2bf(acc[2]) : 0;
+                h[3] = bf2f(m.y >> 16) > 0.f ? f2bf(acc[3]) : 0;
+            }
+            uint2 st;
+            st.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+            st.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+            *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.out) + (int64_t)vol * a.out_vstride + node * 16 +
+                                      4 * g) = st;
+        }
+    }
+}
+
+// ---- bwd-weight --------------------------------------------------------------------------
+//
+// Per workgroup: one TX x TY x TZ tile of output nodes of one volume.  For each tap,
+// D[co][ci] = sum over the tile's nodes of g[node][co] * x[node + tap][ci]  (k = nodes).
+// Both operands are staged planar in LDS (channel-major) so that 8 consecutive nodes of
+// one channel are contiguous.  Output: partial[block][tap][co][ci] and the bias partial
+// sum_node g[node][co] at partial[block][27 * 256 + co].
+template <int CIN>
+__global__ __launch_bounds__(NTHREADS) void k_conv_bwdw(BwdWArgs a) {
+    constexpr int NX = LZ * LY * LX, NG = TZ * TY * TX;
+    __shared__ __align__(16) uint16_t xs[CIN * NX];
+    __shared__ __align__(16) uint16_t gs[16 * NG];
+    __shared__ float bsum[NTHREADS];
+
+    int b = blockIdx.x;
+    const int txi = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int tyi = b % a.tiles_y;
+    b /= a.tiles_y;
+    const int tzi = b % a.tiles_z;
+    const int vol = b / a.tiles_z;
+    const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * TZ;
+    const uint16_t* xin = a.x + (int64_t)vol * a.x_vstride;
+    const uint16_t* gin = a.g + (int64_t)vol * a.g_vstride;
+
+    for (int v = threadIdx.x; v < NX; v += NTHREADS) {
+        const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
+        const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+        const bool in = gx < a.ix && gy < a.iy && gz < a.iz;
+        const int64_t src = (((int64_t)gz * a.iy + gy) * a.ix + gx) * CIN;
+        if (CIN == 16) {
+            U4 q0 = {0u, 0u, 0u, 0u}, q1 = {0u, 0u, 0u, 0u};
+            if (in) {
+                q0 = *reinterpret_cast<const U4*>(xin + src);
+                q1 = *reinterpret_cast<const U4*>(xin + src + 8);
+            }
+            const uint32_t w8[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                xs[(2 * c) * NX + v] = (uint16_t)(w8[c] & 0xFFFFu);
+                xs[(2 * c + 1) * NX + v] = (uint16_t)(w8[c] >> 16);
+            }
+        } else {
+            uint32_t q = in ? *reinterpret_cast<const uint32_t*>(xin + src) : 0u;
+            xs[v] = (uint16_t)(q & 0xFFFFu);
+            xs[NX + v] = (uint16_t)(q >> 16);
+        }
+    }
+    for (int v = threadIdx.x; v < NG; v += NTHREADS) {
+        const int tx = v % TX, ty = (v / TX) % TY, tz = v / (TX * TY);
+        const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
+        U4 q0 = {0u, 0u, 0u, 0u}, q1 = {0u, 0u, 0u, 0u};
+        if (gx < a.ox && gy < a.oy && gz < a.oz) {
+            const int64_t src = (((int64_t)gz * a.oy + gy) * a.ox + gx) * 16;
+            q0 = *reinterpret_cast<const U4*>(gin + src);
+            q1 = *reinterpret_cast<const U4*>(gin + src + 8);
+        }
+        const uint32_t w8[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            gs[(2 * c) * NG + v] = (uint16_t)(w8[c] & 0xFFFFu);
+            gs[(2 * c + 1) * NG + v] = (uint16_t)(w8[c] >> 16);
+        }
+    }
+    __syncthreads();
+
+    float* part = a.partial + (int64_t)blockIdx.x * CNN_PARTIAL_STRIDE;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    for (int t = wv; t < 27; t += NTHREADS / 64) {
+        int dz, dy, dx;
+        tap_xyz(t, dz, dy, dx);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < NG / 32; ++c) {
+            const int row = 2 * c + (g >> 1);           // row = tz * TY + ty
+            const int ty = row % TY, tz = row / TY, xo = 8 * (g & 1);
+            const U4 aop = *reinterpret_cast<const U4*>(&gs[j * NG + row * TX + xo]);
+            U4 bop = {0u, 0u, 0u, 0u};
+            if (j < CIN) {
+                const uint16_t* p = &xs[j * NX + ((tz + dz) * LY + ty + dy) * LX + xo + dx];
+                bop.x = (uint32_t)p[0] | ((uint32_t)p[1] << 16);
+                bop.y = (uint32_t)p[2] | ((uint32_t)p[3] << 16);
+                bop.z = (uint32_t)p[4] | ((uint32_t)p[5] << 16);
+                bop.w = (uint32_t)p[6] | ((uint32_t)p[7] << 16);
+            }
+            acc = mfma_bf16(aop, bop, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[t * 256 + (4 * g + r) * 16 + j] = acc[r];
+    }
+    // bias: sum over the tile of g[node][co]; 16 threads per channel
+    {
+        const int co = threadIdx.x & 15, q = threadIdx.x >> 4;
+        float s = 0.f;
+        for (int v = q; v < NG; v += NTHREADS / 16) s += bf2f(gs[co * NG + v]);
+        bsum[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x < 16) {
+            float t = 0.f;
+            for (int k = 0; k < NTHREADS / 16; ++k) t += bsum[k * 16 + threadIdx.x];
+            part[27 * 256 + threadIdx.x] = t;
+        }
+    }
+}
+
+// Sum of the per-workgroup partials into the flat gradient of one layer (FP32, the
+// parameter order W[co][ci][tap], b[co]).
+__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ partial, int nblocks, int cin,
+                                                     int cout, float* __restrict__ grad) {
+    const int nw = cout * cin * 27;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nw + cout) return;
+    int src;
+    if (p < nw) {
+        const int co = p / (cin * 27), ci = (p / 27) % cin, t = p % 27;
+        src = t * 256 + co * 16 + ci;
+    } else {
+        src = 27 * 256 + (p - nw);
+    }
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * CNN_PARTIAL_STRIDE + src];
+    grad[p] = s;
+}
+
+// Loss: r = y - log(gamma + 0.01) at nodes with gamma >= 0; output gradient
+// bf16(scale * r) into channel 0 of a 16-channel tensor (other channels 0), and one
+// partial sum of r^2 per workgroup.
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ gamma,
+                                              int64_t n, float scale, uint16_t* __restrict__ gout,
+                                              float* __restrict__ loss_part) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float gm = gamma[i];
+        float r = 0.f;
+        if (gm >= 0.f) r = y[i] - logf(gm + 0.01f);
+        s += r * r;
+        U4 q0 = {(uint32_t)f2bf(scale * r), 0u, 0u, 0u}, q1 = {0u, 0u, 0u, 0u};
+        *reinterpret_cast<U4*>(gout + i * 16) = q0;
+        *reinterpret_cast<U4*>(gout + i * 16 + 8) = q1;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// Adam with bias correction (c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t)).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, float* __restrict__ m,
+                                              float* __restrict__ v, const float* __restrict__ grad, int n, float lr,
+                                              float beta1, float beta2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = grad[i];
+    const float mi = beta1 * m[i] + (1.f - beta1) * gi;
+    const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] = theta[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// Fragments of one layer from the FP32 parameters.  Lane l of chunk c holds row l % 16
+// and k = 32 c + 8 (l / 16) + e, e = 0..7.
+//   forward : row = co; k = tap * cin + ci
+//   backward: row = ci; k = tap' * 16 + co, tap' = 26 - tap (flipped kernel, bwd-data)
+__global__ __launch_bounds__(64) void k_pack(const float* __restrict__ w, int cin, int cout, int bwd, int nch,
+                                             uint16_t* __restrict__ frag) {
+    const int c = blockIdx.x, lane = threadIdx.x;
+    if (c >= nch) return;
+    const int row = lane & 15, g = lane >> 4;
+    uint16_t h[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = 32 * c + 8 * g + e;
+        float val = 0.f;
+        if (!bwd) {
+            const int t = k / cin, ci = k % cin;
+            if (t < 27 && row < cout) val = w[(row * cin + ci) * 27 + t];
+        } else {
+            const int tp = k / 16, co = k % 16;
+            if (tp < 27 && co < cout && row < cin) val = w[(co * cin + row) * 27 + (26 - tp)];
+        }
+        h[e] = f2bf(val);
+    }
+    U4 q;
+    q.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+    q.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+    q.z = (uint32_t)h[4] | ((uint32_t)h[5] << 16);
+    q.w = (uint32_t)h[6] | ((uint32_t)h[7] << 16);
+    reinterpret_cast<U4*>(frag)[c * 64 + lane] = q;
+}
+
+// Features on the grid padded by 4: f0 = D_r * fl32(1/Dmax), f1 = (D_e - D_r) * inv_dd,
+// both bf16; 0 outside the grid.  Dmax and inv_dd come from the prep's scalars.
+__global__ __launch_bounds__(256) void k_features(const float* __restrict__ ref, const float* __restrict__ ev,
+                                                  int nz, int ny, int nx, const Scalars* __restrict__ sc,
+                                                  uint16_t* __restrict__ feat) {
+    const int pz = nz + 8, py = ny + 8, px = nx + 8;
+    const int64_t total = (int64_t)pz * py * px;
+    const float dmax = ord_to_float(sc->dmax_ord);
+    const float inv_max = 1.0f / dmax;
+    const float inv_dd = sc->inv_dd;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int x = (int)(i % px) - 4, y = (int)((i / px) % py) - 4, z = (int)(i / ((int64_t)px * py)) - 4;
+        uint32_t q = 0u;
+        if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) {
+            const int64_t n = ((int64_t)z * ny + y) * nx + x;
+            const float r = ref[n], e = ev[n];
+            q = (uint32_t)f2bf(r * inv_max) | ((uint32_t)f2bf((e - r) * inv_dd) << 16);
+        }
+        reinterpret_cast<uint32_t*>(feat)[i] = q;
+    }
+}
+
+int grid_for(int64_t n, int64_t cap) {
+    int64_t b = (n + 255) / 256;
+    if (b > cap) b = cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+int64_t conv_blocks(const int o[3], int nvol) {
+    return (int64_t)((o[2] + TX - 1) / TX) * ((o[1] + TY - 1) / TY) * ((o[0] + TZ - 1) / TZ) * nvol;
+}
+
+hipError_t launch_conv(int cin, int mode, const uint16_t* in, const int i[3], int64_t in_vstride,
+                       const uint16_t* wfrag, const float* bias, int cout, const uint16_t* mask, void* out,
+                       const int o[3], int64_t out_vstride, int off, int nvol, hipStream_t s) {
+    ConvArgs a{};
+    a.in = in;
+    a.iz = i[0];
+    a.iy = i[1];
+    a.ix = i[2];
+    a.in_vstride = in_vstride;
+    a.wfrag = wfrag;
+    a.bias = bias;
+    a.cout = cout;
+    a.mask = mask;
+    a.out = out;
+    a.oz = o[0];
+    a.oy = o[1];
+    a.ox = o[2];
+    a.out_vstride = out_vstride;
+    a.off = off;
+    a.tiles_x = (o[2] + TX - 1) / TX;
+    a.tiles_y = (o[1] + TY - 1) / TY;
+    a.tiles_z = (o[0] + TZ - 1) / TZ;
+    const int64_t nb = conv_blocks(o, nvol);
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb), block(NTHREADS);
+    if (cin == 2 && mode == 0) hipLaunchKernelGGL((k_conv<2, 0>), grid, block, 0, s, a);
+    else if (cin == 16 && mode == 0) hipLaunchKernelGGL((k_conv<16, 0>), grid, block, 0, s, a);
+    else if (cin == 16 && mode == 1) hipLaunchKernelGGL((k_conv<16, 1>), grid, block, 0, s, a);
+    else if (cin == 16 && mode == 2) hipLaunchKernelGGL((k_conv<16, 2>), grid, block, 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_bwdw(int cin, const uint16_t* x, const int i[3], int64_t x_vstride, const uint16_t* g,
+                            const int o[3], int64_t g_vstride, int nvol, float* partial, hipStream_t s) {
+    BwdWArgs a{};
+    a.x = x;
+    a.iz = i[0];
+    a.iy = i[1];
+    a.ix = i[2];
+    a.x_vstride = x_vstride;
+    a.g = g;
+    a.oz = o[0];
+    a.oy = o[1];
+    a.ox = o[2];
+    a.g_vstride = g_vstride;
+    a.partial = partial;
+    a.tiles_x = (o[2] + TX - 1) / TX;
+    a.tiles_y = (o[1] + TY - 1) / TY;
+    a.tiles_z = (o[0] + TZ - 1) / TZ;
+    const int64_t nb = conv_blocks(o, nvol);
+    if (nb <= 0) return hipSuccess;
+    if (cin == 2) hipLaunchKernelGGL((k_conv_bwdw<2>), dim3((unsigned)nb), dim3(NTHREADS), 0, s, a);
+    else if (cin == 16) hipLaunchKernelGGL((k_conv_bwdw<16>), dim3((unsigned)nb), dim3(NTHREADS), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const float* partial, int nblocks, int cin, int cout, float* grad, hipStream_t s) {
+    const int n = cout * cin * 27 + cout;
+    hipLaunchKernelGGL(k_grad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, partial, nblocks, cin, cout, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(const float* y, const float* gamma, int64_t n, float scale, uint16_t* gout, float* loss_part,
+                       int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_loss, dim3(nblocks), dim3(256), 0, s, y, gamma, n, scale, gout, loss_part);
+    return hipGetLastError();
+}
+
+int loss_blocks(int64_t n) { return grid_for(n, 1024); }
+
+hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int n, float lr, float beta1,
+                       float beta2, float eps, float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, theta, m, v, grad, n, lr, beta1, beta2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* w, int cin, int cout, int bwd, uint16_t* frag, hipStream_t s) {
+    const int nch = bwd ? 14 : (cin == 16 ? 14 : 2);
+    hipLaunchKernelGGL(k_pack, dim3(nch), dim3(64), 0, s, w, cin, cout, bwd, nch, frag);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(const float* ref, const float* ev, const int n[3], const Scalars* sc, uint16_t* feat,
+                           hipStream_t s) {
+    const int64_t total = (int64_t)(n[0] + 8) * (n[1] + 8) * (n[2] + 8);
+    hipLaunchKernelGGL(k_features, dim3(grid_for(total, 4096)), dim3(256), 0, s, ref, ev, n[0], n[1], n[2], sc, feat);
+    return hipGetLastError();
+}
+
+}  // namespace gammax

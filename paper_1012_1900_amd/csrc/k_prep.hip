@@ -64,6 +64,24 @@ __global__ __launch_bounds__(PREP_THREADS) void k_dose_max(PrepArgs a) {
     }
 }
 
+// 1b. dose maximum and the global 1/dD only (no mask, no compaction): one block reduces
+// the partials of k_dose_max.
+__global__ __launch_bounds__(PREP_THREADS) void k_dose_finish(PrepArgs a, int nb_red) {
+    uint32_t dm = 0u, bad = 0u;
+    for (int j = threadIdx.x; j < nb_red; j += PREP_THREADS) {
+        dm = max(dm, a.part[j]);
+        bad |= a.part[MAX_BLOCKS + j];
+    }
+    block_max_or(dm, bad);
+    if (threadIdx.x == 0) {
+        const float dmax = ord_to_float(dm);
+        a.sc->dmax_ord = dm;
+        a.sc->flags = bad ? FLAG_NONFINITE : 0u;
+        a.sc->thr_val = a.thr * dmax;
+        a.sc->inv_dd = 1.0f / (a.dd * dmax);
+    }
+}
+
 __device__ __forceinline__ bool node_masked(float dr, float thr_val, int local) {
     return dr >= thr_val && (!local || dr > 0.0f);
 }
@@ -238,6 +256,13 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_prep_count, dim3((unsigned)nb), dim3(PREP_THREADS), 0, s, a, nbr);
     hipLaunchKernelGGL(k_prep_scan, dim3(1), dim3(PREP_THREADS), 0, s, a, (int)nb);
     hipLaunchKernelGGL(k_prep_emit, dim3((unsigned)nb), dim3(PREP_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dose_scalars(const PrepArgs& a, hipStream_t s) {
+    const int nbr = reduce_blocks(a.n);
+    hipLaunchKernelGGL(k_dose_max, dim3(nbr), dim3(PREP_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_dose_finish, dim3(1), dim3(PREP_THREADS), 0, s, a, nbr);
     return hipGetLastError();
 }
 

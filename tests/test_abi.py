@@ -32,7 +32,10 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ["gamma_map", "gammax_map", "gammax_ctx_create", "gammax_ctx_destroy",
                  "gammax_sort_pairs", "gammax_build_table", "gammax_pass_count",
-                 "gammax_status_string", "gammax_last_error", "gammax_options_default"]:
+                 "gammax_status_string", "gammax_last_error", "gammax_options_default",
+                 "gammax_model_create", "gammax_model_destroy", "gammax_model_get_params",
+                 "gammax_model_features", "gammax_model_predict", "gammax_model_forward",
+                 "gammax_model_train_step", "gammax_model_last_error"]:
         assert must in names
 
 
@@ -95,3 +98,18 @@ def test_null_context(abi):
     assert lib.gammax_sort_pairs(None, None, None, 0, None) == abi.E_NULL
     assert lib.gammax_pass_count(None, None, 0, None, None) == abi.E_NULL
     assert lib.gammax_ctx_destroy(None) == abi.OK
+
+
+def test_null_model(abi):
+    lib = abi.raw_library()
+    h = C.c_void_p()
+    crop = (C.c_int64 * 3)(8, 8, 8)
+    hp = abi.Adam(1e-3, 0.9, 0.999, 1e-8)
+    assert lib.gammax_model_create(0, None, C.byref(h)) == abi.E_NULL
+    assert lib.gammax_model_destroy(None) == abi.OK
+    assert lib.gammax_model_get_params(None, None, None) == abi.E_NULL
+    assert lib.gammax_model_forward(None, 1, crop, None, None, None) == abi.E_NULL
+    assert lib.gammax_model_train_step(None, 1, crop, None, None, C.byref(hp), None, None) == abi.E_NULL
+    assert lib.gammax_model_predict(None, None, None, None, None, None, None) == abi.E_NULL
+    assert lib.gammax_model_features(None, None, None, None, None, None) == abi.E_NULL
+    assert lib.gammax_model_last_error(None) == b""
