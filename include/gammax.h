@@ -58,8 +58,21 @@ typedef enum { GAMMAX_GLOBAL = 0, GAMMAX_LOCAL = 1 } gammax_norm_t;
 typedef enum {
     GAMMAX_SORT_NONE = 0,     /* as they were queued (default) */
     GAMMAX_SORT_DD = 1,       /* ascending |DD| / dD ("DD sorting", Algorithm A2 step 3) */
-    GAMMAX_SORT_BOUND = 2     /* ascending gamma bound after the key-0 cells */
+    GAMMAX_SORT_BOUND = 2,    /* ascending gamma bound after the key-0 cells */
+    GAMMAX_SORT_PREDICTED = 3 /* ascending predicted gamma (needs a model; 3D) */
 } gammax_sort_t;
+
+/* Search radius of the walk past the key-0 cells. */
+typedef enum {
+    GAMMAX_RADIUS_PLAIN = 0,  /* walk until the next key reaches the current gamma (default) */
+    GAMMAX_RADIUS_LEARNED = 1 /* first walk only while the key is below radius_factor * gamma_hat
+                                 (gamma_hat from the model); a node whose gamma is not certified
+                                 inside that radius then finishes with the plain walk from where
+                                 the first one stopped.  Results equal the plain search.  3D only;
+                                 2D problems use the plain radius. */
+} gammax_radius_t;
+
+typedef struct gammax_model gammax_model_t;
 
 /* Arithmetic of the per-simplex projections. */
 typedef enum {
@@ -93,7 +106,10 @@ typedef struct {
     int32_t cell_lanes;       /* layout of the pass over the key-0 cells: 0 = automatic
                                  (one lane per node), 1 = one lane per node, 4 (2D) or
                                  8 (3D) = one lane per cell */
-    int32_t reserved[5];      /* must be 0 */
+    int32_t radius_mode;      /* gammax_radius_t */
+    const gammax_model_t *model;  /* the model for GAMMAX_RADIUS_LEARNED / GAMMAX_SORT_PREDICTED */
+    double radius_factor;     /* f of the learned radius f * gamma_hat, >= 1 (default 1.1) */
+    int32_t reserved[4];      /* must be 0 */
 } gammax_options_t;
 
 typedef struct {
@@ -116,12 +132,15 @@ typedef struct {
     float ms_tail;            /*   their table walk (step 6) */
     float ms_guard;           /*   FP64-guarded redo of nodes that met an ill-conditioned
                                    tetrahedron (guarded precision, 3D), and the count reduction */
+    uint64_t n_fallback;      /* learned radius: tail nodes not certified inside f * gamma_hat */
+    float ms_cnn;             /* timing = 1 only: features and CNN inference (learned radius) */
+    int32_t pad_;
 } gammax_result_t;
 
 typedef struct gammax_ctx gammax_ctx_t;
 
 /* Fill `opt` with the defaults: no sort, guarded FP32, cond_threshold 1e6, no timing,
- * automatic tail lanes. */
+ * automatic tail lanes, plain radius, radius_factor 1.1. */
 void gammax_options_default(gammax_options_t *opt);
 
 /* Create a context bound to HIP device `device`.  *ctx receives the handle. */
@@ -200,8 +219,6 @@ gammax_status_t gammax_pass_count(gammax_ctx_t *ctx, const float *gamma_dev, int
  * Parameters: GAMMAX_MODEL_NPARAM floats, per layer W[co][ci][dz][dy][dx] then b[co].
  */
 #define GAMMAX_MODEL_NPARAM 15169
-
-typedef struct gammax_model gammax_model_t;
 
 typedef struct {
     float lr;       /* Adam step size */

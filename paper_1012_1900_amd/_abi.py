@@ -40,10 +40,12 @@ E_RADIUS = -7
 E_DOSE = -8
 
 GLOBAL, LOCAL = 0, 1
-SORT_NONE, SORT_DD, SORT_BOUND = 0, 1, 2
+SORT_NONE, SORT_DD, SORT_BOUND, SORT_PREDICTED = 0, 1, 2, 3
 PREC_FP32, PREC_GUARDED, PREC_FP64 = 0, 1, 2
+RADIUS_PLAIN, RADIUS_LEARNED = 0, 1
 
-_SORT = {"none": SORT_NONE, "dd": SORT_DD, "bound": SORT_BOUND}
+_SORT = {"none": SORT_NONE, "dd": SORT_DD, "bound": SORT_BOUND, "predicted": SORT_PREDICTED}
+_RADIUS = {"plain": RADIUS_PLAIN, "learned": RADIUS_LEARNED}
 _PREC = {"fp32": PREC_FP32, "guarded": PREC_GUARDED, "fp64": PREC_FP64}
 
 
@@ -74,7 +76,10 @@ class Options(C.Structure):
         ("timing", C.c_int32),
         ("tail_lanes", C.c_int32),
         ("cell_lanes", C.c_int32),
-        ("reserved", C.c_int32 * 5),
+        ("radius_mode", C.c_int32),
+        ("model", C.c_void_p),
+        ("radius_factor", C.c_double),
+        ("reserved", C.c_int32 * 4),
     ]
 
 
@@ -98,6 +103,9 @@ class Result(C.Structure):
         ("ms_sort", C.c_float),
         ("ms_tail", C.c_float),
         ("ms_guard", C.c_float),
+        ("n_fallback", C.c_uint64),
+        ("ms_cnn", C.c_float),
+        ("pad_", C.c_int32),
     ]
 
 
@@ -197,6 +205,9 @@ class GammaResult:
     ms_sort: float
     ms_tail: float
     ms_guard: float
+    n_fallback: int
+    ms_cnn: float
+    pad_: int = 0
 
 
 def _torch():
@@ -229,8 +240,12 @@ def make_problem(shape: Sequence[int], spacing: Sequence[float], dd: float, dta:
 
 
 def make_options(sort: str = "none", precision: str = "guarded", cond_threshold: float = 1e6,
-                 timing: bool = False, tail_lanes: int = 0, cell_lanes: int = 0) -> Options:
+                 timing: bool = False, tail_lanes: int = 0, cell_lanes: int = 0, radius: str = "plain",
+                 model=None, radius_factor: float = 1.1) -> Options:
     o = default_options()
+    o.radius_mode = _RADIUS[radius]
+    o.model = model.handle if model is not None else None
+    o.radius_factor = float(radius_factor)
     o.sort_mode = _SORT[sort]
     o.precision = _PREC[precision]
     o.cond_threshold = float(cond_threshold)
@@ -243,8 +258,8 @@ def make_options(sort: str = "none", precision: str = "guarded", cond_threshold:
 def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
                dose_threshold: float = 0.1, local: bool = False, *, sort: str = "none",
                precision: str = "guarded", cond_threshold: float = 1e6, timing: bool = False,
-               tail_lanes: int = 0, cell_lanes: int = 0, out=None, ctx: Optional[Context] = None,
-               stream=None):
+               tail_lanes: int = 0, cell_lanes: int = 0, radius: str = "plain", model=None,
+               radius_factor: float = 1.1, out=None, ctx: Optional[Context] = None, stream=None):
     """Gamma map of a dose pair on the GPU.  Returns (gamma tensor, GammaResult).
 
     ``ref``/``ev``: float32 device tensors of shape (ny, nx) or (nz, ny, nx); ``spacing``
@@ -266,7 +281,8 @@ def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
     dev = ref.device.index if ref.device.index is not None else torch.cuda.current_device()
     ctx = ctx or context(dev)
     p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
-    o = make_options(sort, precision, cond_threshold, timing, tail_lanes, cell_lanes)
+    o = make_options(sort, precision, cond_threshold, timing, tail_lanes, cell_lanes, radius, model,
+                     radius_factor)
     r = Result()
     s = stream if stream is not None else torch.cuda.current_stream(ref.device)
     with torch.cuda.device(ref.device):

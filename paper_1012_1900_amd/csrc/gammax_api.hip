@@ -31,8 +31,9 @@ struct GraphKey {
     int32_t ndim, norm;
     int64_t shape[3];
     double spacing[3], dd, dta, thr;
-    int32_t sort_mode, precision, tail_lanes, timing;
-    double cond_threshold;
+    int32_t sort_mode, precision, tail_lanes, cell_lanes, timing, radius_mode;
+    double cond_threshold, radius_factor;
+    const void* model;
     uint64_t generation;   // bumped on every (re)allocation and table build
 };
 
@@ -76,11 +77,13 @@ struct gammax_ctx {
     hipGraphExec_t graph = nullptr;
     GraphKey graph_key{};
     bool graph_broken = false;      // capture failed once: launch directly from then on
-    hipEvent_t ev[10] = {};
+    hipEvent_t ev[12] = {};
     bool events = false;
     // learned radius: features and hidden activations of one grid
     unsigned char* cnn_ws = nullptr;
     int64_t cnn_ws_cap = 0;
+    float* yhat = nullptr;          // log(gamma_hat + 0.01) per grid node
+    int64_t yhat_cap = 0;
 };
 
 namespace {
@@ -134,16 +137,16 @@ gammax_status_t grow(gammax_ctx* c, P** p, int64_t* cap, int64_t need) {
     return GAMMAX_OK;
 }
 
-// The 8 node work arrays share one allocation of 8 * cap words.
+// The node work arrays share one allocation of kWorkArrays * cap words.
+enum { W_NODES, W_TAIL_NODE, W_TAIL_F, W_TAIL_KEY, W_TAIL_POS, W_TMP_K, W_TMP_V, W_GUARD, W_FALLBACK, kWorkArrays };
 gammax_status_t grow_work(gammax_ctx* c, int64_t n) {
     if (n <= c->work_cap && c->work) return GAMMAX_OK;
-    int64_t words = c->work ? 8 * c->work_cap : 0;
-    gammax_status_t st = grow(c, &c->work, &words, 8 * (n > 0 ? n : 1));
-    c->work_cap = st == GAMMAX_OK ? words / 8 : 0;
+    int64_t words = c->work ? kWorkArrays * c->work_cap : 0;
+    gammax_status_t st = grow(c, &c->work, &words, kWorkArrays * (n > 0 ? n : 1));
+    c->work_cap = st == GAMMAX_OK ? words / kWorkArrays : 0;
     return st;
 }
 uint32_t* work_array(gammax_ctx* c, int k) { return c->work + (int64_t)k * c->work_cap; }
-enum { W_NODES, W_TAIL_NODE, W_TAIL_F, W_TAIL_KEY, W_TAIL_POS, W_TMP_K, W_TMP_V, W_GUARD };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -168,8 +171,14 @@ gammax_status_t check_problem(gammax_ctx* c, const gammax_problem_t* p, int64_t*
 }
 
 gammax_status_t check_options(gammax_ctx* c, const gammax_options_t* o) {
-    if (o->sort_mode < GAMMAX_SORT_NONE || o->sort_mode > GAMMAX_SORT_BOUND)
+    if (o->sort_mode < GAMMAX_SORT_NONE || o->sort_mode > GAMMAX_SORT_PREDICTED)
         return fail(c, GAMMAX_E_PARAM, "unknown sort_mode");
+    if (o->radius_mode != GAMMAX_RADIUS_PLAIN && o->radius_mode != GAMMAX_RADIUS_LEARNED)
+        return fail(c, GAMMAX_E_PARAM, "unknown radius_mode");
+    if (!(o->radius_factor >= 1.0) || !std::isfinite(o->radius_factor))
+        return fail(c, GAMMAX_E_PARAM, "radius_factor must be finite and >= 1");
+    if ((o->radius_mode == GAMMAX_RADIUS_LEARNED || o->sort_mode == GAMMAX_SORT_PREDICTED) && !o->model)
+        return fail(c, GAMMAX_E_NULL, "the learned radius and the predicted order need a model");
     if (o->precision < GAMMAX_PREC_FP32 || o->precision > GAMMAX_PREC_FP64)
         return fail(c, GAMMAX_E_PARAM, "unknown precision");
     if (!(o->cond_threshold >= 1.0)) return fail(c, GAMMAX_E_PARAM, "cond_threshold must be >= 1");
@@ -179,8 +188,10 @@ gammax_status_t check_options(gammax_ctx* c, const gammax_options_t* o) {
         return fail(c, GAMMAX_E_PARAM, "tail_lanes must be 0, 1, 8, 16, 32 or 64");
     if (!(o->cell_lanes == 0 || o->cell_lanes == 1 || o->cell_lanes == 4 || o->cell_lanes == 8))
         return fail(c, GAMMAX_E_PARAM, "cell_lanes must be 0, 1, 4 or 8");
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
         if (o->reserved[i] != 0) return fail(c, GAMMAX_E_PARAM, "reserved option fields must be 0");
+    if (o->model && c && o->model->device != c->device)
+        return fail(c, GAMMAX_E_PARAM, "model and context live on different devices");
     return GAMMAX_OK;
 }
 
@@ -276,6 +287,53 @@ struct CallSetup {
     int64_t n;
 };
 
+// Workspace of the CNN over one grid: features (o+8, 2 channels), then the three hidden
+// activations (o+6, o+4, o+2; 16 channels), each 256-byte aligned.
+struct CnnWs {
+    uint16_t *feat, *a1, *a2, *a3;
+    int64_t bytes;
+};
+CnnWs cnn_layout(unsigned char* base, const int o[3]) {
+    CnnWs w{};
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        uint16_t* p = base ? (uint16_t*)(base + off) : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    int sh[3];
+    act_shape(o, 8, sh);
+    w.feat = take(vol_of(sh) * 4);
+    act_shape(o, 6, sh);
+    w.a1 = take(vol_of(sh) * 32);
+    act_shape(o, 4, sh);
+    w.a2 = take(vol_of(sh) * 32);
+    act_shape(o, 2, sh);
+    w.a3 = take(vol_of(sh) * 32);
+    w.bytes = off;
+    return w;
+}
+
+gammax_status_t grow_cnn(gammax_ctx* c, const int o[3], CnnWs* w) {
+    const int64_t need = cnn_layout(nullptr, o).bytes;
+    if (need > c->cnn_ws_cap || !c->cnn_ws) {
+        gammax_status_t st = grow(c, &c->cnn_ws, &c->cnn_ws_cap, need);
+        if (st != GAMMAX_OK) return st;
+    }
+    *w = cnn_layout(c->cnn_ws, o);
+    return GAMMAX_OK;
+}
+
+// The model is used on 3D problems when the learned radius or the predicted order is asked
+// for (2D problems keep the plain radius and order by |DD|).
+bool uses_model(const gammax_problem_t* p, const gammax_options_t* o) {
+    return p->ndim == 3 && o->model &&
+           (o->radius_mode == GAMMAX_RADIUS_LEARNED || o->sort_mode == GAMMAX_SORT_PREDICTED);
+}
+
+// Queue the features and the CNN (after the prep, which provides the dose maximum and dD).
+gammax_status_t enqueue_cnn(gammax_ctx* c, const CallSetup& cs, hipStream_t s, bool timing);
+
 // Queue the compaction (Kernel 1).  ev0/ev1 (optional) bracket it.
 gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int64_t ntiles = prep_tiles(cs.n);
@@ -296,6 +354,18 @@ gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, 
     pa.sums = c->sums;
     HIPCHK(c, launch_prep(pa, s));
     if (ev1) HIPCHK(c, hipEventRecord(ev1, s));
+    return GAMMAX_OK;
+}
+
+gammax_status_t enqueue_cnn(gammax_ctx* c, const CallSetup& cs, hipStream_t s, bool timing) {
+    if (!uses_model(cs.p, cs.opt)) return GAMMAX_OK;
+    if (timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
+    const int o[3] = {(int)cs.p->shape[0], (int)cs.p->shape[1], (int)cs.p->shape[2]};
+    CnnWs w = cnn_layout(c->cnn_ws, o);
+    gammax_model* m = const_cast<gammax_model*>(cs.opt->model);
+    HIPCHK(c, launch_features(cs.ref, cs.ev, o, c->d_sc, w.feat, s));
+    HIPCHK(c, model_forward(m, w.feat, 1, o, w.a1, w.a2, w.a3, c->yhat, s));
+    if (timing) HIPCHK(c, hipEventRecord(c->ev[10], s));
     return GAMMAX_OK;
 }
 
@@ -343,7 +413,11 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
     sa.den_guard = (float)guard;
     sa.k1 = c->tab_valid ? c->tab_k1 : INFINITY;
     sa.r2_cap = r2_cap;
-    sa.tail_key = opt.sort_mode == GAMMAX_SORT_BOUND ? 1 : 0;
+    const bool learned = uses_model(p, &opt);
+    sa.tail_key = opt.sort_mode == GAMMAX_SORT_BOUND ? 1 : ((opt.sort_mode == GAMMAX_SORT_PREDICTED && learned) ? 2 : 0);
+    sa.yhat = learned ? c->yhat : nullptr;
+    sa.spec_factor = (float)opt.radius_factor;
+    sa.fb_list = work_array(c, W_FALLBACK);
     sa.nodes = work_array(c, W_NODES);
     sa.tail_node = work_array(c, W_TAIL_NODE);
     sa.tail_f = work_array(c, W_TAIL_F);
@@ -358,6 +432,7 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
     plan.tail_lanes = opt.tail_lanes;
     // one lane per node (shared neighbourhood loads) unless one lane per cell is asked for
     plan.zero_lanes = (opt.cell_lanes == 4 || opt.cell_lanes == 8) ? 1 : 0;
+    plan.spec = (learned && opt.radius_mode == GAMMAX_RADIUS_LEARNED) ? 1 : 0;
     plan.M = m_bound;
     const double s3[3] = {p->spacing_mm[0] / p->dta_mm, p->spacing_mm[1] / p->dta_mm,
                           nd == 3 ? p->spacing_mm[2] / p->dta_mm : 1.0};
@@ -398,8 +473,12 @@ GraphKey key_of(gammax_ctx* c, const CallSetup& cs) {
     k.sort_mode = cs.opt->sort_mode;
     k.precision = cs.opt->precision;
     k.tail_lanes = cs.opt->tail_lanes;
+    k.cell_lanes = cs.opt->cell_lanes;
     k.timing = cs.opt->timing;
+    k.radius_mode = cs.opt->radius_mode;
     k.cond_threshold = cs.opt->cond_threshold;
+    k.radius_factor = cs.opt->radius_factor;
+    k.model = cs.opt->model;
     k.generation = c->generation;
     return k;
 }
@@ -419,6 +498,7 @@ gammax_status_t launch_graph(gammax_ctx* c, const CallSetup& cs, uint32_t m_boun
         HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         gammax_status_t st = enqueue_prep(c, cs, c->cap_stream, timing ? c->ev[0] : nullptr,
                                           timing ? c->ev[1] : nullptr);
+        if (st == GAMMAX_OK) st = enqueue_cnn(c, cs, c->cap_stream, timing);
         if (st == GAMMAX_OK) st = enqueue_search(c, cs, m_bound, r2_cap, c->cap_stream, timing);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -439,7 +519,7 @@ gammax_status_t launch_graph(gammax_ctx* c, const CallSetup& cs, uint32_t m_boun
     return GAMMAX_OK;
 }
 
-void fill_result(gammax_ctx* c, gammax_result_t* res, bool timing, float ms_table) {
+void fill_result(gammax_ctx* c, gammax_result_t* res, bool timing, float ms_table, bool cnn) {
     const Scalars& h = *c->h_sc;
     const float r2 = u2f(h.r2_bits);
     res->n_evaluated = h.n_masked;
@@ -461,50 +541,15 @@ void fill_result(gammax_ctx* c, gammax_result_t* res, bool timing, float ms_tabl
         res->ms_sort = elapsed(c->ev[5], c->ev[6]);
         res->ms_tail = elapsed(c->ev[6], c->ev[7]);
         res->ms_guard = elapsed(c->ev[7], c->ev[8]);
+        res->ms_cnn = cnn ? elapsed(c->ev[9], c->ev[10]) : 0.0f;
     }
+    res->n_fallback = h.n_fallback;
 }
 
 gammax_status_t device_errors(gammax_ctx* c, bool local) {
     if (c->h_sc->flags & FLAG_NONFINITE) return fail(c, GAMMAX_E_NONFINITE, "a dose value is NaN or infinite");
     if (!local && !(ord_to_float(c->h_sc->dmax_ord) > 0.0f))
         return fail(c, GAMMAX_E_DOSE, "max reference dose is not positive");
-    return GAMMAX_OK;
-}
-
-// Workspace of the CNN over one grid: features (o+8, 2 channels), then the three hidden
-// activations (o+6, o+4, o+2; 16 channels), each 256-byte aligned.
-struct CnnWs {
-    uint16_t *feat, *a1, *a2, *a3;
-    int64_t bytes;
-};
-CnnWs cnn_layout(unsigned char* base, const int o[3]) {
-    CnnWs w{};
-    int64_t off = 0;
-    auto take = [&](int64_t bytes) {
-        uint16_t* p = base ? (uint16_t*)(base + off) : nullptr;
-        off += (bytes + 255) / 256 * 256;
-        return p;
-    };
-    int sh[3];
-    act_shape(o, 8, sh);
-    w.feat = take(vol_of(sh) * 4);
-    act_shape(o, 6, sh);
-    w.a1 = take(vol_of(sh) * 32);
-    act_shape(o, 4, sh);
-    w.a2 = take(vol_of(sh) * 32);
-    act_shape(o, 2, sh);
-    w.a3 = take(vol_of(sh) * 32);
-    w.bytes = off;
-    return w;
-}
-
-gammax_status_t grow_cnn(gammax_ctx* c, const int o[3], CnnWs* w) {
-    const int64_t need = cnn_layout(nullptr, o).bytes;
-    if (need > c->cnn_ws_cap || !c->cnn_ws) {
-        gammax_status_t st = grow(c, &c->cnn_ws, &c->cnn_ws_cap, need);
-        if (st != GAMMAX_OK) return st;
-    }
-    *w = cnn_layout(c->cnn_ws, o);
     return GAMMAX_OK;
 }
 
@@ -548,6 +593,9 @@ void gammax_options_default(gammax_options_t* opt) {
     opt->cond_threshold = 1e6;
     opt->timing = 0;
     opt->tail_lanes = 0;
+    opt->radius_mode = GAMMAX_RADIUS_PLAIN;
+    opt->model = nullptr;
+    opt->radius_factor = 1.1;
 }
 
 const char* gammax_status_string(gammax_status_t st) {
@@ -587,7 +635,7 @@ gammax_status_t gammax_ctx_destroy(gammax_ctx_t* c) {
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void* dev[] = {c->d_sc, c->d_cnt, c->d_count, c->work, c->blockcnt, c->part, c->hist,
-                   c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws};
+                   c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws, c->yhat};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* host[] = {c->h_sc, c->h_cnt, c->h_count};
@@ -627,6 +675,13 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
     if ((st = grow(c, &c->hist, &c->hist_cap, sort_hist_words(n))) != GAMMAX_OK) return st;
     if ((st = grow(c, &c->sums, &c->sums_cap, search_sums_needed((uint32_t)n))) != GAMMAX_OK) return st;
     if (timing && (st = ensure_events(c)) != GAMMAX_OK) return st;
+    const bool learned = uses_model(p, &opt);
+    if (learned) {
+        const int o[3] = {(int)p->shape[0], (int)p->shape[1], (int)p->shape[2]};
+        CnnWs w;
+        if ((st = grow_cnn(c, o, &w)) != GAMMAX_OK) return st;
+        if ((st = grow(c, &c->yhat, &c->yhat_cap, n)) != GAMMAX_OK) return st;
+    }
 
     CallSetup cs{p, &opt, ref, ev, gamma, n};
     const TableGeom g = geom_of(p);
@@ -638,6 +693,7 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
         if (timing || c->graph_broken) {
             if ((st = enqueue_prep(c, cs, s, timing ? c->ev[0] : nullptr, timing ? c->ev[1] : nullptr)) != GAMMAX_OK)
                 return st;
+            if ((st = enqueue_cnn(c, cs, s, timing)) != GAMMAX_OK) return st;
             if ((st = enqueue_search(c, cs, (uint32_t)n, r2_cap, s, timing)) != GAMMAX_OK) return st;
         } else {
             st = launch_graph(c, cs, (uint32_t)n, r2_cap, s);
@@ -650,6 +706,7 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
                 if ((st = enqueue_prep(c, cs, s, timing ? c->ev[0] : nullptr, timing ? c->ev[1] : nullptr)) !=
                     GAMMAX_OK)
                     return st;
+                if ((st = enqueue_cnn(c, cs, s, timing)) != GAMMAX_OK) return st;
                 if ((st = enqueue_search(c, cs, (uint32_t)n, r2_cap, s, timing)) != GAMMAX_OK) return st;
             }
         }
@@ -657,7 +714,7 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
         HIPCHK(c, hipStreamSynchronize(s));
         if ((st = device_errors(c, local)) != GAMMAX_OK) return st;
         if (!(c->h_sc->flags & FLAG_TABLE_SHORT)) {
-            fill_result(c, res, timing, 0.0f);
+            fill_result(c, res, timing, 0.0f, learned);
             return GAMMAX_OK;
         }
         // the radius outgrew the cached table: build a larger one below and run again
@@ -683,6 +740,7 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
             ms_table = elapsed(c->ev[2], c->ev[3]);
         }
     }
+    if (M > 0 && (st = enqueue_cnn(c, cs, s, timing)) != GAMMAX_OK) return st;
     if (M > 0) {
         const bool walk = r2 > 0.0f && c->tab_valid;
         const bool keep = c->tab_valid;
@@ -691,11 +749,11 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
         c->tab_valid = keep;
         if (st != GAMMAX_OK) return st;
     } else if (timing) {
-        for (int k = 4; k <= 8; ++k) HIPCHK(c, hipEventRecord(c->ev[k], s));
+        for (int k = 4; k <= 10; ++k) HIPCHK(c, hipEventRecord(c->ev[k], s));
     }
     HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    fill_result(c, res, timing, ms_table);
+    fill_result(c, res, timing, ms_table, learned);
     return GAMMAX_OK;
 }
 

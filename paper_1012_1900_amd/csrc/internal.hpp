@@ -18,7 +18,8 @@ struct Scalars {
     uint32_t n_tail;        // nodes whose walk continues past the zero-key cells
     uint32_t n_guard;       // nodes queued for the FP64-guarded pass
     uint32_t maxg2_bits;    // max gamma^2 found (non-negative float bits)
-    uint32_t pad[3];
+    uint32_t n_fallback;    // learned radius: tail nodes not certified inside 1.1 * gamma_hat
+    uint32_t pad[2];
     unsigned long long n_pass;
     unsigned long long n_border;
     unsigned long long n_fp64;
@@ -155,7 +156,10 @@ struct SearchArgs {
     double sx, sy, sz;       // s_i in double for the FP64 paths
     float k1;                // key^2 of the first table row after the zero-key cells (+inf: none)
     float r2_cap;            // the table holds every cell with key^2 < r2_cap
-    int tail_key;            // key of the tail sort: 0 = gamma0^2 (DD sort), 1 = bound after shell 0
+    int tail_key;            // key of the tail sort: 0 = gamma0^2 (DD sort), 1 = bound after the
+                             // key-0 cells, 2 = predicted gamma (learned ordering)
+    const float* yhat;       // learned radius: log(gamma_hat + 0.01) per grid node, or null
+    float spec_factor;       // the speculative walk stops at key >= spec_factor * gamma_hat
     // work lists
     const uint32_t* nodes;   // masked nodes in grid order (M)
     uint32_t* tail_node;     // tail: node index
@@ -163,6 +167,7 @@ struct SearchArgs {
     uint32_t* tail_key_arr;  // tail: sort key
     uint32_t* tail_pos;      // tail: position (sort payload)
     uint32_t* guard_list;    // nodes that met an ill-conditioned tetrahedron
+    uint32_t* fb_list;       // learned radius: tail items to finish with the plain walk
     BlockSums* sums;         // per-block partial counts
 };
 
@@ -177,6 +182,8 @@ struct SearchPlan {
     int ndim, precision;
     int tail_lanes;          // lanes per node in the tail walk: 1 (one lane per node) or 8..64
     int zero_lanes;          // pass A: 1 = one lane per cell, 0 = one lane per node
+    int spec;                // 1: speculative tail walk inside spec_factor * gamma_hat, then the
+                             //    plain walk for the nodes it could not certify
     uint32_t M;
     ZeroGeo zero;
     uint32_t* tmp_keys;      // sort scratch, M entries each

@@ -111,6 +111,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a, int nb_
             sc->n_tail = 0u;
             sc->n_guard = 0u;
             sc->maxg2_bits = 0u;
+            sc->n_fallback = 0u;
             sc->n_pass = 0ull;
             sc->n_border = 0ull;
             sc->n_fp64 = 0ull;

@@ -415,6 +415,34 @@ __device__ __forceinline__ void finish_node(const SearchArgs& a, int node, float
     gm = max(gm, f2u(gam * gam));
 }
 
+// Learned radius.  gamma_hat = max(exp(y) - 0.01, 0) from the CNN output y at the node;
+// the speculative walk takes the bound min(gamma^2, (f * gamma_hat)^2).  The same float
+// expression serves the speculative walk and the fallback, so both see the same bound.
+__device__ __forceinline__ float pred_gamma(const SearchArgs& a, int node) {
+    return fmaxf(expf(a.yhat[node]) - 0.01f, 0.0f);
+}
+__device__ __forceinline__ float spec_bound2(const SearchArgs& a, int node) {
+    const float r = a.spec_factor * pred_gamma(a, node);
+    return r * r;
+}
+// Sort key of a queued tail node: gamma0^2 (DD sort), the bound after the key-0 cells,
+// or the predicted gamma (all non-negative floats: bit order = numeric order).
+__device__ __forceinline__ uint32_t tail_sort_key(const SearchArgs& a, int node, float F0, float F) {
+    if (a.tail_key == 2) return f2u(pred_gamma(a, node));
+    return a.tail_key ? f2u(F) : f2u(F0);
+}
+// First table row with key^2 >= r2 (rows are in ascending key order), at least `first`.
+// Rows before it either were evaluated by the speculative walk or could not improve it.
+__device__ __forceinline__ int resume_row(const TabEntry* tab, int n, int first, float r2) {
+    int lo = first, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (tab[mid].key2 < r2) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Pass A in 3D.  MODE 0: FP32; MODE 1: FP32 and flag ill-conditioned tetrahedra.
 template <int MODE>
 __global__ __launch_bounds__(SEARCH_THREADS) void k_zero3(SearchArgs a, ZeroGeo zg, BlockSums* sums) {
@@ -485,7 +513,7 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_zero3(SearchArgs a, ZeroGeo 
     if (to_tail) {
         a.tail_node[pos] = (uint32_t)node;
         a.tail_f[pos] = f2u(F);
-        a.tail_key_arr[pos] = a.tail_key ? f2u(F) : f2u(F0);
+        a.tail_key_arr[pos] = tail_sort_key(a, node, F0, F);
         a.tail_pos[pos] = pos;
     }
     if (MODE == 1) {
@@ -552,7 +580,7 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_zero2(SearchArgs a, ZeroGeo 
     if (to_tail) {
         a.tail_node[pos] = (uint32_t)node;
         a.tail_f[pos] = f2u(F);
-        a.tail_key_arr[pos] = a.tail_key ? f2u(F) : f2u(F0);
+        a.tail_key_arr[pos] = tail_sort_key(a, node, F0, F);
         a.tail_pos[pos] = pos;
     }
     block_sums(sums, npass, nborder, 0u, ncells, gm);
@@ -654,7 +682,7 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_zero_group(SearchArgs a, Zer
         if (to_tail) {
             a.tail_node[pos] = (uint32_t)node;
             a.tail_f[pos] = f2u(F);
-            a.tail_key_arr[pos] = a.tail_key ? f2u(F) : f2u(F0);
+            a.tail_key_arr[pos] = tail_sort_key(a, node, F0, F);
             a.tail_pos[pos] = pos;
         }
         if (MODE == 1) {
@@ -668,11 +696,14 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_zero_group(SearchArgs a, Zer
 // The walk.  TAIL: items are tail positions, the walk starts at row `first` with the bound
 // left by pass A; otherwise items are node indices and the walk starts at row 0 with
 // gamma0.  MODE 0: FP32; 1: FP32 + flag; 2: FP32 with FP64 re-projection; 3: FP64.
+// spec (TAIL only): 0 plain; 1 speculative (bound min(gamma^2, (f gamma_hat)^2); a node
+// whose gamma^2 stays above (f gamma_hat)^2 is queued on the fallback list instead of
+// finished); 2 fallback (the plain walk from the first row at or beyond f gamma_hat).
 template <int DIM, int MODE, bool TAIL>
 __global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const TabEntry* __restrict__ tab,
                                                          const uint32_t* __restrict__ order,
                                                          const uint32_t* __restrict__ count, int first,
-                                                         BlockSums* sums) {
+                                                         int spec, BlockSums* sums) {
     using T = typename std::conditional<MODE == 3, double, float>::type;
     constexpr int GMODE = DIM == 3 ? (MODE == 1 ? 1 : (MODE == 2 ? 2 : 0)) : 0;
     const uint32_t M = *count;
@@ -722,13 +753,24 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const Tab
         if (!live) F = T(0);
         const T invdd = MODE == 3 ? (T)inv_dd64 : (T)inv_dd;
         const T drT = (T)dr;
-        uint32_t lane_cells = TAIL ? zero_cells(DIM, x, y, z, nx, ny, nz) : 0u, lane_fp64 = 0;
+        uint32_t lane_cells = 0, lane_fp64 = 0;
         bool ill = false;
+        // learned radius: the speculative bound, and the fallback's first row
+        const float r2s = (TAIL && spec && live) ? spec_bound2(a, node) : Num<float>::inf();
+        int lstart = first;
+        if (TAIL && spec == 2 && live) lstart = resume_row(tab, a.tab_len, first, r2s);
+        int wstart = lstart;
+        if (TAIL && spec == 2) {
+            // the wave starts at its smallest row (the rows are wave-uniform loads)
+#pragma unroll
+            for (int o = WAVE / 2; o > 0; o >>= 1) wstart = min(wstart, __shfl_xor(wstart, o));
+        }
 
-        for (int n = first; n < a.tab_len; ++n) {
+        for (int n = wstart; n < a.tab_len; ++n) {
             const TabEntry e = tab[n];
-            const bool act = live && ((T)e.key2 < F);
-            if (__ballot(act) == 0ull) break;
+            const T bound = (TAIL && spec == 1) ? vmin<T>(F, (T)r2s) : F;
+            const bool act = live && n >= lstart && ((T)e.key2 < bound);
+            if (__ballot(live && ((T)e.key2 < bound)) == 0ull) break;
             const int qx = x + e.ax, qy = y + e.ay, qz = z + e.az;
             const bool cin = (unsigned)qx < (unsigned)nx && (unsigned)qy < (unsigned)ny &&
                              (DIM == 2 || (unsigned)qz < (unsigned)nz);
@@ -788,14 +830,23 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const Tab
         }
 
         const bool to_guard = MODE == 1 && live && ill;
-        if (live && !to_guard) {
+        const bool to_fb = TAIL && spec == 1 && live && !to_guard && (float)F > r2s;
+        if (live && !to_guard && !to_fb) {
             finish_node(a, node, (float)F, npass, nborder, gm);
-            cells += lane_cells;
+            cells += lane_cells + (TAIL ? zero_cells(DIM, x, y, z, nx, ny, nz) : 0u);
             n_fp64 += lane_fp64;
         }
+        if (to_fb) cells += lane_cells;
         if (MODE == 1) {
             const uint32_t gpos = block_append(to_guard, &a.sc->n_guard);
             if (to_guard) a.guard_list[gpos] = (uint32_t)node;
+        }
+        if (TAIL && spec == 1) {
+            const uint32_t fpos = block_append(to_fb, &a.sc->n_fallback);
+            if (to_fb) {
+                a.fb_list[fpos] = item;
+                a.tail_f[item] = f2u((float)F);
+            }
         }
     }
     block_sums(sums, npass, nborder, n_fp64, cells, gm);
@@ -810,11 +861,12 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const Tab
 // g_req: lanes per node (8..64), or 0 to pick it from the tail length on the device: about
 // 2^19 lanes in flight fill the GPU, so a short tail gets wide groups (latency) and a long
 // one narrow groups (fewer rows past the break).
+// spec: as in k_walk (1 speculative, 2 fallback from the first row at or beyond f gamma_hat).
 template <int DIM, int MODE>
 __global__ __launch_bounds__(SEARCH_THREADS) void k_tail_group(SearchArgs a, const TabEntry* __restrict__ tab,
                                                                const uint32_t* __restrict__ order,
                                                                const uint32_t* __restrict__ count, int first,
-                                                               int g_req, BlockSums* sums) {
+                                                               int g_req, int spec, BlockSums* sums) {
     constexpr int GMODE = (DIM == 3 && MODE == 1) ? 1 : 0;
     const uint32_t M = *count;
     int G = g_req;
@@ -846,17 +898,21 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_tail_group(SearchArgs a, con
         float F = live ? u2f(a.tail_f[item]) : 0.0f;
         uint32_t lane_cells = 0;
         bool ill = false;
+        const float r2s = (spec && live) ? spec_bound2(a, node) : Num<float>::inf();
+        // the fallback resumes at the first row the speculative bound cut off (per group)
+        const int start = (spec == 2 && live) ? resume_row(tab, a.tab_len, first, r2s) : first;
 
-        for (int n0 = first; n0 < a.tab_len; n0 += G) {
-            const float k_first = tab[n0].key2;       // wave-uniform row: scalar load
-            const bool grp_act = live && k_first < F;
+        for (int n0 = start; n0 < a.tab_len; n0 += G) {
+            const float k_first = tab[n0].key2;       // uniform per group
+            const float bound = spec == 1 ? vmin<float>(F, r2s) : F;
+            const bool grp_act = live && k_first < bound;
             if (__ballot(grp_act) == 0ull) break;
             const int n = n0 + gl;
             TabEntry e;
             bool act = false;
             if (grp_act && n < a.tab_len) {
                 e = tab[n];
-                act = e.key2 < F;
+                act = e.key2 < bound;
             }
             int qx = 0, qy = 0, qz = 0;
             if (act) {
@@ -920,13 +976,22 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_tail_group(SearchArgs a, con
         }
         const bool leader = live && gl == 0;
         const bool to_guard = MODE == 1 && leader && ill;
-        if (leader && !to_guard) {
+        const bool to_fb = spec == 1 && leader && !to_guard && F > r2s;
+        if (leader && !to_guard && !to_fb) {
             finish_node(a, node, F, npass, nborder, gm);
             cells += lane_cells + zero_cells(DIM, x, y, z, nx, ny, nz);
         }
+        if (to_fb) cells += lane_cells;
         if (MODE == 1) {
             const uint32_t gpos = block_append(to_guard, &a.sc->n_guard);
             if (to_guard) a.guard_list[gpos] = (uint32_t)node;
+        }
+        if (spec == 1) {
+            const uint32_t fpos = block_append(to_fb, &a.sc->n_fallback);
+            if (to_fb) {
+                a.fb_list[fpos] = item;
+                a.tail_f[item] = f2u(F);
+            }
         }
     }
     block_sums(sums, npass, nborder, 0u, cells, gm);
@@ -978,25 +1043,46 @@ unsigned blocks_for(uint32_t m) { return (m + SEARCH_THREADS - 1) / SEARCH_THREA
 
 template <int DIM, int MODE, bool TAIL>
 void walk(const SearchArgs& a, const uint32_t* order, const uint32_t* count, int first, unsigned blocks,
-          BlockSums* sums, hipStream_t s) {
+          BlockSums* sums, hipStream_t s, int spec = 0) {
     hipLaunchKernelGGL((k_walk<DIM, MODE, TAIL>), dim3(blocks), dim3(SEARCH_THREADS), 0, s, a, a.tab, order,
-                       count, first, sums);
+                       count, first, spec, sums);
 }
 
 template <int DIM, int MODE>
-void tail_group_g(const SearchArgs& a, int G, int first, unsigned blocks, BlockSums* sums, hipStream_t s) {
-    hipLaunchKernelGGL((k_tail_group<DIM, MODE>), dim3(blocks), dim3(SEARCH_THREADS), 0, s, a, a.tab, a.tail_pos,
-                       &a.sc->n_tail, first, G, sums);
+void tail_group_g(const SearchArgs& a, const uint32_t* order, const uint32_t* count, int G, int first,
+                  unsigned blocks, int spec, BlockSums* sums, hipStream_t s) {
+    hipLaunchKernelGGL((k_tail_group<DIM, MODE>), dim3(blocks), dim3(SEARCH_THREADS), 0, s, a, a.tab, order, count,
+                       first, G, spec, sums);
 }
 
-void tail_group(const SearchArgs& a, int ndim, int mode, int G, int first, unsigned blocks, BlockSums* sums,
-                hipStream_t s) {
+void tail_group(const SearchArgs& a, const uint32_t* order, const uint32_t* count, int ndim, int mode, int G,
+                int first, unsigned blocks, int spec, BlockSums* sums, hipStream_t s) {
     if (ndim == 3) {
-        if (mode == 1) tail_group_g<3, 1>(a, G, first, blocks, sums, s);
-        else tail_group_g<3, 0>(a, G, first, blocks, sums, s);
+        if (mode == 1) tail_group_g<3, 1>(a, order, count, G, first, blocks, spec, sums, s);
+        else tail_group_g<3, 0>(a, order, count, G, first, blocks, spec, sums, s);
     } else {
-        tail_group_g<2, 0>(a, G, first, blocks, sums, s);
+        tail_group_g<2, 0>(a, order, count, G, first, blocks, spec, sums, s);
     }
+}
+
+// Pass B over `order` (count on the device): one lane per node (G == 1) or G lanes.
+unsigned tail_pass(const SearchArgs& a, const SearchPlan& p, const uint32_t* order, const uint32_t* count,
+                   int first, bool guarded, int spec, unsigned tb, BlockSums* sums, hipStream_t s) {
+    const int G = p.tail_lanes;   // 0: chosen on the device from the list length
+    if (G == 1) {
+        if (p.ndim == 3) {
+            if (guarded) walk<3, 1, true>(a, order, count, first, tb, sums, s, spec);
+            else walk<3, 0, true>(a, order, count, first, tb, sums, s, spec);
+        } else {
+            walk<2, 0, true>(a, order, count, first, tb, sums, s, spec);
+        }
+        return tb;
+    }
+    const unsigned groups = SEARCH_THREADS / (unsigned)(G ? G : 8);
+    unsigned gb = (p.M + groups - 1) / groups;
+    if (gb > kTailBlocks) gb = kTailBlocks;
+    tail_group(a, order, count, p.ndim, guarded ? 1 : 0, G, first, gb, spec, sums, s);
+    return gb;
 }
 
 }  // namespace
@@ -1047,24 +1133,12 @@ hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s
             if (e != hipSuccess) return e;
         }
         if (p.ev_sort_end) (void)hipEventRecord(p.ev_sort_end, s);
-        // pass B
+        // pass B (with the learned radius: the speculative walk, then the plain walk of the
+        // nodes it could not certify, resumed where the speculative bound cut them off)
         if (a.tab_len > first) {
-            const int G = p.tail_lanes;   // 0: chosen on the device from the tail length
-            if (G == 1) {
-                if (p.ndim == 3) {
-                    if (guarded) walk<3, 1, true>(a, a.tail_pos, &a.sc->n_tail, first, tb, sums, s);
-                    else walk<3, 0, true>(a, a.tail_pos, &a.sc->n_tail, first, tb, sums, s);
-                } else {
-                    walk<2, 0, true>(a, a.tail_pos, &a.sc->n_tail, first, tb, sums, s);
-                }
-                used += (int)tb;
-            } else {
-                const unsigned groups = SEARCH_THREADS / (unsigned)(G ? G : 8);
-                unsigned gb = (p.M + groups - 1) / groups;
-                if (gb > kTailBlocks) gb = kTailBlocks;
-                tail_group(a, p.ndim, guarded ? 1 : 0, G, first, gb, sums, s);
-                used += (int)gb;
-            }
+            const int spec = p.spec ? 1 : 0;
+            used += (int)tail_pass(a, p, a.tail_pos, &a.sc->n_tail, first, guarded, spec, tb, sums, s);
+            if (spec) used += (int)tail_pass(a, p, a.fb_list, &a.sc->n_fallback, first, guarded, 2, tb, sums, s);
         }
         if (p.ev_tail_end) (void)hipEventRecord(p.ev_tail_end, s);
         // guard pass

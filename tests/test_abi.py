@@ -50,7 +50,8 @@ def test_options_defaults(abi):
     assert o.sort_mode == abi.SORT_NONE
     assert o.precision == abi.PREC_GUARDED
     assert o.cond_threshold == 1e6
-    assert o.timing == 0 and o.tail_lanes == 0 and o.cell_lanes == 0 and list(o.reserved) == [0] * 5
+    assert o.timing == 0 and o.tail_lanes == 0 and o.cell_lanes == 0 and list(o.reserved) == [0] * 4
+    assert o.radius_mode == abi.RADIUS_PLAIN and not o.model and o.radius_factor == 1.1
 
 
 def test_status_strings(abi):
@@ -113,3 +114,26 @@ def test_null_model(abi):
     assert lib.gammax_model_predict(None, None, None, None, None, None, None) == abi.E_NULL
     assert lib.gammax_model_features(None, None, None, None, None, None) == abi.E_NULL
     assert lib.gammax_model_last_error(None) == b""
+
+
+def test_struct_layouts_match_the_header(abi, tmp_path):
+    """ctypes mirrors of the C structs have the C compiler's sizes and offsets."""
+    import subprocess
+    structs = {"gammax_problem_t": abi.Problem, "gammax_options_t": abi.Options,
+               "gammax_result_t": abi.Result, "gammax_adam_t": abi.Adam}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gammax.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
