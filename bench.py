@@ -27,6 +27,7 @@ METRIC = "ref voxels/sec, 3D 3%/3mm: plain vs learned-radius at |Δγ|≤1e-5; %
 # 2 triangles.
 FLOP_PER_CELL = {3: 392, 2: 82}
 PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (packed)
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 
 # HBM bytes per launch of the dominant kernel, from the FETCH_SIZE and WRITE_SIZE counter
 # runs summarised in the named profile (each counter scaled by what it reads for a plain
@@ -108,6 +109,9 @@ def main():
     ap.add_argument("--tail-lanes", type=int, default=0, choices=[0, 1, 8, 16, 32, 64])
     ap.add_argument("--cell-lanes", type=int, default=0, choices=[0, 1, 4, 8])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-radius leg")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1012_1900_amd", "weights",
+                                                      "cnn_3d_2.5mm_3pct3mm.npy"))
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a profiler reference "
@@ -144,36 +148,64 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    kw = dict(sort=args.sort, precision=args.precision, tail_lanes=args.tail_lanes,
-              cell_lanes=args.cell_lanes, out=out)
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, **kw)
-    torch.cuda.synchronize()
+    def leg(extra):
+        """W warm-up maps, K timed maps (graph replay), then K maps with HIP events per phase."""
+        kw = dict(sort=args.sort, precision=args.precision, tail_lanes=args.tail_lanes,
+                  cell_lanes=args.cell_lanes, out=out)
+        kw.update(extra)
+        for _ in range(args.warmup):
+            gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, r_last = gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phases = []
+        for _ in range(args.steps):
+            _, r = gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, timing=True, **kw)
+            phases.append(r)
+        torch.cuda.synchronize()
+        return wall / args.steps, r_last, phases
 
-    # timed region: K full gamma maps as a user calls them (steady state: one graph replay
-    # and one synchronisation per map)
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, r_last = gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, **kw)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1e3 * wall / args.steps
+    log(f"plain search: warmup {args.warmup}, timing {args.steps} steps")
+    sec, r_last, phases = leg({})
+    g_plain = out.clone()
+    ms_per_step = 1e3 * sec
     M = r_last.n_evaluated
-    value = M / (wall / args.steps)
-
-    # per-kernel durations: the same K maps with HIP events recorded on the launch stream
-    # around each phase (these calls queue the kernels directly instead of replaying)
-    phases = []
-    for _ in range(args.steps):
-        _, r = gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, timing=True, **kw)
-        phases.append(r)
-    torch.cuda.synchronize()
-    mean = lambda f: float(np.mean([getattr(p, f) for p in phases]))  # noqa: E731
+    value = M / sec
+    mean = lambda f, ph=phases: float(np.mean([getattr(p, f) for p in ph]))  # noqa: E731
     ms_search = mean("ms_search")
     log(f"{M} nodes, {ms_per_step:.3f} ms/step, search {ms_search:.4f} ms")
+
+    # the learned radius on the same pair: speculative walk inside 1.1 gamma_hat, tail
+    # ordered by the prediction (the network's inference inside the timed map)
+    learned = None
+    if nd == 3 and not args.no_learned and os.path.exists(args.weights):
+        model = gx.Model(np.load(args.weights, allow_pickle=False))
+        log("learned radius")
+        lsec, lr_last, lph = leg(dict(radius="learned", sort="predicted", model=model))
+        ms_cnn = mean("ms_cnn", lph)
+        shp = pair.ref.shape
+        # algorithmic MACs of the dense network: layer l over the grid grown by 2 (3 - l) per side
+        macs = sum(np.prod([n + 2 * (3 - l) for n in shp]) * m
+                   for l, m in enumerate((2 * 16 * 27, 16 * 16 * 27, 16 * 16 * 27, 16 * 27)))
+        cnn_tflops = 2 * macs / (ms_cnn * 1e-3) / 1e12
+        learned = {
+            "value": round(lr_last.n_evaluated / lsec, 1),
+            "ms_per_step": round(1e3 * lsec, 4),
+            "speedup_vs_plain": round(sec / lsec, 3),
+            "n_tail": int(lr_last.n_tail),
+            "n_fallback": int(lr_last.n_fallback),
+            "identical_to_plain": bool(torch.equal(out, g_plain)),
+            "phases_ms": {k: round(mean(k, lph), 4) for k in ("ms_prep", "ms_cnn", "ms_search", "ms_sort",
+                                                              "ms_tail", "ms_guard")},
+            "weights": os.path.relpath(args.weights, ROOT),
+            "cnn_roofline": {"bound": "mfma", "achieved": round(cnn_tflops, 2), "peak": PEAK_BF16_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(cnn_tflops / PEAK_BF16_TFLOPS, 4),
+                             "algorithmic_flop_per_inference": int(2 * macs)},
+        }
+        log(f"learned: {learned['ms_per_step']} ms/step, {learned['n_fallback']}/{learned['n_tail']} fallbacks")
 
     wc = work_counts(cfg, seed, args.dd, args.dta)
     cells = wc["cells_visited"] if wc else None
@@ -224,6 +256,7 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "learned": learned,
     }
     print(json.dumps(line), flush=True)
 

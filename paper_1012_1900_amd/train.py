@@ -68,8 +68,10 @@ def main():
     ap.add_argument("--heldout-seed0", type=int, default=20000)
     ap.add_argument("--crops-per-pair", type=int, default=8)
     ap.add_argument("--crop", type=int, nargs=3, default=[24, 24, 32])
-    ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--high-gamma", type=float, default=0.5,
+                    help="half of the crops centre on nodes with gamma at least this")
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=16)
@@ -101,9 +103,13 @@ def main():
         gam, _ = gx.gammax_map(ref, ev, spacing, args.dd, args.dta, 0.1, ctx=ctx)
         feat = gx.model_features(ref, ev, spacing, args.dd, args.dta, ctx=ctx)
         masked = torch.nonzero(gam >= 0).cpu().numpy()
+        # half of the crops centre on nodes of large gamma: the ones that walk past the
+        # key-0 cells are rare, and they are where the prediction is used
+        high = torch.nonzero(gam >= args.high_gamma).cpu().numpy()
         nz, ny, nx = gam.shape
-        for _ in range(args.crops_per_pair):
-            z, y, x = masked[rng.integers(len(masked))]
+        for c in range(args.crops_per_pair):
+            pool_c = high if (c % 2 == 1 and len(high)) else masked
+            z, y, x = pool_c[rng.integers(len(pool_c))]
             oz = int(np.clip(z - c0 // 2, 0, nz - c0))
             oy = int(np.clip(y - c1 // 2, 0, ny - c1))
             ox = int(np.clip(x - c2 // 2, 0, nx - c2))
@@ -123,8 +129,8 @@ def main():
         idx = torch.from_numpy(rng.integers(0, n_crops, size=args.batch)).to(dev)
         loss = model.train_step(feats_all[idx].contiguous(), labels_all[idx].contiguous(), lr=lr)
         losses.append(loss)
-        if (step + 1) % 250 == 0:
-            log(f"step {step + 1}: loss {np.mean(losses[-250:]):.4f} lr {lr:.2e} ({time.time() - t0:.1f} s)")
+        if (step + 1) % 1000 == 0:
+            log(f"step {step + 1}: loss {np.mean(losses[-1000:]):.4f} lr {lr:.2e} ({time.time() - t0:.1f} s)")
     t_train = time.time() - t0
     params = model.params()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
@@ -163,6 +169,7 @@ def main():
         "train_seeds": [args.train_seed0, args.train_seed0 + args.train_pairs - 1],
         "heldout_seeds": [args.heldout_seed0, args.heldout_seed0 + args.heldout_pairs - 1],
         "crops_per_pair": args.crops_per_pair, "crop": args.crop, "batch": args.batch,
+        "high_gamma": args.high_gamma,
         "steps": args.steps, "lr": args.lr, "seed": args.seed,
         "final_train_loss": float(np.mean(losses[-250:])),
         "data_seconds": round(t_data, 1), "train_seconds": round(t_train, 1),

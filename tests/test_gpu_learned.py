@@ -119,3 +119,49 @@ def test_learned_needs_a_model(gx, pair):
     assert e.value.status == -1
     with pytest.raises(gx.GammaxError):
         gx.gammax_map(ref, ev, pair.spacing, 0.03, 3.0, 0.1, radius="learned", model=None, radius_factor=0.5)
+
+
+def _spearman(a, b):
+    ra = np.argsort(np.argsort(a)).astype(np.float64)
+    rb = np.argsort(np.argsort(b)).astype(np.float64)
+    ra -= ra.mean()
+    rb -= rb.mean()
+    return float((ra * rb).sum() / np.sqrt((ra * ra).sum() * (rb * rb).sum()))
+
+
+def _lockstep_efficiency(work, order, wave=64):
+    """Useful fraction of a one-lane-per-node walk: sum of walk lengths over
+    sum over waves of 64 x the longest walk in the wave."""
+    w = work[order]
+    pad = (-len(w)) % wave
+    w = np.concatenate([w, np.zeros(pad, dtype=w.dtype)]).reshape(-1, wave)
+    return float(w.sum() / (w.max(axis=1).sum() * wave))
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_trained_network_gains_over_the_dd_order(gx):
+    """What the trained network buys on a held-out pair (seed 20000, never trained on):
+    its prediction ranks the exact gamma better than the dose difference does, and
+    ordering the nodes that walk past the key-0 cells by it fills the waves of the
+    one-lane-per-node walk better than the paper's DD order.  Exact gamma and per-node
+    walk lengths come from the oracle."""
+    import oracle
+    from dosegen import make_config_pair
+    pair = make_config_pair("3d_128x128x96_2.5mm", 20000)
+    ref, ev = dev(pair.ref), dev(pair.eval)
+    m = gx.Model(np.load(WEIGHTS, allow_pickle=False))
+    y = host(m.predict(ref, ev, pair.spacing, 0.03, 3.0))
+    o = oracle.gamma(pair.ref, pair.eval, pair.spacing, 0.03, 3.0, 0.1)
+    mask = o.gamma >= 0
+    g = o.gamma[mask]
+    ghat = np.maximum(np.exp(y[mask].astype(np.float64)) - 0.01, 0.0)
+    g0 = np.abs(pair.eval.astype(np.float64) - pair.ref)[mask] / (0.03 * float(pair.ref.max()))
+    assert _spearman(ghat, g) > _spearman(g0, g) + 0.02
+    # the tail: nodes that visit more than the 8 key-0 cells
+    cells = o.cells.reshape(pair.ref.shape)[mask].astype(np.int64)
+    tail = cells > 8
+    assert tail.sum() > 256
+    work = cells[tail] - 8
+    eff_hat = _lockstep_efficiency(work, np.argsort(ghat[tail], kind="stable"))
+    eff_dd = _lockstep_efficiency(work, np.argsort(g0[tail], kind="stable"))
+    assert eff_hat > eff_dd, (eff_hat, eff_dd)
