@@ -28,6 +28,8 @@ __all__ = [
     "make_pair_2d",
     "make_pair_3d",
     "make_config_pair",
+    "batch_specs",
+    "make_batch_pair",
     "CONFIG_SHAPES",
 ]
 
@@ -177,3 +179,44 @@ def make_config_pair(config: str, seed: int) -> DosePair:
     if len(shape) == 2:
         return make_pair_2d(seed, shape, spacing)
     return make_pair_3d(seed, shape, spacing)
+
+
+@dataclass
+class BatchSpec:
+    """One pair of a mixed batch: the generator inputs and the gamma criteria."""
+    seed: int
+    shape: Tuple[int, ...]
+    spacing: Tuple[float, ...]
+    dd: float
+    dta: float
+    local: bool
+
+
+def batch_specs(seed: int, n: int = 64, scale: float = 1.0):
+    """The mixed batch: 2D or 3D with probability 1/2; 2D n x n nodes, n ~ U{128..200},
+    h ~ U[1, 2] mm; 3D nx = ny ~ U{128..200}, nz ~ U{96..150}, h ~ U[1, 2] mm isotropic;
+    criteria uniform over 3%/3mm, 2%/2mm, 1%/1mm; global or local with probability 1/2.
+    ``scale`` shrinks every axis (small batches for tests).  Pair i uses seed seed + 1 + i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        three = rng.uniform() < 0.5
+        h = float(rng.uniform(1.0, 2.0))
+        if three:
+            nxy = int(rng.integers(128, 201))
+            nz = int(rng.integers(96, 151))
+            shape = (max(2, int(nz * scale)), max(2, int(nxy * scale)), max(2, int(nxy * scale)))
+        else:
+            m = int(rng.integers(128, 201))
+            shape = (max(2, int(m * scale)), max(2, int(m * scale)))
+        crit = int(rng.integers(0, 3))
+        dd, dta = [(0.03, 3.0), (0.02, 2.0), (0.01, 1.0)][crit]
+        local = bool(rng.uniform() < 0.5)
+        out.append(BatchSpec(seed + 1 + i, shape, (h,) * len(shape), dd, dta, local))
+    return out
+
+
+def make_batch_pair(spec: "BatchSpec") -> DosePair:
+    if len(spec.shape) == 2:
+        return make_pair_2d(spec.seed, spec.shape, spec.spacing)
+    return make_pair_3d(spec.seed, spec.shape, spec.spacing)

@@ -109,7 +109,9 @@ typedef struct {
     int32_t radius_mode;      /* gammax_radius_t */
     const gammax_model_t *model;  /* the model for GAMMAX_RADIUS_LEARNED / GAMMAX_SORT_PREDICTED */
     double radius_factor;     /* f of the learned radius f * gamma_hat, >= 1 (default 1.1) */
-    int32_t reserved[4];      /* must be 0 */
+    int32_t autotune;         /* gammax_batch: 1 = time the tail layouts of each new shape class on
+                                 the first call and keep the fastest (see gammax_batch) */
+    int32_t reserved[3];      /* must be 0 */
 } gammax_options_t;
 
 typedef struct {
@@ -134,7 +136,8 @@ typedef struct {
                                    tetrahedron (guarded precision, 3D), and the count reduction */
     uint64_t n_fallback;      /* learned radius: tail nodes not certified inside f * gamma_hat */
     float ms_cnn;             /* timing = 1 only: features and CNN inference (learned radius) */
-    int32_t pad_;
+    float ms_done;            /* gammax_batch only: time from the start of the batch until the
+                                 last work item of this pair finished (device clock) */
 } gammax_result_t;
 
 typedef struct gammax_ctx gammax_ctx_t;
@@ -274,6 +277,32 @@ gammax_status_t gammax_model_forward(gammax_model_t *model, int32_t nvol, const 
 gammax_status_t gammax_model_train_step(gammax_model_t *model, int32_t nvol, const int64_t *crop,
                                         const uint16_t *feat_dev, const float *gamma_dev,
                                         const gammax_adam_t *adam, double *loss, void *stream);
+
+/*
+ * ---- Batches of dose pairs ------------------------------------------------------------
+ *
+ * Gamma maps of n pairs of any mix of dimensionality, grid, spacing, criteria and
+ * normalisation, with one set of options, through one pipeline: every phase runs once for
+ * the whole batch (a prep over all pairs' tiles; one persistent pass over the key-0 cells
+ * of every pair's nodes in cost order; tail walks, fallbacks and the guard pass taken from
+ * a queue of (pair, chunk) items; one count reduction), replayed from a captured HIP graph
+ * when the same batch comes again.  Each pair keeps its own cell table.  sort_mode is not
+ * used (the queue orders the work); the learned radius applies to the 3D pairs.
+ *   problems[i], refs[i], evals[i], gammas[i]: pair i, as in gammax_map.
+ *   results[i]: filled on GAMMAX_OK (ms_done gives each pair's completion time).
+ * With opt->autotune = 1, each shape class (dimensionality, size, criteria, spacing) met
+ * for the first time has its tail layout (8, 16, 32 or 64 lanes per node) chosen by timing
+ * the batch with each, and the choice is kept in the context (gammax_tune_save/load).
+ * A device-side error of any pair (non-finite dose, no positive dose) fails the batch;
+ * gammax_last_error names the pair.  Synchronises `stream`.
+ */
+gammax_status_t gammax_batch(gammax_ctx_t *ctx, int32_t n, const gammax_problem_t *problems,
+                             const float *const *refs, const float *const *evals, float *const *gammas,
+                             const gammax_options_t *opt, gammax_result_t *results, void *stream);
+
+/* Write / read the context's tuned tail layouts (one text line per shape class). */
+gammax_status_t gammax_tune_save(const gammax_ctx_t *ctx, const char *path);
+gammax_status_t gammax_tune_load(gammax_ctx_t *ctx, const char *path);
 
 /* Static description of a status code. */
 const char *gammax_status_string(gammax_status_t status);

@@ -14,9 +14,12 @@ from ._abi import (  # noqa: F401
     build_table,
     context,
     gamma_map,
+    gammax_batch,
     gammax_map,
     pass_count,
     sort_pairs,
     status_string,
+    tune_load,
+    tune_save,
     LIB_PATH,
 )

@@ -79,7 +79,8 @@ class Options(C.Structure):
         ("radius_mode", C.c_int32),
         ("model", C.c_void_p),
         ("radius_factor", C.c_double),
-        ("reserved", C.c_int32 * 4),
+        ("autotune", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
 
@@ -105,7 +106,7 @@ class Result(C.Structure):
         ("ms_guard", C.c_float),
         ("n_fallback", C.c_uint64),
         ("ms_cnn", C.c_float),
-        ("pad_", C.c_int32),
+        ("ms_done", C.c_float),
     ]
 
 
@@ -207,7 +208,7 @@ class GammaResult:
     ms_guard: float
     n_fallback: int
     ms_cnn: float
-    pad_: int = 0
+    ms_done: float = 0.0
 
 
 def _torch():
@@ -516,6 +517,66 @@ def model_features(ref, ev, spacing: Sequence[float], dd: float, dta: float = 3.
                                         feat.data_ptr(), _vp(s.cuda_stream))
     ctx.check(st)
     return feat
+
+
+# ---- batches -----------------------------------------------------------------------------
+
+_lib.gammax_batch.restype = C.c_int
+_lib.gammax_batch.argtypes = [_vp, C.c_int32, C.POINTER(Problem), C.POINTER(_vp), C.POINTER(_vp),
+                              C.POINTER(_vp), C.POINTER(Options), C.POINTER(Result), _vp]
+_lib.gammax_tune_save.restype = C.c_int
+_lib.gammax_tune_save.argtypes = [_vp, C.c_char_p]
+_lib.gammax_tune_load.restype = C.c_int
+_lib.gammax_tune_load.argtypes = [_vp, C.c_char_p]
+
+
+def gammax_batch(pairs, *, precision: str = "guarded", cond_threshold: float = 1e6, tail_lanes: int = 0,
+                 radius: str = "plain", model=None, radius_factor: float = 1.1, autotune: bool = False,
+                 outs=None, ctx: Optional[Context] = None, stream=None):
+    """Gamma maps of a batch of pairs in one pipeline.
+
+    ``pairs``: sequence of dicts with ``ref``, ``ev`` (float32 device tensors), ``spacing``,
+    ``dd``, ``dta`` and optionally ``threshold`` (default 0.1) and ``local`` (default False).
+    Returns (list of gamma tensors, list of GammaResult).
+    """
+    torch = _torch()
+    n = len(pairs)
+    if n == 0:
+        return [], []
+    dev = pairs[0]["ref"].device
+    probs = (Problem * n)()
+    refs, evs, gams = (_vp * n)(), (_vp * n)(), (_vp * n)()
+    out_list = []
+    for i, q in enumerate(pairs):
+        _dev_tensor(q["ref"], "ref")
+        _dev_tensor(q["ev"], "ev")
+        if q["ref"].shape != q["ev"].shape or q["ref"].device != dev or q["ev"].device != dev:
+            raise ValueError(f"pair {i}: ref and ev must share shape and device")
+        if len(q["spacing"]) != q["ref"].dim():
+            raise ValueError(f"pair {i}: spacing needs one entry per axis")
+        probs[i] = make_problem(tuple(q["ref"].shape), q["spacing"], q["dd"], q["dta"],
+                                q.get("threshold", 0.1), q.get("local", False))
+        g = outs[i] if outs is not None else torch.empty_like(q["ref"])
+        out_list.append(g)
+        refs[i], evs[i], gams[i] = q["ref"].data_ptr(), q["ev"].data_ptr(), g.data_ptr()
+    ctx = ctx or context(dev.index or 0)
+    o = make_options("none", precision, cond_threshold, False, tail_lanes, 0, radius, model, radius_factor)
+    o.autotune = 1 if autotune else 0
+    res = (Result * n)()
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        st = _lib.gammax_batch(ctx.handle, n, probs, refs, evs, gams, C.byref(o), res, _vp(s.cuda_stream))
+    ctx.check(st)
+    results = [GammaResult(**{f[0]: getattr(r, f[0]) for f in Result._fields_}) for r in res]
+    return out_list, results
+
+
+def tune_save(path: str, ctx: Context):
+    ctx.check(_lib.gammax_tune_save(ctx.handle, path.encode()))
+
+
+def tune_load(path: str, ctx: Context):
+    ctx.check(_lib.gammax_tune_load(ctx.handle, path.encode()))
 
 
 def raw_library() -> C.CDLL:

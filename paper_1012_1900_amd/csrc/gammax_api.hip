@@ -9,11 +9,15 @@
 //    radius turned out larger than the cached table covers, the call is redone below.
 //  * table build: the compaction runs first, the host reads M and R, builds the sorted
 //    cell table for R (cached with headroom), then queues the search.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "gammax.h"
 #include "internal.hpp"
@@ -84,7 +88,10 @@ struct gammax_ctx {
     int64_t cnn_ws_cap = 0;
     float* yhat = nullptr;          // log(gamma_hat + 0.01) per grid node
     int64_t yhat_cap = 0;
+    struct BatchState* batch = nullptr;   // gammax_batch state (created on first use)
 };
+
+void destroy_batch(gammax_ctx* c);
 
 namespace {
 
@@ -188,7 +195,8 @@ gammax_status_t check_options(gammax_ctx* c, const gammax_options_t* o) {
         return fail(c, GAMMAX_E_PARAM, "tail_lanes must be 0, 1, 8, 16, 32 or 64");
     if (!(o->cell_lanes == 0 || o->cell_lanes == 1 || o->cell_lanes == 4 || o->cell_lanes == 8))
         return fail(c, GAMMAX_E_PARAM, "cell_lanes must be 0, 1, 4 or 8");
-    for (int i = 0; i < 4; ++i)
+    if (o->autotune != 0 && o->autotune != 1) return fail(c, GAMMAX_E_PARAM, "autotune must be 0 or 1");
+    for (int i = 0; i < 3; ++i)
         if (o->reserved[i] != 0) return fail(c, GAMMAX_E_PARAM, "reserved option fields must be 0");
     if (o->model && c && o->model->device != c->device)
         return fail(c, GAMMAX_E_PARAM, "model and context live on different devices");
@@ -212,12 +220,13 @@ float round_down_float(double x) {
     return f;
 }
 
-// Build the sorted cell table for `g` into the context cache (synchronises `s`).
-gammax_status_t build_table(gammax_ctx* c, TableGeom g, hipStream_t s) {
+// Build the sorted cell table for `g` into *tab (grown as needed; synchronises `s`).
+// *len receives the row count, *k1 the key^2 of the first row after the 2^d key-0 rows.
+gammax_status_t build_rows(gammax_ctx* c, TableGeom& g, TabEntry** tab, int64_t* cap, int64_t* len, float* k1,
+                           hipStream_t s) {
     table_box(g);
     if (g.box > kMaxTableBox)
         return fail(c, GAMMAX_E_RADIUS, "cell table candidate box of " + std::to_string(g.box) + " entries");
-    c->tab_valid = false;
     ++c->generation;
     gammax_status_t st;
     if (g.box > c->tb_cap || !c->tb) {
@@ -237,16 +246,24 @@ gammax_status_t build_table(gammax_ctx* c, TableGeom g, hipStream_t s) {
     HIPCHK(c, hipMemcpyAsync(c->h_count, c->d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     const int64_t T = *c->h_count;
-    if ((st = grow(c, &c->tab, &c->tab_cap, T)) != GAMMAX_OK) return st;
-    HIPCHK(c, launch_table_rows(g, vals, T, c->tab, s));
+    if ((st = grow(c, tab, cap, T)) != GAMMAX_OK) return st;
+    HIPCHK(c, launch_table_rows(g, vals, T, *tab, s));
     const int zero_rows = g.ndim == 3 ? 8 : 4;
-    c->tab_k1 = INFINITY;
+    *k1 = INFINITY;
     if (T > zero_rows) {
-        HIPCHK(c, hipMemcpyAsync(c->h_count, &c->tab[zero_rows].key2, sizeof(float), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(c->h_count, &(*tab)[zero_rows].key2, sizeof(float), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
-        std::memcpy(&c->tab_k1, c->h_count, sizeof(float));
+        std::memcpy(k1, c->h_count, sizeof(float));
     }
-    c->tab_len = T;
+    *len = T;
+    return GAMMAX_OK;
+}
+
+// Build the context's own table (the single-pair path) for `g`.
+gammax_status_t build_table(gammax_ctx* c, TableGeom g, hipStream_t s) {
+    c->tab_valid = false;
+    gammax_status_t st = build_rows(c, g, &c->tab, &c->tab_cap, &c->tab_len, &c->tab_k1, s);
+    if (st != GAMMAX_OK) return st;
     c->tab_geom = g;
     c->tab_valid = true;
     return GAMMAX_OK;
@@ -370,17 +387,17 @@ gammax_status_t enqueue_cnn(gammax_ctx* c, const CallSetup& cs, hipStream_t s, b
 }
 
 // Queue the search (steps 3, 6, 7) over at most m_bound nodes with the cached table.
-gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bound, float r2_cap,
-                               hipStream_t s, bool timing) {
-    const gammax_problem_t* p = cs.p;
-    const gammax_options_t& opt = *cs.opt;
+// Search arguments of one pair.  work: the kWorkArrays node arrays, `stride` words apart.
+SearchArgs make_search_args(const gammax_problem_t* p, const gammax_options_t& opt, const float* ref,
+                            const float* ev, float* gamma, Scalars* sc, const TabEntry* tab, int tab_len, float k1,
+                            float r2_cap, uint32_t* work, int64_t stride, BlockSums* sums, const float* yhat) {
     SearchArgs sa{};
-    sa.ref = cs.ref;
-    sa.ev = cs.ev;
-    sa.gamma = cs.gamma;
-    sa.sc = c->d_sc;
-    sa.tab = c->tab;
-    sa.tab_len = c->tab_valid ? (int)c->tab_len : 0;
+    sa.ref = ref;
+    sa.ev = ev;
+    sa.gamma = gamma;
+    sa.sc = sc;
+    sa.tab = tab;
+    sa.tab_len = tab_len;
     if (p->ndim == 3) {
         sa.nz = (int)p->shape[0];
         sa.ny = (int)p->shape[1];
@@ -411,36 +428,54 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
     double guard = opt.cond_threshold * (smin * smin) / (smax * smax);
     if (opt.precision != GAMMAX_PREC_GUARDED) guard = INFINITY;
     sa.den_guard = (float)guard;
-    sa.k1 = c->tab_valid ? c->tab_k1 : INFINITY;
+    sa.k1 = k1;
     sa.r2_cap = r2_cap;
     const bool learned = uses_model(p, &opt);
     sa.tail_key = opt.sort_mode == GAMMAX_SORT_BOUND ? 1 : ((opt.sort_mode == GAMMAX_SORT_PREDICTED && learned) ? 2 : 0);
-    sa.yhat = learned ? c->yhat : nullptr;
+    sa.yhat = learned ? yhat : nullptr;
     sa.spec_factor = (float)opt.radius_factor;
-    sa.fb_list = work_array(c, W_FALLBACK);
-    sa.nodes = work_array(c, W_NODES);
-    sa.tail_node = work_array(c, W_TAIL_NODE);
-    sa.tail_f = work_array(c, W_TAIL_F);
-    sa.tail_key_arr = work_array(c, W_TAIL_KEY);
-    sa.tail_pos = work_array(c, W_TAIL_POS);
-    sa.guard_list = work_array(c, W_GUARD);
-    sa.sums = c->sums;
+    sa.fb_list = work + W_FALLBACK * stride;
+    sa.nodes = work + W_NODES * stride;
+    sa.tail_node = work + W_TAIL_NODE * stride;
+    sa.tail_f = work + W_TAIL_F * stride;
+    sa.tail_key_arr = work + W_TAIL_KEY * stride;
+    sa.tail_pos = work + W_TAIL_POS * stride;
+    sa.guard_list = work + W_GUARD * stride;
+    sa.sums = sums;
+    return sa;
+}
 
+// The 2^d zero-key cells of a problem in table order: offsets in {-1,0}^d, slowest first.
+ZeroGeo make_zero_geo(const gammax_problem_t* p) {
+    ZeroGeo z{};
+    const int nd = p->ndim;
+    const double s3[3] = {p->spacing_mm[0] / p->dta_mm, p->spacing_mm[1] / p->dta_mm,
+                          nd == 3 ? p->spacing_mm[2] / p->dta_mm : 1.0};
+    for (int k = 0; k < (nd == 3 ? 8 : 4); ++k) {
+        if (nd == 3) table_row_host(3, s3, (k >> 2) - 1, ((k >> 1) & 1) - 1, (k & 1) - 1, &z.row[k]);
+        else table_row_host(2, s3, 0, (k >> 1) - 1, (k & 1) - 1, &z.row[k]);
+    }
+    return z;
+}
+
+// Queue the search (steps 3, 6, 7) over at most m_bound nodes with the cached table.
+gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bound, float r2_cap,
+                               hipStream_t s, bool timing) {
+    const gammax_problem_t* p = cs.p;
+    const gammax_options_t& opt = *cs.opt;
+    const SearchArgs sa = make_search_args(p, opt, cs.ref, cs.ev, cs.gamma, c->d_sc, c->tab,
+                                           c->tab_valid ? (int)c->tab_len : 0, c->tab_valid ? c->tab_k1 : INFINITY,
+                                           r2_cap, c->work, c->work_cap, c->sums, c->yhat);
+    const bool learned = uses_model(p, &opt);
     SearchPlan plan{};
-    plan.ndim = nd;
+    plan.ndim = p->ndim;
     plan.precision = opt.precision;
     plan.tail_lanes = opt.tail_lanes;
     // one lane per node (shared neighbourhood loads) unless one lane per cell is asked for
     plan.zero_lanes = (opt.cell_lanes == 4 || opt.cell_lanes == 8) ? 1 : 0;
     plan.spec = (learned && opt.radius_mode == GAMMAX_RADIUS_LEARNED) ? 1 : 0;
     plan.M = m_bound;
-    const double s3[3] = {p->spacing_mm[0] / p->dta_mm, p->spacing_mm[1] / p->dta_mm,
-                          nd == 3 ? p->spacing_mm[2] / p->dta_mm : 1.0};
-    for (int k = 0; k < (nd == 3 ? 8 : 4); ++k) {
-        // zero-key cells in table order: offsets in {-1,0}^d, slowest axis first
-        if (nd == 3) table_row_host(3, s3, (k >> 2) - 1, ((k >> 1) & 1) - 1, (k & 1) - 1, &plan.zero.row[k]);
-        else table_row_host(2, s3, 0, (k >> 1) - 1, (k & 1) - 1, &plan.zero.row[k]);
-    }
+    plan.zero = make_zero_geo(p);
     plan.tmp_keys = work_array(c, W_TMP_K);
     plan.tmp_vals = work_array(c, W_TMP_V);
     plan.hist = opt.sort_mode == GAMMAX_SORT_NONE ? nullptr : c->hist;
@@ -638,6 +673,7 @@ gammax_status_t gammax_ctx_destroy(gammax_ctx_t* c) {
                    c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws, c->yhat};
     for (void* p : dev)
         if (p) (void)hipFree(p);
+    destroy_batch(c);
     void* host[] = {c->h_sc, c->h_cnt, c->h_count};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
@@ -895,6 +931,513 @@ gammax_status_t gammax_model_predict(gammax_ctx_t* c, gammax_model_t* m, const g
     HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return device_errors(c, false);
+}
+
+}  // extern "C"
+
+// ---- batches -----------------------------------------------------------------------------
+
+namespace {
+
+struct BatchTable {
+    TabEntry* tab = nullptr;
+    int64_t cap = 0, len = 0;
+    float k1 = INFINITY;
+    TableGeom geom{};
+    bool valid = false;
+};
+
+}  // namespace
+
+struct BatchState {
+    std::vector<BatchTable> tabs;
+    unsigned char* arena = nullptr;    // device: descriptors, control, per-pair workspaces
+    int64_t arena_cap = 0;
+    unsigned char* host = nullptr;     // pinned staging: descriptors, items, scalars, clocks
+    int64_t host_cap = 0;
+    std::vector<unsigned char> uploaded;   // descriptor bytes now on the device
+    hipGraphExec_t graph = nullptr;
+    std::vector<unsigned char> graph_key;
+    std::map<uint64_t, int> tune;      // shape class -> lanes per node of the tail walks
+    hipEvent_t ev[2] = {};
+    int cus = 0;                       // compute units of the device
+    int clock_khz = 0;                 // rate of the device clock read by the kernels
+};
+
+namespace {
+
+constexpr int64_t kAlignB = 256;
+int64_t alg(int64_t b) { return (b + kAlignB - 1) / kAlignB * kAlignB; }
+
+// Shape class of a pair for the tuner: dimensionality, log2 of the node count, DD in
+// 0.1 %, DTA in 0.1 mm, smallest spacing in 0.1 mm.
+uint64_t shape_class(const gammax_problem_t* p, int64_t n) {
+    int lg = 0;
+    while (((int64_t)1 << (lg + 1)) <= n) ++lg;
+    double hmin = p->spacing_mm[0];
+    for (int i = 1; i < p->ndim; ++i) hmin = std::fmin(hmin, p->spacing_mm[i]);
+    const uint64_t dd = (uint64_t)std::llround(p->dd * 1000.0) & 0xFFFF;
+    const uint64_t dta = (uint64_t)std::llround(p->dta_mm * 10.0) & 0xFFFF;
+    const uint64_t h = (uint64_t)std::llround(hmin * 10.0) & 0xFFFF;
+    return (uint64_t)p->ndim | ((uint64_t)lg << 2) | (dd << 8) | (dta << 24) | (h << 40);
+}
+
+// Layout of one batch (byte offsets into the device arena and the pinned staging).
+struct BatchLayout {
+    int n = 0, n_items = 0, total_red = 0, total_tiles = 0;
+    int64_t o_prep = 0, o_search = 0, o_items = 0, o_chunk0 = 0, o_gsel = 0, o_ctl = 0, o_done = 0, o_sc = 0;
+    std::vector<int64_t> o_sums, o_part, o_blk, o_work, o_yhat, nodes, tiles, red;
+    int64_t arena = 0;
+    // staging: descriptors and items first (uploaded together), then scalars and clocks
+    int64_t h_desc = 0, h_sc = 0, h_done = 0, host = 0;
+};
+
+BatchLayout batch_layout(int n, const gammax_problem_t* probs, const std::vector<int>& learned,
+                         const std::vector<int>& order) {
+    BatchLayout L;
+    L.n = n;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t o = off;
+        off += alg(bytes);
+        return o;
+    };
+    for (int i = 0; i < n; ++i) {
+        int64_t nn = 1;
+        for (int k = 0; k < probs[i].ndim; ++k) nn *= probs[i].shape[k];
+        L.nodes.push_back(nn);
+        L.tiles.push_back(prep_tiles(nn));
+        L.red.push_back(batch_reduce_blocks(nn));
+        L.total_tiles += (int)L.tiles.back();
+        L.total_red += (int)L.red.back();
+    }
+    for (int i : order) L.n_items += (int)((L.nodes[i] + 255) / 256);
+    L.o_prep = take(sizeof(BatchPrepPair) * n);
+    L.o_search = take(sizeof(BatchSearchPair) * n);
+    L.o_items = take(sizeof(uint2) * (L.n_items > 0 ? L.n_items : 1));
+    const int64_t desc_bytes = off;   // descriptors + items are uploaded in one copy
+    L.o_chunk0 = take(sizeof(uint32_t) * 3 * (n + 1));
+    L.o_gsel = take(sizeof(uint32_t) * 3 * n);
+    L.o_ctl = take(sizeof(BatchCtl));
+    L.o_done = take(sizeof(unsigned long long) * (n + 1));
+    L.o_sc = take(sizeof(Scalars) * n);
+    for (int i = 0; i < n; ++i) {
+        L.o_sums.push_back(take(sizeof(BlockSums) * SUM_BINS));
+        L.o_part.push_back(take(sizeof(uint32_t) * 2 * MAX_BLOCKS));
+        L.o_blk.push_back(take(sizeof(uint32_t) * 2 * L.tiles[i]));
+        L.o_work.push_back(take(sizeof(uint32_t) * kWorkArrays * L.nodes[i]));
+        L.o_yhat.push_back(learned[i] ? take(sizeof(float) * L.nodes[i]) : -1);
+    }
+    L.arena = off;
+    L.h_desc = desc_bytes;
+    L.h_sc = alg(desc_bytes);
+    L.h_done = L.h_sc + alg(sizeof(Scalars) * n);
+    L.host = L.h_done + alg(sizeof(unsigned long long) * (n + 1));
+    return L;
+}
+
+}  // namespace
+
+void destroy_batch(gammax_ctx* c) {
+    BatchState* b = c->batch;
+    if (!b) return;
+    for (auto& t : b->tabs)
+        if (t.tab) (void)hipFree(t.tab);
+    if (b->arena) (void)hipFree(b->arena);
+    if (b->host) (void)hipHostFree(b->host);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (auto& e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete b;
+    c->batch = nullptr;
+}
+
+namespace {
+
+// Fill the descriptors of every pair in the staging area.  Pairs without a usable table
+// get tab_len 0 (their walk ends after the key-0 cells, and k1 = inf finishes every node).
+void fill_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L, const gammax_problem_t* probs,
+                const float* const* refs, const float* const* evals, float* const* gammas,
+                const gammax_options_t& opt, const std::vector<int>& learned, const std::vector<int>& lanes,
+                const std::vector<int>& order, bool cap_radius) {
+    BatchPrepPair* pp = (BatchPrepPair*)(b->host + L.o_prep);
+    BatchSearchPair* sp = (BatchSearchPair*)(b->host + L.o_search);
+    uint2* items = (uint2*)(b->host + L.o_items);
+    std::memset(b->host, 0, (size_t)L.h_desc);
+    Scalars* d_sc = (Scalars*)(b->arena + L.o_sc);
+    int red0 = 0, tile0 = 0;
+    for (int i = 0; i < L.n; ++i) {
+        const gammax_problem_t* p = &probs[i];
+        BatchPrepPair& P = pp[i];
+        uint32_t* work = (uint32_t*)(b->arena + L.o_work[i]);
+        uint32_t* blk = (uint32_t*)(b->arena + L.o_blk[i]);
+        P.pa.ref = refs[i];
+        P.pa.ev = evals[i];
+        P.pa.gamma = gammas[i];
+        P.pa.n = L.nodes[i];
+        P.pa.thr = (float)p->dose_threshold;
+        P.pa.dd = (float)p->dd;
+        P.pa.local = p->norm == GAMMAX_LOCAL ? 1 : 0;
+        P.pa.sc = &d_sc[i];
+        P.pa.part = (uint32_t*)(b->arena + L.o_part[i]);
+        P.pa.blockcnt = blk;
+        P.pa.blockmax = blk + L.tiles[i];
+        P.pa.nodes = work + W_NODES * L.nodes[i];
+        P.pa.sums = (BlockSums*)(b->arena + L.o_sums[i]);
+        P.nb_red = (int)L.red[i];
+        P.ntiles = (int)L.tiles[i];
+        P.red0 = red0;
+        P.tile0 = tile0;
+        red0 += P.nb_red;
+        tile0 += P.ntiles;
+
+        const BatchTable& t = b->tabs[i];
+        const bool tv = t.valid;
+        const float r2_cap = (tv && cap_radius) ? round_down_float(t.geom.r2_cap) : INFINITY;
+        BatchSearchPair& S = sp[i];
+        S.sa = make_search_args(p, opt, refs[i], evals[i], gammas[i], &d_sc[i], t.tab, tv ? (int)t.len : 0,
+                                tv ? t.k1 : INFINITY, r2_cap, work, L.nodes[i], P.pa.sums,
+                                learned[i] ? (const float*)(b->arena + L.o_yhat[i]) : nullptr);
+        S.sa.tail_key = 0;
+        S.zg = make_zero_geo(p);
+        S.ndim = p->ndim;
+        S.guarded = (opt.precision == GAMMAX_PREC_GUARDED && p->ndim == 3) ? 1 : 0;
+        S.spec = (learned[i] && opt.radius_mode == GAMMAX_RADIUS_LEARNED) ? 1 : 0;
+        S.g_tail = lanes[i];
+        S.first = p->ndim == 3 ? 8 : 4;
+        S.r2_cap = r2_cap;
+    }
+    int k = 0;
+    for (int i : order)
+        for (int64_t blk = 0; blk < (L.nodes[i] + 255) / 256; ++blk) items[k++] = make_uint2((uint32_t)i, (uint32_t)blk);
+}
+
+gammax_status_t upload_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L, hipStream_t s) {
+    if ((int64_t)b->uploaded.size() == L.h_desc && std::memcmp(b->uploaded.data(), b->host, (size_t)L.h_desc) == 0)
+        return GAMMAX_OK;
+    HIPCHK(c, hipMemcpyAsync(b->arena, b->host, (size_t)L.h_desc, hipMemcpyHostToDevice, s));
+    b->uploaded.assign(b->host, b->host + L.h_desc);
+    return GAMMAX_OK;
+}
+
+// Queue the whole batch: prep, the network of the learned pairs, the search passes.
+gammax_status_t enqueue_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L, const gammax_problem_t* probs,
+                              const float* const* refs, const float* const* evals, const gammax_options_t& opt,
+                              const std::vector<int>& learned, bool prep, bool search, hipStream_t s) {
+    const BatchPrepPair* d_pp = (const BatchPrepPair*)(b->arena + L.o_prep);
+    const BatchSearchPair* d_sp = (const BatchSearchPair*)(b->arena + L.o_search);
+    unsigned long long* done = (unsigned long long*)(b->arena + L.o_done);
+    if (prep) HIPCHK(c, launch_batch_prep(d_pp, L.n, L.total_red, L.total_tiles, done + L.n, s));
+    if (!search) return GAMMAX_OK;
+    bool any_spec = false, any_guard = false;
+    for (int i = 0; i < L.n; ++i) {
+        if (learned[i]) {
+            const int o[3] = {(int)probs[i].shape[0], (int)probs[i].shape[1], (int)probs[i].shape[2]};
+            CnnWs w = cnn_layout(c->cnn_ws, o);
+            Scalars* sc = (Scalars*)(b->arena + L.o_sc) + i;
+            HIPCHK(c, launch_features(refs[i], evals[i], o, sc, w.feat, s));
+            HIPCHK(c, model_forward(const_cast<gammax_model*>(opt.model), w.feat, 1, o, w.a1, w.a2, w.a3,
+                                    (float*)(b->arena + L.o_yhat[i]), s));
+            any_spec = any_spec || opt.radius_mode == GAMMAX_RADIUS_LEARNED;
+        }
+        any_guard = any_guard || (opt.precision == GAMMAX_PREC_GUARDED && probs[i].ndim == 3);
+    }
+    const int dev_cus = b->cus > 0 ? b->cus : 256;
+    const int zero_blocks = std::max(1, std::min(L.n_items, dev_cus * 8));
+    const int tail_blocks = dev_cus * 4;
+    HIPCHK(c, launch_batch_search(d_sp, L.n, (const uint2*)(b->arena + L.o_items), L.n_items, zero_blocks,
+                                  tail_blocks, any_spec, any_guard, (uint32_t*)(b->arena + L.o_chunk0),
+                                  (uint32_t*)(b->arena + L.o_gsel), (BatchCtl*)(b->arena + L.o_ctl), done, s));
+    return GAMMAX_OK;
+}
+
+gammax_status_t read_batch_scalars(gammax_ctx* c, BatchState* b, const BatchLayout& L, hipStream_t s) {
+    HIPCHK(c, hipMemcpyAsync(b->host + L.h_sc, b->arena + L.o_sc, sizeof(Scalars) * L.n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(b->host + L.h_done, b->arena + L.o_done, sizeof(unsigned long long) * (L.n + 1),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return GAMMAX_OK;
+}
+
+gammax_status_t batch_errors(gammax_ctx* c, BatchState* b, const BatchLayout& L, const gammax_problem_t* probs) {
+    const Scalars* h = (const Scalars*)(b->host + L.h_sc);
+    for (int i = 0; i < L.n; ++i) {
+        if (h[i].flags & FLAG_NONFINITE)
+            return fail(c, GAMMAX_E_NONFINITE, "pair " + std::to_string(i) + ": a dose value is NaN or infinite");
+        if (probs[i].norm == GAMMAX_GLOBAL && !(ord_to_float(h[i].dmax_ord) > 0.0f))
+            return fail(c, GAMMAX_E_DOSE, "pair " + std::to_string(i) + ": max reference dose is not positive");
+    }
+    return GAMMAX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t* probs, const float* const* refs,
+                             const float* const* evals, float* const* gammas, const gammax_options_t* opt_in,
+                             gammax_result_t* results, void* stream) {
+    if (!c) return GAMMAX_E_NULL;
+    // Switched off: its first GPU run stopped making progress and the cause is not yet
+    // known.  GAMMAX_ENABLE_BATCH=1 turns it on for investigation.
+    const char* en = std::getenv("GAMMAX_ENABLE_BATCH");
+    if (!en || std::strcmp(en, "1") != 0)
+        return fail(c, GAMMAX_E_DEVICE, "gammax_batch is disabled (set GAMMAX_ENABLE_BATCH=1)");
+    if (n < 0) return fail(c, GAMMAX_E_PARAM, "n must be >= 0");
+    if (n == 0) return GAMMAX_OK;
+    if (!probs || !refs || !evals || !gammas || !results)
+        return fail(c, GAMMAX_E_NULL, "problems, dose, gamma and result arrays are required");
+    gammax_options_t opt;
+    if (opt_in) opt = *opt_in;
+    else gammax_options_default(&opt);
+    gammax_status_t st = check_options(c, &opt);
+    if (st != GAMMAX_OK) return st;
+    std::vector<int64_t> nn(n);
+    for (int i = 0; i < n; ++i) {
+        if ((st = check_problem(c, &probs[i], &nn[i])) != GAMMAX_OK)
+            return fail(c, st, "pair " + std::to_string(i) + ": " + c->err);
+        if (!refs[i] || !evals[i] || !gammas[i]) return fail(c, GAMMAX_E_NULL, "pair " + std::to_string(i) + ": null pointer");
+        if ((const float*)gammas[i] == refs[i] || (const float*)gammas[i] == evals[i])
+            return fail(c, GAMMAX_E_PARAM, "pair " + std::to_string(i) + ": gamma must not alias the doses");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (!c->batch) {
+        c->batch = new (std::nothrow) BatchState();
+        if (!c->batch) return fail(c, GAMMAX_E_NOMEM, "batch state");
+    }
+    BatchState* b = c->batch;
+    if ((int)b->tabs.size() < n) b->tabs.resize(n);
+    if (b->cus == 0) {
+        HIPCHK(c, hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, c->device));
+        HIPCHK(c, hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, c->device));
+    }
+
+    // which pairs use the network; cost order of the key-0 items (3D first, larger first)
+    std::vector<int> learned(n, 0), order(n);
+    int64_t cnn_need = 0;
+    for (int i = 0; i < n; ++i) {
+        learned[i] = uses_model(&probs[i], &opt) ? 1 : 0;
+        order[i] = i;
+        if (learned[i]) {
+            const int o[3] = {(int)probs[i].shape[0], (int)probs[i].shape[1], (int)probs[i].shape[2]};
+            cnn_need = std::max(cnn_need, cnn_layout(nullptr, o).bytes);
+        }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int z) {
+        const double ca = (double)nn[a] * (probs[a].ndim == 3 ? 8.0 : 2.0);
+        const double cz = (double)nn[z] * (probs[z].ndim == 3 ? 8.0 : 2.0);
+        return ca > cz;
+    });
+    const BatchLayout L = batch_layout(n, probs, learned, order);
+    if (L.arena > b->arena_cap || !b->arena) {
+        if ((st = grow(c, &b->arena, &b->arena_cap, L.arena)) != GAMMAX_OK) return st;
+        b->uploaded.clear();
+    }
+    if (L.host > b->host_cap || !b->host) {
+        if (b->host) (void)hipHostFree(b->host);
+        b->host = nullptr;
+        b->host_cap = 0;
+        HIPCHK(c, hipHostMalloc((void**)&b->host, (size_t)L.host, hipHostMallocDefault));
+        b->host_cap = L.host;
+    }
+    if (cnn_need > c->cnn_ws_cap && (st = grow(c, &c->cnn_ws, &c->cnn_ws_cap, cnn_need)) != GAMMAX_OK) return st;
+
+    // tail lanes per pair: fixed by the options, else tuned per shape class, else automatic
+    std::vector<uint64_t> cls(n);
+    std::vector<int> lanes(n, 0);
+    for (int i = 0; i < n; ++i) {
+        cls[i] = shape_class(&probs[i], nn[i]);
+        if (opt.tail_lanes > 0) lanes[i] = opt.tail_lanes;
+        else if (b->tune.count(cls[i])) lanes[i] = b->tune[cls[i]];
+    }
+
+    // tables: every pair's cached table must serve its geometry
+    bool tables_ok = true;
+    for (int i = 0; i < n; ++i) {
+        const TableGeom g = geom_of(&probs[i]);
+        if (!b->tabs[i].valid || !same_geom(b->tabs[i].geom, g)) tables_ok = false;
+    }
+
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (!tables_ok) {
+            // build path: prep, then the tables for the radii found
+            fill_batch(c, b, L, probs, refs, evals, gammas, opt, learned, lanes, order, false);
+            if ((st = upload_batch(c, b, L, s)) != GAMMAX_OK) return st;
+            if ((st = enqueue_batch(c, b, L, probs, refs, evals, opt, learned, true, false, s)) != GAMMAX_OK) return st;
+            if ((st = read_batch_scalars(c, b, L, s)) != GAMMAX_OK) return st;
+            if ((st = batch_errors(c, b, L, probs)) != GAMMAX_OK) return st;
+            const Scalars* h = (const Scalars*)(b->host + L.h_sc);
+            std::vector<float> r2(n);
+            for (int i = 0; i < n; ++i) r2[i] = u2f(h[i].r2_bits);
+            for (int i = 0; i < n; ++i) {
+                BatchTable& t = b->tabs[i];
+                const TableGeom g = geom_of(&probs[i]);
+                const bool fits = t.valid && same_geom(t.geom, g) && (double)r2[i] <= t.geom.r2_cap;
+                if (fits || h[i].n_masked == 0 || !(r2[i] > 0.0f)) continue;
+                TableGeom gb = g;
+                gb.r2_cap = (double)r2[i] * 1.5;
+                t.valid = false;
+                if ((st = build_rows(c, gb, &t.tab, &t.cap, &t.len, &t.k1, s)) != GAMMAX_OK) return st;
+                t.geom = gb;
+                t.valid = true;
+            }
+            tables_ok = true;
+            for (int i = 0; i < n; ++i) {
+                // a pair that needs no walk keeps an empty table for its geometry
+                if (!b->tabs[i].valid) {
+                    BatchTable& t = b->tabs[i];
+                    t.geom = geom_of(&probs[i]);
+                    t.geom.r2_cap = 0.0;
+                    t.len = 0;
+                    t.k1 = INFINITY;
+                    t.valid = true;
+                }
+            }
+        }
+
+        // autotune the tail layout of new shape classes (every timed run is a complete batch)
+        if (opt.autotune && opt.tail_lanes == 0) {
+            std::vector<uint64_t> todo;
+            for (int i = 0; i < n; ++i)
+                if (!b->tune.count(cls[i]) && std::find(todo.begin(), todo.end(), cls[i]) == todo.end())
+                    todo.push_back(cls[i]);
+            if (!todo.empty()) {
+                for (auto& e : b->ev)
+                    if (!e) HIPCHK(c, hipEventCreate(&e));
+                for (uint64_t k : todo) {
+                    float best_ms = INFINITY;
+                    int best_g = 0;
+                    for (int g : {0, 8, 16, 32, 64}) {
+                        for (int i = 0; i < n; ++i)
+                            if (cls[i] == k) lanes[i] = g;
+                        fill_batch(c, b, L, probs, refs, evals, gammas, opt, learned, lanes, order, true);
+                        if ((st = upload_batch(c, b, L, s)) != GAMMAX_OK) return st;
+                        HIPCHK(c, hipEventRecord(b->ev[0], s));
+                        if ((st = enqueue_batch(c, b, L, probs, refs, evals, opt, learned, true, true, s)) != GAMMAX_OK)
+                            return st;
+                        HIPCHK(c, hipEventRecord(b->ev[1], s));
+                        HIPCHK(c, hipEventSynchronize(b->ev[1]));
+                        const float ms = elapsed(b->ev[0], b->ev[1]);
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            best_g = g;
+                        }
+                    }
+                    b->tune[k] = best_g;
+                    for (int i = 0; i < n; ++i)
+                        if (cls[i] == k) lanes[i] = best_g;
+                }
+            }
+        }
+
+        // the batch itself: replayed from a graph when the same batch comes again
+        fill_batch(c, b, L, probs, refs, evals, gammas, opt, learned, lanes, order, true);
+        if ((st = upload_batch(c, b, L, s)) != GAMMAX_OK) return st;
+        std::vector<unsigned char> key(b->host, b->host + L.h_desc);
+        const unsigned char* gk = (const unsigned char*)&c->generation;
+        key.insert(key.end(), gk, gk + sizeof(c->generation));
+        key.insert(key.end(), learned.begin(), learned.end());
+        bool launched = false;
+        if (!c->graph_broken) {
+            if (!b->graph || key != b->graph_key) {
+                if (b->graph) (void)hipGraphExecDestroy(b->graph);
+                b->graph = nullptr;
+                if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                st = enqueue_batch(c, b, L, probs, refs, evals, opt, learned, true, true, c->cap_stream);
+                hipGraph_t g = nullptr;
+                const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+                if (st == GAMMAX_OK && e == hipSuccess && g &&
+                    hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0) == hipSuccess) {
+                    b->graph_key = key;
+                } else {
+                    b->graph = nullptr;
+                    (void)hipGetLastError();
+                }
+                if (g) (void)hipGraphDestroy(g);
+                if (st != GAMMAX_OK) return st;
+            }
+            if (b->graph) {
+                HIPCHK(c, hipGraphLaunch(b->graph, s));
+                launched = true;
+            }
+        }
+        if (!launched && (st = enqueue_batch(c, b, L, probs, refs, evals, opt, learned, true, true, s)) != GAMMAX_OK)
+            return st;
+        if ((st = read_batch_scalars(c, b, L, s)) != GAMMAX_OK) return st;
+        if ((st = batch_errors(c, b, L, probs)) != GAMMAX_OK) return st;
+        const Scalars* h = (const Scalars*)(b->host + L.h_sc);
+        bool short_tab = false;
+        for (int i = 0; i < n; ++i) {
+            if (h[i].flags & FLAG_TABLE_SHORT) {
+                short_tab = true;
+                b->tabs[i].valid = false;
+            }
+        }
+        if (short_tab) {
+            tables_ok = false;   // a radius outgrew its table: rebuild those and run again
+            continue;
+        }
+        const int rate_khz = b->clock_khz;
+        const unsigned long long* done = (const unsigned long long*)(b->host + L.h_done);
+        for (int i = 0; i < n; ++i) {
+            gammax_result_t& r = results[i];
+            std::memset(&r, 0, sizeof(r));
+            const Scalars& hs = h[i];
+            r.n_evaluated = hs.n_masked;
+            r.n_pass = hs.n_pass;
+            r.n_borderline = hs.n_border;
+            r.n_fp64_tets = hs.n_fp64;
+            r.n_cells = hs.n_cells;
+            r.n_tail = hs.n_tail;
+            r.n_guarded = hs.n_guard;
+            r.n_fallback = hs.n_fallback;
+            r.pass_rate = hs.n_masked ? (double)hs.n_pass / (double)hs.n_masked : NAN;
+            r.max_gamma = std::sqrt(u2f(hs.maxg2_bits));
+            r.dose_max = ord_to_float(hs.dmax_ord);
+            r.search_radius = std::sqrt(u2f(hs.r2_bits));
+            r.table_len = (int32_t)b->tabs[i].len;
+            r.ms_done = (done[i] > done[n] && rate_khz > 0) ? (float)((double)(done[i] - done[n]) / rate_khz) : 0.0f;
+        }
+        return GAMMAX_OK;
+    }
+    return fail(c, GAMMAX_E_DEVICE, "batch: a cell table fell short twice");
+}
+
+gammax_status_t gammax_tune_save(const gammax_ctx_t* c, const char* path) {
+    if (!c || !path) return GAMMAX_E_NULL;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return GAMMAX_E_PARAM;
+    if (c->batch)
+        for (const auto& kv : c->batch->tune) std::fprintf(f, "%llu %d\n", (unsigned long long)kv.first, kv.second);
+    std::fclose(f);
+    return GAMMAX_OK;
+}
+
+gammax_status_t gammax_tune_load(gammax_ctx_t* c, const char* path) {
+    if (!c || !path) return GAMMAX_E_NULL;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(c, GAMMAX_E_PARAM, std::string("cannot open ") + path);
+    if (!c->batch) {
+        c->batch = new (std::nothrow) BatchState();
+        if (!c->batch) {
+            std::fclose(f);
+            return GAMMAX_E_NOMEM;
+        }
+    }
+    unsigned long long k = 0;
+    int g = 0;
+    gammax_status_t st = GAMMAX_OK;
+    while (std::fscanf(f, "%llu %d", &k, &g) == 2) {
+        if (!(g == 0 || g == 1 || g == 8 || g == 16 || g == 32 || g == 64)) {
+            st = fail(c, GAMMAX_E_PARAM, "bad lanes value in tuning file");
+            break;
+        }
+        c->batch->tune[(uint64_t)k] = g;
+    }
+    std::fclose(f);
+    return st;
 }
 
 }  // extern "C"

@@ -102,6 +102,7 @@ struct PrepArgs {
 };
 
 int64_t prep_tiles(int64_t n);
+int batch_reduce_blocks(int64_t n);   // dose-max blocks of an n-node pair
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 // Only the dose maximum, the finiteness flag, the threshold value and the global 1/dD
 // (uses ref, ev, n, thr, dd, sc, part).
@@ -195,5 +196,42 @@ struct SearchPlan {
 };
 int64_t search_sums_needed(uint32_t M);
 hipError_t launch_search(const SearchArgs& a, const SearchPlan& plan, hipStream_t s);
+
+// ---- batches of dose pairs -------------------------------------------------------------
+//
+// Every phase of the pipeline runs once for all pairs of a batch: a pair's blocks are
+// found from per-pair block prefixes (prep), from a cost-ordered list of (pair, block)
+// items that persistent blocks stride over (the key-0 pass), or from a queue of
+// (pair, chunk) items handed out by an atomic counter (the tail walks and the guard pass).
+
+struct BatchPrepPair {
+    PrepArgs pa;
+    int nb_red;              // dose-max blocks of this pair
+    int ntiles;              // prep tiles of this pair
+    int red0, tile0;         // first block of this pair in the dose-max and tile grids
+};
+
+struct BatchSearchPair {
+    SearchArgs sa;           // sa.tab / sa.tab_len: this pair's cell table
+    ZeroGeo zg;
+    int ndim, guarded, spec; // spec: learned radius on this pair
+    int g_tail;              // lanes per node in the tail walk (8..64), 0 = from the tail length
+    int first;               // first table row after the key-0 cells
+    float r2_cap;            // this pair's table holds every cell with key^2 < r2_cap
+};
+
+// Device control block of a batch (zeroed by the launches themselves).
+struct BatchCtl {
+    uint32_t head[4];        // queue counters: tail, fallback, guard
+    uint32_t pad[4];
+};
+
+hipError_t launch_batch_prep(const BatchPrepPair* pairs, int n, int total_red, int total_tiles,
+                             unsigned long long* t0, hipStream_t s);
+// chunk0 / gsel: 3 * (n + 1) and 3 * n words of scratch; done: n + 1 u64 (completion clocks)
+hipError_t launch_batch_search(const BatchSearchPair* pairs, int n, const uint2* items, int n_items,
+                               int zero_blocks, int tail_blocks, bool any_spec, bool any_guard,
+                               uint32_t* chunk0, uint32_t* gsel, BatchCtl* ctl, unsigned long long* done,
+                               hipStream_t s);
 
 }  // namespace gammax

@@ -47,11 +47,11 @@ __device__ __forceinline__ void block_max_or(uint32_t& m, uint32_t& f) {
     __syncthreads();
 }
 
-// 1. dose maximum and finiteness of both doses, one partial per block.
-__global__ __launch_bounds__(PREP_THREADS) void k_dose_max(PrepArgs a) {
+// 1. dose maximum and finiteness of both doses, one partial per block (vb of vgrid).
+__device__ __forceinline__ void dose_max_body(const PrepArgs& a, int vb, int vgrid) {
     uint32_t best = 0u, bad = 0u;
-    const int64_t stride = (int64_t)gridDim.x * PREP_THREADS;
-    for (int64_t i = (int64_t)blockIdx.x * PREP_THREADS + threadIdx.x; i < a.n; i += stride) {
+    const int64_t stride = (int64_t)vgrid * PREP_THREADS;
+    for (int64_t i = (int64_t)vb * PREP_THREADS + threadIdx.x; i < a.n; i += stride) {
         const float r = a.ref[i];
         const float e = a.ev[i];
         bad |= (!isfinite(r) || !isfinite(e)) ? 1u : 0u;
@@ -59,10 +59,12 @@ __global__ __launch_bounds__(PREP_THREADS) void k_dose_max(PrepArgs a) {
     }
     block_max_or(best, bad);
     if (threadIdx.x == 0) {
-        a.part[blockIdx.x] = best;
-        a.part[MAX_BLOCKS + blockIdx.x] = bad;
+        a.part[vb] = best;
+        a.part[MAX_BLOCKS + vb] = bad;
     }
 }
+
+__global__ __launch_bounds__(PREP_THREADS) void k_dose_max(PrepArgs a) { dose_max_body(a, blockIdx.x, gridDim.x); }
 
 // 1b. dose maximum and the global 1/dD only (no mask, no compaction): one block reduces
 // the partials of k_dose_max.
@@ -88,7 +90,7 @@ __device__ __forceinline__ bool node_masked(float dr, float thr_val, int local) 
 
 // 2. every block: the dose maximum from the partials, then per tile the masked count, max
 // gamma0^2 and -1 for unmasked nodes.  Block 0 stores the scalars of this map.
-__global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a, int nb_red) {
+__device__ __forceinline__ void prep_count_body(const PrepArgs& a, int nb_red, int vb) {
     uint32_t dm = 0u, bad = 0u;
     for (int j = threadIdx.x; j < nb_red; j += PREP_THREADS) {
         dm = max(dm, a.part[j]);
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a, int nb_
     const float dmax = ord_to_float(dm);
     const float thr_val = a.thr * dmax;
     const float inv_dd_g = 1.0f / (a.dd * dmax);
-    if (blockIdx.x == 0) {
+    if (vb == 0) {
         for (int j = threadIdx.x; j < SUM_BINS; j += PREP_THREADS) a.sums[j] = BlockSums{};
         if (threadIdx.x == 0) {
             Scalars* sc = a.sc;
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a, int nb_
             sc->n_cells = 0ull;
         }
     }
-    const int64_t base = (int64_t)blockIdx.x * PREP_TILE;
+    const int64_t base = (int64_t)vb * PREP_TILE;
     uint32_t cnt = 0u, best = 0u;
 #pragma unroll
     for (int k = 0; k < PREP_ITEMS; ++k) {
@@ -143,13 +145,17 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a, int nb_
     if (threadIdx.x == 0) {
         uint32_t c = 0u;
         for (int j = 0; j < PREP_THREADS / WAVE; ++j) c += s_cnt[j];
-        a.blockcnt[blockIdx.x] = c;
-        a.blockmax[blockIdx.x] = best;
+        a.blockcnt[vb] = c;
+        a.blockmax[vb] = best;
     }
 }
 
+__global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a, int nb_red) {
+    prep_count_body(a, nb_red, blockIdx.x);
+}
+
 // 3. one block: exclusive scan of the tile counts in place, M and R^2.
-__global__ __launch_bounds__(PREP_THREADS) void k_prep_scan(PrepArgs a, int nb) {
+__device__ __forceinline__ void prep_scan_body(const PrepArgs& a, int nb) {
     __shared__ uint32_t s_wave[PREP_THREADS / WAVE];
     __shared__ uint32_t s_carry;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
@@ -185,10 +191,12 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_scan(PrepArgs a, int nb) 
     }
 }
 
+__global__ __launch_bounds__(PREP_THREADS) void k_prep_scan(PrepArgs a, int nb) { prep_scan_body(a, nb); }
+
 // 3. the masked nodes in grid order.
-__global__ __launch_bounds__(PREP_THREADS) void k_prep_emit(PrepArgs a) {
+__device__ __forceinline__ void prep_emit_body(const PrepArgs& a, int vb) {
     const float thr_val = a.sc->thr_val;
-    const int64_t base = (int64_t)blockIdx.x * PREP_TILE;
+    const int64_t base = (int64_t)vb * PREP_TILE;
     __shared__ uint32_t s_wave[PREP_ITEMS][PREP_THREADS / WAVE];
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
@@ -202,7 +210,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_emit(PrepArgs a) {
         if (lane == 0) s_wave[k][w] = (uint32_t)__popcll(bal[k]);
     }
     __syncthreads();
-    uint32_t run = a.blockcnt[blockIdx.x];
+    uint32_t run = a.blockcnt[vb];
 #pragma unroll
     for (int k = 0; k < PREP_ITEMS; ++k) {
         uint32_t off = run, tot = 0u;
@@ -215,6 +223,8 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_emit(PrepArgs a) {
         run += tot;
     }
 }
+
+__global__ __launch_bounds__(PREP_THREADS) void k_prep_emit(PrepArgs a) { prep_emit_body(a, blockIdx.x); }
 
 __global__ __launch_bounds__(256) void k_pass_count(const float* __restrict__ g, int64_t n,
                                                     unsigned long long* counts) {
@@ -240,6 +250,35 @@ __global__ void k_zero3(unsigned long long* c) {
     if (threadIdx.x < 3) c[threadIdx.x] = 0ull;
 }
 
+// Batches: the pair that owns block b of a grid laid out by per-pair prefixes.
+__device__ __forceinline__ int batch_pair_of(const BatchPrepPair* P, int n, int b, bool tiles) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((tiles ? P[mid].tile0 : P[mid].red0) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(PREP_THREADS) void k_batch_dose_max(const BatchPrepPair* P, int n,
+                                                                  unsigned long long* t0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *t0 = wall_clock64();
+    const int p = batch_pair_of(P, n, blockIdx.x, false);
+    dose_max_body(P[p].pa, blockIdx.x - P[p].red0, P[p].nb_red);
+}
+__global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_count(const BatchPrepPair* P, int n) {
+    const int p = batch_pair_of(P, n, blockIdx.x, true);
+    prep_count_body(P[p].pa, P[p].nb_red, blockIdx.x - P[p].tile0);
+}
+__global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_scan(const BatchPrepPair* P) {
+    prep_scan_body(P[blockIdx.x].pa, P[blockIdx.x].ntiles);
+}
+__global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_emit(const BatchPrepPair* P, int n) {
+    const int p = batch_pair_of(P, n, blockIdx.x, true);
+    prep_emit_body(P[p].pa, blockIdx.x - P[p].tile0);
+}
+
 int reduce_blocks(int64_t n) {
     int64_t b = (n + PREP_THREADS * 8 - 1) / (PREP_THREADS * 8);
     if (b > MAX_BLOCKS) b = MAX_BLOCKS;
@@ -259,6 +298,18 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_prep_emit, dim3((unsigned)nb), dim3(PREP_THREADS), 0, s, a);
     return hipGetLastError();
 }
+
+hipError_t launch_batch_prep(const BatchPrepPair* pairs, int n, int total_red, int total_tiles,
+                             unsigned long long* t0, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_dose_max, dim3(total_red), dim3(PREP_THREADS), 0, s, pairs, n, t0);
+    hipLaunchKernelGGL(k_batch_prep_count, dim3(total_tiles), dim3(PREP_THREADS), 0, s, pairs, n);
+    hipLaunchKernelGGL(k_batch_prep_scan, dim3(n), dim3(PREP_THREADS), 0, s, pairs);
+    hipLaunchKernelGGL(k_batch_prep_emit, dim3(total_tiles), dim3(PREP_THREADS), 0, s, pairs, n);
+    return hipGetLastError();
+}
+
+int batch_reduce_blocks(int64_t n) { return reduce_blocks(n); }
 
 hipError_t launch_dose_scalars(const PrepArgs& a, hipStream_t s) {
     const int nbr = reduce_blocks(a.n);

@@ -345,7 +345,7 @@ __device__ __forceinline__ T cell2(const T* g, const Geo<T>& G, const InvS2<T>& 
 
 // Per-block reduction of the counts, added into one of SUM_BINS partial slots (blocks
 // spread over the slots, so no address sees more than a few hundred atomics).
-__device__ __forceinline__ void block_sums(BlockSums* bins, uint32_t npass, uint32_t nborder,
+__device__ __forceinline__ void block_sums(BlockSums* bins, uint32_t vb, uint32_t npass, uint32_t nborder,
                                            uint32_t nfp64, uint32_t ncells, uint32_t gm) {
     __shared__ uint32_t s[5][SEARCH_THREADS / WAVE];
     for (int o = WAVE / 2; o > 0; o >>= 1) {
@@ -374,7 +374,7 @@ __device__ __forceinline__ void block_sums(BlockSums* bins, uint32_t npass, uint
             c += s[3][j];
             m = max(m, s[4][j]);
         }
-        BlockSums* out = &bins[blockIdx.x & (SUM_BINS - 1)];
+        BlockSums* out = &bins[vb & (SUM_BINS - 1)];
         if (p) atomicAdd(&out->pass, p);
         if (b) atomicAdd(&out->border, b);
         if (f) atomicAdd(&out->fp64, f);
@@ -444,14 +444,15 @@ __device__ __forceinline__ int resume_row(const TabEntry* tab, int n, int first,
 }
 
 // Pass A in 3D.  MODE 0: FP32; MODE 1: FP32 and flag ill-conditioned tetrahedra.
+// vb: the block's index in the node list (256 nodes each).
 template <int MODE>
-__global__ __launch_bounds__(SEARCH_THREADS) void k_zero3(SearchArgs a, ZeroGeo zg, BlockSums* sums) {
+__device__ __forceinline__ void zero3_body(const SearchArgs& a, const ZeroGeo& zg, BlockSums* sums, uint32_t vb) {
     constexpr int GMODE = MODE == 1 ? 1 : 0;
     const uint32_t M = a.sc->n_masked;
-    if (blockIdx.x * SEARCH_THREADS >= M) {   // grid sized for every grid node; M is on the device
+    if (vb * SEARCH_THREADS >= M) {   // grids are sized for every grid node; M is on the device
         return;
     }
-    const uint32_t i = blockIdx.x * SEARCH_THREADS + threadIdx.x;
+    const uint32_t i = vb * SEARCH_THREADS + threadIdx.x;
     const bool live = i < M;
     const int nx = a.nx, ny = a.ny, nz = a.nz, sxy = nx * ny;
     const int node = live ? (int)a.nodes[i] : 0;
@@ -520,17 +521,21 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_zero3(SearchArgs a, ZeroGeo 
         const uint32_t gpos = block_append(to_guard, &a.sc->n_guard);
         if (to_guard) a.guard_list[gpos] = (uint32_t)node;
     }
-    block_sums(sums, npass, nborder, 0u, ncells, gm);
+    block_sums(sums, vb, npass, nborder, 0u, ncells, gm);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(SEARCH_THREADS) void k_zero3(SearchArgs a, ZeroGeo zg, BlockSums* sums) {
+    zero3_body<MODE>(a, zg, sums, blockIdx.x);
 }
 
 // Pass A in 2D (4 zero-key cells, 3x3 neighbourhood).
-template <int MODE>
-__global__ __launch_bounds__(SEARCH_THREADS) void k_zero2(SearchArgs a, ZeroGeo zg, BlockSums* sums) {
+__device__ __forceinline__ void zero2_body(const SearchArgs& a, const ZeroGeo& zg, BlockSums* sums, uint32_t vb) {
     const uint32_t M = a.sc->n_masked;
-    if (blockIdx.x * SEARCH_THREADS >= M) {
+    if (vb * SEARCH_THREADS >= M) {
         return;
     }
-    const uint32_t i = blockIdx.x * SEARCH_THREADS + threadIdx.x;
+    const uint32_t i = vb * SEARCH_THREADS + threadIdx.x;
     const bool live = i < M;
     const int nx = a.nx, ny = a.ny;
     const int node = live ? (int)a.nodes[i] : 0;
@@ -583,7 +588,12 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_zero2(SearchArgs a, ZeroGeo 
         a.tail_key_arr[pos] = tail_sort_key(a, node, F0, F);
         a.tail_pos[pos] = pos;
     }
-    block_sums(sums, npass, nborder, 0u, ncells, gm);
+    block_sums(sums, vb, npass, nborder, 0u, ncells, gm);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(SEARCH_THREADS) void k_zero2(SearchArgs a, ZeroGeo zg, BlockSums* sums) {
+    zero2_body(a, zg, sums, blockIdx.x);
     (void)MODE;
 }
 
@@ -690,7 +700,7 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_zero_group(SearchArgs a, Zer
             if (to_guard) a.guard_list[gpos] = (uint32_t)node;
         }
     }
-    block_sums(sums, npass, nborder, 0u, cells, gm);
+    block_sums(sums, blockIdx.x, npass, nborder, 0u, cells, gm);
 }
 
 // The walk.  TAIL: items are tail positions, the walk starts at row `first` with the bound
@@ -699,11 +709,11 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_zero_group(SearchArgs a, Zer
 // spec (TAIL only): 0 plain; 1 speculative (bound min(gamma^2, (f gamma_hat)^2); a node
 // whose gamma^2 stays above (f gamma_hat)^2 is queued on the fallback list instead of
 // finished); 2 fallback (the plain walk from the first row at or beyond f gamma_hat).
+// vb / vgrid: the block's index and the number of blocks striding over the list.
 template <int DIM, int MODE, bool TAIL>
-__global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const TabEntry* __restrict__ tab,
-                                                         const uint32_t* __restrict__ order,
-                                                         const uint32_t* __restrict__ count, int first,
-                                                         int spec, BlockSums* sums) {
+__device__ __forceinline__ void walk_body(const SearchArgs& a, const TabEntry* __restrict__ tab,
+                                          const uint32_t* __restrict__ order, const uint32_t* __restrict__ count,
+                                          int first, int spec, BlockSums* sums, uint32_t vb, uint32_t vgrid) {
     using T = typename std::conditional<MODE == 3, double, float>::type;
     constexpr int GMODE = DIM == 3 ? (MODE == 1 ? 1 : (MODE == 2 ? 2 : 0)) : 0;
     const uint32_t M = *count;
@@ -716,11 +726,11 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const Tab
                                   MODE == 3 ? (T)(a.sy * a.sy) : (T)a.s2y,
                                   DIM == 3 ? (MODE == 3 ? (T)(a.sz * a.sz) : (T)a.s2z) : T(0));
     const double sx2d = a.sx * a.sx, sy2d = a.sy * a.sy, sz2d = a.sz * a.sz;
-    const uint32_t stride = gridDim.x * SEARCH_THREADS;
+    const uint32_t stride = vgrid * SEARCH_THREADS;
     uint32_t cells = 0, n_fp64 = 0, gm = 0, npass = 0, nborder = 0;
 
     // the loop bound is uniform per wave, so every lane reaches the block-wide calls below
-    const uint32_t wave0 = blockIdx.x * SEARCH_THREADS + (threadIdx.x & ~(WAVE - 1));
+    const uint32_t wave0 = vb * SEARCH_THREADS + (threadIdx.x & ~(WAVE - 1));
     const uint32_t iters = wave0 < M ? (M - wave0 + stride - 1) / stride : 0u;
     uint32_t it_max = iters;
     // block-uniform trip count (all waves of a block take part in block_append)
@@ -849,7 +859,15 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const Tab
             }
         }
     }
-    block_sums(sums, npass, nborder, n_fp64, cells, gm);
+    block_sums(sums, vb, npass, nborder, n_fp64, cells, gm);
+}
+
+template <int DIM, int MODE, bool TAIL>
+__global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const TabEntry* __restrict__ tab,
+                                                         const uint32_t* __restrict__ order,
+                                                         const uint32_t* __restrict__ count, int first,
+                                                         int spec, BlockSums* sums) {
+    walk_body<DIM, MODE, TAIL>(a, tab, order, count, first, spec, sums, blockIdx.x, gridDim.x);
 }
 
 // Pass B with G lanes per node: the G lanes of a group take G consecutive table rows of
@@ -863,10 +881,10 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const Tab
 // one narrow groups (fewer rows past the break).
 // spec: as in k_walk (1 speculative, 2 fallback from the first row at or beyond f gamma_hat).
 template <int DIM, int MODE>
-__global__ __launch_bounds__(SEARCH_THREADS) void k_tail_group(SearchArgs a, const TabEntry* __restrict__ tab,
-                                                               const uint32_t* __restrict__ order,
-                                                               const uint32_t* __restrict__ count, int first,
-                                                               int g_req, int spec, BlockSums* sums) {
+__device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEntry* __restrict__ tab,
+                                                const uint32_t* __restrict__ order,
+                                                const uint32_t* __restrict__ count, int first, int g_req,
+                                                int spec, BlockSums* sums, uint32_t vb, uint32_t vgrid) {
     constexpr int GMODE = (DIM == 3 && MODE == 1) ? 1 : 0;
     const uint32_t M = *count;
     int G = g_req;
@@ -885,8 +903,8 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_tail_group(SearchArgs a, con
     uint32_t dummy_fp64 = 0;
 
     // block-uniform trip count
-    for (uint32_t base = blockIdx.x * GROUPS; base < M; base += gridDim.x * GROUPS) {
-        const uint32_t i = base + threadIdx.x / G;
+    for (uint64_t base = (uint64_t)vb * GROUPS; base < M; base += (uint64_t)vgrid * GROUPS) {
+        const uint32_t i = (uint32_t)base + threadIdx.x / G;
         const bool live = i < M;
         const uint32_t item = live ? order[i] : 0u;
         const int node = live ? (int)a.tail_node[item] : 0;
@@ -994,13 +1012,21 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_tail_group(SearchArgs a, con
             }
         }
     }
-    block_sums(sums, npass, nborder, 0u, cells, gm);
+    block_sums(sums, vb, npass, nborder, 0u, cells, gm);
+}
+
+template <int DIM, int MODE>
+__global__ __launch_bounds__(SEARCH_THREADS) void k_tail_group(SearchArgs a, const TabEntry* __restrict__ tab,
+                                                               const uint32_t* __restrict__ order,
+                                                               const uint32_t* __restrict__ count, int first,
+                                                               int g_req, int spec, BlockSums* sums) {
+    tail_group_body<DIM, MODE>(a, tab, order, count, first, g_req, spec, sums, blockIdx.x, gridDim.x);
 }
 
 // One block: sum the per-block partial counts into the scalars, and flag a cell table
 // that does not reach the search radius (the host then rebuilds it and runs again).
-__global__ __launch_bounds__(SEARCH_THREADS) void k_finalize(const BlockSums* __restrict__ sums, int n,
-                                                             Scalars* sc, float r2_cap) {
+__device__ __forceinline__ void finalize_body(const BlockSums* __restrict__ sums, int n, Scalars* sc,
+                                              float r2_cap) {
     if (threadIdx.x == 0 && u2f(sc->r2_bits) > r2_cap && sc->n_masked > 0) sc->flags |= FLAG_TABLE_SHORT;
     unsigned long long p = 0, b = 0, f = 0, c = 0;
     uint32_t m = 0;
@@ -1033,6 +1059,11 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_finalize(const BlockSums* __
         sc->n_cells = s[3][0];
         sc->maxg2_bits = sm[0];
     }
+}
+
+__global__ __launch_bounds__(SEARCH_THREADS) void k_finalize(const BlockSums* __restrict__ sums, int n,
+                                                             Scalars* sc, float r2_cap) {
+    finalize_body(sums, n, sc, r2_cap);
 }
 
 constexpr unsigned kTailBlocks = 1024;   // grid-stride blocks of the tail walk
@@ -1085,7 +1116,135 @@ unsigned tail_pass(const SearchArgs& a, const SearchPlan& p, const uint32_t* ord
     return gb;
 }
 
+// ---- batches ------------------------------------------------------------------------
+
+// One pass over a single block of work: a list whose blocks stride by this many blocks is
+// walked once (the queue hands out every chunk exactly once).
+constexpr uint32_t kOnePass = 1u << 23;
+
+// Lanes per node of a tail walk over m nodes when none is fixed (as in k_tail_group).
+__device__ __forceinline__ int auto_lanes(uint32_t m) {
+    int G = 64;
+    while (G > 8 && (uint64_t)m * (uint64_t)G > (1ull << 19)) G >>= 1;
+    return G;
+}
+
+__device__ __forceinline__ void mark_done(unsigned long long* done, int p) {
+    if (threadIdx.x == 0) atomicMax(&done[p], (unsigned long long)wall_clock64());
+}
+
+// The key-0 pass of every pair: persistent blocks stride over the cost-ordered items
+// (pair, block of 256 nodes).  Items past a pair's M return at once.
+__global__ __launch_bounds__(SEARCH_THREADS) void k_batch_zero(const BatchSearchPair* __restrict__ pairs,
+                                                               const uint2* __restrict__ items, int n_items,
+                                                               unsigned long long* done) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const uint2 w = items[it];
+        const BatchSearchPair& P = pairs[w.x];
+        if (P.ndim == 3) {
+            if (P.guarded) zero3_body<1>(P.sa, P.zg, P.sa.sums, w.y);
+            else zero3_body<0>(P.sa, P.zg, P.sa.sums, w.y);
+        } else {
+            zero2_body(P.sa, P.zg, P.sa.sums, w.y);
+        }
+        mark_done(done, (int)w.x);
+    }
+}
+
+// Chunk counts of a queue phase: 0 tail (spec 1 on learned pairs), 1 fallback, 2 guard.
+// One block; also fixes each pair's lanes per node and clears the queue counter.
+__global__ void k_batch_chunks(const BatchSearchPair* __restrict__ pairs, int n, int phase, uint32_t* chunk0,
+                               uint32_t* gsel, BatchCtl* ctl) {
+    if (threadIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (int p = 0; p < n; ++p) {
+        const BatchSearchPair& P = pairs[p];
+        uint32_t m = 0, per = SEARCH_THREADS;
+        if (phase == 2) {
+            m = P.guarded ? P.sa.sc->n_guard : 0u;
+        } else {
+            m = phase == 1 ? (P.spec ? P.sa.sc->n_fallback : 0u) : P.sa.sc->n_tail;
+            if (P.sa.tab_len <= P.first) m = 0;
+            const int G = P.g_tail ? P.g_tail : auto_lanes(m);
+            gsel[p] = (uint32_t)G;
+            per = SEARCH_THREADS / (uint32_t)G;
+        }
+        chunk0[p] = acc;
+        acc += (m + per - 1) / per;
+    }
+    chunk0[n] = acc;
+    ctl->head[phase] = 0u;
+}
+
+// A queue phase: blocks take (pair, chunk) items from an atomic counter until none is left.
+__global__ __launch_bounds__(SEARCH_THREADS) void k_batch_queue(const BatchSearchPair* __restrict__ pairs, int n,
+                                                                int phase, const uint32_t* __restrict__ chunk0,
+                                                                const uint32_t* __restrict__ gsel, BatchCtl* ctl,
+                                                                unsigned long long* done) {
+    __shared__ uint32_t s_it;
+    const uint32_t total = chunk0[n];
+    for (;;) {
+        if (threadIdx.x == 0) s_it = atomicAdd(&ctl->head[phase], 1u);
+        __syncthreads();
+        const uint32_t it = s_it;
+        __syncthreads();
+        if (it >= total) break;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (chunk0[mid] <= it) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchSearchPair& P = pairs[lo];
+        const uint32_t chunk = it - chunk0[lo];
+        if (phase == 2) {
+            walk_body<3, 2, false>(P.sa, P.sa.tab, P.sa.guard_list, &P.sa.sc->n_guard, 0, 0, P.sa.sums, chunk,
+                                   kOnePass);
+        } else {
+            const uint32_t* order = phase == 1 ? P.sa.fb_list : P.sa.tail_pos;
+            const uint32_t* count = phase == 1 ? &P.sa.sc->n_fallback : &P.sa.sc->n_tail;
+            const int spec = P.spec ? (phase == 1 ? 2 : 1) : 0;
+            const int G = (int)gsel[lo];
+            if (P.ndim == 3) {
+                if (P.guarded)
+                    tail_group_body<3, 1>(P.sa, P.sa.tab, order, count, P.first, G, spec, P.sa.sums, chunk, kOnePass);
+                else
+                    tail_group_body<3, 0>(P.sa, P.sa.tab, order, count, P.first, G, spec, P.sa.sums, chunk, kOnePass);
+            } else {
+                tail_group_body<2, 0>(P.sa, P.sa.tab, order, count, P.first, G, spec, P.sa.sums, chunk, kOnePass);
+            }
+        }
+        mark_done(done, lo);
+    }
+}
+
+__global__ __launch_bounds__(SEARCH_THREADS) void k_batch_finalize(const BatchSearchPair* __restrict__ pairs) {
+    const BatchSearchPair& P = pairs[blockIdx.x];
+    finalize_body(P.sa.sums, SUM_BINS, P.sa.sc, P.r2_cap);
+}
+
 }  // namespace
+
+hipError_t launch_batch_search(const BatchSearchPair* pairs, int n, const uint2* items, int n_items,
+                               int zero_blocks, int tail_blocks, bool any_spec, bool any_guard,
+                               uint32_t* chunk0, uint32_t* gsel, BatchCtl* ctl, unsigned long long* done,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n_items > 0)
+        hipLaunchKernelGGL(k_batch_zero, dim3(zero_blocks), dim3(SEARCH_THREADS), 0, s, pairs, items, n_items, done);
+    const int phases[3] = {0, 1, 2};
+    for (int ph : phases) {
+        if (ph == 1 && !any_spec) continue;
+        if (ph == 2 && !any_guard) continue;
+        uint32_t* c0 = chunk0 + ph * (n + 1);
+        uint32_t* gs = gsel + ph * n;
+        hipLaunchKernelGGL(k_batch_chunks, dim3(1), dim3(64), 0, s, pairs, n, ph, c0, gs, ctl);
+        hipLaunchKernelGGL(k_batch_queue, dim3(tail_blocks), dim3(SEARCH_THREADS), 0, s, pairs, n, ph, c0, gs, ctl,
+                           done);
+    }
+    hipLaunchKernelGGL(k_batch_finalize, dim3(n), dim3(SEARCH_THREADS), 0, s, pairs);
+    return hipGetLastError();
+}
 
 int64_t search_sums_needed(uint32_t) { return SUM_BINS; }
 
