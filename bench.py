@@ -37,7 +37,7 @@ TRAFFIC = {
     "3d_128x128x96_2.5mm": {
         "bytes": (15.62 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "740b2005b4861fd6fa1ae5638b1f6a2639b9a43ba51ae3483dcfabdb5ac33b29",
+        "sha256": "e0857a83348406326f88667718d16537933033024d4d688346b8408b78024b7d",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }
