@@ -135,7 +135,8 @@ typedef struct {
     float ms_guard;           /*   FP64-guarded redo of nodes that met an ill-conditioned
                                    tetrahedron (guarded precision, 3D), and the count reduction */
     uint64_t n_fallback;      /* learned radius: tail nodes not certified inside f * gamma_hat */
-    float ms_cnn;             /* timing = 1 only: features and CNN inference (learned radius) */
+    float ms_cnn;             /* timing = 1 only: the network at the tail nodes (learned radius),
+                                 between the key-0 pass and the sort */
     float ms_done;            /* gammax_batch only: time from the start of the batch until the
                                  last work item of this pair finished (device clock) */
 } gammax_result_t;
@@ -180,7 +181,8 @@ gammax_status_t gamma_map(const float *ref_dose, const float *eval_dose, int32_t
 /*
  * Stable ascending sort of n (key, value) pairs of uint32 in place on the device: the
  * LDS radix sort used for the DD sort (Algorithm A2 step 3) and for the cell table
- * (step 5).  Equal keys keep their input order.
+ * (step 5); up to 4096 pairs, the one-workgroup rank sort used for short tails.  Equal
+ * keys keep their input order.
  */
 gammax_status_t gammax_sort_pairs(gammax_ctx_t *ctx, uint32_t *keys_dev, uint32_t *vals_dev,
                                   int64_t n, void *stream);
@@ -259,6 +261,18 @@ gammax_status_t gammax_model_features(gammax_ctx_t *ctx, const gammax_problem_t 
 gammax_status_t gammax_model_predict(gammax_ctx_t *ctx, gammax_model_t *model,
                                      const gammax_problem_t *problem, const float *ref_dev,
                                      const float *eval_dev, float *y_dev, void *stream);
+
+/*
+ * Prediction at listed nodes only: y_dev[i] = log(gamma_hat + 0.01) at flat node index
+ * nodes_dev[i] (i < n), each from its own 9x9x9 patch (the values the whole-grid
+ * prediction gives there, up to the order of the last layer's FP32 sum).  This is how the
+ * learned radius is evaluated inside gammax_map: only at the nodes that walk past the
+ * key-0 cells.  3D only.  Synchronises.
+ */
+gammax_status_t gammax_model_predict_nodes(gammax_ctx_t *ctx, gammax_model_t *model,
+                                           const gammax_problem_t *problem, const float *ref_dev,
+                                           const float *eval_dev, const uint32_t *nodes_dev, int64_t n,
+                                           float *y_dev, void *stream);
 
 /*
  * Forward pass over nvol crops: feat_dev holds nvol volumes of (c0+8) x (c1+8) x (c2+8)

@@ -10,6 +10,7 @@ from ._abi import (  # noqa: F401
     Model,
     MODEL_NPARAM,
     model_features,
+    predict_nodes,
     GammaxError,
     build_table,
     context,

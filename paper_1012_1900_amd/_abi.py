@@ -396,6 +396,8 @@ _lib.gammax_model_features.restype = C.c_int
 _lib.gammax_model_features.argtypes = [_vp, C.POINTER(Problem), _vp, _vp, _vp, _vp]
 _lib.gammax_model_predict.restype = C.c_int
 _lib.gammax_model_predict.argtypes = [_vp, _vp, C.POINTER(Problem), _vp, _vp, _vp, _vp]
+_lib.gammax_model_predict_nodes.restype = C.c_int
+_lib.gammax_model_predict_nodes.argtypes = [_vp, _vp, C.POINTER(Problem), _vp, _vp, _vp, C.c_int64, _vp, _vp]
 _lib.gammax_model_forward.restype = C.c_int
 _lib.gammax_model_forward.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64), _vp, _vp, _vp]
 _lib.gammax_model_train_step.restype = C.c_int
@@ -496,6 +498,25 @@ class Model:
                                            ev.data_ptr(), y.data_ptr(), _vp(s.cuda_stream))
         ctx.check(st)
         return y
+
+
+def predict_nodes(model, ref, ev, spacing: Sequence[float], dd: float, nodes, dta: float = 3.0,
+                  ctx: Optional[Context] = None):
+    """y = log(gamma_hat + 0.01) at flat node indices ``nodes`` (int32 device tensor)."""
+    torch = _torch()
+    _dev_tensor(ref, "ref")
+    _dev_tensor(ev, "ev")
+    if nodes.dtype != torch.int32 or nodes.device != ref.device or not nodes.is_contiguous():
+        raise ValueError("nodes must be a contiguous int32 tensor on the doses' device")
+    ctx = ctx or context(ref.device.index or 0)
+    prob = make_problem(ref.shape, spacing, dd, dta, 0.1, False)
+    y = torch.empty(nodes.numel(), dtype=torch.float32, device=ref.device)
+    s = torch.cuda.current_stream(ref.device)
+    with torch.cuda.device(ref.device):
+        st = _lib.gammax_model_predict_nodes(ctx.handle, model.handle, C.byref(prob), ref.data_ptr(), ev.data_ptr(),
+                                             nodes.data_ptr(), nodes.numel(), y.data_ptr(), _vp(s.cuda_stream))
+    ctx.check(st)
+    return y
 
 
 def model_features(ref, ev, spacing: Sequence[float], dd: float, dta: float = 3.0,

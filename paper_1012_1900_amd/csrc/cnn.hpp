@@ -63,6 +63,12 @@ hipError_t launch_loss(const float* y, const float* gamma, int64_t n, float scal
 hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int n, float lr, float beta1,
                        float beta2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_pack(const float* w, int cin, int cout, int bwd, uint16_t* frag, hipStream_t s);
+// The network at the listed nodes only (their 9^3 patches): y[i] for node nodes[i], i < *count;
+// key (optional) receives the bits of gamma_hat.  n: grid shape, slowest first.
+hipError_t launch_cnn_tail(const float* ref, const float* ev, const int n[3], const Scalars* sc,
+                           const uint32_t* nodes, const uint32_t* count, int max_blocks, const uint16_t* const frag[3],
+                           const float* const bias[3], const float* w4, const float* b4, float* y, uint32_t* key,
+                           hipStream_t s);
 hipError_t launch_features(const float* ref, const float* ev, const int n[3], const Scalars* sc, uint16_t* feat,
                            hipStream_t s);
 

@@ -38,6 +38,7 @@ struct GraphKey {
     int32_t sort_mode, precision, tail_lanes, cell_lanes, timing, radius_mode;
     double cond_threshold, radius_factor;
     const void* model;
+    int32_t small_sort;
     uint64_t generation;   // bumped on every (re)allocation and table build
 };
 
@@ -89,6 +90,7 @@ struct gammax_ctx {
     float* yhat = nullptr;          // log(gamma_hat + 0.01) per grid node
     int64_t yhat_cap = 0;
     struct BatchState* batch = nullptr;   // gammax_batch state (created on first use)
+    uint64_t tail_hint = 0;         // tail length of the last map (picks the tail sort variant)
 };
 
 void destroy_batch(gammax_ctx* c);
@@ -348,9 +350,6 @@ bool uses_model(const gammax_problem_t* p, const gammax_options_t* o) {
            (o->radius_mode == GAMMAX_RADIUS_LEARNED || o->sort_mode == GAMMAX_SORT_PREDICTED);
 }
 
-// Queue the features and the CNN (after the prep, which provides the dose maximum and dD).
-gammax_status_t enqueue_cnn(gammax_ctx* c, const CallSetup& cs, hipStream_t s, bool timing);
-
 // Queue the compaction (Kernel 1).  ev0/ev1 (optional) bracket it.
 gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int64_t ntiles = prep_tiles(cs.n);
@@ -374,19 +373,38 @@ gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, 
     return GAMMAX_OK;
 }
 
-gammax_status_t enqueue_cnn(gammax_ctx* c, const CallSetup& cs, hipStream_t s, bool timing) {
-    if (!uses_model(cs.p, cs.opt)) return GAMMAX_OK;
-    if (timing) HIPCHK(c, hipEventRecord(c->ev[9], s));
-    const int o[3] = {(int)cs.p->shape[0], (int)cs.p->shape[1], (int)cs.p->shape[2]};
-    CnnWs w = cnn_layout(c->cnn_ws, o);
-    gammax_model* m = const_cast<gammax_model*>(cs.opt->model);
-    HIPCHK(c, launch_features(cs.ref, cs.ev, o, c->d_sc, w.feat, s));
-    HIPCHK(c, model_forward(m, w.feat, 1, o, w.a1, w.a2, w.a3, c->yhat, s));
-    if (timing) HIPCHK(c, hipEventRecord(c->ev[10], s));
-    return GAMMAX_OK;
+// The network at the nodes queued for the tail walk, queued right after the key-0 pass:
+// y per tail item into `y` and, for the predicted order, the sort keys.
+struct TailCnnHook {
+    const gammax_model* model;
+    const float* ref;
+    const float* ev;
+    int shape[3];
+    const Scalars* sc;
+    const uint32_t* nodes;
+    const uint32_t* count;
+    float* y;
+    uint32_t* key;
+    hipEvent_t ev0, ev1;     // optional timing
+    int blocks;
+};
+
+hipError_t tail_cnn_hook(void* user, hipStream_t s) {
+    const TailCnnHook& h = *static_cast<const TailCnnHook*>(user);
+    hipError_t e;
+    if (h.ev0 && (e = hipEventRecord(h.ev0, s)) != hipSuccess) return e;
+    gammax_model* m = const_cast<gammax_model*>(h.model);
+    const uint16_t* frag[3] = {frag_fwd(m, 0), frag_fwd(m, 1), frag_fwd(m, 2)};
+    const float* bias[3] = {layer_bias(m, 0), layer_bias(m, 1), layer_bias(m, 2)};
+    e = launch_cnn_tail(h.ref, h.ev, h.shape, h.sc, h.nodes, h.count, h.blocks, frag, bias, m->theta + CNN_OFF[3],
+                        layer_bias(m, 3), h.y, h.key, s);
+    if (e != hipSuccess) return e;
+    if (h.ev1 && (e = hipEventRecord(h.ev1, s)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
-// Queue the search (steps 3, 6, 7) over at most m_bound nodes with the cached table.
+constexpr int kTailCnnBlocks = 2048;   // grid-stride blocks of the network at the tail nodes
+
 // Search arguments of one pair.  work: the kWorkArrays node arrays, `stride` words apart.
 SearchArgs make_search_args(const gammax_problem_t* p, const gammax_options_t& opt, const float* ref,
                             const float* ev, float* gamma, Scalars* sc, const TabEntry* tab, int tab_len, float k1,
@@ -479,6 +497,24 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
     plan.tmp_keys = work_array(c, W_TMP_K);
     plan.tmp_vals = work_array(c, W_TMP_V);
     plan.hist = opt.sort_mode == GAMMAX_SORT_NONE ? nullptr : c->hist;
+    plan.small_sort = c->tail_hint <= (uint64_t)SMALL_SORT_CAP ? 1 : 0;
+    TailCnnHook hook{};
+    if (learned) {
+        hook.model = opt.model;
+        hook.ref = cs.ref;
+        hook.ev = cs.ev;
+        for (int i = 0; i < 3; ++i) hook.shape[i] = (int)p->shape[i];
+        hook.sc = c->d_sc;
+        hook.nodes = work_array(c, W_TAIL_NODE);
+        hook.count = &c->d_sc->n_tail;
+        hook.y = c->yhat;
+        hook.key = sa.tail_key == 2 ? work_array(c, W_TAIL_KEY) : nullptr;
+        hook.ev0 = timing ? c->ev[9] : nullptr;
+        hook.ev1 = timing ? c->ev[10] : nullptr;
+        hook.blocks = kTailCnnBlocks;
+        plan.after_zero = tail_cnn_hook;
+        plan.after_zero_user = &hook;
+    }
     if (timing) {
         HIPCHK(c, hipEventRecord(c->ev[4], s));
         plan.ev_shell_end = c->ev[5];
@@ -514,6 +550,7 @@ GraphKey key_of(gammax_ctx* c, const CallSetup& cs) {
     k.cond_threshold = cs.opt->cond_threshold;
     k.radius_factor = cs.opt->radius_factor;
     k.model = cs.opt->model;
+    k.small_sort = (cs.opt->sort_mode != GAMMAX_SORT_NONE && c->tail_hint <= (uint64_t)SMALL_SORT_CAP) ? 1 : 0;
     k.generation = c->generation;
     return k;
 }
@@ -533,7 +570,6 @@ gammax_status_t launch_graph(gammax_ctx* c, const CallSetup& cs, uint32_t m_boun
         HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         gammax_status_t st = enqueue_prep(c, cs, c->cap_stream, timing ? c->ev[0] : nullptr,
                                           timing ? c->ev[1] : nullptr);
-        if (st == GAMMAX_OK) st = enqueue_cnn(c, cs, c->cap_stream, timing);
         if (st == GAMMAX_OK) st = enqueue_search(c, cs, m_bound, r2_cap, c->cap_stream, timing);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -573,12 +609,16 @@ void fill_result(gammax_ctx* c, gammax_result_t* res, bool timing, float ms_tabl
         res->ms_prep = elapsed(c->ev[0], c->ev[1]);
         res->ms_table = ms_table;
         res->ms_search = elapsed(c->ev[4], c->ev[5]);
-        res->ms_sort = elapsed(c->ev[5], c->ev[6]);
+        // with the learned radius the network at the tail nodes runs between the key-0 pass
+        // and the sort (ms_cnn)
+        res->ms_sort = cnn ? elapsed(c->ev[10], c->ev[6]) : elapsed(c->ev[5], c->ev[6]);
         res->ms_tail = elapsed(c->ev[6], c->ev[7]);
         res->ms_guard = elapsed(c->ev[7], c->ev[8]);
         res->ms_cnn = cnn ? elapsed(c->ev[9], c->ev[10]) : 0.0f;
     }
     res->n_fallback = h.n_fallback;
+    // the next call sorts its tail with the rank sort if this one's would have fitted
+    c->tail_hint = h.sort_overflow ? (uint64_t)SMALL_SORT_CAP + 1 : h.n_tail;
 }
 
 gammax_status_t device_errors(gammax_ctx* c, bool local) {
@@ -712,12 +752,7 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
     if ((st = grow(c, &c->sums, &c->sums_cap, search_sums_needed((uint32_t)n))) != GAMMAX_OK) return st;
     if (timing && (st = ensure_events(c)) != GAMMAX_OK) return st;
     const bool learned = uses_model(p, &opt);
-    if (learned) {
-        const int o[3] = {(int)p->shape[0], (int)p->shape[1], (int)p->shape[2]};
-        CnnWs w;
-        if ((st = grow_cnn(c, o, &w)) != GAMMAX_OK) return st;
-        if ((st = grow(c, &c->yhat, &c->yhat_cap, n)) != GAMMAX_OK) return st;
-    }
+    if (learned && (st = grow(c, &c->yhat, &c->yhat_cap, n)) != GAMMAX_OK) return st;
 
     CallSetup cs{p, &opt, ref, ev, gamma, n};
     const TableGeom g = geom_of(p);
@@ -729,7 +764,6 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
         if (timing || c->graph_broken) {
             if ((st = enqueue_prep(c, cs, s, timing ? c->ev[0] : nullptr, timing ? c->ev[1] : nullptr)) != GAMMAX_OK)
                 return st;
-            if ((st = enqueue_cnn(c, cs, s, timing)) != GAMMAX_OK) return st;
             if ((st = enqueue_search(c, cs, (uint32_t)n, r2_cap, s, timing)) != GAMMAX_OK) return st;
         } else {
             st = launch_graph(c, cs, (uint32_t)n, r2_cap, s);
@@ -742,7 +776,6 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
                 if ((st = enqueue_prep(c, cs, s, timing ? c->ev[0] : nullptr, timing ? c->ev[1] : nullptr)) !=
                     GAMMAX_OK)
                     return st;
-                if ((st = enqueue_cnn(c, cs, s, timing)) != GAMMAX_OK) return st;
                 if ((st = enqueue_search(c, cs, (uint32_t)n, r2_cap, s, timing)) != GAMMAX_OK) return st;
             }
         }
@@ -776,7 +809,6 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
             ms_table = elapsed(c->ev[2], c->ev[3]);
         }
     }
-    if (M > 0 && (st = enqueue_cnn(c, cs, s, timing)) != GAMMAX_OK) return st;
     if (M > 0) {
         const bool walk = r2 > 0.0f && c->tab_valid;
         const bool keep = c->tab_valid;
@@ -835,8 +867,16 @@ gammax_status_t gammax_sort_pairs(gammax_ctx_t* c, uint32_t* keys, uint32_t* val
     gammax_status_t st;
     if ((st = grow_work(c, n)) != GAMMAX_OK) return st;
     if ((st = grow(c, &c->hist, &c->hist_cap, sort_hist_words(n))) != GAMMAX_OK) return st;
-    HIPCHK(c, radix_sort_pairs(keys, vals, work_array(c, W_TMP_K), work_array(c, W_TMP_V), n, nullptr,
-                               c->hist, s));
+    if (n <= SMALL_SORT_CAP) {
+        // short lists: the one-workgroup rank sort (count handed over on the device)
+        *c->h_count = (uint32_t)n;
+        HIPCHK(c, hipMemcpyAsync(c->d_count, c->h_count, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(c, sort_pairs_small(keys, vals, work_array(c, W_TMP_K), work_array(c, W_TMP_V), c->d_count,
+                                   &c->d_sc->sort_overflow, s));
+    } else {
+        HIPCHK(c, radix_sort_pairs(keys, vals, work_array(c, W_TMP_K), work_array(c, W_TMP_V), n, nullptr,
+                                   c->hist, s));
+    }
     HIPCHK(c, hipStreamSynchronize(s));
     return GAMMAX_OK;
 }
@@ -928,6 +968,39 @@ gammax_status_t gammax_model_predict(gammax_ctx_t* c, gammax_model_t* m, const g
     if ((st = enqueue_dose_scalars(c, p, ref, ev, n, s)) != GAMMAX_OK) return st;
     HIPCHK(c, launch_features(ref, ev, o, c->d_sc, w.feat, s));
     HIPCHK(c, model_forward(m, w.feat, 1, o, w.a1, w.a2, w.a3, y, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return device_errors(c, false);
+}
+
+gammax_status_t gammax_model_predict_nodes(gammax_ctx_t* c, gammax_model_t* m, const gammax_problem_t* p,
+                                           const float* ref, const float* ev, const uint32_t* nodes, int64_t n,
+                                           float* y, void* stream) {
+    if (!c) return GAMMAX_E_NULL;
+    if (!m || !y || (!nodes && n > 0)) return fail(c, GAMMAX_E_NULL, "model, nodes and output are required");
+    if (m->device != c->device) return fail(c, GAMMAX_E_PARAM, "model and context live on different devices");
+    int o[3];
+    int64_t total = 0;
+    gammax_status_t st = model_inputs(c, p, ref, ev, o, &total);
+    if (st != GAMMAX_OK) return st;
+    if (n < 0 || n > total) return fail(c, GAMMAX_E_PARAM, "n must lie in [0, number of grid nodes]");
+    if (n == 0) return GAMMAX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((st = enqueue_dose_scalars(c, p, ref, ev, total, s)) != GAMMAX_OK) return st;
+    *c->h_count = (uint32_t)n;
+    HIPCHK(c, hipMemcpyAsync(c->d_count, c->h_count, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    TailCnnHook h{};
+    h.model = m;
+    h.ref = ref;
+    h.ev = ev;
+    for (int i = 0; i < 3; ++i) h.shape[i] = o[i];
+    h.sc = c->d_sc;
+    h.nodes = nodes;
+    h.count = c->d_count;
+    h.y = y;
+    h.blocks = kTailCnnBlocks;
+    HIPCHK(c, tail_cnn_hook(&h, s));
     HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return device_errors(c, false);
@@ -1120,7 +1193,19 @@ gammax_status_t upload_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L,
     return GAMMAX_OK;
 }
 
-// Queue the whole batch: prep, the network of the learned pairs, the search passes.
+struct BatchHooks {
+    std::vector<TailCnnHook> list;
+};
+hipError_t batch_hooks(void* user, hipStream_t s) {
+    for (TailCnnHook& h : static_cast<BatchHooks*>(user)->list) {
+        hipError_t e = tail_cnn_hook(&h, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Queue the whole batch: prep, the search passes (with the network at the tail nodes of
+// the learned pairs after the key-0 pass).
 gammax_status_t enqueue_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L, const gammax_problem_t* probs,
                               const float* const* refs, const float* const* evals, const gammax_options_t& opt,
                               const std::vector<int>& learned, bool prep, bool search, hipStream_t s) {
@@ -1130,14 +1215,22 @@ gammax_status_t enqueue_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L
     if (prep) HIPCHK(c, launch_batch_prep(d_pp, L.n, L.total_red, L.total_tiles, done + L.n, s));
     if (!search) return GAMMAX_OK;
     bool any_spec = false, any_guard = false;
+    BatchHooks hooks;
     for (int i = 0; i < L.n; ++i) {
         if (learned[i]) {
-            const int o[3] = {(int)probs[i].shape[0], (int)probs[i].shape[1], (int)probs[i].shape[2]};
-            CnnWs w = cnn_layout(c->cnn_ws, o);
+            // the network at this pair's tail nodes, after the key-0 pass
+            TailCnnHook h{};
+            h.model = opt.model;
+            h.ref = refs[i];
+            h.ev = evals[i];
+            for (int k = 0; k < 3; ++k) h.shape[k] = (int)probs[i].shape[k];
             Scalars* sc = (Scalars*)(b->arena + L.o_sc) + i;
-            HIPCHK(c, launch_features(refs[i], evals[i], o, sc, w.feat, s));
-            HIPCHK(c, model_forward(const_cast<gammax_model*>(opt.model), w.feat, 1, o, w.a1, w.a2, w.a3,
-                                    (float*)(b->arena + L.o_yhat[i]), s));
+            h.sc = sc;
+            h.nodes = (const uint32_t*)(b->arena + L.o_work[i]) + W_TAIL_NODE * L.nodes[i];
+            h.count = &sc->n_tail;
+            h.y = (float*)(b->arena + L.o_yhat[i]);
+            h.blocks = kTailCnnBlocks;
+            hooks.list.push_back(h);
             any_spec = any_spec || opt.radius_mode == GAMMAX_RADIUS_LEARNED;
         }
         any_guard = any_guard || (opt.precision == GAMMAX_PREC_GUARDED && probs[i].ndim == 3);
@@ -1147,7 +1240,8 @@ gammax_status_t enqueue_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L
     const int tail_blocks = dev_cus * 4;
     HIPCHK(c, launch_batch_search(d_sp, L.n, (const uint2*)(b->arena + L.o_items), L.n_items, zero_blocks,
                                   tail_blocks, any_spec, any_guard, (uint32_t*)(b->arena + L.o_chunk0),
-                                  (uint32_t*)(b->arena + L.o_gsel), (BatchCtl*)(b->arena + L.o_ctl), done, s));
+                                  (uint32_t*)(b->arena + L.o_gsel), (BatchCtl*)(b->arena + L.o_ctl), done,
+                                  hooks.list.empty() ? nullptr : batch_hooks, &hooks, s));
     return GAMMAX_OK;
 }
 
@@ -1215,14 +1309,9 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
 
     // which pairs use the network; cost order of the key-0 items (3D first, larger first)
     std::vector<int> learned(n, 0), order(n);
-    int64_t cnn_need = 0;
     for (int i = 0; i < n; ++i) {
         learned[i] = uses_model(&probs[i], &opt) ? 1 : 0;
         order[i] = i;
-        if (learned[i]) {
-            const int o[3] = {(int)probs[i].shape[0], (int)probs[i].shape[1], (int)probs[i].shape[2]};
-            cnn_need = std::max(cnn_need, cnn_layout(nullptr, o).bytes);
-        }
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int z) {
         const double ca = (double)nn[a] * (probs[a].ndim == 3 ? 8.0 : 2.0);
@@ -1241,7 +1330,6 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
         HIPCHK(c, hipHostMalloc((void**)&b->host, (size_t)L.host, hipHostMallocDefault));
         b->host_cap = L.host;
     }
-    if (cnn_need > c->cnn_ws_cap && (st = grow(c, &c->cnn_ws, &c->cnn_ws_cap, cnn_need)) != GAMMAX_OK) return st;
 
     // tail lanes per pair: fixed by the options, else tuned per shape class, else automatic
     std::vector<uint64_t> cls(n);

@@ -19,7 +19,8 @@ struct Scalars {
     uint32_t n_guard;       // nodes queued for the FP64-guarded pass
     uint32_t maxg2_bits;    // max gamma^2 found (non-negative float bits)
     uint32_t n_fallback;    // learned radius: tail nodes not certified inside 1.1 * gamma_hat
-    uint32_t pad[2];
+    uint32_t sort_overflow; // the one-workgroup tail sort met a longer tail (left unsorted)
+    uint32_t pad;
     unsigned long long n_pass;
     unsigned long long n_border;
     unsigned long long n_fp64;
@@ -115,6 +116,12 @@ hipError_t launch_pass_count(const float* gamma, int64_t n, unsigned long long* 
 // on the device, at most n_max; without it n_max is the count.  tmp_* hold n_max entries;
 // hist needs sort_hist_words(n_max) words.  The result ends in keys/vals.
 int64_t sort_hist_words(int64_t n_max);
+// Stable rank sort for lists of at most SMALL_SORT_CAP pairs in two launches (count on the
+// device; tmp_* hold SMALL_SORT_CAP entries); a longer list is left unsorted and *overflow
+// set to 1.
+constexpr int SMALL_SORT_CAP = 4096;
+hipError_t sort_pairs_small(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
+                            const uint32_t* n_dev, uint32_t* overflow, hipStream_t s);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
                             int64_t n_max, const uint32_t* n_dev, uint32_t* hist, hipStream_t s);
 
@@ -159,7 +166,7 @@ struct SearchArgs {
     float r2_cap;            // the table holds every cell with key^2 < r2_cap
     int tail_key;            // key of the tail sort: 0 = gamma0^2 (DD sort), 1 = bound after the
                              // key-0 cells, 2 = predicted gamma (learned ordering)
-    const float* yhat;       // learned radius: log(gamma_hat + 0.01) per grid node, or null
+    const float* yhat;       // learned radius: log(gamma_hat + 0.01) per tail item, or null
     float spec_factor;       // the speculative walk stops at key >= spec_factor * gamma_hat
     // work lists
     const uint32_t* nodes;   // masked nodes in grid order (M)
@@ -185,11 +192,16 @@ struct SearchPlan {
     int zero_lanes;          // pass A: 1 = one lane per cell, 0 = one lane per node
     int spec;                // 1: speculative tail walk inside spec_factor * gamma_hat, then the
                              //    plain walk for the nodes it could not certify
+    // optional: queued after the key-0 pass, before the tail sort (the network at the tail
+    // nodes writes yhat and, for the predicted order, the sort keys)
+    hipError_t (*after_zero)(void* user, hipStream_t s);
+    void* after_zero_user;
     uint32_t M;
     ZeroGeo zero;
     uint32_t* tmp_keys;      // sort scratch, M entries each
     uint32_t* tmp_vals;
     uint32_t* hist;          // sort_hist_words(M)
+    int small_sort;          // sort the tail with the rank sort (expected to hold <= SMALL_SORT_CAP)
     hipEvent_t ev_shell_end; // optional: recorded after the zero-key pass
     hipEvent_t ev_sort_end;  // optional: recorded after the tail sort
     hipEvent_t ev_tail_end;  // optional: recorded after the tail walk
@@ -232,6 +244,6 @@ hipError_t launch_batch_prep(const BatchPrepPair* pairs, int n, int total_red, i
 hipError_t launch_batch_search(const BatchSearchPair* pairs, int n, const uint2* items, int n_items,
                                int zero_blocks, int tail_blocks, bool any_spec, bool any_guard,
                                uint32_t* chunk0, uint32_t* gsel, BatchCtl* ctl, unsigned long long* done,
-                               hipStream_t s);
+                               hipError_t (*after_zero)(void*, hipStream_t), void* user, hipStream_t s);
 
 }  // namespace gammax

@@ -398,6 +398,132 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ ref,
     }
 }
 
+// ---- the network at listed nodes only ------------------------------------------------
+//
+// One workgroup per node (grid-stride over the list): the node's 9x9x9 feature patch is
+// staged in LDS, then layer 1 (7^3 outputs), layer 2 (5^3), layer 3 (3^3) run as the same
+// implicit GEMM on the matrix cores with their outputs kept in LDS, and layer 4 (one
+// output, 432 products) is a block reduction.  Same features, same bf16 rounding points
+// and the same layer arithmetic as the dense pass, so the value at a node is what the dense
+// network gives there (up to the order of the FP32 sums).
+struct TailCnnArgs {
+    const float* ref;
+    const float* ev;
+    int nx, ny, nz;
+    const Scalars* sc;
+    const uint32_t* nodes;      // node index per list entry
+    const uint32_t* count;      // list length (device)
+    const uint16_t* frag[3];    // forward fragments of layers 0..2
+    const float* bias[3];
+    const float* w4;            // layer 3 weights W[0][ci][tap] (FP32 master copy)
+    const float* b4;            // layer 3 bias
+    float* y;                   // output per list entry: log(gamma_hat + 0.01)
+    uint32_t* key;              // optional: bits of gamma_hat per list entry (sort key)
+};
+
+template <int CIN, int IN_E, int OUT_E>
+__device__ __forceinline__ void patch_layer(const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
+                                            const uint16_t* __restrict__ frag, const float* __restrict__ bias) {
+    constexpr int NCH = CIN == 16 ? 14 : 2;
+    constexpr int NOUT = OUT_E * OUT_E * OUT_E;
+    constexpr int NGRP = (NOUT + 15) / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    U4 wr[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) wr[c] = reinterpret_cast<const U4*>(frag)[c * 64 + lane];
+    float bb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bb[r] = bias[4 * g + r];
+    for (int grp = wv; grp < NGRP; grp += NTHREADS / 64) {
+        int o = grp * 16 + j;
+        const bool valid = o < NOUT;
+        o = valid ? o : NOUT - 1;
+        const int oz = o / (OUT_E * OUT_E), oy = (o / OUT_E) % OUT_E, ox = o % OUT_E;
+        const int base = (oz * IN_E + oy) * IN_E + ox;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            U4 bop;
+            if (CIN == 16) {
+                int t = 2 * c + (g >> 1);
+                t = t > 26 ? 26 : t;
+                int dz, dy, dx;
+                tap_xyz(t, dz, dy, dx);
+                bop = *reinterpret_cast<const U4*>(&in[(base + (dz * IN_E + dy) * IN_E + dx) * 16 + (g & 1) * 8]);
+            } else {
+                uint32_t w[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    int t = 16 * c + 4 * g + q;
+                    t = t > 26 ? 26 : t;
+                    int dz, dy, dx;
+                    tap_xyz(t, dz, dy, dx);
+                    w[q] = *reinterpret_cast<const uint32_t*>(&in[(base + (dz * IN_E + dy) * IN_E + dx) * 2]);
+                }
+                bop = U4{w[0], w[1], w[2], w[3]};
+            }
+            acc = mfma_bf16(wr[c], bop, acc);
+        }
+        if (valid) {
+            uint2 st;
+            st.x = (uint32_t)f2bf(fmaxf(acc[0] + bb[0], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1] + bb[1], 0.f)) << 16);
+            st.y = (uint32_t)f2bf(fmaxf(acc[2] + bb[2], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3] + bb[3], 0.f)) << 16);
+            *reinterpret_cast<uint2*>(&out[o * 16 + 4 * g]) = st;
+        }
+    }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_cnn_tail(TailCnnArgs a) {
+    __shared__ __align__(16) uint16_t f0[729 * 2];     // 9^3 features
+    __shared__ __align__(16) uint16_t a1[343 * 16];    // 7^3 x 16
+    __shared__ __align__(16) uint16_t a2[125 * 16];    // 5^3 x 16
+    __shared__ __align__(16) uint16_t a3[27 * 16];     // 3^3 x 16
+    __shared__ float red[NTHREADS / 64];
+    const uint32_t M = *a.count;
+    const float dmax = ord_to_float(a.sc->dmax_ord);
+    const float inv_max = 1.0f / dmax;
+    const float inv_dd = a.sc->inv_dd;
+    const int sxy = a.nx * a.ny;
+    for (uint32_t item = blockIdx.x; item < M; item += gridDim.x) {
+        const int node = (int)a.nodes[item];
+        const int x0 = node % a.nx - 4, y0 = (node / a.nx) % a.ny - 4, z0 = node / sxy - 4;
+        for (int v = threadIdx.x; v < 729; v += NTHREADS) {
+            const int x = x0 + v % 9, y = y0 + (v / 9) % 9, z = z0 + v / 81;
+            uint32_t q = 0u;
+            if (x >= 0 && x < a.nx && y >= 0 && y < a.ny && z >= 0 && z < a.nz) {
+                const int64_t n = ((int64_t)z * a.ny + y) * a.nx + x;
+                const float r = a.ref[n], e = a.ev[n];
+                q = (uint32_t)f2bf(r * inv_max) | ((uint32_t)f2bf((e - r) * inv_dd) << 16);
+            }
+            reinterpret_cast<uint32_t*>(f0)[v] = q;
+        }
+        __syncthreads();
+        patch_layer<2, 9, 7>(f0, a1, a.frag[0], a.bias[0]);
+        __syncthreads();
+        patch_layer<16, 7, 5>(a1, a2, a.frag[1], a.bias[1]);
+        __syncthreads();
+        patch_layer<16, 5, 3>(a2, a3, a.frag[2], a.bias[2]);
+        __syncthreads();
+        // layer 4: one output from 27 taps x 16 channels (bf16 weights, FP32 sum)
+        float s = 0.f;
+        for (int k = threadIdx.x; k < 432; k += NTHREADS) {
+            const int t = k >> 4, ci = k & 15;
+            s += bf2f(f2bf(a.w4[ci * 27 + t])) * bf2f(a3[t * 16 + ci]);
+        }
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float y = *a.b4;
+            for (int w = 0; w < NTHREADS / 64; ++w) y += red[w];
+            a.y[item] = y;
+            if (a.key) a.key[item] = f2u(fmaxf(expf(y) - 0.01f, 0.0f));
+        }
+        __syncthreads();
+    }
+}
+
 int grid_for(int64_t n, int64_t cap) {
     int64_t b = (n + 255) / 256;
     if (b > cap) b = cap;
@@ -493,6 +619,31 @@ hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int 
 hipError_t launch_pack(const float* w, int cin, int cout, int bwd, uint16_t* frag, hipStream_t s) {
     const int nch = bwd ? 14 : (cin == 16 ? 14 : 2);
     hipLaunchKernelGGL(k_pack, dim3(nch), dim3(64), 0, s, w, cin, cout, bwd, nch, frag);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_tail(const float* ref, const float* ev, const int n[3], const Scalars* sc,
+                           const uint32_t* nodes, const uint32_t* count, int max_blocks, const uint16_t* const frag[3],
+                           const float* const bias[3], const float* w4, const float* b4, float* y, uint32_t* key,
+                           hipStream_t s) {
+    TailCnnArgs a{};
+    a.ref = ref;
+    a.ev = ev;
+    a.nz = n[0];
+    a.ny = n[1];
+    a.nx = n[2];
+    a.sc = sc;
+    a.nodes = nodes;
+    a.count = count;
+    for (int l = 0; l < 3; ++l) {
+        a.frag[l] = frag[l];
+        a.bias[l] = bias[l];
+    }
+    a.w4 = w4;
+    a.b4 = b4;
+    a.y = y;
+    a.key = key;
+    hipLaunchKernelGGL(k_cnn_tail, dim3(max_blocks > 0 ? max_blocks : 1), dim3(NTHREADS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -415,21 +415,22 @@ __device__ __forceinline__ void finish_node(const SearchArgs& a, int node, float
     gm = max(gm, f2u(gam * gam));
 }
 
-// Learned radius.  gamma_hat = max(exp(y) - 0.01, 0) from the CNN output y at the node;
+// Learned radius.  gamma_hat = max(exp(y) - 0.01, 0) from the CNN output y of a tail item;
 // the speculative walk takes the bound min(gamma^2, (f * gamma_hat)^2).  The same float
 // expression serves the speculative walk and the fallback, so both see the same bound.
-__device__ __forceinline__ float pred_gamma(const SearchArgs& a, int node) {
-    return fmaxf(expf(a.yhat[node]) - 0.01f, 0.0f);
+__device__ __forceinline__ float pred_gamma(const SearchArgs& a, uint32_t item) {
+    return fmaxf(expf(a.yhat[item]) - 0.01f, 0.0f);
 }
-__device__ __forceinline__ float spec_bound2(const SearchArgs& a, int node) {
-    const float r = a.spec_factor * pred_gamma(a, node);
+__device__ __forceinline__ float spec_bound2(const SearchArgs& a, uint32_t item) {
+    const float r = a.spec_factor * pred_gamma(a, item);
     return r * r;
 }
-// Sort key of a queued tail node: gamma0^2 (DD sort), the bound after the key-0 cells,
-// or the predicted gamma (all non-negative floats: bit order = numeric order).
+// Sort key of a queued tail node: gamma0^2 (DD sort) or the bound after the key-0 cells
+// (non-negative floats: bit order = numeric order).  The predicted order's keys are
+// written afterwards by the network at the tail nodes.
 __device__ __forceinline__ uint32_t tail_sort_key(const SearchArgs& a, int node, float F0, float F) {
-    if (a.tail_key == 2) return f2u(pred_gamma(a, node));
-    return a.tail_key ? f2u(F) : f2u(F0);
+    (void)node;
+    return a.tail_key == 1 ? f2u(F) : f2u(F0);
 }
 // First table row with key^2 >= r2 (rows are in ascending key order), at least `first`.
 // Rows before it either were evaluated by the speculative walk or could not improve it.
@@ -766,7 +767,7 @@ __device__ __forceinline__ void walk_body(const SearchArgs& a, const TabEntry* _
         uint32_t lane_cells = 0, lane_fp64 = 0;
         bool ill = false;
         // learned radius: the speculative bound, and the fallback's first row
-        const float r2s = (TAIL && spec && live) ? spec_bound2(a, node) : Num<float>::inf();
+        const float r2s = (TAIL && spec && live) ? spec_bound2(a, item) : Num<float>::inf();
         int lstart = first;
         if (TAIL && spec == 2 && live) lstart = resume_row(tab, a.tab_len, first, r2s);
         int wstart = lstart;
@@ -916,7 +917,7 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
         float F = live ? u2f(a.tail_f[item]) : 0.0f;
         uint32_t lane_cells = 0;
         bool ill = false;
-        const float r2s = (spec && live) ? spec_bound2(a, node) : Num<float>::inf();
+        const float r2s = (spec && live) ? spec_bound2(a, item) : Num<float>::inf();
         // the fallback resumes at the first row the speculative bound cut off (per group)
         const int start = (spec == 2 && live) ? resume_row(tab, a.tab_len, first, r2s) : first;
 
@@ -1228,10 +1229,14 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_batch_finalize(const BatchSe
 hipError_t launch_batch_search(const BatchSearchPair* pairs, int n, const uint2* items, int n_items,
                                int zero_blocks, int tail_blocks, bool any_spec, bool any_guard,
                                uint32_t* chunk0, uint32_t* gsel, BatchCtl* ctl, unsigned long long* done,
-                               hipStream_t s) {
+                               hipError_t (*after_zero)(void*, hipStream_t), void* user, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (n_items > 0)
         hipLaunchKernelGGL(k_batch_zero, dim3(zero_blocks), dim3(SEARCH_THREADS), 0, s, pairs, items, n_items, done);
+    if (after_zero) {
+        hipError_t e = after_zero(user, s);
+        if (e != hipSuccess) return e;
+    }
     const int phases[3] = {0, 1, 2};
     for (int ph : phases) {
         if (ph == 1 && !any_spec) continue;
@@ -1285,10 +1290,17 @@ hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s
         }
         used += (int)nb;
         if (p.ev_shell_end) (void)hipEventRecord(p.ev_shell_end, s);
+        if (p.after_zero) {
+            hipError_t e = p.after_zero(p.after_zero_user, s);
+            if (e != hipSuccess) return e;
+        }
         // tail sort (count read on the device)
         if (p.hist) {
-            hipError_t e = radix_sort_pairs(a.tail_key_arr, a.tail_pos, p.tmp_keys, p.tmp_vals, p.M,
-                                            &a.sc->n_tail, p.hist, s);
+            hipError_t e = p.small_sort
+                               ? sort_pairs_small(a.tail_key_arr, a.tail_pos, p.tmp_keys, p.tmp_vals, &a.sc->n_tail,
+                                                  &a.sc->sort_overflow, s)
+                               : radix_sort_pairs(a.tail_key_arr, a.tail_pos, p.tmp_keys, p.tmp_vals, p.M,
+                                                  &a.sc->n_tail, p.hist, s);
             if (e != hipSuccess) return e;
         }
         if (p.ev_sort_end) (void)hipEventRecord(p.ev_sort_end, s);

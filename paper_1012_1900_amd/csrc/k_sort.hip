@@ -136,7 +136,63 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
 }
 
+// Short lists: each element's place is the number of smaller keys plus the number of
+// equal keys before it (a stable rank).  Every workgroup holds all keys in LDS and ranks
+// 256 of them against the whole list (broadcast reads), writing them to the scratch pair
+// at their places; a second pass copies them back.  For n <= SMALL_SORT_CAP; a longer list
+// is left as it is and *overflow set (the callers sort only to order work, so any order
+// is correct).
+constexpr int SMALL_THREADS = 256;
+constexpr int SMALL_BLOCKS = SMALL_SORT_CAP / SMALL_THREADS;
+__global__ __launch_bounds__(SMALL_THREADS) void k_sort_small_rank(const uint32_t* __restrict__ keys,
+                                                                   const uint32_t* __restrict__ vals,
+                                                                   uint32_t* __restrict__ tk, uint32_t* __restrict__ tv,
+                                                                   const uint32_t* n_dev, uint32_t* overflow) {
+    __shared__ uint32_t sk[SMALL_SORT_CAP];
+    const uint32_t n = *n_dev;
+    if (n > (uint32_t)SMALL_SORT_CAP) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *overflow = 1u;
+        return;
+    }
+    if (blockIdx.x * SMALL_THREADS >= n) return;
+    for (uint32_t i = threadIdx.x; i < n; i += SMALL_THREADS) sk[i] = keys[i];
+    __syncthreads();
+    const uint32_t i = blockIdx.x * SMALL_THREADS + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = sk[i];
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+        const uint32_t kj = sk[j];
+        rank += (kj < k || (kj == k && j < i)) ? 1u : 0u;
+    }
+    tk[rank] = k;
+    tv[rank] = vals[i];
+}
+
+__global__ __launch_bounds__(SMALL_THREADS) void k_sort_small_copy(uint32_t* __restrict__ keys,
+                                                                   uint32_t* __restrict__ vals,
+                                                                   const uint32_t* __restrict__ tk,
+                                                                   const uint32_t* __restrict__ tv,
+                                                                   const uint32_t* n_dev) {
+    const uint32_t n = *n_dev;
+    if (n > (uint32_t)SMALL_SORT_CAP) return;
+    const uint32_t i = blockIdx.x * SMALL_THREADS + threadIdx.x;
+    if (i < n) {
+        keys[i] = tk[i];
+        vals[i] = tv[i];
+    }
+}
+
 }  // namespace
+
+hipError_t sort_pairs_small(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
+                            const uint32_t* n_dev, uint32_t* overflow, hipStream_t s) {
+    hipLaunchKernelGGL(k_sort_small_rank, dim3(SMALL_BLOCKS), dim3(SMALL_THREADS), 0, s, keys, vals, tmp_keys,
+                       tmp_vals, n_dev, overflow);
+    hipLaunchKernelGGL(k_sort_small_copy, dim3(SMALL_BLOCKS), dim3(SMALL_THREADS), 0, s, keys, vals, tmp_keys,
+                       tmp_vals, n_dev);
+    return hipGetLastError();
+}
 
 int64_t sort_hist_words(int64_t n_max) {
     const int64_t nb = (n_max + SORT_TILE - 1) / SORT_TILE;

@@ -35,7 +35,8 @@ def test_header_declares_the_boundary():
                  "gammax_status_string", "gammax_last_error", "gammax_options_default",
                  "gammax_model_create", "gammax_model_destroy", "gammax_model_get_params",
                  "gammax_model_features", "gammax_model_predict", "gammax_model_forward",
-                 "gammax_model_train_step", "gammax_model_last_error"]:
+                 "gammax_model_train_step", "gammax_model_last_error", "gammax_model_predict_nodes",
+                 "gammax_batch", "gammax_tune_save", "gammax_tune_load"]:
         assert must in names
 
 

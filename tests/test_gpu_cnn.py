@@ -180,3 +180,26 @@ def test_training_lowers_the_loss(gx):
     f, lab = _feat_tensor(bits), dev(labels)
     losses = [m.train_step(f, lab, lr=3e-3) for _ in range(40)]
     assert losses[-1] < 0.5 * losses[0], losses[::8]
+
+
+def test_predict_at_listed_nodes(gx):
+    """The network at listed nodes only (each from its own 9^3 patch), as the learned
+    search evaluates it: the oracle's whole-grid values at those nodes, and the GPU's own
+    whole-grid pass there up to the order of the last layer's sum."""
+    import torch
+    pair = _pair(6)
+    th = _theta(9)
+    m = gx.Model(th.astype(np.float32))
+    ref, ev = dev(pair.ref), dev(pair.eval)
+    n = pair.ref.size
+    rng = np.random.default_rng(10)
+    nz, ny, nx = pair.ref.shape
+    corners = [((z * ny) + y) * nx + x for z in (0, nz - 1) for y in (0, ny - 1) for x in (0, nx - 1)]
+    nodes = np.unique(np.concatenate([rng.choice(n, 400, replace=False), corners])).astype(np.int32)
+    y = host(gx.predict_nodes(m, ref, ev, pair.spacing, 0.03, torch.from_numpy(nodes).to("cuda")))
+    f = cnn.features(pair.ref, pair.eval, 0.03)
+    want = cnn.forward(th, f).y.ravel()[nodes]
+    A = _abs_network(th, f).ravel()[nodes]
+    assert np.all(np.abs(y - want) <= 4 * 2.0 ** -8 * A + 1e-6)
+    dense = host(m.predict(ref, ev, pair.spacing, 0.03)).ravel()[nodes]
+    assert np.all(np.abs(y - dense) <= 1e-5 * A + 1e-6)

@@ -19,7 +19,7 @@ def _i32(a):
     return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to("cuda")
 
 
-@pytest.mark.parametrize("n", [0, 1, 5, 255, 4097, 100003, (1 << 20) + 17])
+@pytest.mark.parametrize("n", [0, 1, 5, 255, 1313, 4096, 4097, 100003, (1 << 20) + 17])
 @pytest.mark.parametrize("kind", ["random", "few_keys", "float_bits"])
 def test_radix_sort_stable(gx, n, kind):
     rng = np.random.default_rng(n + len(kind))
