@@ -58,7 +58,7 @@ struct gammax_ctx {
     // node work lists: 8 arrays of work_cap uint32 in one allocation
     uint32_t* work = nullptr;
     int64_t work_cap = 0;
-    uint32_t* blockcnt = nullptr;   // prep tiles: counts, then maxima
+    uint32_t* blockcnt = nullptr;   // prep tiles: counts, then the tile-group sums
     int64_t blk_cap = 0;
     uint32_t* part = nullptr;       // dose-max partials
     int64_t part_cap = 0;
@@ -365,7 +365,9 @@ gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, 
     pa.sc = c->d_sc;
     pa.part = c->part;
     pa.blockcnt = c->blockcnt;
-    pa.blockmax = c->blockcnt + ntiles;
+    prep_groups(cs.n, &pa.super_shift, &pa.n_super);
+    pa.super = c->blockcnt + ntiles;
+    pa.ntiles = (int)ntiles;
     pa.nodes = work_array(c, W_NODES);
     pa.sums = c->sums;
     HIPCHK(c, launch_prep(pa, s));
@@ -403,7 +405,7 @@ hipError_t tail_cnn_hook(void* user, hipStream_t s) {
     return hipSuccess;
 }
 
-constexpr int kTailCnnBlocks = 2048;   // grid-stride blocks of the network at the tail nodes
+constexpr int kTailCnnBlocks = 2048;   // grid-stride one-wave blocks of the network at the tail nodes (8 per CU)
 
 // Search arguments of one pair.  work: the kWorkArrays node arrays, `stride` words apart.
 SearchArgs make_search_args(const gammax_problem_t* p, const gammax_options_t& opt, const float* ref,
@@ -746,7 +748,7 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
     // workspace, sized for all n nodes so that the steady path needs no count from the host
     const int64_t ntiles = prep_tiles(n);
     if ((st = grow_work(c, n)) != GAMMAX_OK) return st;
-    if ((st = grow(c, &c->blockcnt, &c->blk_cap, 2 * ntiles)) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->blockcnt, &c->blk_cap, prep_words(n))) != GAMMAX_OK) return st;
     if ((st = grow(c, &c->part, &c->part_cap, 2 * MAX_BLOCKS)) != GAMMAX_OK) return st;
     if ((st = grow(c, &c->hist, &c->hist_cap, sort_hist_words(n))) != GAMMAX_OK) return st;
     if ((st = grow(c, &c->sums, &c->sums_cap, search_sums_needed((uint32_t)n))) != GAMMAX_OK) return st;
@@ -1097,7 +1099,7 @@ BatchLayout batch_layout(int n, const gammax_problem_t* probs, const std::vector
     for (int i = 0; i < n; ++i) {
         L.o_sums.push_back(take(sizeof(BlockSums) * SUM_BINS));
         L.o_part.push_back(take(sizeof(uint32_t) * 2 * MAX_BLOCKS));
-        L.o_blk.push_back(take(sizeof(uint32_t) * 2 * L.tiles[i]));
+        L.o_blk.push_back(take(sizeof(uint32_t) * prep_words(L.nodes[i])));
         L.o_work.push_back(take(sizeof(uint32_t) * kWorkArrays * L.nodes[i]));
         L.o_yhat.push_back(learned[i] ? take(sizeof(float) * L.nodes[i]) : -1);
     }
@@ -1154,7 +1156,9 @@ void fill_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L, const gammax
         P.pa.sc = &d_sc[i];
         P.pa.part = (uint32_t*)(b->arena + L.o_part[i]);
         P.pa.blockcnt = blk;
-        P.pa.blockmax = blk + L.tiles[i];
+        prep_groups(L.nodes[i], &P.pa.super_shift, &P.pa.n_super);
+        P.pa.super = blk + L.tiles[i];
+        P.pa.ntiles = (int)L.tiles[i];
         P.pa.nodes = work + W_NODES * L.nodes[i];
         P.pa.sums = (BlockSums*)(b->arena + L.o_sums[i]);
         P.nb_red = (int)L.red[i];

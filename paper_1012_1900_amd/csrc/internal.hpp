@@ -96,13 +96,20 @@ struct PrepArgs {
     int local;
     Scalars* sc;
     uint32_t* part;     // 2 * MAX_BLOCKS words: dose-max partials and non-finite flags
-    uint32_t* blockcnt; // one per prep tile: masked count (then its exclusive scan)
-    uint32_t* blockmax; // one per prep tile: max gamma0^2 bits
+    uint32_t* blockcnt; // one per prep tile: masked count
+    uint32_t* super;    // 2 * n_super: masked count and max gamma0^2 bits per group of tiles
+    int ntiles;         // prep tiles (prep_tiles(n))
+    int super_shift;    // a group holds 2^super_shift consecutive tiles
+    int n_super;
     uint32_t* nodes;    // M entries: masked node indices in grid order
     BlockSums* sums;    // SUM_BINS partial-count slots of the search, zeroed here
 };
 
 int64_t prep_tiles(int64_t n);
+// Tile groups of the compaction: 2^shift >= sqrt(tiles) tiles per group; words = the
+// tile counts plus two words per group.
+void prep_groups(int64_t n, int* shift, int* n_super);
+int64_t prep_words(int64_t n);
 int batch_reduce_blocks(int64_t n);   // dose-max blocks of an n-node pair
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 // Only the dose maximum, the finiteness flag, the threshold value and the global 1/dD

@@ -421,21 +421,31 @@ struct TailCnnArgs {
     uint32_t* key;              // optional: bits of gamma_hat per list entry (sort key)
 };
 
-template <int CIN, int IN_E, int OUT_E>
+// One wave evaluates the network at one listed node at a time, from its own 9^3 feature
+// patch: 7^3, 5^3 and 3^3 hidden activations, then the single output.  The wave holds the
+// fragments of the first three layers in registers for all its nodes; its LDS is two
+// buffers that the layers use in turn (features and 5^3 in Y, 7^3 and 3^3 in X), about
+// 15 KB.  The fragments take about 120 VGPRs, so two waves fit a SIMD (eight per compute
+// unit) without spills; they hide one another's gather and LDS latency.
+constexpr int TAIL_THREADS = 64;
+constexpr int TAIL_X_ELEMS = 343 * 16;   // bf16
+constexpr int TAIL_Y_ELEMS = 125 * 16;   // >= 729 * 2 features
+constexpr int TAIL_GATHER = (729 + 63) / 64;
+
+// Output nodes [0, OUT_E^3) of a valid 3^3 convolution of the IN_E^3 x CIN patch `in` into
+// the OUT_E^3 x 16 patch `out` (ReLU, bf16), 16 nodes per MFMA group.
+template <int CIN, int IN_E, int OUT_E, int NCH>
 __device__ __forceinline__ void patch_layer(const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
-                                            const uint16_t* __restrict__ frag, const float* __restrict__ bias) {
-    constexpr int NCH = CIN == 16 ? 14 : 2;
+                                            const U4 (&wr)[NCH], const float* __restrict__ bias) {
     constexpr int NOUT = OUT_E * OUT_E * OUT_E;
     constexpr int NGRP = (NOUT + 15) / 16;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int j = lane & 15, g = lane >> 4;
-    U4 wr[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) wr[c] = reinterpret_cast<const U4*>(frag)[c * 64 + lane];
     float bb[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) bb[r] = bias[4 * g + r];
-    for (int grp = wv; grp < NGRP; grp += NTHREADS / 64) {
+#pragma unroll 1
+    for (int grp = 0; grp < NGRP; ++grp) {
         int o = grp * 16 + j;
         const bool valid = o < NOUT;
         o = valid ? o : NOUT - 1;
@@ -474,53 +484,78 @@ __device__ __forceinline__ void patch_layer(const uint16_t* __restrict__ in, uin
     }
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_cnn_tail(TailCnnArgs a) {
-    __shared__ __align__(16) uint16_t f0[729 * 2];     // 9^3 features
-    __shared__ __align__(16) uint16_t a1[343 * 16];    // 7^3 x 16
-    __shared__ __align__(16) uint16_t a2[125 * 16];    // 5^3 x 16
-    __shared__ __align__(16) uint16_t a3[27 * 16];     // 3^3 x 16
-    __shared__ float red[NTHREADS / 64];
+// The features of the 9^3 patch around `node` (zero outside the grid), as packed bf16 pairs.
+__device__ __forceinline__ void tail_gather(const TailCnnArgs& a, int node, float inv_max, float inv_dd,
+                                            uint32_t (&q)[TAIL_GATHER]) {
+    const int lane = threadIdx.x & 63;
+    const int x0 = node % a.nx - 4, y0 = (node / a.nx) % a.ny - 4, z0 = node / (a.nx * a.ny) - 4;
+#pragma unroll
+    for (int r = 0; r < TAIL_GATHER; ++r) {
+        const int v = lane + 64 * r;
+        const int x = x0 + v % 9, y = y0 + (v / 9) % 9, z = z0 + v / 81;
+        float rv = 0.f, ev = 0.f;
+        const bool in = v < 729 && x >= 0 && x < a.nx && y >= 0 && y < a.ny && z >= 0 && z < a.nz;
+        if (in) {
+            const int64_t n = ((int64_t)z * a.ny + y) * a.nx + x;
+            rv = a.ref[n];
+            ev = a.ev[n];
+        }
+        q[r] = in ? ((uint32_t)f2bf(rv * inv_max) | ((uint32_t)f2bf((ev - rv) * inv_dd) << 16)) : 0u;
+    }
+}
+
+__device__ __forceinline__ void tail_store(uint16_t* Y, const uint32_t (&q)[TAIL_GATHER]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < TAIL_GATHER; ++r)
+        if (lane + 64 * r < 729) reinterpret_cast<uint32_t*>(Y)[lane + 64 * r] = q[r];
+}
+
+__global__ __launch_bounds__(TAIL_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_cnn_tail(TailCnnArgs a) {
+    __shared__ __align__(16) uint16_t X[TAIL_X_ELEMS];
+    __shared__ __align__(16) uint16_t Y[TAIL_Y_ELEMS];
     const uint32_t M = *a.count;
-    const float dmax = ord_to_float(a.sc->dmax_ord);
-    const float inv_max = 1.0f / dmax;
+    if (blockIdx.x >= M) return;
+    const int lane = threadIdx.x & 63;
+    const float inv_max = 1.0f / ord_to_float(a.sc->dmax_ord);
     const float inv_dd = a.sc->inv_dd;
-    const int sxy = a.nx * a.ny;
+    // weights of the whole run: fragments and biases of layers 1-3, bf16 weights of layer 4
+    U4 w0[2], w1[14], w2[14];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) w0[c] = reinterpret_cast<const U4*>(a.frag[0])[c * 64 + lane];
+#pragma unroll
+    for (int c = 0; c < 14; ++c) {
+        w1[c] = reinterpret_cast<const U4*>(a.frag[1])[c * 64 + lane];
+        w2[c] = reinterpret_cast<const U4*>(a.frag[2])[c * 64 + lane];
+    }
+    constexpr int K4 = (432 + 63) / 64;   // layer 4: 27 taps x 16 channels, tap-major
+
     for (uint32_t item = blockIdx.x; item < M; item += gridDim.x) {
-        const int node = (int)a.nodes[item];
-        const int x0 = node % a.nx - 4, y0 = (node / a.nx) % a.ny - 4, z0 = node / sxy - 4;
-        for (int v = threadIdx.x; v < 729; v += NTHREADS) {
-            const int x = x0 + v % 9, y = y0 + (v / 9) % 9, z = z0 + v / 81;
-            uint32_t q = 0u;
-            if (x >= 0 && x < a.nx && y >= 0 && y < a.ny && z >= 0 && z < a.nz) {
-                const int64_t n = ((int64_t)z * a.ny + y) * a.nx + x;
-                const float r = a.ref[n], e = a.ev[n];
-                q = (uint32_t)f2bf(r * inv_max) | ((uint32_t)f2bf((e - r) * inv_dd) << 16);
-            }
-            reinterpret_cast<uint32_t*>(f0)[v] = q;
+        {
+            uint32_t q[TAIL_GATHER];
+            tail_gather(a, (int)a.nodes[item], inv_max, inv_dd, q);
+            __syncthreads();   // the previous node's layer 4 has read X
+            tail_store(Y, q);
         }
         __syncthreads();
-        patch_layer<2, 9, 7>(f0, a1, a.frag[0], a.bias[0]);
+        patch_layer<2, 9, 7, 2>(Y, X, w0, a.bias[0]);
         __syncthreads();
-        patch_layer<16, 7, 5>(a1, a2, a.frag[1], a.bias[1]);
+        patch_layer<16, 7, 5, 14>(X, Y, w1, a.bias[1]);
         __syncthreads();
-        patch_layer<16, 5, 3>(a2, a3, a.frag[2], a.bias[2]);
+        patch_layer<16, 5, 3, 14>(Y, X, w2, a.bias[2]);
         __syncthreads();
-        // layer 4: one output from 27 taps x 16 channels (bf16 weights, FP32 sum)
         float s = 0.f;
-        for (int k = threadIdx.x; k < 432; k += NTHREADS) {
-            const int t = k >> 4, ci = k & 15;
-            s += bf2f(f2bf(a.w4[ci * 27 + t])) * bf2f(a3[t * 16 + ci]);
+#pragma unroll
+        for (int r = 0; r < K4; ++r) {
+            const int k = lane + 64 * r;
+            if (k < 432) s += bf2f(f2bf(a.w4[(k & 15) * 27 + (k >> 4)])) * bf2f(X[k]);
         }
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float y = *a.b4;
-            for (int w = 0; w < NTHREADS / 64; ++w) y += red[w];
+        if (lane == 0) {
+            const float y = *a.b4 + s;
             a.y[item] = y;
             if (a.key) a.key[item] = f2u(fmaxf(expf(y) - 0.01f, 0.0f));
         }
-        __syncthreads();
     }
 }
 
@@ -643,7 +678,7 @@ hipError_t launch_cnn_tail(const float* ref, const float* ev, const int n[3], co
     a.b4 = b4;
     a.y = y;
     a.key = key;
-    hipLaunchKernelGGL(k_cnn_tail, dim3(max_blocks > 0 ? max_blocks : 1), dim3(NTHREADS), 0, s, a);
+    hipLaunchKernelGGL(k_cnn_tail, dim3(max_blocks > 0 ? max_blocks : 1), dim3(TAIL_THREADS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,15 +1,19 @@
 // Normalisation, mask, gamma0 and ordered compaction (Algorithm A2 step 2, "Kernel 1"),
 // plus the stand-alone pass-rate reduction.
 //
-// Four launches, each a coalesced stream over the dose arrays or a short single-block
-// step; results cross blocks only at kernel boundaries (a cross-block hand-over inside
-// a kernel would need device-scope release fences, which write back the XCD's L2):
-//   1. dose maximum and finiteness check: one partial per block;
+// Three launches, each a coalesced stream over the dose arrays; results cross blocks only
+// at kernel boundaries or through atomic adds (a cross-block hand-over inside a kernel
+// would need device-scope release fences, which write back the XCD's L2):
+//   1. dose maximum and finiteness check: one partial per block (block 0 also clears the
+//      tile-group sums);
 //   2. every block reduces those partials itself (a few KB from L2), derives the
 //      threshold and the global 1/dD, then counts the masked nodes of its tile and their
-//      max gamma0^2; block 0 also stores the scalars and clears the search counters;
-//   3. one block: exclusive scan of the tile counts, M and R^2;
-//   4. ordered emit of the masked node indices.
+//      max gamma0^2, stores the count and adds both into its tile group (about sqrt(tiles)
+//      tiles per group, so no address sees many atomics); block 0 also stores the scalars
+//      and clears the search counters;
+//   3. ordered emit of the masked node indices: a block's first slot is the sum of the
+//      groups before its own plus the tiles of its group before it; the last block stores
+//      M and R^2.
 #include "internal.hpp"
 
 namespace gammax {
@@ -62,6 +66,8 @@ __device__ __forceinline__ void dose_max_body(const PrepArgs& a, int vb, int vgr
         a.part[vb] = best;
         a.part[MAX_BLOCKS + vb] = bad;
     }
+    if (a.super && vb == 0)
+        for (int j = threadIdx.x; j < 2 * a.n_super; j += PREP_THREADS) a.super[j] = 0u;
 }
 
 __global__ __launch_bounds__(PREP_THREADS) void k_dose_max(PrepArgs a) { dose_max_body(a, blockIdx.x, gridDim.x); }
@@ -147,7 +153,9 @@ __device__ __forceinline__ void prep_count_body(const PrepArgs& a, int nb_red, i
         uint32_t c = 0u;
         for (int j = 0; j < PREP_THREADS / WAVE; ++j) c += s_cnt[j];
         a.blockcnt[vb] = c;
-        a.blockmax[vb] = best;
+        const int grp = vb >> a.super_shift;
+        if (c) atomicAdd(&a.super[grp], c);
+        if (best) atomicMax(&a.super[a.n_super + grp], best);
     }
 }
 
@@ -155,52 +163,23 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a, int nb_
     prep_count_body(a, nb_red, blockIdx.x);
 }
 
-// 3. one block: exclusive scan of the tile counts in place, M and R^2.
-__device__ __forceinline__ void prep_scan_body(const PrepArgs& a, int nb) {
-    __shared__ uint32_t s_wave[PREP_THREADS / WAVE];
-    __shared__ uint32_t s_carry;
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-    if (threadIdx.x == 0) s_carry = 0u;
-    __syncthreads();
-    uint32_t mx = 0u;
-    for (int b0 = 0; b0 < nb; b0 += PREP_THREADS) {
-        const int i = b0 + threadIdx.x;
-        const uint32_t v = i < nb ? a.blockcnt[i] : 0u;
-        if (i < nb) mx = max(mx, a.blockmax[i]);
-        uint32_t x = v;
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const uint32_t y = (uint32_t)__shfl_up((int)x, o);
-            if (lane >= o) x += y;
-        }
-        if (lane == WAVE - 1) s_wave[w] = x;
-        __syncthreads();
-        uint32_t off = s_carry, tot = 0u;
-        for (int j = 0; j < PREP_THREADS / WAVE; ++j) {
-            if (j < w) off += s_wave[j];
-            tot += s_wave[j];
-        }
-        if (i < nb) a.blockcnt[i] = off + x - v;
-        __syncthreads();
-        if (threadIdx.x == 0) s_carry += tot;
-        __syncthreads();
-    }
-    uint32_t none = 0u;
-    block_max_or(mx, none);
-    if (threadIdx.x == 0) {
-        a.sc->n_masked = s_carry;
-        a.sc->r2_bits = mx;
-    }
-}
-
-__global__ __launch_bounds__(PREP_THREADS) void k_prep_scan(PrepArgs a, int nb) { prep_scan_body(a, nb); }
-
 // 3. the masked nodes in grid order.
 __device__ __forceinline__ void prep_emit_body(const PrepArgs& a, int vb) {
     const float thr_val = a.sc->thr_val;
     const int64_t base = (int64_t)vb * PREP_TILE;
     __shared__ uint32_t s_wave[PREP_ITEMS][PREP_THREADS / WAVE];
+    __shared__ uint32_t s_pre[PREP_THREADS / WAVE];
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    // first slot of this tile: the groups before its own, then its group's earlier tiles
+    {
+        const int grp = vb >> a.super_shift;
+        uint32_t v = 0u;
+        for (int j = threadIdx.x; j < grp; j += PREP_THREADS) v += a.super[j];
+        for (int t = (grp << a.super_shift) + threadIdx.x; t < vb; t += PREP_THREADS) v += a.blockcnt[t];
+        v = wave_sum_u32(v);
+        if (lane == 0) s_pre[w] = v;
+    }
     bool m[PREP_ITEMS];
     unsigned long long bal[PREP_ITEMS];
 #pragma unroll
@@ -211,7 +190,8 @@ __device__ __forceinline__ void prep_emit_body(const PrepArgs& a, int vb) {
         if (lane == 0) s_wave[k][w] = (uint32_t)__popcll(bal[k]);
     }
     __syncthreads();
-    uint32_t run = a.blockcnt[vb];
+    uint32_t run = 0u;
+    for (int j = 0; j < PREP_THREADS / WAVE; ++j) run += s_pre[j];
 #pragma unroll
     for (int k = 0; k < PREP_ITEMS; ++k) {
         uint32_t off = run, tot = 0u;
@@ -222,6 +202,16 @@ __device__ __forceinline__ void prep_emit_body(const PrepArgs& a, int vb) {
         }
         if (m[k]) a.nodes[off + (uint32_t)__popcll(bal[k] & lt)] = (uint32_t)(base + (int64_t)k * PREP_THREADS + threadIdx.x);
         run += tot;
+    }
+    if (vb == a.ntiles - 1) {
+        // the last tile: M and R^2 (the maximum over the groups)
+        uint32_t mx = 0u, none = 0u;
+        for (int j = threadIdx.x; j < a.n_super; j += PREP_THREADS) mx = max(mx, a.super[a.n_super + j]);
+        block_max_or(mx, none);
+        if (threadIdx.x == 0) {
+            a.sc->n_masked = run;
+            a.sc->r2_bits = mx;
+        }
     }
 }
 
@@ -272,9 +262,6 @@ __global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_count(const BatchPr
     const int p = batch_pair_of(P, n, blockIdx.x, true);
     prep_count_body(P[p].pa, P[p].nb_red, blockIdx.x - P[p].tile0);
 }
-__global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_scan(const BatchPrepPair* P) {
-    prep_scan_body(P[blockIdx.x].pa, P[blockIdx.x].ntiles);
-}
 __global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_emit(const BatchPrepPair* P, int n) {
     const int p = batch_pair_of(P, n, blockIdx.x, true);
     prep_emit_body(P[p].pa, blockIdx.x - P[p].tile0);
@@ -290,12 +277,25 @@ int reduce_blocks(int64_t n) {
 
 int64_t prep_tiles(int64_t n) { return (n + PREP_TILE - 1) / PREP_TILE; }
 
+void prep_groups(int64_t n, int* shift, int* n_super) {
+    const int64_t t = prep_tiles(n);
+    int sh = 0;
+    while (((int64_t)1 << (2 * sh)) < t) ++sh;
+    *shift = sh;
+    *n_super = (int)((t + ((int64_t)1 << sh) - 1) >> sh);
+}
+
+int64_t prep_words(int64_t n) {
+    int sh = 0, ns = 0;
+    prep_groups(n, &sh, &ns);
+    return prep_tiles(n) + 2 * (int64_t)ns;
+}
+
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
     const int nbr = reduce_blocks(a.n);
     const int64_t nb = prep_tiles(a.n);
     hipLaunchKernelGGL(k_dose_max, dim3(nbr), dim3(PREP_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_prep_count, dim3((unsigned)nb), dim3(PREP_THREADS), 0, s, a, nbr);
-    hipLaunchKernelGGL(k_prep_scan, dim3(1), dim3(PREP_THREADS), 0, s, a, (int)nb);
     hipLaunchKernelGGL(k_prep_emit, dim3((unsigned)nb), dim3(PREP_THREADS), 0, s, a);
     return hipGetLastError();
 }
@@ -305,7 +305,6 @@ hipError_t launch_batch_prep(const BatchPrepPair* pairs, int n, int total_red, i
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_dose_max, dim3(total_red), dim3(PREP_THREADS), 0, s, pairs, n, t0);
     hipLaunchKernelGGL(k_batch_prep_count, dim3(total_tiles), dim3(PREP_THREADS), 0, s, pairs, n);
-    hipLaunchKernelGGL(k_batch_prep_scan, dim3(n), dim3(PREP_THREADS), 0, s, pairs);
     hipLaunchKernelGGL(k_batch_prep_emit, dim3(total_tiles), dim3(PREP_THREADS), 0, s, pairs, n);
     return hipGetLastError();
 }
