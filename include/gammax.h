@@ -167,6 +167,38 @@ gammax_status_t gammax_map(gammax_ctx_t *ctx, const gammax_problem_t *problem,
                            const float *eval_dev, float *gamma_dev, gammax_result_t *result,
                            void *stream);
 
+/* Maps that may be in flight at once on one context (gammax_map_async). */
+#define GAMMAX_ASYNC_SLOTS 64
+
+/*
+ * Queue one gamma map (the computation of gammax_map) without waiting for it, for callers
+ * that issue maps back to back and collect the results afterwards: the host's launch work
+ * for the next map then overlaps the GPU's work on this one.
+ *   Arguments as in gammax_map, except: options->timing must be 0 (GAMMAX_E_PARAM), and
+ *   *ticket receives a nonzero handle for gammax_map_wait.
+ *   The doses, gamma and options->model must stay valid and the doses unchanged until
+ *   gammax_map_wait returns for this ticket; gamma is complete after it returns.
+ *   When the context has no cell table for this geometry yet, the map runs to completion
+ *   inside this call (as gammax_map does) and the wait only returns its result.
+ *   At most GAMMAX_ASYNC_SLOTS maps may be queued and not collected (GAMMAX_E_PARAM).
+ *   Maps on one context run in issue order on their streams; give every map of a context
+ *   the same stream (they share the context's workspace).  Graph replays are fastest when
+ *   successive maps use the same buffers.
+ */
+gammax_status_t gammax_map_async(gammax_ctx_t *ctx, const gammax_problem_t *problem,
+                                 const gammax_options_t *opt, const float *ref_dev,
+                                 const float *eval_dev, float *gamma_dev, uint64_t *ticket,
+                                 void *stream);
+
+/*
+ * Wait for a map queued by gammax_map_async and fill `result` (as gammax_map does).  Each
+ * ticket is collected once; a second wait returns GAMMAX_E_PARAM.  Dose errors
+ * (GAMMAX_E_NONFINITE, GAMMAX_E_DOSE) are reported here.  If the map's search radius
+ * outgrew the cached cell table, the map runs again here, synchronously, on a larger table
+ * (the doses must still hold the same values), and gamma is rewritten.
+ */
+gammax_status_t gammax_map_wait(gammax_ctx_t *ctx, uint64_t ticket, gammax_result_t *result);
+
 /*
  * The problem statement as a flat call (Sec. 2.1): gamma and pass rate of one dose pair
  * with the default options on a library-owned context for the current device.

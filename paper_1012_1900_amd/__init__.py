@@ -17,6 +17,9 @@ from ._abi import (  # noqa: F401
     gamma_map,
     gammax_batch,
     gammax_map,
+    gammax_map_async,
+    MapTicket,
+    ASYNC_SLOTS,
     pass_count,
     sort_pairs,
     status_string,

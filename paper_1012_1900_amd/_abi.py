@@ -120,6 +120,12 @@ _lib.gammax_ctx_destroy.argtypes = [_vp]
 _lib.gammax_map.restype = C.c_int
 _lib.gammax_map.argtypes = [_vp, C.POINTER(Problem), C.POINTER(Options), _vp, _vp, _vp,
                             C.POINTER(Result), _vp]
+_lib.gammax_map_async.restype = C.c_int
+_lib.gammax_map_async.argtypes = [_vp, C.POINTER(Problem), C.POINTER(Options), _vp, _vp, _vp,
+                                  C.POINTER(C.c_uint64), _vp]
+_lib.gammax_map_wait.restype = C.c_int
+_lib.gammax_map_wait.argtypes = [_vp, C.c_uint64, C.POINTER(Result)]
+ASYNC_SLOTS = 64
 _lib.gamma_map.restype = C.c_int
 _lib.gamma_map.argtypes = [_vp, _vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                            C.c_double, C.c_double, C.c_double, C.c_int32, _vp,
@@ -292,6 +298,58 @@ def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
     ctx.check(st)
     res = GammaResult(**{f[0]: getattr(r, f[0]) for f in Result._fields_})
     return out, res
+
+
+class MapTicket:
+    """A map queued by :func:`gammax_map_async`.  ``wait()`` returns its GammaResult (once);
+    ``gamma`` is the output tensor, complete after the wait."""
+
+    def __init__(self, ctx, ticket: int, gamma, keep):
+        self.ctx, self.ticket, self.gamma, self._keep = ctx, ticket, gamma, keep
+        self._res = None
+
+    def wait(self) -> "GammaResult":
+        if self._res is None:
+            r = Result()
+            self.ctx.check(_lib.gammax_map_wait(self.ctx.handle, self.ticket, C.byref(r)))
+            self._res = GammaResult(**{f[0]: getattr(r, f[0]) for f in Result._fields_})
+            self._keep = None
+        return self._res
+
+
+def gammax_map_async(ref, ev, spacing: Sequence[float], dd: float, dta: float,
+                     dose_threshold: float = 0.1, local: bool = False, *, sort: str = "none",
+                     precision: str = "guarded", cond_threshold: float = 1e6, tail_lanes: int = 0,
+                     cell_lanes: int = 0, radius: str = "plain", model=None, radius_factor: float = 1.1,
+                     out=None, ctx: Optional[Context] = None, stream=None) -> MapTicket:
+    """Queue a gamma map without waiting (``gammax_map_async``); the returned ticket's
+    ``wait()`` gives the GammaResult.  The tensors are kept alive until then and must not
+    be modified before it."""
+    torch = _torch()
+    _dev_tensor(ref, "ref")
+    _dev_tensor(ev, "ev")
+    if ref.shape != ev.shape or ref.device != ev.device:
+        raise ValueError("ref and ev must share shape and device")
+    if len(spacing) != ref.dim():
+        raise ValueError("spacing needs one entry per axis")
+    if out is None:
+        out = torch.empty_like(ref)
+    else:
+        _dev_tensor(out, "out")
+        if out.shape != ref.shape or out.device != ref.device:
+            raise ValueError("out must match ref")
+    dev = ref.device.index if ref.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or context(dev)
+    p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
+    o = make_options(sort, precision, cond_threshold, False, tail_lanes, cell_lanes, radius, model,
+                     radius_factor)
+    t = C.c_uint64(0)
+    s = stream if stream is not None else torch.cuda.current_stream(ref.device)
+    with torch.cuda.device(ref.device):
+        st = _lib.gammax_map_async(ctx.handle, C.byref(p), C.byref(o), ref.data_ptr(), ev.data_ptr(),
+                                   out.data_ptr(), C.byref(t), _vp(s.cuda_stream))
+    ctx.check(st)
+    return MapTicket(ctx, t.value, out, (ref, ev, model))
 
 
 def gamma_map(ref_dose, eval_dose, spacing: Sequence[float], dd: float, dta: float,

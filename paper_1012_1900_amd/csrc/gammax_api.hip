@@ -42,6 +42,22 @@ struct GraphKey {
     uint64_t generation;   // bumped on every (re)allocation and table build
 };
 
+// A map queued by gammax_map_async: its arguments (for a re-run at collection time), the
+// event after the copy of its scalars, and its result if it already ran synchronously.
+struct AsyncSlot {
+    uint64_t ticket = 0;      // 0: free
+    bool done = false;        // ran synchronously; `res` is final
+    bool learned = false;
+    hipEvent_t ev = nullptr;
+    hipStream_t stream = nullptr;
+    gammax_problem_t p{};
+    gammax_options_t o{};
+    const float* ref = nullptr;
+    const float* eval = nullptr;
+    float* gamma = nullptr;
+    gammax_result_t res{};
+};
+
 }  // namespace
 
 struct gammax_ctx {
@@ -91,6 +107,10 @@ struct gammax_ctx {
     int64_t yhat_cap = 0;
     struct BatchState* batch = nullptr;   // gammax_batch state (created on first use)
     uint64_t tail_hint = 0;         // tail length of the last map (picks the tail sort variant)
+    // maps queued by gammax_map_async and not yet collected
+    AsyncSlot* slots = nullptr;     // GAMMAX_ASYNC_SLOTS entries, created on first use
+    Scalars* h_ring = nullptr;      // pinned: the scalars of each slot's map
+    uint64_t next_ticket = 1;
 };
 
 void destroy_batch(gammax_ctx* c);
@@ -125,12 +145,21 @@ gammax_status_t fail(gammax_ctx* c, gammax_status_t st, const std::string& why) 
                         std::string(#call) + ": " + hipGetErrorString(e_));                 \
     } while (0)
 
+// Wait for the maps queued by gammax_map_async that may still run (before a buffer or a
+// graph that they use is released).
+void quiesce(gammax_ctx* c) {
+    if (!c->slots) return;
+    for (int i = 0; i < GAMMAX_ASYNC_SLOTS; ++i)
+        if (c->slots[i].ticket && !c->slots[i].done) (void)hipEventSynchronize(c->slots[i].ev);
+}
+
 // Grow a device buffer to `need` elements (contents are not kept).
 template <typename P>
 gammax_status_t grow(gammax_ctx* c, P** p, int64_t* cap, int64_t need) {
     if (need <= *cap && *p) return GAMMAX_OK;
     ++c->generation;
     if (*p) {
+        quiesce(c);
         hipError_t e = hipFree(*p);
         *p = nullptr;
         *cap = 0;
@@ -558,7 +587,10 @@ GraphKey key_of(gammax_ctx* c, const CallSetup& cs) {
 }
 
 void drop_graph(gammax_ctx* c) {
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph) {
+        quiesce(c);
+        (void)hipGraphExecDestroy(c->graph);
+    }
     c->graph = nullptr;
 }
 
@@ -592,8 +624,8 @@ gammax_status_t launch_graph(gammax_ctx* c, const CallSetup& cs, uint32_t m_boun
     return GAMMAX_OK;
 }
 
-void fill_result(gammax_ctx* c, gammax_result_t* res, bool timing, float ms_table, bool cnn) {
-    const Scalars& h = *c->h_sc;
+void fill_result_from(gammax_ctx* c, const Scalars& h, gammax_result_t* res, bool timing, float ms_table,
+                      bool cnn) {
     const float r2 = u2f(h.r2_bits);
     res->n_evaluated = h.n_masked;
     res->n_pass = h.n_pass;
@@ -623,12 +655,18 @@ void fill_result(gammax_ctx* c, gammax_result_t* res, bool timing, float ms_tabl
     c->tail_hint = h.sort_overflow ? (uint64_t)SMALL_SORT_CAP + 1 : h.n_tail;
 }
 
-gammax_status_t device_errors(gammax_ctx* c, bool local) {
-    if (c->h_sc->flags & FLAG_NONFINITE) return fail(c, GAMMAX_E_NONFINITE, "a dose value is NaN or infinite");
-    if (!local && !(ord_to_float(c->h_sc->dmax_ord) > 0.0f))
+void fill_result(gammax_ctx* c, gammax_result_t* res, bool timing, float ms_table, bool cnn) {
+    fill_result_from(c, *c->h_sc, res, timing, ms_table, cnn);
+}
+
+gammax_status_t scalar_errors(gammax_ctx* c, const Scalars& h, bool local) {
+    if (h.flags & FLAG_NONFINITE) return fail(c, GAMMAX_E_NONFINITE, "a dose value is NaN or infinite");
+    if (!local && !(ord_to_float(h.dmax_ord) > 0.0f))
         return fail(c, GAMMAX_E_DOSE, "max reference dose is not positive");
     return GAMMAX_OK;
 }
+
+gammax_status_t device_errors(gammax_ctx* c, bool local) { return scalar_errors(c, *c->h_sc, local); }
 
 // Dose maximum and the global 1/dD of a pair into the context's scalars.
 gammax_status_t enqueue_dose_scalars(gammax_ctx* c, const gammax_problem_t* p, const float* ref, const float* ev,
@@ -656,6 +694,54 @@ gammax_status_t model_inputs(gammax_ctx* c, const gammax_problem_t* p, const flo
     if (p->ndim != 3) return fail(c, GAMMAX_E_SHAPE, "the learned radius is 3D only");
     for (int i = 0; i < 3; ++i) o[i] = (int)p->shape[i];
     return GAMMAX_OK;
+}
+
+// Checks and workspace of one map call (every step of the steady path then runs without a
+// host round trip).  *opt receives the options in effect, *n the node count.
+gammax_status_t map_setup(gammax_ctx* c, const gammax_problem_t* p, const gammax_options_t* opt_in,
+                          const float* ref, const float* ev, const float* gamma, gammax_options_t* opt,
+                          int64_t* n, bool* learned) {
+    if (!ref || !ev || !gamma) return fail(c, GAMMAX_E_NULL, "dose and gamma pointers are required");
+    gammax_status_t st = check_problem(c, p, n);
+    if (st != GAMMAX_OK) return st;
+    if (gamma == ref || gamma == ev) return fail(c, GAMMAX_E_PARAM, "gamma must not alias the dose arrays");
+    if (opt_in) *opt = *opt_in;
+    else gammax_options_default(opt);
+    if ((st = check_options(c, opt)) != GAMMAX_OK) return st;
+    HIPCHK(c, hipSetDevice(c->device));
+    // workspace, sized for all n nodes so that the steady path needs no count from the host
+    if ((st = grow_work(c, *n)) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->blockcnt, &c->blk_cap, prep_words(*n))) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->part, &c->part_cap, 2 * MAX_BLOCKS)) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->hist, &c->hist_cap, sort_hist_words(*n))) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->sums, &c->sums_cap, search_sums_needed((uint32_t)*n))) != GAMMAX_OK) return st;
+    if (opt->timing && (st = ensure_events(c)) != GAMMAX_OK) return st;
+    *learned = uses_model(p, opt);
+    if (*learned && (st = grow(c, &c->yhat, &c->yhat_cap, *n)) != GAMMAX_OK) return st;
+    return GAMMAX_OK;
+}
+
+bool steady_table(const gammax_ctx* c, const gammax_problem_t* p) {
+    return c->tab_valid && same_geom(c->tab_geom, geom_of(p));
+}
+
+// The whole map on the cached table: graph replay, or direct launches for timed calls.
+gammax_status_t enqueue_steady(gammax_ctx* c, const CallSetup& cs, bool timing, hipStream_t s) {
+    gammax_status_t st;
+    const uint32_t n = (uint32_t)cs.n;
+    const float r2_cap = round_down_float(c->tab_geom.r2_cap);
+    // timed calls launch directly: event timestamps are not read back from graph nodes
+    if (!timing && !c->graph_broken) {
+        st = launch_graph(c, cs, n, r2_cap, s);
+        if (st == GAMMAX_OK) return st;
+        // graph unavailable (remembered): queue the kernels directly
+        c->graph_broken = true;
+        drop_graph(c);
+        (void)hipGetLastError();
+    }
+    if ((st = enqueue_prep(c, cs, s, timing ? c->ev[0] : nullptr, timing ? c->ev[1] : nullptr)) != GAMMAX_OK)
+        return st;
+    return enqueue_search(c, cs, n, r2_cap, s, timing);
 }
 
 }  // namespace
@@ -716,7 +802,11 @@ gammax_status_t gammax_ctx_destroy(gammax_ctx_t* c) {
     for (void* p : dev)
         if (p) (void)hipFree(p);
     destroy_batch(c);
-    void* host[] = {c->h_sc, c->h_cnt, c->h_count};
+    if (c->slots) {
+        for (int i = 0; i < GAMMAX_ASYNC_SLOTS; ++i) (void)hipEventDestroy(c->slots[i].ev);
+        delete[] c->slots;
+    }
+    void* host[] = {c->h_sc, c->h_cnt, c->h_count, c->h_ring};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
     if (c->events)
@@ -729,58 +819,22 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
                            const float* ref, const float* ev, float* gamma, gammax_result_t* res,
                            void* stream) {
     if (!c) return GAMMAX_E_NULL;
-    if (!ref || !ev || !gamma || !res) return fail(c, GAMMAX_E_NULL, "dose, gamma and result pointers are required");
+    if (!res) return fail(c, GAMMAX_E_NULL, "result pointer is required");
     int64_t n = 0;
-    gammax_status_t st = check_problem(c, p, &n);
-    if (st != GAMMAX_OK) return st;
-    if ((const float*)gamma == ref || (const float*)gamma == ev)
-        return fail(c, GAMMAX_E_PARAM, "gamma must not alias the dose arrays");
+    bool learned = false;
     gammax_options_t opt;
-    if (opt_in) opt = *opt_in;
-    else gammax_options_default(&opt);
-    if ((st = check_options(c, &opt)) != GAMMAX_OK) return st;
+    gammax_status_t st = map_setup(c, p, opt_in, ref, ev, gamma, &opt, &n, &learned);
+    if (st != GAMMAX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(c, hipSetDevice(c->device));
     std::memset(res, 0, sizeof(*res));
     const bool timing = opt.timing != 0;
     const bool local = p->norm == GAMMAX_LOCAL;
-
-    // workspace, sized for all n nodes so that the steady path needs no count from the host
-    const int64_t ntiles = prep_tiles(n);
-    if ((st = grow_work(c, n)) != GAMMAX_OK) return st;
-    if ((st = grow(c, &c->blockcnt, &c->blk_cap, prep_words(n))) != GAMMAX_OK) return st;
-    if ((st = grow(c, &c->part, &c->part_cap, 2 * MAX_BLOCKS)) != GAMMAX_OK) return st;
-    if ((st = grow(c, &c->hist, &c->hist_cap, sort_hist_words(n))) != GAMMAX_OK) return st;
-    if ((st = grow(c, &c->sums, &c->sums_cap, search_sums_needed((uint32_t)n))) != GAMMAX_OK) return st;
-    if (timing && (st = ensure_events(c)) != GAMMAX_OK) return st;
-    const bool learned = uses_model(p, &opt);
-    if (learned && (st = grow(c, &c->yhat, &c->yhat_cap, n)) != GAMMAX_OK) return st;
-
     CallSetup cs{p, &opt, ref, ev, gamma, n};
     const TableGeom g = geom_of(p);
 
     // steady state: the cached table serves this geometry; no host round trip before the end
-    if (c->tab_valid && same_geom(c->tab_geom, g)) {
-        const float r2_cap = round_down_float(c->tab_geom.r2_cap);
-        // timed calls launch directly: event timestamps are not read back from graph nodes
-        if (timing || c->graph_broken) {
-            if ((st = enqueue_prep(c, cs, s, timing ? c->ev[0] : nullptr, timing ? c->ev[1] : nullptr)) != GAMMAX_OK)
-                return st;
-            if ((st = enqueue_search(c, cs, (uint32_t)n, r2_cap, s, timing)) != GAMMAX_OK) return st;
-        } else {
-            st = launch_graph(c, cs, (uint32_t)n, r2_cap, s);
-            if (st != GAMMAX_OK) {
-                // graph unavailable (remembered unless only the timed capture failed): queue
-                // the kernels directly
-                if (!timing) c->graph_broken = true;
-                drop_graph(c);
-                (void)hipGetLastError();
-                if ((st = enqueue_prep(c, cs, s, timing ? c->ev[0] : nullptr, timing ? c->ev[1] : nullptr)) !=
-                    GAMMAX_OK)
-                    return st;
-                if ((st = enqueue_search(c, cs, (uint32_t)n, r2_cap, s, timing)) != GAMMAX_OK) return st;
-            }
-        }
+    if (steady_table(c, p)) {
+        if ((st = enqueue_steady(c, cs, timing, s)) != GAMMAX_OK) return st;
         HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
         if ((st = device_errors(c, local)) != GAMMAX_OK) return st;
@@ -824,6 +878,91 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
     HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     fill_result(c, res, timing, ms_table, learned);
+    return GAMMAX_OK;
+}
+
+gammax_status_t gammax_map_async(gammax_ctx_t* c, const gammax_problem_t* p, const gammax_options_t* opt_in,
+                                 const float* ref, const float* ev, float* gamma, uint64_t* ticket, void* stream) {
+    if (!c) return GAMMAX_E_NULL;
+    if (!ticket) return fail(c, GAMMAX_E_NULL, "ticket pointer is required");
+    *ticket = 0;
+    if (opt_in && opt_in->timing) return fail(c, GAMMAX_E_PARAM, "timing is not available for queued maps");
+    int64_t n = 0;
+    bool learned = false;
+    gammax_options_t opt;
+    gammax_status_t st = map_setup(c, p, opt_in, ref, ev, gamma, &opt, &n, &learned);
+    if (st != GAMMAX_OK) return st;
+    if (!c->slots) {
+        AsyncSlot* sl = new (std::nothrow) AsyncSlot[GAMMAX_ASYNC_SLOTS];
+        if (!sl) return fail(c, GAMMAX_E_NOMEM, "queued map slots");
+        for (int i = 0; i < GAMMAX_ASYNC_SLOTS; ++i) {
+            if (hipEventCreateWithFlags(&sl[i].ev, hipEventDisableTiming) != hipSuccess) {
+                for (int k = 0; k < i; ++k) (void)hipEventDestroy(sl[k].ev);
+                delete[] sl;
+                return fail(c, GAMMAX_E_DEVICE, "hipEventCreateWithFlags failed");
+            }
+        }
+        if (hipHostMalloc((void**)&c->h_ring, sizeof(Scalars) * GAMMAX_ASYNC_SLOTS, hipHostMallocDefault) !=
+            hipSuccess) {
+            c->h_ring = nullptr;
+            for (int i = 0; i < GAMMAX_ASYNC_SLOTS; ++i) (void)hipEventDestroy(sl[i].ev);
+            delete[] sl;
+            return fail(c, GAMMAX_E_NOMEM, "pinned scalars of the queued maps");
+        }
+        c->slots = sl;
+    }
+    const int i = (int)(c->next_ticket % GAMMAX_ASYNC_SLOTS);
+    AsyncSlot& sl = c->slots[i];
+    if (sl.ticket)
+        return fail(c, GAMMAX_E_PARAM, "GAMMAX_ASYNC_SLOTS maps are in flight: collect one with gammax_map_wait");
+    hipStream_t s = (hipStream_t)stream;
+    sl.p = *p;
+    sl.o = opt;
+    sl.ref = ref;
+    sl.eval = ev;
+    sl.gamma = gamma;
+    sl.stream = s;
+    sl.learned = learned;
+    if (steady_table(c, p)) {
+        // the whole map, then its scalars into this slot's pinned copy; nothing waits
+        CallSetup cs{p, &opt, ref, ev, gamma, n};
+        if ((st = enqueue_steady(c, cs, false, s)) != GAMMAX_OK) return st;
+        HIPCHK(c, hipMemcpyAsync(&c->h_ring[i], c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipEventRecord(sl.ev, s));
+        sl.done = false;
+    } else {
+        // no table for this geometry yet: the map runs to completion here (it builds one)
+        if ((st = gammax_map(c, p, &opt, ref, ev, gamma, &sl.res, stream)) != GAMMAX_OK) return st;
+        sl.done = true;
+    }
+    sl.ticket = c->next_ticket++;
+    *ticket = sl.ticket;
+    return GAMMAX_OK;
+}
+
+gammax_status_t gammax_map_wait(gammax_ctx_t* c, uint64_t ticket, gammax_result_t* res) {
+    if (!c) return GAMMAX_E_NULL;
+    if (!res) return fail(c, GAMMAX_E_NULL, "result pointer is required");
+    if (!c->slots || ticket == 0 || c->slots[ticket % GAMMAX_ASYNC_SLOTS].ticket != ticket)
+        return fail(c, GAMMAX_E_PARAM, "unknown ticket (never issued or already collected)");
+    const int i = (int)(ticket % GAMMAX_ASYNC_SLOTS);
+    AsyncSlot& sl = c->slots[i];
+    sl.ticket = 0;   // collected, whatever follows
+    if (sl.done) {
+        *res = sl.res;
+        return GAMMAX_OK;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipEventSynchronize(sl.ev));
+    const Scalars& h = c->h_ring[i];
+    gammax_status_t st = scalar_errors(c, h, sl.p.norm == GAMMAX_LOCAL);
+    if (st != GAMMAX_OK) return st;
+    if (h.flags & FLAG_TABLE_SHORT) {
+        // the radius outgrew the cached table: the map again, synchronously, on a larger one
+        return gammax_map(c, &sl.p, &sl.o, sl.ref, sl.eval, sl.gamma, res, sl.stream);
+    }
+    std::memset(res, 0, sizeof(*res));
+    fill_result_from(c, h, res, false, 0.0f, sl.learned);
     return GAMMAX_OK;
 }
 

@@ -484,42 +484,51 @@ __device__ __forceinline__ void patch_layer(const uint16_t* __restrict__ in, uin
     }
 }
 
-// The features of the 9^3 patch around `node` (zero outside the grid), as packed bf16 pairs.
+// The features of rounds [R0, R0 + NR) of the 9^3 patch around `node` (zero outside the
+// grid), stored into Y as packed bf16 pairs.  Every lane loads a node in every round (a
+// clamped in-grid node where the patch leaves the grid) and all loads are issued before
+// any is used, so the rounds share one memory latency; the empty asm keeps the compiler
+// from sinking each load into its own branch.
+template <int R0, int NR>
 __device__ __forceinline__ void tail_gather(const TailCnnArgs& a, int node, float inv_max, float inv_dd,
-                                            uint32_t (&q)[TAIL_GATHER]) {
+                                            uint16_t* Y) {
     const int lane = threadIdx.x & 63;
     const int x0 = node % a.nx - 4, y0 = (node / a.nx) % a.ny - 4, z0 = node / (a.nx * a.ny) - 4;
+    float rv[NR], ev[NR];
+    uint32_t inside = 0u;
 #pragma unroll
-    for (int r = 0; r < TAIL_GATHER; ++r) {
-        const int v = lane + 64 * r;
+    for (int r = 0; r < NR; ++r) {
+        const int u = lane + 64 * (R0 + r);
+        const int v = u < 729 ? u : 728;
         const int x = x0 + v % 9, y = y0 + (v / 9) % 9, z = z0 + v / 81;
-        float rv = 0.f, ev = 0.f;
-        const bool in = v < 729 && x >= 0 && x < a.nx && y >= 0 && y < a.ny && z >= 0 && z < a.nz;
-        if (in) {
-            const int64_t n = ((int64_t)z * a.ny + y) * a.nx + x;
-            rv = a.ref[n];
-            ev = a.ev[n];
-        }
-        q[r] = in ? ((uint32_t)f2bf(rv * inv_max) | ((uint32_t)f2bf((ev - rv) * inv_dd) << 16)) : 0u;
+        const bool in = u < 729 && x >= 0 && x < a.nx && y >= 0 && y < a.ny && z >= 0 && z < a.nz;
+        inside |= in ? (1u << r) : 0u;
+        const int xc = min(max(x, 0), a.nx - 1), yc = min(max(y, 0), a.ny - 1), zc = min(max(z, 0), a.nz - 1);
+        const int64_t n = ((int64_t)zc * a.ny + yc) * a.nx + xc;
+        rv[r] = a.ref[n];
+        ev[r] = a.ev[n];
     }
-}
-
-__device__ __forceinline__ void tail_store(uint16_t* Y, const uint32_t (&q)[TAIL_GATHER]) {
-    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int r = 0; r < TAIL_GATHER; ++r)
-        if (lane + 64 * r < 729) reinterpret_cast<uint32_t*>(Y)[lane + 64 * r] = q[r];
+    for (int r = 0; r < NR; ++r) {
+        asm volatile("" : "+v"(rv[r]), "+v"(ev[r]));
+        const uint32_t pk = (uint32_t)f2bf(rv[r] * inv_max) | ((uint32_t)f2bf((ev[r] - rv[r]) * inv_dd) << 16);
+        const int u = lane + 64 * (R0 + r);
+        if (u < 729) reinterpret_cast<uint32_t*>(Y)[u] = ((inside >> r) & 1u) ? pk : 0u;
+    }
 }
 
 __global__ __launch_bounds__(TAIL_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_cnn_tail(TailCnnArgs a) {
     __shared__ __align__(16) uint16_t X[TAIL_X_ELEMS];
     __shared__ __align__(16) uint16_t Y[TAIL_Y_ELEMS];
+    // constants of the whole run: biases of layers 1-3, bf16-rounded layer 4 weights in
+    // (tap, channel) order, layer 4 bias
+    __shared__ float C[3 * 16 + 432 + 1];
     const uint32_t M = *a.count;
     if (blockIdx.x >= M) return;
     const int lane = threadIdx.x & 63;
     const float inv_max = 1.0f / ord_to_float(a.sc->dmax_ord);
     const float inv_dd = a.sc->inv_dd;
-    // weights of the whole run: fragments and biases of layers 1-3, bf16 weights of layer 4
+    // fragments of layers 1-3, held for the whole run
     U4 w0[2], w1[14], w2[14];
 #pragma unroll
     for (int c = 0; c < 2; ++c) w0[c] = reinterpret_cast<const U4*>(a.frag[0])[c * 64 + lane];
@@ -529,30 +538,37 @@ __global__ __launch_bounds__(TAIL_THREADS) __attribute__((amdgpu_waves_per_eu(2,
         w2[c] = reinterpret_cast<const U4*>(a.frag[2])[c * 64 + lane];
     }
     constexpr int K4 = (432 + 63) / 64;   // layer 4: 27 taps x 16 channels, tap-major
+    for (int k = lane; k < 3 * 16 + 432 + 1; k += 64) {
+        float v;
+        if (k < 48) v = a.bias[k >> 4][k & 15];
+        else if (k < 48 + 432) v = bf2f(f2bf(a.w4[((k - 48) & 15) * 27 + ((k - 48) >> 4)]));
+        else v = *a.b4;
+        C[k] = v;
+    }
 
+    int node_next = (int)a.nodes[blockIdx.x];
     for (uint32_t item = blockIdx.x; item < M; item += gridDim.x) {
-        {
-            uint32_t q[TAIL_GATHER];
-            tail_gather(a, (int)a.nodes[item], inv_max, inv_dd, q);
-            __syncthreads();   // the previous node's layer 4 has read X
-            tail_store(Y, q);
-        }
+        const int node = node_next;
+        if (item + gridDim.x < M) node_next = (int)a.nodes[item + gridDim.x];
+        // Y is free: the previous node's layer 3 read it before the barrier that followed
+        tail_gather<0, TAIL_GATHER / 2>(a, node, inv_max, inv_dd, Y);
+        tail_gather<TAIL_GATHER / 2, TAIL_GATHER - TAIL_GATHER / 2>(a, node, inv_max, inv_dd, Y);
         __syncthreads();
-        patch_layer<2, 9, 7, 2>(Y, X, w0, a.bias[0]);
+        patch_layer<2, 9, 7, 2>(Y, X, w0, C);
         __syncthreads();
-        patch_layer<16, 7, 5, 14>(X, Y, w1, a.bias[1]);
+        patch_layer<16, 7, 5, 14>(X, Y, w1, C + 16);
         __syncthreads();
-        patch_layer<16, 5, 3, 14>(Y, X, w2, a.bias[2]);
+        patch_layer<16, 5, 3, 14>(Y, X, w2, C + 32);
         __syncthreads();
         float s = 0.f;
 #pragma unroll
         for (int r = 0; r < K4; ++r) {
             const int k = lane + 64 * r;
-            if (k < 432) s += bf2f(f2bf(a.w4[(k & 15) * 27 + (k >> 4)])) * bf2f(X[k]);
+            if (k < 432) s += C[48 + k] * bf2f(X[k]);
         }
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
         if (lane == 0) {
-            const float y = *a.b4 + s;
+            const float y = C[48 + 432] + s;
             a.y[item] = y;
             if (a.key) a.key[item] = f2u(fmaxf(expf(y) - 0.01f, 0.0f));
         }

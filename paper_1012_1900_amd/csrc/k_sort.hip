@@ -148,23 +148,41 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small_rank(const uint32_
                                                                    const uint32_t* __restrict__ vals,
                                                                    uint32_t* __restrict__ tk, uint32_t* __restrict__ tv,
                                                                    const uint32_t* n_dev, uint32_t* overflow) {
-    __shared__ uint32_t sk[SMALL_SORT_CAP];
+    __shared__ __align__(16) uint32_t sk[SMALL_SORT_CAP];
     const uint32_t n = *n_dev;
     if (n > (uint32_t)SMALL_SORT_CAP) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *overflow = 1u;
         return;
     }
     if (blockIdx.x * SMALL_THREADS >= n) return;
-    for (uint32_t i = threadIdx.x; i < n; i += SMALL_THREADS) sk[i] = keys[i];
+    // keys padded to a multiple of 16 with the largest value (they rank after every key)
+    const uint32_t n16 = (n + 15u) & ~15u;
+    for (uint32_t j = threadIdx.x; j < n16; j += SMALL_THREADS) sk[j] = j < n ? keys[j] : 0xFFFFFFFFu;
     __syncthreads();
     const uint32_t i = blockIdx.x * SMALL_THREADS + threadIdx.x;
     if (i >= n) return;
     const uint32_t k = sk[i];
-    uint32_t rank = 0;
-    for (uint32_t j = 0; j < n; ++j) {
-        const uint32_t kj = sk[j];
-        rank += (kj < k || (kj == k && j < i)) ? 1u : 0u;
+    // rank = #{j : key_j < k} + #{j < i : key_j == k}: the first term over all keys (the
+    // padding never counts), the second over the keys before i.  Sixteen keys per step
+    // from four 16-byte LDS reads, so the reads overlap instead of forming one chain.
+    uint32_t less = 0, eq_before = 0;
+    const uint4* s4 = reinterpret_cast<const uint4*>(sk);
+    for (uint32_t j = 0; j < n16; j += 16) {
+        uint4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = s4[(j >> 2) + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t kk[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t jj = j + 4 * u + e;
+                less += kk[e] < k ? 1u : 0u;
+                eq_before += (kk[e] == k && jj < i) ? 1u : 0u;
+            }
+        }
     }
+    const uint32_t rank = less + eq_before;
     tk[rank] = k;
     tv[rank] = vals[i];
 }
