@@ -38,7 +38,7 @@ TRAFFIC = {
     "3d_128x128x96_2.5mm": {
         "bytes": (15.62 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "40d3e51772ca84746b9ac516dcfa7fe3874f3d079c6d5e6ce1cbf8fbceb02adf",
+        "sha256": "e034ba34f700b36316f4e4a594f1ce72bcd070463a16de0c669f9945df6500b5",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }

@@ -129,6 +129,10 @@ int64_t sort_hist_words(int64_t n_max);
 constexpr int SMALL_SORT_CAP = 4096;
 hipError_t sort_pairs_small(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
                             const uint32_t* n_dev, uint32_t* overflow, hipStream_t s);
+// The same rank sort of a list whose values are its positions 0..n-1: order[] receives the
+// positions in stable key order (one launch; the keys stay where they are).
+hipError_t sort_order_small(const uint32_t* keys, uint32_t* order, const uint32_t* n_dev, uint32_t* overflow,
+                            hipStream_t s);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
                             int64_t n_max, const uint32_t* n_dev, uint32_t* hist, hipStream_t s);
 

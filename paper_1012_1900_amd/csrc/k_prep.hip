@@ -8,9 +8,9 @@
 //      tile-group sums);
 //   2. every block reduces those partials itself (a few KB from L2), derives the
 //      threshold and the global 1/dD, then counts the masked nodes of its tile and their
-//      max gamma0^2, stores the count and adds both into its tile group (about sqrt(tiles)
-//      tiles per group, so no address sees many atomics); block 0 also stores the scalars
-//      and clears the search counters;
+//      max gamma0^2, stores the count and adds both into its tile group (about
+//      sqrt(tiles) / 8 tiles per group, so no address sees many atomics); block 0 also
+//      stores the scalars and clears the search counters;
 //   3. ordered emit of the masked node indices: a block's first slot is the sum of the
 //      groups before its own plus the tiles of its group before it; the last block stores
 //      M and R^2.
@@ -54,12 +54,24 @@ __device__ __forceinline__ void block_max_or(uint32_t& m, uint32_t& f) {
 // 1. dose maximum and finiteness of both doses, one partial per block (vb of vgrid).
 __device__ __forceinline__ void dose_max_body(const PrepArgs& a, int vb, int vgrid) {
     uint32_t best = 0u, bad = 0u;
-    const int64_t stride = (int64_t)vgrid * PREP_THREADS;
-    for (int64_t i = (int64_t)vb * PREP_THREADS + threadIdx.x; i < a.n; i += stride) {
-        const float r = a.ref[i];
-        const float e = a.ev[i];
-        bad |= (!isfinite(r) || !isfinite(e)) ? 1u : 0u;
-        best = max(best, float_to_ord(r));
+    // DM_ITEMS nodes per thread per step, all loads of a step issued before the first use
+    // (indices clamped to the last node; the clamped copies do not change a max or an or)
+    constexpr int DM_ITEMS = 8;
+    const int64_t step = (int64_t)vgrid * PREP_THREADS * DM_ITEMS;
+    for (int64_t b0 = (int64_t)vb * PREP_THREADS * DM_ITEMS; b0 < a.n; b0 += step) {
+        float r[DM_ITEMS], e[DM_ITEMS];
+#pragma unroll
+        for (int k = 0; k < DM_ITEMS; ++k) {
+            const int64_t i = b0 + (int64_t)k * PREP_THREADS + threadIdx.x;
+            const int64_t j = i < a.n ? i : a.n - 1;
+            r[k] = a.ref[j];
+            e[k] = a.ev[j];
+        }
+#pragma unroll
+        for (int k = 0; k < DM_ITEMS; ++k) {
+            bad |= (!isfinite(r[k]) || !isfinite(e[k])) ? 1u : 0u;
+            best = max(best, float_to_ord(r[k]));
+        }
     }
     block_max_or(best, bad);
     if (threadIdx.x == 0) {
@@ -97,10 +109,31 @@ __device__ __forceinline__ bool node_masked(float dr, float thr_val, int local) 
 // 2. every block: the dose maximum from the partials, then per tile the masked count, max
 // gamma0^2 and -1 for unmasked nodes.  Block 0 stores the scalars of this map.
 __device__ __forceinline__ void prep_count_body(const PrepArgs& a, int nb_red, int vb) {
+    // this tile's doses first (they do not depend on the dose maximum), then the partials:
+    // all loads in flight together, indices clamped to valid entries
+    const int64_t base = (int64_t)vb * PREP_TILE;
+    float rr[PREP_ITEMS], ee[PREP_ITEMS];
+#pragma unroll
+    for (int k = 0; k < PREP_ITEMS; ++k) {
+        const int64_t i = base + (int64_t)k * PREP_THREADS + threadIdx.x;
+        const int64_t j = i < a.n ? i : a.n - 1;
+        rr[k] = a.ref[j];
+        ee[k] = a.ev[j];
+    }
+    constexpr int PR = MAX_BLOCKS / PREP_THREADS;
+    uint32_t pm[PR], pb[PR];
+#pragma unroll
+    for (int r = 0; r < PR; ++r) {
+        const int j = threadIdx.x + PREP_THREADS * r;
+        const int jj = j < nb_red ? j : 0;
+        pm[r] = a.part[jj];
+        pb[r] = a.part[MAX_BLOCKS + jj];
+    }
     uint32_t dm = 0u, bad = 0u;
-    for (int j = threadIdx.x; j < nb_red; j += PREP_THREADS) {
-        dm = max(dm, a.part[j]);
-        bad |= a.part[MAX_BLOCKS + j];
+#pragma unroll
+    for (int r = 0; r < PR; ++r) {
+        dm = max(dm, pm[r]);
+        bad |= pb[r];
     }
     block_max_or(dm, bad);
     const float dmax = ord_to_float(dm);
@@ -127,15 +160,14 @@ __device__ __forceinline__ void prep_count_body(const PrepArgs& a, int nb_red, i
             sc->n_cells = 0ull;
         }
     }
-    const int64_t base = (int64_t)vb * PREP_TILE;
     uint32_t cnt = 0u, best = 0u;
 #pragma unroll
     for (int k = 0; k < PREP_ITEMS; ++k) {
         const int64_t i = base + (int64_t)k * PREP_THREADS + threadIdx.x;
         if (i < a.n) {
-            const float dr = a.ref[i];
+            const float dr = rr[k];
             if (node_masked(dr, thr_val, a.local)) {
-                const float de = a.ev[i];
+                const float de = ee[k];
                 const float g2 = gamma0_sq(de, dr, node_inv_dd(dr, inv_dd_g, a.dd, a.local));
                 best = max(best, f2u(g2));
                 ++cnt;
@@ -171,6 +203,13 @@ __device__ __forceinline__ void prep_emit_body(const PrepArgs& a, int vb) {
     __shared__ uint32_t s_pre[PREP_THREADS / WAVE];
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    // this tile's reference doses (clamped indices), in flight while the prefix is summed
+    float rr[PREP_ITEMS];
+#pragma unroll
+    for (int k = 0; k < PREP_ITEMS; ++k) {
+        const int64_t i = base + (int64_t)k * PREP_THREADS + threadIdx.x;
+        rr[k] = a.ref[i < a.n ? i : a.n - 1];
+    }
     // first slot of this tile: the groups before its own, then its group's earlier tiles
     {
         const int grp = vb >> a.super_shift;
@@ -185,7 +224,7 @@ __device__ __forceinline__ void prep_emit_body(const PrepArgs& a, int vb) {
 #pragma unroll
     for (int k = 0; k < PREP_ITEMS; ++k) {
         const int64_t i = base + (int64_t)k * PREP_THREADS + threadIdx.x;
-        m[k] = i < a.n && node_masked(a.ref[i], thr_val, a.local);
+        m[k] = i < a.n && node_masked(rr[k], thr_val, a.local);
         bal[k] = __ballot(m[k]);
         if (lane == 0) s_wave[k][w] = (uint32_t)__popcll(bal[k]);
     }
@@ -278,9 +317,12 @@ int reduce_blocks(int64_t n) {
 int64_t prep_tiles(int64_t n) { return (n + PREP_TILE - 1) / PREP_TILE; }
 
 void prep_groups(int64_t n, int* shift, int* n_super) {
+    // 2^sh tiles per group with 4^(sh + 3) >= tiles: about sqrt(tiles) / 8 tiles share a
+    // group counter (same-address atomics from blocks on every XCD serialise), and the
+    // emit reads about 8 sqrt(tiles) group sums
     const int64_t t = prep_tiles(n);
     int sh = 0;
-    while (((int64_t)1 << (2 * sh)) < t) ++sh;
+    while (((int64_t)1 << (2 * (sh + 3))) < t) ++sh;
     *shift = sh;
     *n_super = (int)((t + ((int64_t)1 << sh) - 1) >> sh);
 }

@@ -1297,8 +1297,7 @@ hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s
         // tail sort (count read on the device)
         if (p.hist) {
             hipError_t e = p.small_sort
-                               ? sort_pairs_small(a.tail_key_arr, a.tail_pos, p.tmp_keys, p.tmp_vals, &a.sc->n_tail,
-                                                  &a.sc->sort_overflow, s)
+                               ? sort_order_small(a.tail_key_arr, a.tail_pos, &a.sc->n_tail, &a.sc->sort_overflow, s)
                                : radix_sort_pairs(a.tail_key_arr, a.tail_pos, p.tmp_keys, p.tmp_vals, p.M,
                                                   &a.sc->n_tail, p.hist, s);
             if (e != hipSuccess) return e;

@@ -137,54 +137,82 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 }
 
 // Short lists: each element's place is the number of smaller keys plus the number of
-// equal keys before it (a stable rank).  Every workgroup holds all keys in LDS and ranks
-// 256 of them against the whole list (broadcast reads), writing them to the scratch pair
-// at their places; a second pass copies them back.  For n <= SMALL_SORT_CAP; a longer list
-// is left as it is and *overflow set (the callers sort only to order work, so any order
-// is correct).
+// equal keys before it (a stable rank).  A workgroup ranks 64 keys: it holds the whole list
+// in LDS and each of its four waves counts against one quarter of it (broadcast reads),
+// the quarters then summed in LDS, so the O(n) comparisons of a key are spread over four
+// waves and the grid has n/16 waves.  For n <= SMALL_SORT_CAP; a longer list is left as it
+// is and *overflow set (the callers sort only to order work, so any order is correct).
+// ORDER_ONLY: the values are the positions 0..n-1 (a work list in its queue order); the
+// sorted positions are written straight into `vals` and the keys are not moved.
+// Otherwise the pairs go to the scratch arrays at their places and a second pass copies
+// them back.
 constexpr int SMALL_THREADS = 256;
-constexpr int SMALL_BLOCKS = SMALL_SORT_CAP / SMALL_THREADS;
+constexpr int SMALL_KEYS = 64;    // keys ranked per workgroup
+constexpr int SMALL_BLOCKS = SMALL_SORT_CAP / SMALL_KEYS;
+template <bool ORDER_ONLY>
 __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small_rank(const uint32_t* __restrict__ keys,
-                                                                   const uint32_t* __restrict__ vals,
+                                                                   uint32_t* __restrict__ vals,
                                                                    uint32_t* __restrict__ tk, uint32_t* __restrict__ tv,
                                                                    const uint32_t* n_dev, uint32_t* overflow) {
     __shared__ __align__(16) uint32_t sk[SMALL_SORT_CAP];
+    __shared__ uint32_t s_part[SMALL_THREADS / SMALL_KEYS][SMALL_KEYS];
     const uint32_t n = *n_dev;
     if (n > (uint32_t)SMALL_SORT_CAP) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *overflow = 1u;
         return;
     }
-    if (blockIdx.x * SMALL_THREADS >= n) return;
-    // keys padded to a multiple of 16 with the largest value (they rank after every key)
-    const uint32_t n16 = (n + 15u) & ~15u;
-    for (uint32_t j = threadIdx.x; j < n16; j += SMALL_THREADS) sk[j] = j < n ? keys[j] : 0xFFFFFFFFu;
-    __syncthreads();
-    const uint32_t i = blockIdx.x * SMALL_THREADS + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t k = sk[i];
-    // rank = #{j : key_j < k} + #{j < i : key_j == k}: the first term over all keys (the
-    // padding never counts), the second over the keys before i.  Sixteen keys per step
-    // from four 16-byte LDS reads, so the reads overlap instead of forming one chain.
-    uint32_t less = 0, eq_before = 0;
-    const uint4* s4 = reinterpret_cast<const uint4*>(sk);
-    for (uint32_t j = 0; j < n16; j += 16) {
-        uint4 q[4];
+    if (blockIdx.x * SMALL_KEYS >= n) return;
+    // keys padded to a multiple of 64 with the largest value (they rank after every key);
+    // every thread issues all its loads (clamped to the last key) before the first store,
+    // so the staging costs one memory latency
+    const uint32_t n64 = (n + 63u) & ~63u;
+    {
+        constexpr int R = SMALL_SORT_CAP / SMALL_THREADS;
+        uint32_t v[R];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) q[u] = s4[(j >> 2) + u];
+        for (int r = 0; r < R; ++r) {
+            const uint32_t j = threadIdx.x + SMALL_THREADS * r;
+            v[r] = keys[j < n ? j : n - 1];
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t kk[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t jj = j + 4 * u + e;
-                less += kk[e] < k ? 1u : 0u;
-                eq_before += (kk[e] == k && jj < i) ? 1u : 0u;
-            }
+        for (int r = 0; r < R; ++r) {
+            asm volatile("" : "+v"(v[r]));
+            const uint32_t j = threadIdx.x + SMALL_THREADS * r;
+            if (j < n64) sk[j] = j < n ? v[r] : 0xFFFFFFFFu;
         }
     }
-    const uint32_t rank = less + eq_before;
-    tk[rank] = k;
-    tv[rank] = vals[i];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & (SMALL_KEYS - 1), part = threadIdx.x / SMALL_KEYS;
+    const uint32_t i = blockIdx.x * SMALL_KEYS + lane;
+    const uint32_t k = sk[i < n ? i : 0];
+    // this wave's quarter [j0, j1) of the list (a multiple of 16 long)
+    const uint32_t q = n64 / 4;
+    const uint32_t j0 = part * q, j1 = j0 + q;
+    // #{j : key_j < k} + #{j < i : key_j == k} over the quarter; the padding never counts
+    uint32_t cnt = 0;
+    const uint4* s4 = reinterpret_cast<const uint4*>(sk);
+    for (uint32_t j = j0; j < j1; j += 16) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = s4[(j >> 2) + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t kk[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cnt += (kk[e] < k || (kk[e] == k && j + 4 * u + e < i)) ? 1u : 0u;
+        }
+    }
+    s_part[part][lane] = cnt;
+    __syncthreads();
+    if (part != 0 || i >= n) return;
+    uint32_t rank = 0;
+    for (int p = 0; p < SMALL_THREADS / SMALL_KEYS; ++p) rank += s_part[p][lane];
+    if (ORDER_ONLY) {
+        vals[rank] = i;
+    } else {
+        tk[rank] = k;
+        tv[rank] = vals[i];
+    }
 }
 
 __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small_copy(uint32_t* __restrict__ keys,
@@ -194,8 +222,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small_copy(uint32_t* __r
                                                                    const uint32_t* n_dev) {
     const uint32_t n = *n_dev;
     if (n > (uint32_t)SMALL_SORT_CAP) return;
-    const uint32_t i = blockIdx.x * SMALL_THREADS + threadIdx.x;
-    if (i < n) {
+    for (uint32_t i = blockIdx.x * SMALL_THREADS + threadIdx.x; i < n; i += gridDim.x * SMALL_THREADS) {
         keys[i] = tk[i];
         vals[i] = tv[i];
     }
@@ -205,10 +232,17 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small_copy(uint32_t* __r
 
 hipError_t sort_pairs_small(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
                             const uint32_t* n_dev, uint32_t* overflow, hipStream_t s) {
-    hipLaunchKernelGGL(k_sort_small_rank, dim3(SMALL_BLOCKS), dim3(SMALL_THREADS), 0, s, keys, vals, tmp_keys,
-                       tmp_vals, n_dev, overflow);
-    hipLaunchKernelGGL(k_sort_small_copy, dim3(SMALL_BLOCKS), dim3(SMALL_THREADS), 0, s, keys, vals, tmp_keys,
-                       tmp_vals, n_dev);
+    hipLaunchKernelGGL(k_sort_small_rank<false>, dim3(SMALL_BLOCKS), dim3(SMALL_THREADS), 0, s, keys, vals,
+                       tmp_keys, tmp_vals, n_dev, overflow);
+    hipLaunchKernelGGL(k_sort_small_copy, dim3(SMALL_SORT_CAP / SMALL_THREADS), dim3(SMALL_THREADS), 0, s, keys,
+                       vals, tmp_keys, tmp_vals, n_dev);
+    return hipGetLastError();
+}
+
+hipError_t sort_order_small(const uint32_t* keys, uint32_t* order, const uint32_t* n_dev, uint32_t* overflow,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_sort_small_rank<true>, dim3(SMALL_BLOCKS), dim3(SMALL_THREADS), 0, s, keys, order,
+                       nullptr, nullptr, n_dev, overflow);
     return hipGetLastError();
 }
 
