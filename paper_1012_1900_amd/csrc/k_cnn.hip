@@ -432,8 +432,33 @@ constexpr int TAIL_X_ELEMS = 343 * 16;   // bf16
 constexpr int TAIL_Y_ELEMS = 125 * 16;   // >= 729 * 2 features
 constexpr int TAIL_GATHER = (729 + 63) / 64;
 
+// B operand of chunk c for the output node whose input-patch base index is `base` (this
+// lane's k slice: 8 channels of one tap for 16 input channels, 4 taps x 2 channels for 2).
+template <int CIN, int IN_E>
+__device__ __forceinline__ U4 patch_bop(const uint16_t* __restrict__ in, int base, int c, int g) {
+    if (CIN == 16) {
+        int t = 2 * c + (g >> 1);
+        t = t > 26 ? 26 : t;
+        int dz, dy, dx;
+        tap_xyz(t, dz, dy, dx);
+        return *reinterpret_cast<const U4*>(&in[(base + (dz * IN_E + dy) * IN_E + dx) * 16 + (g & 1) * 8]);
+    } else {
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int t = 16 * c + 4 * g + q;
+            t = t > 26 ? 26 : t;
+            int dz, dy, dx;
+            tap_xyz(t, dz, dy, dx);
+            w[q] = *reinterpret_cast<const uint32_t*>(&in[(base + (dz * IN_E + dy) * IN_E + dx) * 2]);
+        }
+        return U4{w[0], w[1], w[2], w[3]};
+    }
+}
+
 // Output nodes [0, OUT_E^3) of a valid 3^3 convolution of the IN_E^3 x CIN patch `in` into
-// the OUT_E^3 x 16 patch `out` (ReLU, bf16), 16 nodes per MFMA group.
+// the OUT_E^3 x 16 patch `out` (ReLU, bf16), 16 nodes per MFMA group.  Two groups are
+// computed together so that their two accumulation chains alternate on the matrix core.
 template <int CIN, int IN_E, int OUT_E, int NCH>
 __device__ __forceinline__ void patch_layer(const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
                                             const U4 (&wr)[NCH], const float* __restrict__ bias) {
@@ -445,41 +470,34 @@ __device__ __forceinline__ void patch_layer(const uint16_t* __restrict__ in, uin
 #pragma unroll
     for (int r = 0; r < 4; ++r) bb[r] = bias[4 * g + r];
 #pragma unroll 1
-    for (int grp = 0; grp < NGRP; ++grp) {
-        int o = grp * 16 + j;
-        const bool valid = o < NOUT;
-        o = valid ? o : NOUT - 1;
-        const int oz = o / (OUT_E * OUT_E), oy = (o / OUT_E) % OUT_E, ox = o % OUT_E;
-        const int base = (oz * IN_E + oy) * IN_E + ox;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int grp = 0; grp < NGRP; grp += 2) {
+        int o[2], base[2];
+        bool valid[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            o[h] = (grp + h) * 16 + j;
+            valid[h] = o[h] < NOUT;   // (grp + 1 == NGRP: the second group is all invalid)
+            o[h] = valid[h] ? o[h] : NOUT - 1;
+            const int oz = o[h] / (OUT_E * OUT_E), oy = (o[h] / OUT_E) % OUT_E, ox = o[h] % OUT_E;
+            base[h] = (oz * IN_E + oy) * IN_E + ox;
+        }
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            U4 bop;
-            if (CIN == 16) {
-                int t = 2 * c + (g >> 1);
-                t = t > 26 ? 26 : t;
-                int dz, dy, dx;
-                tap_xyz(t, dz, dy, dx);
-                bop = *reinterpret_cast<const U4*>(&in[(base + (dz * IN_E + dy) * IN_E + dx) * 16 + (g & 1) * 8]);
-            } else {
-                uint32_t w[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    int t = 16 * c + 4 * g + q;
-                    t = t > 26 ? 26 : t;
-                    int dz, dy, dx;
-                    tap_xyz(t, dz, dy, dx);
-                    w[q] = *reinterpret_cast<const uint32_t*>(&in[(base + (dz * IN_E + dy) * IN_E + dx) * 2]);
-                }
-                bop = U4{w[0], w[1], w[2], w[3]};
-            }
-            acc = mfma_bf16(wr[c], bop, acc);
+            const U4 b0 = patch_bop<CIN, IN_E>(in, base[0], c, g);
+            const U4 b1 = patch_bop<CIN, IN_E>(in, base[1], c, g);
+            acc0 = mfma_bf16(wr[c], b0, acc0);
+            acc1 = mfma_bf16(wr[c], b1, acc1);
         }
-        if (valid) {
-            uint2 st;
-            st.x = (uint32_t)f2bf(fmaxf(acc[0] + bb[0], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1] + bb[1], 0.f)) << 16);
-            st.y = (uint32_t)f2bf(fmaxf(acc[2] + bb[2], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3] + bb[3], 0.f)) << 16);
-            *reinterpret_cast<uint2*>(&out[o * 16 + 4 * g]) = st;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const f32x4 acc = h ? acc1 : acc0;
+            if (valid[h]) {
+                uint2 st;
+                st.x = (uint32_t)f2bf(fmaxf(acc[0] + bb[0], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1] + bb[1], 0.f)) << 16);
+                st.y = (uint32_t)f2bf(fmaxf(acc[2] + bb[2], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3] + bb[3], 0.f)) << 16);
+                *reinterpret_cast<uint2*>(&out[o[h] * 16 + 4 * g]) = st;
+            }
         }
     }
 }
