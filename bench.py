@@ -141,7 +141,7 @@ def run_mixed(args):
 
     def one(q):
         return gx.gammax_map_async(q["ref"], q["ev"], q["spacing"], q["dd"], q["dta"], 0.1, q["local"],
-                                   out=q["out"], ctx=q["ctx"], stream=q["stream"])
+                                   sort=args.sort, out=q["out"], ctx=q["ctx"], stream=q["stream"])
 
     log("warm-up (tables and graphs)")
     for _ in range(max(1, args.warmup)):
@@ -197,6 +197,7 @@ def run_mixed(args):
             "pair_ms_p99": round(float(np.percentile(ms, 99)), 4),
             "pair_ms_max": round(float(ms.max()), 4),
             "streams": len(streams),
+            "sort": args.sort,
             "slowest_pairs": slow,
         },
     }

@@ -162,6 +162,19 @@ def test_tiny_and_boundary_heavy(gx, shape, local):
     assert_parity(host(g), o.gamma, f"rough {shape}")
 
 
+@pytest.mark.parametrize("shape", [(13, 64, 80), (33, 96, 100)])
+def test_prep_partial_tile_group(gx, shape):
+    """Grids whose prep tiles (1024 nodes) do not fill the last tile group: 65 tiles in
+    groups of 2, 310 tiles in groups of 4.  The compaction's order and count, R and every
+    gamma must still match the oracle."""
+    p = make_pair_3d(31, shape=shape, spacing=(2.5, 2.5, 2.5))
+    o = oracle.gamma(p.ref, p.eval, p.spacing, 0.03, 3.0, 0.1)
+    g, r = gx.gammax_map(dev(p.ref), dev(p.eval), p.spacing, 0.03, 3.0, 0.1)
+    assert_parity(host(g), o.gamma, f"partial tile group {shape}")
+    assert r.n_evaluated == o.n_evaluated
+    assert r.search_radius == pytest.approx(o.radius, rel=1e-6)
+
+
 def test_threshold_edges(gx):
     p = make_pair_2d(21, shape=(50, 70))
     for thr in [0.0, 0.5, 0.99]:
