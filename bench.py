@@ -38,7 +38,7 @@ TRAFFIC = {
     "3d_128x128x96_2.5mm": {
         "bytes": (15.62 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "e034ba34f700b36316f4e4a594f1ce72bcd070463a16de0c669f9945df6500b5",
+        "sha256": "4aa6d7d5060a0d5381f60b15d1975813e0e781c2eb69c238b98bb359874643e6",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }

@@ -139,6 +139,9 @@ typedef struct {
                                  between the key-0 pass and the sort */
     float ms_done;            /* gammax_batch only: time from the start of the batch until the
                                  last work item of this pair finished (device clock) */
+    uint32_t long_walk_rows;  /* longest walk past the key-0 cells, in table rows, when above
+                                 256 (else 0).  The next map on the same context then uses
+                                 wider lane groups for its tail (automatic tail_lanes only). */
 } gammax_result_t;
 
 typedef struct gammax_ctx gammax_ctx_t;

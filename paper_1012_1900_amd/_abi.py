@@ -107,6 +107,7 @@ class Result(C.Structure):
         ("n_fallback", C.c_uint64),
         ("ms_cnn", C.c_float),
         ("ms_done", C.c_float),
+        ("long_walk_rows", C.c_uint32),
     ]
 
 
@@ -215,6 +216,7 @@ class GammaResult:
     n_fallback: int
     ms_cnn: float
     ms_done: float = 0.0
+    long_walk_rows: int = 0
 
 
 def _torch():

@@ -39,6 +39,7 @@ struct GraphKey {
     double cond_threshold, radius_factor;
     const void* model;
     int32_t small_sort;
+    int32_t tail_min_lanes;
     uint64_t generation;   // bumped on every (re)allocation and table build
 };
 
@@ -107,6 +108,7 @@ struct gammax_ctx {
     int64_t yhat_cap = 0;
     struct BatchState* batch = nullptr;   // gammax_batch state (created on first use)
     uint64_t tail_hint = 0;         // tail length of the last map (picks the tail sort variant)
+    uint32_t long_rows = 0;         // longest tail walk of the last map, if long (widens the tail groups)
     // maps queued by gammax_map_async and not yet collected
     AsyncSlot* slots = nullptr;     // GAMMAX_ASYNC_SLOTS entries, created on first use
     Scalars* h_ring = nullptr;      // pinned: the scalars of each slot's map
@@ -379,6 +381,15 @@ bool uses_model(const gammax_problem_t* p, const gammax_options_t* o) {
            (o->radius_mode == GAMMAX_RADIUS_LEARNED || o->sort_mode == GAMMAX_SORT_PREDICTED);
 }
 
+// Least lanes per node of the automatic tail layout: wide enough that the longest walk of
+// the context's last map (if it was long) takes about 32 dependent steps.
+int tail_min_lanes(const gammax_ctx* c) {
+    if (c->long_rows == 0) return 0;
+    int g = 8;
+    while (g < 64 && (uint64_t)g * 32 < c->long_rows) g <<= 1;
+    return g;
+}
+
 // Queue the compaction (Kernel 1).  ev0/ev1 (optional) bracket it.
 gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int64_t ntiles = prep_tiles(cs.n);
@@ -520,6 +531,7 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
     plan.ndim = p->ndim;
     plan.precision = opt.precision;
     plan.tail_lanes = opt.tail_lanes;
+    plan.tail_min_lanes = tail_min_lanes(c);
     // one lane per node (shared neighbourhood loads) unless one lane per cell is asked for
     plan.zero_lanes = (opt.cell_lanes == 4 || opt.cell_lanes == 8) ? 1 : 0;
     plan.spec = (learned && opt.radius_mode == GAMMAX_RADIUS_LEARNED) ? 1 : 0;
@@ -582,6 +594,7 @@ GraphKey key_of(gammax_ctx* c, const CallSetup& cs) {
     k.radius_factor = cs.opt->radius_factor;
     k.model = cs.opt->model;
     k.small_sort = (cs.opt->sort_mode != GAMMAX_SORT_NONE && c->tail_hint <= (uint64_t)SMALL_SORT_CAP) ? 1 : 0;
+    k.tail_min_lanes = tail_min_lanes(c);
     k.generation = c->generation;
     return k;
 }
@@ -651,8 +664,11 @@ void fill_result_from(gammax_ctx* c, const Scalars& h, gammax_result_t* res, boo
         res->ms_cnn = cnn ? elapsed(c->ev[9], c->ev[10]) : 0.0f;
     }
     res->n_fallback = h.n_fallback;
-    // the next call sorts its tail with the rank sort if this one's would have fitted
+    res->long_walk_rows = h.long_rows;
+    // the next call sorts its tail with the rank sort if this one's would have fitted, and
+    // widens its tail groups if this one had long walks
     c->tail_hint = h.sort_overflow ? (uint64_t)SMALL_SORT_CAP + 1 : h.n_tail;
+    c->long_rows = h.long_rows;
 }
 
 void fill_result(gammax_ctx* c, gammax_result_t* res, bool timing, float ms_table, bool cnn) {

@@ -20,7 +20,7 @@ struct Scalars {
     uint32_t maxg2_bits;    // max gamma^2 found (non-negative float bits)
     uint32_t n_fallback;    // learned radius: tail nodes not certified inside 1.1 * gamma_hat
     uint32_t sort_overflow; // the one-workgroup tail sort met a longer tail (left unsorted)
-    uint32_t pad;
+    uint32_t long_rows;     // longest tail walk in table rows, when above LONG_WALK_ROWS (else 0)
     unsigned long long n_pass;
     unsigned long long n_border;
     unsigned long long n_fp64;
@@ -28,6 +28,8 @@ struct Scalars {
 };
 
 enum : uint32_t { FLAG_NONFINITE = 1u, FLAG_TABLE_SHORT = 2u };
+// A tail walk longer than this many table rows is recorded in Scalars::long_rows.
+constexpr uint32_t LONG_WALK_ROWS = 256;
 
 // Per-block partial counts of a search launch; reduced by one finishing block (no
 // contended atomics on a single address).
@@ -200,6 +202,7 @@ struct ZeroGeo {
 struct SearchPlan {
     int ndim, precision;
     int tail_lanes;          // lanes per node in the tail walk: 1 (one lane per node) or 8..64
+    int tail_min_lanes;      // automatic tail lanes (tail_lanes 0): at least this many (0: 8)
     int zero_lanes;          // pass A: 1 = one lane per cell, 0 = one lane per node
     int spec;                // 1: speculative tail walk inside spec_factor * gamma_hat, then the
                              //    plain walk for the nodes it could not certify

@@ -877,9 +877,11 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_walk(SearchArgs a, const Tab
 // G rows while the first of them still has key^2 < gamma^2.  Every row the sequential walk
 // would evaluate is evaluated; up to G-1 rows past its break may be too.
 // MODE 0: FP32; 1: FP32 + flag ill-conditioned tetrahedra (3D).
-// g_req: lanes per node (8..64), or 0 to pick it from the tail length on the device: about
-// 2^19 lanes in flight fill the GPU, so a short tail gets wide groups (latency) and a long
-// one narrow groups (fewer rows past the break).
+// g_req: lanes per node (8..64), or <= 0 to pick it from the tail length on the device:
+// about 2^19 lanes in flight fill the GPU, so a short tail gets wide groups (latency) and a
+// long one narrow groups (fewer rows past the break), but never fewer than -g_req (when
+// negative) lanes: a tail whose longest walks are long needs wide groups whatever its
+// length, since the kernel lasts as long as its longest walk.
 // spec: as in k_walk (1 speculative, 2 fallback from the first row at or beyond f gamma_hat).
 template <int DIM, int MODE>
 __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEntry* __restrict__ tab,
@@ -889,9 +891,12 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
     constexpr int GMODE = (DIM == 3 && MODE == 1) ? 1 : 0;
     const uint32_t M = *count;
     int G = g_req;
-    if (G == 0) {
+    if (G <= 0) {
+        // automatic: -g_req (if given) is the least width, raised for lists whose longest
+        // walks would otherwise take many dependent steps
+        const int gmin = G < 0 ? -G : 8;
         G = 64;
-        while (G > 8 && (uint64_t)M * (uint64_t)G > (1ull << 19)) G >>= 1;
+        while (G > gmin && (uint64_t)M * (uint64_t)G > (1ull << 19)) G >>= 1;
     }
     const int GROUPS = SEARCH_THREADS / G;
     const int gl = threadIdx.x % G;               // lane within the group
@@ -920,12 +925,14 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
         const float r2s = (spec && live) ? spec_bound2(a, item) : Num<float>::inf();
         // the fallback resumes at the first row the speculative bound cut off (per group)
         const int start = (spec == 2 && live) ? resume_row(tab, a.tab_len, first, r2s) : first;
+        uint32_t steps = 0;   // batches of G rows this group walked
 
         for (int n0 = start; n0 < a.tab_len; n0 += G) {
             const float k_first = tab[n0].key2;       // uniform per group
             const float bound = spec == 1 ? vmin<float>(F, r2s) : F;
             const bool grp_act = live && k_first < bound;
             if (__ballot(grp_act) == 0ull) break;
+            steps += grp_act ? 1u : 0u;
             const int n = n0 + gl;
             TabEntry e;
             bool act = false;
@@ -992,6 +999,14 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
         for (int o = G / 2; o > 0; o >>= 1) {
             lane_cells += (uint32_t)__shfl_xor((int)lane_cells, o);
             ill = (__shfl_xor((int)ill, o) != 0) || ill;
+        }
+        // record a long walk (rare): the next map of this context widens its groups
+        {
+            uint32_t rows = (live && gl == 0) ? steps * (uint32_t)G : 0u;
+            if (__ballot(rows > LONG_WALK_ROWS) != 0ull) {
+                for (int o = WAVE / 2; o > 0; o >>= 1) rows = max(rows, (uint32_t)__shfl_xor((int)rows, o));
+                if ((threadIdx.x & (WAVE - 1)) == 0) atomicMax(&a.sc->long_rows, rows);
+            }
         }
         const bool leader = live && gl == 0;
         const bool to_guard = MODE == 1 && leader && ill;
@@ -1100,7 +1115,8 @@ void tail_group(const SearchArgs& a, const uint32_t* order, const uint32_t* coun
 // Pass B over `order` (count on the device): one lane per node (G == 1) or G lanes.
 unsigned tail_pass(const SearchArgs& a, const SearchPlan& p, const uint32_t* order, const uint32_t* count,
                    int first, bool guarded, int spec, unsigned tb, BlockSums* sums, hipStream_t s) {
-    const int G = p.tail_lanes;   // 0: chosen on the device from the list length
+    // 0: chosen on the device from the list length; negative: the same with a least width
+    const int G = p.tail_lanes ? p.tail_lanes : -(p.tail_min_lanes > 8 ? p.tail_min_lanes : 8);
     if (G == 1) {
         if (p.ndim == 3) {
             if (guarded) walk<3, 1, true>(a, order, count, first, tb, sums, s, spec);
@@ -1110,7 +1126,7 @@ unsigned tail_pass(const SearchArgs& a, const SearchPlan& p, const uint32_t* ord
         }
         return tb;
     }
-    const unsigned groups = SEARCH_THREADS / (unsigned)(G ? G : 8);
+    const unsigned groups = SEARCH_THREADS / (unsigned)(G > 0 ? G : -G);
     unsigned gb = (p.M + groups - 1) / groups;
     if (gb > kTailBlocks) gb = kTailBlocks;
     tail_group(a, order, count, p.ndim, guarded ? 1 : 0, G, first, gb, spec, sums, s);

@@ -175,6 +175,26 @@ def test_prep_partial_tile_group(gx, shape):
     assert r.search_radius == pytest.approx(o.radius, rel=1e-6)
 
 
+def test_long_walks_widen_the_tail(gx):
+    """A local-normalised pair whose longest tail walks run to thousands of table rows: the
+    first map records the longest walk, the next map of the context walks its tail in
+    wider lane groups.  Both match the oracle."""
+    p = make_pair_3d(40064, shape=(32, 48, 48), spacing=(1.0, 1.0, 1.0))
+    o = oracle.gamma(p.ref, p.eval, p.spacing, 0.03, 3.0, 0.1, True)
+    ctx = gx.Context(0)
+    ref, ev = dev(p.ref), dev(p.eval)
+    g1, r1 = gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, True, ctx=ctx)
+    g1 = host(g1)
+    g2, r2 = gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, True, ctx=ctx)
+    assert r1.long_walk_rows > 256 and r2.long_walk_rows > 256
+    for g, lab in ((g1, "first map"), (host(g2), "widened tail")):
+        assert_parity(g, o.gamma, lab)
+    assert r1.n_evaluated == r2.n_evaluated == o.n_evaluated
+    # fixed layouts are not widened
+    g3, r3 = gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, True, tail_lanes=8, ctx=ctx)
+    assert_parity(host(g3), o.gamma, "fixed 8 lanes")
+
+
 def test_threshold_edges(gx):
     p = make_pair_2d(21, shape=(50, 70))
     for thr in [0.0, 0.5, 0.99]:
