@@ -49,6 +49,8 @@ struct AsyncSlot {
     uint64_t ticket = 0;      // 0: free
     bool done = false;        // ran synchronously; `res` is final
     bool learned = false;
+    int ring = -1;            // slot of the pinned scalar ring this map publishes to
+    Scalars sc{};             // its scalars, copied out when the ring slot was needed again
     hipEvent_t ev = nullptr;
     hipStream_t stream = nullptr;
     gammax_problem_t p{};
@@ -111,8 +113,13 @@ struct gammax_ctx {
     uint32_t long_rows = 0;         // longest tail walk of the last map, if long (widens the tail groups)
     // maps queued by gammax_map_async and not yet collected
     AsyncSlot* slots = nullptr;     // GAMMAX_ASYNC_SLOTS entries, created on first use
-    Scalars* h_ring = nullptr;      // pinned: the scalars of each slot's map
     uint64_t next_ticket = 1;
+    // Every map ends with a kernel that writes its scalars into the pinned ring, at the slot
+    // given by a device-side map counter: inside the captured graph, so no runtime copy has
+    // to wait for the graph to drain.  The host counts the maps it launches the same way.
+    Scalars* h_ring = nullptr;      // pinned, GAMMAX_ASYNC_SLOTS entries
+    uint32_t* d_seq = nullptr;      // device map counter
+    uint64_t seq = 0;               // host count of the maps launched
 };
 
 void destroy_batch(gammax_ctx* c);
@@ -153,6 +160,23 @@ void quiesce(gammax_ctx* c) {
     if (!c->slots) return;
     for (int i = 0; i < GAMMAX_ASYNC_SLOTS; ++i)
         if (c->slots[i].ticket && !c->slots[i].done) (void)hipEventSynchronize(c->slots[i].ev);
+}
+
+// The ring slot the next launched map publishes to (the host's count of launched maps;
+// the caller adds one once the map is queued).  A queued map that still holds that slot
+// has its scalars copied out first.
+int claim_ring(gammax_ctx* c) {
+    const int r = (int)(c->seq % GAMMAX_ASYNC_SLOTS);
+    if (c->slots)
+        for (int i = 0; i < GAMMAX_ASYNC_SLOTS; ++i) {
+            AsyncSlot& sl = c->slots[i];
+            if (sl.ticket && !sl.done && sl.ring == r) {
+                (void)hipEventSynchronize(sl.ev);
+                sl.sc = c->h_ring[r];
+                sl.ring = -1;
+            }
+        }
+    return r;
 }
 
 // Grow a device buffer to `need` elements (contents are not kept).
@@ -238,6 +262,22 @@ gammax_status_t check_options(gammax_ctx* c, const gammax_options_t* o) {
 
 __global__ void k_zero_u32(uint32_t* p) {
     if (threadIdx.x == 0) *p = 0u;
+}
+
+// The map's scalars into the pinned ring at the slot of the device map counter, made
+// visible at system scope before the kernel ends; then the counter moves on.  One wave:
+// every lane reads the same counter value.  (A runtime device-to-host copy queued after a
+// graph starts several microseconds after the graph's last kernel; this kernel is part of
+// the graph.)
+__global__ void k_publish_scalars(const Scalars* __restrict__ src, uint32_t* seq, Scalars* ring) {
+    constexpr int W = (int)(sizeof(Scalars) / sizeof(uint32_t));
+    static_assert(sizeof(Scalars) % sizeof(uint32_t) == 0, "Scalars is a whole number of words");
+    const uint32_t k = *seq;
+    Scalars* dst = ring + (k % GAMMAX_ASYNC_SLOTS);
+    const int t = threadIdx.x;
+    if (t < W) reinterpret_cast<volatile uint32_t*>(dst)[t] = reinterpret_cast<const uint32_t*>(src)[t];
+    if (t == 0) *seq = k + 1u;
+    __threadfence_system();
 }
 
 bool same_geom(const TableGeom& a, const TableGeom& b) {
@@ -566,6 +606,8 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
     }
     HIPCHK(c, launch_search(sa, plan, s));
     if (timing) HIPCHK(c, hipEventRecord(c->ev[8], s));
+    hipLaunchKernelGGL(k_publish_scalars, dim3(1), dim3(64), 0, s, (const Scalars*)c->d_sc, c->d_seq, c->h_ring);
+    HIPCHK(c, hipGetLastError());
     return GAMMAX_OK;
 }
 
@@ -799,7 +841,10 @@ gammax_status_t gammax_ctx_create(int device, gammax_ctx_t** out) {
         hipMalloc((void**)&c->d_cnt, 3 * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc((void**)&c->h_cnt, 3 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void**)&c->d_count, sizeof(uint32_t)) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_count, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->h_count, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_ring, sizeof(Scalars) * GAMMAX_ASYNC_SLOTS, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&c->d_seq, sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->d_seq, 0, sizeof(uint32_t)) != hipSuccess) {
         gammax_ctx_destroy(c);
         return GAMMAX_E_NOMEM;
     }
@@ -813,7 +858,7 @@ gammax_status_t gammax_ctx_destroy(gammax_ctx_t* c) {
     (void)hipDeviceSynchronize();
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    void* dev[] = {c->d_sc, c->d_cnt, c->d_count, c->work, c->blockcnt, c->part, c->hist,
+    void* dev[] = {c->d_sc, c->d_cnt, c->d_count, c->d_seq, c->work, c->blockcnt, c->part, c->hist,
                    c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws, c->yhat};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -850,9 +895,11 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
 
     // steady state: the cached table serves this geometry; no host round trip before the end
     if (steady_table(c, p)) {
+        const int r = claim_ring(c);
         if ((st = enqueue_steady(c, cs, timing, s)) != GAMMAX_OK) return st;
-        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        ++c->seq;
         HIPCHK(c, hipStreamSynchronize(s));
+        *c->h_sc = c->h_ring[r];
         if ((st = device_errors(c, local)) != GAMMAX_OK) return st;
         if (!(c->h_sc->flags & FLAG_TABLE_SHORT)) {
             fill_result(c, res, timing, 0.0f, learned);
@@ -885,14 +932,19 @@ gammax_status_t gammax_map(gammax_ctx_t* c, const gammax_problem_t* p, const gam
         const bool walk = r2 > 0.0f && c->tab_valid;
         const bool keep = c->tab_valid;
         if (!walk) c->tab_valid = false;   // no table needed (every gamma0 is 0)
+        const int r = claim_ring(c);
         st = enqueue_search(c, cs, M, INFINITY, s, timing);
         c->tab_valid = keep;
         if (st != GAMMAX_OK) return st;
-    } else if (timing) {
-        for (int k = 4; k <= 10; ++k) HIPCHK(c, hipEventRecord(c->ev[k], s));
+        ++c->seq;
+        HIPCHK(c, hipStreamSynchronize(s));
+        *c->h_sc = c->h_ring[r];
+    } else {
+        if (timing)
+            for (int k = 4; k <= 10; ++k) HIPCHK(c, hipEventRecord(c->ev[k], s));
+        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
     }
-    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
     fill_result(c, res, timing, ms_table, learned);
     return GAMMAX_OK;
 }
@@ -918,13 +970,6 @@ gammax_status_t gammax_map_async(gammax_ctx_t* c, const gammax_problem_t* p, con
                 return fail(c, GAMMAX_E_DEVICE, "hipEventCreateWithFlags failed");
             }
         }
-        if (hipHostMalloc((void**)&c->h_ring, sizeof(Scalars) * GAMMAX_ASYNC_SLOTS, hipHostMallocDefault) !=
-            hipSuccess) {
-            c->h_ring = nullptr;
-            for (int i = 0; i < GAMMAX_ASYNC_SLOTS; ++i) (void)hipEventDestroy(sl[i].ev);
-            delete[] sl;
-            return fail(c, GAMMAX_E_NOMEM, "pinned scalars of the queued maps");
-        }
         c->slots = sl;
     }
     const int i = (int)(c->next_ticket % GAMMAX_ASYNC_SLOTS);
@@ -940,10 +985,12 @@ gammax_status_t gammax_map_async(gammax_ctx_t* c, const gammax_problem_t* p, con
     sl.stream = s;
     sl.learned = learned;
     if (steady_table(c, p)) {
-        // the whole map, then its scalars into this slot's pinned copy; nothing waits
+        // the whole map (its last kernel publishes the scalars to ring slot r); nothing waits
         CallSetup cs{p, &opt, ref, ev, gamma, n};
+        const int r = claim_ring(c);
         if ((st = enqueue_steady(c, cs, false, s)) != GAMMAX_OK) return st;
-        HIPCHK(c, hipMemcpyAsync(&c->h_ring[i], c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        ++c->seq;
+        sl.ring = r;
         HIPCHK(c, hipEventRecord(sl.ev, s));
         sl.done = false;
     } else {
@@ -970,7 +1017,7 @@ gammax_status_t gammax_map_wait(gammax_ctx_t* c, uint64_t ticket, gammax_result_
     }
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipEventSynchronize(sl.ev));
-    const Scalars& h = c->h_ring[i];
+    const Scalars h = sl.ring >= 0 ? c->h_ring[sl.ring] : sl.sc;
     gammax_status_t st = scalar_errors(c, h, sl.p.norm == GAMMAX_LOCAL);
     if (st != GAMMAX_OK) return st;
     if (h.flags & FLAG_TABLE_SHORT) {

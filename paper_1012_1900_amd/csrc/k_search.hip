@@ -345,8 +345,10 @@ __device__ __forceinline__ T cell2(const T* g, const Geo<T>& G, const InvS2<T>& 
 
 // Per-block reduction of the counts, added into one of SUM_BINS partial slots (blocks
 // spread over the slots, so no address sees more than a few hundred atomics).
+// bins == nullptr: add straight into the map's scalars (`direct`).
 __device__ __forceinline__ void block_sums(BlockSums* bins, uint32_t vb, uint32_t npass, uint32_t nborder,
-                                           uint32_t nfp64, uint32_t ncells, uint32_t gm) {
+                                           uint32_t nfp64, uint32_t ncells, uint32_t gm,
+                                           Scalars* direct = nullptr) {
     __shared__ uint32_t s[5][SEARCH_THREADS / WAVE];
     for (int o = WAVE / 2; o > 0; o >>= 1) {
         npass += (uint32_t)__shfl_xor((int)npass, o);
@@ -374,12 +376,20 @@ __device__ __forceinline__ void block_sums(BlockSums* bins, uint32_t vb, uint32_
             c += s[3][j];
             m = max(m, s[4][j]);
         }
-        BlockSums* out = &bins[vb & (SUM_BINS - 1)];
-        if (p) atomicAdd(&out->pass, p);
-        if (b) atomicAdd(&out->border, b);
-        if (f) atomicAdd(&out->fp64, f);
-        if (c) atomicAdd(&out->cells, c);
-        if (m) atomicMax(&out->maxg2, m);
+        if (bins) {
+            BlockSums* out = &bins[vb & (SUM_BINS - 1)];
+            if (p) atomicAdd(&out->pass, p);
+            if (b) atomicAdd(&out->border, b);
+            if (f) atomicAdd(&out->fp64, f);
+            if (c) atomicAdd(&out->cells, c);
+            if (m) atomicMax(&out->maxg2, m);
+        } else {
+            if (p) atomicAdd(&direct->n_pass, p);
+            if (b) atomicAdd(&direct->n_border, b);
+            if (f) atomicAdd(&direct->n_fp64, f);
+            if (c) atomicAdd(&direct->n_cells, c);
+            if (m) atomicMax(&direct->maxg2_bits, m);
+        }
     }
 }
 
@@ -860,7 +870,7 @@ __device__ __forceinline__ void walk_body(const SearchArgs& a, const TabEntry* _
             }
         }
     }
-    block_sums(sums, vb, npass, nborder, n_fp64, cells, gm);
+    block_sums(sums, vb, npass, nborder, n_fp64, cells, gm, a.sc);
 }
 
 template <int DIM, int MODE, bool TAIL>
@@ -1041,6 +1051,9 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_tail_group(SearchArgs a, con
 
 // One block: sum the per-block partial counts into the scalars, and flag a cell table
 // that does not reach the search radius (the host then rebuilds it and runs again).
+// ADD: add the sums into the scalars (which the prep zeroed) instead of storing them, so
+// that other blocks may add theirs at the same time.
+template <bool ADD = false>
 __device__ __forceinline__ void finalize_body(const BlockSums* __restrict__ sums, int n, Scalars* sc,
                                               float r2_cap) {
     if (threadIdx.x == 0 && u2f(sc->r2_bits) > r2_cap && sc->n_masked > 0) sc->flags |= FLAG_TABLE_SHORT;
@@ -1069,17 +1082,35 @@ __device__ __forceinline__ void finalize_body(const BlockSums* __restrict__ sums
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        sc->n_pass = s[0][0];
-        sc->n_border = s[1][0];
-        sc->n_fp64 = s[2][0];
-        sc->n_cells = s[3][0];
-        sc->maxg2_bits = sm[0];
+        if (ADD) {
+            if (s[0][0]) atomicAdd(&sc->n_pass, s[0][0]);
+            if (s[1][0]) atomicAdd(&sc->n_border, s[1][0]);
+            if (s[2][0]) atomicAdd(&sc->n_fp64, s[2][0]);
+            if (s[3][0]) atomicAdd(&sc->n_cells, s[3][0]);
+            if (sm[0]) atomicMax(&sc->maxg2_bits, sm[0]);
+        } else {
+            sc->n_pass = s[0][0];
+            sc->n_border = s[1][0];
+            sc->n_fp64 = s[2][0];
+            sc->n_cells = s[3][0];
+            sc->maxg2_bits = sm[0];
+        }
     }
 }
 
 __global__ __launch_bounds__(SEARCH_THREADS) void k_finalize(const BlockSums* __restrict__ sums, int n,
                                                              Scalars* sc, float r2_cap) {
     finalize_body(sums, n, sc, r2_cap);
+}
+
+// The guard pass and the count reduction in one launch (guarded precision, 3D): block 0
+// first adds the partial slots of the earlier passes into the scalars, then every block
+// redoes its share of the guard list in FP64-guarded precision and adds its own counts
+// straight into the scalars (a block with no guard nodes adds nothing).
+__global__ __launch_bounds__(SEARCH_THREADS) void k_guard_finalize(SearchArgs a, const TabEntry* __restrict__ tab,
+                                                                   const BlockSums* __restrict__ sums) {
+    if (blockIdx.x == 0) finalize_body<true>(sums, SUM_BINS, a.sc, a.r2_cap);
+    walk_body<3, 2, false>(a, tab, a.guard_list, &a.sc->n_guard, 0, 0, nullptr, blockIdx.x, gridDim.x);
 }
 
 constexpr unsigned kTailBlocks = 1024;   // grid-stride blocks of the tail walk
@@ -1327,10 +1358,10 @@ hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s
             if (spec) used += (int)tail_pass(a, p, a.fb_list, &a.sc->n_fallback, first, guarded, 2, tb, sums, s);
         }
         if (p.ev_tail_end) (void)hipEventRecord(p.ev_tail_end, s);
-        // guard pass
+        // guard pass, with the count reduction in the same launch
         if (guarded) {
-            walk<3, 2, false>(a, a.guard_list, &a.sc->n_guard, 0, kGuardBlocks, sums, s);
-            used += (int)kGuardBlocks;
+            hipLaunchKernelGGL(k_guard_finalize, dim3(kGuardBlocks), dim3(SEARCH_THREADS), 0, s, a, a.tab, sums);
+            return hipGetLastError();
         }
     }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(SEARCH_THREADS), 0, s, sums, SUM_BINS, a.sc, a.r2_cap);
