@@ -36,9 +36,9 @@ PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 # hash differs the traffic is reported as null.
 TRAFFIC = {
     "3d_128x128x96_2.5mm": {
-        "bytes": (15.62 + 2.25) * 1e6,
+        "bytes": (15.61 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "4aa6d7d5060a0d5381f60b15d1975813e0e781c2eb69c238b98bb359874643e6",
+        "sha256": "f6741f1b706a458491adf20956b63591560ddb31ece0eedebd3bebde338a6b7c",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }
