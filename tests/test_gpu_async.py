@@ -128,3 +128,29 @@ def test_slot_limit_and_single_collection(gx, pair):
     st = lib.gammax_map_async(ctx.handle, C.byref(p), C.byref(o), ref.data_ptr(), ev.data_ptr(), out.data_ptr(),
                               C.byref(tk), None)
     assert st == _abi.E_PARAM and tk.value == 0
+
+
+def test_queued_learned_and_2d(gx, pair):
+    """Queued maps with the learned radius (the network inside the replayed graph) and of a
+    2D pair: the same gamma and counts as the synchronous calls."""
+    from dosegen import make_config_pair
+    from oracle import cnn
+    model = gx.Model(cnn.init_params(5).astype(np.float32))
+    ref, ev = dev(pair.ref), dev(pair.eval)
+    kw = dict(radius="learned", sort="predicted", model=model)
+    g1, r1 = gx.gammax_map(ref, ev, pair.spacing, 0.03, 3.0, 0.1, ctx=gx.Context(0), **kw)
+    ctx = gx.Context(0)
+    ts = [gx.gammax_map_async(ref, ev, pair.spacing, 0.03, 3.0, 0.1, ctx=ctx, **kw) for _ in range(4)]
+    for t in ts:
+        r = t.wait()
+        _same(r, r1)
+        assert r.n_fallback == r1.n_fallback
+        assert np.array_equal(host(t.gamma), host(g1))
+    p2 = make_config_pair("2d_64x64_1mm", 3)
+    a, b = dev(p2.ref), dev(p2.eval)
+    g2, r2 = gx.gammax_map(a, b, p2.spacing, 0.03, 3.0, 0.1, ctx=gx.Context(0))
+    ctx2 = gx.Context(0)
+    ts = [gx.gammax_map_async(a, b, p2.spacing, 0.03, 3.0, 0.1, ctx=ctx2) for _ in range(3)]
+    for t in ts:
+        _same(t.wait(), r2)
+        assert np.array_equal(host(t.gamma), host(g2))
