@@ -203,6 +203,23 @@ gammax_status_t gammax_map_async(gammax_ctx_t *ctx, const gammax_problem_t *prob
 gammax_status_t gammax_map_wait(gammax_ctx_t *ctx, uint64_t ticket, gammax_result_t *result);
 
 /*
+ * Gamma maps of n dose pairs in one call (the computation of gammax_map for each).  Pair i
+ * uses a context of its own, kept by `ctx` for later calls at the same index (its cell
+ * table, captured graph and workspace stay cached: a repeated batch replays), and the
+ * pairs are queued round-robin on `stream` and three internal streams, so small maps run
+ * beside large ones.  The maps start after the work queued on `stream` before the call, and later work
+ * on `stream` follows them; the call returns when every map is complete.
+ *   problems/refs/evals/gammas/results: n entries each; buffers as in gammax_map.
+ *   opt: NULL for the defaults; timing must be 0.
+ * On an error the status of the first failing pair is returned and gammax_last_error names
+ * the pair; the maps already queued are completed first.
+ */
+gammax_status_t gammax_map_many(gammax_ctx_t *ctx, int32_t n, const gammax_problem_t *problems,
+                                const float *const *refs_dev, const float *const *evals_dev,
+                                float *const *gammas_dev, const gammax_options_t *opt,
+                                gammax_result_t *results, void *stream);
+
+/*
  * The problem statement as a flat call (Sec. 2.1): gamma and pass rate of one dose pair
  * with the default options on a library-owned context for the current device.
  * shape/spacing_mm hold ndim entries each (slowest axis first); norm is gammax_norm_t.

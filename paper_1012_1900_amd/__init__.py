@@ -18,6 +18,7 @@ from ._abi import (  # noqa: F401
     gammax_batch,
     gammax_map,
     gammax_map_async,
+    gammax_map_many,
     MapTicket,
     ASYNC_SLOTS,
     pass_count,

@@ -652,6 +652,51 @@ def gammax_batch(pairs, *, precision: str = "guarded", cond_threshold: float = 1
     return out_list, results
 
 
+_lib.gammax_map_many.restype = C.c_int
+_lib.gammax_map_many.argtypes = [_vp, C.c_int32, C.POINTER(Problem), C.POINTER(_vp), C.POINTER(_vp),
+                                 C.POINTER(_vp), C.POINTER(Options), C.POINTER(Result), _vp]
+
+
+def gammax_map_many(pairs, *, sort: str = "none", precision: str = "guarded", cond_threshold: float = 1e6,
+                    tail_lanes: int = 0, radius: str = "plain", model=None, radius_factor: float = 1.1,
+                    outs=None, ctx: Optional[Context] = None, stream=None):
+    """Gamma maps of several pairs in one call (``gammax_map_many``): each pair index keeps
+    a context of its own inside ``ctx``, the pairs run on the stream and three internal ones.
+
+    ``pairs``: sequence of dicts with ``ref``, ``ev`` (float32 device tensors), ``spacing``,
+    ``dd``, ``dta`` and optionally ``threshold`` (default 0.1) and ``local`` (default False).
+    Returns (list of gamma tensors, list of GammaResult).
+    """
+    torch = _torch()
+    n = len(pairs)
+    if n == 0:
+        return [], []
+    dev = pairs[0]["ref"].device
+    probs = (Problem * n)()
+    refs, evs, gams = (_vp * n)(), (_vp * n)(), (_vp * n)()
+    out_list = []
+    for i, q in enumerate(pairs):
+        _dev_tensor(q["ref"], "ref")
+        _dev_tensor(q["ev"], "ev")
+        if q["ref"].shape != q["ev"].shape or q["ref"].device != dev or q["ev"].device != dev:
+            raise ValueError(f"pair {i}: ref and ev must share shape and device")
+        if len(q["spacing"]) != q["ref"].dim():
+            raise ValueError(f"pair {i}: spacing needs one entry per axis")
+        probs[i] = make_problem(tuple(q["ref"].shape), q["spacing"], q["dd"], q["dta"],
+                                q.get("threshold", 0.1), q.get("local", False))
+        g = outs[i] if outs is not None else torch.empty_like(q["ref"])
+        out_list.append(g)
+        refs[i], evs[i], gams[i] = q["ref"].data_ptr(), q["ev"].data_ptr(), g.data_ptr()
+    ctx = ctx or context(dev.index or 0)
+    o = make_options(sort, precision, cond_threshold, False, tail_lanes, 0, radius, model, radius_factor)
+    res = (Result * n)()
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        st = _lib.gammax_map_many(ctx.handle, n, probs, refs, evs, gams, C.byref(o), res, _vp(s.cuda_stream))
+    ctx.check(st)
+    return out_list, [GammaResult(**{f[0]: getattr(r, f[0]) for f in Result._fields_}) for r in res]
+
+
 def tune_save(path: str, ctx: Context):
     ctx.check(_lib.gammax_tune_save(ctx.handle, path.encode()))
 

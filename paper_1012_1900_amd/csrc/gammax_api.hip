@@ -109,6 +109,7 @@ struct gammax_ctx {
     float* yhat = nullptr;          // log(gamma_hat + 0.01) per grid node
     int64_t yhat_cap = 0;
     struct BatchState* batch = nullptr;   // gammax_batch state (created on first use)
+    struct ManyState* many = nullptr;     // gammax_map_many state (created on first use)
     uint64_t tail_hint = 0;         // tail length of the last map (picks the tail sort variant)
     uint32_t long_rows = 0;         // longest tail walk of the last map, if long (widens the tail groups)
     // maps queued by gammax_map_async and not yet collected
@@ -123,6 +124,18 @@ struct gammax_ctx {
 };
 
 void destroy_batch(gammax_ctx* c);
+
+// gammax_map_many: a context per pair index (its table, graph and workspace stay cached
+// across calls) and the streams the pairs are spread over: the caller's stream and three
+// internal ones (a process gets four hardware queues; a fifth stream would share one).
+constexpr int kManyStreams = 4;
+struct ManyState {
+    std::vector<gammax_ctx*> subs;
+    hipStream_t streams[kManyStreams - 1] = {};
+    hipEvent_t ev_in = nullptr;
+    hipEvent_t ev_out[kManyStreams - 1] = {};
+};
+void destroy_many(gammax_ctx* c);
 
 namespace {
 
@@ -863,6 +876,7 @@ gammax_status_t gammax_ctx_destroy(gammax_ctx_t* c) {
     for (void* p : dev)
         if (p) (void)hipFree(p);
     destroy_batch(c);
+    destroy_many(c);
     if (c->slots) {
         for (int i = 0; i < GAMMAX_ASYNC_SLOTS; ++i) (void)hipEventDestroy(c->slots[i].ev);
         delete[] c->slots;
@@ -1329,6 +1343,19 @@ void destroy_batch(gammax_ctx* c) {
     c->batch = nullptr;
 }
 
+void destroy_many(gammax_ctx* c) {
+    ManyState* m = c->many;
+    if (!m) return;
+    for (gammax_ctx* sub : m->subs) (void)gammax_ctx_destroy(sub);
+    for (auto& st : m->streams)
+        if (st) (void)hipStreamDestroy(st);
+    if (m->ev_in) (void)hipEventDestroy(m->ev_in);
+    for (auto& e : m->ev_out)
+        if (e) (void)hipEventDestroy(e);
+    delete m;
+    c->many = nullptr;
+}
+
 namespace {
 
 // Fill the descriptors of every pair in the staging area.  Pairs without a usable table
@@ -1697,6 +1724,66 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
         return GAMMAX_OK;
     }
     return fail(c, GAMMAX_E_DEVICE, "batch: a cell table fell short twice");
+}
+
+gammax_status_t gammax_map_many(gammax_ctx_t* c, int32_t n, const gammax_problem_t* probs, const float* const* refs,
+                                const float* const* evals, float* const* gammas, const gammax_options_t* opt,
+                                gammax_result_t* results, void* stream) {
+    if (!c) return GAMMAX_E_NULL;
+    if (n < 0) return fail(c, GAMMAX_E_PARAM, "n must be >= 0");
+    if (n == 0) return GAMMAX_OK;
+    if (!probs || !refs || !evals || !gammas || !results)
+        return fail(c, GAMMAX_E_NULL, "problems, dose, gamma and result arrays are required");
+    if (opt && opt->timing) return fail(c, GAMMAX_E_PARAM, "timing is not available for gammax_map_many");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (!c->many) {
+        ManyState* m = new (std::nothrow) ManyState();
+        if (!m) return fail(c, GAMMAX_E_NOMEM, "gammax_map_many state");
+        c->many = m;
+        for (auto& st : m->streams) HIPCHK(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming));
+        for (auto& e : m->ev_out) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    ManyState* m = c->many;
+    while ((int)m->subs.size() < n) {
+        gammax_ctx* sub = nullptr;
+        const gammax_status_t st = gammax_ctx_create(c->device, &sub);
+        if (st != GAMMAX_OK) return fail(c, st, "gammax_map_many: context for a pair");
+        m->subs.push_back(sub);
+    }
+    // the internal streams start after the caller's work on `stream`
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipEventRecord(m->ev_in, s));
+    for (auto& st : m->streams) HIPCHK(c, hipStreamWaitEvent(st, m->ev_in, 0));
+    std::vector<uint64_t> tickets(n, 0);
+    gammax_status_t first = GAMMAX_OK;
+    std::string why;
+    int queued = 0;
+    for (int i = 0; i < n; ++i) {
+        const int k = i % kManyStreams;
+        const gammax_status_t st = gammax_map_async(m->subs[i], &probs[i], opt, refs[i], evals[i], gammas[i],
+                                                    &tickets[i], k == 0 ? s : m->streams[k - 1]);
+        if (st != GAMMAX_OK) {
+            first = st;
+            why = "pair " + std::to_string(i) + ": " + m->subs[i]->err;
+            break;
+        }
+        ++queued;
+    }
+    for (int i = 0; i < queued; ++i) {
+        const gammax_status_t st = gammax_map_wait(m->subs[i], tickets[i], &results[i]);
+        if (st != GAMMAX_OK && first == GAMMAX_OK) {
+            first = st;
+            why = "pair " + std::to_string(i) + ": " + m->subs[i]->err;
+        }
+    }
+    // later work on the caller's stream follows the maps
+    for (int k = 0; k < kManyStreams - 1; ++k) {
+        HIPCHK(c, hipEventRecord(m->ev_out[k], m->streams[k]));
+        HIPCHK(c, hipStreamWaitEvent(s, m->ev_out[k], 0));
+    }
+    if (first != GAMMAX_OK) return fail(c, first, why);
+    return GAMMAX_OK;
 }
 
 gammax_status_t gammax_tune_save(const gammax_ctx_t* c, const char* path) {

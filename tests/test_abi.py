@@ -37,7 +37,7 @@ def test_header_declares_the_boundary():
                  "gammax_model_features", "gammax_model_predict", "gammax_model_forward",
                  "gammax_model_train_step", "gammax_model_last_error", "gammax_model_predict_nodes",
                  "gammax_batch", "gammax_tune_save", "gammax_tune_load", "gammax_map_async",
-                 "gammax_map_wait"]:
+                 "gammax_map_wait", "gammax_map_many"]:
         assert must in names
 
 
@@ -101,6 +101,7 @@ def test_null_context(abi):
     t = C.c_uint64(7)
     assert lib.gammax_map_async(None, C.byref(p), None, None, None, None, C.byref(t), None) == abi.E_NULL
     assert lib.gammax_map_wait(None, 1, C.byref(r)) == abi.E_NULL
+    assert lib.gammax_map_many(None, 1, None, None, None, None, None, None, None) == abi.E_NULL
     assert lib.gammax_sort_pairs(None, None, None, 0, None) == abi.E_NULL
     assert lib.gammax_pass_count(None, None, 0, None, None) == abi.E_NULL
     assert lib.gammax_ctx_destroy(None) == abi.OK
