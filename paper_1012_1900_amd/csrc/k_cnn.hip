@@ -42,6 +42,30 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint32_t h) { return __builtin_bit_cast(float, (h & 0xFFFFu) << 16); }
 
+// Two floats rounded to bf16 (nearest even, as f2bf for every non-NaN value) in one
+// hardware conversion; `lo` in the low half.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack2bf(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
+}
+
+// floor(v / E) for 0 <= v < 4096 as a multiply and a shift: with M = ceil(2^16 / E) the
+// excess v (M E - 2^16) / (E 2^16) stays below 1/E there.
+template <int E>
+constexpr uint32_t div_magic() { return (65536u + E - 1) / E; }
+template <int E>
+constexpr bool div_magic_exact() {
+    for (uint32_t v = 0; v < 4096; ++v)
+        if (((v * div_magic<E>()) >> 16) != v / E) return false;
+    return true;
+}
+template <int E>
+__device__ __forceinline__ uint32_t div_small(uint32_t v) {
+    static_assert(div_magic_exact<E>(), "multiply-shift division inexact");
+    return (v * div_magic<E>()) >> 16;
+}
+
 __device__ __forceinline__ f32x4 mfma_bf16(const U4& a, const U4& b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
                                                    0, 0, 0);
@@ -478,8 +502,11 @@ __device__ __forceinline__ void patch_layer(const uint16_t* __restrict__ in, uin
             o[h] = (grp + h) * 16 + j;
             valid[h] = o[h] < NOUT;   // (grp + 1 == NGRP: the second group is all invalid)
             o[h] = valid[h] ? o[h] : NOUT - 1;
-            const int oz = o[h] / (OUT_E * OUT_E), oy = (o[h] / OUT_E) % OUT_E, ox = o[h] % OUT_E;
-            base[h] = (oz * IN_E + oy) * IN_E + ox;
+            // o = (oz OUT_E + oy) OUT_E + ox  ->  base = (oz IN_E + oy) IN_E + ox
+            //   = o + (IN_E - OUT_E) (q + IN_E oz), q = o / OUT_E = oz OUT_E + oy
+            const uint32_t q = div_small<OUT_E>((uint32_t)o[h]);
+            const uint32_t oz = div_small<OUT_E>(q);
+            base[h] = o[h] + (IN_E - OUT_E) * (int)(q + IN_E * oz);
         }
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -494,8 +521,8 @@ __device__ __forceinline__ void patch_layer(const uint16_t* __restrict__ in, uin
             const f32x4 acc = h ? acc1 : acc0;
             if (valid[h]) {
                 uint2 st;
-                st.x = (uint32_t)f2bf(fmaxf(acc[0] + bb[0], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1] + bb[1], 0.f)) << 16);
-                st.y = (uint32_t)f2bf(fmaxf(acc[2] + bb[2], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3] + bb[3], 0.f)) << 16);
+                st.x = pack2bf(fmaxf(acc[0] + bb[0], 0.f), fmaxf(acc[1] + bb[1], 0.f));
+                st.y = pack2bf(fmaxf(acc[2] + bb[2], 0.f), fmaxf(acc[3] + bb[3], 0.f));
                 *reinterpret_cast<uint2*>(&out[o[h] * 16 + 4 * g]) = st;
             }
         }
@@ -510,7 +537,10 @@ __device__ __forceinline__ void patch_layer(const uint16_t* __restrict__ in, uin
 template <int R0, int NR>
 __device__ __forceinline__ void tail_gather(const TailCnnArgs& a, int node, float inv_max, float inv_dd,
                                             uint16_t* Y) {
-    const int lane = threadIdx.x & 63;
+    // the lane's patch coordinates are recomputed per call (this path serves only nodes
+    // near the grid's faces) rather than held in registers across the node loop
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
     const int x0 = node % a.nx - 4, y0 = (node / a.nx) % a.ny - 4, z0 = node / (a.nx * a.ny) - 4;
     float rv[NR], ev[NR];
     uint32_t inside = 0u;
@@ -529,9 +559,34 @@ __device__ __forceinline__ void tail_gather(const TailCnnArgs& a, int node, floa
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         asm volatile("" : "+v"(rv[r]), "+v"(ev[r]));
-        const uint32_t pk = (uint32_t)f2bf(rv[r] * inv_max) | ((uint32_t)f2bf((ev[r] - rv[r]) * inv_dd) << 16);
+        const uint32_t pk = pack2bf(rv[r] * inv_max, (ev[r] - rv[r]) * inv_dd);
         const int u = lane + 64 * (R0 + r);
         if (u < 729) reinterpret_cast<uint32_t*>(Y)[u] = ((inside >> r) & 1u) ? pk : 0u;
+    }
+}
+
+// The same features for a node whose 9^3 patch lies inside the grid: voxel u of the patch
+// is the patch corner plus the byte offset G[u] (G[729..767] = 0, an in-patch voxel whose
+// value the masked store drops), so a round costs one table read and two loads.
+template <int R0, int NR>
+__device__ __forceinline__ void tail_gather_inner(const TailCnnArgs& a, int64_t corner, const uint32_t* G,
+                                                  float inv_max, float inv_dd, uint16_t* Y) {
+    const int lane = threadIdx.x & 63;
+    const char* pr = reinterpret_cast<const char*>(a.ref + corner);
+    const char* pe = reinterpret_cast<const char*>(a.ev + corner);
+    float rv[NR], ev[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const uint32_t off = G[lane + 64 * (R0 + r)];
+        rv[r] = *reinterpret_cast<const float*>(pr + off);
+        ev[r] = *reinterpret_cast<const float*>(pe + off);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        asm volatile("" : "+v"(rv[r]), "+v"(ev[r]));
+        const int u = lane + 64 * (R0 + r);
+        if (64 * (R0 + r) + 63 < 729 || u < 729)
+            reinterpret_cast<uint32_t*>(Y)[u] = pack2bf(rv[r] * inv_max, (ev[r] - rv[r]) * inv_dd);
     }
 }
 
@@ -541,6 +596,7 @@ __global__ __launch_bounds__(TAIL_THREADS) __attribute__((amdgpu_waves_per_eu(2,
     // constants of the whole run: biases of layers 1-3, bf16-rounded layer 4 weights in
     // (tap, channel) order, layer 4 bias
     __shared__ float C[3 * 16 + 432 + 1];
+    __shared__ uint32_t G[64 * TAIL_GATHER];
     const uint32_t M = *a.count;
     if (blockIdx.x >= M) return;
     const int lane = threadIdx.x & 63;
@@ -563,14 +619,28 @@ __global__ __launch_bounds__(TAIL_THREADS) __attribute__((amdgpu_waves_per_eu(2,
         else v = *a.b4;
         C[k] = v;
     }
+    for (int u = lane; u < 64 * TAIL_GATHER; u += 64) {
+        const int v = u < 729 ? u : 0;
+        G[u] = (uint32_t)((((int64_t)(v / 81) * a.ny + (v / 9) % 9) * a.nx + v % 9) * 4);
+    }
+    __syncthreads();
+    const int64_t plane = (int64_t)a.nx * a.ny;
+    const bool offs32 = plane * 9 * 4 < (int64_t(1) << 32);   // G's byte offsets fit 32 bits
 
     int node_next = (int)a.nodes[blockIdx.x];
     for (uint32_t item = blockIdx.x; item < M; item += gridDim.x) {
         const int node = node_next;
         if (item + gridDim.x < M) node_next = (int)a.nodes[item + gridDim.x];
         // Y is free: the previous node's layer 3 read it before the barrier that followed
-        tail_gather<0, TAIL_GATHER / 2>(a, node, inv_max, inv_dd, Y);
-        tail_gather<TAIL_GATHER / 2, TAIL_GATHER - TAIL_GATHER / 2>(a, node, inv_max, inv_dd, Y);
+        const int x = node % a.nx, y = (node / a.nx) % a.ny, z = node / (a.nx * a.ny);
+        if (offs32 && x >= 4 && x + 4 < a.nx && y >= 4 && y + 4 < a.ny && z >= 4 && z + 4 < a.nz) {
+            const int64_t corner = node - 4 * (plane + a.nx + 1);
+            tail_gather_inner<0, TAIL_GATHER / 2>(a, corner, G, inv_max, inv_dd, Y);
+            tail_gather_inner<TAIL_GATHER / 2, TAIL_GATHER - TAIL_GATHER / 2>(a, corner, G, inv_max, inv_dd, Y);
+        } else {
+            tail_gather<0, TAIL_GATHER / 2>(a, node, inv_max, inv_dd, Y);
+            tail_gather<TAIL_GATHER / 2, TAIL_GATHER - TAIL_GATHER / 2>(a, node, inv_max, inv_dd, Y);
+        }
         __syncthreads();
         patch_layer<2, 9, 7, 2>(Y, X, w0, C);
         __syncthreads();
