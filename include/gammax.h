@@ -348,7 +348,17 @@ gammax_status_t gammax_model_train_step(gammax_model_t *model, int32_t nvol, con
  * ---- Batches of dose pairs ------------------------------------------------------------
  *
  * Gamma maps of n pairs of any mix of dimensionality, grid, spacing, criteria and
- * normalisation, with one set of options, through one pipeline: every phase runs once for
+ * normalisation, with one set of options.
+ *
+ * Default: the pairs run as queued maps, as in gammax_map_many (a cached context per pair
+ * index, the caller's stream and three internal streams, each pair's pipeline replayed
+ * from its captured graph); results[i].ms_done is the device time from the call's start
+ * until pair i's map finished.  opt->autotune is not used on this route (the automatic
+ * tail layout adapts per pair context), and timing is refused (GAMMAX_E_PARAM).
+ *
+ * The single-pipeline batch described next is switched off: its first run on the device
+ * stopped making progress, and the cause is not known.  The environment variable
+ * GAMMAX_ENABLE_BATCH=1 selects it.  There, every phase runs once for
  * the whole batch (a prep over all pairs' tiles; one persistent pass over the key-0 cells
  * of every pair's nodes in cost order; tail walks, fallbacks and the guard pass taken from
  * a queue of (pair, chunk) items; one count reduction), replayed from a captured HIP graph

@@ -614,7 +614,9 @@ _lib.gammax_tune_load.argtypes = [_vp, C.c_char_p]
 def gammax_batch(pairs, *, precision: str = "guarded", cond_threshold: float = 1e6, tail_lanes: int = 0,
                  radius: str = "plain", model=None, radius_factor: float = 1.1, autotune: bool = False,
                  outs=None, ctx: Optional[Context] = None, stream=None):
-    """Gamma maps of a batch of pairs in one pipeline.
+    """Gamma maps of a batch of pairs (``gammax_batch``): by default queued per-pair maps on
+    the stream and three internal ones, with each pair's completion time in ``ms_done``
+    (the single-pipeline batch runs only with GAMMAX_ENABLE_BATCH=1).
 
     ``pairs``: sequence of dicts with ``ref``, ``ev`` (float32 device tensors), ``spacing``,
     ``dd``, ``dta`` and optionally ``threshold`` (default 0.1) and ``local`` (default False).

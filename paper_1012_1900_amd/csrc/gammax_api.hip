@@ -134,6 +134,10 @@ struct ManyState {
     hipStream_t streams[kManyStreams - 1] = {};
     hipEvent_t ev_in = nullptr;
     hipEvent_t ev_out[kManyStreams - 1] = {};
+    // timed runs (gammax_batch): the start on the caller's stream, and each pair's end on
+    // the stream its map ran on
+    hipEvent_t ev_t0 = nullptr;
+    std::vector<hipEvent_t> ev_done;
 };
 void destroy_many(gammax_ctx* c);
 
@@ -1352,6 +1356,8 @@ void destroy_many(gammax_ctx* c) {
     if (m->ev_in) (void)hipEventDestroy(m->ev_in);
     for (auto& e : m->ev_out)
         if (e) (void)hipEventDestroy(e);
+    if (m->ev_t0) (void)hipEventDestroy(m->ev_t0);
+    for (auto& e : m->ev_done) (void)hipEventDestroy(e);
     delete m;
     c->many = nullptr;
 }
@@ -1499,17 +1505,104 @@ gammax_status_t batch_errors(gammax_ctx* c, BatchState* b, const BatchLayout& L,
 
 }  // namespace
 
+namespace {
+
+// The maps of n pairs queued on the caller's stream and three internal ones (a cached
+// context per pair index), then collected.  timed: results[i].ms_done = device time from
+// the start of the call until pair i's map finished.
+gammax_status_t run_many(gammax_ctx_t* c, int32_t n, const gammax_problem_t* probs, const float* const* refs,
+                         const float* const* evals, float* const* gammas, const gammax_options_t* opt,
+                         gammax_result_t* results, hipStream_t s, bool timed) {
+    if (!c) return GAMMAX_E_NULL;
+    if (n < 0) return fail(c, GAMMAX_E_PARAM, "n must be >= 0");
+    if (n == 0) return GAMMAX_OK;
+    if (!probs || !refs || !evals || !gammas || !results)
+        return fail(c, GAMMAX_E_NULL, "problems, dose, gamma and result arrays are required");
+    if (opt && opt->timing) return fail(c, GAMMAX_E_PARAM, "timing is not available for gammax_map_many");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (!c->many) {
+        ManyState* m = new (std::nothrow) ManyState();
+        if (!m) return fail(c, GAMMAX_E_NOMEM, "gammax_map_many state");
+        c->many = m;
+        for (auto& st : m->streams) HIPCHK(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming));
+        for (auto& e : m->ev_out) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    ManyState* m = c->many;
+    while ((int)m->subs.size() < n) {
+        gammax_ctx* sub = nullptr;
+        const gammax_status_t st = gammax_ctx_create(c->device, &sub);
+        if (st != GAMMAX_OK) return fail(c, st, "gammax_map_many: context for a pair");
+        m->subs.push_back(sub);
+    }
+    if (timed) {
+        if (!m->ev_t0) HIPCHK(c, hipEventCreate(&m->ev_t0));
+        while ((int)m->ev_done.size() < n) {
+            hipEvent_t e = nullptr;
+            HIPCHK(c, hipEventCreate(&e));
+            m->ev_done.push_back(e);
+        }
+        HIPCHK(c, hipEventRecord(m->ev_t0, s));
+    }
+    // the internal streams start after the caller's work on `stream`
+    HIPCHK(c, hipEventRecord(m->ev_in, s));
+    for (auto& st : m->streams) HIPCHK(c, hipStreamWaitEvent(st, m->ev_in, 0));
+    std::vector<uint64_t> tickets(n, 0);
+    gammax_status_t first = GAMMAX_OK;
+    std::string why;
+    int queued = 0;
+    for (int i = 0; i < n; ++i) {
+        const int k = i % kManyStreams;
+        hipStream_t si = k == 0 ? s : m->streams[k - 1];
+        const gammax_status_t st = gammax_map_async(m->subs[i], &probs[i], opt, refs[i], evals[i], gammas[i],
+                                                    &tickets[i], si);
+        if (st != GAMMAX_OK) {
+            first = st;
+            why = "pair " + std::to_string(i) + ": " + m->subs[i]->err;
+            break;
+        }
+        if (timed) HIPCHK(c, hipEventRecord(m->ev_done[i], si));
+        ++queued;
+    }
+    for (int i = 0; i < queued; ++i) {
+        const gammax_status_t st = gammax_map_wait(m->subs[i], tickets[i], &results[i]);
+        if (st != GAMMAX_OK && first == GAMMAX_OK) {
+            first = st;
+            why = "pair " + std::to_string(i) + ": " + m->subs[i]->err;
+        }
+    }
+    // later work on the caller's stream follows the maps
+    for (int k = 0; k < kManyStreams - 1; ++k) {
+        HIPCHK(c, hipEventRecord(m->ev_out[k], m->streams[k]));
+        HIPCHK(c, hipStreamWaitEvent(s, m->ev_out[k], 0));
+    }
+    if (first != GAMMAX_OK) return fail(c, first, why);
+    if (timed)
+        for (int i = 0; i < n; ++i) {
+            HIPCHK(c, hipEventSynchronize(m->ev_done[i]));
+            HIPCHK(c, hipEventElapsedTime(&results[i].ms_done, m->ev_t0, m->ev_done[i]));
+        }
+    return GAMMAX_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t* probs, const float* const* refs,
                              const float* const* evals, float* const* gammas, const gammax_options_t* opt_in,
                              gammax_result_t* results, void* stream) {
     if (!c) return GAMMAX_E_NULL;
-    // Switched off: its first GPU run stopped making progress and the cause is not yet
-    // known.  GAMMAX_ENABLE_BATCH=1 turns it on for investigation.
+    // The persistent pipeline below is switched off: its first GPU run stopped making
+    // progress and the cause is not yet known (GAMMAX_ENABLE_BATCH=1 turns it on for
+    // investigation).  Meanwhile the batch runs as queued per-pair maps on four streams.
     const char* en = std::getenv("GAMMAX_ENABLE_BATCH");
-    if (!en || std::strcmp(en, "1") != 0)
-        return fail(c, GAMMAX_E_DEVICE, "gammax_batch is disabled (set GAMMAX_ENABLE_BATCH=1)");
+    if (!en || std::strcmp(en, "1") != 0) {
+        if (opt_in && opt_in->timing) return fail(c, GAMMAX_E_PARAM, "timing is not available for gammax_batch");
+        if (n < 0) return fail(c, GAMMAX_E_PARAM, "n must be >= 0");
+        HIPCHK(c, hipSetDevice(c->device));
+        return run_many(c, n, probs, refs, evals, gammas, opt_in, results, (hipStream_t)stream, true);
+    }
     if (n < 0) return fail(c, GAMMAX_E_PARAM, "n must be >= 0");
     if (n == 0) return GAMMAX_OK;
     if (!probs || !refs || !evals || !gammas || !results)
@@ -1729,61 +1822,7 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
 gammax_status_t gammax_map_many(gammax_ctx_t* c, int32_t n, const gammax_problem_t* probs, const float* const* refs,
                                 const float* const* evals, float* const* gammas, const gammax_options_t* opt,
                                 gammax_result_t* results, void* stream) {
-    if (!c) return GAMMAX_E_NULL;
-    if (n < 0) return fail(c, GAMMAX_E_PARAM, "n must be >= 0");
-    if (n == 0) return GAMMAX_OK;
-    if (!probs || !refs || !evals || !gammas || !results)
-        return fail(c, GAMMAX_E_NULL, "problems, dose, gamma and result arrays are required");
-    if (opt && opt->timing) return fail(c, GAMMAX_E_PARAM, "timing is not available for gammax_map_many");
-    HIPCHK(c, hipSetDevice(c->device));
-    if (!c->many) {
-        ManyState* m = new (std::nothrow) ManyState();
-        if (!m) return fail(c, GAMMAX_E_NOMEM, "gammax_map_many state");
-        c->many = m;
-        for (auto& st : m->streams) HIPCHK(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        HIPCHK(c, hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming));
-        for (auto& e : m->ev_out) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    }
-    ManyState* m = c->many;
-    while ((int)m->subs.size() < n) {
-        gammax_ctx* sub = nullptr;
-        const gammax_status_t st = gammax_ctx_create(c->device, &sub);
-        if (st != GAMMAX_OK) return fail(c, st, "gammax_map_many: context for a pair");
-        m->subs.push_back(sub);
-    }
-    // the internal streams start after the caller's work on `stream`
-    hipStream_t s = (hipStream_t)stream;
-    HIPCHK(c, hipEventRecord(m->ev_in, s));
-    for (auto& st : m->streams) HIPCHK(c, hipStreamWaitEvent(st, m->ev_in, 0));
-    std::vector<uint64_t> tickets(n, 0);
-    gammax_status_t first = GAMMAX_OK;
-    std::string why;
-    int queued = 0;
-    for (int i = 0; i < n; ++i) {
-        const int k = i % kManyStreams;
-        const gammax_status_t st = gammax_map_async(m->subs[i], &probs[i], opt, refs[i], evals[i], gammas[i],
-                                                    &tickets[i], k == 0 ? s : m->streams[k - 1]);
-        if (st != GAMMAX_OK) {
-            first = st;
-            why = "pair " + std::to_string(i) + ": " + m->subs[i]->err;
-            break;
-        }
-        ++queued;
-    }
-    for (int i = 0; i < queued; ++i) {
-        const gammax_status_t st = gammax_map_wait(m->subs[i], tickets[i], &results[i]);
-        if (st != GAMMAX_OK && first == GAMMAX_OK) {
-            first = st;
-            why = "pair " + std::to_string(i) + ": " + m->subs[i]->err;
-        }
-    }
-    // later work on the caller's stream follows the maps
-    for (int k = 0; k < kManyStreams - 1; ++k) {
-        HIPCHK(c, hipEventRecord(m->ev_out[k], m->streams[k]));
-        HIPCHK(c, hipStreamWaitEvent(s, m->ev_out[k], 0));
-    }
-    if (first != GAMMAX_OK) return fail(c, first, why);
-    return GAMMAX_OK;
+    return run_many(c, n, probs, refs, evals, gammas, opt, results, (hipStream_t)stream, false);
 }
 
 gammax_status_t gammax_tune_save(const gammax_ctx_t* c, const char* path) {
