@@ -20,6 +20,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+TRAIN_SPACING_MM = 2.5   # grid spacing of the shipped network's training pairs
 METRIC = "ref voxels/sec, 3D 3%/3mm: plain vs learned-radius at |Δγ|≤1e-5; %FP32 peak"
 
 # FP32 operations per evaluated cell of the closed-form face projections (3D: 8 corner
@@ -318,14 +319,21 @@ def main():
     learned = None
     if nd == 3 and not args.no_learned and os.path.exists(args.weights):
         model = gx.Model(np.load(args.weights, allow_pickle=False))
-        log("learned radius")
-        lsec, lr_last, lph = leg(dict(radius="learned", sort="predicted", model=model))
+        # the network was trained on a 2.5 mm grid: a grid at half that spacing feeds it the
+        # pair average-pooled 2x2x2 and interpolates its prediction back
+        cnn_pool = 2 if all(abs(2.0 * h - TRAIN_SPACING_MM) < 1e-9 for h in pair.spacing) else 0
+        log(f"learned radius (cnn_pool {cnn_pool})")
+        lsec, lr_last, lph = leg(dict(radius="learned", sort="predicted", model=model, cnn_pool=cnn_pool))
         ms_cnn = mean("ms_cnn", lph)
         # algorithmic MACs of the network at one tail node, from its 9^3 patch: layer l
         # produces (7 - 2 l)^3 outputs of its per-output MACs
         macs_node = sum((7 - 2 * l) ** 3 * m
                         for l, m in enumerate((2 * 16 * 27, 16 * 16 * 27, 16 * 16 * 27, 16 * 27)))
         macs = macs_node * int(lr_last.n_tail)
+        if cnn_pool:
+            # pooled input: the whole coarse grid, 15,120 MACs per coarse node
+            coarse = int(np.prod([(n + 1) // 2 for n in pair.ref.shape]))
+            macs = coarse * sum(m for m in (2 * 16 * 27, 16 * 16 * 27, 16 * 16 * 27, 16 * 27))
         cnn_tflops = 2 * macs / (ms_cnn * 1e-3) / 1e12
         learned = {
             "value": round(lr_last.n_evaluated / lsec, 1),
@@ -338,10 +346,12 @@ def main():
             "phases_ms": {k: round(mean(k, lph), 4) for k in ("ms_prep", "ms_cnn", "ms_search", "ms_sort",
                                                               "ms_tail", "ms_guard")},
             "weights": os.path.relpath(args.weights, ROOT),
+            "cnn_pool": cnn_pool,
             "cnn_roofline": {"bound": "mfma", "achieved": round(cnn_tflops, 2), "peak": PEAK_BF16_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(cnn_tflops / PEAK_BF16_TFLOPS, 4),
                              "algorithmic_flop_per_launch": int(2 * macs),
-                             "flop_per_tail_node": int(2 * macs_node), "avg_launch_ms": round(ms_cnn, 5)},
+                             "flop_per_tail_node": None if cnn_pool else int(2 * macs_node),
+                             "avg_launch_ms": round(ms_cnn, 5)},
         }
         log(f"learned: {learned['ms_per_step']} ms/step, {learned['n_fallback']}/{learned['n_tail']} fallbacks")
 

@@ -111,7 +111,13 @@ typedef struct {
     double radius_factor;     /* f of the learned radius f * gamma_hat, >= 1 (default 1.1) */
     int32_t autotune;         /* gammax_batch: 1 = time the tail layouts of each new shape class on
                                  the first call and keep the fastest (see gammax_batch) */
-    int32_t reserved[3];      /* must be 0 */
+    int32_t cnn_pool;         /* resolution of the network input (learned radius / predicted order):
+                                 0 = the grid's own (each tail node's 9^3 patch);
+                                 2 = the pair average-pooled 2x2x2 (a grid at half the model's
+                                 training spacing), the network over the whole coarse grid and
+                                 gamma_hat interpolated trilinearly at the tail nodes
+                                 (see gammax_model_predict_nodes_pooled) */
+    int32_t reserved[2];      /* must be 0 */
 } gammax_options_t;
 
 typedef struct {
@@ -325,6 +331,23 @@ gammax_status_t gammax_model_predict_nodes(gammax_ctx_t *ctx, gammax_model_t *mo
                                            const gammax_problem_t *problem, const float *ref_dev,
                                            const float *eval_dev, const uint32_t *nodes_dev, int64_t n,
                                            float *y_dev, void *stream);
+
+/*
+ * Prediction at listed nodes of a grid finer than the model's training grid (the network
+ * input is not a quantity of the paper; the pooling keeps the network at the spacing it
+ * was trained on).  The pair is average-pooled 2x2x2 onto the coarse grid ceil(n / 2) per
+ * axis (coarse node c takes the mean of the fine nodes 2c, 2c + 1 per axis that exist), the
+ * features use the fine grid's max reference dose, the network runs on the whole coarse
+ * grid (as gammax_model_predict), and at each listed fine node p the coarse values
+ * gamma_hat + 0.01 = exp(y) are interpolated trilinearly at coarse position (p - 1/2) / 2
+ * per axis (clamped to the coarse grid): y_dev[i] = log of that value.  This is what
+ * gammax_map evaluates with options cnn_pool = 2.  Arguments as gammax_model_predict_nodes;
+ * the workspace (coarse features and activations) belongs to the context.  Synchronises.
+ */
+gammax_status_t gammax_model_predict_nodes_pooled(gammax_ctx_t *ctx, gammax_model_t *model,
+                                                  const gammax_problem_t *problem, const float *ref_dev,
+                                                  const float *eval_dev, const uint32_t *nodes_dev, int64_t n,
+                                                  float *y_dev, void *stream);
 
 /*
  * Forward pass over nvol crops: feat_dev holds nvol volumes of (c0+8) x (c1+8) x (c2+8)

@@ -28,6 +28,13 @@ log(gamma + 0.01) at that node.
   to bfloat16 (it is a matrix-core operand in the kernels); the weight gradients are
   exact sums of those bf16 products here, FP32 sums in the kernels.
 
+* Pooled input (for a grid at half the spacing the network was trained on): the pair is
+  averaged over 2x2x2 blocks onto the coarse grid ceil(n / 2) per axis (a block at an odd
+  edge averages the fine nodes it holds), the features use the fine grid's Dmax, the
+  network runs on the coarse grid, and at a fine node p the coarse values of
+  gamma_hat + 0.01 = exp(y) are interpolated trilinearly at coarse position (p - 1/2) / 2
+  per axis (coarse node k sits at fine position 2k + 1/2), clamped to the coarse grid.
+
 Parameter layout (one flat float array, the order the C ABI uses): for each layer l,
 W_l[co][ci][dz][dy][dx] followed by b_l[co].
 """
@@ -234,3 +241,60 @@ def predict_gamma(theta: np.ndarray, ref: np.ndarray, ev: np.ndarray, dd: float)
     """gamma_hat = max(exp(y) - 0.01, 0) at every grid node."""
     y = forward(theta, features(ref, ev, dd)).y
     return np.maximum(np.exp(y) - GAMMA_EPS, 0.0)
+
+
+def pool2(vol: np.ndarray) -> np.ndarray:
+    """FP64 mean over each 2x2x2 block of a 3D volume (ceil(n / 2) blocks per axis; a block
+    at an odd edge averages the nodes it holds)."""
+    v = np.asarray(vol, dtype=np.float64)
+    cz, cy, cx = [(n + 1) // 2 for n in v.shape]
+    total = np.zeros((cz, cy, cx))
+    count = np.zeros((cz, cy, cx))
+    for dz in range(2):
+        for dy in range(2):
+            for dx in range(2):
+                part = v[dz::2, dy::2, dx::2]
+                total[:part.shape[0], :part.shape[1], :part.shape[2]] += part
+                count[:part.shape[0], :part.shape[1], :part.shape[2]] += 1.0
+    return total / count
+
+
+def pooled_axis(p: np.ndarray, c: int):
+    """Trilinear interpolation on one axis: lower coarse index, upper index and weight of
+    the upper one for fine indices p (coarse node k at fine position 2k + 1/2)."""
+    u = np.clip((np.asarray(p, dtype=np.float64) - 0.5) / 2.0, 0.0, c - 1.0)
+    i0 = np.minimum(np.floor(u).astype(np.int64), c - 1)
+    i1 = np.minimum(i0 + 1, c - 1)
+    return i0, i1, u - i0
+
+
+def upsample_at(yc: np.ndarray, fine_shape, nodes: np.ndarray) -> np.ndarray:
+    """y at flat fine-grid node indices from the coarse output yc: exp(yc) interpolated
+    trilinearly, then log."""
+    nz, ny, nx = fine_shape
+    nodes = np.asarray(nodes, dtype=np.int64)
+    z, y, x = nodes // (ny * nx), (nodes // nx) % ny, nodes % nx
+    cz, cy, cx = yc.shape
+    z0, z1, tz = pooled_axis(z, cz)
+    y0, y1, ty = pooled_axis(y, cy)
+    x0, x1, tx = pooled_axis(x, cx)
+    g = np.exp(np.asarray(yc, dtype=np.float64))
+    val = np.zeros(len(nodes))
+    for zi, wz in ((z0, 1.0 - tz), (z1, tz)):
+        for yi, wy in ((y0, 1.0 - ty), (y1, ty)):
+            for xi, wx in ((x0, 1.0 - tx), (x1, tx)):
+                val += wz * wy * wx * g[zi, yi, xi]
+    return np.log(val)
+
+
+def pooled_forward(theta: np.ndarray, ref: np.ndarray, ev: np.ndarray, dd: float) -> Forward:
+    """The network on the pooled pair's coarse grid (features with the fine Dmax)."""
+    dmax = float(np.asarray(ref, dtype=np.float32).max())
+    f = features(pool2(ref).astype(np.float32), pool2(ev).astype(np.float32), dd, dose_max=dmax)
+    return forward(theta, f)
+
+
+def predict_pooled_at(theta: np.ndarray, ref: np.ndarray, ev: np.ndarray, dd: float,
+                      nodes: np.ndarray) -> np.ndarray:
+    """y = log(gamma_hat + 0.01) at fine nodes from the pooled input."""
+    return upsample_at(pooled_forward(theta, ref, ev, dd).y, np.shape(ref), nodes)

@@ -80,7 +80,8 @@ class Options(C.Structure):
         ("model", C.c_void_p),
         ("radius_factor", C.c_double),
         ("autotune", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("cnn_pool", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
 
@@ -250,8 +251,9 @@ def make_problem(shape: Sequence[int], spacing: Sequence[float], dd: float, dta:
 
 def make_options(sort: str = "none", precision: str = "guarded", cond_threshold: float = 1e6,
                  timing: bool = False, tail_lanes: int = 0, cell_lanes: int = 0, radius: str = "plain",
-                 model=None, radius_factor: float = 1.1) -> Options:
+                 model=None, radius_factor: float = 1.1, cnn_pool: int = 0) -> Options:
     o = default_options()
+    o.cnn_pool = int(cnn_pool)
     o.radius_mode = _RADIUS[radius]
     o.model = model.handle if model is not None else None
     o.radius_factor = float(radius_factor)
@@ -268,7 +270,8 @@ def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
                dose_threshold: float = 0.1, local: bool = False, *, sort: str = "none",
                precision: str = "guarded", cond_threshold: float = 1e6, timing: bool = False,
                tail_lanes: int = 0, cell_lanes: int = 0, radius: str = "plain", model=None,
-               radius_factor: float = 1.1, out=None, ctx: Optional[Context] = None, stream=None):
+               radius_factor: float = 1.1, cnn_pool: int = 0, out=None, ctx: Optional[Context] = None,
+               stream=None):
     """Gamma map of a dose pair on the GPU.  Returns (gamma tensor, GammaResult).
 
     ``ref``/``ev``: float32 device tensors of shape (ny, nx) or (nz, ny, nx); ``spacing``
@@ -291,7 +294,7 @@ def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
     ctx = ctx or context(dev)
     p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
     o = make_options(sort, precision, cond_threshold, timing, tail_lanes, cell_lanes, radius, model,
-                     radius_factor)
+                     radius_factor, cnn_pool)
     r = Result()
     s = stream if stream is not None else torch.cuda.current_stream(ref.device)
     with torch.cuda.device(ref.device):
@@ -323,7 +326,7 @@ def gammax_map_async(ref, ev, spacing: Sequence[float], dd: float, dta: float,
                      dose_threshold: float = 0.1, local: bool = False, *, sort: str = "none",
                      precision: str = "guarded", cond_threshold: float = 1e6, tail_lanes: int = 0,
                      cell_lanes: int = 0, radius: str = "plain", model=None, radius_factor: float = 1.1,
-                     out=None, ctx: Optional[Context] = None, stream=None) -> MapTicket:
+                     cnn_pool: int = 0, out=None, ctx: Optional[Context] = None, stream=None) -> MapTicket:
     """Queue a gamma map without waiting (``gammax_map_async``); the returned ticket's
     ``wait()`` gives the GammaResult.  The tensors are kept alive until then and must not
     be modified before it."""
@@ -344,7 +347,7 @@ def gammax_map_async(ref, ev, spacing: Sequence[float], dd: float, dta: float,
     ctx = ctx or context(dev)
     p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
     o = make_options(sort, precision, cond_threshold, False, tail_lanes, cell_lanes, radius, model,
-                     radius_factor)
+                     radius_factor, cnn_pool)
     t = C.c_uint64(0)
     s = stream if stream is not None else torch.cuda.current_stream(ref.device)
     with torch.cuda.device(ref.device):
@@ -458,6 +461,8 @@ _lib.gammax_model_predict.restype = C.c_int
 _lib.gammax_model_predict.argtypes = [_vp, _vp, C.POINTER(Problem), _vp, _vp, _vp, _vp]
 _lib.gammax_model_predict_nodes.restype = C.c_int
 _lib.gammax_model_predict_nodes.argtypes = [_vp, _vp, C.POINTER(Problem), _vp, _vp, _vp, C.c_int64, _vp, _vp]
+_lib.gammax_model_predict_nodes_pooled.restype = C.c_int
+_lib.gammax_model_predict_nodes_pooled.argtypes = [_vp, _vp, C.POINTER(Problem), _vp, _vp, _vp, C.c_int64, _vp, _vp]
 _lib.gammax_model_forward.restype = C.c_int
 _lib.gammax_model_forward.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64), _vp, _vp, _vp]
 _lib.gammax_model_train_step.restype = C.c_int
@@ -561,8 +566,11 @@ class Model:
 
 
 def predict_nodes(model, ref, ev, spacing: Sequence[float], dd: float, nodes, dta: float = 3.0,
-                  ctx: Optional[Context] = None):
-    """y = log(gamma_hat + 0.01) at flat node indices ``nodes`` (int32 device tensor)."""
+                  ctx: Optional[Context] = None, pool: int = 0):
+    """y = log(gamma_hat + 0.01) at flat node indices ``nodes`` (int32 device tensor).
+    ``pool=2``: from the pair average-pooled 2x2x2 (``gammax_model_predict_nodes_pooled``)."""
+    if pool not in (0, 2):
+        raise ValueError("pool must be 0 or 2")
     torch = _torch()
     _dev_tensor(ref, "ref")
     _dev_tensor(ev, "ev")
@@ -573,8 +581,9 @@ def predict_nodes(model, ref, ev, spacing: Sequence[float], dd: float, nodes, dt
     y = torch.empty(nodes.numel(), dtype=torch.float32, device=ref.device)
     s = torch.cuda.current_stream(ref.device)
     with torch.cuda.device(ref.device):
-        st = _lib.gammax_model_predict_nodes(ctx.handle, model.handle, C.byref(prob), ref.data_ptr(), ev.data_ptr(),
-                                             nodes.data_ptr(), nodes.numel(), y.data_ptr(), _vp(s.cuda_stream))
+        fn = _lib.gammax_model_predict_nodes_pooled if pool == 2 else _lib.gammax_model_predict_nodes
+        st = fn(ctx.handle, model.handle, C.byref(prob), ref.data_ptr(), ev.data_ptr(), nodes.data_ptr(),
+                nodes.numel(), y.data_ptr(), _vp(s.cuda_stream))
     ctx.check(st)
     return y
 
@@ -613,7 +622,7 @@ _lib.gammax_tune_load.argtypes = [_vp, C.c_char_p]
 
 def gammax_batch(pairs, *, precision: str = "guarded", cond_threshold: float = 1e6, tail_lanes: int = 0,
                  radius: str = "plain", model=None, radius_factor: float = 1.1, autotune: bool = False,
-                 outs=None, ctx: Optional[Context] = None, stream=None):
+                 cnn_pool: int = 0, outs=None, ctx: Optional[Context] = None, stream=None):
     """Gamma maps of a batch of pairs (``gammax_batch``): by default queued per-pair maps on
     the stream and three internal ones, with each pair's completion time in ``ms_done``
     (the single-pipeline batch runs only with GAMMAX_ENABLE_BATCH=1).
@@ -643,7 +652,8 @@ def gammax_batch(pairs, *, precision: str = "guarded", cond_threshold: float = 1
         out_list.append(g)
         refs[i], evs[i], gams[i] = q["ref"].data_ptr(), q["ev"].data_ptr(), g.data_ptr()
     ctx = ctx or context(dev.index or 0)
-    o = make_options("none", precision, cond_threshold, False, tail_lanes, 0, radius, model, radius_factor)
+    o = make_options("none", precision, cond_threshold, False, tail_lanes, 0, radius, model, radius_factor,
+                     cnn_pool)
     o.autotune = 1 if autotune else 0
     res = (Result * n)()
     s = stream if stream is not None else torch.cuda.current_stream(dev)
@@ -661,7 +671,7 @@ _lib.gammax_map_many.argtypes = [_vp, C.c_int32, C.POINTER(Problem), C.POINTER(_
 
 def gammax_map_many(pairs, *, sort: str = "none", precision: str = "guarded", cond_threshold: float = 1e6,
                     tail_lanes: int = 0, radius: str = "plain", model=None, radius_factor: float = 1.1,
-                    outs=None, ctx: Optional[Context] = None, stream=None):
+                    cnn_pool: int = 0, outs=None, ctx: Optional[Context] = None, stream=None):
     """Gamma maps of several pairs in one call (``gammax_map_many``): each pair index keeps
     a context of its own inside ``ctx``, the pairs run on the stream and three internal ones.
 
@@ -690,7 +700,7 @@ def gammax_map_many(pairs, *, sort: str = "none", precision: str = "guarded", co
         out_list.append(g)
         refs[i], evs[i], gams[i] = q["ref"].data_ptr(), q["ev"].data_ptr(), g.data_ptr()
     ctx = ctx or context(dev.index or 0)
-    o = make_options(sort, precision, cond_threshold, False, tail_lanes, 0, radius, model, radius_factor)
+    o = make_options(sort, precision, cond_threshold, False, tail_lanes, 0, radius, model, radius_factor, cnn_pool)
     res = (Result * n)()
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     with torch.cuda.device(dev):

@@ -71,5 +71,15 @@ hipError_t launch_cnn_tail(const float* ref, const float* ev, const int n[3], co
                            hipStream_t s);
 hipError_t launch_features(const float* ref, const float* ev, const int n[3], const Scalars* sc, uint16_t* feat,
                            hipStream_t s);
+// Coarse grid of the 2x2x2 average pooling of an n grid: ceil(n / 2) per axis.
+void pool2_shape(const int n[3], int c[3]);
+// Features (as launch_features, with the fine grid's Dmax and inv_dd from sc) of the pair
+// average-pooled 2x2x2 onto the coarse grid c = pool2_shape(n), padded by 4.
+hipError_t launch_features_pool2(const float* ref, const float* ev, const int n[3], const Scalars* sc,
+                                 uint16_t* feat, hipStream_t s);
+// y at the listed fine nodes from the network output yc on the coarse grid of the pooled
+// pair: gamma_hat + 0.01 = exp(yc) interpolated trilinearly, y its log; key as launch_cnn_tail.
+hipError_t launch_cnn_upsample(const float* yc, const int n[3], const uint32_t* nodes, const uint32_t* count,
+                               int max_blocks, float* y, uint32_t* key, hipStream_t s);
 
 }  // namespace gammax

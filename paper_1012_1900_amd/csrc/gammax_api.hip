@@ -40,6 +40,7 @@ struct GraphKey {
     const void* model;
     int32_t small_sort;
     int32_t tail_min_lanes;
+    int32_t cnn_pool;
     uint64_t generation;   // bumped on every (re)allocation and table build
 };
 
@@ -108,6 +109,8 @@ struct gammax_ctx {
     int64_t cnn_ws_cap = 0;
     float* yhat = nullptr;          // log(gamma_hat + 0.01) per grid node
     int64_t yhat_cap = 0;
+    float* ycoarse = nullptr;       // the network's output on the pooled coarse grid (cnn_pool 2)
+    int64_t ycoarse_cap = 0;
     struct BatchState* batch = nullptr;   // gammax_batch state (created on first use)
     struct ManyState* many = nullptr;     // gammax_map_many state (created on first use)
     uint64_t tail_hint = 0;         // tail length of the last map (picks the tail sort variant)
@@ -270,7 +273,8 @@ gammax_status_t check_options(gammax_ctx* c, const gammax_options_t* o) {
     if (!(o->cell_lanes == 0 || o->cell_lanes == 1 || o->cell_lanes == 4 || o->cell_lanes == 8))
         return fail(c, GAMMAX_E_PARAM, "cell_lanes must be 0, 1, 4 or 8");
     if (o->autotune != 0 && o->autotune != 1) return fail(c, GAMMAX_E_PARAM, "autotune must be 0 or 1");
-    for (int i = 0; i < 3; ++i)
+    if (o->cnn_pool != 0 && o->cnn_pool != 2) return fail(c, GAMMAX_E_PARAM, "cnn_pool must be 0 or 2");
+    for (int i = 0; i < 2; ++i)
         if (o->reserved[i] != 0) return fail(c, GAMMAX_E_PARAM, "reserved option fields must be 0");
     if (o->model && c && o->model->device != c->device)
         return fail(c, GAMMAX_E_PARAM, "model and context live on different devices");
@@ -431,6 +435,18 @@ gammax_status_t grow_cnn(gammax_ctx* c, const int o[3], CnnWs* w) {
     return GAMMAX_OK;
 }
 
+// Workspace of the pooled network input (cnn_pool 2) of a 3D problem: the CNN workspace of
+// the coarse grid and its output.
+gammax_status_t grow_pooled(gammax_ctx* c, const gammax_problem_t* p) {
+    const int n[3] = {(int)p->shape[0], (int)p->shape[1], (int)p->shape[2]};
+    int co[3];
+    pool2_shape(n, co);
+    CnnWs w;
+    gammax_status_t st = grow_cnn(c, co, &w);
+    if (st != GAMMAX_OK) return st;
+    return grow(c, &c->ycoarse, &c->ycoarse_cap, (int64_t)co[0] * co[1] * co[2]);
+}
+
 // The model is used on 3D problems when the learned radius or the predicted order is asked
 // for (2D problems keep the plain radius and order by |DD|).
 bool uses_model(const gammax_problem_t* p, const gammax_options_t* o) {
@@ -479,6 +495,10 @@ struct TailCnnHook {
     const float* ref;
     const float* ev;
     int shape[3];
+    // cnn_pool 2: the pooled pair's features, coarse activations and output
+    bool pooled;
+    CnnWs ws;
+    float* ycoarse;
     const Scalars* sc;
     const uint32_t* nodes;
     const uint32_t* count;
@@ -493,6 +513,16 @@ hipError_t tail_cnn_hook(void* user, hipStream_t s) {
     hipError_t e;
     if (h.ev0 && (e = hipEventRecord(h.ev0, s)) != hipSuccess) return e;
     gammax_model* m = const_cast<gammax_model*>(h.model);
+    if (h.pooled) {
+        int co[3];
+        pool2_shape(h.shape, co);
+        if ((e = launch_features_pool2(h.ref, h.ev, h.shape, h.sc, h.ws.feat, s)) != hipSuccess) return e;
+        if ((e = model_forward(m, h.ws.feat, 1, co, h.ws.a1, h.ws.a2, h.ws.a3, h.ycoarse, s)) != hipSuccess) return e;
+        if ((e = launch_cnn_upsample(h.ycoarse, h.shape, h.nodes, h.count, h.blocks, h.y, h.key, s)) != hipSuccess)
+            return e;
+        if (h.ev1 && (e = hipEventRecord(h.ev1, s)) != hipSuccess) return e;
+        return hipSuccess;
+    }
     const uint16_t* frag[3] = {frag_fwd(m, 0), frag_fwd(m, 1), frag_fwd(m, 2)};
     const float* bias[3] = {layer_bias(m, 0), layer_bias(m, 1), layer_bias(m, 2)};
     e = launch_cnn_tail(h.ref, h.ev, h.shape, h.sc, h.nodes, h.count, h.blocks, frag, bias, m->theta + CNN_OFF[3],
@@ -500,6 +530,15 @@ hipError_t tail_cnn_hook(void* user, hipStream_t s) {
     if (e != hipSuccess) return e;
     if (h.ev1 && (e = hipEventRecord(h.ev1, s)) != hipSuccess) return e;
     return hipSuccess;
+}
+
+// Point the hook at the pooled workspace (sized by grow_pooled for this problem).
+void set_pooled(gammax_ctx* c, TailCnnHook* h) {
+    int co[3];
+    pool2_shape(h->shape, co);
+    h->pooled = true;
+    h->ws = cnn_layout(c->cnn_ws, co);
+    h->ycoarse = c->ycoarse;
 }
 
 constexpr int kTailCnnBlocks = 2048;   // grid-stride one-wave blocks of the network at the tail nodes (8 per CU)
@@ -612,6 +651,7 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
         hook.ev0 = timing ? c->ev[9] : nullptr;
         hook.ev1 = timing ? c->ev[10] : nullptr;
         hook.blocks = kTailCnnBlocks;
+        if (opt.cnn_pool == 2) set_pooled(c, &hook);
         plan.after_zero = tail_cnn_hook;
         plan.after_zero_user = &hook;
     }
@@ -654,6 +694,7 @@ GraphKey key_of(gammax_ctx* c, const CallSetup& cs) {
     k.model = cs.opt->model;
     k.small_sort = (cs.opt->sort_mode != GAMMAX_SORT_NONE && c->tail_hint <= (uint64_t)SMALL_SORT_CAP) ? 1 : 0;
     k.tail_min_lanes = tail_min_lanes(c);
+    k.cnn_pool = cs.opt->cnn_pool;
     k.generation = c->generation;
     return k;
 }
@@ -793,6 +834,7 @@ gammax_status_t map_setup(gammax_ctx* c, const gammax_problem_t* p, const gammax
     if (opt->timing && (st = ensure_events(c)) != GAMMAX_OK) return st;
     *learned = uses_model(p, opt);
     if (*learned && (st = grow(c, &c->yhat, &c->yhat_cap, *n)) != GAMMAX_OK) return st;
+    if (*learned && opt->cnn_pool == 2 && (st = grow_pooled(c, p)) != GAMMAX_OK) return st;
     return GAMMAX_OK;
 }
 
@@ -876,7 +918,7 @@ gammax_status_t gammax_ctx_destroy(gammax_ctx_t* c) {
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void* dev[] = {c->d_sc, c->d_cnt, c->d_count, c->d_seq, c->work, c->blockcnt, c->part, c->hist,
-                   c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws, c->yhat};
+                   c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws, c->yhat, c->ycoarse};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     destroy_batch(c);
@@ -1155,6 +1197,44 @@ gammax_status_t gammax_pass_count(gammax_ctx_t* c, const float* gamma_dev, int64
 
 }  // extern "C"
 
+namespace {
+
+gammax_status_t predict_nodes(gammax_ctx_t* c, gammax_model_t* m, const gammax_problem_t* p, const float* ref,
+                              const float* ev, const uint32_t* nodes, int64_t n, float* y, void* stream, bool pooled) {
+    if (!c) return GAMMAX_E_NULL;
+    if (!m || !y || (!nodes && n > 0)) return fail(c, GAMMAX_E_NULL, "model, nodes and output are required");
+    if (m->device != c->device) return fail(c, GAMMAX_E_PARAM, "model and context live on different devices");
+    int o[3];
+    int64_t total = 0;
+    gammax_status_t st = model_inputs(c, p, ref, ev, o, &total);
+    if (st != GAMMAX_OK) return st;
+    if (n < 0 || n > total) return fail(c, GAMMAX_E_PARAM, "n must lie in [0, number of grid nodes]");
+    if (n == 0) return GAMMAX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (pooled && (st = grow_pooled(c, p)) != GAMMAX_OK) return st;
+    if ((st = enqueue_dose_scalars(c, p, ref, ev, total, s)) != GAMMAX_OK) return st;
+    *c->h_count = (uint32_t)n;
+    HIPCHK(c, hipMemcpyAsync(c->d_count, c->h_count, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    TailCnnHook h{};
+    h.model = m;
+    h.ref = ref;
+    h.ev = ev;
+    for (int i = 0; i < 3; ++i) h.shape[i] = o[i];
+    h.sc = c->d_sc;
+    h.nodes = nodes;
+    h.count = c->d_count;
+    h.y = y;
+    h.blocks = kTailCnnBlocks;
+    if (pooled) set_pooled(c, &h);
+    HIPCHK(c, tail_cnn_hook(&h, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return device_errors(c, false);
+}
+
+}  // namespace
+
 extern "C" {
 
 gammax_status_t gammax_model_features(gammax_ctx_t* c, const gammax_problem_t* p, const float* ref,
@@ -1198,34 +1278,13 @@ gammax_status_t gammax_model_predict(gammax_ctx_t* c, gammax_model_t* m, const g
 gammax_status_t gammax_model_predict_nodes(gammax_ctx_t* c, gammax_model_t* m, const gammax_problem_t* p,
                                            const float* ref, const float* ev, const uint32_t* nodes, int64_t n,
                                            float* y, void* stream) {
-    if (!c) return GAMMAX_E_NULL;
-    if (!m || !y || (!nodes && n > 0)) return fail(c, GAMMAX_E_NULL, "model, nodes and output are required");
-    if (m->device != c->device) return fail(c, GAMMAX_E_PARAM, "model and context live on different devices");
-    int o[3];
-    int64_t total = 0;
-    gammax_status_t st = model_inputs(c, p, ref, ev, o, &total);
-    if (st != GAMMAX_OK) return st;
-    if (n < 0 || n > total) return fail(c, GAMMAX_E_PARAM, "n must lie in [0, number of grid nodes]");
-    if (n == 0) return GAMMAX_OK;
-    hipStream_t s = (hipStream_t)stream;
-    HIPCHK(c, hipSetDevice(c->device));
-    if ((st = enqueue_dose_scalars(c, p, ref, ev, total, s)) != GAMMAX_OK) return st;
-    *c->h_count = (uint32_t)n;
-    HIPCHK(c, hipMemcpyAsync(c->d_count, c->h_count, sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    TailCnnHook h{};
-    h.model = m;
-    h.ref = ref;
-    h.ev = ev;
-    for (int i = 0; i < 3; ++i) h.shape[i] = o[i];
-    h.sc = c->d_sc;
-    h.nodes = nodes;
-    h.count = c->d_count;
-    h.y = y;
-    h.blocks = kTailCnnBlocks;
-    HIPCHK(c, tail_cnn_hook(&h, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    return device_errors(c, false);
+    return predict_nodes(c, m, p, ref, ev, nodes, n, y, stream, false);
+}
+
+gammax_status_t gammax_model_predict_nodes_pooled(gammax_ctx_t* c, gammax_model_t* m, const gammax_problem_t* p,
+                                                  const float* ref, const float* ev, const uint32_t* nodes, int64_t n,
+                                                  float* y, void* stream) {
+    return predict_nodes(c, m, p, ref, ev, nodes, n, y, stream, true);
 }
 
 }  // extern "C"
@@ -1612,6 +1671,7 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
     else gammax_options_default(&opt);
     gammax_status_t st = check_options(c, &opt);
     if (st != GAMMAX_OK) return st;
+    if (opt.cnn_pool != 0) return fail(c, GAMMAX_E_PARAM, "cnn_pool is not available on the single-pipeline batch");
     std::vector<int64_t> nn(n);
     for (int i = 0; i < n; ++i) {
         if ((st = check_problem(c, &probs[i], &nn[i])) != GAMMAX_OK)

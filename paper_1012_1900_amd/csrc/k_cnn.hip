@@ -422,6 +422,84 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ ref,
     }
 }
 
+// Features of the pair average-pooled 2x2x2 onto the coarse grid (cz, cy, cx) = ceil(n / 2),
+// padded by 4: coarse node c takes the mean of the fine nodes 2c and 2c + 1 per axis that lie
+// in the grid (fewer at an odd edge); f0 and f1 as in k_features, with the fine grid's Dmax
+// and inv_dd.  One thread per padded coarse node; the fine loads of neighbouring threads
+// are contiguous pairs along x.
+__global__ __launch_bounds__(256) void k_features_pool2(const float* __restrict__ ref, const float* __restrict__ ev,
+                                                        int nz, int ny, int nx, const Scalars* __restrict__ sc,
+                                                        uint16_t* __restrict__ feat) {
+    const int cz = (nz + 1) >> 1, cy = (ny + 1) >> 1, cx = (nx + 1) >> 1;
+    const int pz = cz + 8, py = cy + 8, px = cx + 8;
+    const int64_t total = (int64_t)pz * py * px;
+    const float dmax = ord_to_float(sc->dmax_ord);
+    const float inv_max = 1.0f / dmax;
+    const float inv_dd = sc->inv_dd;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int x = (int)(i % px) - 4, y = (int)((i / px) % py) - 4, z = (int)(i / ((int64_t)px * py)) - 4;
+        uint32_t q = 0u;
+        if (x >= 0 && x < cx && y >= 0 && y < cy && z >= 0 && z < cz) {
+            float sr = 0.f, se = 0.f;
+            int cnt = 0;
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const int fz = 2 * z + dz, fy = 2 * y + dy, fx = 2 * x + dx;
+                        if (fz < nz && fy < ny && fx < nx) {
+                            const int64_t n = ((int64_t)fz * ny + fy) * nx + fx;
+                            sr += ref[n];
+                            se += ev[n];
+                            ++cnt;
+                        }
+                    }
+            const float r = sr / (float)cnt, e = se / (float)cnt;
+            q = pack2bf(r * inv_max, (e - r) * inv_dd);
+        }
+        reinterpret_cast<uint32_t*>(feat)[i] = q;
+    }
+}
+
+// Trilinear weights of fine node index p on a coarse axis of c nodes whose node k sits at
+// fine position 2k + 1/2: coarse position u = (p - 1/2) / 2 clamped to [0, c - 1].
+__device__ __forceinline__ void pool2_axis(int p, int c, int& i0, int& i1, float& t) {
+    float u = 0.5f * (float)p - 0.25f;
+    u = fminf(fmaxf(u, 0.0f), (float)(c - 1));
+    i0 = min((int)u, c - 1);
+    i1 = min(i0 + 1, c - 1);
+    t = u - (float)i0;
+}
+
+// y at listed fine nodes (grid nz x ny x nx) from the coarse network output yc (grid
+// ceil(n / 2)): exp(yc) = gamma_hat + 0.01 interpolated trilinearly, y = its log.
+__global__ __launch_bounds__(256) void k_cnn_upsample(const float* __restrict__ yc, int nz, int ny, int nx,
+                                                      const uint32_t* __restrict__ nodes,
+                                                      const uint32_t* __restrict__ count, float* __restrict__ y,
+                                                      uint32_t* __restrict__ key) {
+    const int cz = (nz + 1) >> 1, cy = (ny + 1) >> 1, cx = (nx + 1) >> 1;
+    const uint32_t M = *count;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < M; i += gridDim.x * 256) {
+        const int node = (int)nodes[i];
+        const int x = node % nx, yy = (node / nx) % ny, z = node / (nx * ny);
+        int z0, z1, y0, y1, x0, x1;
+        float tz, ty, tx;
+        pool2_axis(z, cz, z0, z1, tz);
+        pool2_axis(yy, cy, y0, y1, ty);
+        pool2_axis(x, cx, x0, x1, tx);
+        float g[8];   // corner k: z from bit 2, y from bit 1, x from bit 0
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            g[k] = expf(yc[((int64_t)(k & 4 ? z1 : z0) * cy + (k & 2 ? y1 : y0)) * cx + (k & 1 ? x1 : x0)]);
+        const float v00 = g[0] + tx * (g[1] - g[0]), v01 = g[2] + tx * (g[3] - g[2]);
+        const float v10 = g[4] + tx * (g[5] - g[4]), v11 = g[6] + tx * (g[7] - g[6]);
+        const float v0 = v00 + ty * (v01 - v00), v1 = v10 + ty * (v11 - v10);
+        const float v = v0 + tz * (v1 - v0);
+        const float yv = logf(v);
+        y[i] = yv;
+        if (key) key[i] = f2u(fmaxf(expf(yv) - 0.01f, 0.0f));
+    }
+}
+
 // ---- the network at listed nodes only ------------------------------------------------
 //
 // One workgroup per node (grid-stride over the list): the node's 9x9x9 feature patch is
@@ -790,6 +868,27 @@ hipError_t launch_features(const float* ref, const float* ev, const int n[3], co
                            hipStream_t s) {
     const int64_t total = (int64_t)(n[0] + 8) * (n[1] + 8) * (n[2] + 8);
     hipLaunchKernelGGL(k_features, dim3(grid_for(total, 4096)), dim3(256), 0, s, ref, ev, n[0], n[1], n[2], sc, feat);
+    return hipGetLastError();
+}
+
+void pool2_shape(const int n[3], int c[3]) {
+    for (int i = 0; i < 3; ++i) c[i] = (n[i] + 1) / 2;
+}
+
+hipError_t launch_features_pool2(const float* ref, const float* ev, const int n[3], const Scalars* sc,
+                                 uint16_t* feat, hipStream_t s) {
+    int c[3];
+    pool2_shape(n, c);
+    const int64_t total = (int64_t)(c[0] + 8) * (c[1] + 8) * (c[2] + 8);
+    hipLaunchKernelGGL(k_features_pool2, dim3(grid_for(total, 4096)), dim3(256), 0, s, ref, ev, n[0], n[1], n[2], sc,
+                       feat);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_upsample(const float* yc, const int n[3], const uint32_t* nodes, const uint32_t* count,
+                               int max_blocks, float* y, uint32_t* key, hipStream_t s) {
+    hipLaunchKernelGGL(k_cnn_upsample, dim3(max_blocks > 0 ? max_blocks : 1), dim3(256), 0, s, yc, n[0], n[1], n[2],
+                       nodes, count, y, key);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ def test_header_declares_the_boundary():
                  "gammax_model_features", "gammax_model_predict", "gammax_model_forward",
                  "gammax_model_train_step", "gammax_model_last_error", "gammax_model_predict_nodes",
                  "gammax_batch", "gammax_tune_save", "gammax_tune_load", "gammax_map_async",
-                 "gammax_map_wait", "gammax_map_many"]:
+                 "gammax_map_wait", "gammax_map_many", "gammax_model_predict_nodes_pooled"]:
         assert must in names
 
 
@@ -52,7 +52,8 @@ def test_options_defaults(abi):
     assert o.sort_mode == abi.SORT_NONE
     assert o.precision == abi.PREC_GUARDED
     assert o.cond_threshold == 1e6
-    assert o.timing == 0 and o.tail_lanes == 0 and o.cell_lanes == 0 and list(o.reserved) == [0] * 3 and o.autotune == 0
+    assert o.timing == 0 and o.tail_lanes == 0 and o.cell_lanes == 0 and list(o.reserved) == [0] * 2
+    assert o.autotune == 0 and o.cnn_pool == 0
     assert o.radius_mode == abi.RADIUS_PLAIN and not o.model and o.radius_factor == 1.1
 
 

@@ -203,3 +203,35 @@ def test_predict_at_listed_nodes(gx):
     assert np.all(np.abs(y - want) <= 4 * 2.0 ** -8 * A + 1e-6)
     dense = host(m.predict(ref, ev, pair.spacing, 0.03)).ravel()[nodes]
     assert np.all(np.abs(y - dense) <= 1e-5 * A + 1e-6)
+
+
+def test_predict_pooled_at_listed_nodes(gx):
+    """The pooled input (gammax_model_predict_nodes_pooled): the pair averaged 2x2x2, the
+    network on the coarse grid, exp(y) interpolated trilinearly at the fine nodes.  Against
+    the oracle, within the bf16 bound of the 8 coarse corners of each node (the log of an
+    interpolated exp moves by at most the largest corner error); odd and even axes."""
+    import torch
+    from dosegen import make_pair_3d
+    pair = make_pair_3d(8, shape=(25, 30, 27), spacing=(1.25, 1.25, 1.25))
+    th = _theta(11)
+    m = gx.Model(th.astype(np.float32))
+    ref, ev = dev(pair.ref), dev(pair.eval)
+    n = pair.ref.size
+    rng = np.random.default_rng(12)
+    nz, ny, nx = pair.ref.shape
+    corners = [((z * ny) + y) * nx + x for z in (0, nz - 1) for y in (0, ny - 1) for x in (0, nx - 1)]
+    nodes = np.unique(np.concatenate([rng.choice(n, 600, replace=False), corners])).astype(np.int32)
+    y = host(gx.predict_nodes(m, ref, ev, pair.spacing, 0.03, torch.from_numpy(nodes).to("cuda"), pool=2))
+    want = cnn.predict_pooled_at(th, pair.ref, pair.eval, 0.03, nodes)
+    dmax = float(pair.ref.max())
+    fc = cnn.features(cnn.pool2(pair.ref).astype(np.float32), cnn.pool2(pair.eval).astype(np.float32), 0.03,
+                      dose_max=dmax)
+    A = _abs_network(th, fc)
+    z, yy, x = np.unravel_index(nodes.astype(np.int64), pair.ref.shape)
+    bound = np.zeros(len(nodes))
+    axes = [cnn.pooled_axis(p, c) for p, c in ((z, A.shape[0]), (yy, A.shape[1]), (x, A.shape[2]))]
+    for zi in axes[0][:2]:
+        for yi in axes[1][:2]:
+            for xi in axes[2][:2]:
+                bound = np.maximum(bound, A[zi, yi, xi])
+    assert np.all(np.abs(y - want) <= 4 * 2.0 ** -8 * bound + 1e-5)

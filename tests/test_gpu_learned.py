@@ -165,3 +165,27 @@ def test_trained_network_gains_over_the_dd_order(gx):
     eff_hat = _lockstep_efficiency(work, np.argsort(ghat[tail], kind="stable"))
     eff_dd = _lockstep_efficiency(work, np.argsort(g0[tail], kind="stable"))
     assert eff_hat > eff_dd, (eff_hat, eff_dd)
+
+
+@pytest.mark.parametrize("kind", ["random", "zero"])
+def test_learned_pooled_input_equals_plain(gx, models, kind):
+    """cnn_pool = 2 (a 1.25 mm grid, the network on the pair pooled to 2.5 mm): the same
+    gamma as the plain search, also on graph replays and queued maps."""
+    from dosegen import make_pair_3d
+    p = make_pair_3d(33, shape=(48, 50, 46), spacing=(1.25, 1.25, 1.25))
+    ref, ev = dev(p.ref), dev(p.eval)
+    g_plain, r_plain = gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1)
+    ctx = gx.Context(0)
+    kw = dict(radius="learned", sort="predicted", model=models[kind], cnn_pool=2, ctx=ctx)
+    for _ in range(3):
+        g_l, r_l = gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, **kw)
+        assert np.array_equal(host(g_plain), host(g_l))
+        assert (r_l.n_pass, r_l.n_tail) == (r_plain.n_pass, r_plain.n_tail)
+    assert r_plain.n_tail > 0
+    if kind == "zero":
+        assert r_l.n_fallback == r_l.n_tail
+    t = gx.gammax_map_async(ref, ev, p.spacing, 0.03, 3.0, 0.1, **kw)
+    t.wait()
+    assert np.array_equal(host(g_plain), host(t.gamma))
+    _, r_t = gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, timing=True, **kw)
+    assert r_t.ms_cnn > 0

@@ -243,3 +243,60 @@ def _loss_without_relu_mask(theta, feats, gamma, mask, rounding=True):
         if l > 0:
             g = cnn.conv3d_bwd_data(g, w, fw.inputs[l].shape[1:])
     return float((r * r).sum() / cnt), cnn.flatten(grads), fw
+
+
+# ---- pooled input (a grid at half the training spacing) ---------------------------------
+
+def test_pool2_brute_force_odd_and_even_shapes():
+    rng = np.random.default_rng(70)
+    for shape in ((3, 5, 4), (4, 2, 6), (1, 3, 2)):
+        v = rng.uniform(0.0, 2.0, size=shape)
+        got = cnn.pool2(v)
+        want = np.zeros(tuple((n + 1) // 2 for n in shape))
+        for cz in range(want.shape[0]):
+            for cy in range(want.shape[1]):
+                for cx in range(want.shape[2]):
+                    vals = [v[z, y, x] for z in (2 * cz, 2 * cz + 1) for y in (2 * cy, 2 * cy + 1)
+                            for x in (2 * cx, 2 * cx + 1)
+                            if z < shape[0] and y < shape[1] and x < shape[2]]
+                    want[cz, cy, cx] = sum(vals) / len(vals)
+        assert np.allclose(got, want, rtol=0, atol=1e-15)
+
+
+def test_pool2_preserves_constants_and_even_sums():
+    assert np.all(cnn.pool2(np.full((5, 7, 3), 1.25)) == 1.25)
+    v = np.random.default_rng(71).uniform(size=(6, 4, 8))
+    assert np.isclose(8.0 * cnn.pool2(v).sum(), v.sum(), rtol=1e-14)
+
+
+def test_upsample_reproduces_linear_gamma_and_clamps_at_edges():
+    """exp(y) interpolated trilinearly: a positive linear function of the coarse index is
+    reproduced exactly at every fine node, with the coarse position (p - 1/2) / 2 clamped
+    to the coarse grid."""
+    fine = (9, 8, 11)
+    cz, cy, cx = [(n + 1) // 2 for n in fine]
+    a, b = 2.0, np.array([0.3, -0.1, 0.05])
+    kz, ky, kx = np.meshgrid(np.arange(cz), np.arange(cy), np.arange(cx), indexing="ij")
+    yc = np.log(a + b[0] * kz + b[1] * ky + b[2] * kx)
+    nodes = np.arange(np.prod(fine))
+    got = np.exp(cnn.upsample_at(yc, fine, nodes))
+    z, y, x = np.unravel_index(nodes, fine)
+    u = [np.clip((p - 0.5) / 2.0, 0, c - 1) for p, c in ((z, cz), (y, cy), (x, cx))]
+    want = a + b[0] * u[0] + b[1] * u[1] + b[2] * u[2]
+    assert np.allclose(got, want, rtol=1e-13, atol=0)
+    # node 0 clamps to coarse node 0 on every axis; constants stay constant
+    assert np.isclose(got[0], np.exp(yc[0, 0, 0]), rtol=1e-14)
+    assert np.allclose(cnn.upsample_at(np.full((cz, cy, cx), -0.7), fine, nodes), -0.7, rtol=0, atol=1e-15)
+
+
+def test_pooled_forward_of_block_constant_pair_is_the_coarse_network():
+    """A fine pair that is constant on every 2x2x2 block pools back to the coarse pair, so
+    the pooled network is the network on the coarse pair (same Dmax)."""
+    rng = np.random.default_rng(72)
+    cref = rng.uniform(0.1, 2.0, size=(6, 5, 7)).astype(np.float32)
+    cev = (cref * rng.uniform(0.9, 1.1, size=cref.shape)).astype(np.float32)
+    rep = lambda c: np.repeat(np.repeat(np.repeat(c, 2, 0), 2, 1), 2, 2)
+    th = cnn.init_params(73)
+    got = cnn.pooled_forward(th, rep(cref), rep(cev), 0.03).y
+    want = cnn.forward(th, cnn.features(cref, cev, 0.03)).y
+    assert np.array_equal(got, want)
