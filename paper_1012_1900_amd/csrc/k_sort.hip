@@ -13,7 +13,7 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr int SORT_THREADS = 256;
-constexpr int SORT_CHUNKS = 16;
+constexpr int SORT_CHUNKS = 4;
 constexpr int SORT_TILE = SORT_THREADS * SORT_CHUNKS;
 constexpr int RADIX = 256;
 constexpr int NWAVES = SORT_THREADS / WAVE;
@@ -27,11 +27,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __r
                                                              int shift, uint32_t* __restrict__ hist,
                                                              int64_t nb) {
     const int64_t n = count_of(n_max, n_dev);
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    if (base >= n) return;   // uniform: the scan and the scatter use only the tiles that exist
     __shared__ uint32_t h[RADIX];
     h[threadIdx.x] = 0u;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
-#pragma unroll 4
+#pragma unroll
     for (int k = 0; k < SORT_CHUNKS; ++k) {
         int64_t i = base + (int64_t)k * SORT_THREADS + threadIdx.x;
         if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
@@ -63,18 +64,22 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
     return off + x - v;
 }
 
-// One workgroup per digit: exclusive scan of that digit's counts over the tiles.
+// One workgroup per digit: exclusive scan of that digit's counts over the tiles that hold
+// elements (the first ceil(n / SORT_TILE) of the nb the grid was sized for).
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scan(uint32_t* __restrict__ hist, int64_t nb,
+                                                             int64_t n_max, const uint32_t* n_dev,
                                                              uint32_t* __restrict__ totals) {
     __shared__ uint32_t s_wave[NWAVES];
+    const int64_t n = count_of(n_max, n_dev);
+    const int64_t used = min(nb, (n + SORT_TILE - 1) / SORT_TILE);
     uint32_t* row = hist + (int64_t)blockIdx.x * nb;
     uint32_t carry = 0u;
-    for (int64_t b0 = 0; b0 < nb; b0 += SORT_THREADS) {
+    for (int64_t b0 = 0; b0 < used; b0 += SORT_THREADS) {
         int64_t i = b0 + threadIdx.x;
-        uint32_t v = i < nb ? row[i] : 0u;
+        uint32_t v = i < used ? row[i] : 0u;
         uint32_t tot;
         uint32_t ex = block_exclusive_scan(v, s_wave, &tot);
-        if (i < nb) row[i] = carry + ex;
+        if (i < used) row[i] = carry + ex;
         carry += tot;
     }
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
@@ -100,14 +105,20 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const int lane = t & (WAVE - 1), w = t / WAVE;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
     const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    // every chunk's pair is loaded before the first is ranked: one memory latency per tile
+    uint32_t keys[SORT_CHUNKS], vals[SORT_CHUNKS];
+#pragma unroll
+    for (int k = 0; k < SORT_CHUNKS; ++k) {
+        const int64_t i = base + (int64_t)k * SORT_THREADS + t;
+        const int64_t j = i < n ? i : n - 1;   // n > base: the clamped index is in range
+        keys[k] = kin[j];
+        vals[k] = vin[j];
+    }
+#pragma unroll
     for (int k = 0; k < SORT_CHUNKS; ++k) {
         const int64_t i = base + (int64_t)k * SORT_THREADS + t;
         const bool valid = i < n;
-        uint32_t key = 0u, val = 0u;
-        if (valid) {
-            key = kin[i];
-            val = vin[i];
-        }
+        const uint32_t key = valid ? keys[k] : 0u, val = vals[k];
         const uint32_t dig = (key >> shift) & (RADIX - 1);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -260,7 +271,7 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, 
     for (int shift = 0; shift < 32; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(SORT_THREADS), 0, s, ki, n_max, n_dev,
                            shift, hist, nb);
-        hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nb, totals);
+        hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nb, n_max, n_dev, totals);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo,
                            n_max, n_dev, shift, hist, totals, nb);
         uint32_t* tk = ki;
