@@ -101,6 +101,116 @@ def cpu_baseline(pair, dd, dta, reps):
     }, o
 
 
+# ---- sweeps of the paper's scaling studies --------------------------------------------------
+
+# resolution levels of the scaling study (Sec. 3.5): the same box as the 3D workloads
+# (240 x 320 x 320 mm, z slowest) sampled at the paper's four grid sizes
+SWEEP_RESOLUTIONS = ((144, 128, 128), (72, 256, 256), (144, 256, 256), (72, 512, 512))
+SWEEP_BOX_MM = (240.0, 320.0, 320.0)
+
+
+def _time_maps(gx, torch, ref, ev, spacing, dd, dta, steps, warmup):
+    """ms per queued map (graph replays, results collected inside the timed region), the
+    phase times of one timed map, and that map's gamma and result."""
+    for _ in range(warmup):
+        gx.gammax_map(ref, ev, spacing, dd, dta, 0.1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = [gx.gammax_map_async(ref, ev, spacing, dd, dta, 0.1) for _ in range(steps)]
+    for t in tickets:
+        t.wait()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    g, r = gx.gammax_map(ref, ev, spacing, dd, dta, 0.1, timing=True)
+    return ms, g, r
+
+
+def _sweep_point(gx, torch, np, ref, ev, spacing, dd, dta, args, **extra):
+    steps = min(args.steps, gx.ASYNC_SLOTS)
+    ms, g, r = _time_maps(gx, torch, ref, ev, spacing, dd, dta, steps, args.warmup)
+    gh = g.double()
+    gam = gh[gh >= 0]
+    # the search proper (the paper's T_gamma): key-0 pass, sort, walk, guard; no prep
+    ms_gamma = r.ms_search + r.ms_sort + r.ms_tail + r.ms_guard
+    pt = dict(dd=dd, dta=dta, shape=list(ref.shape), spacing_mm=[round(h, 4) for h in spacing],
+              n_grid=int(ref.numel()), n_evaluated=int(r.n_evaluated), ms_per_map=round(ms, 4),
+              ms_gamma=round(ms_gamma, 4), n_cells=int(r.n_cells), n_tail=int(r.n_tail),
+              sum_gamma3=float((gam ** 3).sum().item()), pass_rate=round(r.pass_rate, 6),
+              max_gamma=round(r.max_gamma, 4))
+    pt.update(extra)
+    print(json.dumps(pt), flush=True)
+    return pt
+
+
+def _fit_line(x, y):
+    import numpy as np
+    x, y = np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64)
+    a, b = np.polyfit(x, y, 1)
+    pred = a * x + b
+    ss = float(((y - y.mean()) ** 2).sum())
+    r2 = 1.0 - float(((y - pred) ** 2).sum()) / ss if ss > 0 else 1.0
+    return float(a), float(b), r2
+
+
+def run_sweep(args):
+    """The paper's scaling studies on synthetic pairs, one JSON line per point and a last
+    line with the fits:
+    * criteria: DD x DTA in {1,2,3}% x {1,2,3} mm on the 256x256x192 workload (Table 3);
+    * resolution: the 3D generator over one box at four grid sizes, T ~ N^a (Fig. 2);
+    * shift: evaluation dose + s Dmax inside the 10 % region, s = -10 % ... +10 % in 1 %
+      steps, on the 256x256x192 workload, T against sum(gamma^3) (Fig. 1b)."""
+    import numpy as np
+    import torch
+
+    import paper_1012_1900_amd as gx
+    from dosegen import make_config_pair, make_pair_3d
+
+    dev = torch.device("cuda", 0)
+    kind = args.sweep
+    pts = []
+    if kind in ("criteria", "shift"):
+        cfg, seed, _ = WORKLOADS["3d_256x256x192_1.25mm"]
+        pair = make_config_pair(cfg, seed)
+        ref = torch.from_numpy(pair.ref).to(dev)
+    if kind == "criteria":
+        ev = torch.from_numpy(pair.eval).to(dev)
+        for dd in (0.01, 0.02, 0.03):
+            for dta in (1.0, 2.0, 3.0):
+                pts.append(_sweep_point(gx, torch, np, ref, ev, pair.spacing, dd, dta, args))
+        t = {(p["dd"], p["dta"]): p["ms_gamma"] for p in pts}
+        summary = dict(sweep="criteria", proportional_ms_gamma=[t[(0.01, 1.0)], t[(0.02, 2.0)], t[(0.03, 3.0)]])
+    elif kind == "resolution":
+        for shape in SWEEP_RESOLUTIONS:
+            spacing = tuple(b / n for b, n in zip(SWEEP_BOX_MM, shape))
+            log(f"generating {shape}")
+            p = make_pair_3d(WORKLOADS["3d_256x256x192_1.25mm"][1], shape=shape, spacing=spacing)
+            r_, e_ = torch.from_numpy(p.ref).to(dev), torch.from_numpy(p.eval).to(dev)
+            pts.append(_sweep_point(gx, torch, np, r_, e_, spacing, args.dd, args.dta, args))
+            del r_, e_
+        n = [p["n_grid"] for p in pts]
+        a_map, _, r2_map = _fit_line(np.log(n), np.log([p["ms_per_map"] for p in pts]))
+        a_g, _, r2_g = _fit_line(np.log(n), np.log([p["ms_gamma"] for p in pts]))
+        a_c, _, r2_c = _fit_line(np.log(n), np.log([p["n_cells"] for p in pts]))
+        summary = dict(sweep="resolution", exponent_ms_per_map=round(a_map, 3), r2_ms_per_map=round(r2_map, 4),
+                       exponent_ms_gamma=round(a_g, 3), r2_ms_gamma=round(r2_g, 4),
+                       exponent_cells=round(a_c, 3), r2_cells=round(r2_c, 4))
+    elif kind == "shift":
+        ev0 = torch.from_numpy(pair.eval).to(dev)
+        dmax = float(pair.ref.max())
+        region = ref >= 0.1 * dmax
+        for k in range(-10, 11):
+            ev = torch.where(region, ev0 + (0.01 * k) * dmax, ev0)
+            pts.append(_sweep_point(gx, torch, np, ref, ev, pair.spacing, args.dd, args.dta, args, shift=k / 100))
+        s3 = [p["sum_gamma3"] for p in pts]
+        a, b, r2 = _fit_line(s3, [p["ms_gamma"] for p in pts])
+        ac, bc, r2c = _fit_line(s3, [p["n_cells"] for p in pts])
+        summary = dict(sweep="shift", ms_gamma_vs_sum_gamma3=dict(slope=a, intercept_ms=round(b, 4), r2=round(r2, 4)),
+                       cells_vs_sum_gamma3=dict(slope=ac, intercept=round(bc, 1), r2=round(r2c, 4)))
+    else:
+        raise SystemExit(f"unknown sweep {kind}")
+    print(json.dumps(summary), flush=True)
+
+
 def _mixed_pair(spec):
     from dosegen import make_batch_pair
     p = make_batch_pair(spec)
@@ -226,6 +336,8 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1012_1900_amd", "weights",
                                                       "cnn_3d_2.5mm_3pct3mm.npy"))
     ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--sweep", choices=["criteria", "resolution", "shift"], default=None,
+                    help="run one of the paper's scaling studies instead of the benchmark line")
     ap.add_argument("--streams", type=int, default=4,
                     help="mixed batch: spread the pairs round-robin over this many streams (the GPU "
                          "runs 4 hardware queues per process)")
@@ -242,6 +354,9 @@ def main():
 
     if args.workload == MIXED[0]:
         run_mixed(args)
+        return
+    if args.sweep:
+        run_sweep(args)
         return
 
     import numpy as np
