@@ -209,6 +209,36 @@ __device__ __forceinline__ double tet_fp64(const GuardCtx& c, int perm) {
     return (t1 <= 1.0 && t1 >= t2 && t2 >= t3 && t3 >= 0.0) ? N * L : __builtin_huge_val();
 }
 
+// Normalised dose difference of a cell vertex, rounded as its own product: the walks of
+// every tail layout feed the projections the same values, whatever the compiler fuses
+// around them.
+template <typename T>
+__device__ __forceinline__ T dose_norm(T v, T dr, T inv) {
+#pragma clang fp contract(off)
+    return (v - dr) * inv;
+}
+
+// Whether any of the six tetrahedra of a 3D cell has a normal-equation denominator above
+// den_guard: the test cell3 applies (GMODE 1), with its chain steps and its summation order.
+__device__ __forceinline__ bool tets_ill(const float* g, const InvS2<float>& is, float den_guard) {
+    auto p = [](float hi, float lo, float inv) {
+        const float d = hi - lo;
+        return d * (d * inv);
+    };
+    const float p0x = p(g[1], g[0], is.x), p0y = p(g[2], g[0], is.y), p0z = p(g[4], g[0], is.z);
+    const float p1y = p(g[3], g[1], is.y), p1z = p(g[5], g[1], is.z);
+    const float p2x = p(g[3], g[2], is.x), p2z = p(g[6], g[2], is.z);
+    const float p4x = p(g[5], g[4], is.x), p4y = p(g[6], g[4], is.y);
+    const float p3z = p(g[7], g[3], is.z), p5y = p(g[7], g[5], is.y), p6x = p(g[7], g[6], is.x);
+    bool ill = ((1.0f + p0x) + p1y) + p3z > den_guard;
+    ill = ill || ((1.0f + p0x) + p1z) + p5y > den_guard;
+    ill = ill || ((1.0f + p0y) + p2x) + p3z > den_guard;
+    ill = ill || ((1.0f + p0y) + p2z) + p6x > den_guard;
+    ill = ill || ((1.0f + p0z) + p4x) + p5y > den_guard;
+    ill = ill || ((1.0f + p0z) + p4y) + p6x > den_guard;
+    return ill;
+}
+
 // All faces owned by one 3D cell; returns the smallest dist^2 (or +inf).
 // ok_*: the cell extends along that axis inside the grid (MASKED only).
 // GMODE 0: no guard; 1: flag an ill-conditioned tetrahedron (ill = true); 2: project it
@@ -821,7 +851,7 @@ __device__ __forceinline__ void walk_body(const SearchArgs& a, const TabEntry* _
                 v[7] = a.ev[base + oz + oy + ox];
                 T g[8];
 #pragma unroll
-                for (int b = 0; b < 8; ++b) g[b] = ((T)v[b] - drT) * invdd;
+                for (int b = 0; b < 8; ++b) g[b] = dose_norm<T>((T)v[b], drT, invdd);
                 GuardCtx gc{};
                 if constexpr (GMODE == 2) {
                     gc = GuardCtx{a.ev, base, ox, oy, oz, dr, inv_dd64, e.ax, e.ay, e.az, sx2d, sy2d, sz2d};
@@ -840,7 +870,7 @@ __device__ __forceinline__ void walk_body(const SearchArgs& a, const TabEntry* _
                 v[3] = a.ev[base + oy + ox];
                 T g[4];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) g[b] = ((T)v[b] - drT) * invdd;
+                for (int b = 0; b < 4; ++b) g[b] = dose_norm<T>((T)v[b], drT, invdd);
                 T c;
                 if (wave_masked)
                     c = cell2<T, true>(g, G, is, okx, oky);
@@ -963,36 +993,55 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
             const bool edge = !(okx && oky && okz);
             const bool wave_masked = __ballot(work && edge) != 0ull;
             float c = Num<float>::inf();
+            constexpr int NV = DIM == 3 ? 8 : 4;
+            float g[NV];
+            // Dose bound: the PL dose inside the cell lies between its vertex values, so a
+            // cell whose vertex differences share a sign is at least key^2 + (smallest
+            // |difference|)^2 from the node; at or above F it cannot lower F and is skipped
+            // (still counted as visited).  A lane's decision is its own, so the result does
+            // not depend on which nodes share the wave.
+            bool need = false;
             if (work) {
                 lane_cells += edge ? 0u : 1u;
                 const int base_i = (DIM == 3 ? qz * sxy : 0) + qy * nx + qx;
                 const int ox = okx ? 1 : 0, oy = oky ? nx : 0, oz = (DIM == 3 && okz) ? sxy : 0;
-                const Geo<float> Gm = geo_from_row(e);
+                g[0] = a.ev[base_i];
+                g[1] = a.ev[base_i + ox];
+                g[2] = a.ev[base_i + oy];
+                g[3] = a.ev[base_i + oy + ox];
                 if constexpr (DIM == 3) {
-                    float g[8];
-                    g[0] = a.ev[base_i];
-                    g[1] = a.ev[base_i + ox];
-                    g[2] = a.ev[base_i + oy];
-                    g[3] = a.ev[base_i + oy + ox];
                     g[4] = a.ev[base_i + oz];
                     g[5] = a.ev[base_i + oz + ox];
                     g[6] = a.ev[base_i + oz + oy];
                     g[7] = a.ev[base_i + oz + oy + ox];
+                }
+                float gmin = Num<float>::inf(), gmax = -Num<float>::inf();
 #pragma unroll
-                    for (int b = 0; b < 8; ++b) g[b] = (g[b] - dr) * inv_dd;
+                for (int b = 0; b < NV; ++b) {
+                    g[b] = dose_norm<float>(g[b], dr, inv_dd);
+                    gmin = vmin<float>(gmin, g[b]);
+                    gmax = __builtin_fmaxf(gmax, g[b]);
+                }
+                const float m = gmin > 0.0f ? gmin : (gmax < 0.0f ? -gmax : 0.0f);
+                // margin 2^-8 F: far above the rounding of the projections, so a skipped
+                // cell's projected value could not have been below F either, and F, the
+                // walk and the result are bit for bit those of the unpruned walk
+                need = e.key2 + m * m < F + F * 0x1p-8f;
+                // the guard still judges a skipped cell's tetrahedra (whether a node is
+                // redone in FP64 must not depend on the pruning)
+                if constexpr (GMODE == 1)
+                    if (!need && okx && oky && okz) ill = ill || tets_ill(g, is, a.den_guard);
+            }
+            // the whole projection only where some lane of the wave needs it
+            if (__ballot(need) != 0ull && need) {
+                const Geo<float> Gm = geo_from_row(e);
+                if constexpr (DIM == 3) {
                     if (wave_masked)
                         c = cell3<float, true, GMODE>(g, Gm, is, okx, oky, okz, a.den_guard, gc, dummy_fp64, ill);
                     else
                         c = cell3<float, false, GMODE>(g, Gm, is, true, true, true, a.den_guard, gc, dummy_fp64,
                                                        ill);
                 } else {
-                    float g[4];
-                    g[0] = a.ev[base_i];
-                    g[1] = a.ev[base_i + ox];
-                    g[2] = a.ev[base_i + oy];
-                    g[3] = a.ev[base_i + oy + ox];
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) g[b] = (g[b] - dr) * inv_dd;
                     if (wave_masked)
                         c = cell2<float, true>(g, Gm, is, okx, oky);
                     else
@@ -1042,7 +1091,7 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
 }
 
 template <int DIM, int MODE>
-__global__ __launch_bounds__(SEARCH_THREADS) void k_tail_group(SearchArgs a, const TabEntry* __restrict__ tab,
+__global__ __launch_bounds__(SEARCH_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_tail_group(SearchArgs a, const TabEntry* __restrict__ tab,
                                                                const uint32_t* __restrict__ order,
                                                                const uint32_t* __restrict__ count, int first,
                                                                int g_req, int spec, BlockSums* sums) {
