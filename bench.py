@@ -37,9 +37,9 @@ PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 # hash differs the traffic is reported as null.
 TRAFFIC = {
     "3d_128x128x96_2.5mm": {
-        "bytes": (15.61 + 2.25) * 1e6,
+        "bytes": (15.63 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "f6741f1b706a458491adf20956b63591560ddb31ece0eedebd3bebde338a6b7c",
+        "sha256": "1a10e562a2eab690be8079d06ea6cd3f655f2b0e6aaae48a7ac224881d84d37c",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }
