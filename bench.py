@@ -331,6 +331,8 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "guarded", "fp64"], default="guarded")
     ap.add_argument("--tail-lanes", type=int, default=0, choices=[0, 1, 8, 16, 32, 64])
     ap.add_argument("--cell-lanes", type=int, default=0, choices=[0, 1, 4, 8])
+    ap.add_argument("--projection", choices=["faces", "ju"], default="faces",
+                    help="key-0 pass: every owned face without branches, or Ju et al.'s recursion")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-radius leg")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1012_1900_amd", "weights",
@@ -389,7 +391,7 @@ def main():
         K synchronous maps (gammax_map: one host round trip each); then K maps with HIP
         events per phase."""
         kw = dict(sort=args.sort, precision=args.precision, tail_lanes=args.tail_lanes,
-                  cell_lanes=args.cell_lanes, out=out)
+                  cell_lanes=args.cell_lanes, projection=args.projection, out=out)
         kw.update(extra)
         for _ in range(args.warmup):
             gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, **kw)
@@ -516,6 +518,7 @@ def main():
             "n_evaluated": int(M),
             "sort": args.sort,
             "precision": args.precision,
+            "projection": args.projection,
             "cells_visited_oracle": cells,
             "n_tail": int(phases[-1].n_tail),
             "phases_ms": {k: round(mean(k), 4) for k in ("ms_prep", "ms_table", "ms_search", "ms_sort",

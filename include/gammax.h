@@ -117,7 +117,12 @@ typedef struct {
                                  training spacing), the network over the whole coarse grid and
                                  gamma_hat interpolated trilinearly at the tail nodes
                                  (see gammax_model_predict_nodes_pooled) */
-    int32_t reserved[2];      /* must be 0 */
+    int32_t projection;       /* point-to-simplex distance in the key-0 pass (3D): 0 = every face
+                                 a cell owns, without branches (Algorithm A2's Kernel 3, default);
+                                 1 = Ju et al.'s recursion (Algorithm A1 step 4-b-i): each
+                                 tetrahedron, then only the facets, edges and vertices its
+                                 negative weights point to.  Same gamma up to rounding. */
+    int32_t reserved[1];      /* must be 0 */
 } gammax_options_t;
 
 typedef struct {

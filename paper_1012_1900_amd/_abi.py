@@ -47,6 +47,7 @@ RADIUS_PLAIN, RADIUS_LEARNED = 0, 1
 _SORT = {"none": SORT_NONE, "dd": SORT_DD, "bound": SORT_BOUND, "predicted": SORT_PREDICTED}
 _RADIUS = {"plain": RADIUS_PLAIN, "learned": RADIUS_LEARNED}
 _PREC = {"fp32": PREC_FP32, "guarded": PREC_GUARDED, "fp64": PREC_FP64}
+_PROJ = {"faces": 0, "ju": 1}
 
 
 class GammaxError(RuntimeError):
@@ -81,7 +82,8 @@ class Options(C.Structure):
         ("radius_factor", C.c_double),
         ("autotune", C.c_int32),
         ("cnn_pool", C.c_int32),
-        ("reserved", C.c_int32 * 2),
+        ("projection", C.c_int32),
+        ("reserved", C.c_int32 * 1),
     ]
 
 
@@ -251,9 +253,10 @@ def make_problem(shape: Sequence[int], spacing: Sequence[float], dd: float, dta:
 
 def make_options(sort: str = "none", precision: str = "guarded", cond_threshold: float = 1e6,
                  timing: bool = False, tail_lanes: int = 0, cell_lanes: int = 0, radius: str = "plain",
-                 model=None, radius_factor: float = 1.1, cnn_pool: int = 0) -> Options:
+                 model=None, radius_factor: float = 1.1, cnn_pool: int = 0, projection: str = "faces") -> Options:
     o = default_options()
     o.cnn_pool = int(cnn_pool)
+    o.projection = _PROJ[projection]
     o.radius_mode = _RADIUS[radius]
     o.model = model.handle if model is not None else None
     o.radius_factor = float(radius_factor)
@@ -270,8 +273,8 @@ def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
                dose_threshold: float = 0.1, local: bool = False, *, sort: str = "none",
                precision: str = "guarded", cond_threshold: float = 1e6, timing: bool = False,
                tail_lanes: int = 0, cell_lanes: int = 0, radius: str = "plain", model=None,
-               radius_factor: float = 1.1, cnn_pool: int = 0, out=None, ctx: Optional[Context] = None,
-               stream=None):
+               radius_factor: float = 1.1, cnn_pool: int = 0, projection: str = "faces", out=None,
+               ctx: Optional[Context] = None, stream=None):
     """Gamma map of a dose pair on the GPU.  Returns (gamma tensor, GammaResult).
 
     ``ref``/``ev``: float32 device tensors of shape (ny, nx) or (nz, ny, nx); ``spacing``
@@ -294,7 +297,7 @@ def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
     ctx = ctx or context(dev)
     p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
     o = make_options(sort, precision, cond_threshold, timing, tail_lanes, cell_lanes, radius, model,
-                     radius_factor, cnn_pool)
+                     radius_factor, cnn_pool, projection)
     r = Result()
     s = stream if stream is not None else torch.cuda.current_stream(ref.device)
     with torch.cuda.device(ref.device):
@@ -326,7 +329,8 @@ def gammax_map_async(ref, ev, spacing: Sequence[float], dd: float, dta: float,
                      dose_threshold: float = 0.1, local: bool = False, *, sort: str = "none",
                      precision: str = "guarded", cond_threshold: float = 1e6, tail_lanes: int = 0,
                      cell_lanes: int = 0, radius: str = "plain", model=None, radius_factor: float = 1.1,
-                     cnn_pool: int = 0, out=None, ctx: Optional[Context] = None, stream=None) -> MapTicket:
+                     cnn_pool: int = 0, projection: str = "faces", out=None, ctx: Optional[Context] = None,
+                     stream=None) -> MapTicket:
     """Queue a gamma map without waiting (``gammax_map_async``); the returned ticket's
     ``wait()`` gives the GammaResult.  The tensors are kept alive until then and must not
     be modified before it."""
@@ -347,7 +351,7 @@ def gammax_map_async(ref, ev, spacing: Sequence[float], dd: float, dta: float,
     ctx = ctx or context(dev)
     p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
     o = make_options(sort, precision, cond_threshold, False, tail_lanes, cell_lanes, radius, model,
-                     radius_factor, cnn_pool)
+                     radius_factor, cnn_pool, projection)
     t = C.c_uint64(0)
     s = stream if stream is not None else torch.cuda.current_stream(ref.device)
     with torch.cuda.device(ref.device):

@@ -41,6 +41,7 @@ struct GraphKey {
     int32_t small_sort;
     int32_t tail_min_lanes;
     int32_t cnn_pool;
+    int32_t projection;
     uint64_t generation;   // bumped on every (re)allocation and table build
 };
 
@@ -274,7 +275,8 @@ gammax_status_t check_options(gammax_ctx* c, const gammax_options_t* o) {
         return fail(c, GAMMAX_E_PARAM, "cell_lanes must be 0, 1, 4 or 8");
     if (o->autotune != 0 && o->autotune != 1) return fail(c, GAMMAX_E_PARAM, "autotune must be 0 or 1");
     if (o->cnn_pool != 0 && o->cnn_pool != 2) return fail(c, GAMMAX_E_PARAM, "cnn_pool must be 0 or 2");
-    for (int i = 0; i < 2; ++i)
+    if (o->projection != 0 && o->projection != 1) return fail(c, GAMMAX_E_PARAM, "projection must be 0 or 1");
+    for (int i = 0; i < 1; ++i)
         if (o->reserved[i] != 0) return fail(c, GAMMAX_E_PARAM, "reserved option fields must be 0");
     if (o->model && c && o->model->device != c->device)
         return fail(c, GAMMAX_E_PARAM, "model and context live on different devices");
@@ -630,6 +632,7 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
     plan.tail_min_lanes = tail_min_lanes(c);
     // one lane per node (shared neighbourhood loads) unless one lane per cell is asked for
     plan.zero_lanes = (opt.cell_lanes == 4 || opt.cell_lanes == 8) ? 1 : 0;
+    plan.projection = opt.projection;
     plan.spec = (learned && opt.radius_mode == GAMMAX_RADIUS_LEARNED) ? 1 : 0;
     plan.M = m_bound;
     plan.zero = make_zero_geo(p);
@@ -695,6 +698,7 @@ GraphKey key_of(gammax_ctx* c, const CallSetup& cs) {
     k.small_sort = (cs.opt->sort_mode != GAMMAX_SORT_NONE && c->tail_hint <= (uint64_t)SMALL_SORT_CAP) ? 1 : 0;
     k.tail_min_lanes = tail_min_lanes(c);
     k.cnn_pool = cs.opt->cnn_pool;
+    k.projection = cs.opt->projection;
     k.generation = c->generation;
     return k;
 }

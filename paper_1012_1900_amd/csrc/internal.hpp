@@ -204,6 +204,7 @@ struct SearchPlan {
     int tail_lanes;          // lanes per node in the tail walk: 1 (one lane per node) or 8..64
     int tail_min_lanes;      // automatic tail lanes (tail_lanes 0): at least this many (0: 8)
     int zero_lanes;          // pass A: 1 = one lane per cell, 0 = one lane per node
+    int projection;          // pass A in 3D: 0 = all faces a cell owns, 1 = Ju's recursion
     int spec;                // 1: speculative tail walk inside spec_factor * gamma_hat, then the
                              //    plain walk for the nodes it could not certify
     // optional: queued after the key-0 pass, before the tail sort (the network at the tail

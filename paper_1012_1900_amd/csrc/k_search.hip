@@ -334,6 +334,155 @@ __device__ __forceinline__ T cell3(const T* g, const Geo<T>& G, const InvS2<T>& 
     return best;
 }
 
+// ---- Ju et al.'s recursion (Sec. 2.1: the branching form of the A1 distance) -------------
+//
+// The same closed-form chain projections as cell3, organised as the recursion of the
+// sequential algorithm: each of the six Kuhn tetrahedra of a cell is projected first, and
+// only where a barycentric weight is negative are the facets opposite those vertices
+// projected, then their edges, then vertices.  It covers every face of the cell (not only
+// the faces the cell owns), so it serves interior cells; cells at the grid faces keep
+// cell3.  A chain starts at cube vertex U (bit i: +1 along axis i, x = bit 0) and steps
+// through disjoint axis blocks S1, S2, ... that do not meet U.
+struct JuCell {
+    float g[8];
+    float a[3], p[3], p1[3];   // per axis: offset, s^2 a^2, s^2 (a + 1)^2
+    Geo<float> G;
+    InvS2<float> is;
+};
+template <int S>
+__device__ __forceinline__ float ju_mu(const JuCell& K) {
+    static_assert(S >= 1 && S <= 7, "block");
+    if constexpr (S == 1) return K.a[0];
+    else if constexpr (S == 2) return K.a[1];
+    else if constexpr (S == 4) return K.a[2];
+    else if constexpr (S == 3) return K.G.mxy;
+    else if constexpr (S == 5) return K.G.mxz;
+    else if constexpr (S == 6) return K.G.myz;
+    else return K.G.mxyz;
+}
+template <int S>
+__device__ __forceinline__ float ju_inv(const JuCell& K) {
+    if constexpr (S == 1) return K.is.x;
+    else if constexpr (S == 2) return K.is.y;
+    else if constexpr (S == 4) return K.is.z;
+    else if constexpr (S == 3) return K.is.xy;
+    else if constexpr (S == 5) return K.is.xz;
+    else if constexpr (S == 6) return K.is.yz;
+    else return K.is.xyz;
+}
+template <int S>
+__device__ __forceinline__ float ju_res(const JuCell& K) {
+    if constexpr (S == 1 || S == 2 || S == 4) return 0.0f;
+    else if constexpr (S == 3) return K.G.vxy;
+    else if constexpr (S == 5) return K.G.vxz;
+    else if constexpr (S == 6) return K.G.vyz;
+    else return K.G.vxyz;
+}
+// sum of the squared spatial components of vertex U over the axes outside mask S
+template <int U, int S>
+__device__ __forceinline__ float ju_perp(const JuCell& K) {
+    float r = 0.0f;
+    if constexpr (!(S & 1)) r += (U & 1) ? K.p1[0] : K.p[0];
+    if constexpr (!(S & 2)) r += (U & 2) ? K.p1[1] : K.p[1];
+    if constexpr (!(S & 4)) r += (U & 4) ? K.p1[2] : K.p[2];
+    return r;
+}
+template <int U>
+__device__ __forceinline__ float ju_vertex(const JuCell& K) {
+    return ju_perp<U, 0>(K) + K.g[U] * K.g[U];
+}
+template <int U, int S>
+__device__ __forceinline__ Step<float> ju_step(const JuCell& K) {
+    static_assert((U & S) == 0, "a chain steps away from its start");
+    return mk_step(K.g[U | S], K.g[U], ju_mu<S>(K), ju_inv<S>(K));
+}
+// edge from U along block S
+template <int U, int S>
+__device__ __forceinline__ float ju_edge(const JuCell& K) {
+    const Step<float> a = ju_step<U, S>(K);
+    const float N = K.g[U] - a.m;
+    const float L = N * Num<float>::rcp(1.0f + a.p);
+    const float t = -ju_mu<S>(K) - a.w * L;
+    if (t >= 0.0f && t <= 1.0f) return ju_perp<U, S>(K) + ju_res<S>(K) + N * L;
+    return t < 0.0f ? ju_vertex<U>(K) : ju_vertex<U | S>(K);
+}
+// triangle from U through blocks S1 then S2
+template <int U, int S1, int S2>
+__device__ __forceinline__ float ju_tri(const JuCell& K) {
+    const Step<float> a = ju_step<U, S1>(K);
+    const Step<float> b = ju_step<U | S1, S2>(K);
+    const float N = (K.g[U] - a.m) - b.m;
+    const float L = N * Num<float>::rcp((1.0f + a.p) + b.p);
+    const float t1 = -ju_mu<S1>(K) - a.w * L;
+    const float t2 = -ju_mu<S2>(K) - b.w * L;
+    const float w0 = 1.0f - t1, w1 = t1 - t2, w2 = t2;
+    if (w0 >= 0.0f && w1 >= 0.0f && w2 >= 0.0f)
+        return ju_perp<U, S1 | S2>(K) + ju_res<S1>(K) + ju_res<S2>(K) + N * L;
+    float best = Num<float>::inf();
+    if (w0 < 0.0f) best = vmin<float>(best, ju_edge<U | S1, S2>(K));
+    if (w1 < 0.0f) best = vmin<float>(best, ju_edge<U, S1 | S2>(K));
+    if (w2 < 0.0f) best = vmin<float>(best, ju_edge<U, S1>(K));
+    return best;
+}
+// tetrahedron v0 -> A -> A+B -> A+B+C (axis masks A, B, C); den: its normal-equation
+// denominator (the guard's measure)
+template <int A, int B, int C>
+__device__ __forceinline__ float ju_tet(const JuCell& K, float& den) {
+    const Step<float> a = ju_step<0, A>(K);
+    const Step<float> b = ju_step<A, B>(K);
+    const Step<float> c = ju_step<A | B, C>(K);
+    const float N = ((K.g[0] - a.m) - b.m) - c.m;
+    den = ((1.0f + a.p) + b.p) + c.p;
+    const float L = N * Num<float>::rcp(den);
+    const float t1 = -ju_mu<A>(K) - a.w * L;
+    const float t2 = -ju_mu<B>(K) - b.w * L;
+    const float t3 = -ju_mu<C>(K) - c.w * L;
+    const float w0 = 1.0f - t1, w1 = t1 - t2, w2 = t2 - t3, w3 = t3;
+    if (w0 >= 0.0f && w1 >= 0.0f && w2 >= 0.0f && w3 >= 0.0f) return N * L;
+    float best = Num<float>::inf();
+    if (w0 < 0.0f) best = vmin<float>(best, ju_tri<A, B, C>(K));          // drop v0
+    if (w1 < 0.0f) best = vmin<float>(best, ju_tri<0, A | B, C>(K));      // drop v0+A
+    if (w2 < 0.0f) best = vmin<float>(best, ju_tri<0, A, B | C>(K));      // drop v0+A+B
+    if (w3 < 0.0f) best = vmin<float>(best, ju_tri<0, A, B>(K));          // drop v0+A+B+C
+    return best;
+}
+// Interior 3D cell by Ju's recursion: the smallest dist^2 over its six tetrahedra.
+// GMODE 1 flags a tetrahedron whose denominator exceeds den_guard (as cell3 does).
+template <int GMODE>
+__device__ __forceinline__ float cell3_ju(const float* g, const Geo<float>& G, const InvS2<float>& is, float s2x,
+                                          float s2y, float s2z, float den_guard, bool& ill) {
+    JuCell K;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) K.g[b] = g[b];
+    K.a[0] = G.ax;
+    K.a[1] = G.ay;
+    K.a[2] = G.az;
+    K.p[0] = G.px;
+    K.p[1] = G.py;
+    K.p[2] = G.pz;
+    K.p1[0] = s2x * (G.ax + 1.0f) * (G.ax + 1.0f);
+    K.p1[1] = s2y * (G.ay + 1.0f) * (G.ay + 1.0f);
+    K.p1[2] = s2z * (G.az + 1.0f) * (G.az + 1.0f);
+    K.G = G;
+    K.is = is;
+    float den = 0.0f;
+    bool flag = false;
+    float best = ju_tet<1, 2, 4>(K, den);
+    flag = flag || den > den_guard;
+    best = vmin<float>(best, ju_tet<1, 4, 2>(K, den));
+    flag = flag || den > den_guard;
+    best = vmin<float>(best, ju_tet<2, 1, 4>(K, den));
+    flag = flag || den > den_guard;
+    best = vmin<float>(best, ju_tet<2, 4, 1>(K, den));
+    flag = flag || den > den_guard;
+    best = vmin<float>(best, ju_tet<4, 1, 2>(K, den));
+    flag = flag || den > den_guard;
+    best = vmin<float>(best, ju_tet<4, 2, 1>(K, den));
+    flag = flag || den > den_guard;
+    if constexpr (GMODE == 1) ill = ill || flag;
+    return best;
+}
+
 template <typename T, bool MASKED>
 __device__ __forceinline__ T cell2(const T* g, const Geo<T>& G, const InvS2<T>& is, bool okx, bool oky) {
     const T INF = Num<T>::inf();
@@ -486,7 +635,7 @@ __device__ __forceinline__ int resume_row(const TabEntry* tab, int n, int first,
 
 // Pass A in 3D.  MODE 0: FP32; MODE 1: FP32 and flag ill-conditioned tetrahedra.
 // vb: the block's index in the node list (256 nodes each).
-template <int MODE>
+template <int MODE, bool JU = false>
 __device__ __forceinline__ void zero3_body(const SearchArgs& a, const ZeroGeo& zg, BlockSums* sums, uint32_t vb) {
     constexpr int GMODE = MODE == 1 ? 1 : 0;
     const uint32_t M = a.sc->n_masked;
@@ -537,7 +686,10 @@ __device__ __forceinline__ void zero3_body(const SearchArgs& a, const ZeroGeo& z
             v = exists ? v : Num<float>::inf();
             cells += (F > 0.0f && exists && okx && oky && okz) ? 1u : 0u;
         } else {
-            v = cell3<float, false, GMODE>(g, G, is, true, true, true, a.den_guard, gc, n_fp64, ill);
+            if constexpr (JU)
+                v = cell3_ju<GMODE>(g, G, is, a.s2x, a.s2y, a.s2z, a.den_guard, ill);
+            else
+                v = cell3<float, false, GMODE>(g, G, is, true, true, true, a.den_guard, gc, n_fp64, ill);
             cells += F > 0.0f ? 1u : 0u;
         }
         F = F0 > 0.0f ? vmin<float>(F, v) : F;
@@ -565,9 +717,9 @@ __device__ __forceinline__ void zero3_body(const SearchArgs& a, const ZeroGeo& z
     block_sums(sums, vb, npass, nborder, 0u, ncells, gm);
 }
 
-template <int MODE>
+template <int MODE, bool JU = false>
 __global__ __launch_bounds__(SEARCH_THREADS) void k_zero3(SearchArgs a, ZeroGeo zg, BlockSums* sums) {
-    zero3_body<MODE>(a, zg, sums, blockIdx.x);
+    zero3_body<MODE, JU>(a, zg, sums, blockIdx.x);
 }
 
 // Pass A in 2D (4 zero-key cells, 3x3 neighbourhood).
@@ -1378,6 +1530,10 @@ hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s
             } else {
                 hipLaunchKernelGGL((k_zero_group<2, 0>), dim3(zb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
             }
+        } else if (p.ndim == 3 && p.projection == 1) {
+            // Ju's recursion in the key-0 pass (interior cells)
+            if (guarded) hipLaunchKernelGGL((k_zero3<1, true>), dim3(nb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
+            else hipLaunchKernelGGL((k_zero3<0, true>), dim3(nb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
         } else if (p.ndim == 3) {
             if (guarded) hipLaunchKernelGGL(k_zero3<1>, dim3(nb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);
             else hipLaunchKernelGGL(k_zero3<0>, dim3(nb), dim3(SEARCH_THREADS), 0, s, a, p.zero, sums);

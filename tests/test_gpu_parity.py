@@ -55,6 +55,21 @@ def test_anisotropic_3d(gx):
         assert_parity(host(g), o.gamma, f"aniso {crit}")
 
 
+@pytest.mark.parametrize("precision", ["fp32", "guarded"])
+@pytest.mark.parametrize("local", [False, True])
+def test_ju_recursion_projection(gx, small3d, precision, local):
+    """Ju et al.'s recursion in the key-0 pass (projection="ju"): the oracle's gamma within
+    the bar, on isotropic and anisotropic grids, with the pass decisions of the default."""
+    for p, crit in ((small3d, (0.02, 2.0)), (make_pair_3d(8, shape=(23, 31, 29), spacing=(3.0, 2.0, 1.5)), (0.03, 3.0))):
+        o = oracle.gamma(p.ref, p.eval, p.spacing, crit[0], crit[1], 0.1, local)
+        g, r = gx.gammax_map(dev(p.ref), dev(p.eval), p.spacing, crit[0], crit[1], 0.1, local, precision=precision,
+                             projection="ju")
+        assert_parity(host(g), o.gamma, f"ju {crit} local={local} {precision}")
+        g0, r0 = gx.gammax_map(dev(p.ref), dev(p.eval), p.spacing, crit[0], crit[1], 0.1, local, precision=precision)
+        assert r.n_evaluated == r0.n_evaluated
+        assert abs(int(r.n_pass) - int(r0.n_pass)) <= r.n_borderline + r0.n_borderline
+
+
 @pytest.mark.parametrize("precision", ["fp32", "guarded", "fp64"])
 def test_precision_modes(gx, small3d, precision):
     p = small3d
