@@ -9,4 +9,4 @@ GPU library.
 * :mod:`oracle.bruteforce` - an independent exhaustive check (every face of every
   simplex, no pruning, Householder QR) for tiny grids.
 """
-from .core import OracleResult, gamma, simplex_dist, build, max_threads  # noqa: F401
+from .core import OracleResult, gamma, gamma_grids, simplex_dist, build, max_threads  # noqa: F401

@@ -64,6 +64,9 @@ def _load():
         lib.oracle_gamma.restype = C.c_int
         lib.oracle_gamma.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(_Stats), C.c_int]
+        lib.oracle_gamma_grids.restype = C.c_int
+        lib.oracle_gamma_grids.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p, C.POINTER(_Stats), C.c_int]
         lib.oracle_simplex_dist.restype = C.c_double
         lib.oracle_simplex_dist.argtypes = [C.c_int, C.c_int, C.c_void_p]
         lib.oracle_max_threads.restype = C.c_int
@@ -133,6 +136,39 @@ def gamma(ref: np.ndarray, ev: np.ndarray, spacing: Sequence[float], dd: float, 
         cells = cells.reshape(ref64.shape)
     return OracleResult(out, cells, st.n_evaluated, st.n_pass, st.n_borderline, st.cells_visited,
                         st.cells_key0, st.table_len, st.n_masked, st.dose_max, st.threshold, st.radius)
+
+
+def gamma_grids(ref: np.ndarray, ev: np.ndarray, ref_spacing: Sequence[float], ev_spacing: Sequence[float],
+                ev_origin: Sequence[float], dd: float, dta: float, threshold: float = 0.1, local: bool = False,
+                nthreads: int = 0) -> OracleResult:
+    """Gamma index with the evaluation dose on a grid of its own: ``ev`` sampled at
+    ``ev_origin + j * ev_spacing`` (mm, slowest axis first), the reference node k at
+    ``k * ref_spacing``.  Reference nodes outside the evaluation grid's box get -1.  Only
+    gamma and the counts are filled (cells, table and radius are 0)."""
+    ref64 = np.ascontiguousarray(ref, dtype=np.float64)
+    ev64 = np.ascontiguousarray(ev, dtype=np.float64)
+    nd = ref64.ndim
+    if nd not in (2, 3) or ev64.ndim != nd:
+        raise ValueError("ref and eval must both be 2D or both 3D")
+    pb = _Problem()
+    pb.ndim = nd
+    pb.local = 1 if local else 0
+    for i in range(3):
+        pb.shape[i] = ref64.shape[i] if i < nd else 1
+        pb.spacing[i] = float(ref_spacing[i]) if i < nd else 1.0
+    pb.dd, pb.dta, pb.thr = float(dd), float(dta), float(threshold)
+    es = np.array([ev64.shape[i] if i < nd else 1 for i in range(3)], dtype=np.int64)
+    eh = np.array([float(ev_spacing[i]) if i < nd else 1.0 for i in range(3)])
+    eo = np.array([float(ev_origin[i]) if i < nd else 0.0 for i in range(3)])
+    out = np.empty(ref64.size, dtype=np.float64)
+    st = _Stats()
+    rc = _load().oracle_gamma_grids(C.byref(pb), es.ctypes.data, eh.ctypes.data, eo.ctypes.data,
+                                    ref64.ctypes.data, ev64.ctypes.data, out.ctypes.data, C.byref(st),
+                                    int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the problem (code {rc})")
+    return OracleResult(out.reshape(ref64.shape), np.zeros(ref64.shape, dtype=np.int32), st.n_evaluated,
+                        st.n_pass, st.n_borderline, 0, 0, 0, st.n_masked, st.dose_max, st.threshold, 0.0)
 
 
 def simplex_dist(verts: np.ndarray) -> float:

@@ -412,6 +412,179 @@ int oracle_gamma(const oracle_problem_t *pb, const double *ref, const double *ev
     return ORACLE_OK;
 }
 
+/* ---------------------------------------------------------------------------------- */
+/* Two grids: the evaluation dose on a grid of its own (axis-aligned; its own shape,     */
+/* spacing and origin).  Not in the paper; the same definition, Eq. (1), with the        */
+/* surface built over the evaluation grid and the reference point at its own position.   */
+/* ---------------------------------------------------------------------------------- */
+
+/* Readings: a reference node is evaluated when it is masked (as above, on the reference
+ * grid) and lies inside the closed box of the evaluation grid; others get -1.  The search
+ * is a plain scan: the first bound is the nearest of the 2^d vertices of the evaluation
+ * cell that holds the node, and every cell whose exact key (minimum distance from the
+ * node to the closed cell, over DTA) is below that bound has all its simplices evaluated.
+ * No table, no early break, no ordering: obviously complete. */
+static double search_node_grids(int nd, const int64_t *ne, const double *he, const double *u,
+                                double dta, const double *ev, double Dr, double dD, int64_t *n_proj)
+{
+    int64_t c0[3];
+    for (int i = 0; i < nd; ++i) {
+        c0[i] = (int64_t)floor(u[i]);
+        if (c0[i] > ne[i] - 2) c0[i] = ne[i] - 2;
+        if (c0[i] < 0) c0[i] = 0;
+    }
+    /* first bound: nearest vertex of the holding cell */
+    double F = INFINITY;
+    for (int b = 0; b < (1 << nd); ++b) {
+        int64_t lin = 0;
+        double d2 = 0.0;
+        for (int i = 0; i < nd; ++i) {
+            int bit = (b >> (nd - 1 - i)) & 1;
+            int64_t c = c0[i] + bit;
+            lin = lin * ne[i] + c;
+            double x = ((double)c - u[i]) * he[i] / dta;
+            d2 += x * x;
+        }
+        double g = (ev[lin] - Dr) / dD;
+        d2 += g * g;
+        if (d2 < F) F = d2;
+    }
+    /* every cell with key^2 < F */
+    int64_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    const double rad = sqrt(F);
+    for (int i = 0; i < nd; ++i) {
+        int64_t k = (int64_t)ceil(rad * dta / he[i]) + 1;
+        lo[i] = (int64_t)floor(u[i]) - k - 1;
+        hi[i] = (int64_t)floor(u[i]) + k + 1;
+        if (lo[i] < 0) lo[i] = 0;
+        if (hi[i] > ne[i] - 2) hi[i] = ne[i] - 2;
+    }
+    const double F0 = F;
+    int64_t c[3] = {lo[0], lo[1], lo[2]};
+    for (;;) {
+        double key2 = 0.0;
+        for (int i = 0; i < nd; ++i) {
+            double m = 0.0;
+            if ((double)c[i] > u[i]) m = (double)c[i] - u[i];
+            else if (u[i] > (double)c[i] + 1.0) m = u[i] - (double)c[i] - 1.0;
+            double x = m * he[i] / dta;
+            key2 += x * x;
+        }
+        if (key2 < F0) {
+            double corner[8][AMB];
+            for (int b = 0; b < (1 << nd); ++b) {
+                int64_t lin = 0;
+                for (int i = 0; i < nd; ++i) {
+                    int bit = (b >> (nd - 1 - i)) & 1;
+                    int64_t cc = c[i] + bit;
+                    lin = lin * ne[i] + cc;
+                    corner[b][i] = ((double)cc - u[i]) * he[i] / dta;
+                }
+                corner[b][nd] = (ev[lin] - Dr) / dD;
+            }
+            if (nd == 3) {
+                for (int p = 0; p < 6; ++p) {
+                    double v[4][AMB];
+                    int b = 0;
+                    memcpy(v[0], corner[0], sizeof(double) * AMB);
+                    for (int s = 0; s < 3; ++s) {
+                        b |= 1 << (2 - PERM3[p][s]);
+                        memcpy(v[s + 1], corner[b], sizeof(double) * AMB);
+                    }
+                    double d2 = simplex_d2(4, 3, (const double(*)[AMB])v, n_proj);
+                    if (d2 < F) F = d2;
+                }
+            } else {
+                for (int p = 0; p < 2; ++p) {
+                    double v[3][AMB];
+                    int b = 0;
+                    memcpy(v[0], corner[0], sizeof(double) * AMB);
+                    for (int s = 0; s < 2; ++s) {
+                        b |= 1 << (1 - PERM2[p][s]);
+                        memcpy(v[s + 1], corner[b], sizeof(double) * AMB);
+                    }
+                    double d2 = simplex_d2(3, 2, (const double(*)[AMB])v, n_proj);
+                    if (d2 < F) F = d2;
+                }
+            }
+        }
+        int i = nd - 1;
+        while (i >= 0) {
+            if (++c[i] <= hi[i]) break;
+            c[i] = lo[i];
+            --i;
+        }
+        if (i < 0) break;
+    }
+    return sqrt(F);
+}
+
+/*
+ * gamma of every reference node of pb (its shape and spacing describe the reference grid;
+ * the node k sits at k * spacing) against an evaluation dose on the grid ev_shape x
+ * ev_spacing whose node 0 sits at ev_origin (mm, same axis order).  gamma_out: N_ref
+ * entries, -1 where a node is not evaluated.  st (optional): n_evaluated, n_pass,
+ * n_borderline, n_masked, dose_max, threshold.
+ */
+int oracle_gamma_grids(const oracle_problem_t *pb, const int64_t *ev_shape, const double *ev_spacing,
+                       const double *ev_origin, const double *ref, const double *ev, double *gamma_out,
+                       oracle_stats_t *st, int nthreads)
+{
+    if (!problem_ok(pb) || !ev_shape || !ev_spacing || !ev_origin || !ref || !ev || !gamma_out)
+        return ORACLE_E_PARAM;
+    const int nd = pb->ndim;
+    int64_t N = 1;
+    for (int i = 0; i < nd; ++i) {
+        N *= pb->shape[i];
+        if (ev_shape[i] < 2 || !(ev_spacing[i] > 0.0) || !isfinite(ev_origin[i])) return ORACLE_E_PARAM;
+    }
+    double dmax = -INFINITY;
+    for (int64_t i = 0; i < N; ++i) if (ref[i] > dmax) dmax = ref[i];
+    const float thr32 = (float)pb->thr;
+    const double t = (double)(float)((double)thr32 * (double)(float)dmax);
+    if (!pb->local && !(dmax > 0.0)) return ORACLE_E_PARAM;
+    const double dD_global = pb->dd * dmax;
+    int64_t n_eval = 0, n_pass = 0, n_border = 0, n_masked = 0, n_proj = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_eval, n_pass, n_border, n_masked, n_proj)
+    for (int64_t r = 0; r < N; ++r) {
+        double gout = -1.0;
+        if (ref[r] >= t && !(pb->local && !(ref[r] > 0.0))) {
+            ++n_masked;
+            int64_t rc[3] = {0, 0, 0};
+            int64_t rem = r;
+            for (int i = nd - 1; i >= 0; --i) { rc[i] = rem % pb->shape[i]; rem /= pb->shape[i]; }
+            double u[3] = {0.0, 0.0, 0.0};
+            int inside = 1;
+            for (int i = 0; i < nd; ++i) {
+                u[i] = ((double)rc[i] * pb->spacing[i] - ev_origin[i]) / ev_spacing[i];
+                if (!(u[i] >= 0.0) || !(u[i] <= (double)(ev_shape[i] - 1))) inside = 0;
+            }
+            if (inside) {
+                double dD = pb->local ? pb->dd * ref[r] : dD_global;
+                gout = search_node_grids(nd, ev_shape, ev_spacing, u, pb->dta, ev, ref[r], dD, &n_proj);
+                ++n_eval;
+                if (gout <= 1.0) ++n_pass;
+                if (fabs(gout - 1.0) <= 1e-5) ++n_border;
+            }
+        }
+        gamma_out[r] = gout;
+    }
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->n_evaluated = n_eval;
+        st->n_pass = n_pass;
+        st->n_borderline = n_border;
+        st->n_masked = n_masked;
+        st->dose_max = dmax;
+        st->threshold = t;
+    }
+    (void)n_proj;
+    return ORACLE_OK;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP
