@@ -206,6 +206,36 @@ def run_sweep(args):
         ac, bc, r2c = _fit_line(s3, [p["n_cells"] for p in pts])
         summary = dict(sweep="shift", ms_gamma_vs_sum_gamma3=dict(slope=a, intercept_ms=round(b, 4), r2=round(r2, 4)),
                        cells_vs_sum_gamma3=dict(slope=ac, intercept=round(bc, 1), r2=round(r2c, 4)))
+    elif kind == "grids":
+        # the 128x128x96 pair against evaluation doses on other grids over the same box
+        cfg, seed, _ = WORKLOADS["3d_128x128x96_2.5mm"]
+        pair = make_config_pair(cfg, seed)
+        ref = torch.from_numpy(pair.ref).to(dev)
+        rs = pair.ref.shape
+        for ev_sp, shift in (((2.5, 2.5, 2.5), (0.0, 0.0, 0.0)), ((2.5, 2.5, 2.5), (1.25, 1.25, 1.25)),
+                             ((1.25, 1.25, 1.25), (0.0, 0.0, 0.0)), ((5.0, 5.0, 5.0), (0.0, 0.0, 0.0))):
+            es = tuple(max(2, int(round(n * h / e))) for n, h, e in zip(rs, pair.spacing, ev_sp))
+            pe = make_pair_3d(seed, shape=es, spacing=ev_sp)
+            origin = tuple((n - 1) / 2 * h - (m - 1) / 2 * e + d
+                           for n, h, m, e, d in zip(rs, pair.spacing, es, ev_sp, shift))
+            ev = torch.from_numpy(pe.eval).to(dev)
+            out = torch.empty_like(ref)
+            for _ in range(args.warmup):
+                gx.gammax_map_grids(ref, ev, pair.spacing, ev_sp, origin, args.dd, args.dta, 0.1, out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, r = gx.gammax_map_grids(ref, ev, pair.spacing, ev_sp, origin, args.dd, args.dta, 0.1, out=out)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / args.steps
+            pt = dict(ev_spacing_mm=list(ev_sp), ev_shape=list(es), shift_mm=list(shift), ms_per_map=round(ms, 4),
+                      ref_vox_per_s=round(r.n_evaluated / (ms * 1e-3), 1), n_evaluated=int(r.n_evaluated),
+                      n_cells=int(r.n_cells), table_len=int(r.table_len), pass_rate=round(r.pass_rate, 6),
+                      max_gamma=round(r.max_gamma, 4))
+            print(json.dumps(pt), flush=True)
+            pts.append(pt)
+            del ev, out
+        summary = dict(sweep="grids", ms_per_map=[p["ms_per_map"] for p in pts])
     else:
         raise SystemExit(f"unknown sweep {kind}")
     print(json.dumps(summary), flush=True)
@@ -338,7 +368,7 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1012_1900_amd", "weights",
                                                       "cnn_3d_2.5mm_3pct3mm.npy"))
     ap.add_argument("--cpu-reps", type=int, default=2)
-    ap.add_argument("--sweep", choices=["criteria", "resolution", "shift"], default=None,
+    ap.add_argument("--sweep", choices=["criteria", "resolution", "shift", "grids"], default=None,
                     help="run one of the paper's scaling studies instead of the benchmark line")
     ap.add_argument("--streams", type=int, default=4,
                     help="mixed batch: spread the pairs round-robin over this many streams (the GPU "

@@ -230,6 +230,32 @@ gammax_status_t gammax_map_many(gammax_ctx_t *ctx, int32_t n, const gammax_probl
                                 float *const *gammas_dev, const gammax_options_t *opt,
                                 gammax_result_t *results, void *stream);
 
+/* An evaluation grid of its own (axis-aligned): shape and spacing slowest axis first, and the
+ * position of its node 0 in the reference grid's frame (reference node k sits at
+ * k * spacing_mm), in mm. */
+typedef struct {
+    int64_t shape[3];
+    double spacing_mm[3];
+    double origin_mm[3];
+} gammax_grid_t;
+
+/*
+ * Gamma map with the evaluation dose on a grid of its own (not in the paper, which compares
+ * doses on one grid; Eq. (1) unchanged, with the evaluation surface built over eval_grid).
+ * 3D only.  problem: the reference grid and the criteria; eval_dev: prod(eval_grid->shape)
+ * floats.  A masked reference node inside the evaluation grid's closed box is evaluated;
+ * the others get gamma = -1.  Each node walks a table of evaluation cells sorted by a key
+ * that bounds the distance from below for any node position inside its holding cell, from
+ * the nearest vertex of that cell.  Options: precision (FP32, guarded, FP64), tail_lanes
+ * (0 = 16, or 8, 16, 32, 64 lanes per node), cond_threshold; the plain radius and no sort
+ * only (others: GAMMAX_E_PARAM).  Result: counts, max gamma, dose max, search radius (the
+ * largest first bound) and table length.  Synchronises `stream`.
+ */
+gammax_status_t gammax_map_grids(gammax_ctx_t *ctx, const gammax_problem_t *problem,
+                                 const gammax_grid_t *eval_grid, const float *ref_dev,
+                                 const float *eval_dev, float *gamma_dev, const gammax_options_t *opt,
+                                 gammax_result_t *result, void *stream);
+
 /*
  * The problem statement as a flat call (Sec. 2.1): gamma and pass rate of one dose pair
  * with the default options on a library-owned context for the current device.

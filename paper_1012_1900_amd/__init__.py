@@ -19,6 +19,7 @@ from ._abi import (  # noqa: F401
     gammax_map,
     gammax_map_async,
     gammax_map_many,
+    gammax_map_grids,
     MapTicket,
     ASYNC_SLOTS,
     pass_count,

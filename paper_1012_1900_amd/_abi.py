@@ -668,6 +668,48 @@ def gammax_batch(pairs, *, precision: str = "guarded", cond_threshold: float = 1
     return out_list, results
 
 
+class Grid(C.Structure):
+    _fields_ = [("shape", C.c_int64 * 3), ("spacing_mm", C.c_double * 3), ("origin_mm", C.c_double * 3)]
+
+
+_lib.gammax_map_grids.restype = C.c_int
+_lib.gammax_map_grids.argtypes = [_vp, C.POINTER(Problem), C.POINTER(Grid), _vp, _vp, _vp, C.POINTER(Options),
+                                  C.POINTER(Result), _vp]
+
+
+def gammax_map_grids(ref, ev, ref_spacing: Sequence[float], ev_spacing: Sequence[float],
+                     ev_origin: Sequence[float], dd: float, dta: float, dose_threshold: float = 0.1,
+                     local: bool = False, *, precision: str = "guarded", cond_threshold: float = 1e6,
+                     tail_lanes: int = 0, out=None, ctx: Optional[Context] = None, stream=None):
+    """Gamma map with the evaluation dose on a grid of its own (``gammax_map_grids``, 3D):
+    ``ev`` (float32 device tensor) sampled at ``ev_origin + j * ev_spacing`` mm in the frame
+    where reference node k sits at ``k * ref_spacing``.  Returns (gamma on the reference
+    grid, GammaResult); gamma is -1 where a node is not evaluated."""
+    torch = _torch()
+    _dev_tensor(ref, "ref")
+    _dev_tensor(ev, "ev")
+    if ref.dim() != 3 or ev.dim() != 3 or ref.device != ev.device:
+        raise ValueError("ref and ev must be 3D tensors on one device")
+    if out is None:
+        out = torch.empty_like(ref)
+    dev = ref.device.index if ref.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or context(dev)
+    p = make_problem(tuple(ref.shape), ref_spacing, dd, dta, dose_threshold, local)
+    g = Grid()
+    for i in range(3):
+        g.shape[i] = int(ev.shape[i])
+        g.spacing_mm[i] = float(ev_spacing[i])
+        g.origin_mm[i] = float(ev_origin[i])
+    o = make_options("none", precision, cond_threshold, False, tail_lanes, 0)
+    r = Result()
+    s = stream if stream is not None else torch.cuda.current_stream(ref.device)
+    with torch.cuda.device(ref.device):
+        st = _lib.gammax_map_grids(ctx.handle, C.byref(p), C.byref(g), ref.data_ptr(), ev.data_ptr(), out.data_ptr(),
+                                   C.byref(o), C.byref(r), _vp(s.cuda_stream))
+    ctx.check(st)
+    return out, GammaResult(**{f[0]: getattr(r, f[0]) for f in Result._fields_})
+
+
 _lib.gammax_map_many.restype = C.c_int
 _lib.gammax_map_many.argtypes = [_vp, C.c_int32, C.POINTER(Problem), C.POINTER(_vp), C.POINTER(_vp),
                                  C.POINTER(_vp), C.POINTER(Options), C.POINTER(Result), _vp]

@@ -112,6 +112,14 @@ struct gammax_ctx {
     int64_t yhat_cap = 0;
     float* ycoarse = nullptr;       // the network's output on the pooled coarse grid (cnn_pool 2)
     int64_t ycoarse_cap = 0;
+    // gammax_map_grids: listed nodes, their first bounds, the guard list (each n_ref words)
+    // and the lower-key table of the evaluation grid
+    uint32_t* g_work = nullptr;
+    int64_t g_work_cap = 0;
+    TabEntry* g_tab = nullptr;
+    int64_t g_tab_cap = 0, g_tab_len = 0;
+    TableGeom g_geom{};
+    bool g_tab_valid = false;
     struct BatchState* batch = nullptr;   // gammax_batch state (created on first use)
     struct ManyState* many = nullptr;     // gammax_map_many state (created on first use)
     uint64_t tail_hint = 0;         // tail length of the last map (picks the tail sort variant)
@@ -304,7 +312,7 @@ __global__ void k_publish_scalars(const Scalars* __restrict__ src, uint32_t* seq
 }
 
 bool same_geom(const TableGeom& a, const TableGeom& b) {
-    if (a.ndim != b.ndim) return false;
+    if (a.ndim != b.ndim || a.lower != b.lower) return false;
     for (int i = 0; i < a.ndim; ++i)
         if (a.shape[i] != b.shape[i] || a.s[i] != b.s[i]) return false;
     return true;
@@ -922,7 +930,7 @@ gammax_status_t gammax_ctx_destroy(gammax_ctx_t* c) {
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void* dev[] = {c->d_sc, c->d_cnt, c->d_count, c->d_seq, c->work, c->blockcnt, c->part, c->hist,
-                   c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws, c->yhat, c->ycoarse};
+                   c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws, c->yhat, c->ycoarse, c->g_work, c->g_tab};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     destroy_batch(c);
@@ -1240,6 +1248,114 @@ gammax_status_t predict_nodes(gammax_ctx_t* c, gammax_model_t* m, const gammax_p
 }  // namespace
 
 extern "C" {
+
+gammax_status_t gammax_map_grids(gammax_ctx_t* c, const gammax_problem_t* p, const gammax_grid_t* eg,
+                                 const float* ref, const float* ev, float* gamma, const gammax_options_t* opt_in,
+                                 gammax_result_t* res, void* stream) {
+    if (!c) return GAMMAX_E_NULL;
+    if (!ref || !ev || !gamma || !eg) return fail(c, GAMMAX_E_NULL, "dose, gamma and grid pointers are required");
+    int64_t nr = 0;
+    gammax_status_t st = check_problem(c, p, &nr);
+    if (st != GAMMAX_OK) return st;
+    if (p->ndim != 3) return fail(c, GAMMAX_E_SHAPE, "two grids: 3D only");
+    int64_t ne = 1;
+    for (int i = 0; i < 3; ++i) {
+        if (eg->shape[i] < 2 || eg->shape[i] > ((int64_t)1 << 30))
+            return fail(c, GAMMAX_E_SHAPE, "every evaluation axis needs at least 2 nodes");
+        ne *= eg->shape[i];
+        if (ne >= ((int64_t)1 << 31)) return fail(c, GAMMAX_E_SHAPE, "evaluation grid must hold < 2^31 nodes");
+        if (!finite_pos(eg->spacing_mm[i])) return fail(c, GAMMAX_E_PARAM, "evaluation spacing must be finite and > 0");
+        if (!std::isfinite(eg->origin_mm[i])) return fail(c, GAMMAX_E_PARAM, "evaluation origin must be finite");
+    }
+    if ((const float*)gamma == ref || (const float*)gamma == ev)
+        return fail(c, GAMMAX_E_PARAM, "gamma must not alias the dose arrays");
+    gammax_options_t opt;
+    if (opt_in) opt = *opt_in;
+    else gammax_options_default(&opt);
+    if ((st = check_options(c, &opt)) != GAMMAX_OK) return st;
+    if (opt.radius_mode != GAMMAX_RADIUS_PLAIN || opt.sort_mode != GAMMAX_SORT_NONE || opt.timing ||
+        opt.tail_lanes == 1 || opt.cnn_pool || opt.projection)
+        return fail(c, GAMMAX_E_PARAM, "two grids: plain radius, no sort, no timing, lanes 0 or 8..64 only");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((st = grow(c, &c->g_work, &c->g_work_cap, 3 * nr)) != GAMMAX_OK) return st;
+    GridsArgs a{};
+    a.ref = ref;
+    a.ev = ev;
+    a.gamma = gamma;
+    for (int i = 0; i < 3; ++i) {
+        a.rn[i] = (int)p->shape[i];
+        a.en[i] = (int)eg->shape[i];
+        a.rh[i] = p->spacing_mm[i];
+        a.eh[i] = eg->spacing_mm[i];
+        a.eo[i] = eg->origin_mm[i];
+    }
+    a.dta = p->dta_mm;
+    a.dd = p->dd;
+    a.thr = (float)p->dose_threshold;
+    a.local = p->norm == GAMMAX_LOCAL ? 1 : 0;
+    {
+        // kappa(Gram) <= (s_max^2 / s_min^2) * Den in the chain basis (evaluation spacing)
+        double smin = INFINITY, smax = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            smin = std::min(smin, eg->spacing_mm[i]);
+            smax = std::max(smax, eg->spacing_mm[i]);
+        }
+        const double guard = opt.cond_threshold * (smin * smin) / (smax * smax);
+        a.den_guard = opt.precision == GAMMAX_PREC_GUARDED ? (float)guard : INFINITY;
+    }
+    a.sc = c->d_sc;
+    a.list = c->g_work;
+    a.f0 = reinterpret_cast<float*>(c->g_work + nr);
+    a.guard_list = c->g_work + 2 * nr;
+    HIPCHK(c, hipMemsetAsync(c->d_sc, 0, sizeof(Scalars), s));
+    HIPCHK(c, launch_grids_prep(a, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if ((st = scalar_errors(c, *c->h_sc, a.local != 0)) != GAMMAX_OK) return st;
+    const float r2 = u2f(c->h_sc->r2_bits);
+    if (c->h_sc->n_masked > 0 && r2 > 0.0f) {
+        // the lower-key table of the evaluation grid, cached while it reaches far enough
+        TableGeom g{};
+        g.ndim = 3;
+        g.lower = 1;
+        for (int i = 0; i < 3; ++i) {
+            g.shape[i] = eg->shape[i];
+            g.s[i] = eg->spacing_mm[i] / p->dta_mm;
+        }
+        const bool fits = c->g_tab_valid && same_geom(c->g_geom, g) && (double)r2 < c->g_geom.r2_cap;
+        if (!fits) {
+            c->g_tab_valid = false;
+            g.r2_cap = (double)r2 * 1.5;
+            float k1 = 0.0f;
+            if ((st = build_rows(c, g, &c->g_tab, &c->g_tab_cap, &c->g_tab_len, &k1, s)) != GAMMAX_OK) return st;
+            c->g_geom = g;
+            c->g_tab_valid = true;
+        }
+        a.tab = c->g_tab;
+        a.tab_len = (int)c->g_tab_len;
+        const int lanes = opt.tail_lanes > 0 ? opt.tail_lanes : 16;
+        HIPCHK(c, launch_grids_walk(a, opt.precision, false, lanes, s));
+        if (opt.precision == GAMMAX_PREC_GUARDED) HIPCHK(c, launch_grids_walk(a, opt.precision, true, lanes, s));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (res) {
+        const Scalars& h = *c->h_sc;
+        std::memset(res, 0, sizeof(*res));
+        res->n_evaluated = h.n_masked;
+        res->n_pass = h.n_pass;
+        res->n_borderline = h.n_border;
+        res->n_cells = h.n_cells;
+        res->n_guarded = h.n_guard;
+        res->pass_rate = h.n_masked ? (double)h.n_pass / (double)h.n_masked : NAN;
+        res->max_gamma = std::sqrt(u2f(h.maxg2_bits));
+        res->dose_max = ord_to_float(h.dmax_ord);
+        res->search_radius = std::sqrt(u2f(h.r2_bits));
+        res->table_len = h.n_masked > 0 && r2 > 0.0f ? (int32_t)c->g_tab_len : 0;
+    }
+    return GAMMAX_OK;
+}
 
 gammax_status_t gammax_model_features(gammax_ctx_t* c, const gammax_problem_t* p, const float* ref,
                                       const float* ev, uint16_t* feat, void* stream) {

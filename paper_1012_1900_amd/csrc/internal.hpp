@@ -145,6 +145,8 @@ struct TableGeom {
     int64_t shape[3];   // slowest first
     double s[3];        // spacing / DTA, slowest first
     double r2_cap;      // entries with key^2 < r2_cap
+    int lower = 0;      // 1: the key is the lower bound over every node position inside the
+                        // holding cell, sum_i (s_i max(0, |a_i| - 1))^2 (two grids)
     int64_t lo[3], ext[3];  // candidate box per axis (slowest first)
     int64_t box;        // prod(ext)
 };
@@ -223,6 +225,36 @@ struct SearchPlan {
 };
 int64_t search_sums_needed(uint32_t M);
 hipError_t launch_search(const SearchArgs& a, const SearchPlan& plan, hipStream_t s);
+
+// ---- two grids: the evaluation dose on a grid of its own (3D) ---------------------------
+//
+// Reference node k sits at k * rh (mm, slowest axis first); evaluation node j at eo + j * eh.
+// A masked reference node inside the evaluation grid's box is evaluated against the Kuhn
+// surface of the evaluation grid; others get gamma = -1.
+struct GridsArgs {
+    const float* ref;
+    const float* ev;
+    float* gamma;
+    int rn[3], en[3];          // shapes, slowest first
+    double rh[3], eh[3], eo[3];
+    double dta, dd;
+    float thr;
+    int local;
+    float den_guard;
+    Scalars* sc;               // dmax_ord, thr_val, inv_dd, n_masked (= nodes listed), r2_bits,
+                               // n_guard, maxg2_bits, n_pass, n_border, n_cells, flags
+    uint32_t* list;            // listed nodes
+    float* f0;                 // their first bound (nearest vertex of the holding cell, dist^2)
+    uint32_t* guard_list;      // nodes that met an ill-conditioned tetrahedron
+    const TabEntry* tab;       // lower-key table of the evaluation grid
+    int tab_len;
+};
+// Dose maximum and finiteness, then the listing of the evaluated nodes with their first
+// bound (and gamma = -1 everywhere else); sc must be zeroed before.
+hipError_t launch_grids_prep(const GridsArgs& a, hipStream_t s);
+// The walk of the listed nodes: precision 0 FP32, 1 FP32 with the guard (ill-conditioned
+// nodes go to the guard list), 2 FP64; guard: walk the guard list in FP64 instead.
+hipError_t launch_grids_walk(const GridsArgs& a, int precision, bool guard, int lanes, hipStream_t s);
 
 // ---- batches of dose pairs -------------------------------------------------------------
 //

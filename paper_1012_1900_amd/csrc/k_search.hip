@@ -1472,6 +1472,235 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_batch_finalize(const BatchSe
     finalize_body(P.sa.sums, SUM_BINS, P.sa.sc, P.r2_cap);
 }
 
+// ---- two grids (the evaluation dose on a grid of its own, 3D) ---------------------------
+
+// Evaluation-grid position of reference node r: u = (k * rh - eo) / eh per axis (z, y, x).
+__device__ __forceinline__ void grids_pos(const GridsArgs& a, int r, double u[3], bool& inside) {
+    const int x = r % a.rn[2], y = (r / a.rn[2]) % a.rn[1], z = r / (a.rn[2] * a.rn[1]);
+    const int k[3] = {z, y, x};
+    inside = true;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        u[i] = ((double)k[i] * a.rh[i] - a.eo[i]) / a.eh[i];
+        inside = inside && u[i] >= 0.0 && u[i] <= (double)(a.en[i] - 1);
+    }
+}
+
+// Holding cell (lower corner c0, clamped so that the cell exists) and the node's position f
+// inside it, in [0, 1] per axis.
+template <typename T>
+__device__ __forceinline__ void grids_cell(const GridsArgs& a, const double u[3], int c0[3], T f[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        int c = (int)floor(u[i]);
+        c = c > a.en[i] - 2 ? a.en[i] - 2 : (c < 0 ? 0 : c);
+        c0[i] = c;
+        f[i] = (T)(u[i] - (double)c);
+    }
+}
+
+// Spatial constants of the cell at offset (a - f) from the node, in evaluation-grid units
+// (the per-row constants of the one-grid table, for a node off the grid's nodes).
+template <typename T>
+__device__ __forceinline__ Geo<T> geo_frac(T ax, T ay, T az, T sx2, T sy2, T sz2) {
+    Geo<T> g;
+    g.ax = ax; g.ay = ay; g.az = az;
+    g.px = sx2 * ax * ax; g.py = sy2 * ay * ay; g.pz = sz2 * az * az;
+    const T dxy = ax - ay, dxz = ax - az, dyz = ay - az;
+    const T s = sx2 + sy2 + sz2;
+    g.vxy = sx2 * sy2 * dxy * dxy / (sx2 + sy2);
+    g.vxz = sx2 * sz2 * dxz * dxz / (sx2 + sz2);
+    g.vyz = sy2 * sz2 * dyz * dyz / (sy2 + sz2);
+    g.vxyz = (sx2 * sy2 * dxy * dxy + sx2 * sz2 * dxz * dxz + sy2 * sz2 * dyz * dyz) / s;
+    g.mxy = (sx2 * ax + sy2 * ay) / (sx2 + sy2);
+    g.mxz = (sx2 * ax + sz2 * az) / (sx2 + sz2);
+    g.myz = (sy2 * ay + sz2 * az) / (sy2 + sz2);
+    g.mxyz = (sx2 * ax + sy2 * ay + sz2 * az) / s;
+    return g;
+}
+
+__device__ __forceinline__ float grids_thr(const GridsArgs& a, float dmax) { return a.thr * dmax; }
+
+// First bound of a node: the nearest of the 8 vertices of its holding cell.
+template <typename T>
+__device__ __forceinline__ T grids_f0(const GridsArgs& a, const int c0[3], const T f[3], T dr, T inv_dd) {
+    const T s2[3] = {(T)(a.eh[0] / a.dta) * (T)(a.eh[0] / a.dta), (T)(a.eh[1] / a.dta) * (T)(a.eh[1] / a.dta),
+                     (T)(a.eh[2] / a.dta) * (T)(a.eh[2] / a.dta)};
+    T best = Num<T>::inf();
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int bz = (b >> 2) & 1, by = (b >> 1) & 1, bx = b & 1;
+        const T dz = (T)bz - f[0], dy = (T)by - f[1], dx = (T)bx - f[2];
+        const int64_t j = ((int64_t)(c0[0] + bz) * a.en[1] + (c0[1] + by)) * a.en[2] + (c0[2] + bx);
+        const T gv = ((T)a.ev[j] - dr) * inv_dd;
+        best = vmin<T>(best, s2[0] * dz * dz + s2[1] * dy * dy + s2[2] * dx * dx + gv * gv);
+    }
+    return best;
+}
+
+__global__ __launch_bounds__(256) void k_grids_max(GridsArgs a, int64_t nr, int64_t ne) {
+    float m = -Num<float>::inf();
+    bool bad = false;
+    const int64_t n = nr > ne ? nr : ne;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        if (i < nr) {
+            const float v = a.ref[i];
+            bad = bad || !isfinite(v);
+            m = fmaxf(m, v);
+        }
+        if (i < ne) bad = bad || !isfinite(a.ev[i]);
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0 && m > -Num<float>::inf()) atomicMax(&a.sc->dmax_ord, float_to_ord(m));
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&a.sc->flags, FLAG_NONFINITE);
+}
+
+__global__ __launch_bounds__(256) void k_grids_list(GridsArgs a, int64_t nr) {
+    const float dmax = ord_to_float(a.sc->dmax_ord);
+    const float thr_val = grids_thr(a, dmax);
+    const float inv_dd_g = 1.0f / ((float)a.dd * dmax);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.sc->thr_val = thr_val;
+        a.sc->inv_dd = inv_dd_g;
+    }
+    // block-uniform trip count, so that every lane reaches the appends
+    for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < nr; b0 += (int64_t)gridDim.x * 256) {
+        const int64_t r = b0 + threadIdx.x;
+        bool take = false;
+        float F0 = 0.0f;
+        if (r < nr) {
+            const float dr = a.ref[r];
+            a.gamma[r] = -1.0f;
+            double u[3];
+            bool inside;
+            grids_pos(a, (int)r, u, inside);
+            if (dr >= thr_val && (!a.local || dr > 0.0f) && inside) {
+                int c0[3];
+                float f[3];
+                grids_cell<float>(a, u, c0, f);
+                F0 = grids_f0<float>(a, c0, f, dr, node_inv_dd(dr, inv_dd_g, (float)a.dd, a.local));
+                take = true;
+            }
+        }
+        const uint32_t pos = block_append(take, &a.sc->n_masked);
+        if (take) {
+            a.list[pos] = (uint32_t)r;
+            a.f0[pos] = F0;
+            atomicMax(&a.sc->r2_bits, f2u(F0));
+        }
+    }
+}
+
+// G lanes per node walk the lower-key table of the evaluation grid from row 0.
+template <typename T, int GMODE, bool GUARD>
+__global__ __launch_bounds__(256) void k_grids_walk(GridsArgs a, int G) {
+    const uint32_t M = GUARD ? a.sc->n_guard : a.sc->n_masked;
+    const uint32_t* list = GUARD ? a.guard_list : a.list;
+    const int GROUPS = 256 / G;
+    const int gl = threadIdx.x % G;
+    const double dmax = (double)ord_to_float(a.sc->dmax_ord);
+    const float inv_dd_g = a.sc->inv_dd;
+    const T sx2 = (T)((a.eh[2] / a.dta) * (a.eh[2] / a.dta)), sy2 = (T)((a.eh[1] / a.dta) * (a.eh[1] / a.dta)),
+            sz2 = (T)((a.eh[0] / a.dta) * (a.eh[0] / a.dta));
+    const InvS2<T> is = inv_s2<T>(sx2, sy2, sz2);
+    const int enx = a.en[2], eny = a.en[1], enz = a.en[0], esxy = enx * eny;
+    uint32_t npass = 0, nborder = 0, gm = 0, n_fp64 = 0;
+    unsigned long long cells = 0;
+    GuardCtx gc{};
+    for (uint64_t base = (uint64_t)blockIdx.x * GROUPS; base < M; base += (uint64_t)gridDim.x * GROUPS) {
+        const uint32_t i = (uint32_t)base + threadIdx.x / G;
+        const bool live = i < M;
+        const int r = live ? (int)list[i] : 0;
+        double u[3];
+        bool inside;
+        grids_pos(a, r, u, inside);
+        int c0[3];
+        T f[3];
+        grids_cell<T>(a, u, c0, f);
+        const float dr32 = a.ref[r];
+        const T dr = (T)dr32;
+        T inv_dd;
+        if constexpr (sizeof(T) == 8)
+            inv_dd = a.local ? (T)(1.0 / (a.dd * (double)dr32)) : (T)(1.0 / (a.dd * dmax));
+        else
+            inv_dd = (T)node_inv_dd(dr32, inv_dd_g, (float)a.dd, a.local);
+        T F = live ? (GUARD || sizeof(T) == 8 ? grids_f0<T>(a, c0, f, dr, inv_dd) : (T)a.f0[i]) : T(0);
+        uint32_t lane_cells = 0;
+        bool ill = false;
+        for (int n0 = 0; n0 < a.tab_len; n0 += G) {
+            const bool grp_act = live && (T)a.tab[n0].key2 < F;
+            if (__ballot(grp_act) == 0ull) break;
+            const int n = n0 + gl;
+            TabEntry e;
+            bool act = false;
+            if (grp_act && n < a.tab_len) {
+                e = a.tab[n];
+                act = (T)e.key2 < F;
+            }
+            int cz = 0, cy = 0, cx = 0;
+            if (act) {
+                cz = c0[0] + e.az;
+                cy = c0[1] + e.ay;
+                cx = c0[2] + e.ax;
+            }
+            const bool cin = (unsigned)cx < (unsigned)enx && (unsigned)cy < (unsigned)eny && (unsigned)cz < (unsigned)enz;
+            const bool okx = cx + 1 < enx, oky = cy + 1 < eny, okz = cz + 1 < enz;
+            const bool work = act && cin;
+            const bool edge = !(okx && oky && okz);
+            T c = Num<T>::inf();
+            if (work) {
+                lane_cells += edge ? 0u : 1u;
+                const int64_t b = (int64_t)cz * esxy + (int64_t)cy * enx + cx;
+                const int ox = okx ? 1 : 0, oy = oky ? enx : 0, oz = okz ? esxy : 0;
+                T g[8];
+                g[0] = dose_norm<T>((T)a.ev[b], dr, inv_dd);
+                g[1] = dose_norm<T>((T)a.ev[b + ox], dr, inv_dd);
+                g[2] = dose_norm<T>((T)a.ev[b + oy], dr, inv_dd);
+                g[3] = dose_norm<T>((T)a.ev[b + oy + ox], dr, inv_dd);
+                g[4] = dose_norm<T>((T)a.ev[b + oz], dr, inv_dd);
+                g[5] = dose_norm<T>((T)a.ev[b + oz + ox], dr, inv_dd);
+                g[6] = dose_norm<T>((T)a.ev[b + oz + oy], dr, inv_dd);
+                g[7] = dose_norm<T>((T)a.ev[b + oz + oy + ox], dr, inv_dd);
+                const Geo<T> Gm = geo_frac<T>((T)e.ax - f[2], (T)e.ay - f[1], (T)e.az - f[0], sx2, sy2, sz2);
+                c = cell3<T, true, GMODE>(g, Gm, is, okx, oky, okz, (T)a.den_guard, gc, n_fp64, ill);
+            }
+            for (int o = G / 2; o > 0; o >>= 1) c = vmin<T>(c, __shfl_xor(c, o));
+            F = vmin<T>(F, c);
+        }
+        for (int o = G / 2; o > 0; o >>= 1) {
+            lane_cells += (uint32_t)__shfl_xor((int)lane_cells, o);
+            ill = (__shfl_xor((int)ill, o) != 0) || ill;
+        }
+        const bool leader = live && gl == 0;
+        const bool to_guard = GMODE == 1 && leader && ill;
+        if (leader && !to_guard) {
+            const float gam = (float)sqrt((double)F);
+            a.gamma[r] = gam;
+            npass += gam <= 1.0f;
+            nborder += fabsf(gam - 1.0f) <= 1e-5f;
+            gm = max(gm, f2u(gam * gam));
+            cells += lane_cells;
+        }
+        if (GMODE == 1) {
+            const uint32_t gpos = block_append(to_guard, &a.sc->n_guard);
+            if (to_guard) a.guard_list[gpos] = (uint32_t)r;
+        }
+    }
+    // one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) {
+        npass += (uint32_t)__shfl_xor((int)npass, o);
+        nborder += (uint32_t)__shfl_xor((int)nborder, o);
+        gm = max(gm, (uint32_t)__shfl_xor((int)gm, o));
+        cells += (unsigned long long)__shfl_xor((long long)cells, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (npass) atomicAdd(&a.sc->n_pass, (unsigned long long)npass);
+        if (nborder) atomicAdd(&a.sc->n_border, (unsigned long long)nborder);
+        if (cells) atomicAdd(&a.sc->n_cells, cells);
+        if (gm) atomicMax(&a.sc->maxg2_bits, gm);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_batch_search(const BatchSearchPair* pairs, int n, const uint2* items, int n_items,
@@ -1570,6 +1799,28 @@ hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s
         }
     }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(SEARCH_THREADS), 0, s, sums, SUM_BINS, a.sc, a.r2_cap);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_grids_prep(const GridsArgs& a, hipStream_t s) {
+    const int64_t nr = (int64_t)a.rn[0] * a.rn[1] * a.rn[2];
+    const int64_t ne = (int64_t)a.en[0] * a.en[1] * a.en[2];
+    const int64_t n = nr > ne ? nr : ne;
+    const unsigned b1 = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_grids_max, dim3(b1), dim3(256), 0, s, a, nr, ne);
+    const unsigned b2 = (unsigned)((nr + 255) / 256 < 4096 ? (nr + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_grids_list, dim3(b2), dim3(256), 0, s, a, nr);
+    return hipGetLastError();
+}
+
+hipError_t launch_grids_walk(const GridsArgs& a, int precision, bool guard, int lanes, hipStream_t s) {
+    const int G = lanes;
+    const dim3 grid(2048), block(256);
+    if (guard) hipLaunchKernelGGL((k_grids_walk<double, 0, true>), grid, block, 0, s, a, G);
+    else if (precision == 2) hipLaunchKernelGGL((k_grids_walk<double, 0, false>), grid, block, 0, s, a, G);
+    else if (precision == 1) hipLaunchKernelGGL((k_grids_walk<float, 1, false>), grid, block, 0, s, a, G);
+    else hipLaunchKernelGGL((k_grids_walk<float, 0, false>), grid, block, 0, s, a, G);
     return hipGetLastError();
 }
 

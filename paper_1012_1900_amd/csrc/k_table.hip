@@ -25,7 +25,9 @@ __device__ __forceinline__ void decode_box(const TableGeom& g, uint32_t j, int64
 __device__ __forceinline__ double key2_of(const TableGeom& g, const int64_t a[3]) {
     double k2 = 0.0;
     for (int i = 0; i < g.ndim; ++i) {
-        int64_t m = a[i] > 0 ? a[i] : (a[i] < -1 ? -a[i] - 1 : 0);
+        int64_t m;
+        if (g.lower) m = a[i] > 1 ? a[i] - 1 : (a[i] < -1 ? -a[i] - 1 : 0);
+        else m = a[i] > 0 ? a[i] : (a[i] < -1 ? -a[i] - 1 : 0);
         double d = g.s[i] * (double)m;
         k2 += d * d;
     }
@@ -150,7 +152,7 @@ void table_box(TableGeom& g) {
         // max(0, a, -a-1) < r / s_i  =>  a in [-(c+1), c] with c = ceil(r / s_i)
         double c = std::ceil(r / g.s[i]);
         int64_t lim = (c > (double)g.shape[i]) ? g.shape[i] : (int64_t)c;
-        int64_t lo = -lim - 1, hi = lim;
+        int64_t lo = -lim - 1, hi = g.lower ? lim + 1 : lim;
         if (lo < -(g.shape[i] - 1)) lo = -(g.shape[i] - 1);
         if (hi > g.shape[i] - 1) hi = g.shape[i] - 1;
         g.lo[i] = lo;

@@ -37,7 +37,7 @@ def test_header_declares_the_boundary():
                  "gammax_model_features", "gammax_model_predict", "gammax_model_forward",
                  "gammax_model_train_step", "gammax_model_last_error", "gammax_model_predict_nodes",
                  "gammax_batch", "gammax_tune_save", "gammax_tune_load", "gammax_map_async",
-                 "gammax_map_wait", "gammax_map_many", "gammax_model_predict_nodes_pooled"]:
+                 "gammax_map_wait", "gammax_map_many", "gammax_model_predict_nodes_pooled", "gammax_map_grids"]:
         assert must in names
 
 
