@@ -120,6 +120,7 @@ struct gammax_ctx {
     int64_t g_tab_cap = 0, g_tab_len = 0;
     TableGeom g_geom{};
     bool g_tab_valid = false;
+    float g_k1 = INFINITY;             // key^2 of its first row past the 27 key-0 cells
     struct BatchState* batch = nullptr;   // gammax_batch state (created on first use)
     struct ManyState* many = nullptr;     // gammax_map_many state (created on first use)
     uint64_t tail_hint = 0;         // tail length of the last map (picks the tail sort variant)
@@ -352,7 +353,7 @@ gammax_status_t build_rows(gammax_ctx* c, TableGeom& g, TabEntry** tab, int64_t*
     const int64_t T = *c->h_count;
     if ((st = grow(c, tab, cap, T)) != GAMMAX_OK) return st;
     HIPCHK(c, launch_table_rows(g, vals, T, *tab, s));
-    const int zero_rows = g.ndim == 3 ? 8 : 4;
+    const int zero_rows = g.lower ? 27 : (g.ndim == 3 ? 8 : 4);
     *k1 = INFINITY;
     if (T > zero_rows) {
         HIPCHK(c, hipMemcpyAsync(c->h_count, &(*tab)[zero_rows].key2, sizeof(float), hipMemcpyDeviceToHost, s));
@@ -1278,7 +1279,7 @@ gammax_status_t gammax_map_grids(gammax_ctx_t* c, const gammax_problem_t* p, con
         return fail(c, GAMMAX_E_PARAM, "two grids: plain radius, no sort, no timing, lanes 0 or 8..64 only");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, hipSetDevice(c->device));
-    if ((st = grow(c, &c->g_work, &c->g_work_cap, 3 * nr)) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->g_work, &c->g_work_cap, 5 * nr)) != GAMMAX_OK) return st;
     GridsArgs a{};
     a.ref = ref;
     a.ev = ev;
@@ -1308,6 +1309,8 @@ gammax_status_t gammax_map_grids(gammax_ctx_t* c, const gammax_problem_t* p, con
     a.list = c->g_work;
     a.f0 = reinterpret_cast<float*>(c->g_work + nr);
     a.guard_list = c->g_work + 2 * nr;
+    a.tail_list = c->g_work + 3 * nr;
+    a.tail_f = reinterpret_cast<float*>(c->g_work + 4 * nr);
     HIPCHK(c, hipMemsetAsync(c->d_sc, 0, sizeof(Scalars), s));
     HIPCHK(c, launch_grids_prep(a, s));
     HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
@@ -1327,15 +1330,22 @@ gammax_status_t gammax_map_grids(gammax_ctx_t* c, const gammax_problem_t* p, con
         if (!fits) {
             c->g_tab_valid = false;
             g.r2_cap = (double)r2 * 1.5;
-            float k1 = 0.0f;
-            if ((st = build_rows(c, g, &c->g_tab, &c->g_tab_cap, &c->g_tab_len, &k1, s)) != GAMMAX_OK) return st;
+            if ((st = build_rows(c, g, &c->g_tab, &c->g_tab_cap, &c->g_tab_len, &c->g_k1, s)) != GAMMAX_OK)
+                return st;
             c->g_geom = g;
             c->g_tab_valid = true;
         }
         a.tab = c->g_tab;
         a.tab_len = (int)c->g_tab_len;
+        a.k1 = c->g_k1;
         const int lanes = opt.tail_lanes > 0 ? opt.tail_lanes : 16;
-        HIPCHK(c, launch_grids_walk(a, opt.precision, false, lanes, s));
+        if (opt.precision == GAMMAX_PREC_FP64) {
+            HIPCHK(c, launch_grids_walk(a, opt.precision, false, lanes, s));
+        } else {
+            // the 27 key-0 cells one lane per node, then the walk of the nodes left
+            HIPCHK(c, launch_grids_zero(a, opt.precision, s));
+            HIPCHK(c, launch_grids_tail(a, opt.precision, lanes, s));
+        }
         if (opt.precision == GAMMAX_PREC_GUARDED) HIPCHK(c, launch_grids_walk(a, opt.precision, true, lanes, s));
     }
     HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));

@@ -248,6 +248,9 @@ struct GridsArgs {
     uint32_t* guard_list;      // nodes that met an ill-conditioned tetrahedron
     const TabEntry* tab;       // lower-key table of the evaluation grid
     int tab_len;
+    float k1;                  // key^2 of the first row past the 27 key-0 cells
+    uint32_t* tail_list;       // nodes the key-0 pass leaves for the walk (count: sc->n_tail)
+    float* tail_f;             // and their bound so far
 };
 // Dose maximum and finiteness, then the listing of the evaluated nodes with their first
 // bound (and gamma = -1 everywhere else); sc must be zeroed before.
@@ -255,6 +258,11 @@ hipError_t launch_grids_prep(const GridsArgs& a, hipStream_t s);
 // The walk of the listed nodes: precision 0 FP32, 1 FP32 with the guard (ill-conditioned
 // nodes go to the guard list), 2 FP64; guard: walk the guard list in FP64 instead.
 hipError_t launch_grids_walk(const GridsArgs& a, int precision, bool guard, int lanes, hipStream_t s);
+// FP32 (precision 0, or 1 with the guard): the 27 key-0 cells of every listed node from its
+// shared 4x4x4 neighbourhood, one lane per node; nodes not finished go to the tail list, and
+// the walk of that list (tail = true) starts past the key-0 rows.
+hipError_t launch_grids_zero(const GridsArgs& a, int precision, hipStream_t s);
+hipError_t launch_grids_tail(const GridsArgs& a, int precision, int lanes, hipStream_t s);
 
 // ---- batches of dose pairs -------------------------------------------------------------
 //

@@ -1501,21 +1501,21 @@ __device__ __forceinline__ void grids_cell(const GridsArgs& a, const double u[3]
 
 // Spatial constants of the cell at offset (a - f) from the node, in evaluation-grid units
 // (the per-row constants of the one-grid table, for a node off the grid's nodes).
+// (is: the reciprocals of the block sums of s^2, so no division per cell)
 template <typename T>
-__device__ __forceinline__ Geo<T> geo_frac(T ax, T ay, T az, T sx2, T sy2, T sz2) {
+__device__ __forceinline__ Geo<T> geo_frac(T ax, T ay, T az, T sx2, T sy2, T sz2, const InvS2<T>& is) {
     Geo<T> g;
     g.ax = ax; g.ay = ay; g.az = az;
     g.px = sx2 * ax * ax; g.py = sy2 * ay * ay; g.pz = sz2 * az * az;
     const T dxy = ax - ay, dxz = ax - az, dyz = ay - az;
-    const T s = sx2 + sy2 + sz2;
-    g.vxy = sx2 * sy2 * dxy * dxy / (sx2 + sy2);
-    g.vxz = sx2 * sz2 * dxz * dxz / (sx2 + sz2);
-    g.vyz = sy2 * sz2 * dyz * dyz / (sy2 + sz2);
-    g.vxyz = (sx2 * sy2 * dxy * dxy + sx2 * sz2 * dxz * dxz + sy2 * sz2 * dyz * dyz) / s;
-    g.mxy = (sx2 * ax + sy2 * ay) / (sx2 + sy2);
-    g.mxz = (sx2 * ax + sz2 * az) / (sx2 + sz2);
-    g.myz = (sy2 * ay + sz2 * az) / (sy2 + sz2);
-    g.mxyz = (sx2 * ax + sy2 * ay + sz2 * az) / s;
+    g.vxy = sx2 * sy2 * dxy * dxy * is.xy;
+    g.vxz = sx2 * sz2 * dxz * dxz * is.xz;
+    g.vyz = sy2 * sz2 * dyz * dyz * is.yz;
+    g.vxyz = (sx2 * sy2 * dxy * dxy + sx2 * sz2 * dxz * dxz + sy2 * sz2 * dyz * dyz) * is.xyz;
+    g.mxy = (sx2 * ax + sy2 * ay) * is.xy;
+    g.mxz = (sx2 * ax + sz2 * az) * is.xz;
+    g.myz = (sy2 * ay + sz2 * az) * is.yz;
+    g.mxyz = (sx2 * ax + sy2 * ay + sz2 * az) * is.xyz;
     return g;
 }
 
@@ -1551,11 +1551,21 @@ __global__ __launch_bounds__(256) void k_grids_max(GridsArgs a, int64_t nr, int6
         if (i < ne) bad = bad || !isfinite(a.ev[i]);
     }
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0 && m > -Num<float>::inf()) atomicMax(&a.sc->dmax_ord, float_to_ord(m));
+    // one atomic per wave, and only while it can still raise the maximum (all waves on one
+    // address would serialise)
+    if ((threadIdx.x & 63) == 0 && m > -Num<float>::inf()) {
+        const uint32_t o = float_to_ord(m);
+        if (o > __atomic_load_n(&a.sc->dmax_ord, __ATOMIC_RELAXED)) atomicMax(&a.sc->dmax_ord, o);
+    }
     if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&a.sc->flags, FLAG_NONFINITE);
 }
 
+// Listing in chunks of 16 nodes per thread (4096 per block): one atomic per chunk on the
+// list counter (one per 256 nodes would serialise on that address).
+constexpr int GRIDS_PER_THREAD = 16;
 __global__ __launch_bounds__(256) void k_grids_list(GridsArgs a, int64_t nr) {
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_base;
     const float dmax = ord_to_float(a.sc->dmax_ord);
     const float thr_val = grids_thr(a, dmax);
     const float inv_dd_g = 1.0f / ((float)a.dd * dmax);
@@ -1563,39 +1573,193 @@ __global__ __launch_bounds__(256) void k_grids_list(GridsArgs a, int64_t nr) {
         a.sc->thr_val = thr_val;
         a.sc->inv_dd = inv_dd_g;
     }
-    // block-uniform trip count, so that every lane reaches the appends
-    for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < nr; b0 += (int64_t)gridDim.x * 256) {
-        const int64_t r = b0 + threadIdx.x;
-        bool take = false;
-        float F0 = 0.0f;
-        if (r < nr) {
-            const float dr = a.ref[r];
-            a.gamma[r] = -1.0f;
-            double u[3];
-            bool inside;
-            grids_pos(a, (int)r, u, inside);
-            if (dr >= thr_val && (!a.local || dr > 0.0f) && inside) {
-                int c0[3];
-                float f[3];
-                grids_cell<float>(a, u, c0, f);
-                F0 = grids_f0<float>(a, c0, f, dr, node_inv_dd(dr, inv_dd_g, (float)a.dd, a.local));
-                take = true;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t chunk = 256 * GRIDS_PER_THREAD;
+    // block-uniform trip count, so that every thread reaches the barriers
+    for (int64_t b0 = (int64_t)blockIdx.x * chunk; b0 < nr; b0 += (int64_t)gridDim.x * chunk) {
+        float F0[GRIDS_PER_THREAD];
+        uint32_t takes = 0u, cnt = 0u;
+#pragma unroll
+        for (int k = 0; k < GRIDS_PER_THREAD; ++k) {
+            const int64_t r = b0 + threadIdx.x + 256 * k;
+            F0[k] = 0.0f;
+            if (r < nr) {
+                const float dr = a.ref[r];
+                a.gamma[r] = -1.0f;
+                double u[3];
+                bool inside;
+                grids_pos(a, (int)r, u, inside);
+                if (dr >= thr_val && (!a.local || dr > 0.0f) && inside) {
+                    int c0[3];
+                    float f[3];
+                    grids_cell<float>(a, u, c0, f);
+                    F0[k] = grids_f0<float>(a, c0, f, dr, node_inv_dd(dr, inv_dd_g, (float)a.dd, a.local));
+                    takes |= 1u << k;
+                    ++cnt;
+                }
             }
         }
-        const uint32_t pos = block_append(take, &a.sc->n_masked);
-        if (take) {
-            a.list[pos] = (uint32_t)r;
-            a.f0[pos] = F0;
-            atomicMax(&a.sc->r2_bits, f2u(F0));
+        // exclusive prefix of the per-thread counts over the block
+        uint32_t incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+            if (lane >= o) incl += y;
         }
+        if (lane == 63) s_wsum[w] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t tot = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+            s_base = tot ? atomicAdd(&a.sc->n_masked, tot) : 0u;
+        }
+        __syncthreads();
+        uint32_t pos = s_base + incl - cnt;
+        for (int j2 = 0; j2 < w; ++j2) pos += s_wsum[j2];
+        __syncthreads();   // s_wsum / s_base are reused by the next chunk
+        uint32_t fb = 0u;
+#pragma unroll
+        for (int k = 0; k < GRIDS_PER_THREAD; ++k) {
+            if ((takes >> k) & 1u) {
+                a.list[pos] = (uint32_t)(b0 + threadIdx.x + 256 * k);
+                a.f0[pos] = F0[k];
+                fb = max(fb, f2u(F0[k]));
+                ++pos;
+            }
+        }
+        // the largest first bound: one atomic per wave, only while it can raise it
+        for (int o = 32; o > 0; o >>= 1) fb = max(fb, (uint32_t)__shfl_xor((int)fb, o));
+        if (lane == 0 && fb > __atomic_load_n(&a.sc->r2_bits, __ATOMIC_RELAXED)) atomicMax(&a.sc->r2_bits, fb);
     }
 }
 
 // G lanes per node walk the lower-key table of the evaluation grid from row 0.
-template <typename T, int GMODE, bool GUARD>
+// The 27 key-0 cells (offsets a in {-1,0,1}^3 from the holding cell) of every listed node,
+// one lane per node, from the 4x4x4 evaluation neighbourhood loaded one z-pair of planes at
+// a time (clamped at the grid faces; cells that do not exist are skipped).  A node whose
+// bound is at most k1 is finished; the others go to the tail list.
+template <int GMODE>
+__global__ __launch_bounds__(256) void k_grids_zero(GridsArgs a) {
+    const uint32_t M = a.sc->n_masked;
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x * 256 >= M) return;   // uniform
+    const bool live = i < M;
+    const int r = live ? (int)a.list[i] : (int)a.list[0];
+    double u[3];
+    bool inside;
+    grids_pos(a, r, u, inside);
+    int c0[3];
+    float f[3];
+    grids_cell<float>(a, u, c0, f);
+    const float dr = a.ref[r];
+    const float inv_dd = node_inv_dd(dr, a.sc->inv_dd, (float)a.dd, a.local);
+    const float sx2 = (float)((a.eh[2] / a.dta) * (a.eh[2] / a.dta)), sy2 = (float)((a.eh[1] / a.dta) * (a.eh[1] / a.dta)),
+                sz2 = (float)((a.eh[0] / a.dta) * (a.eh[0] / a.dta));
+    const InvS2<float> is = inv_s2<float>(sx2, sy2, sz2);
+    const int enx = a.en[2], eny = a.en[1], enz = a.en[0];
+    // per axis: does the cell at -1 exist, is the cell at +1 whole
+    const bool lox = c0[2] > 0, loy = c0[1] > 0, loz = c0[0] > 0;
+    const bool hix = c0[2] + 2 < enx, hiy = c0[1] + 2 < eny, hiz = c0[0] + 2 < enz;
+    const bool bnd = !(lox && loy && loz && hix && hiy && hiz);
+    const bool wave_masked = __ballot(live && bnd) != 0ull;
+    auto cl = [](int v, int n) { return v < 0 ? 0 : (v > n - 1 ? n - 1 : v); };
+    int ix[4], iy[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        ix[d] = cl(c0[2] - 1 + d, enx);
+        iy[d] = cl(c0[1] - 1 + d, eny);
+    }
+    float F = live ? a.f0[i] : 0.0f;
+    uint32_t cells = 0, n_fp64 = 0;
+    bool ill = false;
+    GuardCtx gc{};
+#pragma unroll 1
+    for (int az = -1; az <= 1; ++az) {
+        // the two planes of this slab of cells
+        float pl[2][16];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int64_t zb = (int64_t)cl(c0[0] + az + p, enz) * eny;
+#pragma unroll
+            for (int dy = 0; dy < 4; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 4; ++dx)
+                    pl[p][dy * 4 + dx] = a.ev[(zb + iy[dy]) * enx + ix[dx]];
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int k = 0; k < 16; ++k) pl[p][k] = dose_norm<float>(pl[p][k], dr, inv_dd);
+        const bool ez = az < 0 ? loz : true, okz = az > 0 ? hiz : true;
+#pragma unroll
+        for (int ay = -1; ay <= 1; ++ay)
+#pragma unroll
+            for (int ax = -1; ax <= 1; ++ax) {
+                float g[8];
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    g[b] = pl[(b >> 2) & 1][(ay + 1 + ((b >> 1) & 1)) * 4 + (ax + 1 + (b & 1))];
+                const Geo<float> G = geo_frac<float>((float)ax - f[2], (float)ay - f[1], (float)az - f[0], sx2, sy2,
+                                                     sz2, is);
+                const bool ey = ay < 0 ? loy : true, oky = ay > 0 ? hiy : true;
+                const bool ex = ax < 0 ? lox : true, okx = ax > 0 ? hix : true;
+                const bool exists = ex && ey && ez;
+                float v;
+                if (wave_masked) {
+                    v = cell3<float, true, GMODE>(g, G, is, okx, oky, okz, a.den_guard, gc, n_fp64, ill);
+                    v = exists ? v : Num<float>::inf();
+                    cells += (exists && okx && oky && okz) ? 1u : 0u;
+                } else {
+                    v = cell3<float, false, GMODE>(g, G, is, true, true, true, a.den_guard, gc, n_fp64, ill);
+                    cells += 1u;
+                }
+                F = vmin<float>(F, v);
+            }
+    }
+    ill = ill && live;
+    const bool to_guard = GMODE == 1 && ill;
+    const bool to_tail = live && !to_guard && F > a.k1;
+    uint32_t npass = 0, nborder = 0, gm = 0;
+    unsigned long long ncells = 0;
+    if (live && !to_guard && !to_tail) {
+        const float gam = sqrtf(F);
+        a.gamma[r] = gam;
+        npass = gam <= 1.0f;
+        nborder = fabsf(gam - 1.0f) <= 1e-5f;
+        gm = f2u(gam * gam);
+        ncells = cells;
+    }
+    const uint32_t tpos = block_append(to_tail, &a.sc->n_tail);
+    if (to_tail) {
+        a.tail_list[tpos] = (uint32_t)r;
+        a.tail_f[tpos] = F;
+    }
+    if (GMODE == 1) {
+        const uint32_t gpos = block_append(to_guard, &a.sc->n_guard);
+        if (to_guard) a.guard_list[gpos] = (uint32_t)r;
+    }
+    // tail nodes count their key-0 cells in the walk's total: add them here
+    if (to_tail) ncells = cells;
+    for (int o = 32; o > 0; o >>= 1) {
+        npass += (uint32_t)__shfl_xor((int)npass, o);
+        nborder += (uint32_t)__shfl_xor((int)nborder, o);
+        gm = max(gm, (uint32_t)__shfl_xor((int)gm, o));
+        ncells += (unsigned long long)__shfl_xor((long long)ncells, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (npass) atomicAdd(&a.sc->n_pass, (unsigned long long)npass);
+        if (nborder) atomicAdd(&a.sc->n_border, (unsigned long long)nborder);
+        if (ncells) atomicAdd(&a.sc->n_cells, ncells);
+        if (gm) atomicMax(&a.sc->maxg2_bits, gm);
+    }
+}
+
+// LIST 0: the listed nodes from row 0; 1: the guard list (FP64) from row 0; 2: the tail
+// list of the key-0 pass from the first row past the key-0 cells.
+template <typename T, int GMODE, int LIST>
 __global__ __launch_bounds__(256) void k_grids_walk(GridsArgs a, int G) {
-    const uint32_t M = GUARD ? a.sc->n_guard : a.sc->n_masked;
-    const uint32_t* list = GUARD ? a.guard_list : a.list;
+    constexpr bool GUARD = LIST == 1;
+    const uint32_t M = LIST == 1 ? a.sc->n_guard : (LIST == 2 ? a.sc->n_tail : a.sc->n_masked);
+    const uint32_t* list = LIST == 1 ? a.guard_list : (LIST == 2 ? a.tail_list : a.list);
+    const int first = LIST == 2 ? 27 : 0;
     const int GROUPS = 256 / G;
     const int gl = threadIdx.x % G;
     const double dmax = (double)ord_to_float(a.sc->dmax_ord);
@@ -1624,10 +1788,15 @@ __global__ __launch_bounds__(256) void k_grids_walk(GridsArgs a, int G) {
             inv_dd = a.local ? (T)(1.0 / (a.dd * (double)dr32)) : (T)(1.0 / (a.dd * dmax));
         else
             inv_dd = (T)node_inv_dd(dr32, inv_dd_g, (float)a.dd, a.local);
-        T F = live ? (GUARD || sizeof(T) == 8 ? grids_f0<T>(a, c0, f, dr, inv_dd) : (T)a.f0[i]) : T(0);
+        T F = T(0);
+        if (live) {
+            if constexpr (LIST == 2) F = (T)a.tail_f[i];
+            else if (GUARD || sizeof(T) == 8) F = grids_f0<T>(a, c0, f, dr, inv_dd);
+            else F = (T)a.f0[i];
+        }
         uint32_t lane_cells = 0;
         bool ill = false;
-        for (int n0 = 0; n0 < a.tab_len; n0 += G) {
+        for (int n0 = first; n0 < a.tab_len; n0 += G) {
             const bool grp_act = live && (T)a.tab[n0].key2 < F;
             if (__ballot(grp_act) == 0ull) break;
             const int n = n0 + gl;
@@ -1647,6 +1816,7 @@ __global__ __launch_bounds__(256) void k_grids_walk(GridsArgs a, int G) {
             const bool okx = cx + 1 < enx, oky = cy + 1 < eny, okz = cz + 1 < enz;
             const bool work = act && cin;
             const bool edge = !(okx && oky && okz);
+            const bool wave_masked = __ballot(work && edge) != 0ull;
             T c = Num<T>::inf();
             if (work) {
                 lane_cells += edge ? 0u : 1u;
@@ -1661,8 +1831,11 @@ __global__ __launch_bounds__(256) void k_grids_walk(GridsArgs a, int G) {
                 g[5] = dose_norm<T>((T)a.ev[b + oz + ox], dr, inv_dd);
                 g[6] = dose_norm<T>((T)a.ev[b + oz + oy], dr, inv_dd);
                 g[7] = dose_norm<T>((T)a.ev[b + oz + oy + ox], dr, inv_dd);
-                const Geo<T> Gm = geo_frac<T>((T)e.ax - f[2], (T)e.ay - f[1], (T)e.az - f[0], sx2, sy2, sz2);
-                c = cell3<T, true, GMODE>(g, Gm, is, okx, oky, okz, (T)a.den_guard, gc, n_fp64, ill);
+                const Geo<T> Gm = geo_frac<T>((T)e.ax - f[2], (T)e.ay - f[1], (T)e.az - f[0], sx2, sy2, sz2, is);
+                if (wave_masked)
+                    c = cell3<T, true, GMODE>(g, Gm, is, okx, oky, okz, (T)a.den_guard, gc, n_fp64, ill);
+                else
+                    c = cell3<T, false, GMODE>(g, Gm, is, true, true, true, (T)a.den_guard, gc, n_fp64, ill);
             }
             for (int o = G / 2; o > 0; o >>= 1) c = vmin<T>(c, __shfl_xor(c, o));
             F = vmin<T>(F, c);
@@ -1809,7 +1982,8 @@ hipError_t launch_grids_prep(const GridsArgs& a, hipStream_t s) {
     const int64_t n = nr > ne ? nr : ne;
     const unsigned b1 = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
     hipLaunchKernelGGL(k_grids_max, dim3(b1), dim3(256), 0, s, a, nr, ne);
-    const unsigned b2 = (unsigned)((nr + 255) / 256 < 4096 ? (nr + 255) / 256 : 4096);
+    const int64_t chunks = (nr + 256 * GRIDS_PER_THREAD - 1) / (256 * GRIDS_PER_THREAD);
+    const unsigned b2 = (unsigned)(chunks < 4096 ? chunks : 4096);
     hipLaunchKernelGGL(k_grids_list, dim3(b2), dim3(256), 0, s, a, nr);
     return hipGetLastError();
 }
@@ -1817,10 +1991,25 @@ hipError_t launch_grids_prep(const GridsArgs& a, hipStream_t s) {
 hipError_t launch_grids_walk(const GridsArgs& a, int precision, bool guard, int lanes, hipStream_t s) {
     const int G = lanes;
     const dim3 grid(2048), block(256);
-    if (guard) hipLaunchKernelGGL((k_grids_walk<double, 0, true>), grid, block, 0, s, a, G);
-    else if (precision == 2) hipLaunchKernelGGL((k_grids_walk<double, 0, false>), grid, block, 0, s, a, G);
-    else if (precision == 1) hipLaunchKernelGGL((k_grids_walk<float, 1, false>), grid, block, 0, s, a, G);
-    else hipLaunchKernelGGL((k_grids_walk<float, 0, false>), grid, block, 0, s, a, G);
+    if (guard) hipLaunchKernelGGL((k_grids_walk<double, 0, 1>), grid, block, 0, s, a, G);
+    else if (precision == 2) hipLaunchKernelGGL((k_grids_walk<double, 0, 0>), grid, block, 0, s, a, G);
+    else if (precision == 1) hipLaunchKernelGGL((k_grids_walk<float, 1, 0>), grid, block, 0, s, a, G);
+    else hipLaunchKernelGGL((k_grids_walk<float, 0, 0>), grid, block, 0, s, a, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_grids_zero(const GridsArgs& a, int precision, hipStream_t s) {
+    const int64_t nr = (int64_t)a.rn[0] * a.rn[1] * a.rn[2];   // the list holds at most nr nodes
+    const unsigned nb = (unsigned)((nr + 255) / 256);
+    if (precision == 1) hipLaunchKernelGGL(k_grids_zero<1>, dim3(nb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_grids_zero<0>, dim3(nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_grids_tail(const GridsArgs& a, int precision, int lanes, hipStream_t s) {
+    const dim3 grid(2048), block(256);
+    if (precision == 1) hipLaunchKernelGGL((k_grids_walk<float, 1, 2>), grid, block, 0, s, a, lanes);
+    else hipLaunchKernelGGL((k_grids_walk<float, 0, 2>), grid, block, 0, s, a, lanes);
     return hipGetLastError();
 }
 
