@@ -1632,6 +1632,30 @@ __global__ __launch_bounds__(256) void k_grids_list(GridsArgs a, int64_t nr) {
 }
 
 // G lanes per node walk the lower-key table of the evaluation grid from row 0.
+// Whether the cell at offset (ax, ay, az) from the holding cell can still lower F.  The node
+// (at f inside the holding cell) is at least the cell's geometric distance from it, and the
+// PL dose inside the cell lies between its vertex values, so when those share a sign the
+// cell is at least dist^2 + (smallest |g|)^2 away.  A cell at or above F (1 + 2^-8) is
+// skipped: the margin is far above the rounding of the projections, so it could not have
+// lowered F either.  The bound needs no projection, so the guard judges only the cells that
+// are projected: a skipped cell's conditioning cannot change the result.
+__device__ __forceinline__ bool grids_need(const float* g, float ax, float ay, float az, const float* f, float sx2,
+                                           float sy2, float sz2, float F) {
+    float gmin = g[0], gmax = g[0];
+#pragma unroll
+    for (int b = 1; b < 8; ++b) {
+        gmin = vmin<float>(gmin, g[b]);
+        gmax = __builtin_fmaxf(gmax, g[b]);
+    }
+    const float m = gmin > 0.0f ? gmin : (gmax < 0.0f ? -gmax : 0.0f);
+    // distance from f to the interval [a, a + 1], per axis
+    const float dx = __builtin_fmaxf(__builtin_fmaxf(0.0f, ax - f[2]), f[2] - ax - 1.0f);
+    const float dy = __builtin_fmaxf(__builtin_fmaxf(0.0f, ay - f[1]), f[1] - ay - 1.0f);
+    const float dz = __builtin_fmaxf(__builtin_fmaxf(0.0f, az - f[0]), f[0] - az - 1.0f);
+    const float lb = ((sx2 * dx * dx + sy2 * dy * dy) + sz2 * dz * dz) + m * m;
+    return lb < F + F * 0x1p-8f;
+}
+
 // The 27 key-0 cells (offsets a in {-1,0,1}^3 from the holding cell) of every listed node,
 // one lane per node, from the 4x4x4 evaluation neighbourhood loaded one z-pair of planes at
 // a time (clamped at the grid faces; cells that do not exist are skipped).  A node whose
@@ -1697,19 +1721,20 @@ __global__ __launch_bounds__(256) void k_grids_zero(GridsArgs a) {
 #pragma unroll
                 for (int b = 0; b < 8; ++b)
                     g[b] = pl[(b >> 2) & 1][(ay + 1 + ((b >> 1) & 1)) * 4 + (ax + 1 + (b & 1))];
-                const Geo<float> G = geo_frac<float>((float)ax - f[2], (float)ay - f[1], (float)az - f[0], sx2, sy2,
-                                                     sz2, is);
                 const bool ey = ay < 0 ? loy : true, oky = ay > 0 ? hiy : true;
                 const bool ex = ax < 0 ? lox : true, okx = ax > 0 ? hix : true;
-                const bool exists = ex && ey && ez;
-                float v;
-                if (wave_masked) {
-                    v = cell3<float, true, GMODE>(g, G, is, okx, oky, okz, a.den_guard, gc, n_fp64, ill);
-                    v = exists ? v : Num<float>::inf();
-                    cells += (exists && okx && oky && okz) ? 1u : 0u;
-                } else {
-                    v = cell3<float, false, GMODE>(g, G, is, true, true, true, a.den_guard, gc, n_fp64, ill);
-                    cells += 1u;
+                const bool exists = live && ex && ey && ez;
+                const bool whole = okx && oky && okz;
+                cells += (exists && (whole || !wave_masked)) ? 1u : 0u;
+                const bool need = exists && grids_need(g, (float)ax, (float)ay, (float)az, f, sx2, sy2, sz2, F);
+                float v = Num<float>::inf();
+                if (__ballot(need) != 0ull && need) {
+                    const Geo<float> G = geo_frac<float>((float)ax - f[2], (float)ay - f[1], (float)az - f[0], sx2,
+                                                         sy2, sz2, is);
+                    if (wave_masked)
+                        v = cell3<float, true, GMODE>(g, G, is, okx, oky, okz, a.den_guard, gc, n_fp64, ill);
+                    else
+                        v = cell3<float, false, GMODE>(g, G, is, true, true, true, a.den_guard, gc, n_fp64, ill);
                 }
                 F = vmin<float>(F, v);
             }
@@ -1818,11 +1843,12 @@ __global__ __launch_bounds__(256) void k_grids_walk(GridsArgs a, int G) {
             const bool edge = !(okx && oky && okz);
             const bool wave_masked = __ballot(work && edge) != 0ull;
             T c = Num<T>::inf();
+            T g[8];
+            bool need = false;
             if (work) {
                 lane_cells += edge ? 0u : 1u;
                 const int64_t b = (int64_t)cz * esxy + (int64_t)cy * enx + cx;
                 const int ox = okx ? 1 : 0, oy = oky ? enx : 0, oz = okz ? esxy : 0;
-                T g[8];
                 g[0] = dose_norm<T>((T)a.ev[b], dr, inv_dd);
                 g[1] = dose_norm<T>((T)a.ev[b + ox], dr, inv_dd);
                 g[2] = dose_norm<T>((T)a.ev[b + oy], dr, inv_dd);
@@ -1831,6 +1857,10 @@ __global__ __launch_bounds__(256) void k_grids_walk(GridsArgs a, int G) {
                 g[5] = dose_norm<T>((T)a.ev[b + oz + ox], dr, inv_dd);
                 g[6] = dose_norm<T>((T)a.ev[b + oz + oy], dr, inv_dd);
                 g[7] = dose_norm<T>((T)a.ev[b + oz + oy + ox], dr, inv_dd);
+                need = true;
+                if constexpr (sizeof(T) == 4) need = grids_need(g, (float)e.ax, (float)e.ay, (float)e.az, f, sx2, sy2, sz2, F);
+            }
+            if (__ballot(need) != 0ull && need) {
                 const Geo<T> Gm = geo_frac<T>((T)e.ax - f[2], (T)e.ay - f[1], (T)e.az - f[0], sx2, sy2, sz2, is);
                 if (wave_masked)
                     c = cell3<T, true, GMODE>(g, Gm, is, okx, oky, okz, (T)a.den_guard, gc, n_fp64, ill);
