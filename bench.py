@@ -37,9 +37,9 @@ PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 # hash differs the traffic is reported as null.
 TRAFFIC = {
     "3d_128x128x96_2.5mm": {
-        "bytes": (15.62 + 2.25) * 1e6,
+        "bytes": (15.63 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "6b845b65c778967c6be46088ef366c23fad813a4c3efa171d4a33e4a9eccacc3",
+        "sha256": "297d1094c42001bde47ba8e45d098521f9cd48cb730dead6a557a9351a441884",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }
