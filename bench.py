@@ -160,7 +160,11 @@ def run_sweep(args):
     * criteria: DD x DTA in {1,2,3}% x {1,2,3} mm on the 256x256x192 workload (Table 3);
     * resolution: the 3D generator over one box at four grid sizes, T ~ N^a (Fig. 2);
     * shift: evaluation dose + s Dmax inside the 10 % region, s = -10 % ... +10 % in 1 %
-      steps, on the 256x256x192 workload, T against sum(gamma^3) (Fig. 1b)."""
+      steps, on the 256x256x192 workload, T against sum(gamma^3) (Fig. 1b);
+    * order: the same pair at five of those shifts, the sort and the walk past the key-0
+      cells under each ordering key: none, |DD|, the bound after the key-0 cells, the
+      network's gamma_hat, the gamma of the locally linear evaluated dose, and the true
+      gamma (a perfect predictor)."""
     import numpy as np
     import torch
 
@@ -170,7 +174,7 @@ def run_sweep(args):
     dev = torch.device("cuda", 0)
     kind = args.sweep
     pts = []
-    if kind in ("criteria", "shift"):
+    if kind in ("criteria", "shift", "order"):
         cfg, seed, _ = WORKLOADS["3d_256x256x192_1.25mm"]
         pair = make_config_pair(cfg, seed)
         ref = torch.from_numpy(pair.ref).to(dev)
@@ -208,6 +212,50 @@ def run_sweep(args):
         ac, bc, r2c = _fit_line(s3, [p["n_cells"] for p in pts])
         summary = dict(sweep="shift", ms_gamma_vs_sum_gamma3=dict(slope=a, intercept_ms=round(b, 4), r2=round(r2, 4)),
                        cells_vs_sum_gamma3=dict(slope=ac, intercept=round(bc, 1), r2=round(r2c, 4)))
+    elif kind == "order":
+        ev0 = torch.from_numpy(pair.eval).to(dev)
+        dmax = float(pair.ref.max())
+        region = ref >= 0.1 * dmax
+        model = None
+        if os.path.exists(args.weights):
+            model = gx.Model(np.load(args.weights, allow_pickle=False))
+        crit = (args.dd, args.dta)
+        reps = max(3, min(args.steps, 20))
+        for k in (-10, -5, 0, 5, 10):
+            ev = torch.where(region, ev0 + (0.01 * k) * dmax, ev0)
+            truth, _ = gx.gammax_map(ref, ev, pair.spacing, *crit, 0.1)
+            # gamma of the evaluated dose taken as linear around each node: |dD| over the
+            # norm of (Delta D, DTA |grad D_e|)
+            grads = torch.gradient(ev, spacing=list(pair.spacing))
+            g2 = sum(g * g for g in grads)
+            lin = ((ev - ref).abs() / torch.sqrt((args.dd * dmax) ** 2 + g2 * args.dta ** 2)).contiguous()
+            keys = [("none", {}), ("dd", {"sort": "dd"}), ("bound", {"sort": "bound"})]
+            if model is not None:
+                keys.append(("gamma_hat", {"sort": "predicted", "model": model, "cnn_pool": 2}))
+            keys += [("gamma_lin", {"sort": "given", "order_key": lin}),
+                     ("gamma_true", {"sort": "given", "order_key": truth.clamp_min(0.0).contiguous()})]
+            if args.tail_lanes:
+                for _, kw in keys:
+                    kw["tail_lanes"] = args.tail_lanes
+            row = dict(shift=k / 100, tail_lanes=args.tail_lanes)
+            for name, kw in keys:
+                for _ in range(args.warmup):
+                    gx.gammax_map(ref, ev, pair.spacing, *crit, 0.1, **kw)
+                ph = []
+                for _ in range(reps):
+                    g, r = gx.gammax_map(ref, ev, pair.spacing, *crit, 0.1, timing=True, **kw)
+                    ph.append((r.ms_sort, r.ms_tail, r.ms_cnn))
+                if not torch.equal(g, truth):
+                    raise RuntimeError(f"order {name}: gamma differs from the unsorted map")
+                m = np.mean(np.asarray(ph), axis=0)
+                row[name] = dict(ms_sort=round(float(m[0]), 4), ms_tail=round(float(m[1]), 4),
+                                 ms_cnn=round(float(m[2]), 4))
+            row["n_tail"] = int(r.n_tail)
+            print(json.dumps(row), flush=True)
+            pts.append(row)
+        names = [n for n in pts[0] if isinstance(pts[0][n], dict)]
+        summary = dict(sweep="order", ms_tail_mean={n: round(float(np.mean([p[n]["ms_tail"] for p in pts])), 4)
+                                                    for n in names})
     elif kind == "grids":
         # the 128x128x96 pair against evaluation doses on other grids over the same box
         cfg, seed, _ = WORKLOADS["3d_128x128x96_2.5mm"]
@@ -372,7 +420,7 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2, help="fewest oracle repetitions")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="least CPU time the oracle baseline runs for")
-    ap.add_argument("--sweep", choices=["criteria", "resolution", "shift", "grids"], default=None,
+    ap.add_argument("--sweep", choices=["criteria", "resolution", "shift", "order", "grids"], default=None,
                     help="run one of the paper's scaling studies instead of the benchmark line")
     ap.add_argument("--streams", type=int, default=4,
                     help="mixed batch: spread the pairs round-robin over this many streams (the GPU "

@@ -59,7 +59,10 @@ typedef enum {
     GAMMAX_SORT_NONE = 0,     /* as they were queued (default) */
     GAMMAX_SORT_DD = 1,       /* ascending |DD| / dD ("DD sorting", Algorithm A2 step 3) */
     GAMMAX_SORT_BOUND = 2,    /* ascending gamma bound after the key-0 cells */
-    GAMMAX_SORT_PREDICTED = 3 /* ascending predicted gamma (needs a model; 3D) */
+    GAMMAX_SORT_PREDICTED = 3, /* ascending predicted gamma (needs a model; 3D) */
+    GAMMAX_SORT_GIVEN = 4     /* ascending key given by the caller per node (options.order_key;
+                                 plain radius, single maps): e.g. a known gamma, to measure
+                                 what a perfect predictor's order buys */
 } gammax_sort_t;
 
 /* Search radius of the walk past the key-0 cells. */
@@ -123,6 +126,10 @@ typedef struct {
                                  tetrahedron, then only the facets, edges and vertices its
                                  negative weights point to.  Same gamma up to rounding. */
     int32_t reserved[1];      /* must be 0 */
+    const float *order_key;   /* GAMMAX_SORT_GIVEN: device array, one float per grid node in the
+                                 doses' layout (negative keys and NaN count as 0); read by the
+                                 map, so it must stay valid and unchanged until the map is
+                                 complete.  Ignored by the other orders. */
 } gammax_options_t;
 
 typedef struct {

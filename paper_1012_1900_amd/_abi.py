@@ -40,11 +40,11 @@ E_RADIUS = -7
 E_DOSE = -8
 
 GLOBAL, LOCAL = 0, 1
-SORT_NONE, SORT_DD, SORT_BOUND, SORT_PREDICTED = 0, 1, 2, 3
+SORT_NONE, SORT_DD, SORT_BOUND, SORT_PREDICTED, SORT_GIVEN = 0, 1, 2, 3, 4
 PREC_FP32, PREC_GUARDED, PREC_FP64 = 0, 1, 2
 RADIUS_PLAIN, RADIUS_LEARNED = 0, 1
 
-_SORT = {"none": SORT_NONE, "dd": SORT_DD, "bound": SORT_BOUND, "predicted": SORT_PREDICTED}
+_SORT = {"none": SORT_NONE, "dd": SORT_DD, "bound": SORT_BOUND, "predicted": SORT_PREDICTED, "given": SORT_GIVEN}
 _RADIUS = {"plain": RADIUS_PLAIN, "learned": RADIUS_LEARNED}
 _PREC = {"fp32": PREC_FP32, "guarded": PREC_GUARDED, "fp64": PREC_FP64}
 _PROJ = {"faces": 0, "ju": 1}
@@ -84,6 +84,7 @@ class Options(C.Structure):
         ("cnn_pool", C.c_int32),
         ("projection", C.c_int32),
         ("reserved", C.c_int32 * 1),
+        ("order_key", C.c_void_p),
     ]
 
 
@@ -253,8 +254,12 @@ def make_problem(shape: Sequence[int], spacing: Sequence[float], dd: float, dta:
 
 def make_options(sort: str = "none", precision: str = "guarded", cond_threshold: float = 1e6,
                  timing: bool = False, tail_lanes: int = 0, cell_lanes: int = 0, radius: str = "plain",
-                 model=None, radius_factor: float = 1.1, cnn_pool: int = 0, projection: str = "faces") -> Options:
+                 model=None, radius_factor: float = 1.1, cnn_pool: int = 0, projection: str = "faces",
+                 order_key: Optional[int] = None) -> Options:
+    """Options of a map; ``order_key`` is the device address of the per-node key of
+    ``sort="given"``."""
     o = default_options()
+    o.order_key = order_key
     o.cnn_pool = int(cnn_pool)
     o.projection = _PROJ[projection]
     o.radius_mode = _RADIUS[radius]
@@ -269,16 +274,27 @@ def make_options(sort: str = "none", precision: str = "guarded", cond_threshold:
     return o
 
 
+def _order_key_ptr(order_key, ref):
+    """Device address of the per-node key of the given order (checked against ``ref``)."""
+    if order_key is None:
+        return None
+    _dev_tensor(order_key, "order_key")
+    if order_key.shape != ref.shape or order_key.device != ref.device:
+        raise ValueError("order_key must match ref in shape and device")
+    return order_key.data_ptr()
+
+
 def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
                dose_threshold: float = 0.1, local: bool = False, *, sort: str = "none",
                precision: str = "guarded", cond_threshold: float = 1e6, timing: bool = False,
                tail_lanes: int = 0, cell_lanes: int = 0, radius: str = "plain", model=None,
-               radius_factor: float = 1.1, cnn_pool: int = 0, projection: str = "faces", out=None,
-               ctx: Optional[Context] = None, stream=None):
+               radius_factor: float = 1.1, cnn_pool: int = 0, projection: str = "faces", order_key=None,
+               out=None, ctx: Optional[Context] = None, stream=None):
     """Gamma map of a dose pair on the GPU.  Returns (gamma tensor, GammaResult).
 
     ``ref``/``ev``: float32 device tensors of shape (ny, nx) or (nz, ny, nx); ``spacing``
     in mm in the same axis order.  gamma is -1 where a node is not evaluated.
+    ``order_key``: with ``sort="given"``, a float32 device tensor shaped like ``ref``.
     """
     torch = _torch()
     _dev_tensor(ref, "ref")
@@ -297,7 +313,7 @@ def gammax_map(ref, ev, spacing: Sequence[float], dd: float, dta: float,
     ctx = ctx or context(dev)
     p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
     o = make_options(sort, precision, cond_threshold, timing, tail_lanes, cell_lanes, radius, model,
-                     radius_factor, cnn_pool, projection)
+                     radius_factor, cnn_pool, projection, _order_key_ptr(order_key, ref))
     r = Result()
     s = stream if stream is not None else torch.cuda.current_stream(ref.device)
     with torch.cuda.device(ref.device):
@@ -329,8 +345,8 @@ def gammax_map_async(ref, ev, spacing: Sequence[float], dd: float, dta: float,
                      dose_threshold: float = 0.1, local: bool = False, *, sort: str = "none",
                      precision: str = "guarded", cond_threshold: float = 1e6, tail_lanes: int = 0,
                      cell_lanes: int = 0, radius: str = "plain", model=None, radius_factor: float = 1.1,
-                     cnn_pool: int = 0, projection: str = "faces", out=None, ctx: Optional[Context] = None,
-                     stream=None) -> MapTicket:
+                     cnn_pool: int = 0, projection: str = "faces", order_key=None, out=None,
+                     ctx: Optional[Context] = None, stream=None) -> MapTicket:
     """Queue a gamma map without waiting (``gammax_map_async``); the returned ticket's
     ``wait()`` gives the GammaResult.  The tensors are kept alive until then and must not
     be modified before it."""
@@ -351,14 +367,14 @@ def gammax_map_async(ref, ev, spacing: Sequence[float], dd: float, dta: float,
     ctx = ctx or context(dev)
     p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
     o = make_options(sort, precision, cond_threshold, False, tail_lanes, cell_lanes, radius, model,
-                     radius_factor, cnn_pool, projection)
+                     radius_factor, cnn_pool, projection, _order_key_ptr(order_key, ref))
     t = C.c_uint64(0)
     s = stream if stream is not None else torch.cuda.current_stream(ref.device)
     with torch.cuda.device(ref.device):
         st = _lib.gammax_map_async(ctx.handle, C.byref(p), C.byref(o), ref.data_ptr(), ev.data_ptr(),
                                    out.data_ptr(), C.byref(t), _vp(s.cuda_stream))
     ctx.check(st)
-    return MapTicket(ctx, t.value, out, (ref, ev, model))
+    return MapTicket(ctx, t.value, out, (ref, ev, model, order_key))
 
 
 def gamma_map(ref_dose, eval_dose, spacing: Sequence[float], dd: float, dta: float,

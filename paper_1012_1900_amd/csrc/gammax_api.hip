@@ -42,6 +42,7 @@ struct GraphKey {
     int32_t tail_min_lanes;
     int32_t cnn_pool;
     int32_t projection;
+    const float* order_key;
     uint64_t generation;   // bumped on every (re)allocation and table build
 };
 
@@ -265,8 +266,13 @@ gammax_status_t check_problem(gammax_ctx* c, const gammax_problem_t* p, int64_t*
 }
 
 gammax_status_t check_options(gammax_ctx* c, const gammax_options_t* o) {
-    if (o->sort_mode < GAMMAX_SORT_NONE || o->sort_mode > GAMMAX_SORT_PREDICTED)
+    if (o->sort_mode < GAMMAX_SORT_NONE || o->sort_mode > GAMMAX_SORT_GIVEN)
         return fail(c, GAMMAX_E_PARAM, "unknown sort_mode");
+    if (o->sort_mode == GAMMAX_SORT_GIVEN) {
+        if (!o->order_key) return fail(c, GAMMAX_E_NULL, "the given order needs order_key");
+        if (o->radius_mode != GAMMAX_RADIUS_PLAIN)
+            return fail(c, GAMMAX_E_PARAM, "the given order runs with the plain radius only");
+    }
     if (o->radius_mode != GAMMAX_RADIUS_PLAIN && o->radius_mode != GAMMAX_RADIUS_LEARNED)
         return fail(c, GAMMAX_E_PARAM, "unknown radius_mode");
     if (!(o->radius_factor >= 1.0) || !std::isfinite(o->radius_factor))
@@ -519,6 +525,20 @@ struct TailCnnHook {
     int blocks;
 };
 
+// The given order: the caller's key of every queued tail node, written where the network
+// writes its predictions in the predicted order.
+struct GivenKeyHook {
+    const uint32_t* nodes;
+    const uint32_t* count;
+    const float* given;
+    uint32_t* key;
+};
+
+hipError_t given_key_hook(void* user, hipStream_t s) {
+    const GivenKeyHook& h = *static_cast<const GivenKeyHook*>(user);
+    return launch_given_keys(h.nodes, h.count, h.given, h.key, s);
+}
+
 hipError_t tail_cnn_hook(void* user, hipStream_t s) {
     const TailCnnHook& h = *static_cast<const TailCnnHook*>(user);
     hipError_t e;
@@ -598,7 +618,9 @@ SearchArgs make_search_args(const gammax_problem_t* p, const gammax_options_t& o
     sa.k1 = k1;
     sa.r2_cap = r2_cap;
     const bool learned = uses_model(p, &opt);
-    sa.tail_key = opt.sort_mode == GAMMAX_SORT_BOUND ? 1 : ((opt.sort_mode == GAMMAX_SORT_PREDICTED && learned) ? 2 : 0);
+    sa.tail_key = opt.sort_mode == GAMMAX_SORT_BOUND
+                      ? 1
+                      : (((opt.sort_mode == GAMMAX_SORT_PREDICTED && learned) || opt.sort_mode == GAMMAX_SORT_GIVEN) ? 2 : 0);
     sa.yhat = learned ? yhat : nullptr;
     sa.spec_factor = (float)opt.radius_factor;
     sa.fb_list = work + W_FALLBACK * stride;
@@ -667,6 +689,15 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
         plan.after_zero = tail_cnn_hook;
         plan.after_zero_user = &hook;
     }
+    GivenKeyHook ghook{};
+    if (opt.sort_mode == GAMMAX_SORT_GIVEN) {
+        ghook.nodes = work_array(c, W_TAIL_NODE);
+        ghook.count = &c->d_sc->n_tail;
+        ghook.given = opt.order_key;
+        ghook.key = work_array(c, W_TAIL_KEY);
+        plan.after_zero = given_key_hook;
+        plan.after_zero_user = &ghook;
+    }
     if (timing) {
         HIPCHK(c, hipEventRecord(c->ev[4], s));
         plan.ev_shell_end = c->ev[5];
@@ -708,6 +739,7 @@ GraphKey key_of(gammax_ctx* c, const CallSetup& cs) {
     k.tail_min_lanes = tail_min_lanes(c);
     k.cnn_pool = cs.opt->cnn_pool;
     k.projection = cs.opt->projection;
+    k.order_key = cs.opt->sort_mode == GAMMAX_SORT_GIVEN ? cs.opt->order_key : nullptr;
     k.generation = c->generation;
     return k;
 }
@@ -1708,6 +1740,8 @@ gammax_status_t run_many(gammax_ctx_t* c, int32_t n, const gammax_problem_t* pro
     if (!probs || !refs || !evals || !gammas || !results)
         return fail(c, GAMMAX_E_NULL, "problems, dose, gamma and result arrays are required");
     if (opt && opt->timing) return fail(c, GAMMAX_E_PARAM, "timing is not available for gammax_map_many");
+    if (opt && opt->sort_mode == GAMMAX_SORT_GIVEN)
+        return fail(c, GAMMAX_E_PARAM, "the given order is for single maps (one key array per grid)");
     HIPCHK(c, hipSetDevice(c->device));
     if (!c->many) {
         ManyState* m = new (std::nothrow) ManyState();
@@ -1802,6 +1836,8 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
     gammax_status_t st = check_options(c, &opt);
     if (st != GAMMAX_OK) return st;
     if (opt.cnn_pool != 0) return fail(c, GAMMAX_E_PARAM, "cnn_pool is not available on the single-pipeline batch");
+    if (opt.sort_mode == GAMMAX_SORT_GIVEN)
+        return fail(c, GAMMAX_E_PARAM, "the given order is for single maps (one key array per grid)");
     std::vector<int64_t> nn(n);
     for (int i = 0; i < n; ++i) {
         if ((st = check_problem(c, &probs[i], &nn[i])) != GAMMAX_OK)

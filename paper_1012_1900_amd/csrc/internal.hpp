@@ -133,6 +133,10 @@ hipError_t sort_pairs_small(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, 
                             const uint32_t* n_dev, uint32_t* overflow, hipStream_t s);
 // The same rank sort of a list whose values are its positions 0..n-1: order[] receives the
 // positions in stable key order (one launch; the keys stay where they are).
+// Sort keys of the queued tail nodes from a caller's per-node key: key[i] = the bits of
+// max(given[nodes[i]], 0) (NaN as 0) for i < *count.
+hipError_t launch_given_keys(const uint32_t* nodes, const uint32_t* count, const float* given, uint32_t* key,
+                             hipStream_t s);
 hipError_t sort_order_small(const uint32_t* keys, uint32_t* order, const uint32_t* n_dev, uint32_t* overflow,
                             hipStream_t s);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,

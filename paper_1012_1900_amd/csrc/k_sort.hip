@@ -22,6 +22,18 @@ __device__ __forceinline__ int64_t count_of(int64_t n_max, const uint32_t* n_dev
     return n_dev ? (int64_t)*n_dev : n_max;
 }
 
+// Sort keys from a caller's per-node key (non-negative floats order as their bits).
+__global__ __launch_bounds__(SORT_THREADS) void k_given_keys(const uint32_t* __restrict__ nodes,
+                                                             const uint32_t* __restrict__ count,
+                                                             const float* __restrict__ given,
+                                                             uint32_t* __restrict__ key) {
+    const uint32_t n = *count;
+    for (uint32_t i = blockIdx.x * SORT_THREADS + threadIdx.x; i < n; i += gridDim.x * SORT_THREADS) {
+        const float v = given[nodes[i]];
+        key[i] = __float_as_uint(v > 0.0f ? v : 0.0f);   // NaN and negatives: 0
+    }
+}
+
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              int64_t n_max, const uint32_t* n_dev,
                                                              int shift, uint32_t* __restrict__ hist,
@@ -281,6 +293,12 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, 
         vi = vo;
         vo = tv;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_given_keys(const uint32_t* nodes, const uint32_t* count, const float* given, uint32_t* key,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_given_keys, dim3(512), dim3(SORT_THREADS), 0, s, nodes, count, given, key);
     return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ def test_options_defaults(abi):
     assert o.precision == abi.PREC_GUARDED
     assert o.cond_threshold == 1e6
     assert o.timing == 0 and o.tail_lanes == 0 and o.cell_lanes == 0 and list(o.reserved) == [0]
-    assert o.autotune == 0 and o.cnn_pool == 0 and o.projection == 0
+    assert o.autotune == 0 and o.cnn_pool == 0 and o.projection == 0 and o.order_key is None
     assert o.radius_mode == abi.RADIUS_PLAIN and not o.model and o.radius_factor == 1.1
 
 

@@ -110,6 +110,45 @@ def test_sort_modes_and_determinism(gx, small3d):
     assert ra.n_tail > 0 and ra.n_tail == rb.n_tail
 
 
+@pytest.mark.parametrize("kind", ["3d", "2d"])
+def test_given_order(gx, small3d, kind):
+    """A caller's key orders the walk past the key-0 cells; gamma, counts and the tail are
+    those of the unsorted walk whatever the key: the true gamma, noise, or negative and NaN
+    keys (which count as 0)."""
+    import torch
+    p = small3d if kind == "3d" else make_config_pair("2d_64x64_1mm", 5)
+    ref, ev = dev(p.ref), dev(p.eval)
+    crit = (0.02, 2.0) if kind == "3d" else (0.01, 1.0)
+    base, rb = gx.gammax_map(ref, ev, p.spacing, *crit, 0.1, sort="none")
+    assert rb.n_tail > 0
+    gen = torch.Generator(device=ref.device).manual_seed(3)
+    noise = torch.rand(ref.shape, generator=gen, device=ref.device)
+    odd = noise - 0.5
+    odd.view(-1)[::7] = float("nan")
+    for key in (base.clone(), noise, odd):
+        g, r = gx.gammax_map(ref, ev, p.spacing, *crit, 0.1, sort="given", order_key=key)
+        assert np.array_equal(host(g), host(base))
+        assert (r.n_cells, r.n_pass, r.n_tail, r.n_guarded) == (rb.n_cells, rb.n_pass, rb.n_tail, rb.n_guarded)
+    # queued, twice with the same key (the second replays the captured map)
+    for _ in range(2):
+        t = gx.gammax_map_async(ref, ev, p.spacing, *crit, 0.1, sort="given", order_key=noise)
+        r = t.wait()
+        assert np.array_equal(host(t.gamma), host(base)) and r.n_cells == rb.n_cells
+
+
+def test_given_order_refusals(gx, small3d):
+    p = small3d
+    ref, ev = dev(p.ref), dev(p.eval)
+    with pytest.raises(gx.GammaxError):
+        gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, sort="given")
+    with pytest.raises(ValueError):
+        gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, sort="given", order_key=ref[:1].contiguous())
+    with pytest.raises(gx.GammaxError):
+        gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, sort="given", order_key=ref, radius="learned")
+    with pytest.raises(gx.GammaxError):
+        gx.gammax_map_many([dict(ref=ref, ev=ev, spacing=p.spacing, dd=0.03, dta=3.0)], sort="given")
+
+
 def test_full_c1_bench_configuration(gx):
     """The benchmark workload, every node compared (the oracle takes about a second)."""
     p = make_config_pair("3d_128x128x96_2.5mm", 100)
