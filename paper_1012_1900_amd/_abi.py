@@ -532,6 +532,17 @@ class Model:
         self.check(_lib.gammax_model_get_params(self.handle, None, out.ctypes.data))
         return out
 
+    def save(self, path: str):
+        """Store the parameters as one flat float32 ``.npy`` array (the trainer's format)."""
+        import numpy as np
+        np.save(path, self.params(), allow_pickle=False)
+
+    @classmethod
+    def load(cls, path: str, device: int = 0) -> "Model":
+        """A model from a ``.npy`` parameter file written by :meth:`save` or the trainer."""
+        import numpy as np
+        return cls(np.load(path, allow_pickle=False), device)
+
     def forward(self, feats):
         """y for a batch of feature crops: int16/uint16 tensor (B, c0+8, c1+8, c2+8, 2)."""
         torch = _torch()

@@ -235,3 +235,13 @@ def test_predict_pooled_at_listed_nodes(gx):
             for xi in axes[2][:2]:
                 bound = np.maximum(bound, A[zi, yi, xi])
     assert np.all(np.abs(y - want) <= 4 * 2.0 ** -8 * bound + 1e-5)
+
+
+def test_model_save_load(gx, tmp_path):
+    """Parameters round-trip through a .npy file bit for bit."""
+    m = gx.Model(_theta(11))
+    path = str(tmp_path / "theta.npy")
+    m.save(path)
+    m2 = gx.Model.load(path)
+    assert np.array_equal(m.params(), m2.params())
+    assert np.array_equal(m2.params(), np.asarray(_theta(11), dtype=np.float32).ravel())
