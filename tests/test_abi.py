@@ -57,6 +57,12 @@ def test_options_defaults(abi):
     assert o.radius_mode == abi.RADIUS_PLAIN and not o.model and o.radius_factor == 1.1
 
 
+def test_options_given_order(abi):
+    o = abi.make_options(sort="given", order_key=0x7f0000001000)
+    assert o.sort_mode == abi.SORT_GIVEN == 4 and o.order_key == 0x7f0000001000
+    assert abi.make_options(sort="dd").order_key is None
+
+
 def test_status_strings(abi):
     for st in range(0, -9, -1):
         s = abi.status_string(st)
