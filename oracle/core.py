@@ -56,21 +56,26 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def configure(lib):
+    """Declare the C signatures of the oracle's entry points on a loaded library (this
+    oracle's, or a variant compiled from an edited copy of its source by a test)."""
+    lib.oracle_gamma.restype = C.c_int
+    lib.oracle_gamma.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(_Stats), C.c_int]
+    lib.oracle_gamma_grids.restype = C.c_int
+    lib.oracle_gamma_grids.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.POINTER(_Stats), C.c_int]
+    lib.oracle_simplex_dist.restype = C.c_double
+    lib.oracle_simplex_dist.argtypes = [C.c_int, C.c_int, C.c_void_p]
+    lib.oracle_max_threads.restype = C.c_int
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
         build()
-        lib = C.CDLL(_LIB)
-        lib.oracle_gamma.restype = C.c_int
-        lib.oracle_gamma.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_void_p,
-                                     C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(_Stats), C.c_int]
-        lib.oracle_gamma_grids.restype = C.c_int
-        lib.oracle_gamma_grids.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                           C.c_void_p, C.c_void_p, C.POINTER(_Stats), C.c_int]
-        lib.oracle_simplex_dist.restype = C.c_double
-        lib.oracle_simplex_dist.argtypes = [C.c_int, C.c_int, C.c_void_p]
-        lib.oracle_max_threads.restype = C.c_int
-        _lib = lib
+        _lib = configure(C.CDLL(_LIB))
     return _lib
 
 
