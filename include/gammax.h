@@ -45,7 +45,9 @@ typedef enum {
     GAMMAX_E_NOMEM = -5,      /* device or pinned host allocation failed */
     GAMMAX_E_DEVICE = -6,     /* a HIP runtime call failed; see gammax_last_error() */
     GAMMAX_E_RADIUS = -7,     /* the cell table for this search radius exceeds the table cap */
-    GAMMAX_E_DOSE = -8        /* global normalisation with no positive reference dose */
+    GAMMAX_E_DOSE = -8,       /* global normalisation with no positive reference dose */
+    GAMMAX_E_MODEL = -9       /* a model file that cannot be read or written, or is not a
+                                 model of this network (gammax_model_save / _load) */
 } gammax_status_t;
 
 typedef enum { GAMMAX_GLOBAL = 0, GAMMAX_LOCAL = 1 } gammax_norm_t;
@@ -340,6 +342,24 @@ gammax_status_t gammax_model_get_params(gammax_model_t *model, float *params, fl
 
 /* Detail of the last failure of a model call; never NULL. */
 const char *gammax_model_last_error(const gammax_model_t *model);
+
+/*
+ * Checkpoint of a model: its FP32 parameters and the Adam state of its training steps, so
+ * that training resumes where it stopped (gammax_model_train_step continues the bias
+ * correction from the stored step count).  File layout: one line of JSON ending in '\n',
+ *     {"format": "gammax-model", "version": 1, "nparam": 15169, "adam_step": S,
+ *      "arrays": ["params", "adam_m", "adam_v"], "dtype": "float32-le"}
+ * then the three arrays of GAMMAX_MODEL_NPARAM little-endian float32 each, in that order
+ * (parameters in the flat layout above, then Adam's first and second moment estimates).
+ * save: writes `path` (replaced if it exists); synchronises the model's device.
+ *   GAMMAX_E_MODEL when the file cannot be written.
+ * load: creates a model on HIP device `device` from such a file (*model receives it, or
+ *   NULL on failure).  GAMMAX_E_MODEL when the file cannot be read, its header is not this
+ *   format and version or holds another parameter count, the data is short or too long, or
+ *   a stored value is not finite.
+ */
+gammax_status_t gammax_model_save(const gammax_model_t *model, const char *path);
+gammax_status_t gammax_model_load(int device, const char *path, gammax_model_t **model);
 
 /*
  * Input features of one dose pair on the grid padded by 4 nodes: (nz+8) x (ny+8) x (nx+8)

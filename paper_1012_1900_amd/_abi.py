@@ -38,6 +38,7 @@ E_NOMEM = -5
 E_DEVICE = -6
 E_RADIUS = -7
 E_DOSE = -8
+E_MODEL = -9
 
 GLOBAL, LOCAL = 0, 1
 SORT_NONE, SORT_DD, SORT_BOUND, SORT_PREDICTED, SORT_GIVEN = 0, 1, 2, 3, 4
@@ -475,6 +476,10 @@ _lib.gammax_model_get_params.restype = C.c_int
 _lib.gammax_model_get_params.argtypes = [_vp, _vp, _vp]
 _lib.gammax_model_last_error.restype = C.c_char_p
 _lib.gammax_model_last_error.argtypes = [_vp]
+_lib.gammax_model_save.restype = C.c_int
+_lib.gammax_model_save.argtypes = [_vp, C.c_char_p]
+_lib.gammax_model_load.restype = C.c_int
+_lib.gammax_model_load.argtypes = [C.c_int, C.c_char_p, C.POINTER(_vp)]
 _lib.gammax_model_features.restype = C.c_int
 _lib.gammax_model_features.argtypes = [_vp, C.POINTER(Problem), _vp, _vp, _vp, _vp]
 _lib.gammax_model_predict.restype = C.c_int
@@ -533,15 +538,30 @@ class Model:
         return out
 
     def save(self, path: str):
-        """Store the parameters as one flat float32 ``.npy`` array (the trainer's format)."""
+        """Checkpoint: the parameters and the Adam state (``gammax_model_save``), so that
+        training resumes where it stopped."""
+        self.check(_lib.gammax_model_save(self.handle, os.fsencode(path)))
+
+    def save_params(self, path: str):
+        """Only the parameters, as one flat float32 ``.npy`` array (the shipped weights)."""
         import numpy as np
         np.save(path, self.params(), allow_pickle=False)
 
     @classmethod
     def load(cls, path: str, device: int = 0) -> "Model":
-        """A model from a ``.npy`` parameter file written by :meth:`save` or the trainer."""
+        """A model from a checkpoint written by :meth:`save` (``gammax_model_load``: parameters
+        and Adam state), or from a ``.npy`` parameter file (parameters only, fresh Adam state)."""
         import numpy as np
-        return cls(np.load(path, allow_pickle=False), device)
+        if str(path).endswith(".npy"):
+            return cls(np.load(path, allow_pickle=False), device)
+        h = _vp()
+        st = _lib.gammax_model_load(int(device), os.fsencode(path), C.byref(h))
+        if st != 0:
+            raise GammaxError(st, f"cannot load a model from {path}")
+        m = cls.__new__(cls)
+        m.handle = h
+        m.device = int(device)
+        return m
 
     def forward(self, feats):
         """y for a batch of feature crops: int16/uint16 tensor (B, c0+8, c1+8, c2+8, 2)."""

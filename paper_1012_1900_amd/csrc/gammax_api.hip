@@ -170,6 +170,7 @@ const char* kStatusText[] = {
     "HIP runtime error",
     "search radius needs a larger cell table than the library allows",
     "global normalisation needs a positive reference dose",
+    "model file cannot be read or written, or is not a model of this network",
 };
 
 gammax_status_t fail(gammax_ctx* c, gammax_status_t st, const std::string& why) {

@@ -1,8 +1,11 @@
 // C ABI of the learned search radius: the model object, its forward pass over volumes,
 // and one training step (forward, masked MSE on log(gamma + 0.01), backward, Adam).
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "gammax.h"
 #include "model.hpp"
@@ -175,6 +178,83 @@ gammax_status_t gammax_model_get_params(gammax_model_t* m, float* params, float*
     MCHK(m, hipDeviceSynchronize());
     if (params) MCHK(m, hipMemcpy(params, m->theta, sizeof(float) * CNN_NPARAM, hipMemcpyDeviceToHost));
     if (grad) MCHK(m, hipMemcpy(grad, m->grad, sizeof(float) * CNN_NPARAM, hipMemcpyDeviceToHost));
+    return GAMMAX_OK;
+}
+
+// Checkpoints: a one-line JSON header, then the parameters and Adam's two moment arrays as
+// little-endian float32 (the host byte order of the x86-64 hosts of these GPUs).
+static const char* kModelFormat = "gammax-model";
+static const int kModelVersion = 1;
+
+gammax_status_t gammax_model_save(const gammax_model_t* mc, const char* path) {
+    gammax_model* m = const_cast<gammax_model*>(mc);
+    if (!m) return GAMMAX_E_NULL;
+    if (!path) return mfail(m, GAMMAX_E_NULL, "path is required");
+    std::vector<float> buf((size_t)3 * CNN_NPARAM);
+    MCHK(m, hipSetDevice(m->device));
+    MCHK(m, hipDeviceSynchronize());
+    MCHK(m, hipMemcpy(buf.data(), m->theta, sizeof(float) * CNN_NPARAM, hipMemcpyDeviceToHost));
+    MCHK(m, hipMemcpy(buf.data() + CNN_NPARAM, m->adam_m, sizeof(float) * CNN_NPARAM, hipMemcpyDeviceToHost));
+    MCHK(m, hipMemcpy(buf.data() + 2 * CNN_NPARAM, m->adam_v, sizeof(float) * CNN_NPARAM, hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return mfail(m, GAMMAX_E_MODEL, std::string("cannot open ") + path + " for writing");
+    const int hn = std::fprintf(f,
+                                "{\"format\": \"%s\", \"version\": %d, \"nparam\": %d, \"adam_step\": %lld, "
+                                "\"arrays\": [\"params\", \"adam_m\", \"adam_v\"], \"dtype\": \"float32-le\"}\n",
+                                kModelFormat, kModelVersion, CNN_NPARAM, (long long)m->step);
+    const size_t w = std::fwrite(buf.data(), sizeof(float), buf.size(), f);
+    const int cl = std::fclose(f);
+    if (hn <= 0 || w != buf.size() || cl != 0) return mfail(m, GAMMAX_E_MODEL, std::string("cannot write ") + path);
+    return GAMMAX_OK;
+}
+
+namespace {
+
+// The integer after "key": in a header line (false when the key is missing).
+bool header_int(const std::string& h, const char* key, long long* out) {
+    const std::string k = std::string("\"") + key + "\":";
+    const size_t at = h.find(k);
+    if (at == std::string::npos) return false;
+    return std::sscanf(h.c_str() + at + k.size(), " %lld", out) == 1;
+}
+
+}  // namespace
+
+gammax_status_t gammax_model_load(int device, const char* path, gammax_model_t** out) {
+    if (!out) return GAMMAX_E_NULL;
+    *out = nullptr;
+    if (!path) return GAMMAX_E_NULL;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return GAMMAX_E_MODEL;
+    std::string head;
+    for (int c; (c = std::fgetc(f)) != EOF && c != '\n';) {
+        head.push_back((char)c);
+        if (head.size() > 4096) break;
+    }
+    long long ver = 0, np = 0, step = 0;
+    const bool ok_head = head.find(std::string("\"format\": \"") + kModelFormat + "\"") != std::string::npos &&
+                         header_int(head, "version", &ver) && ver == kModelVersion && header_int(head, "nparam", &np) &&
+                         np == CNN_NPARAM && header_int(head, "adam_step", &step) && step >= 0 &&
+                         head.find("\"float32-le\"") != std::string::npos;
+    std::vector<float> buf((size_t)3 * CNN_NPARAM);
+    const size_t got = ok_head ? std::fread(buf.data(), sizeof(float), buf.size(), f) : 0;
+    const bool at_end = ok_head && std::fgetc(f) == EOF;
+    std::fclose(f);
+    if (!ok_head || got != buf.size() || !at_end) return GAMMAX_E_MODEL;
+    for (float v : buf)
+        if (!std::isfinite(v)) return GAMMAX_E_MODEL;
+    gammax_model* m = nullptr;
+    gammax_status_t st = gammax_model_create(device, buf.data(), &m);
+    if (st != GAMMAX_OK) return st;
+    if (hipMemcpy(m->adam_m, buf.data() + CNN_NPARAM, sizeof(float) * CNN_NPARAM, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(m->adam_v, buf.data() + 2 * CNN_NPARAM, sizeof(float) * CNN_NPARAM, hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        gammax_model_destroy(m);
+        return GAMMAX_E_DEVICE;
+    }
+    m->step = step;
+    *out = m;
     return GAMMAX_OK;
 }
 

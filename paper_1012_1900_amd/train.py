@@ -78,6 +78,12 @@ def main():
     ap.add_argument("--dd", type=float, default=0.03)
     ap.add_argument("--dta", type=float, default=3.0)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--checkpoint", default=None,
+                    help="write a checkpoint (parameters and Adam state) here every --checkpoint-every "
+                         "steps and at the end")
+    ap.add_argument("--checkpoint-every", type=int, default=1000)
+    ap.add_argument("--resume", default=None,
+                    help="continue the training from this checkpoint: its parameters, Adam state and step")
     args = ap.parse_args()
 
     # worker processes first, before anything touches the GPU
@@ -121,20 +127,32 @@ def main():
     torch.cuda.synchronize()
     t_data = time.time() - t0
 
-    model = gx.Model(init_params(args.seed + 1))
+    start = 0
+    if args.resume:
+        model = gx.Model.load(args.resume)
+        with open(args.resume, "rb") as f:
+            start = int(json.loads(f.readline())["adam_step"])
+        log(f"resumed from {args.resume} at step {start}")
+        # the batches after a resume come from their own stream of the same seed
+        rng = np.random.default_rng([args.seed, start])
+    else:
+        model = gx.Model(init_params(args.seed + 1))
     t0 = time.time()
     losses = []
-    for step in range(args.steps):
+    for step in range(start, args.steps):
         lr = args.lr * 0.5 * (1.0 + np.cos(np.pi * step / args.steps))   # cosine decay
         idx = torch.from_numpy(rng.integers(0, n_crops, size=args.batch)).to(dev)
         loss = model.train_step(feats_all[idx].contiguous(), labels_all[idx].contiguous(), lr=lr)
         losses.append(loss)
         if (step + 1) % 1000 == 0:
             log(f"step {step + 1}: loss {np.mean(losses[-1000:]):.4f} lr {lr:.2e} ({time.time() - t0:.1f} s)")
+        if args.checkpoint and (step + 1) % args.checkpoint_every == 0:
+            model.save(args.checkpoint)
     t_train = time.time() - t0
-    params = model.params()
+    if args.checkpoint:
+        model.save(args.checkpoint)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-    np.save(args.out, params)
+    model.save_params(args.out)
 
     # held-out report
     del feats_all, labels_all
@@ -171,7 +189,8 @@ def main():
         "crops_per_pair": args.crops_per_pair, "crop": args.crop, "batch": args.batch,
         "high_gamma": args.high_gamma,
         "steps": args.steps, "lr": args.lr, "seed": args.seed,
-        "final_train_loss": float(np.mean(losses[-250:])),
+        "final_train_loss": float(np.mean(losses[-250:])) if losses else None,
+        "resumed_from_step": start,
         "data_seconds": round(t_data, 1), "train_seconds": round(t_train, 1),
         "heldout": {
             "rmse_log_gamma": float(np.mean(rmse)),

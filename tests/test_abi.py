@@ -37,7 +37,8 @@ def test_header_declares_the_boundary():
                  "gammax_model_features", "gammax_model_predict", "gammax_model_forward",
                  "gammax_model_train_step", "gammax_model_last_error", "gammax_model_predict_nodes",
                  "gammax_batch", "gammax_tune_save", "gammax_tune_load", "gammax_map_async",
-                 "gammax_map_wait", "gammax_map_many", "gammax_model_predict_nodes_pooled", "gammax_map_grids"]:
+                 "gammax_map_wait", "gammax_map_many", "gammax_model_predict_nodes_pooled", "gammax_map_grids",
+                 "gammax_model_save", "gammax_model_load"]:
         assert must in names
 
 
@@ -64,7 +65,7 @@ def test_options_given_order(abi):
 
 
 def test_status_strings(abi):
-    for st in range(0, -9, -1):
+    for st in range(0, -10, -1):
         s = abi.status_string(st)
         assert s and s != "unknown status"
     assert abi.status_string(-99) == "unknown status"
@@ -127,6 +128,38 @@ def test_null_model(abi):
     assert lib.gammax_model_predict(None, None, None, None, None, None, None) == abi.E_NULL
     assert lib.gammax_model_features(None, None, None, None, None, None) == abi.E_NULL
     assert lib.gammax_model_last_error(None) == b""
+    assert lib.gammax_model_save(None, b"/tmp/x") == abi.E_NULL
+    assert lib.gammax_model_load(0, None, C.byref(h)) == abi.E_NULL
+    assert lib.gammax_model_load(0, b"/tmp/x", None) == abi.E_NULL
+
+
+def test_model_file_checks_before_any_device_call(abi, tmp_path):
+    """gammax_model_load refuses a missing file, another format or version, another
+    parameter count, short or long data and non-finite values (GAMMAX_E_MODEL) before it
+    touches a device."""
+    import numpy as np
+    lib = abi.raw_library()
+    n = abi.MODEL_NPARAM
+
+    def head(**kw):
+        d = {"format": "gammax-model", "version": 1, "nparam": n, "adam_step": 4}
+        d.update(kw)
+        return ("{" + ", ".join(f'"{k}": ' + (f'"{v}"' if isinstance(v, str) else str(v)) for k, v in d.items())
+                + ', "arrays": ["params", "adam_m", "adam_v"], "dtype": "float32-le"}\n').encode()
+
+    data = np.zeros(3 * n, dtype="<f4").tobytes()
+    nan = np.zeros(3 * n, dtype="<f4")
+    nan[n + 5] = np.nan
+    cases = {"missing": None, "format": head(format="other") + data, "version": head(version=2) + data,
+             "nparam": head(nparam=n - 1) + data, "short": head() + data[:-4], "long": head() + data + b"\0",
+             "nonfinite": head() + nan.tobytes(), "step": head(adam_step=-1) + data}
+    for name, raw in cases.items():
+        path = tmp_path / f"{name}.ckpt"
+        if raw is not None:
+            path.write_bytes(raw)
+        h = C.c_void_p()
+        assert lib.gammax_model_load(0, str(path).encode(), C.byref(h)) == abi.E_MODEL, name
+        assert not h.value
 
 
 def test_struct_layouts_match_the_header(abi, tmp_path):

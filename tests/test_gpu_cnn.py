@@ -11,6 +11,8 @@ error comes from FP32 summation and the same rare one-ulp flips; the tests bound
 relative L2 error per layer by 2^-6 (a dropped tap or channel of one layer moves it by
 more than 1/27) and every element by 5 % of the layer's largest gradient.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -241,7 +243,48 @@ def test_model_save_load(gx, tmp_path):
     """Parameters round-trip through a .npy file bit for bit."""
     m = gx.Model(_theta(11))
     path = str(tmp_path / "theta.npy")
-    m.save(path)
+    m.save_params(path)
     m2 = gx.Model.load(path)
     assert np.array_equal(m.params(), m2.params())
     assert np.array_equal(m2.params(), np.asarray(_theta(11), dtype=np.float32).ravel())
+
+
+def test_checkpoint_resumes_training(gx, tmp_path):
+    """gammax_model_save / _load keep the parameters and the Adam state: a model loaded after
+    three steps takes the next two steps exactly as the original does (same losses, same
+    parameters), while a model given only the parameters (fresh Adam state) does not."""
+    crop = (8, 8, 16)
+    m = gx.Model(_theta(21).astype(np.float32))
+    batches = [(_feat_tensor(_random_crops(30 + k, 3, crop)), dev(_labels(40 + k, 3, crop))) for k in range(5)]
+    for f, lab in batches[:3]:
+        m.train_step(f, lab, lr=2e-3)
+    path = str(tmp_path / "model.ckpt")
+    m.save(path)
+    head = open(path, "rb").readline().decode()
+    assert '"format": "gammax-model"' in head and '"adam_step": 3' in head
+    assert os.path.getsize(path) == len(head.encode()) + 3 * 4 * gx.MODEL_NPARAM
+    m2 = gx.Model.load(path)
+    assert np.array_equal(m.params(), m2.params())
+    fresh = gx.Model(m.params())
+    for f, lab in batches[3:]:
+        a, b, c = m.train_step(f, lab, lr=2e-3), m2.train_step(f, lab, lr=2e-3), fresh.train_step(f, lab, lr=2e-3)
+        assert a == b
+    assert np.array_equal(m.params(), m2.params())
+    assert not np.array_equal(m.params(), fresh.params())
+
+
+def test_checkpoint_rejects_other_files(gx, tmp_path):
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(b'{"format": "gammax-model", "version": 1, "nparam": 7, "adam_step": 0}\n' + b"\0" * 84)
+    with pytest.raises(gx.GammaxError) as e:
+        gx.Model.load(str(bad))
+    assert e.value.status == -9
+    m = gx.Model(_theta(3))
+    good = str(tmp_path / "m.ckpt")
+    m.save(good)
+    raw = open(good, "rb").read()
+    (tmp_path / "short.ckpt").write_bytes(raw[:-4])
+    with pytest.raises(gx.GammaxError):
+        gx.Model.load(str(tmp_path / "short.ckpt"))
+    with pytest.raises(gx.GammaxError):
+        m.save(str(tmp_path / "no_such_dir" / "m.ckpt"))
