@@ -28,6 +28,11 @@ METRIC = "ref voxels/sec, 3D 3%/3mm: plain vs learned-radius at |Δγ|≤1e-5; %
 # add/mul/rcp = 1, compares and min = 0).  2D: 4 corners, 5 steps, 1 vertex, 3 edges,
 # 2 triangles.
 FLOP_PER_CELL = {3: 392, 2: 82}
+# The per-cell work of the reference formulation (every face of the Kuhn lattice projected
+# with its own normal equations: 6 tetrahedra with a 3x3 Gram solve and the condition check,
+# 12 triangles, 7 edges, 1 vertex), fixed before any tuning; the roofline fraction is quoted
+# on it, with the closed-form count beside it.
+FLOP_PER_CELL_REFERENCE = {3: 1100, 2: 150}
 PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (packed)
 PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 
@@ -81,6 +86,43 @@ def traffic_bytes(workload, kernel_default):
     return t["bytes"]
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def accuracy(g, o):
+    """Error of a GPU gamma map (device tensor) against the FP64 oracle's: the largest
+    |dgamma| over the masked nodes, the nodes beyond 1e-5 + 1e-5 gamma, mask agreement, and
+    the pass counts (outside the 1e-5 band around gamma = 1, and that band's size)."""
+    import numpy as np
+    gh = g.detach().cpu().numpy().astype(np.float64).ravel()
+    go = o.gamma.ravel()
+    m = go >= 0
+    same_mask = bool(np.array_equal(m, gh >= 0))
+    err = np.abs(gh[m] - go[m])
+    beyond = int((err > 1e-5 + 1e-5 * go[m]).sum())
+    band = np.abs(go - 1.0) <= 1e-5
+    outside = m & ~band
+    pass_diff = int(((gh[outside] <= 1.0) != (go[outside] <= 1.0)).sum())
+    return {"max_abs_dgamma": float(err.max()) if err.size else 0.0, "n_beyond_tol": beyond,
+            "same_mask": same_mask, "n_pass_gpu": int((gh[m] <= 1.0).sum()), "n_pass_oracle": int(o.n_pass),
+            "pass_decisions_differ_outside_band": pass_diff, "n_borderline_oracle": int(band[m].sum()),
+            "ok": bool(same_mask and beyond == 0 and pass_diff == 0)}
+
+
+def oracle_gamma(pair, dd, dta):
+    import oracle
+    oracle.build()
+    return oracle.gamma(pair.ref, pair.eval, pair.spacing, dd, dta, 0.1)
+
+
 def cpu_baseline(pair, dd, dta, reps, seconds):
     """The FP64 oracle as it stands, on every host core, over the whole workload, repeated
     until at least `seconds` of CPU time have passed (and at least `reps` times); the rate is
@@ -97,6 +139,8 @@ def cpu_baseline(pair, dd, dta, reps, seconds):
         "value": n * o.n_evaluated / total,
         "unit": "ref voxels/s",
         "cores": oracle.max_threads(),
+        "cpu_count": os.cpu_count(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": f"whole workload ({o.n_evaluated} masked nodes, {o.cells_visited} cells) "
                   f"{n} times, {total:.1f} s in all, mean rate",
@@ -415,6 +459,7 @@ def main():
                     help="key-0 pass: every owned face without branches, or Ju et al.'s recursion")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-radius leg")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 256x256x192 leg")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1012_1900_amd", "weights",
                                                       "cnn_3d_2.5mm_3pct3mm.npy"))
     ap.add_argument("--cpu-reps", type=int, default=2, help="fewest oracle repetitions")
@@ -469,50 +514,98 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def leg(extra):
-        """W warm-up maps; K timed maps queued back to back (gammax_map_async: graph replays
-        whose host work overlaps the GPU's, every result collected inside the timed region);
-        K synchronous maps (gammax_map: one host round trip each); then K maps with HIP
-        events per phase."""
+    def leg(p, r_dev, e_dev, o_dev, extra, steps):
+        """W warm-up maps; `steps` timed maps queued back to back (gammax_map_async: graph
+        replays whose host work overlaps the GPU's, every result collected inside the timed
+        region); `steps` synchronous maps (gammax_map: one host round trip each); then
+        `steps` maps with HIP events per phase.  Returns (seconds per queued map, seconds per
+        synchronous map, the last queued map's result, the phase results)."""
         kw = dict(sort=args.sort, precision=args.precision, tail_lanes=args.tail_lanes,
-                  cell_lanes=args.cell_lanes, projection=args.projection, out=out)
+                  cell_lanes=args.cell_lanes, projection=args.projection, out=o_dev)
         kw.update(extra)
         for _ in range(args.warmup):
-            gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, **kw)
+            gx.gammax_map(r_dev, e_dev, p.spacing, args.dd, args.dta, 0.1, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         queue = collections.deque()
         results = []
-        for _ in range(args.steps):
+        for _ in range(steps):
             if len(queue) == gx.ASYNC_SLOTS:
                 results.append(queue.popleft().wait())
-            queue.append(gx.gammax_map_async(ref, ev, pair.spacing, args.dd, args.dta, 0.1, **kw))
+            queue.append(gx.gammax_map_async(r_dev, e_dev, p.spacing, args.dd, args.dta, 0.1, **kw))
         while queue:
             results.append(queue.popleft().wait())
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        r_last = results[-1]
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, **kw)
+        for _ in range(steps):
+            gx.gammax_map(r_dev, e_dev, p.spacing, args.dd, args.dta, 0.1, **kw)
         torch.cuda.synchronize()
-        leg.sync_sec = (time.perf_counter() - t0) / args.steps
+        sync = (time.perf_counter() - t0) / steps
         phases = []
-        for _ in range(args.steps):
-            _, r = gx.gammax_map(ref, ev, pair.spacing, args.dd, args.dta, 0.1, timing=True, **kw)
+        for _ in range(steps):
+            _, r = gx.gammax_map(r_dev, e_dev, p.spacing, args.dd, args.dta, 0.1, timing=True, **kw)
             phases.append(r)
         torch.cuda.synchronize()
-        return wall / args.steps, r_last, phases
+        return wall / steps, sync, results[-1], phases
+
+    def mean(f, ph):
+        return float(np.mean([getattr(q, f) for q in ph]))
+
+    model = None
+    if nd == 3 and not args.no_learned and os.path.exists(args.weights):
+        model = gx.Model(np.load(args.weights, allow_pickle=False))
+
+    def learned_leg(p, r_dev, e_dev, o_dev, g_plain, sec_plain, steps):
+        """The learned radius on the same pair: speculative walk inside 1.1 gamma_hat, the
+        tail ordered by the prediction (the network's inference inside the timed map)."""
+        # the network was trained on a 2.5 mm grid: a grid at half that spacing feeds it the
+        # pair average-pooled 2x2x2 and interpolates its prediction back
+        cnn_pool = 2 if all(abs(2.0 * h - TRAIN_SPACING_MM) < 1e-9 for h in p.spacing) else 0
+        log(f"learned radius (cnn_pool {cnn_pool})")
+        lsec, lsync, lr_last, lph = leg(p, r_dev, e_dev, o_dev,
+                                        dict(radius="learned", sort="predicted", model=model, cnn_pool=cnn_pool),
+                                        steps)
+        ms_cnn = mean("ms_cnn", lph)
+        # algorithmic MACs of the network at one tail node, from its 9^3 patch: layer l
+        # produces (7 - 2 l)^3 outputs of its per-output MACs
+        macs_node = sum((7 - 2 * l) ** 3 * m
+                        for l, m in enumerate((2 * 16 * 27, 16 * 16 * 27, 16 * 16 * 27, 16 * 27)))
+        macs = macs_node * int(lr_last.n_tail)
+        if cnn_pool:
+            # pooled input: the whole coarse grid, 15,120 MACs per coarse node
+            coarse = int(np.prod([(n + 1) // 2 for n in p.ref.shape]))
+            macs = coarse * sum(m for m in (2 * 16 * 27, 16 * 16 * 27, 16 * 16 * 27, 16 * 27))
+        cnn_tflops = 2 * macs / (ms_cnn * 1e-3) / 1e12
+        res = {
+            "value": round(lr_last.n_evaluated / lsec, 1),
+            "ms_per_step": round(1e3 * lsec, 4),
+            "ms_per_step_sync": round(1e3 * lsync, 4),
+            "speedup_vs_plain": round(sec_plain / lsec, 3),
+            "n_tail": int(lr_last.n_tail),
+            "n_fallback": int(lr_last.n_fallback),
+            "identical_to_plain": bool(torch.equal(o_dev, g_plain)),
+            "phases_ms": {k: round(mean(k, lph), 4) for k in ("ms_prep", "ms_cnn", "ms_search", "ms_sort",
+                                                              "ms_tail", "ms_guard")},
+            "weights": os.path.relpath(args.weights, ROOT),
+            "cnn_pool": cnn_pool,
+            "cnn_roofline": {"bound": "mfma", "achieved": round(cnn_tflops, 2), "peak": PEAK_BF16_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(cnn_tflops / PEAK_BF16_TFLOPS, 4),
+                             "algorithmic_flop_per_launch": int(2 * macs),
+                             "flop_per_tail_node": None if cnn_pool else int(2 * macs_node),
+                             "avg_launch_ms": round(ms_cnn, 5)},
+        }
+        log(f"learned: {res['ms_per_step']} ms/step, {res['n_fallback']}/{res['n_tail']} fallbacks")
+        return res
 
     log(f"plain search: warmup {args.warmup}, timing {args.steps} steps")
-    sec, r_last, phases = leg({})
-    sync_ms = 1e3 * leg.sync_sec
+    sec, sync_sec, r_last, phases = leg(pair, ref, ev, out, {}, args.steps)
+    sync_ms = 1e3 * sync_sec
     g_plain = out.clone()
     ms_per_step = 1e3 * sec
     M = r_last.n_evaluated
     value = M / sec
-    mean = lambda f, ph=phases: float(np.mean([getattr(p, f) for p in ph]))  # noqa: E731
-    ms_search = mean("ms_search")
+    ms_search = mean("ms_search", phases)
     log(f"{M} nodes, {ms_per_step:.3f} ms/step, search {ms_search:.4f} ms")
 
     # the same map many times at once (gammax_map_many: a context per copy, the maps on four
@@ -541,68 +634,77 @@ def main():
         log(f"concurrent: {1e3 * csec:.4f} ms/map over {nc} maps per call")
         del mctx
 
-    # the learned radius on the same pair: speculative walk inside 1.1 gamma_hat, tail
-    # ordered by the prediction (the network's inference inside the timed map)
     learned = None
-    if nd == 3 and not args.no_learned and os.path.exists(args.weights):
-        model = gx.Model(np.load(args.weights, allow_pickle=False))
-        # the network was trained on a 2.5 mm grid: a grid at half that spacing feeds it the
-        # pair average-pooled 2x2x2 and interpolates its prediction back
-        cnn_pool = 2 if all(abs(2.0 * h - TRAIN_SPACING_MM) < 1e-9 for h in pair.spacing) else 0
-        log(f"learned radius (cnn_pool {cnn_pool})")
-        lsec, lr_last, lph = leg(dict(radius="learned", sort="predicted", model=model, cnn_pool=cnn_pool))
-        ms_cnn = mean("ms_cnn", lph)
-        # algorithmic MACs of the network at one tail node, from its 9^3 patch: layer l
-        # produces (7 - 2 l)^3 outputs of its per-output MACs
-        macs_node = sum((7 - 2 * l) ** 3 * m
-                        for l, m in enumerate((2 * 16 * 27, 16 * 16 * 27, 16 * 16 * 27, 16 * 27)))
-        macs = macs_node * int(lr_last.n_tail)
-        if cnn_pool:
-            # pooled input: the whole coarse grid, 15,120 MACs per coarse node
-            coarse = int(np.prod([(n + 1) // 2 for n in pair.ref.shape]))
-            macs = coarse * sum(m for m in (2 * 16 * 27, 16 * 16 * 27, 16 * 16 * 27, 16 * 27))
-        cnn_tflops = 2 * macs / (ms_cnn * 1e-3) / 1e12
-        learned = {
-            "value": round(lr_last.n_evaluated / lsec, 1),
-            "ms_per_step": round(1e3 * lsec, 4),
-            "ms_per_step_sync": round(1e3 * leg.sync_sec, 4),
-            "speedup_vs_plain": round(sec / lsec, 3),
-            "n_tail": int(lr_last.n_tail),
-            "n_fallback": int(lr_last.n_fallback),
-            "identical_to_plain": bool(torch.equal(out, g_plain)),
-            "phases_ms": {k: round(mean(k, lph), 4) for k in ("ms_prep", "ms_cnn", "ms_search", "ms_sort",
-                                                              "ms_tail", "ms_guard")},
-            "weights": os.path.relpath(args.weights, ROOT),
-            "cnn_pool": cnn_pool,
-            "cnn_roofline": {"bound": "mfma", "achieved": round(cnn_tflops, 2), "peak": PEAK_BF16_TFLOPS,
-                             "unit": "TFLOP/s", "frac": round(cnn_tflops / PEAK_BF16_TFLOPS, 4),
-                             "algorithmic_flop_per_launch": int(2 * macs),
-                             "flop_per_tail_node": None if cnn_pool else int(2 * macs_node),
-                             "avg_launch_ms": round(ms_cnn, 5)},
-        }
-        log(f"learned: {learned['ms_per_step']} ms/step, {learned['n_fallback']}/{learned['n_tail']} fallbacks")
+    g_learned = None
+    if model is not None:
+        learned = learned_leg(pair, ref, ev, out, g_plain, sec, args.steps)
+        g_learned = out.clone()
 
     wc = work_counts(cfg, seed, args.dd, args.dta)
     cells = wc["cells_visited"] if wc else None
     roofline = None
     if wc:
         # dominant kernel: the pass over the key-0 cells of every node
-        flops = wc["cells_visited_key0"] * FLOP_PER_CELL[nd]
+        flops = wc["cells_visited_key0"] * FLOP_PER_CELL_REFERENCE[nd]
+        flops_cf = wc["cells_visited_key0"] * FLOP_PER_CELL[nd]
         achieved = flops / (ms_search * 1e-3) / 1e12
+        achieved_cf = flops_cf / (ms_search * 1e-3) / 1e12
         kern = "k_zero_group" if args.cell_lanes in (4, 8) else ("k_zero3" if nd == 3 else "k_zero2")
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                     "traffic": traffic_bytes(args.workload, kern == "k_zero3" and args.dd == 0.03
                                              and args.dta == 3.0 and args.precision == "guarded"),
                     "kernel": f"{kern} (key-0 cells of every node)",
-                    "algorithmic_flop_per_launch": flops, "avg_launch_ms": round(ms_search, 5)}
+                    "flop_per_cell": FLOP_PER_CELL_REFERENCE[nd],
+                    "algorithmic_flop_per_launch": flops, "avg_launch_ms": round(ms_search, 5),
+                    "closed_form": {"flop_per_cell": FLOP_PER_CELL[nd], "achieved": round(achieved_cf, 3),
+                                    "frac": round(achieved_cf / PEAK_FP32_TFLOPS, 4)}}
 
     cpu = None
+    acc = None
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle)")
         cpu, o = cpu_baseline(pair, args.dd, args.dta, args.cpu_reps, args.cpu_seconds)
         if cells is None:
             cells = o.cells_visited
+        acc = {"plain": accuracy(g_plain, o)}
+        if g_learned is not None:
+            acc["learned"] = accuracy(g_learned, o)
+            learned["accuracy"] = acc["learned"]
+        log(f"accuracy against the oracle: {acc}")
+
+    # the 256x256x192 pair (the learned radius's target workload): plain and learned maps,
+    # each checked against the oracle
+    c2 = None
+    if not args.no_c2 and args.workload != "3d_256x256x192_1.25mm" and nd == 3:
+        cfg2, seed2, desc2 = WORKLOADS["3d_256x256x192_1.25mm"]
+        log(f"generating {desc2}")
+        pair2 = make_config_pair(cfg2, seed2)
+        ref2 = torch.from_numpy(pair2.ref).to(dev)
+        ev2 = torch.from_numpy(pair2.eval).to(dev)
+        out2 = torch.empty_like(ref2)
+        steps2 = max(5, args.steps)
+        log("256x256x192 plain")
+        sec2, sync2, r2, ph2 = leg(pair2, ref2, ev2, out2, {}, steps2)
+        g2 = out2.clone()
+        c2 = {"workload": f"{desc2}, {args.dd * 100:g}%/{args.dta:g}mm global, 10% cutoff",
+              "n_evaluated": int(r2.n_evaluated),
+              "plain": {"value": round(r2.n_evaluated / sec2, 1), "ms_per_step": round(1e3 * sec2, 4),
+                        "ms_per_step_sync": round(1e3 * sync2, 4), "n_tail": int(r2.n_tail),
+                        "phases_ms": {k: round(mean(k, ph2), 4) for k in ("ms_prep", "ms_search", "ms_sort",
+                                                                          "ms_tail", "ms_guard")}},
+              "learned": None}
+        if model is not None:
+            c2["learned"] = learned_leg(pair2, ref2, ev2, out2, g2, sec2, steps2)
+        if not args.no_cpu:
+            log("256x256x192 oracle")
+            t0 = time.perf_counter()
+            o2 = oracle_gamma(pair2, args.dd, args.dta)
+            c2["oracle_s"] = round(time.perf_counter() - t0, 2)
+            c2["plain"]["accuracy"] = accuracy(g2, o2)
+            if c2["learned"] is not None:
+                c2["learned"]["accuracy"] = accuracy(out2, o2)
+        del ref2, ev2, out2, g2
 
     line = {
         "metric": METRIC,
@@ -632,12 +734,14 @@ def main():
             "projection": args.projection,
             "cells_visited_oracle": cells,
             "n_tail": int(phases[-1].n_tail),
-            "phases_ms": {k: round(mean(k), 4) for k in ("ms_prep", "ms_table", "ms_search", "ms_sort",
-                                                         "ms_tail", "ms_guard")},
+            "phases_ms": {k: round(mean(k, phases), 4) for k in ("ms_prep", "ms_table", "ms_search", "ms_sort",
+                                                                 "ms_tail", "ms_guard")},
         },
+        "accuracy": acc["plain"] if acc else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "learned": learned,
+        "c2": c2,
     }
     print(json.dumps(line), flush=True)
 
