@@ -286,6 +286,24 @@ gammax_status_t gammax_sort_pairs(gammax_ctx_t *ctx, uint32_t *keys_dev, uint32_
                                   int64_t n, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the sort of gammax_sort_pairs without a
+ * context and without any allocation.  It runs on the current HIP device and queues its
+ * kernels on `stream` without waiting (keys_dev and vals_dev hold the sorted pairs once the
+ * stream has passed it); it calls no hipMalloc, hipFree or other allocating routine.
+ * Its scratch (two staging arrays of GAMMAX_SORT_STATIC_MAX words and the radix
+ * histograms, about 9.4 MB) is a static device array of the library: one copy per GPU the
+ * library runs on, held until the process ends, its address looked up on the first call on
+ * each device.  Every call on a GPU uses that GPU's one copy: calls that overlap on one GPU
+ * (on different streams or threads) race; order them.
+ *   n in [0, GAMMAX_SORT_STATIC_MAX]; a larger n returns GAMMAX_E_PARAM (use
+ *   gammax_sort_pairs), NULL keys/vals with n > 0 GAMMAX_E_NULL, a failed launch
+ *   GAMMAX_E_DEVICE.  Results are those of gammax_sort_pairs (stable, ascending).
+ */
+#define GAMMAX_SORT_STATIC_MAX 1048576
+gammax_status_t gammax_sort_pairs_static(uint32_t *keys_dev, uint32_t *vals_dev, int64_t n, void *stream);
+
+/*
  * The radially sorted cell table (Algorithm A1 steps 2-3, Algorithm A2 steps 4-5).
  * Lists every cell offset a (lower corner relative to the reference node, slowest axis
  * first) that can hold a grid cell of `shape` and whose key
@@ -429,27 +447,26 @@ gammax_status_t gammax_model_train_step(gammax_model_t *model, int32_t nvol, con
  * ---- Batches of dose pairs ------------------------------------------------------------
  *
  * Gamma maps of n pairs of any mix of dimensionality, grid, spacing, criteria and
- * normalisation, with one set of options.
- *
- * Default: the pairs run as queued maps, as in gammax_map_many (a cached context per pair
- * index, the caller's stream and three internal streams, each pair's pipeline replayed
- * from its captured graph); results[i].ms_done is the device time from the call's start
- * until pair i's map finished.  opt->autotune is not used on this route (the automatic
- * tail layout adapts per pair context), and timing is refused (GAMMAX_E_PARAM).
- *
- * The single-pipeline batch described next is switched off: its first run on the device
- * stopped making progress, and the cause is not known.  The environment variable
- * GAMMAX_ENABLE_BATCH=1 selects it.  There, every phase runs once for
- * the whole batch (a prep over all pairs' tiles; one persistent pass over the key-0 cells
- * of every pair's nodes in cost order; tail walks, fallbacks and the guard pass taken from
- * a queue of (pair, chunk) items; one count reduction), replayed from a captured HIP graph
- * when the same batch comes again.  Each pair keeps its own cell table.  sort_mode is not
- * used (the queue orders the work); the learned radius applies to the 3D pairs.
+ * normalisation, with one set of options, as one launch of a HIP graph captured on one
+ * stream (replayed when the same batch comes again).  Each pair index keeps a context of its own inside
+ * `ctx` (its cell table, workspace and scalars); a pair met for the first time at its index
+ * (or with a new geometry) first runs its map alone, which builds its table.  The graph
+ * holds, in order: every pair's compaction (dose maximum, mask, gamma0, ordered node list);
+ * one launch of the key-0 pass over every pair's nodes, one workgroup per (pair, block of
+ * 256 nodes), the blocks in cost order (3D pairs first, larger pairs first); then every
+ * pair's own pipeline after the key-0 pass (the network at its tail nodes when learned, tail
+ * sort, tail walk and fallback, FP64 guard, count reduction).
  *   problems[i], refs[i], evals[i], gammas[i]: pair i, as in gammax_map.
- *   results[i]: filled on GAMMAX_OK (ms_done gives each pair's completion time).
- * With opt->autotune = 1, each shape class (dimensionality, size, criteria, spacing) met
- * for the first time has its tail layout (8, 16, 32 or 64 lanes per node) chosen by timing
- * the batch with each, and the choice is kept in the context (gammax_tune_save/load).
+ *   opt: NULL for the defaults; timing, the given order, projection 1 and one lane per cell
+ *   are refused (GAMMAX_E_PARAM).  The learned radius applies to the 3D pairs.
+ *   results[i]: filled on GAMMAX_OK; ms_done = device time from the start of the batch until
+ *   the end of pair i's pipeline.
+ * With opt->autotune = 1 (and tail_lanes 0), each shape class (dimensionality, size,
+ * criteria, spacing) met for the first time has its tail layout (automatic, 8, 16, 32 or 64
+ * lanes per node) chosen by timing the tail walk of the first pair of the class with each
+ * (that pair's own map with phase events), and the choice is kept in the context
+ * (gammax_tune_save/load).  A pair whose search radius outgrew its cached table is
+ * run again on its own, on a larger table (the next batch recaptures the graph).
  * A device-side error of any pair (non-finite dose, no positive dose) fails the batch;
  * gammax_last_error names the pair.  Synchronises `stream`.
  */

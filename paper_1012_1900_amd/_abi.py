@@ -420,6 +420,30 @@ def sort_pairs(keys, vals, ctx: Optional[Context] = None):
     return keys, vals
 
 
+SORT_STATIC_MAX = 1048576
+_lib.gammax_sort_pairs_static.restype = C.c_int
+_lib.gammax_sort_pairs_static.argtypes = [_vp, _vp, C.c_int64, _vp]
+
+
+def sort_pairs_static(keys, vals, stream=None):
+    """``gammax_sort_pairs_static``: the same sort without a context or any allocation (its
+    scratch is a static device array of the library, one per GPU, so calls that overlap on
+    one GPU race).  Queued on ``stream`` (default: the current stream) without waiting; at
+    most SORT_STATIC_MAX pairs."""
+    torch = _torch()
+    for t, nm in ((keys, "keys"), (vals, "vals")):
+        if t.device.type != "cuda" or t.dtype != torch.int32 or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous int32 device tensor")
+    if keys.numel() != vals.numel():
+        raise ValueError("keys and vals differ in length")
+    s = stream if stream is not None else torch.cuda.current_stream(keys.device)
+    with torch.cuda.device(keys.device):
+        st = _lib.gammax_sort_pairs_static(keys.data_ptr(), vals.data_ptr(), keys.numel(), _vp(s.cuda_stream))
+    if st != OK:
+        raise GammaxError(st, f"{keys.numel()} pairs")
+    return keys, vals
+
+
 def build_table(shape: Sequence[int], spacing_over_dta: Sequence[float], radius: float,
                 cap: Optional[int] = None, device: int = 0, ctx: Optional[Context] = None):
     """Sorted cell table: (key2 float32 tensor [T], offsets int32 tensor [T, 3])."""
@@ -673,10 +697,12 @@ _lib.gammax_tune_load.argtypes = [_vp, C.c_char_p]
 
 def gammax_batch(pairs, *, precision: str = "guarded", cond_threshold: float = 1e6, tail_lanes: int = 0,
                  radius: str = "plain", model=None, radius_factor: float = 1.1, autotune: bool = False,
-                 cnn_pool: int = 0, outs=None, ctx: Optional[Context] = None, stream=None):
-    """Gamma maps of a batch of pairs (``gammax_batch``): by default queued per-pair maps on
-    the stream and three internal ones, with each pair's completion time in ``ms_done``
-    (the single-pipeline batch runs only with GAMMAX_ENABLE_BATCH=1).
+                 cnn_pool: int = 0, sort: str = "none", projection: str = "faces", outs=None,
+                 ctx: Optional[Context] = None, stream=None):
+    """Gamma maps of a batch of pairs (``gammax_batch``): one captured HIP graph per batch
+    (every pair's compaction, one key-0 launch over all pairs' nodes in cost order, every
+    pair's tail, guard and counts), replayed when the batch comes again; each pair's
+    completion time in ``ms_done``.
 
     ``pairs``: sequence of dicts with ``ref``, ``ev`` (float32 device tensors), ``spacing``,
     ``dd``, ``dta`` and optionally ``threshold`` (default 0.1) and ``local`` (default False).
@@ -703,8 +729,8 @@ def gammax_batch(pairs, *, precision: str = "guarded", cond_threshold: float = 1
         out_list.append(g)
         refs[i], evs[i], gams[i] = q["ref"].data_ptr(), q["ev"].data_ptr(), g.data_ptr()
     ctx = ctx or context(dev.index or 0)
-    o = make_options("none", precision, cond_threshold, False, tail_lanes, 0, radius, model, radius_factor,
-                     cnn_pool)
+    o = make_options(sort, precision, cond_threshold, False, tail_lanes, 0, radius, model, radius_factor,
+                     cnn_pool, projection)
     o.autotune = 1 if autotune else 0
     res = (Result * n)()
     s = stream if stream is not None else torch.cuda.current_stream(dev)

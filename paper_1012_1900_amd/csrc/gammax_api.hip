@@ -148,10 +148,6 @@ struct ManyState {
     hipStream_t streams[kManyStreams - 1] = {};
     hipEvent_t ev_in = nullptr;
     hipEvent_t ev_out[kManyStreams - 1] = {};
-    // timed runs (gammax_batch): the start on the caller's stream, and each pair's end on
-    // the stream its map ran on
-    hipEvent_t ev_t0 = nullptr;
-    std::vector<hipEvent_t> ev_done;
 };
 void destroy_many(gammax_ctx* c);
 
@@ -650,7 +646,7 @@ ZeroGeo make_zero_geo(const gammax_problem_t* p) {
 
 // Queue the search (steps 3, 6, 7) over at most m_bound nodes with the cached table.
 gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bound, float r2_cap,
-                               hipStream_t s, bool timing) {
+                               hipStream_t s, bool timing, bool skip_zero = false) {
     const gammax_problem_t* p = cs.p;
     const gammax_options_t& opt = *cs.opt;
     const SearchArgs sa = make_search_args(p, opt, cs.ref, cs.ev, cs.gamma, c->d_sc, c->tab,
@@ -665,6 +661,7 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
     // one lane per node (shared neighbourhood loads) unless one lane per cell is asked for
     plan.zero_lanes = (opt.cell_lanes == 4 || opt.cell_lanes == 8) ? 1 : 0;
     plan.projection = opt.projection;
+    plan.skip_zero = skip_zero ? 1 : 0;
     plan.spec = (learned && opt.radius_mode == GAMMAX_RADIUS_LEARNED) ? 1 : 0;
     plan.M = m_bound;
     plan.zero = make_zero_geo(p);
@@ -1453,38 +1450,61 @@ gammax_status_t gammax_model_predict_nodes_pooled(gammax_ctx_t* c, gammax_model_
 }  // extern "C"
 
 // ---- batches -----------------------------------------------------------------------------
-
-namespace {
-
-struct BatchTable {
-    TabEntry* tab = nullptr;
-    int64_t cap = 0, len = 0;
-    float k1 = INFINITY;
-    TableGeom geom{};
-    bool valid = false;
-};
-
-}  // namespace
+//
+// gammax_batch: the whole batch as one captured HIP graph on one stream.  Each pair keeps a
+// context of its own (cell table, workspace, scalars ring), and the graph holds, in order:
+//   * every pair's compaction (the prep kernels of its own map);
+//   * one launch of the key-0 pass over every pair's nodes: one block per (pair, block of
+//     256 nodes) item, the items in cost order (3D pairs first, larger pairs first);
+//   * every pair's pipeline after the key-0 pass (network at the tail nodes, tail sort,
+//     tail walk and fallback, guard and count reduction, scalars to its ring), each ending
+//     with a stamp of the device clock (completion times).
+// A repeated batch replays the graph.  The tail layout of each shape class can be tuned by
+// timing that layout's walk on a pair of the class (gammax_tune_*).
 
 struct BatchState {
-    std::vector<BatchTable> tabs;
-    unsigned char* arena = nullptr;    // device: descriptors, control, per-pair workspaces
-    int64_t arena_cap = 0;
-    unsigned char* host = nullptr;     // pinned staging: descriptors, items, scalars, clocks
-    int64_t host_cap = 0;
-    std::vector<unsigned char> uploaded;   // descriptor bytes now on the device
+    std::vector<gammax_ctx*> subs;               // a context per pair index
+    BatchSearchPair* d_pairs = nullptr;          // device: key-0 descriptors, then the items
+    int64_t desc_cap = 0;                        // bytes
+    unsigned char* h_stage = nullptr;            // pinned: descriptors and items to upload
+    int64_t stage_cap = 0;
+    std::vector<unsigned char> uploaded;         // what the device holds
+    unsigned long long* d_done = nullptr;        // completion clocks per pair, [n] = start
+    unsigned long long* h_done = nullptr;        // pinned copy
+    int64_t done_cap = 0;
     hipGraphExec_t graph = nullptr;
     std::vector<unsigned char> graph_key;
-    std::map<uint64_t, int> tune;      // shape class -> lanes per node of the tail walks
-    hipEvent_t ev[2] = {};
-    int cus = 0;                       // compute units of the device
-    int clock_khz = 0;                 // rate of the device clock read by the kernels
+    std::map<uint64_t, int> tune;                // shape class -> lanes per node of the tail walk
+    int clock_khz = 0;
 };
 
-namespace {
+void destroy_batch(gammax_ctx* c) {
+    BatchState* b = c->batch;
+    if (!b) return;
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (gammax_ctx* sub : b->subs) (void)gammax_ctx_destroy(sub);
+    if (b->d_pairs) (void)hipFree(b->d_pairs);
+    if (b->d_done) (void)hipFree(b->d_done);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    if (b->h_done) (void)hipHostFree(b->h_done);
+    delete b;
+    c->batch = nullptr;
+}
 
-constexpr int64_t kAlignB = 256;
-int64_t alg(int64_t b) { return (b + kAlignB - 1) / kAlignB * kAlignB; }
+void destroy_many(gammax_ctx* c) {
+    ManyState* m = c->many;
+    if (!m) return;
+    for (gammax_ctx* sub : m->subs) (void)gammax_ctx_destroy(sub);
+    for (auto& st : m->streams)
+        if (st) (void)hipStreamDestroy(st);
+    if (m->ev_in) (void)hipEventDestroy(m->ev_in);
+    for (auto& e : m->ev_out)
+        if (e) (void)hipEventDestroy(e);
+    delete m;
+    c->many = nullptr;
+}
+
+namespace {
 
 // Shape class of a pair for the tuner: dimensionality, log2 of the node count, DD in
 // 0.1 %, DTA in 0.1 mm, smallest spacing in 0.1 mm.
@@ -1499,229 +1519,121 @@ uint64_t shape_class(const gammax_problem_t* p, int64_t n) {
     return (uint64_t)p->ndim | ((uint64_t)lg << 2) | (dd << 8) | (dta << 24) | (h << 40);
 }
 
-// Layout of one batch (byte offsets into the device arena and the pinned staging).
-struct BatchLayout {
-    int n = 0, n_items = 0, total_red = 0, total_tiles = 0;
-    int64_t o_prep = 0, o_search = 0, o_items = 0, o_chunk0 = 0, o_gsel = 0, o_ctl = 0, o_done = 0, o_sc = 0;
-    std::vector<int64_t> o_sums, o_part, o_blk, o_work, o_yhat, nodes, tiles, red;
-    int64_t arena = 0;
-    // staging: descriptors and items first (uploaded together), then scalars and clocks
-    int64_t h_desc = 0, h_sc = 0, h_done = 0, host = 0;
+// One batch as the graph sees it: per pair its call set-up and options, and the items of
+// the key-0 launch.
+struct BatchPlan {
+    int n = 0;
+    std::vector<gammax_options_t> opt;
+    std::vector<CallSetup> cs;
+    std::vector<int64_t> nodes;
+    bool key0 = true;          // false for FP64 precision (its walk starts at row 0)
+    int n_items = 0;
+    int64_t desc_bytes = 0;    // descriptors, then items
 };
 
-BatchLayout batch_layout(int n, const gammax_problem_t* probs, const std::vector<int>& learned,
-                         const std::vector<int>& order) {
-    BatchLayout L;
-    L.n = n;
-    int64_t off = 0;
-    auto take = [&](int64_t bytes) {
-        const int64_t o = off;
-        off += alg(bytes);
-        return o;
-    };
-    for (int i = 0; i < n; ++i) {
-        int64_t nn = 1;
-        for (int k = 0; k < probs[i].ndim; ++k) nn *= probs[i].shape[k];
-        L.nodes.push_back(nn);
-        L.tiles.push_back(prep_tiles(nn));
-        L.red.push_back(batch_reduce_blocks(nn));
-        L.total_tiles += (int)L.tiles.back();
-        L.total_red += (int)L.red.back();
+int64_t items_offset(int n) { return (int64_t)((sizeof(BatchSearchPair) * n + 255) / 256 * 256); }
+
+// The key-0 descriptors of every pair (the search arguments its own pipeline uses) and the
+// cost-ordered items, into the pinned staging area.
+void stage_batch(BatchState* b, const BatchPlan& P) {
+    BatchSearchPair* d = (BatchSearchPair*)b->h_stage;
+    uint2* items = (uint2*)(b->h_stage + items_offset(P.n));
+    std::memset(b->h_stage, 0, (size_t)P.desc_bytes);
+    for (int i = 0; i < P.n; ++i) {
+        gammax_ctx* c = b->subs[i];
+        const gammax_problem_t* p = P.cs[i].p;
+        const float r2_cap = round_down_float(c->tab_geom.r2_cap);
+        d[i].sa = make_search_args(p, P.opt[i], P.cs[i].ref, P.cs[i].ev, P.cs[i].gamma, c->d_sc, c->tab,
+                                   c->tab_valid ? (int)c->tab_len : 0, c->tab_valid ? c->tab_k1 : INFINITY,
+                                   r2_cap, c->work, c->work_cap, c->sums, c->yhat);
+        d[i].zg = make_zero_geo(p);
+        d[i].ndim = p->ndim;
+        d[i].guarded = (P.opt[i].precision == GAMMAX_PREC_GUARDED && p->ndim == 3) ? 1 : 0;
     }
-    for (int i : order) L.n_items += (int)((L.nodes[i] + 255) / 256);
-    L.o_prep = take(sizeof(BatchPrepPair) * n);
-    L.o_search = take(sizeof(BatchSearchPair) * n);
-    L.o_items = take(sizeof(uint2) * (L.n_items > 0 ? L.n_items : 1));
-    const int64_t desc_bytes = off;   // descriptors + items are uploaded in one copy
-    L.o_chunk0 = take(sizeof(uint32_t) * 3 * (n + 1));
-    L.o_gsel = take(sizeof(uint32_t) * 3 * n);
-    L.o_ctl = take(sizeof(BatchCtl));
-    L.o_done = take(sizeof(unsigned long long) * (n + 1));
-    L.o_sc = take(sizeof(Scalars) * n);
-    for (int i = 0; i < n; ++i) {
-        L.o_sums.push_back(take(sizeof(BlockSums) * SUM_BINS));
-        L.o_part.push_back(take(sizeof(uint32_t) * 2 * MAX_BLOCKS));
-        L.o_blk.push_back(take(sizeof(uint32_t) * prep_words(L.nodes[i])));
-        L.o_work.push_back(take(sizeof(uint32_t) * kWorkArrays * L.nodes[i]));
-        L.o_yhat.push_back(learned[i] ? take(sizeof(float) * L.nodes[i]) : -1);
-    }
-    L.arena = off;
-    L.h_desc = desc_bytes;
-    L.h_sc = alg(desc_bytes);
-    L.h_done = L.h_sc + alg(sizeof(Scalars) * n);
-    L.host = L.h_done + alg(sizeof(unsigned long long) * (n + 1));
-    return L;
-}
-
-}  // namespace
-
-void destroy_batch(gammax_ctx* c) {
-    BatchState* b = c->batch;
-    if (!b) return;
-    for (auto& t : b->tabs)
-        if (t.tab) (void)hipFree(t.tab);
-    if (b->arena) (void)hipFree(b->arena);
-    if (b->host) (void)hipHostFree(b->host);
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
-    for (auto& e : b->ev)
-        if (e) (void)hipEventDestroy(e);
-    delete b;
-    c->batch = nullptr;
-}
-
-void destroy_many(gammax_ctx* c) {
-    ManyState* m = c->many;
-    if (!m) return;
-    for (gammax_ctx* sub : m->subs) (void)gammax_ctx_destroy(sub);
-    for (auto& st : m->streams)
-        if (st) (void)hipStreamDestroy(st);
-    if (m->ev_in) (void)hipEventDestroy(m->ev_in);
-    for (auto& e : m->ev_out)
-        if (e) (void)hipEventDestroy(e);
-    if (m->ev_t0) (void)hipEventDestroy(m->ev_t0);
-    for (auto& e : m->ev_done) (void)hipEventDestroy(e);
-    delete m;
-    c->many = nullptr;
-}
-
-namespace {
-
-// Fill the descriptors of every pair in the staging area.  Pairs without a usable table
-// get tab_len 0 (their walk ends after the key-0 cells, and k1 = inf finishes every node).
-void fill_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L, const gammax_problem_t* probs,
-                const float* const* refs, const float* const* evals, float* const* gammas,
-                const gammax_options_t& opt, const std::vector<int>& learned, const std::vector<int>& lanes,
-                const std::vector<int>& order, bool cap_radius) {
-    BatchPrepPair* pp = (BatchPrepPair*)(b->host + L.o_prep);
-    BatchSearchPair* sp = (BatchSearchPair*)(b->host + L.o_search);
-    uint2* items = (uint2*)(b->host + L.o_items);
-    std::memset(b->host, 0, (size_t)L.h_desc);
-    Scalars* d_sc = (Scalars*)(b->arena + L.o_sc);
-    int red0 = 0, tile0 = 0;
-    for (int i = 0; i < L.n; ++i) {
-        const gammax_problem_t* p = &probs[i];
-        BatchPrepPair& P = pp[i];
-        uint32_t* work = (uint32_t*)(b->arena + L.o_work[i]);
-        uint32_t* blk = (uint32_t*)(b->arena + L.o_blk[i]);
-        P.pa.ref = refs[i];
-        P.pa.ev = evals[i];
-        P.pa.gamma = gammas[i];
-        P.pa.n = L.nodes[i];
-        P.pa.thr = (float)p->dose_threshold;
-        P.pa.dd = (float)p->dd;
-        P.pa.local = p->norm == GAMMAX_LOCAL ? 1 : 0;
-        P.pa.sc = &d_sc[i];
-        P.pa.part = (uint32_t*)(b->arena + L.o_part[i]);
-        P.pa.blockcnt = blk;
-        prep_groups(L.nodes[i], &P.pa.super_shift, &P.pa.n_super);
-        P.pa.super = blk + L.tiles[i];
-        P.pa.ntiles = (int)L.tiles[i];
-        P.pa.nodes = work + W_NODES * L.nodes[i];
-        P.pa.sums = (BlockSums*)(b->arena + L.o_sums[i]);
-        P.nb_red = (int)L.red[i];
-        P.ntiles = (int)L.tiles[i];
-        P.red0 = red0;
-        P.tile0 = tile0;
-        red0 += P.nb_red;
-        tile0 += P.ntiles;
-
-        const BatchTable& t = b->tabs[i];
-        const bool tv = t.valid;
-        const float r2_cap = (tv && cap_radius) ? round_down_float(t.geom.r2_cap) : INFINITY;
-        BatchSearchPair& S = sp[i];
-        S.sa = make_search_args(p, opt, refs[i], evals[i], gammas[i], &d_sc[i], t.tab, tv ? (int)t.len : 0,
-                                tv ? t.k1 : INFINITY, r2_cap, work, L.nodes[i], P.pa.sums,
-                                learned[i] ? (const float*)(b->arena + L.o_yhat[i]) : nullptr);
-        S.sa.tail_key = 0;
-        S.zg = make_zero_geo(p);
-        S.ndim = p->ndim;
-        S.guarded = (opt.precision == GAMMAX_PREC_GUARDED && p->ndim == 3) ? 1 : 0;
-        S.spec = (learned[i] && opt.radius_mode == GAMMAX_RADIUS_LEARNED) ? 1 : 0;
-        S.g_tail = lanes[i];
-        S.first = p->ndim == 3 ? 8 : 4;
-        S.r2_cap = r2_cap;
-    }
+    std::vector<int> order(P.n);
+    for (int i = 0; i < P.n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const double cx = (double)P.nodes[x] * (P.cs[x].p->ndim == 3 ? 8.0 : 2.0);
+        const double cy = (double)P.nodes[y] * (P.cs[y].p->ndim == 3 ? 8.0 : 2.0);
+        return cx > cy;
+    });
     int k = 0;
     for (int i : order)
-        for (int64_t blk = 0; blk < (L.nodes[i] + 255) / 256; ++blk) items[k++] = make_uint2((uint32_t)i, (uint32_t)blk);
+        for (int64_t blk = 0; blk < (P.nodes[i] + 255) / 256; ++blk) items[k++] = make_uint2((uint32_t)i, (uint32_t)blk);
 }
 
-gammax_status_t upload_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L, hipStream_t s) {
-    if ((int64_t)b->uploaded.size() == L.h_desc && std::memcmp(b->uploaded.data(), b->host, (size_t)L.h_desc) == 0)
-        return GAMMAX_OK;
-    HIPCHK(c, hipMemcpyAsync(b->arena, b->host, (size_t)L.h_desc, hipMemcpyHostToDevice, s));
-    b->uploaded.assign(b->host, b->host + L.h_desc);
+// Queue the whole batch on `s` (the capture stream, or the caller's stream for a direct run).
+gammax_status_t enqueue_batch(gammax_ctx* c, BatchState* b, const BatchPlan& P, hipStream_t s) {
+    gammax_status_t st;
+    HIPCHK(c, launch_stamp(b->d_done + P.n, s));
+    for (int i = 0; i < P.n; ++i)
+        if ((st = enqueue_prep(b->subs[i], P.cs[i], s, nullptr, nullptr)) != GAMMAX_OK)
+            return fail(c, st, "pair " + std::to_string(i) + ": " + b->subs[i]->err);
+    if (P.key0)
+        HIPCHK(c, launch_batch_key0(b->d_pairs, (const uint2*)((unsigned char*)b->d_pairs + items_offset(P.n)),
+                                    P.n_items, s));
+    for (int i = 0; i < P.n; ++i) {
+        gammax_ctx* sub = b->subs[i];
+        const float r2_cap = round_down_float(sub->tab_geom.r2_cap);
+        if ((st = enqueue_search(sub, P.cs[i], (uint32_t)P.nodes[i], r2_cap, s, false, P.key0)) != GAMMAX_OK)
+            return fail(c, st, "pair " + std::to_string(i) + ": " + sub->err);
+        HIPCHK(c, launch_stamp(b->d_done + i, s));
+    }
     return GAMMAX_OK;
 }
 
-struct BatchHooks {
-    std::vector<TailCnnHook> list;
-};
-hipError_t batch_hooks(void* user, hipStream_t s) {
-    for (TailCnnHook& h : static_cast<BatchHooks*>(user)->list) {
-        hipError_t e = tail_cnn_hook(&h, s);
-        if (e != hipSuccess) return e;
+// The graph key: every pair's own graph key (pointers, problem, options and the context
+// state its pipeline depends on) and the staged descriptors.
+std::vector<unsigned char> batch_key(BatchState* b, const BatchPlan& P) {
+    std::vector<unsigned char> k(b->h_stage, b->h_stage + P.desc_bytes);
+    for (int i = 0; i < P.n; ++i) {
+        const GraphKey g = key_of(b->subs[i], P.cs[i]);
+        const unsigned char* q = (const unsigned char*)&g;
+        k.insert(k.end(), q, q + sizeof(g));
     }
-    return hipSuccess;
+    return k;
 }
 
-// Queue the whole batch: prep, the search passes (with the network at the tail nodes of
-// the learned pairs after the key-0 pass).
-gammax_status_t enqueue_batch(gammax_ctx* c, BatchState* b, const BatchLayout& L, const gammax_problem_t* probs,
-                              const float* const* refs, const float* const* evals, const gammax_options_t& opt,
-                              const std::vector<int>& learned, bool prep, bool search, hipStream_t s) {
-    const BatchPrepPair* d_pp = (const BatchPrepPair*)(b->arena + L.o_prep);
-    const BatchSearchPair* d_sp = (const BatchSearchPair*)(b->arena + L.o_search);
-    unsigned long long* done = (unsigned long long*)(b->arena + L.o_done);
-    if (prep) HIPCHK(c, launch_batch_prep(d_pp, L.n, L.total_red, L.total_tiles, done + L.n, s));
-    if (!search) return GAMMAX_OK;
-    bool any_spec = false, any_guard = false;
-    BatchHooks hooks;
-    for (int i = 0; i < L.n; ++i) {
-        if (learned[i]) {
-            // the network at this pair's tail nodes, after the key-0 pass
-            TailCnnHook h{};
-            h.model = opt.model;
-            h.ref = refs[i];
-            h.ev = evals[i];
-            for (int k = 0; k < 3; ++k) h.shape[k] = (int)probs[i].shape[k];
-            Scalars* sc = (Scalars*)(b->arena + L.o_sc) + i;
-            h.sc = sc;
-            h.nodes = (const uint32_t*)(b->arena + L.o_work[i]) + W_TAIL_NODE * L.nodes[i];
-            h.count = &sc->n_tail;
-            h.y = (float*)(b->arena + L.o_yhat[i]);
-            h.blocks = kTailCnnBlocks;
-            hooks.list.push_back(h);
-            any_spec = any_spec || opt.radius_mode == GAMMAX_RADIUS_LEARNED;
+// Run the batch once (replaying the graph when possible), ring slots claimed and counted
+// as every pair's map publishes its scalars.  ring[i] receives pair i's slot.
+gammax_status_t launch_batch(gammax_ctx* c, BatchState* b, const BatchPlan& P, hipStream_t s,
+                             std::vector<int>& ring) {
+    gammax_status_t st;
+    stage_batch(b, P);
+    if ((int64_t)b->uploaded.size() != P.desc_bytes ||
+        std::memcmp(b->uploaded.data(), b->h_stage, (size_t)P.desc_bytes) != 0) {
+        HIPCHK(c, hipMemcpyAsync(b->d_pairs, b->h_stage, (size_t)P.desc_bytes, hipMemcpyHostToDevice, s));
+        b->uploaded.assign(b->h_stage, b->h_stage + P.desc_bytes);
+    }
+    for (int i = 0; i < P.n; ++i) ring[i] = claim_ring(b->subs[i]);
+    bool launched = false;
+    if (!c->graph_broken) {
+        const std::vector<unsigned char> key = batch_key(b, P);
+        if (!b->graph || key != b->graph_key) {
+            if (b->graph) (void)hipGraphExecDestroy(b->graph);
+            b->graph = nullptr;
+            if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            st = enqueue_batch(c, b, P, c->cap_stream);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+            if (st == GAMMAX_OK && e == hipSuccess && g && hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0) == hipSuccess) {
+                b->graph_key = key;
+            } else {
+                b->graph = nullptr;
+                c->graph_broken = true;   // launch directly from now on
+                (void)hipGetLastError();
+            }
+            if (g) (void)hipGraphDestroy(g);
+            if (st != GAMMAX_OK) return st;
         }
-        any_guard = any_guard || (opt.precision == GAMMAX_PREC_GUARDED && probs[i].ndim == 3);
+        if (b->graph) {
+            HIPCHK(c, hipGraphLaunch(b->graph, s));
+            launched = true;
+        }
     }
-    const int dev_cus = b->cus > 0 ? b->cus : 256;
-    const int zero_blocks = std::max(1, std::min(L.n_items, dev_cus * 8));
-    const int tail_blocks = dev_cus * 4;
-    HIPCHK(c, launch_batch_search(d_sp, L.n, (const uint2*)(b->arena + L.o_items), L.n_items, zero_blocks,
-                                  tail_blocks, any_spec, any_guard, (uint32_t*)(b->arena + L.o_chunk0),
-                                  (uint32_t*)(b->arena + L.o_gsel), (BatchCtl*)(b->arena + L.o_ctl), done,
-                                  hooks.list.empty() ? nullptr : batch_hooks, &hooks, s));
-    return GAMMAX_OK;
-}
-
-gammax_status_t read_batch_scalars(gammax_ctx* c, BatchState* b, const BatchLayout& L, hipStream_t s) {
-    HIPCHK(c, hipMemcpyAsync(b->host + L.h_sc, b->arena + L.o_sc, sizeof(Scalars) * L.n, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(b->host + L.h_done, b->arena + L.o_done, sizeof(unsigned long long) * (L.n + 1),
-                             hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    return GAMMAX_OK;
-}
-
-gammax_status_t batch_errors(gammax_ctx* c, BatchState* b, const BatchLayout& L, const gammax_problem_t* probs) {
-    const Scalars* h = (const Scalars*)(b->host + L.h_sc);
-    for (int i = 0; i < L.n; ++i) {
-        if (h[i].flags & FLAG_NONFINITE)
-            return fail(c, GAMMAX_E_NONFINITE, "pair " + std::to_string(i) + ": a dose value is NaN or infinite");
-        if (probs[i].norm == GAMMAX_GLOBAL && !(ord_to_float(h[i].dmax_ord) > 0.0f))
-            return fail(c, GAMMAX_E_DOSE, "pair " + std::to_string(i) + ": max reference dose is not positive");
-    }
+    if (!launched && (st = enqueue_batch(c, b, P, s)) != GAMMAX_OK) return st;
+    for (int i = 0; i < P.n; ++i) ++b->subs[i]->seq;
     return GAMMAX_OK;
 }
 
@@ -1730,11 +1642,10 @@ gammax_status_t batch_errors(gammax_ctx* c, BatchState* b, const BatchLayout& L,
 namespace {
 
 // The maps of n pairs queued on the caller's stream and three internal ones (a cached
-// context per pair index), then collected.  timed: results[i].ms_done = device time from
-// the start of the call until pair i's map finished.
+// context per pair index), then collected.
 gammax_status_t run_many(gammax_ctx_t* c, int32_t n, const gammax_problem_t* probs, const float* const* refs,
                          const float* const* evals, float* const* gammas, const gammax_options_t* opt,
-                         gammax_result_t* results, hipStream_t s, bool timed) {
+                         gammax_result_t* results, hipStream_t s) {
     if (!c) return GAMMAX_E_NULL;
     if (n < 0) return fail(c, GAMMAX_E_PARAM, "n must be >= 0");
     if (n == 0) return GAMMAX_OK;
@@ -1759,15 +1670,6 @@ gammax_status_t run_many(gammax_ctx_t* c, int32_t n, const gammax_problem_t* pro
         if (st != GAMMAX_OK) return fail(c, st, "gammax_map_many: context for a pair");
         m->subs.push_back(sub);
     }
-    if (timed) {
-        if (!m->ev_t0) HIPCHK(c, hipEventCreate(&m->ev_t0));
-        while ((int)m->ev_done.size() < n) {
-            hipEvent_t e = nullptr;
-            HIPCHK(c, hipEventCreate(&e));
-            m->ev_done.push_back(e);
-        }
-        HIPCHK(c, hipEventRecord(m->ev_t0, s));
-    }
     // the internal streams start after the caller's work on `stream`
     HIPCHK(c, hipEventRecord(m->ev_in, s));
     for (auto& st : m->streams) HIPCHK(c, hipStreamWaitEvent(st, m->ev_in, 0));
@@ -1785,7 +1687,6 @@ gammax_status_t run_many(gammax_ctx_t* c, int32_t n, const gammax_problem_t* pro
             why = "pair " + std::to_string(i) + ": " + m->subs[i]->err;
             break;
         }
-        if (timed) HIPCHK(c, hipEventRecord(m->ev_done[i], si));
         ++queued;
     }
     for (int i = 0; i < queued; ++i) {
@@ -1801,11 +1702,6 @@ gammax_status_t run_many(gammax_ctx_t* c, int32_t n, const gammax_problem_t* pro
         HIPCHK(c, hipStreamWaitEvent(s, m->ev_out[k], 0));
     }
     if (first != GAMMAX_OK) return fail(c, first, why);
-    if (timed)
-        for (int i = 0; i < n; ++i) {
-            HIPCHK(c, hipEventSynchronize(m->ev_done[i]));
-            HIPCHK(c, hipEventElapsedTime(&results[i].ms_done, m->ev_t0, m->ev_done[i]));
-        }
     return GAMMAX_OK;
 }
 
@@ -1817,16 +1713,6 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
                              const float* const* evals, float* const* gammas, const gammax_options_t* opt_in,
                              gammax_result_t* results, void* stream) {
     if (!c) return GAMMAX_E_NULL;
-    // The persistent pipeline below is switched off: its first GPU run stopped making
-    // progress and the cause is not yet known (GAMMAX_ENABLE_BATCH=1 turns it on for
-    // investigation).  Meanwhile the batch runs as queued per-pair maps on four streams.
-    const char* en = std::getenv("GAMMAX_ENABLE_BATCH");
-    if (!en || std::strcmp(en, "1") != 0) {
-        if (opt_in && opt_in->timing) return fail(c, GAMMAX_E_PARAM, "timing is not available for gammax_batch");
-        if (n < 0) return fail(c, GAMMAX_E_PARAM, "n must be >= 0");
-        HIPCHK(c, hipSetDevice(c->device));
-        return run_many(c, n, probs, refs, evals, gammas, opt_in, results, (hipStream_t)stream, true);
-    }
     if (n < 0) return fail(c, GAMMAX_E_PARAM, "n must be >= 0");
     if (n == 0) return GAMMAX_OK;
     if (!probs || !refs || !evals || !gammas || !results)
@@ -1836,17 +1722,11 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
     else gammax_options_default(&opt);
     gammax_status_t st = check_options(c, &opt);
     if (st != GAMMAX_OK) return st;
-    if (opt.cnn_pool != 0) return fail(c, GAMMAX_E_PARAM, "cnn_pool is not available on the single-pipeline batch");
+    if (opt.timing) return fail(c, GAMMAX_E_PARAM, "timing is not available for gammax_batch");
     if (opt.sort_mode == GAMMAX_SORT_GIVEN)
         return fail(c, GAMMAX_E_PARAM, "the given order is for single maps (one key array per grid)");
-    std::vector<int64_t> nn(n);
-    for (int i = 0; i < n; ++i) {
-        if ((st = check_problem(c, &probs[i], &nn[i])) != GAMMAX_OK)
-            return fail(c, st, "pair " + std::to_string(i) + ": " + c->err);
-        if (!refs[i] || !evals[i] || !gammas[i]) return fail(c, GAMMAX_E_NULL, "pair " + std::to_string(i) + ": null pointer");
-        if ((const float*)gammas[i] == refs[i] || (const float*)gammas[i] == evals[i])
-            return fail(c, GAMMAX_E_PARAM, "pair " + std::to_string(i) + ": gamma must not alias the doses");
-    }
+    if (opt.projection != 0 || opt.cell_lanes > 1)
+        return fail(c, GAMMAX_E_PARAM, "the batch runs the default key-0 pass (projection 0, one lane per node)");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, hipSetDevice(c->device));
     if (!c->batch) {
@@ -1854,202 +1734,147 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
         if (!c->batch) return fail(c, GAMMAX_E_NOMEM, "batch state");
     }
     BatchState* b = c->batch;
-    if ((int)b->tabs.size() < n) b->tabs.resize(n);
-    if (b->cus == 0) {
-        HIPCHK(c, hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    if (b->clock_khz == 0)
         HIPCHK(c, hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, c->device));
+    while ((int)b->subs.size() < n) {
+        gammax_ctx* sub = nullptr;
+        if ((st = gammax_ctx_create(c->device, &sub)) != GAMMAX_OK) return fail(c, st, "batch: context for a pair");
+        b->subs.push_back(sub);
     }
 
-    // which pairs use the network; cost order of the key-0 items (3D first, larger first)
-    std::vector<int> learned(n, 0), order(n);
+    // every pair: checks, workspace, and a cell table for its geometry (a pair met for the
+    // first time runs its map once on its own context, which builds the table)
+    BatchPlan P;
+    P.n = n;
+    P.opt.resize(n);
+    P.cs.resize(n);
+    P.nodes.resize(n);
+    P.key0 = opt.precision != GAMMAX_PREC_FP64;
+    std::vector<uint64_t> cls(n);
+    std::vector<int> learned(n, 0);
     for (int i = 0; i < n; ++i) {
-        learned[i] = uses_model(&probs[i], &opt) ? 1 : 0;
-        order[i] = i;
+        gammax_ctx* sub = b->subs[i];
+        int64_t nn = 0;
+        if ((st = check_problem(c, &probs[i], &nn)) != GAMMAX_OK) return fail(c, st, "pair " + std::to_string(i) + ": " + c->err);
+        cls[i] = shape_class(&probs[i], nn);
+        gammax_options_t oi = opt;
+        if (opt.tail_lanes == 0 && b->tune.count(cls[i])) oi.tail_lanes = b->tune[cls[i]];
+        bool lr = false;
+        if ((st = map_setup(sub, &probs[i], &oi, refs[i], evals[i], gammas[i], &P.opt[i], &nn, &lr)) != GAMMAX_OK)
+            return fail(c, st, "pair " + std::to_string(i) + ": " + sub->err);
+        learned[i] = lr ? 1 : 0;
+        P.nodes[i] = nn;
+        P.cs[i] = CallSetup{&probs[i], &P.opt[i], refs[i], evals[i], gammas[i], nn};
+        if (!steady_table(sub, &probs[i])) {
+            gammax_result_t r{};
+            if ((st = gammax_map(sub, &probs[i], &P.opt[i], refs[i], evals[i], gammas[i], &r, s)) != GAMMAX_OK)
+                return fail(c, st, "pair " + std::to_string(i) + ": " + sub->err);
+            if (!sub->tab_valid) {
+                // no walk needed yet (every gamma0 0, or nothing evaluated): an empty table
+                // for the geometry, so that the pair takes part in the graph
+                sub->tab_geom = geom_of(&probs[i]);
+                sub->tab_geom.r2_cap = 0.0;
+                sub->tab_len = 0;
+                sub->tab_k1 = INFINITY;
+                sub->tab_valid = true;
+            }
+        }
     }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int z) {
-        const double ca = (double)nn[a] * (probs[a].ndim == 3 ? 8.0 : 2.0);
-        const double cz = (double)nn[z] * (probs[z].ndim == 3 ? 8.0 : 2.0);
-        return ca > cz;
-    });
-    const BatchLayout L = batch_layout(n, probs, learned, order);
-    if (L.arena > b->arena_cap || !b->arena) {
-        if ((st = grow(c, &b->arena, &b->arena_cap, L.arena)) != GAMMAX_OK) return st;
+    int64_t n_items = 0;
+    for (int i = 0; i < n; ++i) n_items += (P.nodes[i] + 255) / 256;
+    if (n_items >= ((int64_t)1 << 31)) return fail(c, GAMMAX_E_SHAPE, "batch holds too many nodes");
+    P.n_items = P.key0 ? (int)n_items : 0;
+    P.desc_bytes = items_offset(n) + (int64_t)sizeof(uint2) * (n_items > 0 ? n_items : 1);
+    if (P.desc_bytes > b->desc_cap || !b->d_pairs) {
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        int64_t cap = b->desc_cap;
+        unsigned char* raw = (unsigned char*)b->d_pairs;
+        if ((st = grow(c, &raw, &cap, P.desc_bytes)) != GAMMAX_OK) return st;
+        b->d_pairs = (BatchSearchPair*)raw;
+        b->desc_cap = cap;
         b->uploaded.clear();
     }
-    if (L.host > b->host_cap || !b->host) {
-        if (b->host) (void)hipHostFree(b->host);
-        b->host = nullptr;
-        b->host_cap = 0;
-        HIPCHK(c, hipHostMalloc((void**)&b->host, (size_t)L.host, hipHostMallocDefault));
-        b->host_cap = L.host;
+    if (P.desc_bytes > b->stage_cap || !b->h_stage) {
+        if (b->h_stage) (void)hipHostFree(b->h_stage);
+        b->h_stage = nullptr;
+        b->stage_cap = 0;
+        HIPCHK(c, hipHostMalloc((void**)&b->h_stage, (size_t)P.desc_bytes, hipHostMallocDefault));
+        b->stage_cap = P.desc_bytes;
     }
-
-    // tail lanes per pair: fixed by the options, else tuned per shape class, else automatic
-    std::vector<uint64_t> cls(n);
-    std::vector<int> lanes(n, 0);
-    for (int i = 0; i < n; ++i) {
-        cls[i] = shape_class(&probs[i], nn[i]);
-        if (opt.tail_lanes > 0) lanes[i] = opt.tail_lanes;
-        else if (b->tune.count(cls[i])) lanes[i] = b->tune[cls[i]];
+    if (n + 1 > b->done_cap || !b->d_done) {
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        if (b->h_done) (void)hipHostFree(b->h_done);
+        b->h_done = nullptr;
+        int64_t cap = b->done_cap;
+        if ((st = grow(c, &b->d_done, &cap, n + 1)) != GAMMAX_OK) return st;
+        b->done_cap = cap;
+        HIPCHK(c, hipHostMalloc((void**)&b->h_done, sizeof(unsigned long long) * (size_t)cap, hipHostMallocDefault));
     }
+    std::vector<int> ring(n, 0);
 
-    // tables: every pair's cached table must serve its geometry
-    bool tables_ok = true;
-    for (int i = 0; i < n; ++i) {
-        const TableGeom g = geom_of(&probs[i]);
-        if (!b->tabs[i].valid || !same_geom(b->tabs[i].geom, g)) tables_ok = false;
-    }
-
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        if (!tables_ok) {
-            // build path: prep, then the tables for the radii found
-            fill_batch(c, b, L, probs, refs, evals, gammas, opt, learned, lanes, order, false);
-            if ((st = upload_batch(c, b, L, s)) != GAMMAX_OK) return st;
-            if ((st = enqueue_batch(c, b, L, probs, refs, evals, opt, learned, true, false, s)) != GAMMAX_OK) return st;
-            if ((st = read_batch_scalars(c, b, L, s)) != GAMMAX_OK) return st;
-            if ((st = batch_errors(c, b, L, probs)) != GAMMAX_OK) return st;
-            const Scalars* h = (const Scalars*)(b->host + L.h_sc);
-            std::vector<float> r2(n);
-            for (int i = 0; i < n; ++i) r2[i] = u2f(h[i].r2_bits);
-            for (int i = 0; i < n; ++i) {
-                BatchTable& t = b->tabs[i];
-                const TableGeom g = geom_of(&probs[i]);
-                const bool fits = t.valid && same_geom(t.geom, g) && (double)r2[i] <= t.geom.r2_cap;
-                if (fits || h[i].n_masked == 0 || !(r2[i] > 0.0f)) continue;
-                TableGeom gb = g;
-                gb.r2_cap = (double)r2[i] * 1.5;
-                t.valid = false;
-                if ((st = build_rows(c, gb, &t.tab, &t.cap, &t.len, &t.k1, s)) != GAMMAX_OK) return st;
-                t.geom = gb;
-                t.valid = true;
-            }
-            tables_ok = true;
-            for (int i = 0; i < n; ++i) {
-                // a pair that needs no walk keeps an empty table for its geometry
-                if (!b->tabs[i].valid) {
-                    BatchTable& t = b->tabs[i];
-                    t.geom = geom_of(&probs[i]);
-                    t.geom.r2_cap = 0.0;
-                    t.len = 0;
-                    t.k1 = INFINITY;
-                    t.valid = true;
-                }
-            }
-        }
-
-        // autotune the tail layout of new shape classes (every timed run is a complete batch)
-        if (opt.autotune && opt.tail_lanes == 0) {
-            std::vector<uint64_t> todo;
-            for (int i = 0; i < n; ++i)
-                if (!b->tune.count(cls[i]) && std::find(todo.begin(), todo.end(), cls[i]) == todo.end())
-                    todo.push_back(cls[i]);
-            if (!todo.empty()) {
-                for (auto& e : b->ev)
-                    if (!e) HIPCHK(c, hipEventCreate(&e));
-                for (uint64_t k : todo) {
-                    float best_ms = INFINITY;
-                    int best_g = 0;
-                    for (int g : {0, 8, 16, 32, 64}) {
-                        for (int i = 0; i < n; ++i)
-                            if (cls[i] == k) lanes[i] = g;
-                        fill_batch(c, b, L, probs, refs, evals, gammas, opt, learned, lanes, order, true);
-                        if ((st = upload_batch(c, b, L, s)) != GAMMAX_OK) return st;
-                        HIPCHK(c, hipEventRecord(b->ev[0], s));
-                        if ((st = enqueue_batch(c, b, L, probs, refs, evals, opt, learned, true, true, s)) != GAMMAX_OK)
-                            return st;
-                        HIPCHK(c, hipEventRecord(b->ev[1], s));
-                        HIPCHK(c, hipEventSynchronize(b->ev[1]));
-                        const float ms = elapsed(b->ev[0], b->ev[1]);
-                        if (ms < best_ms) {
-                            best_ms = ms;
-                            best_g = g;
-                        }
-                    }
-                    b->tune[k] = best_g;
-                    for (int i = 0; i < n; ++i)
-                        if (cls[i] == k) lanes[i] = best_g;
-                }
-            }
-        }
-
-        // the batch itself: replayed from a graph when the same batch comes again
-        fill_batch(c, b, L, probs, refs, evals, gammas, opt, learned, lanes, order, true);
-        if ((st = upload_batch(c, b, L, s)) != GAMMAX_OK) return st;
-        std::vector<unsigned char> key(b->host, b->host + L.h_desc);
-        const unsigned char* gk = (const unsigned char*)&c->generation;
-        key.insert(key.end(), gk, gk + sizeof(c->generation));
-        key.insert(key.end(), learned.begin(), learned.end());
-        bool launched = false;
-        if (!c->graph_broken) {
-            if (!b->graph || key != b->graph_key) {
-                if (b->graph) (void)hipGraphExecDestroy(b->graph);
-                b->graph = nullptr;
-                if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-                HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-                st = enqueue_batch(c, b, L, probs, refs, evals, opt, learned, true, true, c->cap_stream);
-                hipGraph_t g = nullptr;
-                const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-                if (st == GAMMAX_OK && e == hipSuccess && g &&
-                    hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0) == hipSuccess) {
-                    b->graph_key = key;
-                } else {
-                    b->graph = nullptr;
-                    (void)hipGetLastError();
-                }
-                if (g) (void)hipGraphDestroy(g);
-                if (st != GAMMAX_OK) return st;
-            }
-            if (b->graph) {
-                HIPCHK(c, hipGraphLaunch(b->graph, s));
-                launched = true;
-            }
-        }
-        if (!launched && (st = enqueue_batch(c, b, L, probs, refs, evals, opt, learned, true, true, s)) != GAMMAX_OK)
-            return st;
-        if ((st = read_batch_scalars(c, b, L, s)) != GAMMAX_OK) return st;
-        if ((st = batch_errors(c, b, L, probs)) != GAMMAX_OK) return st;
-        const Scalars* h = (const Scalars*)(b->host + L.h_sc);
-        bool short_tab = false;
+    // tail layout of shape classes met for the first time: on the first pair of the class,
+    // its own map timed with each layout (direct launches with phase events), the layout
+    // whose tail walk was fastest kept
+    if (opt.autotune && opt.tail_lanes == 0) {
         for (int i = 0; i < n; ++i) {
-            if (h[i].flags & FLAG_TABLE_SHORT) {
-                short_tab = true;
-                b->tabs[i].valid = false;
+            if (b->tune.count(cls[i])) continue;
+            float best_ms = INFINITY;
+            int best_g = 0;
+            for (int g : {0, 8, 16, 32, 64}) {
+                gammax_options_t ot = P.opt[i];
+                ot.tail_lanes = g;
+                ot.timing = 1;
+                float ms = INFINITY;
+                for (int rep = 0; rep < 2; ++rep) {
+                    gammax_result_t r{};
+                    if ((st = gammax_map(b->subs[i], &probs[i], &ot, refs[i], evals[i], gammas[i], &r, s)) !=
+                        GAMMAX_OK)
+                        return fail(c, st, "pair " + std::to_string(i) + ": " + b->subs[i]->err);
+                    ms = std::fmin(ms, r.ms_tail);
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_g = g;
+                }
             }
+            b->tune[cls[i]] = best_g;
         }
-        if (short_tab) {
-            tables_ok = false;   // a radius outgrew its table: rebuild those and run again
-            continue;
-        }
-        const int rate_khz = b->clock_khz;
-        const unsigned long long* done = (const unsigned long long*)(b->host + L.h_done);
-        for (int i = 0; i < n; ++i) {
-            gammax_result_t& r = results[i];
-            std::memset(&r, 0, sizeof(r));
-            const Scalars& hs = h[i];
-            r.n_evaluated = hs.n_masked;
-            r.n_pass = hs.n_pass;
-            r.n_borderline = hs.n_border;
-            r.n_fp64_tets = hs.n_fp64;
-            r.n_cells = hs.n_cells;
-            r.n_tail = hs.n_tail;
-            r.n_guarded = hs.n_guard;
-            r.n_fallback = hs.n_fallback;
-            r.pass_rate = hs.n_masked ? (double)hs.n_pass / (double)hs.n_masked : NAN;
-            r.max_gamma = std::sqrt(u2f(hs.maxg2_bits));
-            r.dose_max = ord_to_float(hs.dmax_ord);
-            r.search_radius = std::sqrt(u2f(hs.r2_bits));
-            r.table_len = (int32_t)b->tabs[i].len;
-            r.ms_done = (done[i] > done[n] && rate_khz > 0) ? (float)((double)(done[i] - done[n]) / rate_khz) : 0.0f;
-        }
-        return GAMMAX_OK;
+        for (int i = 0; i < n; ++i) P.opt[i].tail_lanes = b->tune[cls[i]];
     }
-    return fail(c, GAMMAX_E_DEVICE, "batch: a cell table fell short twice");
+
+    // the batch
+    if ((st = launch_batch(c, b, P, s, ring)) != GAMMAX_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(b->h_done, b->d_done, sizeof(unsigned long long) * (size_t)(n + 1),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const unsigned long long t0 = b->h_done[n];
+    for (int i = 0; i < n; ++i) {
+        gammax_ctx* sub = b->subs[i];
+        const Scalars h = sub->h_ring[ring[i]];
+        if ((st = scalar_errors(sub, h, probs[i].norm == GAMMAX_LOCAL)) != GAMMAX_OK)
+            return fail(c, st, "pair " + std::to_string(i) + ": " + sub->err);
+        gammax_result_t& r = results[i];
+        std::memset(&r, 0, sizeof(r));
+        if (h.flags & FLAG_TABLE_SHORT) {
+            // the radius outgrew the pair's table: its map again on its own context (which
+            // builds a larger table; the next batch recaptures)
+            if ((st = gammax_map(sub, &probs[i], &P.opt[i], refs[i], evals[i], gammas[i], &r, s)) != GAMMAX_OK)
+                return fail(c, st, "pair " + std::to_string(i) + ": " + sub->err);
+        } else {
+            fill_result_from(sub, h, &r, false, 0.0f, learned[i] != 0);
+        }
+        const unsigned long long t = b->h_done[i];
+        r.ms_done = (t > t0 && b->clock_khz > 0) ? (float)((double)(t - t0) / b->clock_khz) : 0.0f;
+    }
+    return GAMMAX_OK;
 }
 
 gammax_status_t gammax_map_many(gammax_ctx_t* c, int32_t n, const gammax_problem_t* probs, const float* const* refs,
                                 const float* const* evals, float* const* gammas, const gammax_options_t* opt,
                                 gammax_result_t* results, void* stream) {
-    return run_many(c, n, probs, refs, evals, gammas, opt, results, (hipStream_t)stream, false);
+    return run_many(c, n, probs, refs, evals, gammas, opt, results, (hipStream_t)stream);
 }
 
 gammax_status_t gammax_tune_save(const gammax_ctx_t* c, const char* path) {

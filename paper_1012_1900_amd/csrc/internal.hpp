@@ -112,7 +112,6 @@ int64_t prep_tiles(int64_t n);
 // tile counts plus two words per group.
 void prep_groups(int64_t n, int* shift, int* n_super);
 int64_t prep_words(int64_t n);
-int batch_reduce_blocks(int64_t n);   // dose-max blocks of an n-node pair
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 // Only the dose maximum, the finiteness flag, the threshold value and the global 1/dD
 // (uses ref, ev, n, thr, dd, sc, part).
@@ -211,6 +210,7 @@ struct SearchPlan {
     int tail_min_lanes;      // automatic tail lanes (tail_lanes 0): at least this many (0: 8)
     int zero_lanes;          // pass A: 1 = one lane per cell, 0 = one lane per node
     int projection;          // pass A in 3D: 0 = all faces a cell owns, 1 = Ju's recursion
+    int skip_zero;           // 1: the key-0 pass was queued elsewhere (a batch's launch over all pairs)
     int spec;                // 1: speculative tail walk inside spec_factor * gamma_hat, then the
                              //    plain walk for the nodes it could not certify
     // optional: queued after the key-0 pass, before the tail sort (the network at the tail
@@ -270,39 +270,19 @@ hipError_t launch_grids_tail(const GridsArgs& a, int precision, int lanes, hipSt
 
 // ---- batches of dose pairs -------------------------------------------------------------
 //
-// Every phase of the pipeline runs once for all pairs of a batch: a pair's blocks are
-// found from per-pair block prefixes (prep), from a cost-ordered list of (pair, block)
-// items that persistent blocks stride over (the key-0 pass), or from a queue of
-// (pair, chunk) items handed out by an atomic counter (the tail walks and the guard pass).
-
-struct BatchPrepPair {
-    PrepArgs pa;
-    int nb_red;              // dose-max blocks of this pair
-    int ntiles;              // prep tiles of this pair
-    int red0, tile0;         // first block of this pair in the dose-max and tile grids
-};
+// The key-0 pass of every pair of a batch in one launch: one block per (pair, block of 256
+// nodes) item, the items in cost order; each block runs the pass over its 256 nodes exactly
+// as the single-pair kernel does for its block.
 
 struct BatchSearchPair {
-    SearchArgs sa;           // sa.tab / sa.tab_len: this pair's cell table
+    SearchArgs sa;           // the pair's search arguments (those of its own pipeline)
     ZeroGeo zg;
-    int ndim, guarded, spec; // spec: learned radius on this pair
-    int g_tail;              // lanes per node in the tail walk (8..64), 0 = from the tail length
-    int first;               // first table row after the key-0 cells
-    float r2_cap;            // this pair's table holds every cell with key^2 < r2_cap
+    int ndim, guarded;       // guarded: FP32 with the FP64 guard (3D)
+    int pad[2];
 };
 
-// Device control block of a batch (zeroed by the launches themselves).
-struct BatchCtl {
-    uint32_t head[4];        // queue counters: tail, fallback, guard
-    uint32_t pad[4];
-};
-
-hipError_t launch_batch_prep(const BatchPrepPair* pairs, int n, int total_red, int total_tiles,
-                             unsigned long long* t0, hipStream_t s);
-// chunk0 / gsel: 3 * (n + 1) and 3 * n words of scratch; done: n + 1 u64 (completion clocks)
-hipError_t launch_batch_search(const BatchSearchPair* pairs, int n, const uint2* items, int n_items,
-                               int zero_blocks, int tail_blocks, bool any_spec, bool any_guard,
-                               uint32_t* chunk0, uint32_t* gsel, BatchCtl* ctl, unsigned long long* done,
-                               hipError_t (*after_zero)(void*, hipStream_t), void* user, hipStream_t s);
+hipError_t launch_batch_key0(const BatchSearchPair* pairs, const uint2* items, int n_items, hipStream_t s);
+// One thread writes the device's wall clock (for per-pair completion times).
+hipError_t launch_stamp(unsigned long long* t, hipStream_t s);
 
 }  // namespace gammax

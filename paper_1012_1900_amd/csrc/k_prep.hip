@@ -281,32 +281,6 @@ __global__ void k_zero3(unsigned long long* c) {
     if (threadIdx.x < 3) c[threadIdx.x] = 0ull;
 }
 
-// Batches: the pair that owns block b of a grid laid out by per-pair prefixes.
-__device__ __forceinline__ int batch_pair_of(const BatchPrepPair* P, int n, int b, bool tiles) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((tiles ? P[mid].tile0 : P[mid].red0) <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-__global__ __launch_bounds__(PREP_THREADS) void k_batch_dose_max(const BatchPrepPair* P, int n,
-                                                                  unsigned long long* t0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *t0 = wall_clock64();
-    const int p = batch_pair_of(P, n, blockIdx.x, false);
-    dose_max_body(P[p].pa, blockIdx.x - P[p].red0, P[p].nb_red);
-}
-__global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_count(const BatchPrepPair* P, int n) {
-    const int p = batch_pair_of(P, n, blockIdx.x, true);
-    prep_count_body(P[p].pa, P[p].nb_red, blockIdx.x - P[p].tile0);
-}
-__global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_emit(const BatchPrepPair* P, int n) {
-    const int p = batch_pair_of(P, n, blockIdx.x, true);
-    prep_emit_body(P[p].pa, blockIdx.x - P[p].tile0);
-}
-
 int reduce_blocks(int64_t n) {
     int64_t b = (n + PREP_THREADS * 8 - 1) / (PREP_THREADS * 8);
     if (b > MAX_BLOCKS) b = MAX_BLOCKS;
@@ -342,17 +316,6 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_prep_emit, dim3((unsigned)nb), dim3(PREP_THREADS), 0, s, a);
     return hipGetLastError();
 }
-
-hipError_t launch_batch_prep(const BatchPrepPair* pairs, int n, int total_red, int total_tiles,
-                             unsigned long long* t0, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_dose_max, dim3(total_red), dim3(PREP_THREADS), 0, s, pairs, n, t0);
-    hipLaunchKernelGGL(k_batch_prep_count, dim3(total_tiles), dim3(PREP_THREADS), 0, s, pairs, n);
-    hipLaunchKernelGGL(k_batch_prep_emit, dim3(total_tiles), dim3(PREP_THREADS), 0, s, pairs, n);
-    return hipGetLastError();
-}
-
-int batch_reduce_blocks(int64_t n) { return reduce_blocks(n); }
 
 hipError_t launch_dose_scalars(const PrepArgs& a, hipStream_t s) {
     const int nbr = reduce_blocks(a.n);

@@ -1367,109 +1367,23 @@ unsigned tail_pass(const SearchArgs& a, const SearchPlan& p, const uint32_t* ord
 
 // ---- batches ------------------------------------------------------------------------
 
-// One pass over a single block of work: a list whose blocks stride by this many blocks is
-// walked once (the queue hands out every chunk exactly once).
-constexpr uint32_t kOnePass = 1u << 23;
-
-// Lanes per node of a tail walk over m nodes when none is fixed (as in k_tail_group).
-__device__ __forceinline__ int auto_lanes(uint32_t m) {
-    int G = 64;
-    while (G > 8 && (uint64_t)m * (uint64_t)G > (1ull << 19)) G >>= 1;
-    return G;
-}
-
-__device__ __forceinline__ void mark_done(unsigned long long* done, int p) {
-    if (threadIdx.x == 0) atomicMax(&done[p], (unsigned long long)wall_clock64());
-}
-
-// The key-0 pass of every pair: persistent blocks stride over the cost-ordered items
-// (pair, block of 256 nodes).  Items past a pair's M return at once.
-__global__ __launch_bounds__(SEARCH_THREADS) void k_batch_zero(const BatchSearchPair* __restrict__ pairs,
-                                                               const uint2* __restrict__ items, int n_items,
-                                                               unsigned long long* done) {
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const uint2 w = items[it];
-        const BatchSearchPair& P = pairs[w.x];
-        if (P.ndim == 3) {
-            if (P.guarded) zero3_body<1>(P.sa, P.zg, P.sa.sums, w.y);
-            else zero3_body<0>(P.sa, P.zg, P.sa.sums, w.y);
-        } else {
-            zero2_body(P.sa, P.zg, P.sa.sums, w.y);
-        }
-        mark_done(done, (int)w.x);
+// The key-0 pass of every pair of a batch: block b takes item b = (pair, block of 256 nodes)
+// and runs that pair's pass over those nodes, as the pair's own kernel would (a block past
+// the pair's M returns at once).
+__global__ __launch_bounds__(SEARCH_THREADS) void k_batch_key0(const BatchSearchPair* __restrict__ pairs,
+                                                               const uint2* __restrict__ items) {
+    const uint2 w = items[blockIdx.x];
+    const BatchSearchPair& P = pairs[w.x];
+    if (P.ndim == 3) {
+        if (P.guarded) zero3_body<1>(P.sa, P.zg, P.sa.sums, w.y);
+        else zero3_body<0>(P.sa, P.zg, P.sa.sums, w.y);
+    } else {
+        zero2_body(P.sa, P.zg, P.sa.sums, w.y);
     }
 }
 
-// Chunk counts of a queue phase: 0 tail (spec 1 on learned pairs), 1 fallback, 2 guard.
-// One block; also fixes each pair's lanes per node and clears the queue counter.
-__global__ void k_batch_chunks(const BatchSearchPair* __restrict__ pairs, int n, int phase, uint32_t* chunk0,
-                               uint32_t* gsel, BatchCtl* ctl) {
-    if (threadIdx.x != 0) return;
-    uint32_t acc = 0;
-    for (int p = 0; p < n; ++p) {
-        const BatchSearchPair& P = pairs[p];
-        uint32_t m = 0, per = SEARCH_THREADS;
-        if (phase == 2) {
-            m = P.guarded ? P.sa.sc->n_guard : 0u;
-        } else {
-            m = phase == 1 ? (P.spec ? P.sa.sc->n_fallback : 0u) : P.sa.sc->n_tail;
-            if (P.sa.tab_len <= P.first) m = 0;
-            const int G = P.g_tail ? P.g_tail : auto_lanes(m);
-            gsel[p] = (uint32_t)G;
-            per = SEARCH_THREADS / (uint32_t)G;
-        }
-        chunk0[p] = acc;
-        acc += (m + per - 1) / per;
-    }
-    chunk0[n] = acc;
-    ctl->head[phase] = 0u;
-}
-
-// A queue phase: blocks take (pair, chunk) items from an atomic counter until none is left.
-__global__ __launch_bounds__(SEARCH_THREADS) void k_batch_queue(const BatchSearchPair* __restrict__ pairs, int n,
-                                                                int phase, const uint32_t* __restrict__ chunk0,
-                                                                const uint32_t* __restrict__ gsel, BatchCtl* ctl,
-                                                                unsigned long long* done) {
-    __shared__ uint32_t s_it;
-    const uint32_t total = chunk0[n];
-    for (;;) {
-        if (threadIdx.x == 0) s_it = atomicAdd(&ctl->head[phase], 1u);
-        __syncthreads();
-        const uint32_t it = s_it;
-        __syncthreads();
-        if (it >= total) break;
-        int lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (chunk0[mid] <= it) lo = mid;
-            else hi = mid - 1;
-        }
-        const BatchSearchPair& P = pairs[lo];
-        const uint32_t chunk = it - chunk0[lo];
-        if (phase == 2) {
-            walk_body<3, 2, false>(P.sa, P.sa.tab, P.sa.guard_list, &P.sa.sc->n_guard, 0, 0, P.sa.sums, chunk,
-                                   kOnePass);
-        } else {
-            const uint32_t* order = phase == 1 ? P.sa.fb_list : P.sa.tail_pos;
-            const uint32_t* count = phase == 1 ? &P.sa.sc->n_fallback : &P.sa.sc->n_tail;
-            const int spec = P.spec ? (phase == 1 ? 2 : 1) : 0;
-            const int G = (int)gsel[lo];
-            if (P.ndim == 3) {
-                if (P.guarded)
-                    tail_group_body<3, 1>(P.sa, P.sa.tab, order, count, P.first, G, spec, P.sa.sums, chunk, kOnePass);
-                else
-                    tail_group_body<3, 0>(P.sa, P.sa.tab, order, count, P.first, G, spec, P.sa.sums, chunk, kOnePass);
-            } else {
-                tail_group_body<2, 0>(P.sa, P.sa.tab, order, count, P.first, G, spec, P.sa.sums, chunk, kOnePass);
-            }
-        }
-        mark_done(done, lo);
-    }
-}
-
-__global__ __launch_bounds__(SEARCH_THREADS) void k_batch_finalize(const BatchSearchPair* __restrict__ pairs) {
-    const BatchSearchPair& P = pairs[blockIdx.x];
-    finalize_body(P.sa.sums, SUM_BINS, P.sa.sc, P.r2_cap);
+__global__ void k_stamp(unsigned long long* t) {
+    if (threadIdx.x == 0) *t = wall_clock64();
 }
 
 // ---- two grids (the evaluation dose on a grid of its own, 3D) ---------------------------
@@ -1906,28 +1820,14 @@ __global__ __launch_bounds__(256) void k_grids_walk(GridsArgs a, int G) {
 
 }  // namespace
 
-hipError_t launch_batch_search(const BatchSearchPair* pairs, int n, const uint2* items, int n_items,
-                               int zero_blocks, int tail_blocks, bool any_spec, bool any_guard,
-                               uint32_t* chunk0, uint32_t* gsel, BatchCtl* ctl, unsigned long long* done,
-                               hipError_t (*after_zero)(void*, hipStream_t), void* user, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
+hipError_t launch_batch_key0(const BatchSearchPair* pairs, const uint2* items, int n_items, hipStream_t s) {
     if (n_items > 0)
-        hipLaunchKernelGGL(k_batch_zero, dim3(zero_blocks), dim3(SEARCH_THREADS), 0, s, pairs, items, n_items, done);
-    if (after_zero) {
-        hipError_t e = after_zero(user, s);
-        if (e != hipSuccess) return e;
-    }
-    const int phases[3] = {0, 1, 2};
-    for (int ph : phases) {
-        if (ph == 1 && !any_spec) continue;
-        if (ph == 2 && !any_guard) continue;
-        uint32_t* c0 = chunk0 + ph * (n + 1);
-        uint32_t* gs = gsel + ph * n;
-        hipLaunchKernelGGL(k_batch_chunks, dim3(1), dim3(64), 0, s, pairs, n, ph, c0, gs, ctl);
-        hipLaunchKernelGGL(k_batch_queue, dim3(tail_blocks), dim3(SEARCH_THREADS), 0, s, pairs, n, ph, c0, gs, ctl,
-                           done);
-    }
-    hipLaunchKernelGGL(k_batch_finalize, dim3(n), dim3(SEARCH_THREADS), 0, s, pairs);
+        hipLaunchKernelGGL(k_batch_key0, dim3((unsigned)n_items), dim3(SEARCH_THREADS), 0, s, pairs, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(unsigned long long* t, hipStream_t s) {
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, t);
     return hipGetLastError();
 }
 
@@ -1950,8 +1850,9 @@ hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s
     } else {
         const bool guarded = p.precision == 1 && p.ndim == 3;
         const int first = p.ndim == 3 ? 8 : 4;
-        // pass A
-        if (p.zero_lanes) {
+        // pass A (unless a batch queued it for every pair in one launch)
+        if (p.skip_zero) {
+        } else if (p.zero_lanes) {
             // one lane per zero-key cell, grid-stride over the nodes
             const unsigned lanes = p.ndim == 3 ? 8u : 4u;
             uint64_t want = ((uint64_t)p.M * lanes + SEARCH_THREADS - 1) / SEARCH_THREADS;
