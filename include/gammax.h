@@ -286,24 +286,6 @@ gammax_status_t gammax_sort_pairs(gammax_ctx_t *ctx, uint32_t *keys_dev, uint32_
                                   int64_t n, void *stream);
 
 /*
- * For callers that cannot allocate device memory (code under HIP graph capture, tight
- * serving loops, harnesses that forbid hipMalloc): the sort of gammax_sort_pairs without a
- * context and without any allocation.  It runs on the current HIP device and queues its
- * kernels on `stream` without waiting (keys_dev and vals_dev hold the sorted pairs once the
- * stream has passed it); it calls no hipMalloc, hipFree or other allocating routine.
- * Its scratch (two staging arrays of GAMMAX_SORT_STATIC_MAX words and the radix
- * histograms, about 9.4 MB) is a static device array of the library: one copy per GPU the
- * library runs on, held until the process ends, its address looked up on the first call on
- * each device.  Every call on a GPU uses that GPU's one copy: calls that overlap on one GPU
- * (on different streams or threads) race; order them.
- *   n in [0, GAMMAX_SORT_STATIC_MAX]; a larger n returns GAMMAX_E_PARAM (use
- *   gammax_sort_pairs), NULL keys/vals with n > 0 GAMMAX_E_NULL, a failed launch
- *   GAMMAX_E_DEVICE.  Results are those of gammax_sort_pairs (stable, ascending).
- */
-#define GAMMAX_SORT_STATIC_MAX 1048576
-gammax_status_t gammax_sort_pairs_static(uint32_t *keys_dev, uint32_t *vals_dev, int64_t n, void *stream);
-
-/*
  * The radially sorted cell table (Algorithm A1 steps 2-3, Algorithm A2 steps 4-5).
  * Lists every cell offset a (lower corner relative to the reference node, slowest axis
  * first) that can hold a grid cell of `shape` and whose key

@@ -420,30 +420,6 @@ def sort_pairs(keys, vals, ctx: Optional[Context] = None):
     return keys, vals
 
 
-SORT_STATIC_MAX = 1048576
-_lib.gammax_sort_pairs_static.restype = C.c_int
-_lib.gammax_sort_pairs_static.argtypes = [_vp, _vp, C.c_int64, _vp]
-
-
-def sort_pairs_static(keys, vals, stream=None):
-    """``gammax_sort_pairs_static``: the same sort without a context or any allocation (its
-    scratch is a static device array of the library, one per GPU, so calls that overlap on
-    one GPU race).  Queued on ``stream`` (default: the current stream) without waiting; at
-    most SORT_STATIC_MAX pairs."""
-    torch = _torch()
-    for t, nm in ((keys, "keys"), (vals, "vals")):
-        if t.device.type != "cuda" or t.dtype != torch.int32 or not t.is_contiguous():
-            raise TypeError(f"{nm} must be a contiguous int32 device tensor")
-    if keys.numel() != vals.numel():
-        raise ValueError("keys and vals differ in length")
-    s = stream if stream is not None else torch.cuda.current_stream(keys.device)
-    with torch.cuda.device(keys.device):
-        st = _lib.gammax_sort_pairs_static(keys.data_ptr(), vals.data_ptr(), keys.numel(), _vp(s.cuda_stream))
-    if st != OK:
-        raise GammaxError(st, f"{keys.numel()} pairs")
-    return keys, vals
-
-
 def build_table(shape: Sequence[int], spacing_over_dta: Sequence[float], radius: float,
                 cap: Optional[int] = None, device: int = 0, ctx: Optional[Context] = None):
     """Sorted cell table: (key2 float32 tensor [T], offsets int32 tensor [T, 3])."""
