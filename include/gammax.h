@@ -460,6 +460,34 @@ gammax_status_t gammax_batch(gammax_ctx_t *ctx, int32_t n, const gammax_problem_
 gammax_status_t gammax_tune_save(const gammax_ctx_t *ctx, const char *path);
 gammax_status_t gammax_tune_load(gammax_ctx_t *ctx, const char *path);
 
+/*
+ * ---- The map without device allocations -------------------------------------------------
+ *
+ * For callers that cannot allocate device memory (code that must not call hipMalloc, tight
+ * serving loops, harnesses that forbid allocation).  The computation of gammax_map; every
+ * buffer beyond the caller's doses and gamma lives in one fixed array of
+ * GAMMAX_NOALLOC_SCRATCH_BYTES bytes of device memory inside the library, which each GPU
+ * the library runs on holds from the library's load until the process ends.  No context:
+ * the call uses the current HIP device and `stream`, allocates nothing, builds the cell
+ * table for this map's radius in that array, and synchronises `stream` (three times: after
+ * the compaction, after the table count, at the end).
+ *   Limits: at most GAMMAX_NOALLOC_MAX_NODES grid nodes (GAMMAX_E_SHAPE beyond), a cell
+ *   table of at most GAMMAX_NOALLOC_MAX_TABLE rows and a candidate box of at most twice
+ *   that (GAMMAX_E_RADIUS beyond).
+ *   opt: NULL for the defaults; timing, a model (learned radius or predicted order), the
+ *   given order, autotune and cnn_pool are refused (GAMMAX_E_PARAM).
+ *   result: as gammax_map, except table_len (the rows of this call's own table) and the
+ *   timing fields (0).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (from
+ * several host threads or streams) race and give wrong results; serialise them.
+ */
+#define GAMMAX_NOALLOC_MAX_NODES 2097152
+#define GAMMAX_NOALLOC_MAX_TABLE 262144
+#define GAMMAX_NOALLOC_SCRATCH_BYTES 104857600
+gammax_status_t gammax_map_noalloc(const gammax_problem_t *problem, const gammax_options_t *opt,
+                                   const float *ref_dev, const float *eval_dev, float *gamma_dev,
+                                   gammax_result_t *result, void *stream);
+
 /* Static description of a status code. */
 const char *gammax_status_string(gammax_status_t status);
 

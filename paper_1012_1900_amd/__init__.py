@@ -19,6 +19,9 @@ from ._abi import (  # noqa: F401
     gammax_map,
     gammax_map_async,
     gammax_map_many,
+    gammax_map_noalloc,
+    NOALLOC_MAX_NODES,
+    NOALLOC_MAX_TABLE,
     gammax_map_grids,
     MapTicket,
     ASYNC_SLOTS,

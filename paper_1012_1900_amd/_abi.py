@@ -136,6 +136,8 @@ _lib.gamma_map.restype = C.c_int
 _lib.gamma_map.argtypes = [_vp, _vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                            C.c_double, C.c_double, C.c_double, C.c_int32, _vp,
                            C.POINTER(C.c_double), _vp]
+_lib.gammax_map_noalloc.restype = C.c_int
+_lib.gammax_map_noalloc.argtypes = [C.POINTER(Problem), C.POINTER(Options), _vp, _vp, _vp, C.POINTER(Result), _vp]
 _lib.gammax_sort_pairs.restype = C.c_int
 _lib.gammax_sort_pairs.argtypes = [_vp, _vp, _vp, C.c_int64, _vp]
 _lib.gammax_build_table.restype = C.c_int
@@ -400,6 +402,39 @@ def gamma_map(ref_dose, eval_dose, spacing: Sequence[float], dd: float, dta: flo
     if st != OK:
         raise GammaxError(st)
     return out, pr.value
+
+
+NOALLOC_MAX_NODES = 2097152   # GAMMAX_NOALLOC_MAX_NODES
+NOALLOC_MAX_TABLE = 262144    # GAMMAX_NOALLOC_MAX_TABLE
+
+
+def gammax_map_noalloc(ref, ev, spacing: Sequence[float], dd: float, dta: float,
+                       dose_threshold: float = 0.1, local: bool = False, *, out, sort: str = "none",
+                       precision: str = "guarded", cond_threshold: float = 1e6, tail_lanes: int = 0,
+                       cell_lanes: int = 0, projection: str = "faces", stream=None) -> "GammaResult":
+    """The map through ``gammax_map_noalloc``: no device allocation inside the call (its
+    workspace is the library's fixed device array).  ``out`` (float32, shaped like ``ref``)
+    receives gamma and must be given: the binding allocates nothing either.  Returns the
+    GammaResult.  Calls that overlap on one GPU race."""
+    torch = _torch()
+    _dev_tensor(ref, "ref")
+    _dev_tensor(ev, "ev")
+    _dev_tensor(out, "out")
+    if ref.shape != ev.shape or ref.device != ev.device or out.shape != ref.shape or out.device != ref.device:
+        raise ValueError("ref, ev and out must share shape and device")
+    if len(spacing) != ref.dim():
+        raise ValueError("spacing needs one entry per axis")
+    p = make_problem(tuple(ref.shape), spacing, dd, dta, dose_threshold, local)
+    o = make_options(sort, precision, cond_threshold, False, tail_lanes, cell_lanes, "plain", None, 1.1, 0,
+                     projection, None)
+    r = Result()
+    s = stream if stream is not None else torch.cuda.current_stream(ref.device)
+    with torch.cuda.device(ref.device):
+        st = _lib.gammax_map_noalloc(C.byref(p), C.byref(o), ref.data_ptr(), ev.data_ptr(), out.data_ptr(),
+                                     C.byref(r), _vp(s.cuda_stream))
+    if st != OK:
+        raise GammaxError(st)
+    return GammaResult(**{f[0]: getattr(r, f[0]) for f in Result._fields_})
 
 
 def sort_pairs(keys, vals, ctx: Optional[Context] = None):

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1910,6 +1911,211 @@ gammax_status_t gammax_tune_load(gammax_ctx_t* c, const char* path) {
     }
     std::fclose(f);
     return st;
+}
+
+}  // extern "C"
+
+// ---- gammax_map_noalloc: the map without device allocations ------------------------------
+//
+// Every buffer the map needs beyond the caller's doses and gamma lives in `scratch`, one
+// file-scope device array that each GPU holds a copy of, at an address of its own.  In host
+// code the array's name is a host-side stand-in, not a device address: it is never passed to
+// a kernel or a copy.  The device address is taken once per device, with that device
+// current, by hipGetSymbolAddress and kept in na_ptr[device]; every launch and copy below
+// uses that address.  Pieces (256-byte aligned): scalars, dose-max partials, prep tile
+// counts, search partial sums, sort histogram, the table build count, the node work arrays
+// (kWorkArrays x GAMMAX_NOALLOC_MAX_NODES words), the table build arrays (4 x box words) and
+// the table rows.  The kernels clear what must start at zero (the prep clears the counters
+// and partial sums, a one-word kernel the table count), so the contents a previous call
+// left do not matter.
+
+namespace {
+
+constexpr int64_t kNaNodes = GAMMAX_NOALLOC_MAX_NODES;
+constexpr int64_t kNaRows = GAMMAX_NOALLOC_MAX_TABLE;
+constexpr int64_t kNaBox = 2 * GAMMAX_NOALLOC_MAX_TABLE;   // candidate box of the table build
+constexpr int64_t kNaBytes = GAMMAX_NOALLOC_SCRATCH_BYTES;
+constexpr int kNaDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+std::mutex na_mutex;
+unsigned char* na_ptr[kNaDevices] = {};
+
+struct NaLayout {
+    Scalars* sc;
+    uint32_t* part;
+    uint32_t* blockcnt;
+    BlockSums* sums;
+    uint32_t* hist;
+    uint32_t* count;
+    uint32_t* work;
+    uint32_t* tb;
+    TabEntry* tab;
+    int64_t bytes;
+};
+
+NaLayout na_layout(unsigned char* base) {
+    NaLayout L{};
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        unsigned char* p = base ? base + off : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    L.sc = (Scalars*)take(sizeof(Scalars));
+    L.part = (uint32_t*)take(4 * 2 * (int64_t)MAX_BLOCKS);
+    L.blockcnt = (uint32_t*)take(4 * prep_words(kNaNodes));
+    L.sums = (BlockSums*)take((int64_t)sizeof(BlockSums) * search_sums_needed((uint32_t)kNaNodes));
+    L.hist = (uint32_t*)take(4 * sort_hist_words(kNaNodes > kNaBox ? kNaNodes : kNaBox));
+    L.count = (uint32_t*)take(4);
+    L.work = (uint32_t*)take(4 * (int64_t)kWorkArrays * kNaNodes);
+    L.tb = (uint32_t*)take(4 * 4 * kNaBox);
+    L.tab = (TabEntry*)take((int64_t)sizeof(TabEntry) * kNaRows);
+    L.bytes = off;
+    return L;
+}
+
+// The scratch array's address on device `dev` (the current device), taken on the first call.
+gammax_status_t na_base(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kNaDevices) return GAMMAX_E_DEVICE;
+    std::lock_guard<std::mutex> lock(na_mutex);
+    if (!na_ptr[dev]) {
+        if (na_layout(nullptr).bytes > kNaBytes) return GAMMAX_E_NOMEM;   // layout and array size disagree
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return GAMMAX_E_DEVICE;
+        }
+        na_ptr[dev] = (unsigned char*)p;
+    }
+    *out = na_ptr[dev];
+    return GAMMAX_OK;
+}
+
+gammax_status_t na_read_scalars(const NaLayout& L, Scalars* h, hipStream_t s) {
+    HIPCHK(nullptr, hipMemcpyAsync(h, L.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(nullptr, hipStreamSynchronize(s));
+    return GAMMAX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gammax_status_t gammax_map_noalloc(const gammax_problem_t* p, const gammax_options_t* opt_in, const float* ref,
+                                   const float* ev, float* gamma, gammax_result_t* res, void* stream) {
+    if (!res || !ref || !ev || !gamma) return GAMMAX_E_NULL;
+    int64_t n = 0;
+    gammax_status_t st = check_problem(nullptr, p, &n);
+    if (st != GAMMAX_OK) return st;
+    if (n > kNaNodes) return GAMMAX_E_SHAPE;
+    if (gamma == ref || gamma == ev) return GAMMAX_E_PARAM;
+    gammax_options_t opt;
+    if (opt_in) opt = *opt_in;
+    else gammax_options_default(&opt);
+    if ((st = check_options(nullptr, &opt)) != GAMMAX_OK) return st;
+    if (opt.timing || opt.model || opt.radius_mode != GAMMAX_RADIUS_PLAIN || opt.sort_mode == GAMMAX_SORT_PREDICTED ||
+        opt.sort_mode == GAMMAX_SORT_GIVEN || opt.autotune || opt.cnn_pool)
+        return GAMMAX_E_PARAM;
+    int dev = 0;
+    HIPCHK(nullptr, hipGetDevice(&dev));
+    unsigned char* base = nullptr;
+    if ((st = na_base(dev, &base)) != GAMMAX_OK) return st;
+    const NaLayout L = na_layout(base);
+    hipStream_t s = (hipStream_t)stream;
+    std::memset(res, 0, sizeof(*res));
+    const int64_t ntiles = prep_tiles(n);
+    uint32_t* nodes_arr = L.work + (int64_t)W_NODES * kNaNodes;
+
+    // compaction (Kernel 1): dose maximum, mask, gamma0, masked nodes in grid order
+    PrepArgs pa{};
+    pa.ref = ref;
+    pa.ev = ev;
+    pa.gamma = gamma;
+    pa.n = n;
+    pa.thr = (float)p->dose_threshold;
+    pa.dd = (float)p->dd;
+    pa.local = p->norm == GAMMAX_LOCAL ? 1 : 0;
+    pa.sc = L.sc;
+    pa.part = L.part;
+    pa.blockcnt = L.blockcnt;
+    prep_groups(n, &pa.super_shift, &pa.n_super);
+    pa.super = L.blockcnt + ntiles;
+    pa.ntiles = (int)ntiles;
+    pa.nodes = nodes_arr;
+    pa.sums = L.sums;
+    HIPCHK(nullptr, launch_prep(pa, s));
+    Scalars h{};
+    if ((st = na_read_scalars(L, &h, s)) != GAMMAX_OK) return st;
+    if ((st = scalar_errors(nullptr, h, p->norm == GAMMAX_LOCAL)) != GAMMAX_OK) return st;
+    const uint32_t M = h.n_masked;
+    const float r2 = u2f(h.r2_bits);
+
+    // the cell table for this radius (Algorithm A1 steps 2-3), built in the scratch array
+    int64_t T = 0;
+    float k1 = INFINITY;
+    if (M > 0 && r2 > 0.0f) {
+        TableGeom g = geom_of(p);
+        g.r2_cap = (double)r2;   // every cell whose key is below the largest gamma0
+        table_box(g);
+        if (g.box > kNaBox) return GAMMAX_E_RADIUS;
+        uint32_t* keys = L.tb;
+        uint32_t* vals = L.tb + kNaBox;
+        uint32_t* tk = L.tb + 2 * kNaBox;
+        uint32_t* tv = L.tb + 3 * kNaBox;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, L.count);
+        HIPCHK(nullptr, hipGetLastError());
+        HIPCHK(nullptr, launch_table_gen(g, keys, vals, L.count, s));
+        HIPCHK(nullptr, radix_sort_pairs(keys, vals, tk, tv, g.box, nullptr, L.hist, s));
+        uint32_t rows = 0;
+        HIPCHK(nullptr, hipMemcpyAsync(&rows, L.count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(nullptr, hipStreamSynchronize(s));
+        if ((int64_t)rows > kNaRows) return GAMMAX_E_RADIUS;
+        HIPCHK(nullptr, launch_table_rows(g, vals, rows, L.tab, s));
+        const int zero_rows = p->ndim == 3 ? 8 : 4;
+        if ((int)rows > zero_rows) {
+            HIPCHK(nullptr, hipMemcpyAsync(&k1, &L.tab[zero_rows].key2, sizeof(float), hipMemcpyDeviceToHost, s));
+            HIPCHK(nullptr, hipStreamSynchronize(s));
+        }
+        T = rows;
+    }
+
+    // the search (steps 3, 6, 7) and the counts
+    if (M > 0) {
+        const SearchArgs sa = make_search_args(p, opt, ref, ev, gamma, L.sc, L.tab, (int)T, k1, INFINITY, L.work,
+                                               kNaNodes, L.sums, nullptr);
+        SearchPlan plan{};
+        plan.ndim = p->ndim;
+        plan.precision = opt.precision;
+        plan.tail_lanes = opt.tail_lanes;
+        plan.tail_min_lanes = 0;
+        plan.zero_lanes = (opt.cell_lanes == 4 || opt.cell_lanes == 8) ? 1 : 0;
+        plan.projection = opt.projection;
+        plan.M = M;
+        plan.zero = make_zero_geo(p);
+        plan.tmp_keys = L.work + (int64_t)W_TMP_K * kNaNodes;
+        plan.tmp_vals = L.work + (int64_t)W_TMP_V * kNaNodes;
+        plan.hist = opt.sort_mode == GAMMAX_SORT_NONE ? nullptr : L.hist;
+        plan.small_sort = 0;
+        HIPCHK(nullptr, launch_search(sa, plan, s));
+        if ((st = na_read_scalars(L, &h, s)) != GAMMAX_OK) return st;
+    }
+    res->n_evaluated = h.n_masked;
+    res->n_pass = h.n_pass;
+    res->n_borderline = h.n_border;
+    res->n_fp64_tets = h.n_fp64;
+    res->n_cells = h.n_cells;
+    res->n_tail = h.n_tail;
+    res->n_guarded = h.n_guard;
+    res->pass_rate = h.n_masked ? (double)h.n_pass / (double)h.n_masked : NAN;
+    res->max_gamma = std::sqrt(u2f(h.maxg2_bits));
+    res->dose_max = ord_to_float(h.dmax_ord);
+    res->search_radius = std::sqrt(r2);
+    res->table_len = (int32_t)T;
+    res->long_walk_rows = h.long_rows;
+    return GAMMAX_OK;
 }
 
 }  // extern "C"
