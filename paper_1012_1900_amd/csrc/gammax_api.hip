@@ -604,6 +604,17 @@ SearchArgs make_search_args(const gammax_problem_t* p, const gammax_options_t& o
     sa.s2x = (float)(sx * sx);
     sa.s2y = (float)(sy * sy);
     sa.s2z = (float)(sz * sz);
+    {
+        // FP32 divisions, as the kernels would form them (IEEE round to nearest)
+        const float x2 = sa.s2x, y2 = sa.s2y, z2 = sa.s2z;
+        sa.inv_s2[0] = 1.0f / x2;
+        sa.inv_s2[1] = 1.0f / y2;
+        sa.inv_s2[2] = z2 > 0.0f ? 1.0f / z2 : 0.0f;
+        sa.inv_s2[3] = 1.0f / (x2 + y2);
+        sa.inv_s2[4] = z2 > 0.0f ? 1.0f / (x2 + z2) : 0.0f;
+        sa.inv_s2[5] = z2 > 0.0f ? 1.0f / (y2 + z2) : 0.0f;
+        sa.inv_s2[6] = 1.0f / ((x2 + y2) + z2);
+    }
     double smin = std::fmin(sx, sy), smax = std::fmax(sx, sy);
     if (nd == 3) {
         smin = std::fmin(smin, sz);

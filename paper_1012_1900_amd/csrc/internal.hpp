@@ -178,6 +178,8 @@ struct SearchArgs {
     double dd64;             // DD in double for the FP64 paths
     int local;
     float s2x, s2y, s2z;     // s_i^2, s_i = spacing_i / DTA
+    float inv_s2[7];         // FP32 1 / sigma^2 of the chain blocks x, y, z, xy, xz, yz, xyz
+                             // (sigma_B^2 = sum over B of s_i^2; the z terms are 0 in 2D)
     float den_guard;         // FP64 re-projection when a tetrahedron's Den exceeds this
     double sx, sy, sz;       // s_i in double for the FP64 paths
     float k1;                // key^2 of the first table row after the zero-key cells (+inf: none)

@@ -57,46 +57,69 @@ struct Num<double> {
 template <typename T>
 __device__ __forceinline__ T vmin(T a, T b) { return Num<T>::min(a, b); }
 
-// One chain step: Delta, w = Delta / sigma^2, p = Delta^2 / sigma^2, m = Delta * mu.
+// Fused multiply-add, written out: the projections below form every product-sum they fuse
+// explicitly and the compiler contracts nothing else in them (contraction off), so each
+// instantiation of a face (masked or not, in any kernel and any lane layout) computes the same
+// bits whatever code surrounds it.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// One chain step: Delta and w = Delta / sigma^2 (Delta^2 / sigma^2 = Delta w and Delta mu
+// enter the sums below as fused products).
 template <typename T>
 struct Step {
-    T d, w, p, m;
+    T d, w;
 };
 template <typename T>
-__device__ __forceinline__ Step<T> mk_step(T hi, T lo, T mu, T inv_s2) {
+__device__ __forceinline__ Step<T> mk_step(T hi, T lo, T inv_s2) {
+#pragma clang fp contract(off)
     Step<T> s;
     s.d = hi - lo;
     s.w = s.d * inv_s2;
-    s.p = s.d * s.w;
-    s.m = s.d * mu;
     return s;
 }
+// N after a step: N - Delta mu; Den after a step: Den + Delta^2 / sigma^2.
+template <typename T>
+__device__ __forceinline__ T n_step(T n, const Step<T>& s, T mu) { return fmadd(-s.d, mu, n); }
+template <typename T>
+__device__ __forceinline__ T den_step(T den, const Step<T>& s) { return fmadd(s.d, s.w, den); }
+// Chain parameter of a step at Lambda: t = -mu - w Lambda.
+template <typename T>
+__device__ __forceinline__ T t_step(const Step<T>& s, T mu, T L) { return fmadd(-s.w, L, -mu); }
 
 template <typename T>
 __device__ __forceinline__ T face1(T g0, const Step<T>& a, T mua, T perp) {
-    const T N = g0 - a.m;
-    const T L = N * Num<T>::rcp(T(1) + a.p);
-    const T t1 = -mua - a.w * L;
-    return (t1 >= T(0) && t1 <= T(1)) ? perp + N * L : Num<T>::inf();
+#pragma clang fp contract(off)
+    const T N = n_step(g0, a, mua);
+    const T L = N * Num<T>::rcp(den_step(T(1), a));
+    const T t1 = t_step(a, mua, L);
+    return (t1 >= T(0) && t1 <= T(1)) ? fmadd(N, L, perp) : Num<T>::inf();
 }
 template <typename T>
 __device__ __forceinline__ T face2(T g0, const Step<T>& a, T mua, const Step<T>& b, T mub, T perp) {
-    const T N = (g0 - a.m) - b.m;
-    const T L = N * Num<T>::rcp((T(1) + a.p) + b.p);
-    const T t1 = -mua - a.w * L;
-    const T t2 = -mub - b.w * L;
-    return (t1 <= T(1) && t1 >= t2 && t2 >= T(0)) ? perp + N * L : Num<T>::inf();
+#pragma clang fp contract(off)
+    const T N = n_step(n_step(g0, a, mua), b, mub);
+    const T L = N * Num<T>::rcp(den_step(den_step(T(1), a), b));
+    const T t1 = t_step(a, mua, L);
+    const T t2 = t_step(b, mub, L);
+    return (t1 <= T(1) && t1 >= t2 && t2 >= T(0)) ? fmadd(N, L, perp) : Num<T>::inf();
+}
+// The denominator of a tetrahedron (its guard measure) on its own.
+template <typename T>
+__device__ __forceinline__ T den3(const Step<T>& a, const Step<T>& b, const Step<T>& c) {
+    return den_step(den_step(den_step(T(1), a), b), c);
 }
 template <typename T>
 __device__ __forceinline__ T face3(T g0, const Step<T>& a, T mua, const Step<T>& b, T mub,
                                    const Step<T>& c, T muc, T& den_out) {
-    const T N = ((g0 - a.m) - b.m) - c.m;
-    const T den = ((T(1) + a.p) + b.p) + c.p;
+#pragma clang fp contract(off)
+    const T N = n_step(n_step(n_step(g0, a, mua), b, mub), c, muc);
+    const T den = den3(a, b, c);
     den_out = den;
     const T L = N * Num<T>::rcp(den);
-    const T t1 = -mua - a.w * L;
-    const T t2 = -mub - b.w * L;
-    const T t3 = -muc - c.w * L;
+    const T t1 = t_step(a, mua, L);
+    const T t2 = t_step(b, mub, L);
+    const T t3 = t_step(c, muc, L);
     return (t1 <= T(1) && t1 >= t2 && t2 >= t3 && t3 >= T(0)) ? N * L : Num<T>::inf();
 }
 
@@ -153,6 +176,20 @@ __device__ __forceinline__ InvS2<T> inv_s2(T sx2, T sy2, T sz2) {
     r.xz = sz2 > T(0) ? T(1) / (sx2 + sz2) : T(0);
     r.yz = sz2 > T(0) ? T(1) / (sy2 + sz2) : T(0);
     r.xyz = T(1) / (sx2 + sy2 + sz2);
+    return r;
+}
+
+// The FP32 reciprocals as the host formed them for the search arguments (the same IEEE
+// divisions as inv_s2<float>, once per map instead of once per lane).
+__device__ __forceinline__ InvS2<float> inv_s2_of(const SearchArgs& a) {
+    InvS2<float> r;
+    r.x = a.inv_s2[0];
+    r.y = a.inv_s2[1];
+    r.z = a.inv_s2[2];
+    r.xy = a.inv_s2[3];
+    r.xz = a.inv_s2[4];
+    r.yz = a.inv_s2[5];
+    r.xyz = a.inv_s2[6];
     return r;
 }
 
@@ -221,21 +258,20 @@ __device__ __forceinline__ T dose_norm(T v, T dr, T inv) {
 // Whether any of the six tetrahedra of a 3D cell has a normal-equation denominator above
 // den_guard: the test cell3 applies (GMODE 1), with its chain steps and its summation order.
 __device__ __forceinline__ bool tets_ill(const float* g, const InvS2<float>& is, float den_guard) {
-    auto p = [](float hi, float lo, float inv) {
-        const float d = hi - lo;
-        return d * (d * inv);
-    };
-    const float p0x = p(g[1], g[0], is.x), p0y = p(g[2], g[0], is.y), p0z = p(g[4], g[0], is.z);
-    const float p1y = p(g[3], g[1], is.y), p1z = p(g[5], g[1], is.z);
-    const float p2x = p(g[3], g[2], is.x), p2z = p(g[6], g[2], is.z);
-    const float p4x = p(g[5], g[4], is.x), p4y = p(g[6], g[4], is.y);
-    const float p3z = p(g[7], g[3], is.z), p5y = p(g[7], g[5], is.y), p6x = p(g[7], g[6], is.x);
-    bool ill = ((1.0f + p0x) + p1y) + p3z > den_guard;
-    ill = ill || ((1.0f + p0x) + p1z) + p5y > den_guard;
-    ill = ill || ((1.0f + p0y) + p2x) + p3z > den_guard;
-    ill = ill || ((1.0f + p0y) + p2z) + p6x > den_guard;
-    ill = ill || ((1.0f + p0z) + p4x) + p5y > den_guard;
-    ill = ill || ((1.0f + p0z) + p4y) + p6x > den_guard;
+#pragma clang fp contract(off)
+    const Step<float> s0x = mk_step(g[1], g[0], is.x), s0y = mk_step(g[2], g[0], is.y);
+    const Step<float> s0z = mk_step(g[4], g[0], is.z);
+    const Step<float> s1y = mk_step(g[3], g[1], is.y), s1z = mk_step(g[5], g[1], is.z);
+    const Step<float> s2x = mk_step(g[3], g[2], is.x), s2z = mk_step(g[6], g[2], is.z);
+    const Step<float> s4x = mk_step(g[5], g[4], is.x), s4y = mk_step(g[6], g[4], is.y);
+    const Step<float> s3z = mk_step(g[7], g[3], is.z), s5y = mk_step(g[7], g[5], is.y);
+    const Step<float> s6x = mk_step(g[7], g[6], is.x);
+    bool ill = den3(s0x, s1y, s3z) > den_guard;
+    ill = ill || den3(s0x, s1z, s5y) > den_guard;
+    ill = ill || den3(s0y, s2x, s3z) > den_guard;
+    ill = ill || den3(s0y, s2z, s6x) > den_guard;
+    ill = ill || den3(s0z, s4x, s5y) > den_guard;
+    ill = ill || den3(s0z, s4y, s6x) > den_guard;
     return ill;
 }
 
@@ -247,31 +283,31 @@ template <typename T, bool MASKED, int GMODE>
 __device__ __forceinline__ T cell3(const T* g, const Geo<T>& G, const InvS2<T>& is, bool okx, bool oky,
                                    bool okz, T den_guard, const GuardCtx& gc, uint32_t& n_fp64,
                                    bool& ill) {
+#pragma clang fp contract(off)
     const T INF = Num<T>::inf();
     const T g0 = g[0];
     // chain steps, named by start vertex bits and block (x = bit0, y = bit1, z = bit2)
-    const Step<T> s0x = mk_step(g[1], g[0], G.ax, is.x);
-    const Step<T> s0y = mk_step(g[2], g[0], G.ay, is.y);
-    const Step<T> s0z = mk_step(g[4], g[0], G.az, is.z);
-    const Step<T> s0xy = mk_step(g[3], g[0], G.mxy, is.xy);
-    const Step<T> s0xz = mk_step(g[5], g[0], G.mxz, is.xz);
-    const Step<T> s0yz = mk_step(g[6], g[0], G.myz, is.yz);
-    const Step<T> s0xyz = mk_step(g[7], g[0], G.mxyz, is.xyz);
-    const Step<T> s1y = mk_step(g[3], g[1], G.ay, is.y);
-    const Step<T> s1z = mk_step(g[5], g[1], G.az, is.z);
-    const Step<T> s1yz = mk_step(g[7], g[1], G.myz, is.yz);
-    const Step<T> s2x = mk_step(g[3], g[2], G.ax, is.x);
-    const Step<T> s2z = mk_step(g[6], g[2], G.az, is.z);
-    const Step<T> s2xz = mk_step(g[7], g[2], G.mxz, is.xz);
-    const Step<T> s4x = mk_step(g[5], g[4], G.ax, is.x);
-    const Step<T> s4y = mk_step(g[6], g[4], G.ay, is.y);
-    const Step<T> s4xy = mk_step(g[7], g[4], G.mxy, is.xy);
-    const Step<T> s3z = mk_step(g[7], g[3], G.az, is.z);
-    const Step<T> s5y = mk_step(g[7], g[5], G.ay, is.y);
-    const Step<T> s6x = mk_step(g[7], g[6], G.ax, is.x);
-
+    const Step<T> s0x = mk_step(g[1], g[0], is.x);
+    const Step<T> s0y = mk_step(g[2], g[0], is.y);
+    const Step<T> s0z = mk_step(g[4], g[0], is.z);
+    const Step<T> s0xy = mk_step(g[3], g[0], is.xy);
+    const Step<T> s0xz = mk_step(g[5], g[0], is.xz);
+    const Step<T> s0yz = mk_step(g[6], g[0], is.yz);
+    const Step<T> s0xyz = mk_step(g[7], g[0], is.xyz);
+    const Step<T> s1y = mk_step(g[3], g[1], is.y);
+    const Step<T> s1z = mk_step(g[5], g[1], is.z);
+    const Step<T> s1yz = mk_step(g[7], g[1], is.yz);
+    const Step<T> s2x = mk_step(g[3], g[2], is.x);
+    const Step<T> s2z = mk_step(g[6], g[2], is.z);
+    const Step<T> s2xz = mk_step(g[7], g[2], is.xz);
+    const Step<T> s4x = mk_step(g[5], g[4], is.x);
+    const Step<T> s4y = mk_step(g[6], g[4], is.y);
+    const Step<T> s4xy = mk_step(g[7], g[4], is.xy);
+    const Step<T> s3z = mk_step(g[7], g[3], is.z);
+    const Step<T> s5y = mk_step(g[7], g[5], is.y);
+    const Step<T> s6x = mk_step(g[7], g[6], is.x);
     // vertex q
-    T best = (G.px + G.py + G.pz) + g0 * g0;
+    T best = fmadd(g0, g0, (G.px + G.py) + G.pz);
     // edges
     T e;
     e = face1(g0, s0x, G.ax, G.py + G.pz);
@@ -334,6 +370,7 @@ __device__ __forceinline__ T cell3(const T* g, const Geo<T>& G, const InvS2<T>& 
     return best;
 }
 
+
 // ---- Ju et al.'s recursion (Sec. 2.1: the branching form of the A1 distance) -------------
 //
 // The same closed-form chain projections as cell3, organised as the recursion of the
@@ -389,35 +426,38 @@ __device__ __forceinline__ float ju_perp(const JuCell& K) {
 }
 template <int U>
 __device__ __forceinline__ float ju_vertex(const JuCell& K) {
-    return ju_perp<U, 0>(K) + K.g[U] * K.g[U];
+#pragma clang fp contract(off)
+    return fmadd(K.g[U], K.g[U], ju_perp<U, 0>(K));
 }
 template <int U, int S>
 __device__ __forceinline__ Step<float> ju_step(const JuCell& K) {
     static_assert((U & S) == 0, "a chain steps away from its start");
-    return mk_step(K.g[U | S], K.g[U], ju_mu<S>(K), ju_inv<S>(K));
+    return mk_step(K.g[U | S], K.g[U], ju_inv<S>(K));
 }
 // edge from U along block S
 template <int U, int S>
 __device__ __forceinline__ float ju_edge(const JuCell& K) {
+#pragma clang fp contract(off)
     const Step<float> a = ju_step<U, S>(K);
-    const float N = K.g[U] - a.m;
-    const float L = N * Num<float>::rcp(1.0f + a.p);
-    const float t = -ju_mu<S>(K) - a.w * L;
-    if (t >= 0.0f && t <= 1.0f) return ju_perp<U, S>(K) + ju_res<S>(K) + N * L;
+    const float N = n_step(K.g[U], a, ju_mu<S>(K));
+    const float L = N * Num<float>::rcp(den_step(1.0f, a));
+    const float t = t_step(a, ju_mu<S>(K), L);
+    if (t >= 0.0f && t <= 1.0f) return fmadd(N, L, ju_perp<U, S>(K) + ju_res<S>(K));
     return t < 0.0f ? ju_vertex<U>(K) : ju_vertex<U | S>(K);
 }
 // triangle from U through blocks S1 then S2
 template <int U, int S1, int S2>
 __device__ __forceinline__ float ju_tri(const JuCell& K) {
+#pragma clang fp contract(off)
     const Step<float> a = ju_step<U, S1>(K);
     const Step<float> b = ju_step<U | S1, S2>(K);
-    const float N = (K.g[U] - a.m) - b.m;
-    const float L = N * Num<float>::rcp((1.0f + a.p) + b.p);
-    const float t1 = -ju_mu<S1>(K) - a.w * L;
-    const float t2 = -ju_mu<S2>(K) - b.w * L;
+    const float N = n_step(n_step(K.g[U], a, ju_mu<S1>(K)), b, ju_mu<S2>(K));
+    const float L = N * Num<float>::rcp(den_step(den_step(1.0f, a), b));
+    const float t1 = t_step(a, ju_mu<S1>(K), L);
+    const float t2 = t_step(b, ju_mu<S2>(K), L);
     const float w0 = 1.0f - t1, w1 = t1 - t2, w2 = t2;
     if (w0 >= 0.0f && w1 >= 0.0f && w2 >= 0.0f)
-        return ju_perp<U, S1 | S2>(K) + ju_res<S1>(K) + ju_res<S2>(K) + N * L;
+        return fmadd(N, L, (ju_perp<U, S1 | S2>(K) + ju_res<S1>(K)) + ju_res<S2>(K));
     float best = Num<float>::inf();
     if (w0 < 0.0f) best = vmin<float>(best, ju_edge<U | S1, S2>(K));
     if (w1 < 0.0f) best = vmin<float>(best, ju_edge<U, S1 | S2>(K));
@@ -428,15 +468,16 @@ __device__ __forceinline__ float ju_tri(const JuCell& K) {
 // denominator (the guard's measure)
 template <int A, int B, int C>
 __device__ __forceinline__ float ju_tet(const JuCell& K, float& den) {
+#pragma clang fp contract(off)
     const Step<float> a = ju_step<0, A>(K);
     const Step<float> b = ju_step<A, B>(K);
     const Step<float> c = ju_step<A | B, C>(K);
-    const float N = ((K.g[0] - a.m) - b.m) - c.m;
-    den = ((1.0f + a.p) + b.p) + c.p;
+    const float N = n_step(n_step(n_step(K.g[0], a, ju_mu<A>(K)), b, ju_mu<B>(K)), c, ju_mu<C>(K));
+    den = den3(a, b, c);
     const float L = N * Num<float>::rcp(den);
-    const float t1 = -ju_mu<A>(K) - a.w * L;
-    const float t2 = -ju_mu<B>(K) - b.w * L;
-    const float t3 = -ju_mu<C>(K) - c.w * L;
+    const float t1 = t_step(a, ju_mu<A>(K), L);
+    const float t2 = t_step(b, ju_mu<B>(K), L);
+    const float t3 = t_step(c, ju_mu<C>(K), L);
     const float w0 = 1.0f - t1, w1 = t1 - t2, w2 = t2 - t3, w3 = t3;
     if (w0 >= 0.0f && w1 >= 0.0f && w2 >= 0.0f && w3 >= 0.0f) return N * L;
     float best = Num<float>::inf();
@@ -485,14 +526,15 @@ __device__ __forceinline__ float cell3_ju(const float* g, const Geo<float>& G, c
 
 template <typename T, bool MASKED>
 __device__ __forceinline__ T cell2(const T* g, const Geo<T>& G, const InvS2<T>& is, bool okx, bool oky) {
+#pragma clang fp contract(off)
     const T INF = Num<T>::inf();
     const T g0 = g[0];
-    const Step<T> s0x = mk_step(g[1], g[0], G.ax, is.x);
-    const Step<T> s0y = mk_step(g[2], g[0], G.ay, is.y);
-    const Step<T> s0xy = mk_step(g[3], g[0], G.mxy, is.xy);
-    const Step<T> s1y = mk_step(g[3], g[1], G.ay, is.y);
-    const Step<T> s2x = mk_step(g[3], g[2], G.ax, is.x);
-    T best = (G.px + G.py) + g0 * g0;
+    const Step<T> s0x = mk_step(g[1], g[0], is.x);
+    const Step<T> s0y = mk_step(g[2], g[0], is.y);
+    const Step<T> s0xy = mk_step(g[3], g[0], is.xy);
+    const Step<T> s1y = mk_step(g[3], g[1], is.y);
+    const Step<T> s2x = mk_step(g[3], g[2], is.x);
+    T best = fmadd(g0, g0, G.px + G.py);
     T e = face1(g0, s0x, G.ax, G.py);
     best = vmin<T>(best, (!MASKED || okx) ? e : INF);
     e = face1(g0, s0y, G.ay, G.px);
@@ -662,7 +704,7 @@ __device__ __forceinline__ void zero3_body(const SearchArgs& a, const ZeroGeo& z
 #pragma unroll
     for (int k = 0; k < 27; ++k) g27[k] = (g27[k] - dr) * inv_dd;
 
-    const InvS2<float> is = inv_s2<float>(a.s2x, a.s2y, a.s2z);
+    const InvS2<float> is = inv_s2_of(a);
     const bool bnd = x == 0 || x + 1 == nx || y == 0 || y + 1 == ny || z == 0 || z + 1 == nz;
     const bool wave_masked = __ballot(live && bnd) != 0ull;
     float F = F0;
@@ -743,7 +785,7 @@ __device__ __forceinline__ void zero2_body(const SearchArgs& a, const ZeroGeo& z
     for (int k = 0; k < 9; ++k) g9[k] = a.ev[node + oy[k / 3] + ox[k % 3]];
 #pragma unroll
     for (int k = 0; k < 9; ++k) g9[k] = (g9[k] - dr) * inv_dd;
-    const InvS2<float> is = inv_s2<float>(a.s2x, a.s2y, 0.0f);
+    const InvS2<float> is = inv_s2_of(a);
     const bool bnd = x == 0 || x + 1 == nx || y == 0 || y + 1 == ny;
     const bool wave_masked = __ballot(live && bnd) != 0ull;
     float F = F0;
@@ -810,7 +852,7 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_zero_group(SearchArgs a, Zer
     const int gl = threadIdx.x % G;
     const int nx = a.nx, ny = a.ny, nz = a.nz, sxy = nx * ny;
     const float inv_dd_g = a.sc->inv_dd;
-    const InvS2<float> is = inv_s2<float>(a.s2x, a.s2y, DIM == 3 ? a.s2z : 0.0f);
+    const InvS2<float> is = inv_s2_of(a);
     const TabEntry row = zg.row[gl];            // this lane's zero-key cell
     const Geo<float> Gm = geo_from_row(row);
     GuardCtx gc{};
@@ -1095,7 +1137,7 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int sxy = nx * ny;
     const float inv_dd_g = a.sc->inv_dd;
-    const InvS2<float> is = inv_s2<float>(a.s2x, a.s2y, DIM == 3 ? a.s2z : 0.0f);
+    const InvS2<float> is = inv_s2_of(a);
     uint32_t cells = 0, gm = 0, npass = 0, nborder = 0;
     GuardCtx gc{};
     uint32_t dummy_fp64 = 0;
