@@ -410,6 +410,40 @@ def run_mixed(args):
     slow = [dict(shape=list(data[k]["spec"].shape), spacing_mm=round(data[k]["spec"].spacing[0], 3),
                  criteria=f"{data[k]['dd'] * 100:g}%/{data[k]['dta']:g}mm", local=data[k]["local"],
                  n_tail=int(tails[k]), ms=round(float(ms[k]), 4)) for k in np.argsort(-ms)[:5]]
+    # the same batch as one captured graph (gammax_batch): plain, then with the learned
+    # radius of the shipped network; results compared with the queued maps bit for bit
+    outs_many = [q["out"].clone() for q in data]
+    outs_b = [torch.empty_like(q["ref"]) for q in data]
+
+    def batch_leg(**bkw):
+        bctx = gx.Context(0)
+        for _ in range(max(1, args.warmup)):
+            gx.gammax_batch(data, ctx=bctx, outs=outs_b, sort=args.sort, **bkw)
+        torch.cuda.synchronize()
+        Mb, done = 0, None
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, rs = gx.gammax_batch(data, ctx=bctx, outs=outs_b, sort=args.sort, **bkw)
+            Mb += sum(r.n_evaluated for r in rs)
+            done = np.array([r.ms_done for r in rs])
+        torch.cuda.synchronize()
+        wb = time.perf_counter() - t0
+        same = all(torch.equal(a, b) for a, b in zip(outs_b, outs_many))
+        return {"value": round(Mb / wb, 1), "ms_per_step": round(1e3 * wb / args.steps, 4),
+                "pair_done_ms_p50": round(float(np.percentile(done, 50)), 4),
+                "pair_done_ms_p99": round(float(np.percentile(done, 99)), 4),
+                "pair_done_ms_max": round(float(done.max()), 4),
+                "n_fallback": int(sum(r.n_fallback for r in rs)),
+                "identical_to_queued_maps": bool(same)}
+
+    log("gammax_batch (one captured graph), plain")
+    batch_plain = batch_leg()
+    batch_learned = None
+    if not args.no_learned and os.path.exists(args.weights):
+        log("gammax_batch, learned radius")
+        model = gx.Model(np.load(args.weights, allow_pickle=False))
+        batch_learned = batch_leg(radius="learned", model=model)
+        batch_learned["weights"] = os.path.relpath(args.weights, ROOT)
     nodes = sum(q["ref"].numel() for q in data)
     line = {
         "metric": "ref voxels/sec, mixed batch of 64 pairs (2D/3D, 3/3-2/2-1/1, global/local)",
@@ -438,6 +472,13 @@ def run_mixed(args):
             "streams": len(streams),
             "sort": args.sort,
             "slowest_pairs": slow,
+            "batch_graph": {
+                "submission": "gammax_batch: one captured HIP graph per batch (every pair's compaction, one "
+                              "key-0 launch over all pairs' nodes in cost order, every pair's tail, guard and "
+                              "counts), replayed; per-pair completion times from the device clock",
+                "plain": batch_plain,
+                "learned": batch_learned,
+            },
         },
     }
     print(json.dumps(line), flush=True)
