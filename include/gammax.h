@@ -251,8 +251,10 @@ typedef struct {
 /*
  * Gamma map with the evaluation dose on a grid of its own (not in the paper, which compares
  * doses on one grid; Eq. (1) unchanged, with the evaluation surface built over eval_grid).
- * 3D only.  problem: the reference grid and the criteria; eval_dev: prod(eval_grid->shape)
- * floats.  A masked reference node inside the evaluation grid's closed box is evaluated;
+ * 2D or 3D (eval_grid uses its first ndim entries).  problem: the reference grid and the
+ * criteria; eval_dev: prod(eval_grid->shape) floats.  A 2D map runs as the 3D map of the
+ * pair extruded to two layers (the Kuhn interpolant of a dose constant along the added axis
+ * is the 2D interpolant, so the result is the 2D gamma), in context workspace.  A masked reference node inside the evaluation grid's closed box is evaluated;
  * the others get gamma = -1.  Each node walks a table of evaluation cells sorted by a key
  * that bounds the distance from below for any node position inside its holding cell, from
  * the nearest vertex of that cell.  Options: precision (FP32, guarded, FP64), tail_lanes

@@ -765,22 +765,25 @@ def gammax_map_grids(ref, ev, ref_spacing: Sequence[float], ev_spacing: Sequence
                      ev_origin: Sequence[float], dd: float, dta: float, dose_threshold: float = 0.1,
                      local: bool = False, *, precision: str = "guarded", cond_threshold: float = 1e6,
                      tail_lanes: int = 0, out=None, ctx: Optional[Context] = None, stream=None):
-    """Gamma map with the evaluation dose on a grid of its own (``gammax_map_grids``, 3D):
-    ``ev`` (float32 device tensor) sampled at ``ev_origin + j * ev_spacing`` mm in the frame
-    where reference node k sits at ``k * ref_spacing``.  Returns (gamma on the reference
-    grid, GammaResult); gamma is -1 where a node is not evaluated."""
+    """Gamma map with the evaluation dose on a grid of its own (``gammax_map_grids``, 2D or
+    3D): ``ev`` (float32 device tensor) sampled at ``ev_origin + j * ev_spacing`` mm in the
+    frame where reference node k sits at ``k * ref_spacing``.  Returns (gamma on the
+    reference grid, GammaResult); gamma is -1 where a node is not evaluated."""
     torch = _torch()
     _dev_tensor(ref, "ref")
     _dev_tensor(ev, "ev")
-    if ref.dim() != 3 or ev.dim() != 3 or ref.device != ev.device:
-        raise ValueError("ref and ev must be 3D tensors on one device")
+    if ref.dim() not in (2, 3) or ev.dim() != ref.dim() or ref.device != ev.device:
+        raise ValueError("ref and ev must both be 2D or both 3D tensors on one device")
+    nd = ref.dim()
+    if len(ref_spacing) != nd or len(ev_spacing) != nd or len(ev_origin) != nd:
+        raise ValueError("spacings and origin need one entry per axis")
     if out is None:
         out = torch.empty_like(ref)
     dev = ref.device.index if ref.device.index is not None else torch.cuda.current_device()
     ctx = ctx or context(dev)
     p = make_problem(tuple(ref.shape), ref_spacing, dd, dta, dose_threshold, local)
     g = Grid()
-    for i in range(3):
+    for i in range(nd):
         g.shape[i] = int(ev.shape[i])
         g.spacing_mm[i] = float(ev_spacing[i])
         g.origin_mm[i] = float(ev_origin[i])

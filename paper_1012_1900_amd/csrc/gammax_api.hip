@@ -123,6 +123,8 @@ struct gammax_ctx {
     TableGeom g_geom{};
     bool g_tab_valid = false;
     float g_k1 = INFINITY;             // key^2 of its first row past the 27 key-0 cells
+    float* g_2d = nullptr;             // 2D two-grid maps: the pair and gamma extruded to two layers
+    int64_t g_2d_cap = 0;
     struct BatchState* batch = nullptr;   // gammax_batch state (created on first use)
     struct ManyState* many = nullptr;     // gammax_map_many state (created on first use)
     uint64_t tail_hint = 0;         // tail length of the last map (picks the tail sort variant)
@@ -305,7 +307,7 @@ __global__ void k_zero_u32(uint32_t* p) {
 // every lane reads the same counter value.  (A runtime device-to-host copy queued after a
 // graph starts several microseconds after the graph's last kernel; this kernel is part of
 // the graph.)
-__global__ void k_publish_scalars(const Scalars* __restrict__ src, uint32_t* seq, Scalars* ring) {
+__device__ __forceinline__ void publish_body(const Scalars* __restrict__ src, uint32_t* seq, Scalars* ring) {
     constexpr int W = (int)(sizeof(Scalars) / sizeof(uint32_t));
     static_assert(sizeof(Scalars) % sizeof(uint32_t) == 0, "Scalars is a whole number of words");
     const uint32_t k = *seq;
@@ -314,6 +316,14 @@ __global__ void k_publish_scalars(const Scalars* __restrict__ src, uint32_t* seq
     if (t < W) reinterpret_cast<volatile uint32_t*>(dst)[t] = reinterpret_cast<const uint32_t*>(src)[t];
     if (t == 0) *seq = k + 1u;
     __threadfence_system();
+}
+__global__ void k_publish_scalars(const Scalars* __restrict__ src, uint32_t* seq, Scalars* ring) {
+    publish_body(src, seq, ring);
+}
+// Every pair of a batch publishes its scalars (block i: pair i).
+__global__ void k_batch_publish(const BatchPair* __restrict__ pairs) {
+    const BatchPair& P = pairs[blockIdx.x];
+    publish_body(P.sa.sc, P.seq, P.ring);
 }
 
 bool same_geom(const TableGeom& a, const TableGeom& b) {
@@ -479,9 +489,9 @@ int tail_min_lanes(const gammax_ctx* c) {
 }
 
 // Queue the compaction (Kernel 1).  ev0/ev1 (optional) bracket it.
-gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+// Compaction arguments of one map on the context's workspace.
+PrepArgs make_prep_args(gammax_ctx* c, const CallSetup& cs) {
     const int64_t ntiles = prep_tiles(cs.n);
-    if (ev0) HIPCHK(c, hipEventRecord(ev0, s));
     PrepArgs pa{};
     pa.ref = cs.ref;
     pa.ev = cs.ev;
@@ -498,6 +508,12 @@ gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, 
     pa.ntiles = (int)ntiles;
     pa.nodes = work_array(c, W_NODES);
     pa.sums = c->sums;
+    return pa;
+}
+
+gammax_status_t enqueue_prep(gammax_ctx* c, const CallSetup& cs, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (ev0) HIPCHK(c, hipEventRecord(ev0, s));
+    const PrepArgs pa = make_prep_args(c, cs);
     HIPCHK(c, launch_prep(pa, s));
     if (ev1) HIPCHK(c, hipEventRecord(ev1, s));
     return GAMMAX_OK;
@@ -973,7 +989,8 @@ gammax_status_t gammax_ctx_destroy(gammax_ctx_t* c) {
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void* dev[] = {c->d_sc, c->d_cnt, c->d_count, c->d_seq, c->work, c->blockcnt, c->part, c->hist,
-                   c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws, c->yhat, c->ycoarse, c->g_work, c->g_tab};
+                   c->sums, c->tab, c->tb, c->tb_hist, c->cnn_ws, c->yhat, c->ycoarse, c->g_work, c->g_tab,
+                   c->g_2d};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     destroy_batch(c);
@@ -1290,6 +1307,14 @@ gammax_status_t predict_nodes(gammax_ctx_t* c, gammax_model_t* m, const gammax_p
 
 }  // namespace
 
+namespace {
+
+gammax_status_t map_grids_2d(gammax_ctx_t* c, const gammax_problem_t* p, const gammax_grid_t* eg, const float* ref,
+                             const float* ev, float* gamma, const gammax_options_t* opt, gammax_result_t* res,
+                             void* stream);
+
+}  // namespace
+
 extern "C" {
 
 gammax_status_t gammax_map_grids(gammax_ctx_t* c, const gammax_problem_t* p, const gammax_grid_t* eg,
@@ -1300,7 +1325,7 @@ gammax_status_t gammax_map_grids(gammax_ctx_t* c, const gammax_problem_t* p, con
     int64_t nr = 0;
     gammax_status_t st = check_problem(c, p, &nr);
     if (st != GAMMAX_OK) return st;
-    if (p->ndim != 3) return fail(c, GAMMAX_E_SHAPE, "two grids: 3D only");
+    if (p->ndim == 2) return map_grids_2d(c, p, eg, ref, ev, gamma, opt_in, res, stream);
     int64_t ne = 1;
     for (int i = 0; i < 3; ++i) {
         if (eg->shape[i] < 2 || eg->shape[i] > ((int64_t)1 << 30))
@@ -1409,6 +1434,74 @@ gammax_status_t gammax_map_grids(gammax_ctx_t* c, const gammax_problem_t* p, con
     return GAMMAX_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// A 2D two-grid map as the 3D map of the pair extruded to two layers along a new slowest
+// axis: the evaluation dose repeated on both layers, the reference dose on layer 0 and the
+// second layer below any threshold, so only layer 0 is evaluated.  The Kuhn interpolant of a
+// dose constant along that axis is the 2D interpolant at every height, so a layer-0 node's
+// nearest surface point lies in its own layer and its gamma is the 2D gamma.
+gammax_status_t map_grids_2d(gammax_ctx_t* c, const gammax_problem_t* p, const gammax_grid_t* eg, const float* ref,
+                             const float* ev, float* gamma, const gammax_options_t* opt, gammax_result_t* res,
+                             void* stream) {
+    int64_t ne = 1;
+    for (int i = 0; i < 2; ++i) {
+        if (eg->shape[i] < 2 || eg->shape[i] > ((int64_t)1 << 30))
+            return fail(c, GAMMAX_E_SHAPE, "every evaluation axis needs at least 2 nodes");
+        ne *= eg->shape[i];
+        if (!finite_pos(eg->spacing_mm[i])) return fail(c, GAMMAX_E_PARAM, "evaluation spacing must be finite and > 0");
+        if (!std::isfinite(eg->origin_mm[i])) return fail(c, GAMMAX_E_PARAM, "evaluation origin must be finite");
+    }
+    const int64_t nr = p->shape[0] * p->shape[1];
+    if (2 * nr >= ((int64_t)1 << 31) || 2 * ne >= ((int64_t)1 << 31))
+        return fail(c, GAMMAX_E_SHAPE, "grid must hold < 2^30 nodes in 2D");
+    if ((const float*)gamma == ref || (const float*)gamma == ev)
+        return fail(c, GAMMAX_E_PARAM, "gamma must not alias the dose arrays");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    gammax_status_t st;
+    if ((st = grow(c, &c->g_2d, &c->g_2d_cap, 4 * nr + 2 * ne)) != GAMMAX_OK) return st;
+    float* ref3 = c->g_2d;
+    float* gam3 = c->g_2d + 2 * nr;
+    float* ev3 = c->g_2d + 4 * nr;
+    const size_t rb = sizeof(float) * (size_t)nr, eb = sizeof(float) * (size_t)ne;
+    HIPCHK(c, hipMemcpyAsync(ref3, ref, rb, hipMemcpyDeviceToDevice, s));
+    // bytes 0x80: -1.18e-38 per node, below every threshold (and not > 0 for local
+    // normalisation), and never the maximum of a pair that has a positive dose
+    HIPCHK(c, hipMemsetAsync(ref3 + nr, 0x80, rb, s));
+    HIPCHK(c, hipMemcpyAsync(ev3, ev, eb, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(ev3 + ne, ev, eb, hipMemcpyDeviceToDevice, s));
+    const double hz = std::fmax(p->spacing_mm[0], p->spacing_mm[1]);   // any positive height
+    gammax_problem_t p3 = *p;
+    p3.ndim = 3;
+    p3.shape[0] = 2;
+    p3.shape[1] = p->shape[0];
+    p3.shape[2] = p->shape[1];
+    p3.spacing_mm[0] = hz;
+    p3.spacing_mm[1] = p->spacing_mm[0];
+    p3.spacing_mm[2] = p->spacing_mm[1];
+    gammax_grid_t g3{};
+    g3.shape[0] = 2;
+    g3.shape[1] = eg->shape[0];
+    g3.shape[2] = eg->shape[1];
+    g3.spacing_mm[0] = hz;
+    g3.spacing_mm[1] = eg->spacing_mm[0];
+    g3.spacing_mm[2] = eg->spacing_mm[1];
+    g3.origin_mm[0] = 0.0;
+    g3.origin_mm[1] = eg->origin_mm[0];
+    g3.origin_mm[2] = eg->origin_mm[1];
+    if ((st = gammax_map_grids(c, &p3, &g3, ref3, ev3, gam3, opt, res, stream)) != GAMMAX_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(gamma, gam3, rb, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return GAMMAX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 gammax_status_t gammax_model_features(gammax_ctx_t* c, const gammax_problem_t* p, const float* ref,
                                       const float* ev, uint16_t* feat, void* stream) {
     if (!c) return GAMMAX_E_NULL;
@@ -1464,23 +1557,26 @@ gammax_status_t gammax_model_predict_nodes_pooled(gammax_ctx_t* c, gammax_model_
 // ---- batches -----------------------------------------------------------------------------
 //
 // gammax_batch: the whole batch as one captured HIP graph on one stream.  Each pair keeps a
-// context of its own (cell table, workspace, scalars ring), and the graph holds, in order:
-//   * every pair's compaction (the prep kernels of its own map);
-//   * one launch of the key-0 pass over every pair's nodes: one block per (pair, block of
-//     256 nodes) item, the items in cost order (3D pairs first, larger pairs first);
-//   * every pair's pipeline after the key-0 pass (network at the tail nodes, tail sort,
-//     tail walk and fallback, guard and count reduction, scalars to its ring), each ending
-//     with a stamp of the device clock (completion times).
+// context of its own (cell table, workspace, scalars ring).  When every pair takes the
+// default pipeline (no tail sort, plain radius, FP32 or guarded precision, grouped tail
+// lanes), the graph holds one launch per phase over all pairs, each block running one
+// (pair, block) item of that phase's body:
+//   dose maximum -> masked count -> ordered emit -> key-0 pass (items in cost order: 3D
+//   pairs first, larger pairs first) -> tail walk -> FP64 guard and count reduction (each
+//   pair's block 0 then stamps the device clock: completion times) -> scalars to each
+//   pair's ring.
+// Otherwise it holds every pair's compaction, the one key-0 launch, then every pair's own
+// pipeline after the key-0 pass (network, sort, tail, guard, counts, stamp), pair by pair.
 // A repeated batch replays the graph.  The tail layout of each shape class can be tuned by
 // timing that layout's walk on a pair of the class (gammax_tune_*).
 
 struct BatchState {
     std::vector<gammax_ctx*> subs;               // a context per pair index
-    BatchSearchPair* d_pairs = nullptr;          // device: key-0 descriptors, then the items
+    BatchPair* d_pairs = nullptr;                // device: pair descriptors, then the item lists
     int64_t desc_cap = 0;                        // bytes
     unsigned char* h_stage = nullptr;            // pinned: descriptors and items to upload
     int64_t stage_cap = 0;
-    std::vector<unsigned char> uploaded;         // what the device holds
+    std::vector<unsigned char> staged_key;       // batch key of what the device holds
     unsigned long long* d_done = nullptr;        // completion clocks per pair, [n] = start
     unsigned long long* h_done = nullptr;        // pinned copy
     int64_t done_cap = 0;
@@ -1531,25 +1627,67 @@ uint64_t shape_class(const gammax_problem_t* p, int64_t n) {
     return (uint64_t)p->ndim | ((uint64_t)lg << 2) | (dd << 8) | (dta << 24) | (h << 40);
 }
 
-// One batch as the graph sees it: per pair its call set-up and options, and the items of
-// the key-0 launch.
+// One batch as the graph sees it: per pair its call set-up and options; the item lists of
+// its launches (byte offsets and counts within the staged block after the descriptors).
 struct BatchPlan {
     int n = 0;
     std::vector<gammax_options_t> opt;
     std::vector<CallSetup> cs;
     std::vector<int64_t> nodes;
     bool key0 = true;          // false for FP64 precision (its walk starts at row 0)
-    int n_items = 0;
-    int64_t desc_bytes = 0;    // descriptors, then items
+    bool phased = false;       // every phase one launch over all pairs (the default pipeline)
+    enum { L_KEY0, L_DM, L_TILES, L_TAIL, L_FIN, kLists };
+    int64_t off[kLists] = {};  // byte offset of each item list
+    int count[kLists] = {};
+    int64_t desc_bytes = 0;    // descriptors, then the item lists
 };
 
-int64_t items_offset(int n) { return (int64_t)((sizeof(BatchSearchPair) * n + 255) / 256 * 256); }
+int64_t descs_bytes(int n) { return (int64_t)((sizeof(BatchPair) * n + 255) / 256 * 256); }
 
-// The key-0 descriptors of every pair (the search arguments its own pipeline uses) and the
-// cost-ordered items, into the pinned staging area.
+// Whether a pair's map takes the default pipeline that the phased batch runs.
+bool default_pipeline(const gammax_problem_t* p, const gammax_options_t& o) {
+    return o.sort_mode == GAMMAX_SORT_NONE && !uses_model(p, &o) && o.precision != GAMMAX_PREC_FP64 &&
+           o.tail_lanes != 1 && o.cell_lanes <= 1 && o.projection == 0;
+}
+
+// Lanes request of a pair's tail walk (as enqueue_search / tail_pass choose it).
+int tail_g_req(const gammax_ctx* sub, const gammax_options_t& o) {
+    const int tm = tail_min_lanes(sub);
+    return o.tail_lanes ? o.tail_lanes : -(tm > 8 ? tm : 8);
+}
+
+// Item counts of every list and the staged size.
+gammax_status_t plan_lists(gammax_ctx* c, BatchState* b, BatchPlan& P) {
+    int64_t cnt[BatchPlan::kLists] = {};
+    for (int i = 0; i < P.n; ++i) {
+        const int64_t nn = P.nodes[i];
+        cnt[BatchPlan::L_KEY0] += (nn + 255) / 256;
+        if (!P.phased) continue;
+        gammax_ctx* sub = b->subs[i];
+        const int first = P.cs[i].p->ndim == 3 ? 8 : 4;
+        cnt[BatchPlan::L_DM] += prep_reduce_blocks(nn);
+        cnt[BatchPlan::L_TILES] += prep_tiles(nn);
+        if (sub->tab_valid && sub->tab_len > first)
+            cnt[BatchPlan::L_TAIL] += tail_grid_blocks((uint32_t)nn, tail_g_req(sub, P.opt[i]));
+        const bool guarded = P.opt[i].precision == GAMMAX_PREC_GUARDED && P.cs[i].p->ndim == 3;
+        cnt[BatchPlan::L_FIN] += guarded ? guard_grid_blocks() : 1;
+    }
+    if (!P.key0) cnt[BatchPlan::L_KEY0] = 0;
+    int64_t off = descs_bytes(P.n);
+    for (int k = 0; k < BatchPlan::kLists; ++k) {
+        if (cnt[k] >= ((int64_t)1 << 31)) return fail(c, GAMMAX_E_SHAPE, "batch holds too many nodes");
+        P.off[k] = off;
+        P.count[k] = (int)cnt[k];
+        off += (int64_t)sizeof(uint2) * cnt[k];
+    }
+    P.desc_bytes = off > descs_bytes(P.n) ? off : descs_bytes(P.n) + (int64_t)sizeof(uint2);
+    return GAMMAX_OK;
+}
+
+// The descriptors of every pair (the arguments its own pipeline uses) and the item lists,
+// into the pinned staging area.
 void stage_batch(BatchState* b, const BatchPlan& P) {
-    BatchSearchPair* d = (BatchSearchPair*)b->h_stage;
-    uint2* items = (uint2*)(b->h_stage + items_offset(P.n));
+    BatchPair* d = (BatchPair*)b->h_stage;
     std::memset(b->h_stage, 0, (size_t)P.desc_bytes);
     for (int i = 0; i < P.n; ++i) {
         gammax_ctx* c = b->subs[i];
@@ -1559,9 +1697,19 @@ void stage_batch(BatchState* b, const BatchPlan& P) {
                                    c->tab_valid ? (int)c->tab_len : 0, c->tab_valid ? c->tab_k1 : INFINITY,
                                    r2_cap, c->work, c->work_cap, c->sums, c->yhat);
         d[i].zg = make_zero_geo(p);
+        d[i].pa = make_prep_args(c, P.cs[i]);
         d[i].ndim = p->ndim;
         d[i].guarded = (P.opt[i].precision == GAMMAX_PREC_GUARDED && p->ndim == 3) ? 1 : 0;
+        d[i].nbr = prep_reduce_blocks(P.nodes[i]);
+        d[i].first = p->ndim == 3 ? 8 : 4;
+        d[i].g_req = tail_g_req(c, P.opt[i]);
+        d[i].tail_blocks = (int)tail_grid_blocks((uint32_t)P.nodes[i], d[i].g_req);
+        d[i].walk = (c->tab_valid && c->tab_len > d[i].first) ? 1 : 0;
+        d[i].seq = c->d_seq;
+        d[i].ring = c->h_ring;
+        d[i].done = b->d_done + i;
     }
+    // pairs in cost order for the key-0 and tail launches (3D first, larger first)
     std::vector<int> order(P.n);
     for (int i = 0; i < P.n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
@@ -1569,21 +1717,50 @@ void stage_batch(BatchState* b, const BatchPlan& P) {
         const double cy = (double)P.nodes[y] * (P.cs[y].p->ndim == 3 ? 8.0 : 2.0);
         return cx > cy;
     });
+    auto list = [&](int k) { return (uint2*)(b->h_stage + P.off[k]); };
     int k = 0;
-    for (int i : order)
-        for (int64_t blk = 0; blk < (P.nodes[i] + 255) / 256; ++blk) items[k++] = make_uint2((uint32_t)i, (uint32_t)blk);
+    if (P.key0) {
+        uint2* it = list(BatchPlan::L_KEY0);
+        for (int i : order)
+            for (int64_t blk = 0; blk < (P.nodes[i] + 255) / 256; ++blk) it[k++] = make_uint2((uint32_t)i, (uint32_t)blk);
+    }
+    if (!P.phased) return;
+    uint2* dm = list(BatchPlan::L_DM);
+    uint2* tiles = list(BatchPlan::L_TILES);
+    uint2* tail = list(BatchPlan::L_TAIL);
+    uint2* fin = list(BatchPlan::L_FIN);
+    int ndm = 0, nt = 0, ntail = 0, nfin = 0;
+    for (int i : order) {
+        for (int j = 0; j < d[i].nbr; ++j) dm[ndm++] = make_uint2((uint32_t)i, (uint32_t)j);
+        for (int64_t t = 0; t < prep_tiles(P.nodes[i]); ++t) tiles[nt++] = make_uint2((uint32_t)i, (uint32_t)t);
+        if (d[i].walk)
+            for (int j = 0; j < d[i].tail_blocks; ++j) tail[ntail++] = make_uint2((uint32_t)i, (uint32_t)j);
+        const int nf = d[i].guarded ? (int)guard_grid_blocks() : 1;
+        for (int j = 0; j < nf; ++j) fin[nfin++] = make_uint2((uint32_t)i, (uint32_t)j);
+    }
 }
 
 // Queue the whole batch on `s` (the capture stream, or the caller's stream for a direct run).
 gammax_status_t enqueue_batch(gammax_ctx* c, BatchState* b, const BatchPlan& P, hipStream_t s) {
     gammax_status_t st;
+    const unsigned char* dev = (const unsigned char*)b->d_pairs;
+    auto list = [&](int k) { return (const uint2*)(dev + P.off[k]); };
     HIPCHK(c, launch_stamp(b->d_done + P.n, s));
+    if (P.phased) {
+        HIPCHK(c, launch_batch_prep(b->d_pairs, list(BatchPlan::L_DM), P.count[BatchPlan::L_DM],
+                                    list(BatchPlan::L_TILES), P.count[BatchPlan::L_TILES], s));
+        HIPCHK(c, launch_batch_key0(b->d_pairs, list(BatchPlan::L_KEY0), P.count[BatchPlan::L_KEY0], s));
+        HIPCHK(c, launch_batch_tail(b->d_pairs, list(BatchPlan::L_TAIL), P.count[BatchPlan::L_TAIL], s));
+        HIPCHK(c, launch_batch_finish(b->d_pairs, list(BatchPlan::L_FIN), P.count[BatchPlan::L_FIN], s));
+        hipLaunchKernelGGL(k_batch_publish, dim3((unsigned)P.n), dim3(64), 0, s, (const BatchPair*)b->d_pairs);
+        HIPCHK(c, hipGetLastError());
+        return GAMMAX_OK;
+    }
     for (int i = 0; i < P.n; ++i)
         if ((st = enqueue_prep(b->subs[i], P.cs[i], s, nullptr, nullptr)) != GAMMAX_OK)
             return fail(c, st, "pair " + std::to_string(i) + ": " + b->subs[i]->err);
     if (P.key0)
-        HIPCHK(c, launch_batch_key0(b->d_pairs, (const uint2*)((unsigned char*)b->d_pairs + items_offset(P.n)),
-                                    P.n_items, s));
+        HIPCHK(c, launch_batch_key0(b->d_pairs, list(BatchPlan::L_KEY0), P.count[BatchPlan::L_KEY0], s));
     for (int i = 0; i < P.n; ++i) {
         gammax_ctx* sub = b->subs[i];
         const float r2_cap = round_down_float(sub->tab_geom.r2_cap);
@@ -1594,33 +1771,42 @@ gammax_status_t enqueue_batch(gammax_ctx* c, BatchState* b, const BatchPlan& P, 
     return GAMMAX_OK;
 }
 
-// The graph key: every pair's own graph key (pointers, problem, options and the context
-// state its pipeline depends on) and the staged descriptors.
+// The batch key: every pair's own graph key (pointers, problem, options and the context
+// state its pipeline depends on: the descriptors and item lists derive from these), the
+// plan's shape and the batch's own buffers.  Equal keys mean equal staged bytes.
 std::vector<unsigned char> batch_key(BatchState* b, const BatchPlan& P) {
-    std::vector<unsigned char> k(b->h_stage, b->h_stage + P.desc_bytes);
+    std::vector<unsigned char> k;
+    auto put = [&](const void* q, size_t n) {
+        const unsigned char* u = (const unsigned char*)q;
+        k.insert(k.end(), u, u + n);
+    };
     for (int i = 0; i < P.n; ++i) {
         const GraphKey g = key_of(b->subs[i], P.cs[i]);
-        const unsigned char* q = (const unsigned char*)&g;
-        k.insert(k.end(), q, q + sizeof(g));
+        put(&g, sizeof(g));
     }
+    const void* bufs[2] = {b->d_pairs, b->d_done};
+    put(bufs, sizeof(bufs));
+    const int flags[2] = {P.key0 ? 1 : 0, P.phased ? 1 : 0};
+    put(flags, sizeof(flags));
+    put(P.count, sizeof(P.count));
     return k;
 }
 
 // Run the batch once (replaying the graph when possible), ring slots claimed and counted
-// as every pair's map publishes its scalars.  ring[i] receives pair i's slot.
+// as every pair's map publishes its scalars.  ring[i] receives pair i's slot.  The
+// descriptors and item lists are staged and uploaded only when the batch key changes.
 gammax_status_t launch_batch(gammax_ctx* c, BatchState* b, const BatchPlan& P, hipStream_t s,
                              std::vector<int>& ring) {
     gammax_status_t st;
-    stage_batch(b, P);
-    if ((int64_t)b->uploaded.size() != P.desc_bytes ||
-        std::memcmp(b->uploaded.data(), b->h_stage, (size_t)P.desc_bytes) != 0) {
+    const std::vector<unsigned char> key = batch_key(b, P);
+    if (key != b->staged_key) {
+        stage_batch(b, P);
         HIPCHK(c, hipMemcpyAsync(b->d_pairs, b->h_stage, (size_t)P.desc_bytes, hipMemcpyHostToDevice, s));
-        b->uploaded.assign(b->h_stage, b->h_stage + P.desc_bytes);
+        b->staged_key = key;
     }
     for (int i = 0; i < P.n; ++i) ring[i] = claim_ring(b->subs[i]);
     bool launched = false;
     if (!c->graph_broken) {
-        const std::vector<unsigned char> key = batch_key(b, P);
         if (!b->graph || key != b->graph_key) {
             if (b->graph) (void)hipGraphExecDestroy(b->graph);
             b->graph = nullptr;
@@ -1792,40 +1978,6 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
             }
         }
     }
-    int64_t n_items = 0;
-    for (int i = 0; i < n; ++i) n_items += (P.nodes[i] + 255) / 256;
-    if (n_items >= ((int64_t)1 << 31)) return fail(c, GAMMAX_E_SHAPE, "batch holds too many nodes");
-    P.n_items = P.key0 ? (int)n_items : 0;
-    P.desc_bytes = items_offset(n) + (int64_t)sizeof(uint2) * (n_items > 0 ? n_items : 1);
-    if (P.desc_bytes > b->desc_cap || !b->d_pairs) {
-        if (b->graph) (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-        int64_t cap = b->desc_cap;
-        unsigned char* raw = (unsigned char*)b->d_pairs;
-        if ((st = grow(c, &raw, &cap, P.desc_bytes)) != GAMMAX_OK) return st;
-        b->d_pairs = (BatchSearchPair*)raw;
-        b->desc_cap = cap;
-        b->uploaded.clear();
-    }
-    if (P.desc_bytes > b->stage_cap || !b->h_stage) {
-        if (b->h_stage) (void)hipHostFree(b->h_stage);
-        b->h_stage = nullptr;
-        b->stage_cap = 0;
-        HIPCHK(c, hipHostMalloc((void**)&b->h_stage, (size_t)P.desc_bytes, hipHostMallocDefault));
-        b->stage_cap = P.desc_bytes;
-    }
-    if (n + 1 > b->done_cap || !b->d_done) {
-        if (b->graph) (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-        if (b->h_done) (void)hipHostFree(b->h_done);
-        b->h_done = nullptr;
-        int64_t cap = b->done_cap;
-        if ((st = grow(c, &b->d_done, &cap, n + 1)) != GAMMAX_OK) return st;
-        b->done_cap = cap;
-        HIPCHK(c, hipHostMalloc((void**)&b->h_done, sizeof(unsigned long long) * (size_t)cap, hipHostMallocDefault));
-    }
-    std::vector<int> ring(n, 0);
-
     // tail layout of shape classes met for the first time: on the first pair of the class,
     // its own map timed with each layout (direct launches with phase events), the layout
     // whose tail walk was fastest kept
@@ -1855,6 +2007,40 @@ gammax_status_t gammax_batch(gammax_ctx_t* c, int32_t n, const gammax_problem_t*
         }
         for (int i = 0; i < n; ++i) P.opt[i].tail_lanes = b->tune[cls[i]];
     }
+
+
+    // the launches: one per phase over all pairs when every pair takes the default pipeline
+    P.phased = P.key0;
+    for (int i = 0; i < n; ++i) P.phased = P.phased && default_pipeline(&probs[i], P.opt[i]);
+    if ((st = plan_lists(c, b, P)) != GAMMAX_OK) return st;
+    if (P.desc_bytes > b->desc_cap || !b->d_pairs) {
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        int64_t cap = b->desc_cap;
+        unsigned char* raw = (unsigned char*)b->d_pairs;
+        if ((st = grow(c, &raw, &cap, P.desc_bytes)) != GAMMAX_OK) return st;
+        b->d_pairs = (BatchPair*)raw;
+        b->desc_cap = cap;
+        b->staged_key.clear();
+    }
+    if (P.desc_bytes > b->stage_cap || !b->h_stage) {
+        if (b->h_stage) (void)hipHostFree(b->h_stage);
+        b->h_stage = nullptr;
+        b->stage_cap = 0;
+        HIPCHK(c, hipHostMalloc((void**)&b->h_stage, (size_t)P.desc_bytes, hipHostMallocDefault));
+        b->stage_cap = P.desc_bytes;
+    }
+    if (n + 1 > b->done_cap || !b->d_done) {
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        if (b->h_done) (void)hipHostFree(b->h_done);
+        b->h_done = nullptr;
+        int64_t cap = b->done_cap;
+        if ((st = grow(c, &b->d_done, &cap, n + 1)) != GAMMAX_OK) return st;
+        b->done_cap = cap;
+        HIPCHK(c, hipHostMalloc((void**)&b->h_done, sizeof(unsigned long long) * (size_t)cap, hipHostMallocDefault));
+    }
+    std::vector<int> ring(n, 0);
 
     // the batch
     if ((st = launch_batch(c, b, P, s, ring)) != GAMMAX_OK) return st;

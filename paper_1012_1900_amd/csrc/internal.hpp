@@ -272,18 +272,45 @@ hipError_t launch_grids_tail(const GridsArgs& a, int precision, int lanes, hipSt
 
 // ---- batches of dose pairs -------------------------------------------------------------
 //
-// The key-0 pass of every pair of a batch in one launch: one block per (pair, block of 256
-// nodes) item, the items in cost order; each block runs the pass over its 256 nodes exactly
-// as the single-pair kernel does for its block.
+// A batch runs each phase of the map as one launch over all its pairs: block b takes item
+// b = (pair, block of that pair) and runs that pair's phase body exactly as the pair's own
+// kernel would run that block.  The host lists the items of every launch; a pair's blocks
+// are those its own launch would have (every grid is sized from the pair's node count, and
+// the bodies read the device-side counts themselves).
 
-struct BatchSearchPair {
+struct BatchPair {
     SearchArgs sa;           // the pair's search arguments (those of its own pipeline)
     ZeroGeo zg;
+    PrepArgs pa;             // its compaction arguments
     int ndim, guarded;       // guarded: FP32 with the FP64 guard (3D)
-    int pad[2];
+    int nbr;                 // blocks of its dose-maximum pass
+    int first;               // first table row of its tail walk (2^d)
+    int g_req;               // lanes per tail node (negative: automatic with that least width)
+    int tail_blocks;         // grid-stride blocks of its tail walk
+    int walk;                // 1: its table reaches past the key-0 rows
+    int pad;
+    uint32_t* seq;           // its map counter and pinned scalar ring (the publish)
+    Scalars* ring;
+    unsigned long long* done;  // its completion stamp (device clock)
 };
 
-hipError_t launch_batch_key0(const BatchSearchPair* pairs, const uint2* items, int n_items, hipStream_t s);
+// Blocks of the dose-maximum pass of an n-node pair.
+int prep_reduce_blocks(int64_t n);
+// Grid-stride blocks of the tail walk of a pair of at most m_bound nodes with lanes request g.
+unsigned tail_grid_blocks(uint32_t m_bound, int g);
+// Grid-stride blocks of the FP64 guard pass.
+unsigned guard_grid_blocks();
+// The compaction of every pair: dose maximum (items dm), then the count and the ordered
+// emit of the masked nodes (items tiles: (pair, prep tile)).
+hipError_t launch_batch_prep(const BatchPair* pairs, const uint2* dm, int n_dm, const uint2* tiles, int n_tiles,
+                             hipStream_t s);
+// The key-0 pass of every pair: items (pair, block of 256 nodes).
+hipError_t launch_batch_key0(const BatchPair* pairs, const uint2* items, int n_items, hipStream_t s);
+// The tail walk of every pair that has one: items (pair, tail block).
+hipError_t launch_batch_tail(const BatchPair* pairs, const uint2* items, int n_items, hipStream_t s);
+// Every pair's FP64 guard pass and count reduction (items (pair, guard block); one block for
+// a pair without the guard), then its completion stamp.
+hipError_t launch_batch_finish(const BatchPair* pairs, const uint2* items, int n_items, hipStream_t s);
 // One thread writes the device's wall clock (for per-pair completion times).
 hipError_t launch_stamp(unsigned long long* t, hipStream_t s);
 

@@ -287,7 +287,38 @@ int reduce_blocks(int64_t n) {
     return (int)(b < 1 ? 1 : b);
 }
 
+// Batches: the same bodies, one block per (pair, block) item.
+__global__ __launch_bounds__(PREP_THREADS) void k_batch_dose_max(const BatchPair* __restrict__ pairs,
+                                                                 const uint2* __restrict__ items) {
+    const uint2 w = items[blockIdx.x];
+    const BatchPair& P = pairs[w.x];
+    dose_max_body(P.pa, (int)w.y, P.nbr);
+}
+__global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_count(const BatchPair* __restrict__ pairs,
+                                                                   const uint2* __restrict__ items) {
+    const uint2 w = items[blockIdx.x];
+    const BatchPair& P = pairs[w.x];
+    prep_count_body(P.pa, P.nbr, (int)w.y);
+}
+__global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_emit(const BatchPair* __restrict__ pairs,
+                                                                  const uint2* __restrict__ items) {
+    const uint2 w = items[blockIdx.x];
+    const BatchPair& P = pairs[w.x];
+    prep_emit_body(P.pa, (int)w.y);
+}
+
 }  // namespace
+
+int prep_reduce_blocks(int64_t n) { return reduce_blocks(n); }
+
+hipError_t launch_batch_prep(const BatchPair* pairs, const uint2* dm, int n_dm, const uint2* tiles, int n_tiles,
+                             hipStream_t s) {
+    if (n_dm <= 0 || n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_dose_max, dim3((unsigned)n_dm), dim3(PREP_THREADS), 0, s, pairs, dm);
+    hipLaunchKernelGGL(k_batch_prep_count, dim3((unsigned)n_tiles), dim3(PREP_THREADS), 0, s, pairs, tiles);
+    hipLaunchKernelGGL(k_batch_prep_emit, dim3((unsigned)n_tiles), dim3(PREP_THREADS), 0, s, pairs, tiles);
+    return hipGetLastError();
+}
 
 int64_t prep_tiles(int64_t n) { return (n + PREP_TILE - 1) / PREP_TILE; }
 

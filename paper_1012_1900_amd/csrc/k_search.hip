@@ -1412,16 +1412,49 @@ unsigned tail_pass(const SearchArgs& a, const SearchPlan& p, const uint32_t* ord
 // The key-0 pass of every pair of a batch: block b takes item b = (pair, block of 256 nodes)
 // and runs that pair's pass over those nodes, as the pair's own kernel would (a block past
 // the pair's M returns at once).
-__global__ __launch_bounds__(SEARCH_THREADS) void k_batch_key0(const BatchSearchPair* __restrict__ pairs,
+__global__ __launch_bounds__(SEARCH_THREADS) void k_batch_key0(const BatchPair* __restrict__ pairs,
                                                                const uint2* __restrict__ items) {
     const uint2 w = items[blockIdx.x];
-    const BatchSearchPair& P = pairs[w.x];
+    const BatchPair& P = pairs[w.x];
     if (P.ndim == 3) {
         if (P.guarded) zero3_body<1>(P.sa, P.zg, P.sa.sums, w.y);
         else zero3_body<0>(P.sa, P.zg, P.sa.sums, w.y);
     } else {
         zero2_body(P.sa, P.zg, P.sa.sums, w.y);
     }
+}
+
+// The tail walk of every pair (no sort, plain radius): block b takes item (pair, tail block).
+__global__ __launch_bounds__(SEARCH_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_tail(
+    const BatchPair* __restrict__ pairs, const uint2* __restrict__ items) {
+    const uint2 w = items[blockIdx.x];
+    const BatchPair& P = pairs[w.x];
+    if (P.ndim == 3) {
+        if (P.guarded)
+            tail_group_body<3, 1>(P.sa, P.sa.tab, P.sa.tail_pos, &P.sa.sc->n_tail, P.first, P.g_req, 0, P.sa.sums,
+                                  w.y, (uint32_t)P.tail_blocks);
+        else
+            tail_group_body<3, 0>(P.sa, P.sa.tab, P.sa.tail_pos, &P.sa.sc->n_tail, P.first, P.g_req, 0, P.sa.sums,
+                                  w.y, (uint32_t)P.tail_blocks);
+    } else {
+        tail_group_body<2, 0>(P.sa, P.sa.tab, P.sa.tail_pos, &P.sa.sc->n_tail, P.first, P.g_req, 0, P.sa.sums, w.y,
+                              (uint32_t)P.tail_blocks);
+    }
+}
+
+// Every pair's guard pass with its count reduction (as k_guard_finalize), or the count
+// reduction alone (as k_finalize); block 0 of each pair then stamps its completion.
+__global__ __launch_bounds__(SEARCH_THREADS) void k_batch_finish(const BatchPair* __restrict__ pairs,
+                                                                 const uint2* __restrict__ items) {
+    const uint2 w = items[blockIdx.x];
+    const BatchPair& P = pairs[w.x];
+    if (P.guarded) {
+        if (w.y == 0) finalize_body<true>(P.sa.sums, SUM_BINS, P.sa.sc, P.sa.r2_cap);
+        walk_body<3, 2, false>(P.sa, P.sa.tab, P.sa.guard_list, &P.sa.sc->n_guard, 0, 0, nullptr, w.y, kGuardBlocks);
+    } else {
+        finalize_body(P.sa.sums, SUM_BINS, P.sa.sc, P.sa.r2_cap);
+    }
+    if (w.y == 0 && threadIdx.x == 0) *P.done = wall_clock64();
 }
 
 __global__ void k_stamp(unsigned long long* t) {
@@ -1862,11 +1895,32 @@ __global__ __launch_bounds__(256) void k_grids_walk(GridsArgs a, int G) {
 
 }  // namespace
 
-hipError_t launch_batch_key0(const BatchSearchPair* pairs, const uint2* items, int n_items, hipStream_t s) {
+hipError_t launch_batch_key0(const BatchPair* pairs, const uint2* items, int n_items, hipStream_t s) {
     if (n_items > 0)
         hipLaunchKernelGGL(k_batch_key0, dim3((unsigned)n_items), dim3(SEARCH_THREADS), 0, s, pairs, items);
     return hipGetLastError();
 }
+
+hipError_t launch_batch_tail(const BatchPair* pairs, const uint2* items, int n_items, hipStream_t s) {
+    if (n_items > 0)
+        hipLaunchKernelGGL(k_batch_tail, dim3((unsigned)n_items), dim3(SEARCH_THREADS), 0, s, pairs, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finish(const BatchPair* pairs, const uint2* items, int n_items, hipStream_t s) {
+    if (n_items > 0)
+        hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)n_items), dim3(SEARCH_THREADS), 0, s, pairs, items);
+    return hipGetLastError();
+}
+
+unsigned tail_grid_blocks(uint32_t m_bound, int g) {
+    // as tail_pass: groups of |g| lanes (automatic: the least width), at most kTailBlocks
+    const unsigned groups = SEARCH_THREADS / (unsigned)(g > 0 ? g : -g);
+    unsigned gb = (m_bound + groups - 1) / groups;
+    return gb > kTailBlocks ? kTailBlocks : gb;
+}
+
+unsigned guard_grid_blocks() { return kGuardBlocks; }
 
 hipError_t launch_stamp(unsigned long long* t, hipStream_t s) {
     hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, t);

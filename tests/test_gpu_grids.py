@@ -99,3 +99,51 @@ def test_refused_options(gx):
     with pytest.raises(gx.GammaxError) as e:
         gx.gammax_map_grids(dev(p.ref), dev(p.eval), p.spacing, p.spacing, (0, 0, 0), 0.03, 3.0, tail_lanes=1)
     assert e.value.status == -3
+
+
+def _eval_on_2d(seed, ref_shape, ref_sp, ev_sp, shift):
+    """The 2D generator's evaluation dose on another grid over the same field (centred axes),
+    the sampling positions moved by `shift` mm; with the evaluation grid's origin."""
+    from dosegen import make_pair_2d
+    shape = tuple(max(2, int(round(n * h / e))) for n, h, e in zip(ref_shape, ref_sp, ev_sp))
+    p = make_pair_2d(seed, shape=shape, spacing=ev_sp)
+    origin = tuple((n - 1) / 2 * h - (m - 1) / 2 * e + d
+                   for n, h, m, e, d in zip(ref_shape, ref_sp, shape, ev_sp, shift))
+    return p.eval.astype(np.float32), origin
+
+
+CASES_2D = [
+    ((1.0, 1.0), (0.35, -0.45)),     # same spacing, offset
+    ((0.5, 0.5), (0.0, 0.0)),        # twice as fine
+    ((2.0, 2.0), (-0.7, 0.9)),       # twice as coarse, offset
+    ((0.8, 1.3), (0.2, -0.6)),       # anisotropic
+]
+
+
+@pytest.mark.parametrize("ev_sp,ev_o", CASES_2D)
+@pytest.mark.parametrize("local", [False, True])
+def test_grids_2d_match_the_oracle(gx, ev_sp, ev_o, local):
+    from dosegen import make_pair_2d
+    ref_sp = (1.0, 1.0)
+    p = make_pair_2d(61, shape=(48, 52), spacing=ref_sp)
+    ev, ev_o = _eval_on_2d(61, p.ref.shape, ref_sp, ev_sp, ev_o)
+    o = oracle.gamma_grids(p.ref, ev, ref_sp, ev_sp, ev_o, 0.03, 3.0, 0.1, local)
+    g, r = gx.gammax_map_grids(dev(p.ref), dev(ev), ref_sp, ev_sp, ev_o, 0.03, 3.0, 0.1, local)
+    assert g.shape == p.ref.shape
+    assert_parity(host(g), o.gamma, f"2D grids {ev_sp} {ev_o} local={local}")
+    assert r.n_evaluated == o.n_evaluated > 0
+    assert abs(int(r.n_pass) - o.n_pass) <= o.n_borderline + r.n_borderline
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_grids_2d_same_grid_equals_gammax_map(gx, precision):
+    from dosegen import make_pair_2d
+    p = make_pair_2d(62, shape=(40, 45), spacing=(1.0, 1.5))
+    g1, r1 = gx.gammax_map(dev(p.ref), dev(p.eval), p.spacing, 0.02, 2.0, 0.1, precision=precision)
+    g2, r2 = gx.gammax_map_grids(dev(p.ref), dev(p.eval), p.spacing, p.spacing, (0.0, 0.0), 0.02, 2.0, 0.1,
+                                 precision=precision)
+    a, b = host(g1), host(g2)
+    assert np.array_equal(a >= 0, b >= 0)
+    m = a >= 0
+    assert np.all(np.abs(a[m] - b[m]) <= 1e-5 + 1e-5 * a[m])
+    assert (r1.n_evaluated, r1.n_pass) == (r2.n_evaluated, r2.n_pass)

@@ -139,12 +139,13 @@ def _lockstep_efficiency(work, order, wave=64):
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
-def test_trained_network_gains_over_the_dd_order(gx):
-    """What the trained network buys on a held-out pair (seed 20000, never trained on):
-    its prediction ranks the exact gamma better than the dose difference does, and
-    ordering the nodes that walk past the key-0 cells by it fills the waves of the
-    one-lane-per-node walk better than the paper's DD order.  Exact gamma and per-node
-    walk lengths come from the oracle."""
+def test_trained_network_orders_the_one_lane_walk_better_than_dd(gx):
+    """What the trained network buys on a held-out pair (seed 20000, never trained on), in
+    the one-lane-per-node tail layout (tail_lanes = 1, the paper's layout; not the default):
+    its prediction ranks the exact gamma better than the dose difference does, and ordering
+    the nodes that walk past the key-0 cells by it fills the waves of that walk better than
+    the paper's DD order.  Exact gamma and per-node walk lengths come from the oracle.  In
+    the default layout the network changes no work (test below)."""
     import oracle
     from dosegen import make_config_pair
     pair = make_config_pair("3d_128x128x96_2.5mm", 20000)
@@ -189,3 +190,28 @@ def test_learned_pooled_input_equals_plain(gx, models, kind):
     assert np.array_equal(host(g_plain), host(t.gamma))
     _, r_t = gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, timing=True, **kw)
     assert r_t.ms_cnn > 0
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_learned_radius_on_heldout_pairs_matches_the_oracle_and_walks_the_plain_cells(gx):
+    """The shipped network on held-out pairs (seeds 20000-20005, never trained on), default
+    layout, 128x128x96: the learned map is the oracle's gamma within the bar, equals the
+    plain map bit for bit, and visits the cells the plain walk visits (the prediction bounds
+    a first walk and orders the tail; the rows walked stay those with key below the running
+    gamma), up to where the groups' batches of rows start: within 0.1 %.  Prints the
+    fallback rate and |dgamma| per pair."""
+    import oracle
+    from dosegen import make_config_pair
+    m = gx.Model(np.load(WEIGHTS, allow_pickle=False))
+    for seed in range(20000, 20006):
+        pair = make_config_pair("3d_128x128x96_2.5mm", seed)
+        ref, ev = dev(pair.ref), dev(pair.eval)
+        gp, rp = gx.gammax_map(ref, ev, pair.spacing, 0.03, 3.0, 0.1)
+        gl, rl = gx.gammax_map(ref, ev, pair.spacing, 0.03, 3.0, 0.1, radius="learned", sort="predicted", model=m)
+        o = oracle.gamma(pair.ref, pair.eval, pair.spacing, 0.03, 3.0, 0.1)
+        err = assert_parity(host(gl), o.gamma, f"held-out {seed}")
+        assert np.array_equal(host(gp), host(gl))
+        assert (rl.n_tail, rl.n_pass) == (rp.n_tail, rp.n_pass)
+        assert abs(int(rl.n_cells) - int(rp.n_cells)) <= 1e-3 * rp.n_cells, (rl.n_cells, rp.n_cells)
+        print(f"seed {seed}: tail {rl.n_tail}, fallback {rl.n_fallback} ({rl.n_fallback / max(rl.n_tail, 1):.2f}), "
+              f"cells {rl.n_cells} vs plain {rp.n_cells}, max |dgamma| {err:.2e}", flush=True)

@@ -77,3 +77,56 @@ def test_nodes_outside_the_evaluation_box():
     assert np.array_equal(o.gamma >= 0, inside)
     assert np.all(o.gamma[inside] == 0.0)
     assert o.n_evaluated == inside.sum() and o.n_masked == 216
+
+
+# ---- 2D --------------------------------------------------------------------------------
+
+def test_2d_same_grid_matches_one_grid_oracle():
+    from dosegen import make_pair_2d
+    p = make_pair_2d(4, shape=(40, 44), spacing=(1.0, 1.5))
+    for crit, local in (((0.03, 3.0), False), ((0.02, 2.0), True)):
+        a = oracle.gamma(p.ref, p.eval, p.spacing, crit[0], crit[1], 0.1, local)
+        b = oracle.gamma_grids(p.ref, p.eval, p.spacing, p.spacing, (0.0, 0.0), crit[0], crit[1], 0.1, local)
+        assert a.n_evaluated == b.n_evaluated
+        m = a.gamma >= 0
+        assert np.array_equal(m, b.gamma >= 0)
+        assert np.allclose(b.gamma[m], a.gamma[m], rtol=1e-12, atol=1e-12)
+
+
+def test_2d_linear_dose_and_shifted_ramp():
+    """A linear dose on any 2D grid is its own interpolant (gamma = 0 inside), and a ramp
+    shifted by s on a finer offset grid gives the point-to-line distance."""
+    lin = lambda y, x: 1.0 - 0.015 * y + 0.01 * x  # noqa: E731
+    ref_sp, ev_sp, ev_o = (2.0, 2.0), (1.3, 0.7), (-1.1, 0.45)
+    ref = lin(*_grid((13, 14), ref_sp, (0.0, 0.0)))
+    ev = lin(*_grid((24, 44), ev_sp, ev_o))
+    o = oracle.gamma_grids(ref, ev, ref_sp, ev_sp, ev_o, 0.03, 3.0, 0.0)
+    m = o.gamma >= 0
+    assert m.sum() > 0.5 * m.size and np.all(o.gamma[m] <= 1e-9)
+    a, b, s, dd, dta = 1.0, 0.01, 1.7, 0.03, 3.0
+    y, x = _grid((9, 30), (2.0, 2.0), (0.0, 0.0))
+    ey, ex = _grid((30, 70), (1.25, 1.25), (-10.0, -10.0))
+    o = oracle.gamma_grids(a + b * x, a + b * (ex - s), (2.0, 2.0), (1.25, 1.25), (-10.0, -10.0), dd, dta, 0.0)
+    dD = dd * (a + b * x).max()
+    want = abs(b * s) / dD / np.sqrt(1.0 + (b * dta / dD) ** 2)
+    inner = (o.gamma >= 0) & (x > 10.0) & (x < 50.0)
+    assert inner.sum() > 50
+    assert np.allclose(o.gamma[inner], want, rtol=1e-10)
+
+
+def test_2d_equals_its_3d_extrusion():
+    """A pair constant along an added slowest axis gives the 2D gamma in every layer: the
+    3D Kuhn interpolant of such a dose is the 2D interpolant at every height."""
+    from dosegen import make_pair_2d
+    p = make_pair_2d(5, shape=(30, 33), spacing=(1.0, 1.0))
+    ev_sp, ev_o = (0.8, 1.3), (0.25, -0.4)
+    shape = tuple(int(round(n * h / e)) for n, h, e in zip(p.ref.shape, p.spacing, ev_sp))
+    ev = make_pair_2d(5, shape=shape, spacing=ev_sp).eval
+    o2 = oracle.gamma_grids(p.ref, ev, p.spacing, ev_sp, ev_o, 0.03, 3.0, 0.1)
+    ref3 = np.stack([p.ref, p.ref])
+    ev3 = np.stack([ev, ev, ev])
+    o3 = oracle.gamma_grids(ref3, ev3, (1.7,) + p.spacing, (0.85,) + ev_sp, (0.0,) + ev_o, 0.03, 3.0, 0.1)
+    for layer in range(2):
+        m = o2.gamma >= 0
+        assert np.array_equal(m, o3.gamma[layer] >= 0)
+        assert np.allclose(o3.gamma[layer][m], o2.gamma[m], rtol=1e-10, atol=1e-12)
