@@ -42,9 +42,9 @@ PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 # hash differs the traffic is reported as null.
 TRAFFIC = {
     "3d_128x128x96_2.5mm": {
-        "bytes": (15.63 + 2.25) * 1e6,
+        "bytes": (15.65 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "297d1094c42001bde47ba8e45d098521f9cd48cb730dead6a557a9351a441884",
+        "sha256": "a6e939f25860a0329496158cd15b987a4c9fbca580febb5d7365a05eb31a8dad",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }
@@ -183,9 +183,36 @@ def _sweep_point(gx, torch, np, ref, ev, spacing, dd, dta, args, **extra):
               ms_gamma=round(ms_gamma, 4), n_cells=int(r.n_cells), n_tail=int(r.n_tail),
               sum_gamma3=float((gam ** 3).sum().item()), pass_rate=round(r.pass_rate, 6),
               max_gamma=round(r.max_gamma, 4))
+    if args.sweep_oracle > 0:
+        pt["cpu_baseline"] = _sweep_oracle(np, ref, ev, spacing, dd, dta, g, r, args.sweep_oracle)
     pt.update(extra)
     print(json.dumps(pt), flush=True)
     return pt
+
+
+def _sweep_oracle(np, ref, ev, spacing, dd, dta, g, r, n_sample):
+    """The FP64 oracle beside a sweep point, on a sample of the evaluated nodes (random,
+    seeded): its time per node on the host cores, its gamma against the GPU's at those
+    nodes, and its visited cells per node against the GPU's total per evaluated node."""
+    import oracle
+
+    gh = g.detach().cpu().numpy().ravel()
+    masked = np.flatnonzero(gh >= 0)
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(masked, size=min(n_sample, masked.size), replace=False))
+    rh, eh = ref.detach().cpu().numpy(), ev.detach().cpu().numpy()
+    t0 = time.perf_counter()
+    o = oracle.gamma(rh, eh, spacing, dd, dta, 0.1, subset=idx)
+    sec = time.perf_counter() - t0
+    err = np.abs(gh[idx].astype(np.float64) - o.gamma)
+    bar = 1e-5 + 1e-5 * o.gamma
+    cells_o = float(o.cells.astype(np.float64).mean())
+    return {"kind": "oracle", "sample": f"{idx.size} evaluated nodes drawn at random (seed 7)",
+            "cores": oracle.max_threads(), "value": round(idx.size / sec, 1), "unit": "ref voxels/s",
+            "max_abs_dgamma": float(err.max()), "n_beyond_tol": int((err > bar).sum()),
+            "same_mask": bool(np.all(o.gamma >= 0)),
+            "cells_per_node_oracle": round(cells_o, 3),
+            "cells_per_node_gpu": round(r.n_cells / max(r.n_evaluated, 1), 3)}
 
 
 def _fit_line(x, y):
@@ -506,6 +533,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2, help="fewest oracle repetitions")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="least CPU time the oracle baseline runs for")
+    ap.add_argument("--sweep-oracle", type=int, default=4096,
+                    help="sweeps: evaluated nodes per point on which the FP64 oracle runs beside the GPU (0: none)")
     ap.add_argument("--sweep", choices=["criteria", "resolution", "shift", "order", "grids"], default=None,
                     help="run one of the paper's scaling studies instead of the benchmark line")
     ap.add_argument("--concurrent", type=int, default=16,
