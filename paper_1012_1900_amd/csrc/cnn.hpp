@@ -50,10 +50,17 @@ struct BwdWArgs {
 };
 
 int64_t conv_blocks(const int o[3], int nvol);
-// mode 0: relu -> bf16; 1: linear -> FP32 channel 0; 2: bwd-data with ReLU mask -> bf16
+// mode 0: relu -> bf16; 1: linear -> FP32 channel 0 (the last layer, fragments packed by
+// shifts: launch_pack bwd == 2); 2: bwd-data with ReLU mask -> bf16
 hipError_t launch_conv(int cin, int mode, const uint16_t* in, const int i[3], int64_t in_vstride,
                        const uint16_t* wfrag, const float* bias, int cout, const uint16_t* mask, void* out,
                        const int o[3], int64_t out_vstride, int off, int nvol, hipStream_t s);
+// Layers 1 and 2 fused: features f (2 channels) -> 16 -> 16 channels, ReLU after each, into
+// out (shape o = f - 4), without storing layer 1's output.  Same values as two launch_conv
+// calls (mode 0).
+hipError_t launch_conv12(const uint16_t* feat, const int f[3], int64_t feat_vstride, const uint16_t* wfrag1,
+                         const float* bias1, const uint16_t* wfrag2, const float* bias2, uint16_t* out, const int o[3],
+                         int64_t out_vstride, int nvol, hipStream_t s);
 hipError_t launch_conv_bwdw(int cin, const uint16_t* x, const int i[3], int64_t x_vstride, const uint16_t* g,
                             const int o[3], int64_t g_vstride, int nvol, float* partial, hipStream_t s);
 hipError_t launch_grad_reduce(const float* partial, int nblocks, int cin, int cout, float* grad, hipStream_t s);
@@ -62,6 +69,7 @@ hipError_t launch_loss(const float* y, const float* gamma, int64_t n, float scal
                        int nblocks, hipStream_t s);
 hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int n, float lr, float beta1,
                        float beta2, float eps, float c1, float c2, hipStream_t s);
+// Fragments of one layer: bwd 0 forward, 1 bwd-data, 2 the last layer by shifts.
 hipError_t launch_pack(const float* w, int cin, int cout, int bwd, uint16_t* frag, hipStream_t s);
 // The network at the listed nodes only (their 9^3 patches): y[i] for node nodes[i], i < *count;
 // key (optional) receives the bits of gamma_hat.  n: grid shape, slowest first.

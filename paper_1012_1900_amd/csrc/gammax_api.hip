@@ -423,10 +423,11 @@ struct CallSetup {
     int64_t n;
 };
 
-// Workspace of the CNN over one grid: features (o+8, 2 channels), then the three hidden
-// activations (o+6, o+4, o+2; 16 channels), each 256-byte aligned.
+// Workspace of the CNN over one grid: features (o+8, 2 channels), then the hidden
+// activations of layers 2 and 3 (o+4, o+2; 16 channels), each 256-byte aligned.  Layer 1's
+// output (o+6) is never stored: layers 1 and 2 run fused.
 struct CnnWs {
-    uint16_t *feat, *a1, *a2, *a3;
+    uint16_t *feat, *a2, *a3;
     int64_t bytes;
 };
 CnnWs cnn_layout(unsigned char* base, const int o[3]) {
@@ -440,8 +441,6 @@ CnnWs cnn_layout(unsigned char* base, const int o[3]) {
     int sh[3];
     act_shape(o, 8, sh);
     w.feat = take(vol_of(sh) * 4);
-    act_shape(o, 6, sh);
-    w.a1 = take(vol_of(sh) * 32);
     act_shape(o, 4, sh);
     w.a2 = take(vol_of(sh) * 32);
     act_shape(o, 2, sh);
@@ -562,7 +561,7 @@ hipError_t tail_cnn_hook(void* user, hipStream_t s) {
         int co[3];
         pool2_shape(h.shape, co);
         if ((e = launch_features_pool2(h.ref, h.ev, h.shape, h.sc, h.ws.feat, s)) != hipSuccess) return e;
-        if ((e = model_forward(m, h.ws.feat, 1, co, h.ws.a1, h.ws.a2, h.ws.a3, h.ycoarse, s)) != hipSuccess) return e;
+        if ((e = model_forward(m, h.ws.feat, 1, co, nullptr, h.ws.a2, h.ws.a3, h.ycoarse, s)) != hipSuccess) return e;
         if ((e = launch_cnn_upsample(h.ycoarse, h.shape, h.nodes, h.count, h.blocks, h.y, h.key, s)) != hipSuccess)
             return e;
         if (h.ev1 && (e = hipEventRecord(h.ev1, s)) != hipSuccess) return e;
@@ -1534,7 +1533,7 @@ gammax_status_t gammax_model_predict(gammax_ctx_t* c, gammax_model_t* m, const g
     if ((st = grow_cnn(c, o, &w)) != GAMMAX_OK) return st;
     if ((st = enqueue_dose_scalars(c, p, ref, ev, n, s)) != GAMMAX_OK) return st;
     HIPCHK(c, launch_features(ref, ev, o, c->d_sc, w.feat, s));
-    HIPCHK(c, model_forward(m, w.feat, 1, o, w.a1, w.a2, w.a3, y, s));
+    HIPCHK(c, model_forward(m, w.feat, 1, o, nullptr, w.a2, w.a3, y, s));
     HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return device_errors(c, false);

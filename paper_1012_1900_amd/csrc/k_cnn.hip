@@ -21,6 +21,8 @@
 // transposed kernel and an input offset of -2 (full correlation), times the ReLU mask of
 // the stored activation; bwd-weight contracts over nodes (D[co][ci] per tap, both
 // operands staged planar in LDS), one partial per workgroup, reduced deterministically.
+#include <type_traits>
+
 #include "internal.hpp"
 #include "cnn.hpp"
 
@@ -71,6 +73,15 @@ __device__ __forceinline__ f32x4 mfma_bf16(const U4& a, const U4& b, f32x4 c) {
                                                    0, 0, 0);
 }
 
+// Tile of workgroup b.  Workgroups are dealt to the 8 XCDs in turn (b on XCD b % 8), each
+// with its own L2; neighbouring tiles share halo nodes, so XCD k takes the k-th contiguous
+// eighth of the tiles (in x, then y, z order) and the halos mostly hit its L2.  A bijection
+// of [0, n) whatever the dispatch order, so only locality depends on it.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 constexpr int TX = CNN_TILE_X, TY = CNN_TILE_Y, TZ = CNN_TILE_Z;
 constexpr int LX = TX + 2, LY = TY + 2, LZ = TZ + 2;
 constexpr int NTHREADS = 256;
@@ -81,126 +92,445 @@ __device__ __forceinline__ void tap_xyz(int t, int& dz, int& dy, int& dx) {
     dx = t % 3;
 }
 
+// The 14 k chunks of a layer with 16 input channels: chunk c holds tap chunk_tap(c, 0) in
+// k 0..15 (lane groups 0, 1 of the B operand) and tap chunk_tap(c, 1) in k 16..31 (groups
+// 2, 3), 16 channels each; tap t = 9 dz + 3 dy + dx, 27 = none (zero weights).
+//   c = 3 dz + dy (0..8): (dz, dy, 0) and (dz, dy, 1), an x pair;
+//   c = 9 + dy:           (0, dy, 2) and (1, dy, 2);
+//   c = 12:               (2, 0, 2) and (2, 1, 2);
+//   c = 13:               (2, 2, 2) alone.
+// The x pairs let one B operand (16 nodes of an input row, two x shifts) serve every output
+// row that reads that input row, with the chunk of its (dz, dy).
+__host__ __device__ constexpr int chunk_tap(int c, int h) {
+    return c < 9 ? 9 * (c / 3) + 3 * (c % 3) + h
+                 : (c < 12 ? 9 * h + 3 * (c - 9) + 2 : (c == 12 ? 20 + 3 * h : (h == 0 ? 26 : 27)));
+}
+
 // ---- forward / bwd-data convolution ----------------------------------------------------
 //
 // MODE 0: out = bf16(relu(acc + bias)), 16 channels.
-// MODE 1: out = acc + bias, channel 0 only, FP32 (the last layer).
 // MODE 2: out = bf16(mask > 0 ? acc : 0), 16 channels, no bias (bwd-data with the ReLU
 //         derivative of the stored activation `mask`, which has the output's shape).
-template <int CIN, int MODE>
-__global__ __launch_bounds__(NTHREADS) void k_conv(ConvArgs a) {
-    constexpr int NCH = CIN == 16 ? 14 : 2;      // 32-wide k chunks: ceil(27 * CIN / 32)
-    __shared__ __align__(16) uint16_t tile[LZ * LY * LX * CIN];
+// The last layer (one FP32 output channel, no ReLU) has a kernel of its own, k_conv_last.
+//
+// Tile: FX x FY x FZ output nodes per workgroup of 8 waves, the input tile (halo 2) and
+// the weight fragments staged in LDS (76.5 KB with 16 input channels: two workgroups, 16
+// waves, per compute unit).  Wave w computes the rows y0 + 2w and y0 + 2w + 1 for all FZ
+// planes in one pass: 8 rows whose LDS addresses differ by immediates, so one per-lane
+// address serves them all, and 8 accumulation chains alternate on the matrix core, each
+// chunk's weight fragment (one LDS read) feeding 8 products.  Every row still sums its
+// chunks in order 0, 1, ..., so a row's value does not depend on the grouping.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-    int b = blockIdx.x;
-    const int txi = b % a.tiles_x;
-    b /= a.tiles_x;
-    const int tyi = b % a.tiles_y;
-    b /= a.tiles_y;
-    const int tzi = b % a.tiles_z;
-    const int vol = b / a.tiles_z;
-    const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * TZ;
-    const uint16_t* in = a.in + (int64_t)vol * a.in_vstride;
+constexpr int FX = 16, FY = 16, FZ = 4;
+constexpr int FLX = FX + 2, FLY = FY + 2, FLZ = FZ + 2;
+constexpr int FTHREADS = 512;
+constexpr int FNRY = FY / (FTHREADS / 64);   // y rows per wave
+static_assert(FNRY * (FTHREADS / 64) == FY, "the waves must cover the tile's rows");
 
-    // stage the input tile (halo 2 on the upper side; coordinates shifted by `off`);
-    // nodes outside the input volume read as 0
-    if (CIN == 16) {
-        for (int u = threadIdx.x; u < LZ * LY * LX * 2; u += NTHREADS) {
-            const int v = u >> 1, h = u & 1;
-            const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
-            const int gx = x0 + lx + a.off, gy = y0 + ly + a.off, gz = z0 + lz + a.off;
-            U4 q = {0u, 0u, 0u, 0u};
-            if (gx >= 0 && gx < a.ix && gy >= 0 && gy < a.iy && gz >= 0 && gz < a.iz)
-                q = *reinterpret_cast<const U4*>(in + (((int64_t)gz * a.iy + gy) * a.ix + gx) * 16 + h * 8);
-            *reinterpret_cast<U4*>(&tile[v * 16 + h * 8]) = q;
-        }
-    } else {
-        for (int v = threadIdx.x; v < LZ * LY * LX; v += NTHREADS) {
-            const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
-            const int gx = x0 + lx + a.off, gy = y0 + ly + a.off, gz = z0 + lz + a.off;
-            uint32_t q = 0u;
-            if (gx >= 0 && gx < a.ix && gy >= 0 && gy < a.iy && gz >= 0 && gz < a.iz)
-                q = *reinterpret_cast<const uint32_t*>(in + (((int64_t)gz * a.iy + gy) * a.ix + gx) * 2);
-            *reinterpret_cast<uint32_t*>(&tile[v * 2]) = q;
-        }
+// Offset in nodes of tap t = 9 dz + 3 dy + dx within a staged forward tile.
+__host__ __device__ constexpr int ftap_offset(int t) { return ((t / 9) * FLY + (t / 3) % 3) * FLX + t % 3; }
+
+// Stage the box of BX x BY x BZ nodes with corner (gx0, gy0, gz0) of a channel-last volume
+// (iz, iy, ix, CIN channels) into LDS, node-major with CIN channels per node; nodes outside
+// the volume read as 0.  Thread t owns one 16-byte (16 channels) or 4-byte (2 channels) slot
+// e = t % E of a box row of E slots and the rows t / E + RPR k, so its x coordinate and x
+// bounds test are fixed.  All loads of a thread are issued before the first store, so the
+// rounds share one memory latency (an outside node loads node 0 and stores 0).
+template <int CIN, int BX, int BY, int BZ>
+__device__ __forceinline__ void stage_box(const uint16_t* __restrict__ in, int ix, int iy, int iz, int gx0, int gy0,
+                                          int gz0, uint16_t* tile) {
+    constexpr int PER_NODE = CIN == 16 ? 2 : 1;
+    constexpr int E = BX * PER_NODE, RPR = FTHREADS / E, NROW = BZ * BY;
+    constexpr int ROUNDS = (NROW + RPR - 1) / RPR;
+    constexpr int SLOT = CIN == 16 ? 8 : 2;   // bf16 per slot
+    static_assert(ROUNDS <= 32, "one mask bit per round");
+    using V = typename std::conditional<CIN == 16, u32x4, uint32_t>::type;
+    const int e = threadIdx.x % E, r0 = threadIdx.x / E;
+    const int gx = gx0 + e / PER_NODE;
+    const bool okx = r0 < RPR && (unsigned)gx < (unsigned)ix;
+    const uint16_t* pe = in + (e % PER_NODE) * 8;
+    V q[ROUNDS];
+    uint32_t okm = 0u;
+#pragma unroll
+    for (int k = 0; k < ROUNDS; ++k) {
+        const int row = r0 + RPR * k;
+        const int ly = row % BY, lz = row / BY;
+        const int gy = gy0 + ly, gz = gz0 + lz;
+        const bool ok = okx && row < NROW && (unsigned)gy < (unsigned)iy && (unsigned)gz < (unsigned)iz;
+        okm |= ok ? (1u << k) : 0u;
+        // node index within the volume: below 2^31 (the launchers check)
+        const uint32_t node = ok ? (uint32_t)((gz * iy + gy) * ix + gx) : 0u;
+        q[k] = *reinterpret_cast<const V*>(pe + (uint64_t)node * CIN);
     }
+#pragma unroll
+    for (int k = 0; k < ROUNDS; ++k) {
+        const int row = r0 + RPR * k;
+        if (r0 < RPR && row < NROW)
+            *reinterpret_cast<V*>(&tile[row * (BX * CIN) + e * SLOT]) = ((okm >> k) & 1u) ? q[k] : V(0u);
+    }
+}
 
+// Tile of workgroup blockIdx.x (XCD-aware order): volume and corner of its output box.
+struct FTile {
+    int vol, x0, y0, z0;
+};
+__device__ __forceinline__ FTile ftile_of(int tiles_x, int tiles_y, int tiles_z) {
+    int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    FTile t;
+    const int txi = b % tiles_x;
+    b /= tiles_x;
+    const int tyi = b % tiles_y;
+    b /= tiles_y;
+    const int tzi = b % tiles_z;
+    t.vol = b / tiles_z;
+    t.x0 = txi * FX;
+    t.y0 = tyi * FY;
+    t.z0 = tzi * FZ;
+    return t;
+}
+
+// The 16-channel convolution of a staged FLX x FLY x FLZ tile (node-major, 32 bytes per
+// node) for this wave's rows, and its epilogue.  w: this lane's 14 fragments (registers);
+// bl: 16 biases in LDS.  Wave w computes the FNRY x FZ rows y0 + FNRY w + yy, z0 + rz.
+// Input-row major: each B operand (16 nodes of one input row of the tile, an x pair or
+// the x = 2 taps, one channel half per lane) is read from LDS once and multiplied into
+// every row of the wave that reads it, with the chunk of its offset, so the wave reads 56
+// operands for its 112 products.  Every row still receives its chunks in order 0..13 (the
+// loops run dz outer, dy inner), the same sums as one row at a time.
+template <int MODE>   // 0 or 2
+__device__ __forceinline__ void conv16_rows(const uint16_t* tile, const U4 (&w)[14], const float* bl,
+                                            const ConvArgs& a, const FTile& t) {
+    constexpr int NODE_B = 32, ROW_B = FLX * NODE_B, PLANE_B = FLY * ROW_B;
+    static_assert(FNRY == 2 && FZ == 4, "the operand schedule below is written for 2 x 4 rows");
+    static_assert((FNRY + 1) * ROW_B + (FZ + 1) * PLANE_B < 65536, "LDS immediate offsets are 16 bits");
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int j = lane & 15, g = lane >> 4;
-    U4 wr[NCH];
+    const uint32_t hi = (uint32_t)(g >> 1);
+    const char* tb = reinterpret_cast<const char*>(tile);
+    const int ry0 = wv * FNRY;
+    // lane's node (ry0, z 0, x j), channel half g & 1
+    const uint32_t rbase = (uint32_t)((ry0 * FLX + j) * NODE_B + (g & 1) * 16);
+    // per-kind bases: the second tap of the lane's group (hi) sits one node along x (x pairs),
+    // one plane along z (chunks 9..11) or one row along y (chunk 12); chunk 13's groups 2, 3
+    // carry zero weights and read the first tap
+    const uint32_t bP = rbase + hi * NODE_B;
+    const uint32_t bQ = rbase + 2 * NODE_B + hi * PLANE_B;
+    const uint32_t bR = rbase + 2 * NODE_B + hi * ROW_B;
+    const uint32_t bS = rbase + 2 * NODE_B;
+    auto ld = [&](uint32_t base, int Y, int Z) -> U4 {
+        return *reinterpret_cast<const U4*>(tb + base + (Y * ROW_B + Z * PLANE_B));
+    };
+    f32x4 acc[8];   // row yy * 4 + rz
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) wr[c] = reinterpret_cast<const U4*>(a.wfrag)[c * 64 + lane];
-    float bias[4] = {0.f, 0.f, 0.f, 0.f};
-    if (MODE != 2) {
+    for (int r = 0; r < 8; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // x pairs: input row (Y, Z) feeds output row (yy, rz) with chunk 3 (Z - rz) + (Y - yy)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) bias[r] = (4 * g + r < a.cout) ? a.bias[4 * g + r] : 0.f;
-    }
-    // per-lane LDS offsets (in nodes) of the taps this lane reads in each chunk
-    int toff[CIN == 16 ? NCH : NCH * 4];
-    if (CIN == 16) {
+    for (int Z = 0; Z < FZ + 2; ++Z)
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            int t = 2 * c + (g >> 1);
-            t = t > 26 ? 26 : t;   // zero weights there; any finite operand will do
-            int dz, dy, dx;
-            tap_xyz(t, dz, dy, dx);
-            toff[c] = (dz * LY + dy) * LX + dx;
+        for (int Y = 0; Y < FNRY + 2; ++Y) {
+            const U4 b = ld(bP, Y, Z);
+#pragma unroll
+            for (int yy = 0; yy < FNRY; ++yy)
+#pragma unroll
+                for (int rz = 0; rz < FZ; ++rz) {
+                    const int dy = Y - yy, dz = Z - rz;
+                    if (dy >= 0 && dy <= 2 && dz >= 0 && dz <= 2)
+                        acc[yy * FZ + rz] = mfma_bf16(w[3 * dz + dy], b, acc[yy * FZ + rz]);
+                }
         }
-    } else {
+    // x = 2 taps of planes dz 0 and 1: input row (Y, rz) feeds row (yy, rz) with chunk 9 + (Y - yy)
 #pragma unroll
-        for (int c = 0; c < NCH; ++c)
+    for (int rz = 0; rz < FZ; ++rz)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                int t = 16 * c + 4 * g + q;
-                t = t > 26 ? 26 : t;
-                int dz, dy, dx;
-                tap_xyz(t, dz, dy, dx);
-                toff[c * 4 + q] = (dz * LY + dy) * LX + dx;
+        for (int Y = 0; Y < FNRY + 2; ++Y) {
+            const U4 b = ld(bQ, Y, rz);
+#pragma unroll
+            for (int yy = 0; yy < FNRY; ++yy) {
+                const int dy = Y - yy;
+                if (dy >= 0 && dy <= 2) acc[yy * FZ + rz] = mfma_bf16(w[9 + dy], b, acc[yy * FZ + rz]);
             }
+        }
+    // chunks 12 and 13
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int yy = r / FZ, rz = r % FZ;
+        acc[r] = mfma_bf16(w[12], ld(bR, yy, rz + 2), acc[r]);
     }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int yy = r / FZ, rz = r % FZ;
+        acc[r] = mfma_bf16(w[13], ld(bS, yy + 2, rz + 2), acc[r]);
+    }
+
+    const int ox = t.x0 + j;
+    if (ox >= a.ox) return;
+    const float bias[4] = {bl[4 * g], bl[4 * g + 1], bl[4 * g + 2], bl[4 * g + 3]};
+    const int64_t pstride = (int64_t)a.oy * a.ox * 16;
+#pragma unroll
+    for (int yy = 0; yy < FNRY; ++yy) {
+        const int oy = t.y0 + ry0 + yy;
+        if (oy >= a.oy) break;
+        // output of node (z0 + rz, oy, ox): one pointer, advanced by a plane per row
+        const int64_t e0 = (int64_t)t.vol * a.out_vstride + (((int64_t)t.z0 * a.oy + oy) * a.ox + ox) * 16 + 4 * g;
+        uint16_t* oh = reinterpret_cast<uint16_t*>(a.out) + e0;
+        const uint16_t* mh = a.mask + e0;
+#pragma unroll
+        for (int rz = 0; rz < FZ; ++rz) {
+            if (t.z0 + rz >= a.oz) break;
+            const f32x4 v = acc[yy * FZ + rz];
+            uint2 st;
+            if (MODE == 0) {
+                st.x = pack2bf(fmaxf(v[0] + bias[0], 0.f), fmaxf(v[1] + bias[1], 0.f));
+                st.y = pack2bf(fmaxf(v[2] + bias[2], 0.f), fmaxf(v[3] + bias[3], 0.f));
+            } else {
+                const uint2 m = *reinterpret_cast<const uint2*>(mh);
+                mh += pstride;
+                st.x = pack2bf(bf2f(m.x) > 0.f ? v[0] : 0.f, bf2f(m.x >> 16) > 0.f ? v[1] : 0.f);
+                st.y = pack2bf(bf2f(m.y) > 0.f ? v[2] : 0.f, bf2f(m.y >> 16) > 0.f ? v[3] : 0.f);
+            }
+            *reinterpret_cast<uint2*>(oh) = st;
+            oh += pstride;
+        }
+    }
+}
+
+// Layer 1 (2 -> 16 channels, ReLU, bf16) of NODES nodes of a box of BX x BY x BZ output
+// nodes, written into a 16-channel LDS tile (node-major, 32 bytes per node).  `feat` is the
+// staged 2-channel input box, (BX + 2) x (BY + 2) x (BZ + 2).  16 consecutive box nodes per
+// product (a lane's node index picks its own input address); 2 chunks of 4 taps x 2
+// channels per lane; each wave takes groups w, w + 8, ..., two at a time.  w0: the layer's
+// 2 fragments of this lane; b0: the biases of this lane's 4 output channels.  The same
+// chunks, operands and rounding as k_conv<2, 0>, so the values are those it stores.
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ void layer1_to_lds(const uint16_t* feat, uint16_t* out, const U4 (&w0)[2],
+                                              const float (&b0)[4]) {
+    constexpr int NODES = BX * BY * BZ, NGRP = (NODES + 15) / 16;
+    constexpr int IX = BX + 2, IY = BY + 2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    // per-lane offsets (in input nodes) of the 4 taps of each chunk: tap 16 c + 4 g + q
+    int toff[8];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int tt[4];
+#pragma unroll
+            for (int gg = 0; gg < 4; ++gg) {
+                int t = 16 * c + 4 * gg + q;
+                t = t > 26 ? 26 : t;   // zero weights there
+                tt[gg] = ((t / 9) * IY + (t / 3) % 3) * IX + t % 3;
+            }
+            toff[c * 4 + q] = (g & 2) ? ((g & 1) ? tt[3] : tt[2]) : ((g & 1) ? tt[1] : tt[0]);
+        }
+    const uint32_t* fw = reinterpret_cast<const uint32_t*>(feat);
+#pragma unroll 1
+    for (int grp = wv; grp < NGRP; grp += 2 * (FTHREADS / 64)) {
+        int n[2], base[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            n[h] = (grp + h * (FTHREADS / 64)) * 16 + j;
+            const int m = n[h] < NODES ? n[h] : NODES - 1;
+            const int lx = m % BX, r = m / BX;
+            base[h] = ((r / BY) * IY + r % BY) * IX + lx;
+        }
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            U4 b0v, b1v;
+            b0v.x = fw[base[0] + toff[c * 4 + 0]];
+            b0v.y = fw[base[0] + toff[c * 4 + 1]];
+            b0v.z = fw[base[0] + toff[c * 4 + 2]];
+            b0v.w = fw[base[0] + toff[c * 4 + 3]];
+            b1v.x = fw[base[1] + toff[c * 4 + 0]];
+            b1v.y = fw[base[1] + toff[c * 4 + 1]];
+            b1v.z = fw[base[1] + toff[c * 4 + 2]];
+            b1v.w = fw[base[1] + toff[c * 4 + 3]];
+            acc0 = mfma_bf16(w0[c], b0v, acc0);
+            acc1 = mfma_bf16(w0[c], b1v, acc1);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const f32x4 v = h ? acc1 : acc0;
+            if (n[h] < NODES) {
+                uint2 st;
+                st.x = pack2bf(fmaxf(v[0] + b0[0], 0.f), fmaxf(v[1] + b0[1], 0.f));
+                st.y = pack2bf(fmaxf(v[2] + b0[2], 0.f), fmaxf(v[3] + b0[3], 0.f));
+                *reinterpret_cast<uint2*>(&out[n[h] * 16 + 4 * g]) = st;
+            }
+        }
+    }
+}
+
+// Forward / bwd-data convolution of one FX x FY x FZ output box per workgroup of 8 waves:
+// the input tile (halo 2) and the weight fragments staged in LDS (76.5 KB with 16 input
+// channels: two workgroups, 16 waves, per compute unit).
+template <int CIN, int MODE>
+__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_conv(ConvArgs a) {
+    constexpr int NCH = CIN == 16 ? 14 : 2;      // 32-wide k chunks: ceil(27 * CIN / 32)
+    constexpr int NV = FLZ * FLY * FLX;          // nodes of the staged tile
+    __shared__ __align__(16) uint16_t tile[NV * CIN];
+    __shared__ __align__(16) U4 wl[CIN == 16 ? 1 : NCH * 64];   // layer 1 only
+    __shared__ float bl[16];
+
+    const FTile t = ftile_of(a.tiles_x, a.tiles_y, a.tiles_z);
+    if (threadIdx.x < 16) bl[threadIdx.x] = (MODE != 2 && (int)threadIdx.x < a.cout) ? a.bias[threadIdx.x] : 0.f;
+    if constexpr (CIN == 16) {
+        const int lane = threadIdx.x & 63;
+        U4 w[14];
+#pragma unroll
+        for (int c = 0; c < 14; ++c) w[c] = reinterpret_cast<const U4*>(a.wfrag)[c * 64 + lane];
+        stage_box<CIN, FLX, FLY, FLZ>(a.in + (int64_t)t.vol * a.in_vstride, a.ix, a.iy, a.iz, t.x0 + a.off,
+                                      t.y0 + a.off, t.z0 + a.off, tile);
+        __syncthreads();
+        conv16_rows<MODE>(tile, w, bl, a, t);
+    } else {
+        for (int u = threadIdx.x; u < NCH * 64; u += FTHREADS) wl[u] = reinterpret_cast<const U4*>(a.wfrag)[u];
+        stage_box<CIN, FLX, FLY, FLZ>(a.in + (int64_t)t.vol * a.in_vstride, a.ix, a.iy, a.iz, t.x0 + a.off,
+                                      t.y0 + a.off, t.z0 + a.off, tile);
+        // layer 1 on its own (training keeps its output): FX x FY x FZ outputs from the tile
+        U4 w0[2];
+        float b0[4];
+        const int lane = threadIdx.x & 63, g = lane >> 4;
+        __syncthreads();
+        w0[0] = wl[lane];
+        w0[1] = wl[64 + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) b0[r] = bl[4 * g + r];
+        // compute into LDS rows, then copy out: reuse the rows of the output box
+        __shared__ __align__(16) uint16_t ob[FX * FY * FZ * 16];
+        layer1_to_lds<FX, FY, FZ>(tile, ob, w0, b0);
+        __syncthreads();
+        // store the box: 2 x 16 bytes per node, node-major as the output volume
+        for (int u = threadIdx.x; u < FX * FY * FZ * 2; u += FTHREADS) {
+            const int n = u >> 1, h = u & 1;
+            const int lx = n % FX, r = n / FX, ly = r % FY, lz = r / FY;
+            const int ox = t.x0 + lx, oy = t.y0 + ly, oz = t.z0 + lz;
+            if (ox < a.ox && oy < a.oy && oz < a.oz)
+                *reinterpret_cast<U4*>(reinterpret_cast<uint16_t*>(a.out) + (int64_t)t.vol * a.out_vstride +
+                                       (((int64_t)oz * a.oy + oy) * a.ox + ox) * 16 + h * 8) =
+                    *reinterpret_cast<const U4*>(&ob[n * 16 + h * 8]);
+        }
+    }
+}
+
+// Layers 1 and 2 fused (features -> 16 -> 16 channels, ReLU after each): the workgroup
+// stages the (FX + 4) x (FY + 4) x (FZ + 4) feature box, computes layer 1 on the
+// FLX x FLY x FLZ nodes that layer 2 reads into LDS (halo nodes recomputed by the
+// neighbouring workgroups), then runs layer 2 as k_conv<16, 0> does.  Layer 1's output
+// never leaves the chip.
+struct Conv12Args {
+    ConvArgs l2;                 // layer 2 (in unused: layer 1's output is the tile)
+    const uint16_t* feat;        // padded features, 2 channels
+    int fz, fy, fx;              // feature volume shape
+    int64_t feat_vstride;
+    const void* wfrag1;          // layer 1 fragments (2 chunks)
+    const float* bias1;
+};
+
+__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_conv12(Conv12Args a) {
+    constexpr int NV = FLZ * FLY * FLX;
+    constexpr int FB = (FX + 4) * (FY + 4) * (FZ + 4);   // feature box nodes
+    __shared__ __align__(16) uint16_t tile[NV * 16];
+    __shared__ __align__(16) uint16_t fb[FB * 2];
+    __shared__ float bl[16];
+
+    const ConvArgs& l2 = a.l2;
+    const FTile t = ftile_of(l2.tiles_x, l2.tiles_y, l2.tiles_z);
+    const int lane = threadIdx.x & 63, g = lane >> 4;
+    U4 w2[14];
+#pragma unroll
+    for (int c = 0; c < 14; ++c) w2[c] = reinterpret_cast<const U4*>(l2.wfrag)[c * 64 + lane];
+    U4 w0[2];
+    w0[0] = reinterpret_cast<const U4*>(a.wfrag1)[lane];
+    w0[1] = reinterpret_cast<const U4*>(a.wfrag1)[64 + lane];
+    float b0[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b0[r] = a.bias1[4 * g + r];
+    if (threadIdx.x < 16) bl[threadIdx.x] = (int)threadIdx.x < l2.cout ? l2.bias[threadIdx.x] : 0.f;
+    stage_box<2, FX + 4, FY + 4, FZ + 4>(a.feat + (int64_t)t.vol * a.feat_vstride, a.fx, a.fy, a.fz, t.x0, t.y0,
+                                         t.z0, fb);
+    __syncthreads();
+    layer1_to_lds<FLX, FLY, FLZ>(fb, tile, w0, b0);
+    __syncthreads();
+    conv16_rows<0>(tile, w2, bl, l2, t);
+}
+
+// The last layer (16 channels -> 1, no ReLU, FP32 out) by shifts.  One output channel would
+// use 1 of the 16 rows of a product; instead the rows are the 9 (dz, dy) shifts: for an
+// input row (y, z) of the staged tile, D[s][x] = sum over dx, ci of w[dz, dy, dx, ci]
+// a[y, z, x + dx, ci] (two products: the x pair, then x = 2) is the contribution of that
+// input row to output row (y - dy, z - dz).  Lane (x, g) holds shifts s = 4 g .. 4 g + 3 of
+// each D; it adds those that belong to its wave's 8 output rows (a multiply by its group's
+// 0/1 selector keeps the instruction stream uniform), and the 4 lane groups are summed at
+// the end.  48 products per wave for 8 rows of 16 nodes, against 112 one channel at a time.
+__global__ __launch_bounds__(FTHREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_conv_last(ConvArgs a) {
+    constexpr int NV = FLZ * FLY * FLX;
+    constexpr int NODE_B = 32, ROW_B = FLX * NODE_B, PLANE_B = FLY * ROW_B;
+    static_assert(FNRY == 2 && FZ == 4, "the schedule below is written for 2 x 4 rows");
+    static_assert((FNRY + 1) * ROW_B + (FZ + 1) * PLANE_B < 65536, "LDS immediate offsets are 16 bits");
+    __shared__ __align__(16) uint16_t tile[NV * 16];
+
+    const FTile t = ftile_of(a.tiles_x, a.tiles_y, a.tiles_z);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    const U4 wP = reinterpret_cast<const U4*>(a.wfrag)[lane];
+    const U4 wS = reinterpret_cast<const U4*>(a.wfrag)[64 + lane];
+    const float bias = a.bias[0];
+    stage_box<16, FLX, FLY, FLZ>(a.in + (int64_t)t.vol * a.in_vstride, a.ix, a.iy, a.iz, t.x0, t.y0, t.z0, tile);
     __syncthreads();
 
-    for (int row = wv; row < TY * TZ; row += NTHREADS / 64) {
-        const int ry = row % TY, rz = row / TY;
-        const int oy = y0 + ry, oz = z0 + rz;
-        if (oy >= a.oy || oz >= a.oz) continue;   // wave-uniform
-        const int base = (rz * LY + ry) * LX + j;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const uint32_t hi = (uint32_t)(g >> 1);
+    const char* tb = reinterpret_cast<const char*>(tile);
+    const int ry0 = wv * FNRY;
+    const uint32_t rbase = (uint32_t)((ry0 * FLX + j) * NODE_B + (g & 1) * 16);
+    const uint32_t bP = rbase + hi * NODE_B;   // x pair: groups 2, 3 one node along x
+    const uint32_t bS = rbase + 2 * NODE_B;    // x = 2 (groups 2, 3: zero weights)
+    auto ld = [&](uint32_t base, int Y, int Z) -> U4 {
+        return *reinterpret_cast<const U4*>(tb + base + (Y * ROW_B + Z * PLANE_B));
+    };
+    const float sel[3] = {g == 0 ? 1.f : 0.f, g == 1 ? 1.f : 0.f, g == 2 ? 1.f : 0.f};
+    float acc[8];   // row yy * 4 + rz, this lane group's share
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            U4 bop;
-            if (CIN == 16) {
-                bop = *reinterpret_cast<const U4*>(&tile[(base + toff[c]) * 16 + (g & 1) * 8]);
-            } else {
-                bop.x = *reinterpret_cast<const uint32_t*>(&tile[(base + toff[c * 4 + 0]) * 2]);
-                bop.y = *reinterpret_cast<const uint32_t*>(&tile[(base + toff[c * 4 + 1]) * 2]);
-                bop.z = *reinterpret_cast<const uint32_t*>(&tile[(base + toff[c * 4 + 2]) * 2]);
-                bop.w = *reinterpret_cast<const uint32_t*>(&tile[(base + toff[c * 4 + 3]) * 2]);
-            }
-            acc = mfma_bf16(wr[c], bop, acc);
+    for (int r = 0; r < 8; ++r) acc[r] = 0.f;
+#pragma unroll
+    for (int Z = 0; Z < FZ + 2; ++Z)
+#pragma unroll
+        for (int Y = 0; Y < FNRY + 2; ++Y) {
+            f32x4 d = mfma_bf16(wP, ld(bP, Y, Z), f32x4{0.f, 0.f, 0.f, 0.f});
+            d = mfma_bf16(wS, ld(bS, Y, Z), d);
+#pragma unroll
+            for (int yy = 0; yy < FNRY; ++yy)
+#pragma unroll
+                for (int rz = 0; rz < FZ; ++rz) {
+                    const int dy = Y - yy, dz = Z - rz;
+                    if (dy >= 0 && dy <= 2 && dz >= 0 && dz <= 2) {
+                        const int sh = 3 * dz + dy;
+                        acc[yy * FZ + rz] = __builtin_fmaf(d[sh & 3], sel[sh >> 2], acc[yy * FZ + rz]);
+                    }
+                }
         }
-        const int ox = x0 + j;
-        if (ox >= a.ox) continue;
-        const int64_t node = ((int64_t)oz * a.oy + oy) * a.ox + ox;
-        if (MODE == 1) {
-            if (g == 0) reinterpret_cast<float*>(a.out)[(int64_t)vol * a.out_vstride + node] = acc[0] + bias[0];
-        } else {
-            uint16_t h[4];
-            if (MODE == 0) {
+    // sum the four lane groups (group 3 holds zeros): g and g ^ 1, then g and g ^ 2
 #pragma unroll
-                for (int r = 0; r < 4; ++r) h[r] = f2bf(fmaxf(acc[r] + bias[r], 0.f));
-            } else {
-                const uint2 m = *reinterpret_cast<const uint2*>(a.mask + (int64_t)vol * a.out_vstride + node * 16 + 4 * g);
-                h[0] = bf2f(m.x) > 0.f ? f2bf(acc[0]) : 0;
-                h[1] = bf2f(m.x >> 16) > 0.f ? f2bf(acc[1]) : 0;
-                h[2] = bf2f(m.y) > 0.f ? f2bf(acc[2]) : 0;
-                h[3] = bf2f(m.y >> 16) > 0.f ? f2bf(acc[3]) : 0;
-            }
-            uint2 st;
-            st.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-            st.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-            *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.out) + (int64_t)vol * a.out_vstride + node * 16 +
-                                      4 * g) = st;
+    for (int r = 0; r < 8; ++r) {
+        acc[r] += __shfl_xor(acc[r], 16);
+        acc[r] += __shfl_xor(acc[r], 32);
+    }
+    const int ox = t.x0 + j;
+    if (g != 0 || ox >= a.ox) return;
+    const int64_t pstride = (int64_t)a.oy * a.ox;
+#pragma unroll
+    for (int yy = 0; yy < FNRY; ++yy) {
+        const int oy = t.y0 + ry0 + yy;
+        if (oy >= a.oy) break;
+        float* of = reinterpret_cast<float*>(a.out) + (int64_t)t.vol * a.out_vstride +
+                    (((int64_t)t.z0 * a.oy + oy) * a.ox + ox);
+#pragma unroll
+        for (int rz = 0; rz < FZ; ++rz) {
+            if (t.z0 + rz >= a.oz) break;
+            *of = acc[yy * FZ + rz] + bias;
+            of += pstride;
         }
     }
 }
@@ -371,8 +701,12 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, float* 
 
 // Fragments of one layer from the FP32 parameters.  Lane l of chunk c holds row l % 16
 // and k = 32 c + 8 (l / 16) + e, e = 0..7.
-//   forward : row = co; k = tap * cin + ci
-//   backward: row = ci; k = tap' * 16 + co, tap' = 26 - tap (flipped kernel, bwd-data)
+//   forward, 2 channels : row = co; k = tap * 2 + ci
+//   forward, 16 channels: row = co; k = 16 h + ci, tap chunk_tap(c, h)
+//   backward: row = ci; k = 16 h + co, tap' = chunk_tap(c, h) of the flipped kernel
+//             (tap 26 - tap', bwd-data)
+//   bwd == 2, the last layer (16 -> 1) by shifts: row = s = 3 dz + dy (rows 9..15 zero);
+//             chunk 0: k = 16 dx + ci, dx = 0, 1; chunk 1: k = ci, dx = 2 (k 16..31 zero)
 __global__ __launch_bounds__(64) void k_pack(const float* __restrict__ w, int cin, int cout, int bwd, int nch,
                                              uint16_t* __restrict__ frag) {
     const int c = blockIdx.x, lane = threadIdx.x;
@@ -383,11 +717,18 @@ __global__ __launch_bounds__(64) void k_pack(const float* __restrict__ w, int ci
     for (int e = 0; e < 8; ++e) {
         const int k = 32 * c + 8 * g + e;
         float val = 0.f;
-        if (!bwd) {
-            const int t = k / cin, ci = k % cin;
+        if (bwd == 2) {
+            // one output channel, rows = the 9 (dz, dy) shifts s = 3 dz + dy: chunk 0 holds
+            // dx = k / 16 (0, 1), chunk 1 dx = 2 (k < 16); channel k % 16
+            const int kl = k & 31;   // k within the chunk
+            const int dx = c == 0 ? (kl >> 4) : (kl < 16 ? 2 : 3);
+            if (row < 9 && dx < 3) val = w[(k & 15) * 27 + 9 * (row / 3) + 3 * (row % 3) + dx];
+        } else if (!bwd) {
+            // 16 input channels: the chunk table; 2: tap k / 2, in order
+            const int t = cin == 16 ? chunk_tap(c, (k >> 4) & 1) : k / cin, ci = k % cin;
             if (t < 27 && row < cout) val = w[(row * cin + ci) * 27 + t];
         } else {
-            const int tp = k / 16, co = k % 16;
+            const int tp = chunk_tap(c, (k >> 4) & 1), co = k % 16;
             if (tp < 27 && co < cout && row < cin) val = w[(co * cin + row) * 27 + (26 - tp)];
         }
         h[e] = f2bf(val);
@@ -425,34 +766,54 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ ref,
 // Features of the pair average-pooled 2x2x2 onto the coarse grid (cz, cy, cx) = ceil(n / 2),
 // padded by 4: coarse node c takes the mean of the fine nodes 2c and 2c + 1 per axis that lie
 // in the grid (fewer at an odd edge); f0 and f1 as in k_features, with the fine grid's Dmax
-// and inv_dd.  One thread per padded coarse node; the fine loads of neighbouring threads
-// are contiguous pairs along x.
+// and inv_dd.  One thread per padded coarse node, 32-bit index arithmetic (the launcher
+// bounds the padded coarse volume below 2^31); the two fine nodes of a pair along x are one
+// 8-byte load when nx is even and both volumes start 8-byte aligned (every pair then is),
+// two loads otherwise.  The sums run in the same order either way.
 __global__ __launch_bounds__(256) void k_features_pool2(const float* __restrict__ ref, const float* __restrict__ ev,
                                                         int nz, int ny, int nx, const Scalars* __restrict__ sc,
                                                         uint16_t* __restrict__ feat) {
     const int cz = (nz + 1) >> 1, cy = (ny + 1) >> 1, cx = (nx + 1) >> 1;
-    const int pz = cz + 8, py = cy + 8, px = cx + 8;
-    const int64_t total = (int64_t)pz * py * px;
+    const uint32_t pz = cz + 8, py = cy + 8, px = cx + 8;
+    const uint32_t total = pz * py * px;
     const float dmax = ord_to_float(sc->dmax_ord);
     const float inv_max = 1.0f / dmax;
     const float inv_dd = sc->inv_dd;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-        const int x = (int)(i % px) - 4, y = (int)((i / px) % py) - 4, z = (int)(i / ((int64_t)px * py)) - 4;
+    const bool even = (nx & 1) == 0 && ((reinterpret_cast<uintptr_t>(ref) | reinterpret_cast<uintptr_t>(ev)) & 7) == 0;
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < total; i += gridDim.x * 256u) {
+        const uint32_t row = i / px;
+        const int x = (int)(i - row * px) - 4, y = (int)(row % py) - 4, z = (int)(row / py) - 4;
         uint32_t q = 0u;
         if (x >= 0 && x < cx && y >= 0 && y < cy && z >= 0 && z < cz) {
             float sr = 0.f, se = 0.f;
             int cnt = 0;
+            const int fx = 2 * x;
+            const bool two = fx + 1 < nx;
             for (int dz = 0; dz < 2; ++dz)
-                for (int dy = 0; dy < 2; ++dy)
-                    for (int dx = 0; dx < 2; ++dx) {
-                        const int fz = 2 * z + dz, fy = 2 * y + dy, fx = 2 * x + dx;
-                        if (fz < nz && fy < ny && fx < nx) {
-                            const int64_t n = ((int64_t)fz * ny + fy) * nx + fx;
-                            sr += ref[n];
-                            se += ev[n];
+                for (int dy = 0; dy < 2; ++dy) {
+                    const int fz = 2 * z + dz, fy = 2 * y + dy;
+                    if (fz < nz && fy < ny) {
+                        const int64_t n = ((int64_t)fz * ny + fy) * nx + fx;
+                        float r0, r1, e0, e1;
+                        if (even) {
+                            const float2 rr = *reinterpret_cast<const float2*>(ref + n);
+                            const float2 ee = *reinterpret_cast<const float2*>(ev + n);
+                            r0 = rr.x, r1 = rr.y, e0 = ee.x, e1 = ee.y;
+                        } else {
+                            r0 = ref[n], e0 = ev[n];
+                            r1 = two ? ref[n + 1] : 0.f;
+                            e1 = two ? ev[n + 1] : 0.f;
+                        }
+                        sr += r0;
+                        se += e0;
+                        ++cnt;
+                        if (two) {
+                            sr += r1;
+                            se += e1;
                             ++cnt;
                         }
                     }
+                }
             const float r = sr / (float)cnt, e = se / (float)cnt;
             q = pack2bf(r * inv_max, (e - r) * inv_dd);
         }
@@ -539,8 +900,8 @@ constexpr int TAIL_GATHER = (729 + 63) / 64;
 template <int CIN, int IN_E>
 __device__ __forceinline__ U4 patch_bop(const uint16_t* __restrict__ in, int base, int c, int g) {
     if (CIN == 16) {
-        int t = 2 * c + (g >> 1);
-        t = t > 26 ? 26 : t;
+        int t = chunk_tap(c, g >> 1);
+        t = t > 26 ? 26 : t;   // zero weights there; any finite operand will do
         int dz, dy, dx;
         tap_xyz(t, dz, dy, dx);
         return *reinterpret_cast<const U4*>(&in[(base + (dz * IN_E + dy) * IN_E + dx) * 16 + (g & 1) * 8]);
@@ -772,18 +1133,52 @@ hipError_t launch_conv(int cin, int mode, const uint16_t* in, const int i[3], in
     a.ox = o[2];
     a.out_vstride = out_vstride;
     a.off = off;
-    a.tiles_x = (o[2] + TX - 1) / TX;
-    a.tiles_y = (o[1] + TY - 1) / TY;
-    a.tiles_z = (o[0] + TZ - 1) / TZ;
-    const int64_t nb = conv_blocks(o, nvol);
+    a.tiles_x = (o[2] + FX - 1) / FX;
+    a.tiles_y = (o[1] + FY - 1) / FY;
+    a.tiles_z = (o[0] + FZ - 1) / FZ;
+    const int64_t nb = (int64_t)a.tiles_x * a.tiles_y * a.tiles_z * nvol;
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)nb), block(NTHREADS);
+    // the kernel indexes nodes within one volume in 32 bits
+    if ((int64_t)i[0] * i[1] * i[2] >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb), block(FTHREADS);
     if (cin == 2 && mode == 0) hipLaunchKernelGGL((k_conv<2, 0>), grid, block, 0, s, a);
     else if (cin == 16 && mode == 0) hipLaunchKernelGGL((k_conv<16, 0>), grid, block, 0, s, a);
-    else if (cin == 16 && mode == 1) hipLaunchKernelGGL((k_conv<16, 1>), grid, block, 0, s, a);
+    else if (cin == 16 && mode == 1) hipLaunchKernelGGL(k_conv_last, grid, block, 0, s, a);
     else if (cin == 16 && mode == 2) hipLaunchKernelGGL((k_conv<16, 2>), grid, block, 0, s, a);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_conv12(const uint16_t* feat, const int f[3], int64_t feat_vstride, const uint16_t* wfrag1,
+                         const float* bias1, const uint16_t* wfrag2, const float* bias2, uint16_t* out, const int o[3],
+                         int64_t out_vstride, int nvol, hipStream_t s) {
+    Conv12Args a{};
+    a.feat = feat;
+    a.fz = f[0];
+    a.fy = f[1];
+    a.fx = f[2];
+    a.feat_vstride = feat_vstride;
+    a.wfrag1 = wfrag1;
+    a.bias1 = bias1;
+    ConvArgs& l2 = a.l2;
+    l2.wfrag = wfrag2;
+    l2.bias = bias2;
+    l2.cout = 16;
+    l2.out = out;
+    l2.oz = o[0];
+    l2.oy = o[1];
+    l2.ox = o[2];
+    l2.out_vstride = out_vstride;
+    l2.tiles_x = (o[2] + FX - 1) / FX;
+    l2.tiles_y = (o[1] + FY - 1) / FY;
+    l2.tiles_z = (o[0] + FZ - 1) / FZ;
+    const int64_t nb = (int64_t)l2.tiles_x * l2.tiles_y * l2.tiles_z * nvol;
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    // the kernel indexes nodes within one volume in 32 bits
+    if ((int64_t)f[0] * f[1] * f[2] >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_conv12, dim3((unsigned)nb), dim3(FTHREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -834,7 +1229,7 @@ hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int 
 }
 
 hipError_t launch_pack(const float* w, int cin, int cout, int bwd, uint16_t* frag, hipStream_t s) {
-    const int nch = bwd ? 14 : (cin == 16 ? 14 : 2);
+    const int nch = bwd == 2 ? 2 : (bwd ? 14 : (cin == 16 ? 14 : 2));
     hipLaunchKernelGGL(k_pack, dim3(nch), dim3(64), 0, s, w, cin, cout, bwd, nch, frag);
     return hipGetLastError();
 }
@@ -880,6 +1275,7 @@ hipError_t launch_features_pool2(const float* ref, const float* ev, const int n[
     int c[3];
     pool2_shape(n, c);
     const int64_t total = (int64_t)(c[0] + 8) * (c[1] + 8) * (c[2] + 8);
+    if (total >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_features_pool2, dim3(grid_for(total, 4096)), dim3(256), 0, s, ref, ev, n[0], n[1], n[2], sc,
                        feat);
     return hipGetLastError();

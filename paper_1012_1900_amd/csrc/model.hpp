@@ -39,7 +39,8 @@ inline void act_shape(const int o[3], int grow, int out[3]) {
 inline int64_t vol_of(const int s[3]) { return (int64_t)s[0] * s[1] * s[2]; }
 
 // Forward pass over nvol volumes: feat (o+8, 2 channels) -> a1 (o+6), a2 (o+4),
-// a3 (o+2) (16 channels each, bf16) -> y (o, FP32).
+// a3 (o+2) (16 channels each, bf16) -> y (o, FP32).  a1 == nullptr: layers 1 and 2 run
+// fused and a1 is not stored (inference; training keeps it for the backward pass).
 hipError_t model_forward(gammax_model* m, const uint16_t* feat, int nvol, const int o[3], uint16_t* a1, uint16_t* a2,
                          uint16_t* a3, float* y, hipStream_t s);
 

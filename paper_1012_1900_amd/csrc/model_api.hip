@@ -30,7 +30,8 @@ gammax_status_t mfail(gammax_model* m, gammax_status_t st, const std::string& wh
 hipError_t pack_all(gammax_model* m, hipStream_t s) {
     hipError_t e;
     for (int l = 0; l < CNN_LAYERS; ++l)
-        if ((e = launch_pack(m->theta + CNN_OFF[l], CNN_CIN[l], CNN_COUT[l], 0, frag_fwd(m, l), s)) != hipSuccess)
+        if ((e = launch_pack(m->theta + CNN_OFF[l], CNN_CIN[l], CNN_COUT[l], l == 3 ? 2 : 0, frag_fwd(m, l), s)) !=
+            hipSuccess)
             return e;
     for (int l = 1; l < CNN_LAYERS; ++l)
         if ((e = launch_pack(m->theta + CNN_OFF[l], CNN_CIN[l], CNN_COUT[l], 1, frag_bwd(m, l), s)) != hipSuccess)
@@ -66,12 +67,19 @@ hipError_t model_forward(gammax_model* m, const uint16_t* feat, int nvol, const 
     act_shape(o, 4, s2);
     act_shape(o, 2, s3);
     hipError_t e;
-    if ((e = launch_conv(2, 0, feat, p0, vol_of(p0) * 2, frag_fwd(m, 0), layer_bias(m, 0), 16, nullptr, a1, s1,
-                         vol_of(s1) * 16, 0, nvol, s)) != hipSuccess)
-        return e;
-    if ((e = launch_conv(16, 0, a1, s1, vol_of(s1) * 16, frag_fwd(m, 1), layer_bias(m, 1), 16, nullptr, a2, s2,
-                         vol_of(s2) * 16, 0, nvol, s)) != hipSuccess)
-        return e;
+    if (!a1) {
+        // layers 1 and 2 in one pass, layer 1's output kept on chip
+        if ((e = launch_conv12(feat, p0, vol_of(p0) * 2, frag_fwd(m, 0), layer_bias(m, 0), frag_fwd(m, 1),
+                               layer_bias(m, 1), a2, s2, vol_of(s2) * 16, nvol, s)) != hipSuccess)
+            return e;
+    } else {
+        if ((e = launch_conv(2, 0, feat, p0, vol_of(p0) * 2, frag_fwd(m, 0), layer_bias(m, 0), 16, nullptr, a1, s1,
+                             vol_of(s1) * 16, 0, nvol, s)) != hipSuccess)
+            return e;
+        if ((e = launch_conv(16, 0, a1, s1, vol_of(s1) * 16, frag_fwd(m, 1), layer_bias(m, 1), 16, nullptr, a2, s2,
+                             vol_of(s2) * 16, 0, nvol, s)) != hipSuccess)
+            return e;
+    }
     if ((e = launch_conv(16, 0, a2, s2, vol_of(s2) * 16, frag_fwd(m, 2), layer_bias(m, 2), 16, nullptr, a3, s3,
                          vol_of(s3) * 16, 0, nvol, s)) != hipSuccess)
         return e;
@@ -276,7 +284,7 @@ gammax_status_t gammax_model_forward(gammax_model_t* m, int32_t nvol, const int6
         m->ws_cap = w.bytes;
     }
     w = train_layout(m->ws, nvol, o);
-    MCHK(m, model_forward(m, feat_dev, nvol, o, w.a1, w.a2, w.a3, y_dev, s));
+    MCHK(m, model_forward(m, feat_dev, nvol, o, nullptr, w.a2, w.a3, y_dev, s));
     MCHK(m, hipStreamSynchronize(s));
     return GAMMAX_OK;
 }

@@ -84,6 +84,10 @@ def test_forward_parity(gx, crop):
         assert np.all(err <= bound), (v, float(err.max()), float((err / bound).max()))
         # most nodes agree to FP32 summation accuracy
         assert np.mean(err <= 1e-4 * bound / (4 * 2.0 ** -8)) > 0.95
+        # ... measured against the output itself: the bound above grows with the network's
+        # absolute values and would let a dropped tap through; one-ulp bf16 flips of hidden
+        # activations stay rare, so 95 % of the nodes match to 1e-3 of the output's range
+        assert np.quantile(err, 0.95) <= 1e-3 * (1.0 + np.abs(want).max()), (v, float(np.quantile(err, 0.95)))
 
 
 def _pair(seed, shape=(22, 25, 29)):
@@ -109,6 +113,7 @@ def test_predict_full_grid(gx):
     want = cnn.forward(th, f).y
     bound = 4 * 2.0 ** -8 * _abs_network(th, f) + 1e-6
     assert np.all(np.abs(y - want) <= bound)
+    assert np.quantile(np.abs(y - want), 0.95) <= 1e-3 * (1.0 + np.abs(want).max())
 
 
 def _labels(seed, nvol, crop):
