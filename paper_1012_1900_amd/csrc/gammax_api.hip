@@ -507,6 +507,7 @@ PrepArgs make_prep_args(gammax_ctx* c, const CallSetup& cs) {
     pa.ntiles = (int)ntiles;
     pa.nodes = work_array(c, W_NODES);
     pa.sums = c->sums;
+    pa.mbits = reinterpret_cast<unsigned long long*>(c->blockcnt + prep_mbits_offset(cs.n));
     return pa;
 }
 
@@ -2242,6 +2243,7 @@ gammax_status_t gammax_map_noalloc(const gammax_problem_t* p, const gammax_optio
     pa.ntiles = (int)ntiles;
     pa.nodes = nodes_arr;
     pa.sums = L.sums;
+    pa.mbits = reinterpret_cast<unsigned long long*>(L.blockcnt + prep_mbits_offset(n));
     HIPCHK(nullptr, launch_prep(pa, s));
     Scalars h{};
     if ((st = na_read_scalars(L, &h, s)) != GAMMAX_OK) return st;

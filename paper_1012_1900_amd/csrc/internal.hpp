@@ -105,13 +105,17 @@ struct PrepArgs {
     int n_super;
     uint32_t* nodes;    // M entries: masked node indices in grid order
     BlockSums* sums;    // SUM_BINS partial-count slots of the search, zeroed here
+    unsigned long long* mbits;   // mask bits, one word per 64 nodes of the prep tiles
 };
 
 int64_t prep_tiles(int64_t n);
 // Tile groups of the compaction: 2^shift >= sqrt(tiles) tiles per group; words = the
-// tile counts plus two words per group.
+// tile counts, two words per group, then the mask bits (two words per 64 nodes).
 void prep_groups(int64_t n, int* shift, int* n_super);
 int64_t prep_words(int64_t n);
+// Offset (32-bit words, even) of the mask bits within the prep words: after the tile counts
+// and the group words.
+int64_t prep_mbits_offset(int64_t n);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 // Only the dose maximum, the finiteness flag, the threshold value and the global 1/dD
 // (uses ref, ev, n, thr, dd, sc, part).

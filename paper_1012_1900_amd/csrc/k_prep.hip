@@ -4,16 +4,19 @@
 // Three launches, each a coalesced stream over the dose arrays; results cross blocks only
 // at kernel boundaries or through atomic adds (a cross-block hand-over inside a kernel
 // would need device-scope release fences, which write back the XCD's L2):
-//   1. dose maximum and finiteness check: one partial per block (block 0 also clears the
-//      tile-group sums);
+//   1. maximum and finiteness of D_r: one partial per block (block 0 also clears the
+//      tile-group sums and the flags);
 //   2. every block reduces those partials itself (a few KB from L2), derives the
 //      threshold and the global 1/dD, then counts the masked nodes of its tile and their
-//      max gamma0^2, stores the count and adds both into its tile group (about
-//      sqrt(tiles) / 8 tiles per group, so no address sees many atomics); block 0 also
-//      stores the scalars and clears the search counters;
-//   3. ordered emit of the masked node indices: a block's first slot is the sum of the
-//      groups before its own plus the tiles of its group before it; the last block stores
-//      M and R^2.
+//      max gamma0^2, checks D_e's finiteness, stores the tile's mask bits and count and
+//      adds the count and the maximum into its tile group (about sqrt(tiles) / 8 tiles per
+//      group, so no address sees many atomics); block 0 also stores the scalars and clears
+//      the search counters;
+//   3. ordered emit of the masked node indices from the mask bits: a block's first slot is
+//      the sum of the groups before its own plus the tiles of its group before it; the
+//      last block stores M and R^2.
+// Each dose volume is read once by the compaction except D_r, read twice (its maximum sets
+// the threshold that the mask needs); the emit reads one bit per node.
 #include "internal.hpp"
 
 namespace gammax {
@@ -51,7 +54,10 @@ __device__ __forceinline__ void block_max_or(uint32_t& m, uint32_t& f) {
     __syncthreads();
 }
 
-// 1. dose maximum and finiteness of both doses, one partial per block (vb of vgrid).
+// 1. dose maximum and finiteness of D_r (WITH_EV: of D_e too), one partial per block (vb
+// of vgrid).  The map's compaction checks D_e where it loads it (prep_count_body); there
+// block 0 here clears the flags that the later kernels or into.
+template <bool WITH_EV>
 __device__ __forceinline__ void dose_max_body(const PrepArgs& a, int vb, int vgrid) {
     uint32_t best = 0u, bad = 0u;
     // DM_ITEMS nodes per thread per step, all loads of a step issued before the first use
@@ -65,11 +71,11 @@ __device__ __forceinline__ void dose_max_body(const PrepArgs& a, int vb, int vgr
             const int64_t i = b0 + (int64_t)k * PREP_THREADS + threadIdx.x;
             const int64_t j = i < a.n ? i : a.n - 1;
             r[k] = a.ref[j];
-            e[k] = a.ev[j];
+            if (WITH_EV) e[k] = a.ev[j];
         }
 #pragma unroll
         for (int k = 0; k < DM_ITEMS; ++k) {
-            bad |= (!isfinite(r[k]) || !isfinite(e[k])) ? 1u : 0u;
+            bad |= (!isfinite(r[k]) || (WITH_EV && !isfinite(e[k]))) ? 1u : 0u;
             best = max(best, float_to_ord(r[k]));
         }
     }
@@ -77,12 +83,18 @@ __device__ __forceinline__ void dose_max_body(const PrepArgs& a, int vb, int vgr
     if (threadIdx.x == 0) {
         a.part[vb] = best;
         a.part[MAX_BLOCKS + vb] = bad;
+        if (!WITH_EV && vb == 0) a.sc->flags = 0u;
     }
     if (a.super && vb == 0)
         for (int j = threadIdx.x; j < 2 * a.n_super; j += PREP_THREADS) a.super[j] = 0u;
 }
 
-__global__ __launch_bounds__(PREP_THREADS) void k_dose_max(PrepArgs a) { dose_max_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(PREP_THREADS) void k_dose_max(PrepArgs a) {
+    dose_max_body<false>(a, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(PREP_THREADS) void k_dose_max_both(PrepArgs a) {
+    dose_max_body<true>(a, blockIdx.x, gridDim.x);
+}
 
 // 1b. dose maximum and the global 1/dD only (no mask, no compaction): one block reduces
 // the partials of k_dose_max.
@@ -144,7 +156,7 @@ __device__ __forceinline__ void prep_count_body(const PrepArgs& a, int nb_red, i
         if (threadIdx.x == 0) {
             Scalars* sc = a.sc;
             sc->dmax_ord = dm;
-            sc->flags = bad ? FLAG_NONFINITE : 0u;
+            if (bad) atomicOr(&sc->flags, FLAG_NONFINITE);
             sc->thr_val = thr_val;
             sc->inv_dd = inv_dd_g;
             sc->r2_bits = 0u;
@@ -162,12 +174,17 @@ __device__ __forceinline__ void prep_count_body(const PrepArgs& a, int nb_red, i
         }
     }
     uint32_t cnt = 0u, best = 0u;
+    bool bad_e = false;
+    const int lane = threadIdx.x & (WAVE - 1);
 #pragma unroll
     for (int k = 0; k < PREP_ITEMS; ++k) {
         const int64_t i = base + (int64_t)k * PREP_THREADS + threadIdx.x;
+        bool m = false;
         if (i < a.n) {
             const float dr = rr[k];
-            if (node_masked(dr, thr_val, a.local)) {
+            bad_e |= !isfinite(ee[k]);
+            m = node_masked(dr, thr_val, a.local);
+            if (m) {
                 const float de = ee[k];
                 const float g2 = gamma0_sq(de, dr, node_inv_dd(dr, inv_dd_g, a.dd, a.local));
                 best = max(best, f2u(g2));
@@ -176,7 +193,11 @@ __device__ __forceinline__ void prep_count_body(const PrepArgs& a, int nb_red, i
                 a.gamma[i] = -1.0f;
             }
         }
+        // the mask bits of the wave's 64 consecutive nodes, for the emit
+        const unsigned long long bal = __ballot(m);
+        if (lane == 0) a.mbits[(base + (int64_t)k * PREP_THREADS + (threadIdx.x & ~(WAVE - 1))) / WAVE] = bal;
     }
+    if (__ballot(bad_e) != 0ull && lane == 0) atomicOr(&a.sc->flags, FLAG_NONFINITE);
     __shared__ uint32_t s_cnt[PREP_THREADS / WAVE];
     cnt = wave_sum_u32(cnt);
     if ((threadIdx.x & (WAVE - 1)) == 0) s_cnt[threadIdx.x / WAVE] = cnt;
@@ -198,19 +219,15 @@ __global__ __launch_bounds__(PREP_THREADS) void k_prep_count(PrepArgs a, int nb_
 
 // 3. the masked nodes in grid order.
 __device__ __forceinline__ void prep_emit_body(const PrepArgs& a, int vb) {
-    const float thr_val = a.sc->thr_val;
     const int64_t base = (int64_t)vb * PREP_TILE;
     __shared__ uint32_t s_wave[PREP_ITEMS][PREP_THREADS / WAVE];
     __shared__ uint32_t s_pre[PREP_THREADS / WAVE];
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-    // this tile's reference doses (clamped indices), in flight while the prefix is summed
-    float rr[PREP_ITEMS];
+    // this tile's mask bits (one word per wave and item), in flight while the prefix is summed
+    unsigned long long bal[PREP_ITEMS];
 #pragma unroll
-    for (int k = 0; k < PREP_ITEMS; ++k) {
-        const int64_t i = base + (int64_t)k * PREP_THREADS + threadIdx.x;
-        rr[k] = a.ref[i < a.n ? i : a.n - 1];
-    }
+    for (int k = 0; k < PREP_ITEMS; ++k) bal[k] = a.mbits[(base + (int64_t)k * PREP_THREADS) / WAVE + w];
     // first slot of this tile: the groups before its own, then its group's earlier tiles
     {
         const int grp = vb >> a.super_shift;
@@ -221,12 +238,9 @@ __device__ __forceinline__ void prep_emit_body(const PrepArgs& a, int vb) {
         if (lane == 0) s_pre[w] = v;
     }
     bool m[PREP_ITEMS];
-    unsigned long long bal[PREP_ITEMS];
 #pragma unroll
     for (int k = 0; k < PREP_ITEMS; ++k) {
-        const int64_t i = base + (int64_t)k * PREP_THREADS + threadIdx.x;
-        m[k] = i < a.n && node_masked(rr[k], thr_val, a.local);
-        bal[k] = __ballot(m[k]);
+        m[k] = (bal[k] >> lane) & 1ull;
         if (lane == 0) s_wave[k][w] = (uint32_t)__popcll(bal[k]);
     }
     __syncthreads();
@@ -292,7 +306,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_batch_dose_max(const BatchPair
                                                                  const uint2* __restrict__ items) {
     const uint2 w = items[blockIdx.x];
     const BatchPair& P = pairs[w.x];
-    dose_max_body(P.pa, (int)w.y, P.nbr);
+    dose_max_body<false>(P.pa, (int)w.y, P.nbr);
 }
 __global__ __launch_bounds__(PREP_THREADS) void k_batch_prep_count(const BatchPair* __restrict__ pairs,
                                                                    const uint2* __restrict__ items) {
@@ -333,11 +347,13 @@ void prep_groups(int64_t n, int* shift, int* n_super) {
     *n_super = (int)((t + ((int64_t)1 << sh) - 1) >> sh);
 }
 
-int64_t prep_words(int64_t n) {
+int64_t prep_mbits_offset(int64_t n) {
     int sh = 0, ns = 0;
     prep_groups(n, &sh, &ns);
-    return prep_tiles(n) + 2 * (int64_t)ns;
+    return (prep_tiles(n) + 2 * (int64_t)ns + 1) & ~(int64_t)1;   // 8-byte aligned
 }
+
+int64_t prep_words(int64_t n) { return prep_mbits_offset(n) + 2 * prep_tiles(n) * (PREP_TILE / 64); }
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
     const int nbr = reduce_blocks(a.n);
@@ -350,7 +366,7 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
 
 hipError_t launch_dose_scalars(const PrepArgs& a, hipStream_t s) {
     const int nbr = reduce_blocks(a.n);
-    hipLaunchKernelGGL(k_dose_max, dim3(nbr), dim3(PREP_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_dose_max_both, dim3(nbr), dim3(PREP_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_dose_finish, dim3(1), dim3(PREP_THREADS), 0, s, a, nbr);
     return hipGetLastError();
 }
