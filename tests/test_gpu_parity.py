@@ -279,6 +279,28 @@ def test_device_side_errors(gx):
     assert r.n_evaluated == 64
 
 
+def test_nonfinite_in_either_dose_anywhere(gx):
+    """A NaN or infinity anywhere in either dose (above or below the threshold, in any prep
+    tile) is refused, and the next clean map on the same context is not."""
+    rng = np.random.default_rng(5)
+    shape = (9, 40, 37)
+    ref = (rng.uniform(0.0, 1.0, shape)).astype(np.float32)
+    n = ref.size
+    ctx = gx.Context(0)
+    for which, idx, val in [("ref", 0, np.nan), ("ref", n - 1, np.inf), ("ev", n // 2, np.nan),
+                            ("ev", n - 3, -np.inf), ("ev", 7, np.inf)]:
+        r, e = ref.copy(), ref.copy()
+        tgt = r if which == "ref" else e
+        tgt.flat[idx] = val
+        if which == "ev":
+            r.flat[idx] = 0.0   # below the threshold: the node is not evaluated
+        with pytest.raises(gx.GammaxError) as err:
+            gx.gammax_map(dev(r), dev(e), (2.5, 2.5, 2.5), 0.03, 3.0, 0.1, ctx=ctx)
+        assert err.value.status == -4, (which, idx)
+        g, res = gx.gammax_map(dev(ref), dev(ref), (2.5, 2.5, 2.5), 0.03, 3.0, 0.1, ctx=ctx)
+        assert res.n_evaluated == int((ref >= np.float32(0.1) * ref.max()).sum())
+
+
 def test_flat_entry_point(gx):
     p = make_config_pair("2d_64x64_1mm", 4)
     a, pr = gx.gamma_map(dev(p.ref), dev(p.eval), p.spacing, 0.03, 3.0, 0.1)
