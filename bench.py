@@ -44,7 +44,7 @@ TRAFFIC = {
     "3d_128x128x96_2.5mm": {
         "bytes": (15.65 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "a6e939f25860a0329496158cd15b987a4c9fbca580febb5d7365a05eb31a8dad",
+        "sha256": "e0b99abdc55d3ac77b4e459f4763f60482e7a818d905bc96886d975736ed5cb8",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }

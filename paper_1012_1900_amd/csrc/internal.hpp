@@ -142,8 +142,11 @@ hipError_t launch_given_keys(const uint32_t* nodes, const uint32_t* count, const
                              hipStream_t s);
 hipError_t sort_order_small(const uint32_t* keys, uint32_t* order, const uint32_t* n_dev, uint32_t* overflow,
                             hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs by key bits [low_bit, 32), 8 bits a pass:
+// low_bit 0 sorts whole keys; 16 sorts by the top half (2 passes), which for non-negative
+// float keys orders by value to 7 mantissa bits and keeps the input order within a bucket.
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
-                            int64_t n_max, const uint32_t* n_dev, uint32_t* hist, hipStream_t s);
+                            int64_t n_max, const uint32_t* n_dev, uint32_t* hist, hipStream_t s, int low_bit = 0);
 
 // ---- cell table --------------------------------------------------------------------------
 

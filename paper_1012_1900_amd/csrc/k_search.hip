@@ -1975,12 +1975,14 @@ hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s
             hipError_t e = p.after_zero(p.after_zero_user, s);
             if (e != hipSuccess) return e;
         }
-        // tail sort (count read on the device)
+        // tail sort (count read on the device).  The order only groups similar walks into a
+        // wave (every order gives the same map), so long tails are sorted by the keys' top 16
+        // bits: two radix passes instead of four
         if (p.hist) {
             hipError_t e = p.small_sort
                                ? sort_order_small(a.tail_key_arr, a.tail_pos, &a.sc->n_tail, &a.sc->sort_overflow, s)
                                : radix_sort_pairs(a.tail_key_arr, a.tail_pos, p.tmp_keys, p.tmp_vals, p.M,
-                                                  &a.sc->n_tail, p.hist, s);
+                                                  &a.sc->n_tail, p.hist, s, 16);
             if (e != hipSuccess) return e;
         }
         if (p.ev_sort_end) (void)hipEventRecord(p.ev_sort_end, s);

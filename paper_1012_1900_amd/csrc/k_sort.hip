@@ -275,12 +275,13 @@ int64_t sort_hist_words(int64_t n_max) {
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals,
-                            int64_t n_max, const uint32_t* n_dev, uint32_t* hist, hipStream_t s) {
+                            int64_t n_max, const uint32_t* n_dev, uint32_t* hist, hipStream_t s, int low_bit) {
     if (n_max <= 1) return hipSuccess;
+    if (low_bit < 0 || low_bit > 24 || low_bit % 16 != 0) return hipErrorInvalidValue;   // an even pass count
     const int64_t nb = (n_max + SORT_TILE - 1) / SORT_TILE;
     uint32_t* totals = hist + (int64_t)RADIX * nb;
     uint32_t *ki = keys, *vi = vals, *ko = tmp_keys, *vo = tmp_vals;
-    for (int shift = 0; shift < 32; shift += 8) {
+    for (int shift = low_bit; shift < 32; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(SORT_THREADS), 0, s, ki, n_max, n_dev,
                            shift, hist, nb);
         hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nb, n_max, n_dev, totals);
