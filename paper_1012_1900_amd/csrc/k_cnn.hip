@@ -12,10 +12,13 @@
 // Layouts.  Activations are channel-last: [volume][z][y][x][C] bf16 (C = 16, or 2 for the
 // features), so one node's 16 channels are one 32-byte load.  A convolution is an
 // implicit GEMM per 16-node row segment along x: D[co][node] = sum_k W[co][k] X[k][node],
-// k = (tap, ci).  The weights are the A operand, packed once per update into the lane
-// order of the instruction ("fragments", 16 bytes per lane per 32-wide k chunk) and held
-// in registers; the input tile (with its halo) is staged in LDS and read as the B operand;
-// each lane's result is 4 consecutive output channels of one node (an 8-byte store).
+// k = (tap, ci), in 32-wide chunks (chunk_tap gives the taps of each chunk of a 16-channel
+// layer).  The weights are the A operand, packed once per update into the lane order of
+// the instruction ("fragments", 16 bytes per lane per chunk); the input tile (with its
+// halo) is staged in LDS and read as the B operand; each lane's result is 4 consecutive
+// output channels of one node (an 8-byte store).  Inference fuses layers 1 and 2
+// (k_conv12) and computes the single-channel last layer by shifts (k_conv_last); the
+// network at listed nodes only runs per node from its 9^3 patch (k_cnn_tail).
 //
 // Backward: bwd-data is the same kernel run on the output gradient with the flipped,
 // transposed kernel and an input offset of -2 (full correlation), times the ReLU mask of
