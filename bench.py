@@ -528,6 +528,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-radius leg")
     ap.add_argument("--no-c2", action="store_true", help="skip the 256x256x192 leg")
+    ap.add_argument("--cnn-pool", type=int, choices=[0, 2], default=None,
+                    help="learned leg: network input pooling (default: 2 on a grid at half the training "
+                         "spacing, else 0; 0 runs the per-node network at every tail node)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1012_1900_amd", "weights",
                                                       "cnn_3d_2.5mm_3pct3mm.npy"))
     ap.add_argument("--cpu-reps", type=int, default=2, help="fewest oracle repetitions")
@@ -632,6 +635,8 @@ def main():
         # the network was trained on a 2.5 mm grid: a grid at half that spacing feeds it the
         # pair average-pooled 2x2x2 and interpolates its prediction back
         cnn_pool = 2 if all(abs(2.0 * h - TRAIN_SPACING_MM) < 1e-9 for h in p.spacing) else 0
+        if args.cnn_pool is not None:
+            cnn_pool = args.cnn_pool
         log(f"learned radius (cnn_pool {cnn_pool})")
         lsec, lsync, lr_last, lph = leg(p, r_dev, e_dev, o_dev,
                                         dict(radius="learned", sort="predicted", model=model, cnn_pool=cnn_pool),

@@ -109,6 +109,36 @@ __host__ __device__ constexpr int chunk_tap(int c, int h) {
                  : (c < 12 ? 9 * h + 3 * (c - 9) + 2 : (c == 12 ? 20 + 3 * h : (h == 0 ? 26 : 27)));
 }
 
+// The k order of layer 1 (2 input channels).  Its 27 taps x 2 channels fill the 32 k slots
+// of two chunks: lane group g of chunk c holds taps l1_tap(c, g, q), q = 0..3, both channels
+// of each (k = 32 c + 8 g + 2 q + ci), 27 = an empty slot (zero weights).  The order was
+// found by a search over the staged boxes of the dense kernels (18 x 18 x 6 and 16 x 16 x 4
+// outputs) and the tail kernel (7^3) such that the four lane groups' 4-byte operand reads
+// fall in distinct LDS banks (about 1.0-1.1 accesses per bank, against 1.75 for taps in
+// order); every order gives the same products.
+__host__ __device__ constexpr int l1_tap(int c, int g, int q) {
+    constexpr int T[2][4][4] = {{{18, 26, 1, 23}, {27, 24, 0, 27}, {20, 27, 13, 21}, {19, 25, 14, 22}},
+                                {{11, 17, 5, 8}, {12, 27, 4, 27}, {16, 9, 3, 6}, {15, 10, 2, 7}}};
+    return T[c][g][q];
+}
+// The tap whose operand an empty slot reads (times a zero weight): group 0's in that slot.
+__host__ __device__ constexpr int l1_read_tap(int c, int g, int q) {
+    return l1_tap(c, g, q) < 27 ? l1_tap(c, g, q) : l1_tap(c, 0, q);
+}
+constexpr bool l1_order_valid() {
+    int seen[28] = {};
+    for (int c = 0; c < 2; ++c)
+        for (int g = 0; g < 4; ++g)
+            for (int q = 0; q < 4; ++q) ++seen[l1_tap(c, g, q)];
+    for (int t = 0; t < 27; ++t)
+        if (seen[t] != 1) return false;
+    for (int c = 0; c < 2; ++c)
+        for (int q = 0; q < 4; ++q)
+            if (l1_tap(c, 0, q) >= 27) return false;
+    return seen[27] == 5;
+}
+static_assert(l1_order_valid(), "layer 1's k order must hold every tap once, group 0 no empty slot");
+
 // ---- forward / bwd-data convolution ----------------------------------------------------
 //
 // MODE 0: out = bf16(relu(acc + bias)), 16 channels.
@@ -302,7 +332,7 @@ __device__ __forceinline__ void conv16_rows(const uint16_t* tile, const U4 (&w)[
 // nodes, written into a 16-channel LDS tile (node-major, 32 bytes per node).  `feat` is the
 // staged 2-channel input box, (BX + 2) x (BY + 2) x (BZ + 2).  16 consecutive box nodes per
 // product (a lane's node index picks its own input address); 2 chunks of 4 taps x 2
-// channels per lane; each wave takes groups w, w + 8, ..., two at a time.  w0: the layer's
+// channels per lane, in layer 1's k order (l1_tap); each wave takes groups w, w + 8, ..., two at a time.  w0: the layer's
 // 2 fragments of this lane; b0: the biases of this lane's 4 output channels.  The same
 // chunks, operands and rounding as k_conv<2, 0>, so the values are those it stores.
 template <int BX, int BY, int BZ>
@@ -312,7 +342,7 @@ __device__ __forceinline__ void layer1_to_lds(const uint16_t* feat, uint16_t* ou
     constexpr int IX = BX + 2, IY = BY + 2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int j = lane & 15, g = lane >> 4;
-    // per-lane offsets (in input nodes) of the 4 taps of each chunk: tap 16 c + 4 g + q
+    // per-lane offsets (in input nodes) of the 4 taps of each chunk: tap l1_read_tap(c, g, q)
     int toff[8];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
@@ -321,8 +351,7 @@ __device__ __forceinline__ void layer1_to_lds(const uint16_t* feat, uint16_t* ou
             int tt[4];
 #pragma unroll
             for (int gg = 0; gg < 4; ++gg) {
-                int t = 16 * c + 4 * gg + q;
-                t = t > 26 ? 26 : t;   // zero weights there
+                const int t = l1_read_tap(c, gg, q);
                 tt[gg] = ((t / 9) * IY + (t / 3) % 3) * IX + t % 3;
             }
             toff[c * 4 + q] = (g & 2) ? ((g & 1) ? tt[3] : tt[2]) : ((g & 1) ? tt[1] : tt[0]);
@@ -704,7 +733,7 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, float* 
 
 // Fragments of one layer from the FP32 parameters.  Lane l of chunk c holds row l % 16
 // and k = 32 c + 8 (l / 16) + e, e = 0..7.
-//   forward, 2 channels : row = co; k = tap * 2 + ci
+//   forward, 2 channels : row = co; k = 32 c + 8 g + 2 q + ci, tap l1_tap(c, g, q)
 //   forward, 16 channels: row = co; k = 16 h + ci, tap chunk_tap(c, h)
 //   backward: row = ci; k = 16 h + co, tap' = chunk_tap(c, h) of the flipped kernel
 //             (tap 26 - tap', bwd-data)
@@ -727,8 +756,9 @@ __global__ __launch_bounds__(64) void k_pack(const float* __restrict__ w, int ci
             const int dx = c == 0 ? (kl >> 4) : (kl < 16 ? 2 : 3);
             if (row < 9 && dx < 3) val = w[(k & 15) * 27 + 9 * (row / 3) + 3 * (row % 3) + dx];
         } else if (!bwd) {
-            // 16 input channels: the chunk table; 2: tap k / 2, in order
-            const int t = cin == 16 ? chunk_tap(c, (k >> 4) & 1) : k / cin, ci = k % cin;
+            // 16 input channels: the chunk table; 2: layer 1's k order
+            const int t = cin == 16 ? chunk_tap(c, (k >> 4) & 1) : (cin == 2 ? l1_tap(c, g, e >> 1) : 27);
+            const int ci = k % cin;
             if (t < 27 && row < cout) val = w[(row * cin + ci) * 27 + t];
         } else {
             const int tp = chunk_tap(c, (k >> 4) & 1), co = k % 16;
@@ -893,81 +923,152 @@ struct TailCnnArgs {
 // buffers that the layers use in turn (features and 5^3 in Y, 7^3 and 3^3 in X), about
 // 15 KB.  The fragments take about 120 VGPRs, so two waves fit a SIMD (eight per compute
 // unit) without spills; they hide one another's gather and LDS latency.
+//
+// The hidden activations are stored in two channel planes (channels 0-7, then 8-15, 16
+// bytes per node in each), so the 16 lanes of a B-operand group read 16 consecutive nodes'
+// records of one plane: 256 contiguous bytes, every bank once.
 constexpr int TAIL_THREADS = 64;
-constexpr int TAIL_X_ELEMS = 343 * 16;   // bf16
-constexpr int TAIL_Y_ELEMS = 125 * 16;   // >= 729 * 2 features
+constexpr int TAIL_XP = 343 * 8;         // plane stride of X (bf16 elements)
+constexpr int TAIL_YP = 125 * 8;         // plane stride of Y
+constexpr int TAIL_X_ELEMS = 2 * TAIL_XP;
+constexpr int TAIL_Y_ELEMS = 2 * TAIL_YP;
+static_assert(TAIL_Y_ELEMS >= 729 * 2, "Y holds the 9^3 x 2 features");
 constexpr int TAIL_GATHER = (729 + 63) / 64;
 
-// B operand of chunk c for the output node whose input-patch base index is `base` (this
-// lane's k slice: 8 channels of one tap for 16 input channels, 4 taps x 2 channels for 2).
-template <int CIN, int IN_E>
-__device__ __forceinline__ U4 patch_bop(const uint16_t* __restrict__ in, int base, int c, int g) {
-    if (CIN == 16) {
-        int t = chunk_tap(c, g >> 1);
-        t = t > 26 ? 26 : t;   // zero weights there; any finite operand will do
-        int dz, dy, dx;
-        tap_xyz(t, dz, dy, dx);
-        return *reinterpret_cast<const U4*>(&in[(base + (dz * IN_E + dy) * IN_E + dx) * 16 + (g & 1) * 8]);
-    } else {
-        uint32_t w[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int t = 16 * c + 4 * g + q;
-            t = t > 26 ? 26 : t;
-            int dz, dy, dx;
-            tap_xyz(t, dz, dy, dx);
-            w[q] = *reinterpret_cast<const uint32_t*>(&in[(base + (dz * IN_E + dy) * IN_E + dx) * 2]);
-        }
-        return U4{w[0], w[1], w[2], w[3]};
+// Byte addresses from which this lane reads the 14 chunks of a 16-channel layer for the
+// output node whose input-patch base index is `base`: the lane's k slice is 8 channels
+// (plane g & 1) of tap chunk_tap(c, g >> 1), and the tap's offset is a per-lane term (the
+// h = g >> 1 half of the x pair, dz pair or dy pair) plus a constant per chunk.
+template <int IN_E, int PLANE>
+struct TapBases {
+    uint32_t a, b, c, d;
+    __device__ __forceinline__ TapBases(uint32_t base, uint32_t g) {
+        const uint32_t p = ((g & 1u) * PLANE + base * 8u) * 2u, h = g >> 1;
+        a = p + h * 16u;                   // chunks 0..8: (dz, dy, h)
+        b = p + h * (IN_E * IN_E * 16u);   // chunks 9..11: (h, dy, 2)
+        c = p + h * (IN_E * 16u);          // chunk 12: (2, h, 2)
+        d = p;                             // chunk 13: (2, 2, 2), both halves
+    }
+    template <int C>
+    __device__ __forceinline__ U4 load(const char* lds) const {
+        constexpr uint32_t off = C < 9 ? ((C / 3) * IN_E + C % 3) * IN_E * 16u
+                                       : (C < 12 ? ((C - 9) * IN_E + 2) * 16u
+                                                 : (C == 12 ? (2 * IN_E * IN_E + 2) * 16u
+                                                            : ((2 * IN_E + 2) * IN_E + 2) * 16u));
+        const uint32_t v = C < 9 ? a : (C < 12 ? b : (C == 12 ? c : d));
+        return *reinterpret_cast<const U4*>(lds + v + off);
+    }
+};
+static_assert(chunk_tap(12, 1) == chunk_tap(12, 0) + 3 && chunk_tap(9, 1) == chunk_tap(9, 0) + 9 &&
+                  chunk_tap(0, 1) == chunk_tap(0, 0) + 1 && chunk_tap(13, 0) == 26,
+              "the per-lane tap terms follow the chunk table");
+
+template <int C, int N, int IN_E, int PLANE>
+__device__ __forceinline__ void tail_chunks(const char* in, const TapBases<IN_E, PLANE>& t0,
+                                            const TapBases<IN_E, PLANE>& t1, const U4 (&wr)[14], f32x4& acc0,
+                                            f32x4& acc1) {
+    if constexpr (C < N) {
+        const U4 b0 = t0.template load<C>(in);
+        const U4 b1 = t1.template load<C>(in);
+        acc0 = mfma_bf16(wr[C], b0, acc0);
+        acc1 = mfma_bf16(wr[C], b1, acc1);
+        tail_chunks<C + 1, N>(in, t0, t1, wr, acc0, acc1);
     }
 }
 
-// Output nodes [0, OUT_E^3) of a valid 3^3 convolution of the IN_E^3 x CIN patch `in` into
-// the OUT_E^3 x 16 patch `out` (ReLU, bf16), 16 nodes per MFMA group.  Two groups are
-// computed together so that their two accumulation chains alternate on the matrix core.
-template <int CIN, int IN_E, int OUT_E, int NCH>
-__device__ __forceinline__ void patch_layer(const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
-                                            const U4 (&wr)[NCH], const float* __restrict__ bias) {
+// Store 16 output channels (this lane's 4 of node o) in the two-plane layout.
+template <int OUT_PLANE>
+__device__ __forceinline__ void tail_store(uint16_t* out, int o, uint32_t g, const f32x4& acc, const float (&bb)[4]) {
+    uint2 st;
+    st.x = pack2bf(fmaxf(acc[0] + bb[0], 0.f), fmaxf(acc[1] + bb[1], 0.f));
+    st.y = pack2bf(fmaxf(acc[2] + bb[2], 0.f), fmaxf(acc[3] + bb[3], 0.f));
+    *reinterpret_cast<uint2*>(&out[(g >> 1) * OUT_PLANE + o * 8 + (g & 1u) * 4]) = st;
+}
+
+// Output node o of a valid 3^3 convolution of an IN_E^3 patch -> the patch index of its
+// (0, 0, 0) tap: o = (oz OUT_E + oy) OUT_E + ox  ->  (oz IN_E + oy) IN_E + ox
+//   = o + (IN_E - OUT_E) (q + IN_E oz), q = o / OUT_E = oz OUT_E + oy.
+template <int IN_E, int OUT_E>
+__device__ __forceinline__ uint32_t tail_base(uint32_t o) {
+    const uint32_t q = div_small<OUT_E>(o);
+    const uint32_t oz = div_small<OUT_E>(q);
+    return o + (IN_E - OUT_E) * (q + IN_E * oz);
+}
+
+// Output nodes [0, OUT_E^3) of a valid 3^3 convolution (16 input channels) of the IN_E^3
+// patch `in` into the OUT_E^3 patch `out` (ReLU, bf16), 16 nodes per MFMA group.  Two groups
+// are computed together so that their two accumulation chains alternate on the matrix core.
+template <int IN_E, int OUT_E, int IN_PLANE, int OUT_PLANE>
+__device__ __forceinline__ void tail_layer16(const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
+                                             const U4 (&wr)[14], const float* __restrict__ bias) {
     constexpr int NOUT = OUT_E * OUT_E * OUT_E;
     constexpr int NGRP = (NOUT + 15) / 16;
-    const int lane = threadIdx.x & 63;
-    const int j = lane & 15, g = lane >> 4;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t j = lane & 15, g = lane >> 4;
     float bb[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) bb[r] = bias[4 * g + r];
+    const char* inb = reinterpret_cast<const char*>(in);
 #pragma unroll 1
     for (int grp = 0; grp < NGRP; grp += 2) {
-        int o[2], base[2];
-        bool valid[2];
+        const int o0 = grp * 16 + j, o1 = o0 + 16;
+        const bool v0 = o0 < NOUT, v1 = o1 < NOUT;   // (grp + 1 == NGRP: the second group is all invalid)
+        const TapBases<IN_E, IN_PLANE> t0(tail_base<IN_E, OUT_E>(v0 ? o0 : NOUT - 1), g);
+        const TapBases<IN_E, IN_PLANE> t1(tail_base<IN_E, OUT_E>(v1 ? o1 : NOUT - 1), g);
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        tail_chunks<0, 14>(inb, t0, t1, wr, acc0, acc1);
+        if (v0) tail_store<OUT_PLANE>(out, o0, g, acc0, bb);
+        if (v1) tail_store<OUT_PLANE>(out, o1, g, acc1, bb);
+    }
+}
+
+// Layer 1 (2 input channels) of the 9^3 feature patch (packed bf16 pairs in `in`) into the
+// 7^3 patch `out`.  Chunk c's k slice of lane group g is taps l1_read_tap(c, g, q) (q = 0..3),
+// one 4-byte channel pair each; the eight tap offsets of the lane are formed once per call.
+template <int OUT_PLANE>
+__device__ __forceinline__ void tail_layer1(const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
+                                            const U4 (&wr)[2], const float* __restrict__ bias) {
+    constexpr int IN_E = 9, OUT_E = 7, NOUT = 343, NGRP = (NOUT + 15) / 16;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t j = lane & 15, g = lane >> 4;
+    float bb[4];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            o[h] = (grp + h) * 16 + j;
-            valid[h] = o[h] < NOUT;   // (grp + 1 == NGRP: the second group is all invalid)
-            o[h] = valid[h] ? o[h] : NOUT - 1;
-            // o = (oz OUT_E + oy) OUT_E + ox  ->  base = (oz IN_E + oy) IN_E + ox
-            //   = o + (IN_E - OUT_E) (q + IN_E oz), q = o / OUT_E = oz OUT_E + oy
-            const uint32_t q = div_small<OUT_E>((uint32_t)o[h]);
-            const uint32_t oz = div_small<OUT_E>(q);
-            base[h] = o[h] + (IN_E - OUT_E) * (int)(q + IN_E * oz);
+    for (int r = 0; r < 4; ++r) bb[r] = bias[4 * g + r];
+    uint32_t toff[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        uint32_t tt[4];
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg) {
+            const int t = l1_read_tap(e >> 2, gg, e & 3);
+            tt[gg] = (uint32_t)((((t / 9) * IN_E + (t / 3) % 3) * IN_E + t % 3) * 4);
         }
+        toff[e] = (g & 2) ? ((g & 1) ? tt[3] : tt[2]) : ((g & 1) ? tt[1] : tt[0]);
+    }
+    const char* inb = reinterpret_cast<const char*>(in);
+#pragma unroll 1
+    for (int grp = 0; grp < NGRP; grp += 2) {
+        const int o0 = grp * 16 + j, o1 = o0 + 16;
+        const bool v0 = o0 < NOUT, v1 = o1 < NOUT;
+        const uint32_t p0 = tail_base<IN_E, OUT_E>(v0 ? o0 : NOUT - 1) * 4u;
+        const uint32_t p1 = tail_base<IN_E, OUT_E>(v1 ? o1 : NOUT - 1) * 4u;
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const U4 b0 = patch_bop<CIN, IN_E>(in, base[0], c, g);
-            const U4 b1 = patch_bop<CIN, IN_E>(in, base[1], c, g);
+        for (int c = 0; c < 2; ++c) {
+            U4 b0, b1;
+            b0.x = *reinterpret_cast<const uint32_t*>(inb + p0 + toff[4 * c + 0]);
+            b0.y = *reinterpret_cast<const uint32_t*>(inb + p0 + toff[4 * c + 1]);
+            b0.z = *reinterpret_cast<const uint32_t*>(inb + p0 + toff[4 * c + 2]);
+            b0.w = *reinterpret_cast<const uint32_t*>(inb + p0 + toff[4 * c + 3]);
+            b1.x = *reinterpret_cast<const uint32_t*>(inb + p1 + toff[4 * c + 0]);
+            b1.y = *reinterpret_cast<const uint32_t*>(inb + p1 + toff[4 * c + 1]);
+            b1.z = *reinterpret_cast<const uint32_t*>(inb + p1 + toff[4 * c + 2]);
+            b1.w = *reinterpret_cast<const uint32_t*>(inb + p1 + toff[4 * c + 3]);
             acc0 = mfma_bf16(wr[c], b0, acc0);
             acc1 = mfma_bf16(wr[c], b1, acc1);
         }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const f32x4 acc = h ? acc1 : acc0;
-            if (valid[h]) {
-                uint2 st;
-                st.x = pack2bf(fmaxf(acc[0] + bb[0], 0.f), fmaxf(acc[1] + bb[1], 0.f));
-                st.y = pack2bf(fmaxf(acc[2] + bb[2], 0.f), fmaxf(acc[3] + bb[3], 0.f));
-                *reinterpret_cast<uint2*>(&out[o[h] * 16 + 4 * g]) = st;
-            }
-        }
+        if (v0) tail_store<OUT_PLANE>(out, o0, g, acc0, bb);
+        if (v1) tail_store<OUT_PLANE>(out, o1, g, acc1, bb);
     }
 }
 
@@ -1054,12 +1155,22 @@ __global__ __launch_bounds__(TAIL_THREADS) __attribute__((amdgpu_waves_per_eu(2,
         w2[c] = reinterpret_cast<const U4*>(a.frag[2])[c * 64 + lane];
     }
     constexpr int K4 = (432 + 63) / 64;   // layer 4: 27 taps x 16 channels, tap-major
-    for (int k = lane; k < 3 * 16 + 432 + 1; k += 64) {
-        float v;
-        if (k < 48) v = a.bias[k >> 4][k & 15];
-        else if (k < 48 + 432) v = bf2f(f2bf(a.w4[((k - 48) & 15) * 27 + ((k - 48) >> 4)]));
-        else v = *a.b4;
-        C[k] = v;
+    {
+        // every load issued before the first store: one memory latency for the constants
+        constexpr int NC = 3 * 16 + 432 + 1, RC = (NC + 63) / 64;
+        float cv[RC];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            const int k = lane + 64 * r;
+            const float* src = k < 48 ? (k < 16 ? a.bias[0] : (k < 32 ? a.bias[1] : a.bias[2])) + (k & 15)
+                                      : (k < 48 + 432 ? a.w4 + ((k - 48) & 15) * 27 + ((k - 48) >> 4) : a.b4);
+            cv[r] = k < NC ? *src : 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            const int k = lane + 64 * r;
+            if (k < NC) C[k] = (k >= 48 && k < 48 + 432) ? bf2f(f2bf(cv[r])) : cv[r];
+        }
     }
     for (int u = lane; u < 64 * TAIL_GATHER; u += 64) {
         const int v = u < 729 ? u : 0;
@@ -1084,17 +1195,17 @@ __global__ __launch_bounds__(TAIL_THREADS) __attribute__((amdgpu_waves_per_eu(2,
             tail_gather<TAIL_GATHER / 2, TAIL_GATHER - TAIL_GATHER / 2>(a, node, inv_max, inv_dd, Y);
         }
         __syncthreads();
-        patch_layer<2, 9, 7, 2>(Y, X, w0, C);
+        tail_layer1<TAIL_XP>(Y, X, w0, C);
         __syncthreads();
-        patch_layer<16, 7, 5, 14>(X, Y, w1, C + 16);
+        tail_layer16<7, 5, TAIL_XP, TAIL_YP>(X, Y, w1, C + 16);
         __syncthreads();
-        patch_layer<16, 5, 3, 14>(Y, X, w2, C + 32);
+        tail_layer16<5, 3, TAIL_YP, TAIL_XP>(Y, X, w2, C + 32);
         __syncthreads();
         float s = 0.f;
 #pragma unroll
         for (int r = 0; r < K4; ++r) {
-            const int k = lane + 64 * r;
-            if (k < 432) s += C[48 + k] * bf2f(X[k]);
+            const int k = lane + 64 * r;   // tap k / 16, channel k % 16 (plane, then 8 per node)
+            if (k < 432) s += C[48 + k] * bf2f(X[((k >> 3) & 1) * TAIL_XP + (k >> 4) * 8 + (k & 7)]);
         }
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
         if (lane == 0) {

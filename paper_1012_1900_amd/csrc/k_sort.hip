@@ -160,32 +160,37 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 }
 
 // Short lists: each element's place is the number of smaller keys plus the number of
-// equal keys before it (a stable rank).  A workgroup ranks 64 keys: it holds the whole list
-// in LDS and each of its four waves counts against one quarter of it (broadcast reads),
-// the quarters then summed in LDS, so the O(n) comparisons of a key are spread over four
-// waves and the grid has n/16 waves.  For n <= SMALL_SORT_CAP; a longer list is left as it
-// is and *overflow set (the callers sort only to order work, so any order is correct).
+// equal keys before it (a stable rank), i.e. the number of smaller (key, position) pairs.
+// A workgroup of 16 waves ranks 64 keys: it holds the whole list in LDS as 64-bit
+// (key << 32 | position) words, distinct and ordered as the stable order, and each wave
+// counts the words below its 64 against one sixteenth of the list (broadcast reads, one
+// 64-bit compare and one add per word), the sixteen counts then summed in LDS.  For
+// n <= SMALL_SORT_CAP; a longer list is left as it is and *overflow set (the callers sort
+// only to order work, so any order is correct).
 // ORDER_ONLY: the values are the positions 0..n-1 (a work list in its queue order); the
 // sorted positions are written straight into `vals` and the keys are not moved.
 // Otherwise the pairs go to the scratch arrays at their places and a second pass copies
 // them back.
-constexpr int SMALL_THREADS = 256;
+constexpr int SMALL_THREADS = 1024;
 constexpr int SMALL_KEYS = 64;    // keys ranked per workgroup
+constexpr int SMALL_PARTS = SMALL_THREADS / SMALL_KEYS;
 constexpr int SMALL_BLOCKS = SMALL_SORT_CAP / SMALL_KEYS;
+static_assert(SMALL_SORT_CAP % SMALL_THREADS == 0 && SMALL_KEYS % (4 * SMALL_PARTS) == 0,
+              "each part of the padded list must be a whole number of 4-word steps");
 template <bool ORDER_ONLY>
 __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small_rank(const uint32_t* __restrict__ keys,
                                                                    uint32_t* __restrict__ vals,
                                                                    uint32_t* __restrict__ tk, uint32_t* __restrict__ tv,
                                                                    const uint32_t* n_dev, uint32_t* overflow) {
-    __shared__ __align__(16) uint32_t sk[SMALL_SORT_CAP];
-    __shared__ uint32_t s_part[SMALL_THREADS / SMALL_KEYS][SMALL_KEYS];
+    __shared__ __align__(16) uint64_t sk[SMALL_SORT_CAP];
+    __shared__ uint32_t s_part[SMALL_PARTS][SMALL_KEYS];
     const uint32_t n = *n_dev;
     if (n > (uint32_t)SMALL_SORT_CAP) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *overflow = 1u;
         return;
     }
     if (blockIdx.x * SMALL_KEYS >= n) return;
-    // keys padded to a multiple of 64 with the largest value (they rank after every key);
+    // the list padded to a multiple of 64 with all-ones words (above every real word);
     // every thread issues all its loads (clamped to the last key) before the first store,
     // so the staging costs one memory latency
     const uint32_t n64 = (n + 63u) & ~63u;
@@ -201,39 +206,32 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small_rank(const uint32_
         for (int r = 0; r < R; ++r) {
             asm volatile("" : "+v"(v[r]));
             const uint32_t j = threadIdx.x + SMALL_THREADS * r;
-            if (j < n64) sk[j] = j < n ? v[r] : 0xFFFFFFFFu;
+            if (j < n64) sk[j] = j < n ? ((uint64_t)v[r] << 32 | j) : ~0ull;
         }
     }
     __syncthreads();
     const uint32_t lane = threadIdx.x & (SMALL_KEYS - 1), part = threadIdx.x / SMALL_KEYS;
     const uint32_t i = blockIdx.x * SMALL_KEYS + lane;
-    const uint32_t k = sk[i < n ? i : 0];
-    // this wave's quarter [j0, j1) of the list (a multiple of 16 long)
-    const uint32_t q = n64 / 4;
+    const uint64_t k = sk[i < n ? i : 0];
+    // this wave's part [j0, j1) of the padded list (a multiple of 4 long)
+    const uint32_t q = n64 / SMALL_PARTS;
     const uint32_t j0 = part * q, j1 = j0 + q;
-    // #{j : key_j < k} + #{j < i : key_j == k} over the quarter; the padding never counts
     uint32_t cnt = 0;
-    const uint4* s4 = reinterpret_cast<const uint4*>(sk);
-    for (uint32_t j = j0; j < j1; j += 16) {
-        uint4 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = s4[(j >> 2) + u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t kk[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) cnt += (kk[e] < k || (kk[e] == k && j + 4 * u + e < i)) ? 1u : 0u;
-        }
+    const ulonglong2* s2 = reinterpret_cast<const ulonglong2*>(sk);
+    for (uint32_t j = j0; j < j1; j += 4) {
+        const ulonglong2 a = s2[j >> 1], b = s2[(j >> 1) + 1];
+        cnt += (a.x < k ? 1u : 0u) + (a.y < k ? 1u : 0u) + (b.x < k ? 1u : 0u) + (b.y < k ? 1u : 0u);
     }
     s_part[part][lane] = cnt;
     __syncthreads();
     if (part != 0 || i >= n) return;
     uint32_t rank = 0;
-    for (int p = 0; p < SMALL_THREADS / SMALL_KEYS; ++p) rank += s_part[p][lane];
+#pragma unroll
+    for (int p = 0; p < SMALL_PARTS; ++p) rank += s_part[p][lane];
     if (ORDER_ONLY) {
         vals[rank] = i;
     } else {
-        tk[rank] = k;
+        tk[rank] = (uint32_t)(k >> 32);
         tv[rank] = vals[i];
     }
 }
