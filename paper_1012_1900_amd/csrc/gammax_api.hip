@@ -40,6 +40,7 @@ struct GraphKey {
     double cond_threshold, radius_factor;
     const void* model;
     int32_t small_sort;
+    int32_t short_tail;
     int32_t tail_min_lanes;
     int32_t cnn_pool;
     int32_t projection;
@@ -478,6 +479,15 @@ bool uses_model(const gammax_problem_t* p, const gammax_options_t* o) {
            (o->radius_mode == GAMMAX_RADIUS_LEARNED || o->sort_mode == GAMMAX_SORT_PREDICTED);
 }
 
+// A short tail (the previous map's held at most SMALL_SORT_CAP nodes) in the automatic
+// layout walks in groups of 64 lanes, where a walk of under 64 rows is one batch whatever
+// its bound: the learned radius's speculative bound cannot shorten it, and a fallback would
+// add a batch and a launch.  Such a tail walks with the plain bound (the same result); the
+// nodes the prediction would not have certified are still counted.
+bool short_tail(const gammax_ctx* c, const gammax_options_t& opt) {
+    return opt.tail_lanes == 0 && c->tail_hint <= (uint64_t)SMALL_SORT_CAP;
+}
+
 // Least lanes per node of the automatic tail layout: wide enough that the longest walk of
 // the context's last map (if it was long) takes about 32 dependent steps.
 int tail_min_lanes(const gammax_ctx* c) {
@@ -690,7 +700,7 @@ gammax_status_t enqueue_search(gammax_ctx* c, const CallSetup& cs, uint32_t m_bo
     plan.zero_lanes = (opt.cell_lanes == 4 || opt.cell_lanes == 8) ? 1 : 0;
     plan.projection = opt.projection;
     plan.skip_zero = skip_zero ? 1 : 0;
-    plan.spec = (learned && opt.radius_mode == GAMMAX_RADIUS_LEARNED) ? 1 : 0;
+    plan.spec = (learned && opt.radius_mode == GAMMAX_RADIUS_LEARNED) ? (short_tail(c, opt) ? 3 : 1) : 0;
     plan.M = m_bound;
     plan.zero = make_zero_geo(p);
     plan.tmp_keys = work_array(c, W_TMP_K);
@@ -762,6 +772,7 @@ GraphKey key_of(gammax_ctx* c, const CallSetup& cs) {
     k.radius_factor = cs.opt->radius_factor;
     k.model = cs.opt->model;
     k.small_sort = (cs.opt->sort_mode != GAMMAX_SORT_NONE && c->tail_hint <= (uint64_t)SMALL_SORT_CAP) ? 1 : 0;
+    k.short_tail = short_tail(c, *cs.opt) ? 1 : 0;
     k.tail_min_lanes = tail_min_lanes(c);
     k.cnn_pool = cs.opt->cnn_pool;
     k.projection = cs.opt->projection;
@@ -834,7 +845,7 @@ void fill_result_from(gammax_ctx* c, const Scalars& h, gammax_result_t* res, boo
         res->ms_guard = elapsed(c->ev[7], c->ev[8]);
         res->ms_cnn = cnn ? elapsed(c->ev[9], c->ev[10]) : 0.0f;
     }
-    res->n_fallback = h.n_fallback;
+    res->n_fallback = (uint64_t)h.n_fallback + h.n_fallback_inline;
     res->long_walk_rows = h.long_rows;
     // the next call sorts its tail with the rank sort if this one's would have fitted, and
     // widens its tail groups if this one had long walks

@@ -21,6 +21,8 @@ struct Scalars {
     uint32_t n_fallback;    // learned radius: tail nodes not certified inside 1.1 * gamma_hat
     uint32_t sort_overflow; // the one-workgroup tail sort met a longer tail (left unsorted)
     uint32_t long_rows;     // longest tail walk in table rows, when above LONG_WALK_ROWS (else 0)
+    uint32_t n_fallback_inline;   // learned radius, short tail: nodes the prediction would not certify
+    uint32_t reserved;
     unsigned long long n_pass;
     unsigned long long n_border;
     unsigned long long n_fp64;
@@ -221,7 +223,9 @@ struct SearchPlan {
     int projection;          // pass A in 3D: 0 = all faces a cell owns, 1 = Ju's recursion
     int skip_zero;           // 1: the key-0 pass was queued elsewhere (a batch's launch over all pairs)
     int spec;                // 1: speculative tail walk inside spec_factor * gamma_hat, then the
-                             //    plain walk for the nodes it could not certify
+                             //    plain walk for the nodes it could not certify; 3: a short tail
+                             //    (groups of 64 lanes), walked with the plain bound, the nodes
+                             //    the prediction would not certify counted as fallbacks
     // optional: queued after the key-0 pass, before the tail sort (the network at the tail
     // nodes writes yhat and, for the predicted order, the sort keys)
     hipError_t (*after_zero)(void* user, hipStream_t s);

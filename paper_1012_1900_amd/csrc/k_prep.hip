@@ -167,6 +167,7 @@ __device__ __forceinline__ void prep_count_body(const PrepArgs& a, int nb_red, i
             sc->n_fallback = 0u;
             sc->sort_overflow = 0u;
             sc->long_rows = 0u;
+            sc->n_fallback_inline = 0u;
             sc->n_pass = 0ull;
             sc->n_border = 0ull;
             sc->n_fp64 = 0ull;

@@ -1264,6 +1264,12 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
         const bool leader = live && gl == 0;
         const bool to_guard = MODE == 1 && leader && ill;
         const bool to_fb = spec == 1 && leader && !to_guard && F > r2s;
+        if (spec == 3) {
+            // a short tail walks with the plain bound; the nodes the prediction would not
+            // have certified (F above its bound) are counted as its fallbacks
+            const uint32_t nfb = (uint32_t)__popcll(__ballot(leader && F > r2s));
+            if ((threadIdx.x & (WAVE - 1)) == 0 && nfb) atomicAdd(&a.sc->n_fallback_inline, nfb);
+        }
         if (leader && !to_guard && !to_fb) {
             finish_node(a, node, F, npass, nborder, gm);
             cells += lane_cells + zero_cells(DIM, x, y, z, nx, ny, nz);
@@ -1989,9 +1995,10 @@ hipError_t launch_search(const SearchArgs& a, const SearchPlan& p, hipStream_t s
         // pass B (with the learned radius: the speculative walk, then the plain walk of the
         // nodes it could not certify, resumed where the speculative bound cut them off)
         if (a.tab_len > first) {
-            const int spec = p.spec ? 1 : 0;
+            const int spec = p.spec;
             used += (int)tail_pass(a, p, a.tail_pos, &a.sc->n_tail, first, guarded, spec, tb, sums, s);
-            if (spec) used += (int)tail_pass(a, p, a.fb_list, &a.sc->n_fallback, first, guarded, 2, tb, sums, s);
+            if (spec == 1)
+                used += (int)tail_pass(a, p, a.fb_list, &a.sc->n_fallback, first, guarded, 2, tb, sums, s);
         }
         if (p.ev_tail_end) (void)hipEventRecord(p.ev_tail_end, s);
         // guard pass, with the count reduction in the same launch

@@ -98,6 +98,29 @@ def test_c2_learned_every_node(gx, c2, crit):
         assert o.cells_visited * (1 - 1e-4) <= rr.n_cells <= o.cells_visited + 63 * rr.n_tail
 
 
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_c2_learned_short_and_long_tail_forms(gx, c2):
+    """A fresh context knows no tail yet, so its first learned map takes the short-tail form
+    (groups of 64 lanes walk with the plain bound; the nodes the prediction would not have
+    certified are counted); the next map, knowing the tail is long, takes the speculative
+    walk and its fallback list.  Both are the plain map bit for bit and count the same
+    fallbacks."""
+    p = c2
+    _say("256x256x192 learned: short-tail form, then the fallback list")
+    ref, ev = dev(p.ref), dev(p.eval)
+    model = gx.Model(np.load(WEIGHTS, allow_pickle=False))
+    g_plain, r_plain = gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1)
+    assert r_plain.n_tail > 4096
+    ctx = gx.Context(0)
+    kw = dict(radius="learned", sort="predicted", model=model, cnn_pool=2, ctx=ctx)
+    g1, r1 = gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, **kw)
+    g2, r2 = gx.gammax_map(ref, ev, p.spacing, 0.03, 3.0, 0.1, **kw)
+    for g, r in ((g1, r1), (g2, r2)):
+        assert np.array_equal(host(g), host(g_plain))
+        assert (r.n_pass, r.n_tail) == (r_plain.n_pass, r_plain.n_tail)
+    assert 0 < r1.n_fallback == r2.n_fallback < r1.n_tail
+
+
 def test_c2_precision_ablation(gx, c2):
     """FP32 projections everywhere, the FP64 guard of ill-conditioned tetrahedra, and FP64
     everywhere: each within the bar at every node; FP64 within float rounding of the
