@@ -1009,7 +1009,7 @@ __device__ __forceinline__ void tail_layer16(const uint16_t* __restrict__ in, ui
 #pragma unroll
     for (int r = 0; r < 4; ++r) bb[r] = bias[4 * g + r];
     const char* inb = reinterpret_cast<const char*>(in);
-#pragma unroll 1
+#pragma unroll 2   // two group pairs in flight: their reads overlap the other pair's products
     for (int grp = 0; grp < NGRP; grp += 2) {
         const int o0 = grp * 16 + j, o1 = o0 + 16;
         const bool v0 = o0 < NOUT, v1 = o1 < NOUT;   // (grp + 1 == NGRP: the second group is all invalid)
@@ -1046,7 +1046,7 @@ __device__ __forceinline__ void tail_layer1(const uint16_t* __restrict__ in, uin
         toff[e] = (g & 2) ? ((g & 1) ? tt[3] : tt[2]) : ((g & 1) ? tt[1] : tt[0]);
     }
     const char* inb = reinterpret_cast<const char*>(in);
-#pragma unroll 1
+#pragma unroll 2   // two group pairs in flight: their reads overlap the other pair's products
     for (int grp = 0; grp < NGRP; grp += 2) {
         const int o0 = grp * 16 + j, o1 = o0 + 16;
         const bool v0 = o0 < NOUT, v1 = o1 < NOUT;

@@ -1266,8 +1266,9 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
         const bool to_fb = spec == 1 && leader && !to_guard && F > r2s;
         if (spec == 3) {
             // a short tail walks with the plain bound; the nodes the prediction would not
-            // have certified (F above its bound) are counted as its fallbacks
-            const uint32_t nfb = (uint32_t)__popcll(__ballot(leader && F > r2s));
+            // have certified (F above its bound) are counted as its fallbacks, except those
+            // the guard redoes (as the speculative walk does)
+            const uint32_t nfb = (uint32_t)__popcll(__ballot(leader && !to_guard && F > r2s));
             if ((threadIdx.x & (WAVE - 1)) == 0 && nfb) atomicAdd(&a.sc->n_fallback_inline, nfb);
         }
         if (leader && !to_guard && !to_fb) {

@@ -78,13 +78,23 @@ def test_learned_matches_oracle(gx, models, pair):
     assert_parity(host(g), o.gamma, "learned 2%/2mm")
 
 
-def test_learned_with_forced_guard(gx, models, pair):
+@pytest.mark.parametrize("tail_lanes", [1, 0])
+def test_learned_with_forced_guard(gx, models, pair, tail_lanes):
+    """Every tetrahedron guarded: the learned map is the plain one; in the automatic layout
+    (a short tail: one plain-bound walk) it counts the fallbacks the speculative walk and its
+    list count (tail_lanes = 16), the guarded nodes in neither."""
     ref, ev = dev(pair.ref), dev(pair.eval)
-    kw = dict(cond_threshold=1.0, tail_lanes=1)
+    kw = dict(cond_threshold=1.0, tail_lanes=tail_lanes)
     g_plain, r_p = gx.gammax_map(ref, ev, pair.spacing, 0.03, 3.0, 0.1, **kw)
     g_l, r_l = gx.gammax_map(ref, ev, pair.spacing, 0.03, 3.0, 0.1, radius="learned", model=models["zero"], **kw)
     assert r_p.n_guarded > 0
     assert np.array_equal(host(g_plain), host(g_l))
+    if tail_lanes == 0:
+        kw16 = dict(kw, tail_lanes=16)
+        g16, r16 = gx.gammax_map(ref, ev, pair.spacing, 0.03, 3.0, 0.1, radius="learned", model=models["zero"],
+                                 **kw16)
+        assert np.array_equal(host(g_plain), host(g16))
+        assert r_l.n_fallback == r16.n_fallback
 
 
 def test_learned_replays_and_timing(gx, models, pair):
