@@ -42,9 +42,9 @@ PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 # hash differs the traffic is reported as null.
 TRAFFIC = {
     "3d_128x128x96_2.5mm": {
-        "bytes": (15.65 + 2.25) * 1e6,
+        "bytes": (15.66 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "e0b99abdc55d3ac77b4e459f4763f60482e7a818d905bc96886d975736ed5cb8",
+        "sha256": "ad4ced47cba2a0aae2cc709e54f8ab07992c6e88ec6fcbdc46e1be036f895dd8",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }
