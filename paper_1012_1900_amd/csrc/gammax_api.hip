@@ -1389,45 +1389,69 @@ gammax_status_t gammax_map_grids(gammax_ctx_t* c, const gammax_problem_t* p, con
     a.guard_list = c->g_work + 2 * nr;
     a.tail_list = c->g_work + 3 * nr;
     a.tail_f = reinterpret_cast<float*>(c->g_work + 4 * nr);
-    HIPCHK(c, hipMemsetAsync(c->d_sc, 0, sizeof(Scalars), s));
-    HIPCHK(c, launch_grids_prep(a, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if ((st = scalar_errors(c, *c->h_sc, a.local != 0)) != GAMMAX_OK) return st;
-    const float r2 = u2f(c->h_sc->r2_bits);
-    if (c->h_sc->n_masked > 0 && r2 > 0.0f) {
-        // the lower-key table of the evaluation grid, cached while it reaches far enough
-        TableGeom g{};
-        g.ndim = 3;
-        g.lower = 1;
-        for (int i = 0; i < 3; ++i) {
-            g.shape[i] = eg->shape[i];
-            g.s[i] = eg->spacing_mm[i] / p->dta_mm;
-        }
-        const bool fits = c->g_tab_valid && same_geom(c->g_geom, g) && (double)r2 < c->g_geom.r2_cap;
-        if (!fits) {
-            c->g_tab_valid = false;
-            g.r2_cap = (double)r2 * 1.5;
-            if ((st = build_rows(c, g, &c->g_tab, &c->g_tab_cap, &c->g_tab_len, &c->g_k1, s)) != GAMMAX_OK)
-                return st;
-            c->g_geom = g;
-            c->g_tab_valid = true;
-        }
-        a.tab = c->g_tab;
-        a.tab_len = (int)c->g_tab_len;
-        a.k1 = c->g_k1;
-        const int lanes = opt.tail_lanes > 0 ? opt.tail_lanes : 16;
+    // the lower-key table of the evaluation grid, cached while it reaches far enough
+    TableGeom g{};
+    g.ndim = 3;
+    g.lower = 1;
+    for (int i = 0; i < 3; ++i) {
+        g.shape[i] = eg->shape[i];
+        g.s[i] = eg->spacing_mm[i] / p->dta_mm;
+    }
+    const int lanes = opt.tail_lanes > 0 ? opt.tail_lanes : 16;
+    // the key-0 pass, the walk and the guard over the listed nodes (their count is on the
+    // device); with no table (every first bound is 0) the key-0 pass finishes every node
+    auto search = [&](const TabEntry* tab, int tab_len, float k1) -> hipError_t {
+        a.tab = tab;
+        a.tab_len = tab_len;
+        a.k1 = k1;
+        hipError_t e;
         if (opt.precision == GAMMAX_PREC_FP64) {
-            HIPCHK(c, launch_grids_walk(a, opt.precision, false, lanes, s));
+            if ((e = launch_grids_walk(a, opt.precision, false, lanes, s)) != hipSuccess) return e;
         } else {
             // the 27 key-0 cells one lane per node, then the walk of the nodes left
-            HIPCHK(c, launch_grids_zero(a, opt.precision, s));
-            HIPCHK(c, launch_grids_tail(a, opt.precision, lanes, s));
+            if ((e = launch_grids_zero(a, opt.precision, s)) != hipSuccess) return e;
+            if ((e = launch_grids_tail(a, opt.precision, lanes, s)) != hipSuccess) return e;
         }
-        if (opt.precision == GAMMAX_PREC_GUARDED) HIPCHK(c, launch_grids_walk(a, opt.precision, true, lanes, s));
+        if (opt.precision == GAMMAX_PREC_GUARDED) return launch_grids_walk(a, opt.precision, true, lanes, s);
+        return hipSuccess;
+    };
+    bool done = false;
+    if (c->g_tab_valid && same_geom(c->g_geom, g)) {
+        // a cached table for this geometry: the whole map on it, read back once at the end;
+        // if the radius found has outgrown the table, the map runs again below on a new one
+        HIPCHK(c, hipMemsetAsync(c->d_sc, 0, sizeof(Scalars), s));
+        HIPCHK(c, launch_grids_prep(a, s));
+        HIPCHK(c, search(c->g_tab, (int)c->g_tab_len, c->g_k1));
+        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if ((st = scalar_errors(c, *c->h_sc, a.local != 0)) != GAMMAX_OK) return st;
+        done = !((double)u2f(c->h_sc->r2_bits) >= c->g_geom.r2_cap && c->h_sc->n_masked > 0);
     }
-    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    if (!done) {
+        HIPCHK(c, hipMemsetAsync(c->d_sc, 0, sizeof(Scalars), s));
+        HIPCHK(c, launch_grids_prep(a, s));
+        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if ((st = scalar_errors(c, *c->h_sc, a.local != 0)) != GAMMAX_OK) return st;
+        const float r2f = u2f(c->h_sc->r2_bits);
+        if (c->h_sc->n_masked > 0 && r2f > 0.0f) {
+            const bool fits = c->g_tab_valid && same_geom(c->g_geom, g) && (double)r2f < c->g_geom.r2_cap;
+            if (!fits) {
+                c->g_tab_valid = false;
+                g.r2_cap = (double)r2f * 1.5;
+                if ((st = build_rows(c, g, &c->g_tab, &c->g_tab_cap, &c->g_tab_len, &c->g_k1, s)) != GAMMAX_OK)
+                    return st;
+                c->g_geom = g;
+                c->g_tab_valid = true;
+            }
+            HIPCHK(c, search(c->g_tab, (int)c->g_tab_len, c->g_k1));
+        } else if (c->h_sc->n_masked > 0) {
+            HIPCHK(c, search(nullptr, 0, INFINITY));
+        }
+        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    const float r2 = u2f(c->h_sc->r2_bits);
     if (res) {
         const Scalars& h = *c->h_sc;
         std::memset(res, 0, sizeof(*res));

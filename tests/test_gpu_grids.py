@@ -94,6 +94,38 @@ def test_closed_forms_and_outside_nodes(gx):
     assert np.allclose(g2h[inside], 0.05 / (0.03 * 2.0), rtol=2e-5)
 
 
+@pytest.mark.parametrize("precision", ["guarded", "fp32", "fp64"])
+def test_identical_doses_on_the_same_grid(gx, precision):
+    """Every first bound is 0 (the evaluation dose equals the reference at every node, on the
+    same grid): no table is needed, and every evaluated node has gamma 0 and passes."""
+    p = make_pair_3d(57, shape=(12, 14, 13), spacing=(2.5, 2.5, 2.5))
+    g, r = gx.gammax_map_grids(dev(p.ref), dev(p.ref), p.spacing, p.spacing, (0.0, 0.0, 0.0), 0.03, 3.0, 0.1,
+                               precision=precision)
+    o = oracle.gamma(p.ref, p.ref, p.spacing, 0.03, 3.0, 0.1)
+    gh = host(g)
+    assert np.array_equal(gh >= 0, o.gamma >= 0) and r.n_evaluated > 0
+    assert np.all(gh[gh >= 0] == 0.0)
+    assert r.n_pass == r.n_evaluated
+
+
+def test_cached_table_and_a_radius_that_outgrows_it(gx):
+    """On one context the table built for the first map serves the next ones of the same
+    geometry (one read-back per map); a map whose radius outgrows it runs again on a larger
+    one.  Every map equals the same map on a fresh context bit for bit."""
+    ref_sp, ev_sp, ev_o = (2.5, 2.5, 2.5), (2.5, 2.5, 2.5), (1.25, -0.5, 0.75)
+    p = make_pair_3d(58, shape=(16, 18, 17), spacing=ref_sp)
+    ev_small = p.ref + np.float32(0.3) * (p.eval - p.ref)
+    ev_large = p.ref + np.float32(3.0) * (p.eval - p.ref)
+    ctx = gx.Context(0)
+    for ev in (ev_small, ev_large, ev_small, ev_large):
+        g, r = gx.gammax_map_grids(dev(p.ref), dev(ev), ref_sp, ev_sp, ev_o, 0.03, 3.0, 0.1, ctx=ctx)
+        g0, r0 = gx.gammax_map_grids(dev(p.ref), dev(ev), ref_sp, ev_sp, ev_o, 0.03, 3.0, 0.1, ctx=gx.Context(0))
+        assert np.array_equal(host(g), host(g0))
+        assert (r.n_evaluated, r.n_pass) == (r0.n_evaluated, r0.n_pass)
+    o = oracle.gamma_grids(p.ref, ev_large, ref_sp, ev_sp, ev_o, 0.03, 3.0, 0.1)
+    assert_parity(host(g), o.gamma, "cached table, large radius")
+
+
 def test_refused_options(gx):
     p = make_pair_3d(54, shape=(8, 9, 10), spacing=(2.5, 2.5, 2.5))
     with pytest.raises(gx.GammaxError) as e:
