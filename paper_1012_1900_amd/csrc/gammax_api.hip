@@ -1358,6 +1358,7 @@ gammax_status_t gammax_map_grids(gammax_ctx_t* c, const gammax_problem_t* p, con
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, hipSetDevice(c->device));
     if ((st = grow(c, &c->g_work, &c->g_work_cap, 5 * nr)) != GAMMAX_OK) return st;
+    if ((st = grow(c, &c->part, &c->part_cap, 2 * MAX_BLOCKS)) != GAMMAX_OK) return st;
     GridsArgs a{};
     a.ref = ref;
     a.ev = ev;
@@ -1389,6 +1390,7 @@ gammax_status_t gammax_map_grids(gammax_ctx_t* c, const gammax_problem_t* p, con
     a.guard_list = c->g_work + 2 * nr;
     a.tail_list = c->g_work + 3 * nr;
     a.tail_f = reinterpret_cast<float*>(c->g_work + 4 * nr);
+    a.part = c->part;
     // the lower-key table of the evaluation grid, cached while it reaches far enough
     TableGeom g{};
     g.ndim = 3;

@@ -268,6 +268,7 @@ struct GridsArgs {
     float k1;                  // key^2 of the first row past the 27 key-0 cells
     uint32_t* tail_list;       // nodes the key-0 pass leaves for the walk (count: sc->n_tail)
     float* tail_f;             // and their bound so far
+    uint32_t* part;            // MAX_BLOCKS words: per-block dose maxima (order-preserving bits)
 };
 // Dose maximum and finiteness, then the listing of the evaluated nodes with their first
 // bound (and gamma = -1 everywhere else); sc must be zeroed before.

@@ -1534,38 +1534,59 @@ __device__ __forceinline__ T grids_f0(const GridsArgs& a, const int c0[3], const
     return best;
 }
 
+constexpr int GRIDS_MAX_ITEMS = 8;
 __global__ __launch_bounds__(256) void k_grids_max(GridsArgs a, int64_t nr, int64_t ne) {
     float m = -Num<float>::inf();
     bool bad = false;
     const int64_t n = nr > ne ? nr : ne;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        if (i < nr) {
-            const float v = a.ref[i];
-            bad = bad || !isfinite(v);
-            m = fmaxf(m, v);
+    // GRIDS_MAX_ITEMS nodes of each volume per thread and step, every load of a step issued
+    // before the first use (indices clamped to the last node: the copies change neither the
+    // maximum nor the finiteness check)
+    constexpr int K = GRIDS_MAX_ITEMS;
+    const int64_t step = (int64_t)gridDim.x * 256 * K;
+    for (int64_t b0 = (int64_t)blockIdx.x * 256 * K; b0 < n; b0 += step) {
+        float r[K], e[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int64_t i = b0 + (int64_t)k * 256 + threadIdx.x;
+            r[k] = a.ref[i < nr ? i : nr - 1];
+            e[k] = a.ev[i < ne ? i : ne - 1];
         }
-        if (i < ne) bad = bad || !isfinite(a.ev[i]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            bad = bad || !isfinite(r[k]) || !isfinite(e[k]);
+            m = fmaxf(m, r[k]);
+        }
     }
+    // one partial per block (an atomic maximum per wave on one address serialises: it took
+    // 30-80 us); the listing kernel reduces the partials
+    __shared__ uint32_t s_m[4];
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    // one atomic per wave, and only while it can still raise the maximum (all waves on one
-    // address would serialise)
-    if ((threadIdx.x & 63) == 0 && m > -Num<float>::inf()) {
-        const uint32_t o = float_to_ord(m);
-        if (o > __atomic_load_n(&a.sc->dmax_ord, __ATOMIC_RELAXED)) atomicMax(&a.sc->dmax_ord, o);
-    }
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m > -Num<float>::inf() ? float_to_ord(m) : 0u;
     if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&a.sc->flags, FLAG_NONFINITE);
+    __syncthreads();
+    if (threadIdx.x == 0) a.part[blockIdx.x] = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
 }
 
 // Listing in chunks of 16 nodes per thread (4096 per block): one atomic per chunk on the
 // list counter (one per 256 nodes would serialise on that address).
 constexpr int GRIDS_PER_THREAD = 16;
-__global__ __launch_bounds__(256) void k_grids_list(GridsArgs a, int64_t nr) {
+__global__ __launch_bounds__(256) void k_grids_list(GridsArgs a, int64_t nr, int nb_max) {
     __shared__ uint32_t s_wsum[4];
     __shared__ uint32_t s_base;
-    const float dmax = ord_to_float(a.sc->dmax_ord);
+    // the dose maximum from k_grids_max's partials (every block reduces them itself)
+    uint32_t dm = 0u;
+    for (int j = threadIdx.x; j < nb_max; j += 256) dm = max(dm, a.part[j]);
+    for (int o = 32; o > 0; o >>= 1) dm = max(dm, (uint32_t)__shfl_xor((int)dm, o));
+    if ((threadIdx.x & 63) == 0) s_wsum[threadIdx.x >> 6] = dm;
+    __syncthreads();
+    dm = max(max(s_wsum[0], s_wsum[1]), max(s_wsum[2], s_wsum[3]));
+    __syncthreads();   // s_wsum is reused below
+    const float dmax = ord_to_float(dm);
     const float thr_val = grids_thr(a, dmax);
     const float inv_dd_g = 1.0f / ((float)a.dd * dmax);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.sc->dmax_ord = dm;
         a.sc->thr_val = thr_val;
         a.sc->inv_dd = inv_dd_g;
     }
@@ -1573,15 +1594,22 @@ __global__ __launch_bounds__(256) void k_grids_list(GridsArgs a, int64_t nr) {
     const int64_t chunk = 256 * GRIDS_PER_THREAD;
     // block-uniform trip count, so that every thread reaches the barriers
     for (int64_t b0 = (int64_t)blockIdx.x * chunk; b0 < nr; b0 += (int64_t)gridDim.x * chunk) {
-        float F0[GRIDS_PER_THREAD];
+        float F0[GRIDS_PER_THREAD], drs[GRIDS_PER_THREAD];
         uint32_t takes = 0u, cnt = 0u;
+        // every reference load first, and the gamma = -1 stores after the chunk's loads: a
+        // store between them (gamma may alias the doses, as far as the compiler knows) kept
+        // each node's loads waiting for the previous node's
+#pragma unroll
+        for (int k = 0; k < GRIDS_PER_THREAD; ++k) {
+            const int64_t r = b0 + threadIdx.x + 256 * k;
+            drs[k] = a.ref[r < nr ? r : nr - 1];
+        }
 #pragma unroll
         for (int k = 0; k < GRIDS_PER_THREAD; ++k) {
             const int64_t r = b0 + threadIdx.x + 256 * k;
             F0[k] = 0.0f;
             if (r < nr) {
-                const float dr = a.ref[r];
-                a.gamma[r] = -1.0f;
+                const float dr = drs[k];
                 double u[3];
                 bool inside;
                 grids_pos(a, (int)r, u, inside);
@@ -1594,6 +1622,11 @@ __global__ __launch_bounds__(256) void k_grids_list(GridsArgs a, int64_t nr) {
                     ++cnt;
                 }
             }
+        }
+#pragma unroll
+        for (int k = 0; k < GRIDS_PER_THREAD; ++k) {
+            const int64_t r = b0 + threadIdx.x + 256 * k;
+            if (r < nr) a.gamma[r] = -1.0f;
         }
         // exclusive prefix of the per-thread counts over the block
         uint32_t incl = cnt;
@@ -2017,11 +2050,14 @@ hipError_t launch_grids_prep(const GridsArgs& a, hipStream_t s) {
     const int64_t nr = (int64_t)a.rn[0] * a.rn[1] * a.rn[2];
     const int64_t ne = (int64_t)a.en[0] * a.en[1] * a.en[2];
     const int64_t n = nr > ne ? nr : ne;
-    const unsigned b1 = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    constexpr int64_t kMaxBlocks = 512;   // partials each listing block reduces (<= MAX_BLOCKS)
+    static_assert(kMaxBlocks <= MAX_BLOCKS, "the partials buffer holds MAX_BLOCKS words");
+    const int64_t nb1 = (n + 256 * GRIDS_MAX_ITEMS - 1) / (256 * GRIDS_MAX_ITEMS);
+    const unsigned b1 = (unsigned)(nb1 < kMaxBlocks ? nb1 : kMaxBlocks);
     hipLaunchKernelGGL(k_grids_max, dim3(b1), dim3(256), 0, s, a, nr, ne);
     const int64_t chunks = (nr + 256 * GRIDS_PER_THREAD - 1) / (256 * GRIDS_PER_THREAD);
     const unsigned b2 = (unsigned)(chunks < 4096 ? chunks : 4096);
-    hipLaunchKernelGGL(k_grids_list, dim3(b2), dim3(256), 0, s, a, nr);
+    hipLaunchKernelGGL(k_grids_list, dim3(b2), dim3(256), 0, s, a, nr, (int)b1);
     return hipGetLastError();
 }
 
