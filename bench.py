@@ -44,7 +44,7 @@ TRAFFIC = {
     "3d_128x128x96_2.5mm": {
         "bytes": (15.66 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "d8e0081ad7a2690599459c2b3052bcb3d54e325ca67e3e9e9cfd8cfdfe5a7ec8",
+        "sha256": "d1d91f4116d3ca5c2195ac2c15fb6ba6cb972d61978514731edf3d69a814a1fd",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }

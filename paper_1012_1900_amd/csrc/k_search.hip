@@ -1654,9 +1654,15 @@ __global__ __launch_bounds__(256) void k_grids_list(GridsArgs a, int64_t nr, int
                 ++pos;
             }
         }
-        // the largest first bound: one atomic per wave, only while it can raise it
+        // the largest first bound: one atomic per block and chunk, only while it can raise it
         for (int o = 32; o > 0; o >>= 1) fb = max(fb, (uint32_t)__shfl_xor((int)fb, o));
-        if (lane == 0 && fb > __atomic_load_n(&a.sc->r2_bits, __ATOMIC_RELAXED)) atomicMax(&a.sc->r2_bits, fb);
+        if (lane == 0) s_wsum[w] = fb;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            fb = max(max(s_wsum[0], s_wsum[1]), max(s_wsum[2], s_wsum[3]));
+            if (fb > __atomic_load_n(&a.sc->r2_bits, __ATOMIC_RELAXED)) atomicMax(&a.sc->r2_bits, fb);
+        }
+        __syncthreads();   // s_wsum is reused by the next chunk
     }
 }
 
@@ -1683,6 +1689,38 @@ __device__ __forceinline__ bool grids_need(const float* g, float ax, float ay, f
     const float dz = __builtin_fmaxf(__builtin_fmaxf(0.0f, az - f[0]), f[0] - az - 1.0f);
     const float lb = ((sx2 * dx * dx + sy2 * dy * dy) + sz2 * dz * dz) + m * m;
     return lb < F + F * 0x1p-8f;
+}
+
+// The counts of a block of 256 threads (every thread calls): summed over its waves in LDS and
+// added with one atomic per count.  An atomic per wave on these few addresses serialises.
+__device__ __forceinline__ void grids_counts(Scalars* sc, uint32_t npass, uint32_t nborder, unsigned long long cells,
+                                             uint32_t gm) {
+    __shared__ unsigned long long s_c[4];
+    __shared__ uint32_t s_p[4], s_b[4], s_g[4];
+    for (int o = 32; o > 0; o >>= 1) {
+        npass += (uint32_t)__shfl_xor((int)npass, o);
+        nborder += (uint32_t)__shfl_xor((int)nborder, o);
+        gm = max(gm, (uint32_t)__shfl_xor((int)gm, o));
+        cells += (unsigned long long)__shfl_xor((long long)cells, o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_p[w] = npass;
+        s_b[w] = nborder;
+        s_g[w] = gm;
+        s_c[w] = cells;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        npass = s_p[0] + s_p[1] + s_p[2] + s_p[3];
+        nborder = s_b[0] + s_b[1] + s_b[2] + s_b[3];
+        gm = max(max(s_g[0], s_g[1]), max(s_g[2], s_g[3]));
+        cells = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+        if (npass) atomicAdd(&sc->n_pass, (unsigned long long)npass);
+        if (nborder) atomicAdd(&sc->n_border, (unsigned long long)nborder);
+        if (cells) atomicAdd(&sc->n_cells, cells);
+        if (gm) atomicMax(&sc->maxg2_bits, gm);
+    }
 }
 
 // The 27 key-0 cells (offsets a in {-1,0,1}^3 from the holding cell) of every listed node,
@@ -1792,18 +1830,7 @@ __global__ __launch_bounds__(256) void k_grids_zero(GridsArgs a) {
     }
     // tail nodes count their key-0 cells in the walk's total: add them here
     if (to_tail) ncells = cells;
-    for (int o = 32; o > 0; o >>= 1) {
-        npass += (uint32_t)__shfl_xor((int)npass, o);
-        nborder += (uint32_t)__shfl_xor((int)nborder, o);
-        gm = max(gm, (uint32_t)__shfl_xor((int)gm, o));
-        ncells += (unsigned long long)__shfl_xor((long long)ncells, o);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (npass) atomicAdd(&a.sc->n_pass, (unsigned long long)npass);
-        if (nborder) atomicAdd(&a.sc->n_border, (unsigned long long)nborder);
-        if (ncells) atomicAdd(&a.sc->n_cells, ncells);
-        if (gm) atomicMax(&a.sc->maxg2_bits, gm);
-    }
+    grids_counts(a.sc, npass, nborder, ncells, gm);
 }
 
 // LIST 0: the listed nodes from row 0; 1: the guard list (FP64) from row 0; 2: the tail
@@ -1918,19 +1945,7 @@ __global__ __launch_bounds__(256) void k_grids_walk(GridsArgs a, int G) {
             if (to_guard) a.guard_list[gpos] = (uint32_t)r;
         }
     }
-    // one atomic per wave
-    for (int o = 32; o > 0; o >>= 1) {
-        npass += (uint32_t)__shfl_xor((int)npass, o);
-        nborder += (uint32_t)__shfl_xor((int)nborder, o);
-        gm = max(gm, (uint32_t)__shfl_xor((int)gm, o));
-        cells += (unsigned long long)__shfl_xor((long long)cells, o);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (npass) atomicAdd(&a.sc->n_pass, (unsigned long long)npass);
-        if (nborder) atomicAdd(&a.sc->n_border, (unsigned long long)nborder);
-        if (cells) atomicAdd(&a.sc->n_cells, cells);
-        if (gm) atomicMax(&a.sc->maxg2_bits, gm);
-    }
+    grids_counts(a.sc, npass, nborder, cells, gm);
 }
 
 }  // namespace
