@@ -282,13 +282,25 @@ __global__ __launch_bounds__(256) void k_pass_count(const float* __restrict__ g,
         np += (v >= 0.0f) & (v <= 1.0f);
         nb += (v >= 0.0f) & (fabsf(v - 1.0f) <= 1e-5f);
     }
+    // summed over the block, then one atomic per count (one per wave on these three
+    // addresses serialises)
+    __shared__ uint32_t s[3][256 / WAVE];
     ne = wave_sum_u32(ne);
     np = wave_sum_u32(np);
     nb = wave_sum_u32(nb);
+    const int w = threadIdx.x / WAVE;
     if ((threadIdx.x & (WAVE - 1)) == 0) {
-        if (ne) atomicAdd(&counts[0], (unsigned long long)ne);
-        if (np) atomicAdd(&counts[1], (unsigned long long)np);
-        if (nb) atomicAdd(&counts[2], (unsigned long long)nb);
+        s[0][w] = ne;
+        s[1][w] = np;
+        s[2][w] = nb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t[3] = {0ull, 0ull, 0ull};
+        for (int j = 0; j < (int)(blockDim.x / WAVE); ++j)
+            for (int q = 0; q < 3; ++q) t[q] += s[q][j];
+        for (int q = 0; q < 3; ++q)
+            if (t[q]) atomicAdd(&counts[q], t[q]);
     }
 }
 

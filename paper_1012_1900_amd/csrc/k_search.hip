@@ -1138,7 +1138,7 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
     const int sxy = nx * ny;
     const float inv_dd_g = a.sc->inv_dd;
     const InvS2<float> is = inv_s2_of(a);
-    uint32_t cells = 0, gm = 0, npass = 0, nborder = 0;
+    uint32_t cells = 0, gm = 0, npass = 0, nborder = 0, nfb = 0;
     GuardCtx gc{};
     uint32_t dummy_fp64 = 0;
 
@@ -1264,13 +1264,10 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
         const bool leader = live && gl == 0;
         const bool to_guard = MODE == 1 && leader && ill;
         const bool to_fb = spec == 1 && leader && !to_guard && F > r2s;
-        if (spec == 3) {
-            // a short tail walks with the plain bound; the nodes the prediction would not
-            // have certified (F above its bound) are counted as its fallbacks, except those
-            // the guard redoes (as the speculative walk does)
-            const uint32_t nfb = (uint32_t)__popcll(__ballot(leader && !to_guard && F > r2s));
-            if ((threadIdx.x & (WAVE - 1)) == 0 && nfb) atomicAdd(&a.sc->n_fallback_inline, nfb);
-        }
+        // a short tail walks with the plain bound; the nodes the prediction would not have
+        // certified (F above its bound) are counted as its fallbacks, except those the guard
+        // redoes (as the speculative walk does)
+        if (spec == 3) nfb += (leader && !to_guard && F > r2s) ? 1u : 0u;
         if (leader && !to_guard && !to_fb) {
             finish_node(a, node, F, npass, nborder, gm);
             cells += lane_cells + zero_cells(DIM, x, y, z, nx, ny, nz);
@@ -1286,6 +1283,18 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
                 a.fb_list[fpos] = item;
                 a.tail_f[item] = f2u(F);
             }
+        }
+    }
+    if (spec == 3) {
+        // one atomic per block (one per wave on a single address serialises)
+        __shared__ uint32_t s_fb[SEARCH_THREADS / WAVE];
+        for (int o = WAVE / 2; o > 0; o >>= 1) nfb += (uint32_t)__shfl_xor((int)nfb, o);
+        if ((threadIdx.x & (WAVE - 1)) == 0) s_fb[threadIdx.x / WAVE] = nfb;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0u;
+            for (int j = 0; j < SEARCH_THREADS / WAVE; ++j) t += s_fb[j];
+            if (t) atomicAdd(&a.sc->n_fallback_inline, t);
         }
     }
     block_sums(sums, vb, npass, nborder, 0u, cells, gm);
