@@ -205,8 +205,7 @@ gammax_status_t gammax_map(gammax_ctx_t *ctx, const gammax_problem_t *problem,
  *   inside this call (as gammax_map does) and the wait only returns its result.
  *   At most GAMMAX_ASYNC_SLOTS maps may be queued and not collected (GAMMAX_E_PARAM).
  *   Maps on one context run in issue order on their streams; give every map of a context
- *   the same stream (they share the context's workspace).  Graph replays are fastest when
- *   successive maps use the same buffers.
+ *   the same stream (they share the context's workspace).
  */
 gammax_status_t gammax_map_async(gammax_ctx_t *ctx, const gammax_problem_t *problem,
                                  const gammax_options_t *opt, const float *ref_dev,

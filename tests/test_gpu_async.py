@@ -38,7 +38,7 @@ def test_queue_equals_sync(gx, pair):
     ref, ev = dev(pair.ref), dev(pair.eval)
     ctx = gx.Context(0)
     g1, r1 = gx.gammax_map(ref, ev, pair.spacing, 0.03, 3.0, 0.1, ctx=gx.Context(0))
-    # the first queued call builds the table (runs to completion), the rest replay
+    # the first queued call builds the table (runs to completion), the rest use it
     outs = [gx.gammax_map_async(ref, ev, pair.spacing, 0.03, 3.0, 0.1, ctx=ctx) for _ in range(12)]
     res = [t.wait() for t in outs]
     for t, r in zip(outs, res):
@@ -131,7 +131,7 @@ def test_slot_limit_and_single_collection(gx, pair):
 
 
 def test_queued_learned_and_2d(gx, pair):
-    """Queued maps with the learned radius (the network inside the replayed graph) and of a
+    """Queued maps with the learned radius (the network among the queued launches) and of a
     2D pair: the same gamma and counts as the synchronous calls."""
     from dosegen import make_config_pair
     from oracle import cnn

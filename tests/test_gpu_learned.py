@@ -181,7 +181,7 @@ def test_trained_network_orders_the_one_lane_walk_better_than_dd(gx):
 @pytest.mark.parametrize("kind", ["random", "zero"])
 def test_learned_pooled_input_equals_plain(gx, models, kind):
     """cnn_pool = 2 (a 1.25 mm grid, the network on the pair pooled to 2.5 mm): the same
-    gamma as the plain search, also on graph replays and queued maps."""
+    gamma as the plain search, also on repeated and queued maps."""
     from dosegen import make_pair_3d
     p = make_pair_3d(33, shape=(48, 50, 46), spacing=(1.25, 1.25, 1.25))
     ref, ev = dev(p.ref), dev(p.eval)

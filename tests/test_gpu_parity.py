@@ -129,7 +129,7 @@ def test_given_order(gx, small3d, kind):
         g, r = gx.gammax_map(ref, ev, p.spacing, *crit, 0.1, sort="given", order_key=key)
         assert np.array_equal(host(g), host(base))
         assert (r.n_cells, r.n_pass, r.n_tail, r.n_guarded) == (rb.n_cells, rb.n_pass, rb.n_tail, rb.n_guarded)
-    # queued, twice with the same key (the second replays the captured map)
+    # queued, twice with the same key (both on the cached table)
     for _ in range(2):
         t = gx.gammax_map_async(ref, ev, p.spacing, *crit, 0.1, sort="given", order_key=noise)
         r = t.wait()
@@ -309,9 +309,10 @@ def test_flat_entry_point(gx):
     assert pr == pytest.approx(r.pass_rate)
 
 
-def test_graph_replays_match_direct_launches(gx):
-    """The steady-state call replays a captured graph; every replay must equal a direct
-    (timed, non-graph) run on the same buffers, with eager work between the replays."""
+def test_steady_maps_match_timed_maps(gx):
+    """Steady-state calls on the cached table, with new doses in the same buffers and eager
+    work between them: each equals a timed call (events around every phase) on the same
+    buffers, and the oracle."""
     import torch
     p0 = make_pair_3d(31, shape=(33, 40, 37), spacing=(2.5, 2.5, 2.5))
     ref, ev = dev(p0.ref), dev(p0.eval)
@@ -323,13 +324,13 @@ def test_graph_replays_match_direct_launches(gx):
         ref.copy_(torch.from_numpy(pk.ref))
         ev.copy_(torch.from_numpy(pk.eval))
         junk = torch.randn(1 << 16, device="cuda").sum()   # unrelated eager work
-        _, r_graph = gx.gammax_map(ref, ev, p0.spacing, 0.03, 3.0, 0.1, out=out, ctx=ctx)
-        g_graph = host(out).copy()
-        _, r_direct = gx.gammax_map(ref, ev, p0.spacing, 0.03, 3.0, 0.1, out=out, ctx=ctx, timing=True)
-        assert np.array_equal(g_graph, host(out)), f"replay {k}"
-        assert r_graph.n_pass == r_direct.n_pass and r_graph.n_cells == r_direct.n_cells
+        _, r_steady = gx.gammax_map(ref, ev, p0.spacing, 0.03, 3.0, 0.1, out=out, ctx=ctx)
+        g_steady = host(out).copy()
+        _, r_timed = gx.gammax_map(ref, ev, p0.spacing, 0.03, 3.0, 0.1, out=out, ctx=ctx, timing=True)
+        assert np.array_equal(g_steady, host(out)), f"map {k}"
+        assert r_steady.n_pass == r_timed.n_pass and r_steady.n_cells == r_timed.n_cells
         o = oracle.gamma(pk.ref, pk.eval, pk.spacing, 0.03, 3.0, 0.1)
-        assert_parity(g_graph, o.gamma, f"replay {k}")
+        assert_parity(g_steady, o.gamma, f"map {k}")
         assert float(junk) == float(junk)
     ctx.close()
 
