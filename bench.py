@@ -514,8 +514,8 @@ def run_mixed(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + [MIXED[0]], default="3d_128x128x96_2.5mm")
     ap.add_argument("--dd", type=float, default=0.03)
     ap.add_argument("--dta", type=float, default=3.0)
@@ -588,9 +588,9 @@ def main():
         del src, dst
 
     def leg(p, r_dev, e_dev, o_dev, extra, steps):
-        """W warm-up maps; `steps` timed maps queued back to back (gammax_map_async: graph
-        replays whose host work overlaps the GPU's, every result collected inside the timed
-        region); `steps` synchronous maps (gammax_map: one host round trip each); then
+        """W warm-up maps; `steps` timed maps queued back to back (gammax_map_async: the host
+        work of the next map overlaps the GPU's work on the current one, every result
+        collected inside the timed region); `steps` synchronous maps (gammax_map: one host round trip each); then
         `steps` maps with HIP events per phase.  Returns (seconds per queued map, seconds per
         synchronous map, the last queued map's result, the phase results)."""
         kw = dict(sort=args.sort, precision=args.precision, tail_lanes=args.tail_lanes,
