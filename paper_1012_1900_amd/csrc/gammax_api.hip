@@ -3,10 +3,10 @@
 //
 // Two ways through a call:
 //  * steady state (the cached cell table fits this grid and spacing): every kernel is
-//    queued without a host round trip (the masked count M and the radius stay on the
-//    device; the grids are sized for all N nodes) and, without timing, replayed from a
-//    captured HIP graph.  One synchronisation at the end returns the counts.  If the
-//    radius turned out larger than the cached table covers, the call is redone below.
+//    launched without a host round trip (the masked count M and the radius stay on the
+//    device; the grids are sized for all N nodes).  One synchronisation at the end returns
+//    the counts.  If the radius turned out larger than the cached table covers, the call
+//    is redone below.
 //  * table build: the compaction runs first, the host reads M and R, builds the sorted
 //    cell table for R (cached with headroom), then queues the search.
 #include <algorithm>
@@ -131,8 +131,8 @@ struct gammax_ctx {
     AsyncSlot* slots = nullptr;     // GAMMAX_ASYNC_SLOTS entries, created on first use
     uint64_t next_ticket = 1;
     // Every map ends with a kernel that writes its scalars into the pinned ring, at the slot
-    // given by a device-side map counter: inside the captured graph, so no runtime copy has
-    // to wait for the graph to drain.  The host counts the maps it launches the same way.
+    // given by a device-side map counter, so no runtime copy has to wait for the map's last
+    // kernel to drain.  The host counts the maps it launches the same way.
     Scalars* h_ring = nullptr;      // pinned, GAMMAX_ASYNC_SLOTS entries
     uint32_t* d_seq = nullptr;      // device map counter
     uint64_t seq = 0;               // host count of the maps launched
@@ -140,7 +140,7 @@ struct gammax_ctx {
 
 void destroy_batch(gammax_ctx* c);
 
-// gammax_map_many: a context per pair index (its table, graph and workspace stay cached
+// gammax_map_many: a context per pair index (its table and workspace stay cached
 // across calls) and the streams the pairs are spread over: the caller's stream and three
 // internal ones (a process gets four hardware queues; a fifth stream would share one).
 constexpr int kManyStreams = 4;
@@ -302,9 +302,8 @@ __global__ void k_zero_u32(uint32_t* p) {
 
 // The map's scalars into the pinned ring at the slot of the device map counter, made
 // visible at system scope before the kernel ends; then the counter moves on.  One wave:
-// every lane reads the same counter value.  (A runtime device-to-host copy queued after a
-// graph starts several microseconds after the graph's last kernel; this kernel is part of
-// the graph.)
+// every lane reads the same counter value.  (A runtime device-to-host copy queued after the
+// map's last kernel starts several microseconds after it; a kernel follows at once.)
 __device__ __forceinline__ void publish_body(const Scalars* __restrict__ src, uint32_t* seq, Scalars* ring) {
     constexpr int W = (int)(sizeof(Scalars) / sizeof(uint32_t));
     static_assert(sizeof(Scalars) % sizeof(uint32_t) == 0, "Scalars is a whole number of words");
