@@ -1157,9 +1157,11 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
         uint32_t lane_cells = 0;
         bool ill = false;
         const float r2s = (spec && live) ? spec_bound2(a, item) : Num<float>::inf();
-        // the fallback resumes at the first row the speculative bound cut off (per group)
-        const int start = (spec == 2 && live) ? resume_row(tab, a.tab_len, first, r2s) : first;
+        // the fallback resumes at the first row the speculative bound cut off, which the
+        // speculative launch stored in the (by then unused) sort-key slot of the item
+        const int start = (spec == 2 && live) ? (int)a.tail_key_arr[item] : first;
         uint32_t steps = 0;   // batches of G rows this group walked
+        int last_n0 = -1;     // first row of the group's last batch (speculative walk)
 
         for (int n0 = start; n0 < a.tab_len; n0 += G) {
             const float k_first = tab[n0].key2;       // uniform per group
@@ -1167,6 +1169,7 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
             const bool grp_act = live && k_first < bound;
             if (__ballot(grp_act) == 0ull) break;
             steps += grp_act ? 1u : 0u;
+            last_n0 = grp_act ? n0 : last_n0;
             const int n = n0 + gl;
             TabEntry e;
             bool act = false;
@@ -1278,10 +1281,21 @@ __device__ __forceinline__ void tail_group_body(const SearchArgs& a, const TabEn
             if (to_guard) a.guard_list[gpos] = (uint32_t)node;
         }
         if (spec == 1) {
+            // the first row the speculative bound cut off.  A node sent to the fallback kept
+            // F above r2s, so its bound was r2s throughout: it walked every row before its
+            // last batch and, in that batch, the rows below r2s (a prefix: rows are in key
+            // order); with no batch walked it is the first row
+            const int rr = last_n0 + gl;
+            const bool below = last_n0 >= 0 && rr < a.tab_len && tab[rr].key2 < r2s;
+            const unsigned long long bm = __ballot(below);
+            const int lane = (int)(threadIdx.x & (WAVE - 1));
+            const unsigned long long gmask = G >= WAVE ? ~0ull : (((1ull << G) - 1ull) << (lane & ~(G - 1)));
+            const int cut = last_n0 < 0 ? start : last_n0 + (int)__popcll(bm & gmask);
             const uint32_t fpos = block_append(to_fb, &a.sc->n_fallback);
             if (to_fb) {
                 a.fb_list[fpos] = item;
                 a.tail_f[item] = f2u(F);
+                a.tail_key_arr[item] = (uint32_t)cut;
             }
         }
     }
