@@ -42,9 +42,9 @@ PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 # hash differs the traffic is reported as null.
 TRAFFIC = {
     "3d_128x128x96_2.5mm": {
-        "bytes": (15.65 + 2.25) * 1e6,
+        "bytes": (15.64 + 2.25) * 1e6,
         "source": "paper_1012_1900_amd/csrc/k_search.hip",
-        "sha256": "369fa1e8c5cf9e860d0c4d2126fc70adc62905006a76d08e7412bac49ef53937",
+        "sha256": "7e435a71fae7fe288f525dff3d5614aa0fcc235f56c40e4590c7dd95eee89105",
         "profile": "profiles/pmc_hbm_bytes_128x128x96_2.5mm_3pct3mm.md",
     },
 }
